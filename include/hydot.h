@@ -1,0 +1,202 @@
+/*
+ * hydot.h - C ABI of the MI355X hyperspectral DOT Born hot path.
+ *
+ * Method: Saibaba, Kilmer, Miller, Fantini, "Fast algorithms for hyperspectral
+ * diffuse optical tomography".  The library computes
+ *   - the fields phi = A(lambda)^-1 b for every source and detector right-hand
+ *     side at every wavelength (Sec. 3, eq. multipleshifted), by Algorithm 1
+ *     "Augmented GMRES for parametric systems" with the deflation space recycled
+ *     across wavelengths (Sec. 3.1);
+ *   - the Born operator J_lambda[s,d,k] = -h^3 phi_s(k) phi_d(k) those fields
+ *     define (Sec. 2.1 integral equation with the adjoint field; rows of H in
+ *     eq. measurement), applied matrix-free as J v and J^H w;
+ *   - the parametric level-set shape (Sec. 5, eq. pals) and the data misfit
+ *     (Sec. 5, eq. minimization) with their gradients.
+ *
+ * Discretisation (cell-centred finite volume on a box, voxel index
+ * n = i + nx*(j + ny*k), voxel edge h):
+ *   A(lambda) = D_lambda K + B/(2 A_R) + (mu_a(lambda) + i omega/nu) h^3 I
+ *   (K phi)_n = h * sum_{face neighbours m}(phi_n - phi_m) + 2h phi_n per Dirichlet face,
+ *   B = diag(h^2 * number of Robin faces of voxel n),
+ *   D_lambda = 1/(3 mu_s'(lambda)), mu_a(lambda) = sum_l c_l eps_l(lambda)
+ *   (Sec. 2.1 diffusion equation with the Robin and Dirichlet conditions and
+ *   eq. perturbation; the finite-element matrices of Sec. 2.2 replaced by this
+ *   finite-volume form, which keeps the affine dependence on the wavelength).
+ *
+ * Conventions for every call:
+ *   - Device buffers are allocated and owned by the caller; the library never
+ *     frees caller memory.  The library owns only the opaque operator.
+ *   - Complex data are interleaved (re, im) pairs: HYDOT_C128 = 2 x double,
+ *     HYDOT_C64 = 2 x float.  All arrays are densely packed, C order.
+ *   - Work is enqueued on the caller's stream (NULL = default stream).  Calls
+ *     that return host values synchronise that stream before returning.
+ *   - Arguments are validated before any launch: HYDOT_EINVAL leaves every
+ *     output untouched.  A HIP failure returns HYDOT_EDEVICE.  The message of
+ *     the last non-OK status is returned by hydot_last_error() (per thread).
+ */
+#ifndef HYDOT_H
+#define HYDOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HYDOT_OK = 0,
+  HYDOT_ENOCONV = 1,        /* warning: some systems above tolerance; outputs written */
+  HYDOT_EINVAL = -1,        /* invalid argument; nothing launched, outputs untouched */
+  HYDOT_ENOMEM = -2,        /* workspace too small */
+  HYDOT_EDEVICE = -3,       /* a HIP runtime call failed */
+  HYDOT_EUNSUPPORTED = -4   /* valid but not supported combination (e.g. dtype) */
+} hydot_status;
+
+typedef enum {
+  HYDOT_C128 = 0,           /* complex FP64 (re, im) */
+  HYDOT_C64 = 1,            /* complex FP32 (re, im) */
+  HYDOT_F64 = 3,            /* real FP64 */
+  HYDOT_F32 = 4             /* real FP32 */
+} hydot_dtype;
+
+/* Box grid. robin_faces: bit f set = Robin on face f in the order
+ * (-x, +x, -y, +y, -z, +z); bit clear = zero Dirichlet (Sec. 2.1). 0x3F = all Robin. */
+typedef struct {
+  int32_t nx, ny, nz;       /* >= 1 each; nx*ny*nz < 2^31 */
+  double h_mm;              /* voxel edge [mm], > 0 */
+  double A_R;               /* Robin coefficient A (refractive-index mismatch), > 0 */
+  uint32_t robin_faces;
+} hydot_grid;
+
+/* Background optics per wavelength (host arrays, copied by assemble). */
+typedef struct {
+  int32_t n_lambda;                 /* >= 1 */
+  const double* mus_prime_per_mm;   /* [n_lambda] reduced scattering mu_s' > 0 */
+  int32_t n_species;                /* >= 1, <= 8 */
+  const double* extinction;         /* [n_species][n_lambda] eps_l(lambda) [1/(mm uM)] */
+  const double* conc_uM;            /* [n_species] background concentrations c_l */
+  double omega_over_nu_per_mm;      /* modulation frequency over speed of light in tissue */
+} hydot_optics;
+
+/* Solver flags */
+#define HYDOT_FLAG_NO_RECYCLE  0x1u  /* recycle_k treated as 0 and no multi-shift initial guess */
+#define HYDOT_FLAG_MEAN_SHIFT  0x2u  /* K <- K + mean(sigma') R, sigma'_j <- sigma'_j - mean (Sec. 6.1) */
+#define HYDOT_FLAG_GRAPH       0x4u  /* capture each restart cycle in a hipGraph and replay it */
+#define HYDOT_FLAG_PER_SYSTEM  0x8u  /* plain mode: one (rhs, lambda) system at a time, per-call launches */
+
+#define HYDOT_PREC_FP64  0           /* Krylov basis and operator in complex FP64 */
+#define HYDOT_PREC_MIXED 1           /* complex FP32 Krylov inner solves, FP64 residual refinement */
+
+typedef struct {
+  double rel_tol;           /* stop when ||b - A phi||_2/||b||_2 <= rel_tol (FP64-recomputed), > 0 */
+  int32_t max_iter;         /* cap on Arnoldi steps per system, >= 1 */
+  int32_t restart_m;        /* m: Arnoldi steps per cycle are m - k; m - k in [1, 128] */
+  int32_t recycle_k;        /* k: deflation space dimension, 0..32, < lanczos_n */
+  int32_t lanczos_n;        /* n: shift-invariant Krylov steps on K (Alg. 1 step 1), 1..128 */
+  int32_t precision;        /* HYDOT_PREC_FP64 or HYDOT_PREC_MIXED */
+  uint32_t flags;           /* HYDOT_FLAG_* */
+  double inner_tol;         /* mixed only: relative tolerance of each FP32 inner solve (e.g. 1e-5) */
+  int32_t max_batch;        /* systems solved concurrently (0 = all); ignored with PER_SYSTEM */
+} hydot_solve_opts;
+
+typedef struct hydot_operator hydot_operator;   /* opaque, library-owned */
+
+/* Copy the grid and optics into a new operator (host memory only) and evaluate the
+ * optical model: D_lambda, mu_a(lambda), the shifts sigma_j = (mu_a + i omega/nu)/D,
+ * sigma'_j = 1/(2 A_R D) of eq. multipleshifted and their mean (Sec. 6.1). */
+hydot_status hydot_assemble_operator(const hydot_grid* grid, const hydot_optics* optics,
+                                     hydot_operator** out);
+void hydot_free_operator(hydot_operator* op);
+
+/* Host copies of the per-wavelength model: D [mm], mu_a [1/mm] (each [n_lambda], any may be NULL). */
+hydot_status hydot_operator_optics(const hydot_operator* op, double* D_out, double* mua_out);
+
+/* y_v = A(lambda_v) x_v for n_vec vectors (the matrix-free operator of Sec. 2.2 in
+ * finite-volume form).  x, y: device [n_vec][N] complex of dtype C128 or C64.
+ * lam_index: host [n_vec], each in [0, n_lambda). x and y must not overlap. */
+hydot_status hydot_apply_operator(const hydot_operator* op, int32_t n_vec, const int32_t* lam_index,
+                                  const void* x, void* y, hydot_dtype dtype, hipStream_t stream);
+
+/* Bytes of device workspace hydot_solve_fields needs for n_rhs right-hand sides. */
+hydot_status hydot_solve_workspace_bytes(const hydot_operator* op, int32_t n_rhs,
+                                         const hydot_solve_opts* opts, size_t* bytes);
+
+/* Fields for every right-hand side at every wavelength (Alg. 1, Sec. 3.1).
+ * rhs_voxel: host [n_rhs] voxel indices; right-hand side r is a unit injection
+ *   into that voxel (S = S0 delta(r - r_s) with S0 = 1).  Sources and detectors
+ *   (adjoint fields, Sec. 2.1) are both passed here; slice the output.
+ * phi: device [n_lambda][n_rhs][N], the physical fields (not D*phi), dtype C128 or C64.
+ * workspace: device, >= the size from hydot_solve_workspace_bytes, 256-byte aligned.
+ * iters: host [n_lambda*n_rhs] (lambda-major) Arnoldi steps per system, or NULL.
+ * rel_res: host [n_lambda*n_rhs] final FP64-recomputed ||b - A phi||/||b|| of the
+ *   FP64 iterate (before any conversion to C64), or NULL.
+ * Returns HYDOT_ENOCONV (fields still written) if any system stays above rel_tol. */
+hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
+                                const hydot_solve_opts* opts, void* phi, hydot_dtype phi_dtype,
+                                void* workspace, size_t ws_bytes, int32_t* iters, double* rel_res,
+                                hipStream_t stream);
+
+/* Born products (Sec. 2.1 integral equation; rows of H in eq. measurement), never forming J:
+ *   y[c][l][s][d] = -h^3 sum_k phi_src[l][s][k] * v[c][k] * phi_det[l][d][k]   (no conjugation)
+ * phi_src: device, source s at wavelength l at phi_src + (l*lam_stride + s)*N elements;
+ * phi_det: likewise with d.  lam_stride >= max(S, D) counts N-vectors between wavelengths
+ * (S for a packed source array, n_rhs for slices of the hydot_solve_fields output).
+ * field_dtype C128: v is FP64, y is C128.  C64: v is FP32, y is C64 (FP32 MFMA, FP64 split-K sums).
+ * v: device [n_v][N] real.  y: device [n_v][n_lambda][S][D].  1 <= S, D <= 64, 1 <= n_v <= 64. */
+hydot_status hydot_born_apply(const hydot_operator* op, const void* phi_src, int32_t S,
+                              const void* phi_det, int32_t D, int64_t lam_stride,
+                              hydot_dtype field_dtype, const void* v, int32_t n_v, void* y,
+                              hipStream_t stream);
+
+/* Adjoint product summed over wavelengths:
+ *   g[k] = sum_{l,s,d} conj(J_l[s,d,k]) w[l][s][d] = -h^3 sum conj(phi_src[l][s][k] phi_det[l][d][k]) w[l][s][d]
+ * w: device [n_lambda][S][D] complex and g: device [N] complex, both of field_dtype. */
+hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_src, int32_t S,
+                                      const void* phi_det, int32_t D, int64_t lam_stride,
+                                      hydot_dtype field_dtype, const void* w, void* g,
+                                      hipStream_t stream);
+
+/* PaLS shape (Sec. 5, eq. pals) at the voxel centres ((i+1/2)h, (j+1/2)h, (k+1/2)h):
+ *   mu(r) = H_eps(varphi(r) - tau),  varphi(r) = sum_b alpha_b exp(-(beta_b ||r - chi_b||_dag)^2),
+ *   ||x||_dag = sqrt(||x||^2 + nu^2),  H_eps the C^1 sine-smoothed Heaviside of half-width eps.
+ * p: host [5*n_bumps] = [alpha, beta, chi_x, chi_y, chi_z] (Sec. 5 ordering), 1 <= n_bumps <= 32.
+ * mu: device [N] real of dtype F64 or F32. */
+typedef struct { double tau, eps, nu; } hydot_pals_opts;
+
+hydot_status hydot_pals_shape(const hydot_operator* op, const double* p, int32_t n_bumps,
+                              const hydot_pals_opts* popts, void* mu, hydot_dtype mu_dtype,
+                              hipStream_t stream);
+
+/* Vector-Jacobian product of the shape: grad_p[i] = sum_k (d mu_k / d p_i) * Re(g_k).
+ * g: device [N] of dtype F64, F32, C128 or C64 (the real part is used).
+ * grad_p: host [5*n_bumps].  workspace: device, >= hydot_pals_workspace_bytes(). Synchronises. */
+size_t hydot_pals_workspace_bytes(const hydot_operator* op, int32_t n_bumps);
+hydot_status hydot_pals_shape_vjp(const hydot_operator* op, const double* p, int32_t n_bumps,
+                                  const hydot_pals_opts* popts, const void* g, hydot_dtype g_dtype,
+                                  double* grad_p, void* workspace, size_t ws_bytes,
+                                  hipStream_t stream);
+
+/* Data misfit of the Born model with co-located chromophores (eq. measurement, eq. minimization):
+ *   ebar_l = sum_species eps(lambda_l) dconc,  yhat = ebar_l * Jmu,  r = yhat - y_obs,
+ *   f = 1/2 sum weights^2 |r|^2,
+ *   grad_dconc[sp] = Re sum conj(weights^2 r) eps_sp(lambda_l) Jmu,
+ *   w_adj = ebar_l * weights^2 * r   (input of hydot_born_apply_adjoint for df/dmu = Re J^H w_adj).
+ * Jmu, y_obs, w_adj: device [n_lambda][S][D] complex of dtype C128 or C64 (all the same).
+ * weights: device [n_lambda][S][D] real of the matching real dtype, or NULL for W = I.
+ * dconc: host [n_species].  f, grad_dconc: host outputs.  workspace >= hydot_misfit_workspace_bytes().
+ * Synchronises the stream. */
+size_t hydot_misfit_workspace_bytes(const hydot_operator* op, int32_t S, int32_t D);
+hydot_status hydot_misfit(const hydot_operator* op, int32_t S, int32_t D, const double* dconc,
+                          const void* Jmu, const void* y_obs, const void* weights, hydot_dtype dtype,
+                          void* w_adj, double* f, double* grad_dconc, void* workspace,
+                          size_t ws_bytes, hipStream_t stream);
+
+const char* hydot_last_error(void);
+const char* hydot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYDOT_H */

@@ -1,0 +1,30 @@
+"""Python binding of libhydot, the MI355X hyperspectral DOT Born hot path.
+
+Argument marshalling only: every step runs inside the HIP library
+(``libhydot.so``, C ABI in ``include/hydot.h``).  PyTorch provides device
+memory and streams.  Importing this package loads the library and fails
+loudly if it has not been built (``python -m paper_1410_0986_amd.build``).
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    HydotError,
+    Operator,
+    SolveOptions,
+    PalsOptions,
+    apply_operator,
+    solve_workspace_bytes,
+    solve_fields,
+    born_apply,
+    born_apply_adjoint,
+    pals_shape,
+    pals_shape_vjp,
+    misfit,
+    BornMisfit,
+    library_path,
+    version,
+    C128, C64, F64, F32,
+    PREC_FP64, PREC_MIXED,
+    FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM,
+    OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED,
+)

@@ -1,0 +1,367 @@
+"""ctypes marshalling for libhydot (see include/hydot.h for the contract of each call)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_uint32, c_void_p
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libhydot.so")
+
+if not os.path.exists(_LIBPATH):
+    raise ImportError(f"{_LIBPATH} is not built; run `python -m paper_1410_0986_amd.build` "
+                      "(or __graft_entry__.build()) first")
+_lib = ctypes.CDLL(_LIBPATH)
+
+OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4
+C128, C64, F64, F32 = 0, 1, 3, 4
+PREC_FP64, PREC_MIXED = 0, 1
+FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM = 0x1, 0x2, 0x4, 0x8
+
+
+class HydotError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hydot status {status}: {msg}")
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("h_mm", c_double),
+                ("A_R", c_double), ("robin_faces", c_uint32)]
+
+
+class _Optics(ctypes.Structure):
+    _fields_ = [("n_lambda", c_int32), ("mus_prime_per_mm", POINTER(c_double)), ("n_species", c_int32),
+                ("extinction", POINTER(c_double)), ("conc_uM", POINTER(c_double)),
+                ("omega_over_nu_per_mm", c_double)]
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("rel_tol", c_double), ("max_iter", c_int32), ("restart_m", c_int32),
+                ("recycle_k", c_int32), ("lanczos_n", c_int32), ("precision", c_int32),
+                ("flags", c_uint32), ("inner_tol", c_double), ("max_batch", c_int32)]
+
+
+class _PalsOpts(ctypes.Structure):
+    _fields_ = [("tau", c_double), ("eps", c_double), ("nu", c_double)]
+
+
+def _proto(name, restype, *argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(argtypes)
+    return f
+
+
+_assemble = _proto("hydot_assemble_operator", c_int32, POINTER(_Grid), POINTER(_Optics), POINTER(c_void_p))
+_free = _proto("hydot_free_operator", None, c_void_p)
+_optics = _proto("hydot_operator_optics", c_int32, c_void_p, POINTER(c_double), POINTER(c_double))
+_apply = _proto("hydot_apply_operator", c_int32, c_void_p, c_int32, POINTER(c_int32), c_void_p, c_void_p,
+                c_int32, c_void_p)
+_ws_bytes = _proto("hydot_solve_workspace_bytes", c_int32, c_void_p, c_int32, POINTER(_SolveOpts), POINTER(c_size_t))
+_solve = _proto("hydot_solve_fields", c_int32, c_void_p, c_int32, POINTER(c_int64), POINTER(_SolveOpts), c_void_p,
+                c_int32, c_void_p, c_size_t, POINTER(c_int32), POINTER(c_double), c_void_p)
+_born = _proto("hydot_born_apply", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32,
+               c_void_p, c_int32, c_void_p, c_void_p)
+_born_adj = _proto("hydot_born_apply_adjoint", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64,
+                   c_int32, c_void_p, c_void_p, c_void_p)
+_pals = _proto("hydot_pals_shape", c_int32, c_void_p, POINTER(c_double), c_int32, POINTER(_PalsOpts), c_void_p,
+               c_int32, c_void_p)
+_pals_ws = _proto("hydot_pals_workspace_bytes", c_size_t, c_void_p, c_int32)
+_pals_vjp = _proto("hydot_pals_shape_vjp", c_int32, c_void_p, POINTER(c_double), c_int32, POINTER(_PalsOpts),
+                   c_void_p, c_int32, POINTER(c_double), c_void_p, c_size_t, c_void_p)
+_misfit_ws = _proto("hydot_misfit_workspace_bytes", c_size_t, c_void_p, c_int32, c_int32)
+_misfit = _proto("hydot_misfit", c_int32, c_void_p, c_int32, c_int32, POINTER(c_double), c_void_p, c_void_p,
+                 c_void_p, c_int32, c_void_p, POINTER(c_double), POINTER(c_double), c_void_p, c_size_t, c_void_p)
+_last_error = _proto("hydot_last_error", ctypes.c_char_p)
+_version = _proto("hydot_version", ctypes.c_char_p)
+
+
+def library_path() -> str:
+    return _LIBPATH
+
+
+def version() -> str:
+    return _version().decode()
+
+
+def _check(st: int, allow_noconv: bool = False) -> int:
+    if st == OK or (allow_noconv and st == ENOCONV):
+        return st
+    raise HydotError(st, _last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def _stream(device=None) -> c_void_p:
+    return c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need_cuda(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+
+
+def _ws(nbytes: int, device) -> tuple[torch.Tensor, int]:
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    ptr = buf.data_ptr()
+    return buf, (ptr + 255) & ~255
+
+
+@dataclass
+class SolveOptions:
+    rel_tol: float = 1e-8
+    max_iter: int = 5000
+    restart_m: int = 40
+    recycle_k: int = 10
+    lanczos_n: int = 40
+    precision: int = PREC_FP64
+    flags: int = FLAG_MEAN_SHIFT
+    inner_tol: float = 1e-5
+    max_batch: int = 0
+
+    def _c(self) -> _SolveOpts:
+        return _SolveOpts(self.rel_tol, self.max_iter, self.restart_m, self.recycle_k, self.lanczos_n,
+                          self.precision, self.flags, self.inner_tol, self.max_batch)
+
+
+@dataclass
+class PalsOptions:
+    tau: float = 0.5
+    eps: float = 0.5
+    nu: float = 1e-3
+
+    def _c(self) -> _PalsOpts:
+        return _PalsOpts(self.tau, self.eps, self.nu)
+
+
+class Operator:
+    """A(lambda) on a box grid for every wavelength (hydot_assemble_operator)."""
+
+    def __init__(self, nx, ny, nz, h_mm, A_R, robin_faces, mus_prime, extinction, conc_uM, omega_over_nu):
+        self._mus = np.ascontiguousarray(mus_prime, dtype=np.float64)
+        self._ext = np.ascontiguousarray(np.atleast_2d(extinction), dtype=np.float64)
+        self._conc = np.ascontiguousarray(conc_uM, dtype=np.float64)
+        g = _Grid(int(nx), int(ny), int(nz), float(h_mm), float(A_R), int(robin_faces))
+        o = _Optics(int(self._mus.shape[0]), _dptr(self._mus), int(self._ext.shape[0]), _dptr(self._ext),
+                    _dptr(self._conc), float(omega_over_nu))
+        h = c_void_p()
+        _check(_assemble(ctypes.byref(g), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.nx, self.ny, self.nz, self.h = int(nx), int(ny), int(nz), float(h_mm)
+        self.N = self.nx * self.ny * self.nz
+        self.L = int(self._mus.shape[0])
+        self.n_species = int(self._ext.shape[0])
+        self.extinction = self._ext
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w.nx, w.ny, w.nz, w.h, w.A_R, w.robin_faces, w.mus_prime, w.extinction, w.conc_uM,
+                   w.omega_over_nu)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def optics(self):
+        D = np.empty(self.L)
+        mua = np.empty(self.L)
+        _check(_optics(self._h, _dptr(D), _dptr(mua)))
+        return D, mua
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _free(h)
+            self._h = None
+
+
+def _cdtype(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex128:
+        return C128
+    if t.dtype == torch.complex64:
+        return C64
+    raise ValueError("complex tensors must be complex128 or complex64")
+
+
+def apply_operator(op: Operator, lam_index, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    """y_v = A(lambda_v) x_v; x: [n_vec, N] complex CUDA tensor."""
+    _need_cuda(x, "x")
+    x = x.contiguous()
+    lam = np.ascontiguousarray(lam_index, dtype=np.int32)
+    if x.dim() != 2 or x.shape[1] != op.N or x.shape[0] != lam.shape[0]:
+        raise ValueError("x must be [len(lam_index), N]")
+    if y is None:
+        y = torch.empty_like(x)
+    _check(_apply(op.handle, int(lam.shape[0]), lam.ctypes.data_as(POINTER(c_int32)), c_void_p(x.data_ptr()),
+                  c_void_p(y.data_ptr()), _cdtype(x), _stream(x.device)))
+    return y
+
+
+def solve_workspace_bytes(op: Operator, n_rhs: int, opts: SolveOptions) -> int:
+    n = c_size_t()
+    o = opts._c()
+    _check(_ws_bytes(op.handle, int(n_rhs), ctypes.byref(o), ctypes.byref(n)))
+    return int(n.value)
+
+
+def solve_fields(op: Operator, rhs_voxels, opts: SolveOptions | None = None, out_dtype=torch.complex128,
+                 device="cuda", out: torch.Tensor | None = None):
+    """Fields phi [L, n_rhs, N] for unit injections at rhs_voxels (hydot_solve_fields).
+
+    Returns (phi, iters [L, n_rhs], rel_res [L, n_rhs], status) with status OK or ENOCONV.
+    """
+    opts = opts or SolveOptions()
+    vox = np.ascontiguousarray(rhs_voxels, dtype=np.int64)
+    R = int(vox.shape[0])
+    if out is None:
+        out = torch.empty((op.L, R, op.N), dtype=out_dtype, device=device)
+    _need_cuda(out, "out")
+    if not out.is_contiguous() or tuple(out.shape) != (op.L, R, op.N):
+        raise ValueError("out must be a contiguous [L, n_rhs, N] tensor")
+    o = opts._c()
+    nbytes = solve_workspace_bytes(op, R, opts)
+    buf, wptr = _ws(nbytes, out.device)
+    iters = np.zeros(op.L * R, dtype=np.int32)
+    rel = np.zeros(op.L * R, dtype=np.float64)
+    st = _solve(op.handle, R, vox.ctypes.data_as(POINTER(c_int64)), ctypes.byref(o), c_void_p(out.data_ptr()),
+                _cdtype(out), c_void_p(wptr), c_size_t(nbytes), iters.ctypes.data_as(POINTER(c_int32)),
+                _dptr(rel), _stream(out.device))
+    _check(st, allow_noconv=True)
+    del buf
+    return out, iters.reshape(op.L, R), rel.reshape(op.L, R), st
+
+
+def _field_view(op: Operator, t: torch.Tensor, name: str):
+    _need_cuda(t, name)
+    if t.dim() != 3 or t.shape[0] != op.L or t.shape[2] != op.N:
+        raise ValueError(f"{name} must be [L, count, N]")
+    if t.stride(2) != 1 or (t.shape[1] > 1 and t.stride(1) != op.N) or t.stride(0) % op.N != 0:
+        raise ValueError(f"{name} must have N-contiguous rows (a slice of an [L, R, N] field array)")
+    return t.data_ptr(), int(t.shape[1]), t.stride(0) // op.N
+
+
+def born_apply(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
+    """y[c, l, s, d] = -h^3 sum_k phi_src[l,s,k] v[c,k] phi_det[l,d,k] (hydot_born_apply)."""
+    ps, S, ls = _field_view(op, phi_src, "phi_src")
+    pd, D, ld = _field_view(op, phi_det, "phi_det")
+    if ls != ld:
+        raise ValueError("phi_src and phi_det must share the wavelength stride")
+    if phi_src.dtype != phi_det.dtype:
+        raise ValueError("phi_src and phi_det must share a dtype")
+    dt = _cdtype(phi_src)
+    rdt = torch.float64 if dt == C128 else torch.float32
+    _need_cuda(v, "v")
+    v = v.reshape(-1, op.N).to(rdt).contiguous()
+    y = torch.empty((v.shape[0], op.L, S, D), dtype=phi_src.dtype, device=phi_src.device)
+    _check(_born(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt, c_void_p(v.data_ptr()), int(v.shape[0]),
+                 c_void_p(y.data_ptr()), _stream(phi_src.device)))
+    return y
+
+
+def born_apply_adjoint(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
+    """g[k] = sum_{l,s,d} conj(J_l[s,d,k]) w[l,s,d] (hydot_born_apply_adjoint)."""
+    ps, S, ls = _field_view(op, phi_src, "phi_src")
+    pd, D, ld = _field_view(op, phi_det, "phi_det")
+    if ls != ld:
+        raise ValueError("phi_src and phi_det must share the wavelength stride")
+    dt = _cdtype(phi_src)
+    _need_cuda(w, "w")
+    w = w.to(phi_src.dtype).contiguous()
+    if tuple(w.shape) != (op.L, S, D):
+        raise ValueError("w must be [L, S, D]")
+    g = torch.empty(op.N, dtype=phi_src.dtype, device=phi_src.device)
+    _check(_born_adj(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt, c_void_p(w.data_ptr()),
+                     c_void_p(g.data_ptr()), _stream(phi_src.device)))
+    return g
+
+
+def pals_shape(op: Operator, p, popts: PalsOptions | None = None, dtype=torch.float64, device="cuda") -> torch.Tensor:
+    popts = popts or PalsOptions()
+    pv = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(-1))
+    nb = pv.shape[0] // 5
+    mu = torch.empty(op.N, dtype=dtype, device=device)
+    dt = F64 if dtype == torch.float64 else F32
+    o = popts._c()
+    _check(_pals(op.handle, _dptr(pv), nb, ctypes.byref(o), c_void_p(mu.data_ptr()), dt, _stream(mu.device)))
+    return mu
+
+
+def pals_shape_vjp(op: Operator, p, g: torch.Tensor, popts: PalsOptions | None = None) -> np.ndarray:
+    popts = popts or PalsOptions()
+    pv = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(-1))
+    nb = pv.shape[0] // 5
+    _need_cuda(g, "g")
+    g = g.contiguous()
+    dt = {torch.float64: F64, torch.float32: F32, torch.complex128: C128, torch.complex64: C64}[g.dtype]
+    nbytes = _pals_ws(op.handle, nb)
+    buf, wptr = _ws(nbytes, g.device)
+    out = np.zeros(5 * nb)
+    o = popts._c()
+    _check(_pals_vjp(op.handle, _dptr(pv), nb, ctypes.byref(o), c_void_p(g.data_ptr()), dt, _dptr(out),
+                     c_void_p(wptr), c_size_t(nbytes), _stream(g.device)))
+    del buf
+    return out
+
+
+def misfit(op: Operator, dconc, Jmu: torch.Tensor, y_obs: torch.Tensor, weights: torch.Tensor | None = None):
+    """(f, df/d dconc, w_adj) of the Born data model (hydot_misfit); Jmu, y_obs: [L, S, D]."""
+    _need_cuda(Jmu, "Jmu")
+    Jmu = Jmu.contiguous()
+    y_obs = y_obs.to(Jmu.dtype).contiguous()
+    L, S, D = Jmu.shape
+    dt = _cdtype(Jmu)
+    dc = np.ascontiguousarray(np.asarray(dconc, dtype=np.float64).reshape(-1))
+    if dc.shape[0] != op.n_species:
+        raise ValueError("dconc must have one entry per species")
+    wptr_w = None
+    if weights is not None:
+        rdt = torch.float64 if dt == C128 else torch.float32
+        weights = weights.to(rdt).contiguous()
+        wptr_w = weights.data_ptr()
+    wadj = torch.empty_like(Jmu)
+    nbytes = _misfit_ws(op.handle, S, D)
+    buf, wsp = _ws(nbytes, Jmu.device)
+    f = c_double()
+    gdc = np.zeros(op.n_species)
+    _check(_misfit(op.handle, S, D, _dptr(dc), c_void_p(Jmu.data_ptr()), c_void_p(y_obs.data_ptr()),
+                   c_void_p(wptr_w), dt, c_void_p(wadj.data_ptr()), ctypes.byref(f), _dptr(gdc), c_void_p(wsp),
+                   c_size_t(nbytes), _stream(Jmu.device)))
+    del buf
+    return float(f.value), gdc, wadj
+
+
+class BornMisfit(torch.autograd.Function):
+    """f(dconc, p) = 1/2 ||W (ebar(dconc) J mu(p) - y_obs)||^2 with a hand-written adjoint.
+
+    Forward: PaLS shape -> Born J mu -> misfit.  Backward: Born adjoint J^H (ebar W^2 r)
+    -> PaLS vector-Jacobian product; df/d dconc comes from the misfit kernel.
+    dconc and p are CPU float64 tensors; the fields stay on the GPU.
+    """
+
+    @staticmethod
+    def forward(ctx, dconc, p, op, phi_src, phi_det, y_obs, popts=None, weights=None):
+        popts = popts or PalsOptions()
+        rdt = torch.float64 if phi_src.dtype == torch.complex128 else torch.float32
+        pn = p.detach().cpu().numpy().astype(np.float64)
+        mu = pals_shape(op, pn, popts, dtype=rdt, device=phi_src.device)
+        Jmu = born_apply(op, phi_src, phi_det, mu[None])[0]
+        f, gdc, wadj = misfit(op, dconc.detach().cpu().numpy(), Jmu, y_obs, weights)
+        ctx.op, ctx.popts = op, popts
+        ctx.fields = (phi_src, phi_det)
+        ctx.wadj, ctx.pn, ctx.gdc = wadj, pn, gdc
+        return torch.tensor(f, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gf):
+        phi_src, phi_det = ctx.fields
+        g = born_apply_adjoint(ctx.op, phi_src, phi_det, ctx.wadj)
+        gp = pals_shape_vjp(ctx.op, ctx.pn, g, ctx.popts)
+        s = float(gf)
+        return (torch.from_numpy(s * ctx.gdc), torch.from_numpy(s * gp), None, None, None, None, None, None)

@@ -1,0 +1,364 @@
+// Matrix-free Born products (Sec. 2.1 integral equation with the adjoint field;
+// rows of H in eq. measurement), never forming J:
+//   J v  : y[c][l][s][d] = -h^3 sum_k phi_s(k) v_c(k) phi_d(k)   (per wavelength a
+//          dense contraction Phi_s^T diag(v) Phi_d over the voxels),
+//   J^H w: g[k] = -h^3 sum_l sum_d conj(phi_d(k)) sum_s conj(phi_s(k)) w[l][s][d].
+//
+// Complex products run on real MFMA tiles by real-ification: the operand rows
+// are [Re; Im] of the complex rows, so one real product carries all four real
+// partial products of the complex one.  FP32 fields use
+// v_mfma_f32_16x16x4_f32 with per-stage FP64 accumulation and FP64 split-K
+// sums; FP64 fields use v_mfma_f64_16x16x4_f64.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "operator.h"
+
+namespace hydot {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  using acc = f32x4;
+  __device__ static inline acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<double> {
+  using acc = f64x4;
+  __device__ static inline acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr size_t kLdsCap = 64 * 1024;   // LDS budget per block
+
+inline int pad8(int x) { return (x + 7) / 8 * 8; }
+
+// ---------------------------------------------------------------- J v
+// Block = 4 waves on one (split, wavelength, probe vector).  Rows of the real
+// product: a < Sp -> Re(phi_s v), a >= Sp -> Im(phi_s v); columns b < Dp ->
+// Re phi_d, b >= Dp -> Im phi_d.  Wave w owns output tiles w, w+4, ...
+template <typename T, int TPW, int kKT>
+__global__ __launch_bounds__(kBlock) void k_born_apply(int N, int S, int D, int Sp, int Dp, int64_t lam_stride,
+                                                      const cplx<T>* __restrict__ phs,
+                                                      const cplx<T>* __restrict__ phd,
+                                                      const T* __restrict__ v, int kb, int L,
+                                                      double* __restrict__ part) {
+  constexpr int kKTP = kKT + 4;         // padded LDS row
+  extern __shared__ unsigned char smem_raw[];
+  T* As = (T*)smem_raw;                 // [2Sp][kKTP]
+  T* Bs = As + 2 * Sp * kKTP;           // [2Dp][kKTP]
+  T* vs = Bs + 2 * Dp * kKTP;           // [kKT]
+  const int split = blockIdx.x, l = blockIdx.y, c = blockIdx.z;
+  const int nsplit = gridDim.x;
+  const int k0 = split * kb, k1 = min(N, k0 + kb);
+  const int TA = 2 * Sp / 16, TB = 2 * Dp / 16, T_all = TA * TB;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const cplx<T>* ps = phs + (size_t)l * lam_stride * N;
+  const cplx<T>* pd = phd + (size_t)l * lam_stride * N;
+  const T* vc = v + (size_t)c * N;
+  using MA = typename Mfma<T>::acc;
+  MA acc[TPW];
+  f64x4 tot[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    acc[t] = MA{0, 0, 0, 0};
+    tot[t] = f64x4{0, 0, 0, 0};
+  }
+  for (int kbase = k0; kbase < k1; kbase += kKT) {
+    const int kn = min(kKT, k1 - kbase);
+    for (int i = threadIdx.x; i < kKT; i += kBlock) vs[i] = i < kn ? vc[kbase + i] : (T)0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < Sp * kKT; i += kBlock) {
+      const int s = i / kKT, kk = i % kKT;
+      cplx<T> z{0, 0};
+      if (s < S && kk < kn) z = ps[(size_t)s * N + kbase + kk];
+      const T vv = vs[kk];
+      As[s * kKTP + kk] = z.re * vv;
+      As[(Sp + s) * kKTP + kk] = z.im * vv;
+    }
+    for (int i = threadIdx.x; i < Dp * kKT; i += kBlock) {
+      const int d = i / kKT, kk = i % kKT;
+      cplx<T> z{0, 0};
+      if (d < D && kk < kn) z = pd[(size_t)d * N + kbase + kk];
+      Bs[d * kKTP + kk] = z.re;
+      Bs[(Dp + d) * kKTP + kk] = z.im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int tile = wave + 4 * t;
+      if (tile < T_all) {
+        const int ta = tile / TB, tb = tile % TB;
+        const T* arow = As + (ta * 16 + (lane & 15)) * kKTP + (lane >> 4);
+        const T* brow = Bs + (tb * 16 + (lane & 15)) * kKTP + (lane >> 4);
+#pragma unroll
+        for (int kk = 0; kk < kKT; kk += 4) acc[t] = Mfma<T>::step(arow[kk], brow[kk], acc[t]);
+        // FP64 accumulation across stages
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[t][r] += (double)acc[t][r];
+        acc[t] = MA{0, 0, 0, 0};
+      }
+    }
+    __syncthreads();
+  }
+  // partial tile sums: part[((c*L + l)*nsplit + split)][2Sp][2Dp]
+  double* out = part + ((size_t)(c * L + l) * nsplit + split) * (size_t)(2 * Sp) * (2 * Dp);
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wave + 4 * t;
+    if (tile < T_all) {
+      const int ta = tile / TB, tb = tile % TB;
+      const int col = tb * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = ta * 16 + 4 * (lane >> 4) + r;
+        out[(size_t)row * (2 * Dp) + col] = tot[t][r];
+      }
+    }
+  }
+}
+
+// Sum the split-K partials in a fixed order and assemble the complex result.
+template <typename O>
+__global__ void k_born_apply_finish(int S, int D, int Sp, int Dp, int nsplit, int L, const double* part,
+                                    double scale, O* y) {
+  const int cl = blockIdx.x;  // c*L + l
+  const size_t tile = (size_t)(2 * Sp) * (2 * Dp);
+  for (int e = threadIdx.x; e < S * D; e += blockDim.x) {
+    const int s = e / D, d = e % D;
+    double rr = 0, ii = 0, ri = 0, ir = 0;
+    for (int sp = 0; sp < nsplit; ++sp) {
+      const double* P = part + ((size_t)cl * nsplit + sp) * tile;
+      rr += P[(size_t)s * 2 * Dp + d];
+      ii += P[(size_t)(Sp + s) * 2 * Dp + Dp + d];
+      ri += P[(size_t)s * 2 * Dp + Dp + d];
+      ir += P[(size_t)(Sp + s) * 2 * Dp + d];
+    }
+    const cd z{scale * (rr - ii), scale * (ri + ir)};
+    y[(size_t)cl * S * D + e] = Store<O>::from(z);
+  }
+}
+
+// ---------------------------------------------------------------- J^H w
+// Block = WAVES waves, 16 voxels per wave; loops over all wavelengths and keeps
+// g for its voxels in registers.  Per wavelength, T = A'' B'' on MFMA with
+// A'' = [Re phi_s | Im phi_s] (voxels x 2Sp) and B'' = [[Re w, Im w], [Im w, -Re w]]
+// (2Sp x 2Dp), giving [Re T | Im T] with T = conj(Phi_s)^T-weighted sums; the
+// epilogue contracts T with conj(phi_d) per voxel.
+template <typename T, int WAVES, int TBM>
+__global__ __launch_bounds__(64 * WAVES) void k_born_adjoint(int N, int S, int D, int Sp, int Dp, int64_t lam_stride,
+                                                            int L, const cplx<T>* __restrict__ phs,
+                                                            const cplx<T>* __restrict__ phd,
+                                                            const cplx<T>* __restrict__ w, double scale,
+                                                            cplx<T>* __restrict__ g) {
+  constexpr int VB = 16 * WAVES;      // voxels per block
+  constexpr int VP = VB + 4;          // padded
+  extern __shared__ unsigned char smem_raw[];
+  T* As = (T*)smem_raw;                          // [2Sp][VP]
+  T* Ds = As + 2 * Sp * VP;                      // [2Dp][VP]  (Re rows, then Im rows)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int vbase = blockIdx.x * VB;
+  const int TB = 2 * Dp / 16;
+  using MA = typename Mfma<T>::acc;
+  double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
+  for (int l = 0; l < L; ++l) {
+    const cplx<T>* ps = phs + (size_t)l * lam_stride * N;
+    const cplx<T>* pd = phd + (size_t)l * lam_stride * N;
+    for (int i = threadIdx.x; i < Sp * VB; i += 64 * WAVES) {
+      const int s = i / VB, vv = i % VB;
+      cplx<T> z{0, 0};
+      if (s < S && vbase + vv < N) z = ps[(size_t)s * N + vbase + vv];
+      As[s * VP + vv] = z.re;
+      As[(Sp + s) * VP + vv] = z.im;
+    }
+    for (int i = threadIdx.x; i < Dp * VB; i += 64 * WAVES) {
+      const int d = i / VB, vv = i % VB;
+      cplx<T> z{0, 0};
+      if (d < D && vbase + vv < N) z = pd[(size_t)d * N + vbase + vv];
+      Ds[d * VP + vv] = z.re;
+      Ds[(Dp + d) * VP + vv] = z.im;
+    }
+    const cplx<T>* wl = w + (size_t)l * S * D;
+    __syncthreads();
+    MA acc[TBM];
+#pragma unroll
+    for (int t = 0; t < TBM; ++t) acc[t] = MA{0, 0, 0, 0};
+    const int vox = wave * 16 + (lane & 15);
+    for (int kk = 0; kk < 2 * Sp; kk += 4) {
+      const int kidx = kk + (lane >> 4);
+      const T a = As[kidx * VP + vox];
+      const bool brow = kidx >= Sp;             // rows of Im phi_s
+      const int s = brow ? kidx - Sp : kidx;
+#pragma unroll
+      for (int t = 0; t < TBM; ++t) {
+        if (t < TB) {
+          const int col = t * 16 + (lane & 15);
+          const bool imcol = col >= Dp;
+          const int d = imcol ? col - Dp : col;
+          const cplx<T> ww = (s < S && d < D) ? wl[s * D + d] : cplx<T>{0, 0};
+          // B'' = [[Re w, Im w], [Im w, -Re w]]
+          const T b = brow ? (imcol ? -ww.re : ww.im) : (imcol ? ww.im : ww.re);
+          acc[t] = Mfma<T>::step(a, b, acc[t]);
+        }
+      }
+    }
+    // epilogue: lane holds T[voxel = wave*16 + 4*(lane/16) + r][col = t*16 + lane%16]
+#pragma unroll
+    for (int t = 0; t < TBM; ++t) {
+      if (t < TB) {
+        const int col = t * 16 + (lane & 15);
+        const bool imcol = col >= Dp;
+        const int d = imcol ? col - Dp : col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int vv = wave * 16 + 4 * (lane >> 4) + r;
+          const double e = Ds[d * VP + vv], f = Ds[(Dp + d) * VP + vv];
+          const double tv = (double)acc[t][r];
+          if (!imcol) {          // Re T column
+            gre[r] += e * tv;
+            gim[r] -= f * tv;
+          } else {               // Im T column
+            gre[r] += f * tv;
+            gim[r] += e * tv;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // reduce over the 16 lanes that share a voxel (lane & 15 varies)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      gre[r] += __shfl_xor(gre[r], off, 64);
+      gim[r] += __shfl_xor(gim[r], off, 64);
+    }
+  }
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int vv = vbase + wave * 16 + 4 * (lane >> 4) + r;
+      if (vv < N) g[vv] = cplx<T>{(T)(scale * gre[r]), (T)(scale * gim[r])};
+    }
+  }
+}
+
+template <typename T>
+hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
+                             int64_t ls, const void* v, int n_v, void* y, hipStream_t stream) {
+  const int N = op->gp.N, L = op->L;
+  const int Sp = pad8(S), Dp = pad8(D);
+  const int T_all = (2 * Sp / 16) * (2 * Dp / 16);
+  const int tpw = (T_all + 3) / 4;
+  // voxels per LDS stage: 32 when the staged rows fit the LDS budget, else 16
+  const int kt = (size_t)(2 * Sp + 2 * Dp) * 36 * sizeof(T) + 32 * sizeof(T) <= kLdsCap ? 32 : 16;
+  // split-K so the grid has a few thousand blocks
+  const int max_split = (N + kt - 1) / kt;
+  int nsplit = std::max(1, std::min(max_split, (4096 + L * n_v - 1) / (L * n_v)));
+  int kb = (N + nsplit - 1) / nsplit;
+  kb = (kb + kt - 1) / kt * kt;
+  nsplit = (N + kb - 1) / kb;
+  const size_t pbytes = (size_t)n_v * L * nsplit * (2 * Sp) * (2 * Dp) * sizeof(double);
+  void* part = nullptr;
+  HYDOT_HIP(hipMallocAsync(&part, pbytes, stream));
+  const size_t lds = (size_t)(2 * Sp + 2 * Dp) * (kt + 4) * sizeof(T) + kt * sizeof(T);
+  dim3 grid(nsplit, L, n_v);
+#define HYDOT_BA(TP, KT)                                                                                      \
+  hipLaunchKernelGGL((k_born_apply<T, TP, KT>), grid, dim3(kBlock), lds, stream, N, S, D, Sp, Dp, ls,        \
+                     (const cplx<T>*)phs, (const cplx<T>*)phd, (const T*)v, kb, L, (double*)part)
+#define HYDOT_BA_T(TP) \
+  if (kt == 32) HYDOT_BA(TP, 32); else HYDOT_BA(TP, 16);
+  if (tpw <= 1) { HYDOT_BA_T(1) }
+  else if (tpw <= 2) { HYDOT_BA_T(2) }
+  else if (tpw <= 4) { HYDOT_BA_T(4) }
+  else if (tpw <= 8) { HYDOT_BA_T(8) }
+  else { HYDOT_BA_T(16) }
+#undef HYDOT_BA_T
+#undef HYDOT_BA
+  const double h = op->grid.h_mm;
+  hipLaunchKernelGGL((k_born_apply_finish<cplx<T>>), dim3(n_v * L), dim3(256), 0, stream, S, D, Sp, Dp, nsplit, L,
+                     (const double*)part, -h * h * h, (cplx<T>*)y);
+  hipError_t e = hipGetLastError();
+  hipError_t e2 = hipFreeAsync(part, stream);
+  if (e != hipSuccess) return hip_check(e, "born_apply launch");
+  if (e2 != hipSuccess) return hip_check(e2, "born_apply free");
+  return HYDOT_OK;
+}
+
+template <typename T, int WAVES>
+hydot_status born_adjoint_launch(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
+                                 int64_t ls, const void* w, void* g, hipStream_t stream) {
+  const int N = op->gp.N, L = op->L;
+  const int Sp = pad8(S), Dp = pad8(D);
+  const int TB = 2 * Dp / 16;
+  constexpr int VB = 16 * WAVES, VP = VB + 4;
+  const size_t lds = (size_t)(2 * Sp + 2 * Dp) * VP * sizeof(T);
+  dim3 grid((N + VB - 1) / VB);
+  const double h = op->grid.h_mm;
+  const double sc = -h * h * h;
+#define HYDOT_BJ(TBM)                                                                                     \
+  hipLaunchKernelGGL((k_born_adjoint<T, WAVES, TBM>), grid, dim3(64 * WAVES), lds, stream, N, S, D, Sp, Dp, \
+                     ls, L, (const cplx<T>*)phs, (const cplx<T>*)phd, (const cplx<T>*)w, sc, (cplx<T>*)g)
+  if (TB <= 1) HYDOT_BJ(1);
+  else if (TB <= 2) HYDOT_BJ(2);
+  else if (TB <= 4) HYDOT_BJ(4);
+  else HYDOT_BJ(8);
+#undef HYDOT_BJ
+  HYDOT_HIP(hipGetLastError());
+  return HYDOT_OK;
+}
+
+// waves per block: as many as fit the LDS budget (16 voxels each)
+template <typename T>
+hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
+                               int64_t ls, const void* w, void* g, hipStream_t stream) {
+  const size_t rows = (size_t)(2 * pad8(S) + 2 * pad8(D));
+  if (rows * 68 * sizeof(T) <= kLdsCap) return born_adjoint_launch<T, 4>(op, phs, S, phd, D, ls, w, g, stream);
+  if (rows * 36 * sizeof(T) <= kLdsCap) return born_adjoint_launch<T, 2>(op, phs, S, phd, D, ls, w, g, stream);
+  return born_adjoint_launch<T, 1>(op, phs, S, phd, D, ls, w, g, stream);
+}
+
+static hydot_status born_check(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
+                               int64_t ls, hydot_dtype dt) {
+  if (!op) return fail(HYDOT_EINVAL, "born: null operator");
+  if (!phs || !phd) return fail(HYDOT_EINVAL, "born: null field pointer");
+  if (S < 1 || S > 64 || D < 1 || D > 64) return fail(HYDOT_EINVAL, "born: S and D must be in [1, 64]");
+  if (ls < std::max(S, D)) return fail(HYDOT_EINVAL, "born: lam_stride must be >= max(S, D)");
+  if (dt != HYDOT_C128 && dt != HYDOT_C64) return fail(HYDOT_EUNSUPPORTED, "born: field_dtype must be C128 or C64");
+  return HYDOT_OK;
+}
+
+}  // namespace hydot
+
+using namespace hydot;
+
+extern "C" {
+
+hydot_status hydot_born_apply(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
+                              int32_t D, int64_t lam_stride, hydot_dtype field_dtype, const void* v, int32_t n_v,
+                              void* y, hipStream_t stream) {
+  hydot_status s = born_check(op, phi_src, S, phi_det, D, lam_stride, field_dtype);
+  if (s != HYDOT_OK) return s;
+  if (!v || !y) return fail(HYDOT_EINVAL, "born_apply: null v or y");
+  if (n_v < 1 || n_v > 64) return fail(HYDOT_EINVAL, "born_apply: n_v must be in [1, 64]");
+  if (field_dtype == HYDOT_C128) return born_apply_impl<double>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
+  return born_apply_impl<float>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
+}
+
+hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
+                                      int32_t D, int64_t lam_stride, hydot_dtype field_dtype, const void* w, void* g,
+                                      hipStream_t stream) {
+  hydot_status s = born_check(op, phi_src, S, phi_det, D, lam_stride, field_dtype);
+  if (s != HYDOT_OK) return s;
+  if (!w || !g) return fail(HYDOT_EINVAL, "born_apply_adjoint: null w or g");
+  if (field_dtype == HYDOT_C128) return born_adjoint_impl<double>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
+  return born_adjoint_impl<float>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
+}
+
+}  // extern "C"

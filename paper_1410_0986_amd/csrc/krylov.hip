@@ -1,0 +1,617 @@
+// Host driver of the field solver: Algorithm 1 (augmented GMRES for
+// parametric systems, Sec. 3.1) batched over right-hand sides and wavelengths,
+// restarted with a fixed per-wavelength deflation space, with FP64 residual
+// refinement around FP64 or FP32 inner solves.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "krylov_kernels.h"
+#include "operator.h"
+#include "small_dense.h"
+
+namespace hydot {
+
+// Shift-invariant basis -> U (from V_n) and C (from V_{n+1}) for each right-hand side:
+// U[r][i] = sum_l VL[r][l] cu[r][l][i], C[r][i] = sum_l VL[r][l] cu[r][l][k+i].
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_combine_uc(GridP g, const cd* VL, int vldim, int nl1,
+                                                      const double* ucoef, int k, double* U64, double* C64,
+                                                      float* U32, float* C32, int rhs_off) {
+  const int r = blockIdx.y;
+  const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= (uint32_t)g.N) return;
+  const size_t N = (size_t)g.N;
+  const cd* Vb = VL + (size_t)r * vldim * N;
+  const double* cf = ucoef + (size_t)r * nl1 * 2 * k;
+  double acc[2 * KM];
+#pragma unroll
+  for (int i = 0; i < 2 * KM; ++i) acc[i] = 0.0;
+  for (int l = 0; l < nl1; ++l) {
+    const double v = Vb[(size_t)l * N + n].re;
+#pragma unroll
+    for (int i = 0; i < 2 * KM; ++i)
+      if (i < 2 * k) acc[i] += v * cf[l * 2 * k + i];
+  }
+  const size_t rr = (size_t)(r + rhs_off);
+  for (int i = 0; i < k; ++i) {
+    U64[(rr * k + i) * N + n] = acc[i];
+    C64[(rr * k + i) * N + n] = acc[k + i];
+    if (U32) {
+      U32[(rr * k + i) * N + n] = (float)acc[i];
+      C32[(rr * k + i) * N + n] = (float)acc[k + i];
+    }
+  }
+}
+
+// Partial Gram sums of X = [C_0..C_{k-1}, U_0.., rho U_0..] per (chunk, rhs):
+// out[r][chunk][p] for pairs p = (a <= b) in row-major upper-triangle order.
+__global__ __launch_bounds__(kBlock) void k_gram(GridP g, const double* U64, const double* C64, int k,
+                                                int rhs_off, double* part, int nchunks) {
+  const int r = blockIdx.y + rhs_off;
+  const int chunk = blockIdx.x;
+  const size_t N = (size_t)g.N;
+  const int m = 3 * k;
+  const int npairs = m * (m + 1) / 2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t base = chunk * kChunk;
+  double* out = part + ((size_t)blockIdx.y * nchunks + chunk) * npairs;
+  for (int p = wave; p < npairs; p += kWaves) {
+    // decode p -> (a, b), a <= b
+    int a = 0, rem = p;
+    while (rem >= m - a) { rem -= m - a; ++a; }
+    const int b = a + rem;
+    double acc = 0.0;
+    for (int q = lane; q < kChunk; q += 64) {
+      const uint32_t n = base + q;
+      if (n >= (uint32_t)g.N) break;
+      double va, vb;
+      {
+        const int t = a / k, i = a % k;
+        const double* src = t == 0 ? C64 : U64;
+        va = src[((size_t)r * k + i) * N + n];
+        if (t == 2) va *= (double)voxel_info(g, n).nrobin * g.inv_h;
+      }
+      {
+        const int t = b / k, i = b % k;
+        const double* src = t == 0 ? C64 : U64;
+        vb = src[((size_t)r * k + i) * N + n];
+        if (t == 2) vb *= (double)voxel_info(g, n).nrobin * g.inv_h;
+      }
+      acc += va * vb;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) out[p] = acc;
+  }
+}
+
+__global__ void k_gram_reduce(const double* part, int nchunks, int npairs, int nr, double* gram) {
+  const int r = blockIdx.x;
+  for (int p = threadIdx.x; p < npairs; p += blockDim.x) {
+    double a = 0.0;
+    for (int c = 0; c < nchunks; ++c) a += part[((size_t)r * nchunks + c) * npairs + p];
+    gram[(size_t)r * npairs + p] = a;
+  }
+}
+
+namespace {
+
+struct Plan {
+  int R, L, N;
+  int k, mk, nl, mkmax;
+  int prec;
+  bool recycle, per_system, graph, mean_shift;
+  int nb;       // systems per batch
+  int rl;       // right-hand sides per Lanczos batch (and in the U/C buffers)
+  int nchunks, ndots;
+  int npairs;
+  Small sl;
+  size_t esz;   // inner storage bytes per complex
+  // byte offsets
+  size_t o_prm, o_st, o_VL, o_U64, o_C64, o_U32, o_C32, o_gpart, o_gram, o_ucoef;
+  size_t o_V, o_W, o_Din, o_Rin, o_X, o_Rout, o_part, o_small, o_cnt, o_final, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_opts* o, Plan& p) {
+  if (!op) return fail(HYDOT_EINVAL, "solve: null operator");
+  if (!o) return fail(HYDOT_EINVAL, "solve: null options");
+  if (n_rhs < 1) return fail(HYDOT_EINVAL, "solve: n_rhs must be >= 1");
+  if (!(o->rel_tol > 0.0) || !std::isfinite(o->rel_tol)) return fail(HYDOT_EINVAL, "solve: rel_tol must be > 0");
+  if (o->max_iter < 1) return fail(HYDOT_EINVAL, "solve: max_iter must be >= 1");
+  if (o->precision != HYDOT_PREC_FP64 && o->precision != HYDOT_PREC_MIXED)
+    return fail(HYDOT_EINVAL, "solve: precision must be HYDOT_PREC_FP64 or HYDOT_PREC_MIXED");
+  if (o->flags & ~0xFu) return fail(HYDOT_EINVAL, "solve: unknown flag bits");
+  p.recycle = !(o->flags & HYDOT_FLAG_NO_RECYCLE);
+  p.k = p.recycle ? o->recycle_k : 0;
+  if (p.k < 0 || p.k > kMaxK) return fail(HYDOT_EINVAL, "solve: recycle_k must be in [0, 32]");
+  p.mk = o->restart_m - p.k;
+  if (p.mk < 1 || p.mk > kMaxMK) return fail(HYDOT_EINVAL, "solve: restart_m - recycle_k must be in [1, 128]");
+  p.nl = p.recycle ? o->lanczos_n : 0;
+  if (p.recycle && (p.nl < 1 || p.nl > kMaxMK)) return fail(HYDOT_EINVAL, "solve: lanczos_n must be in [1, 128]");
+  if (p.recycle && p.k >= p.nl) return fail(HYDOT_EINVAL, "solve: recycle_k must be < lanczos_n");
+  if (o->precision == HYDOT_PREC_MIXED && !(o->inner_tol > 0.0 && o->inner_tol < 1.0))
+    return fail(HYDOT_EINVAL, "solve: inner_tol must be in (0, 1) for the mixed path");
+  if (o->max_batch < 0) return fail(HYDOT_EINVAL, "solve: max_batch must be >= 0");
+  p.R = n_rhs;
+  p.L = op->L;
+  p.N = op->gp.N;
+  if ((int64_t)p.R * p.L > 1 << 24) return fail(HYDOT_EINVAL, "solve: too many systems");
+  p.prec = o->precision;
+  p.per_system = (o->flags & HYDOT_FLAG_PER_SYSTEM) != 0;
+  p.graph = (o->flags & HYDOT_FLAG_GRAPH) != 0;
+  p.mean_shift = (o->flags & HYDOT_FLAG_MEAN_SHIFT) != 0;
+  p.mkmax = std::max(p.mk, p.nl);
+  const int total_sys = p.R * p.L;
+  if (p.per_system) {
+    p.nb = 1;
+    p.rl = 1;
+  } else {
+    p.nb = o->max_batch > 0 ? std::min(o->max_batch, total_sys) : total_sys;
+    p.rl = p.R;
+  }
+  if (p.nb > 65535 || p.rl > 65535) return fail(HYDOT_EINVAL, "solve: batch above 65535 systems; set max_batch");
+  p.nchunks = (p.N + kChunk - 1) / kChunk;
+  p.ndots = 3 * p.k + p.mkmax + 2;
+  p.npairs = 3 * p.k * (3 * p.k + 1) / 2;
+  p.sl = make_small(p.k, p.mkmax, p.nl);
+  p.esz = p.prec == HYDOT_PREC_FP64 ? sizeof(cd) : sizeof(cf);
+  const size_t N = (size_t)p.N;
+  const int ns = std::max(p.nb, p.rl);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
+  p.o_prm = take((size_t)ns * sizeof(SysParam));
+  p.o_st = take((size_t)ns * sizeof(SysState));
+  p.o_VL = take(p.recycle ? (size_t)p.rl * (p.nl + 1) * N * sizeof(cd) : 0);
+  const size_t ucount = (size_t)p.rl * p.k * N;
+  p.o_U64 = take(ucount * sizeof(double));
+  p.o_C64 = take(ucount * sizeof(double));
+  p.o_U32 = take(p.prec == HYDOT_PREC_MIXED ? ucount * sizeof(float) : 0);
+  p.o_C32 = take(p.prec == HYDOT_PREC_MIXED ? ucount * sizeof(float) : 0);
+  p.o_gpart = take((size_t)p.rl * p.nchunks * p.npairs * sizeof(double));
+  p.o_gram = take((size_t)p.rl * p.npairs * sizeof(double));
+  p.o_ucoef = take((size_t)p.rl * (p.nl + 1) * 2 * p.k * sizeof(double));
+  p.o_V = take((size_t)p.nb * (p.mk + 1) * N * p.esz);
+  p.o_W = take(std::max((size_t)p.nb * p.esz, (size_t)p.rl * sizeof(cd)) * N);
+  p.o_Din = take((size_t)p.nb * N * p.esz);
+  p.o_Rin = take((size_t)p.nb * N * p.esz);
+  p.o_X = take((size_t)p.nb * N * sizeof(cd));
+  p.o_Rout = take((size_t)p.nb * N * sizeof(cd));
+  p.o_part = take((size_t)ns * p.nchunks * p.ndots * sizeof(cd));
+  p.o_small = take((size_t)ns * p.sl.total * sizeof(cd));
+  p.o_cnt = take(64);
+  p.o_final = take((size_t)ns * sizeof(double));
+  p.total = off;
+  return HYDOT_OK;
+}
+
+// host-side per-right-hand-side set-up data
+struct RhsSetup {
+  std::vector<double> Hbar;   // (nl+1) x nl
+  std::vector<double> gram;   // npairs
+};
+
+struct Solver {
+  const hydot_operator* op;
+  Plan p;
+  char* ws;
+  hipStream_t stream;
+  const hydot_solve_opts* o;
+  std::vector<RhsSetup> rs;   // per right-hand side (global index)
+  const int64_t* rhs_vox;
+
+  template <typename T> T* at(size_t off) const { return (T*)(ws + off); }
+
+  double sigp_mean() const { return p.mean_shift ? op->sigp_mean : 0.0; }
+
+  template <typename S>
+  Ctx<S> ctx(int k, bool lanczos) const {
+    Ctx<S> c;
+    c.g = op->gp;
+    c.k = k;
+    c.mkmax = p.mkmax;
+    c.nchunks = p.nchunks;
+    c.prm = at<SysParam>(p.o_prm);
+    c.st = at<SysState>(p.o_st);
+    c.V = lanczos ? (S*)at<cd>(p.o_VL) : at<S>(p.o_V);
+    c.vdim = lanczos ? p.nl + 1 : p.mk + 1;
+    c.W = at<S>(p.o_W);
+    c.Din = at<S>(p.o_Din);
+    c.Rin = at<S>(p.o_Rin);
+    c.X = at<cd>(p.o_X);
+    c.Rout = at<cd>(p.o_Rout);
+    using R = typename Store<S>::real;
+    if (sizeof(R) == sizeof(double)) {
+      c.C = (const R*)at<double>(p.o_C64);
+      c.U = (const R*)at<double>(p.o_U64);
+    } else {
+      c.C = (const R*)at<float>(p.o_C32);
+      c.U = (const R*)at<float>(p.o_U32);
+    }
+    c.part = at<cd>(p.o_part);
+    c.ndots = p.ndots;
+    c.small = at<cd>(p.o_small);
+    c.sl = p.sl;
+    c.counter = at<int>(p.o_cnt);
+    return c;
+  }
+
+  hydot_status read_counters(int* h) {
+    HYDOT_HIP(hipMemcpyAsync(h, at<int>(p.o_cnt), 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipStreamSynchronize(stream));
+    return HYDOT_OK;
+  }
+
+  // ---------------------------------------------------------------- Lanczos
+  // Shift-invariant Krylov basis of K_hat for right-hand sides [r0, r0+nr) (Alg. 1 step 1),
+  // then U, C (steps 2-4) and the Gram blocks used by the per-wavelength update (Sec. 3.2).
+  hydot_status setup_rhs(int r0, int nr, int buf_off) {
+    const size_t N = (size_t)p.N;
+    const int nl = p.nl, k = p.k;
+    std::vector<SysParam> prm(nr);
+    std::vector<SysState> st(nr);
+    for (int i = 0; i < nr; ++i) {
+      SysParam& q = prm[i];
+      std::memset(&q, 0, sizeof(q));
+      q.sig = cd{0.0, 0.0};
+      q.sigp_abs = sigp_mean();
+      q.sigp_rel = 0.0;
+      q.rhs = i;
+      q.voxel = (int32_t)rhs_vox[r0 + i];
+      std::memset(&st[i], 0, sizeof(SysState));
+      st[i].in_cycle = 1;
+      st[i].cyc_ran = 1;
+    }
+    HYDOT_HIP(hipMemcpyAsync(at<SysParam>(p.o_prm), prm.data(), nr * sizeof(SysParam), hipMemcpyHostToDevice, stream));
+    HYDOT_HIP(hipMemcpyAsync(at<SysState>(p.o_st), st.data(), nr * sizeof(SysState), hipMemcpyHostToDevice, stream));
+    Ctx<cd> c = ctx<cd>(0, true);
+    ReduceArgs ra{};
+    ra.mk = nl;
+    ra.lanczos = 1;
+    ra.max_iter = 1 << 30;
+    dim3 gv(p.nchunks, nr);
+    hipLaunchKernelGGL(k_unit_v0<cd>, gv, dim3(kBlock), 0, stream, c);
+    for (int j = 0; j < nl; ++j) {
+      hipLaunchKernelGGL(k_step_dots<cd>, gv, dim3(kBlock), 0, stream, c, j);
+      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j);
+      hipLaunchKernelGGL(k_step_update<cd>, gv, dim3(kBlock), 0, stream, c, j);
+      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j);
+      hipLaunchKernelGGL(k_step_finish<cd>, gv, dim3(kBlock), 0, stream, c, j);
+    }
+    HYDOT_HIP(hipGetLastError());
+    // Hessenberg matrices back to the host
+    std::vector<cd> smalls((size_t)nr * p.sl.total);
+    std::vector<SysState> st_out(nr);
+    HYDOT_HIP(hipMemcpyAsync(smalls.data(), at<cd>(p.o_small), smalls.size() * sizeof(cd), hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipMemcpyAsync(st_out.data(), at<SysState>(p.o_st), nr * sizeof(SysState), hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipStreamSynchronize(stream));
+    const int ldh = p.mkmax + 1;
+    std::vector<double> ucoef((size_t)nr * (nl + 1) * 2 * k, 0.0);
+    for (int i = 0; i < nr; ++i) {
+      if (st_out[i].nsteps < nl)
+        return fail(HYDOT_EUNSUPPORTED, "solve: shift-invariant Krylov space exhausted before lanczos_n steps; lower lanczos_n");
+      RhsSetup& R = rs[r0 + i];
+      R.Hbar.assign((size_t)(nl + 1) * nl, 0.0);
+      const cd* H = smalls.data() + (size_t)i * p.sl.total + p.sl.H;
+      for (int jj = 0; jj < nl; ++jj)
+        for (int ii = 0; ii <= std::min(jj + 1, nl); ++ii) R.Hbar[ii + (size_t)(nl + 1) * jj] = H[ii + ldh * jj].re;
+      if (k == 0) continue;
+      std::vector<double> Zk, th;
+      if (!dense::harmonic_ritz(nl, k, R.Hbar, Zk, th))
+        return fail(HYDOT_EDEVICE, "solve: projected operator not positive definite in harmonic-Ritz step");
+      // P = Hbar Zk, thin QR P = Qs Y, U = V_n Zk Y^-1, C = V_{n+1} Qs  (Alg. 1 steps 3-4)
+      std::vector<double> P((size_t)(nl + 1) * k, 0.0);
+      for (int cc = 0; cc < k; ++cc)
+        for (int rr = 0; rr <= nl; ++rr) {
+          double s = 0.0;
+          for (int q = 0; q < nl; ++q) s += R.Hbar[rr + (size_t)(nl + 1) * q] * Zk[q + (size_t)nl * cc];
+          P[rr + (size_t)(nl + 1) * cc] = s;
+        }
+      std::vector<double> Qs, Y;
+      dense::thin_qr(nl + 1, k, P, Qs, Y);
+      std::vector<double> ZY((size_t)nl * k, 0.0);   // Zk Y^-1 (row-wise triangular solve)
+      for (int rr = 0; rr < nl; ++rr)
+        for (int cc = 0; cc < k; ++cc) {
+          double s = Zk[rr + (size_t)nl * cc];
+          for (int q = 0; q < cc; ++q) s -= ZY[rr + (size_t)nl * q] * Y[q + (size_t)k * cc];
+          ZY[rr + (size_t)nl * cc] = s / Y[cc + (size_t)k * cc];
+        }
+      double* uc = ucoef.data() + (size_t)i * (nl + 1) * 2 * k;
+      for (int l = 0; l <= nl; ++l)
+        for (int cc = 0; cc < k; ++cc) {
+          uc[l * 2 * k + cc] = l < nl ? ZY[l + (size_t)nl * cc] : 0.0;
+          uc[l * 2 * k + k + cc] = Qs[l + (size_t)(nl + 1) * cc];
+        }
+    }
+    if (k == 0) return HYDOT_OK;
+    HYDOT_HIP(hipMemcpyAsync(at<double>(p.o_ucoef), ucoef.data(), ucoef.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    dim3 gu((p.N + kBlock - 1) / kBlock, nr);
+    const bool mixed = p.prec == HYDOT_PREC_MIXED;
+    float* U32 = mixed ? at<float>(p.o_U32) : nullptr;
+    float* C32 = mixed ? at<float>(p.o_C32) : nullptr;
+    const cd* VL = at<cd>(p.o_VL);
+#define HYDOT_UC(KM)                                                                                          \
+  hipLaunchKernelGGL(k_combine_uc<KM>, gu, dim3(kBlock), 0, stream, op->gp, VL, nl + 1, nl + 1,               \
+                     at<double>(p.o_ucoef), k, at<double>(p.o_U64), at<double>(p.o_C64), U32, C32, buf_off)
+    if (k <= 8) HYDOT_UC(8);
+    else if (k <= 16) HYDOT_UC(16);
+    else HYDOT_UC(32);
+#undef HYDOT_UC
+    hipLaunchKernelGGL(k_gram, dim3(p.nchunks, nr), dim3(kBlock), 0, stream, op->gp, at<double>(p.o_U64),
+                       at<double>(p.o_C64), k, buf_off, at<double>(p.o_gpart), p.nchunks);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nr), dim3(256), 0, stream, at<double>(p.o_gpart), p.nchunks, p.npairs, nr,
+                       at<double>(p.o_gram));
+    HYDOT_HIP(hipGetLastError());
+    std::vector<double> gram((size_t)nr * p.npairs);
+    HYDOT_HIP(hipMemcpyAsync(gram.data(), at<double>(p.o_gram), gram.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipStreamSynchronize(stream));
+    for (int i = 0; i < nr; ++i) rs[r0 + i].gram.assign(gram.begin() + (size_t)i * p.npairs, gram.begin() + (size_t)(i + 1) * p.npairs);
+    return HYDOT_OK;
+  }
+
+  // Per-wavelength deflation basis (Alg. 1 steps 7-8 with the Gram update of Sec. 3.2):
+  // G_j = C_j'^H C_j' from the Gram of [C, U, rho U] with weights (1, sigma, sigma'_rel);
+  // returns its lower Cholesky factor.
+  hydot_status gram_factor(int r, cd sig, double sp, std::vector<dense::zc>& Lf) {
+    const int k = p.k, m = 3 * k;
+    const std::vector<double>& gm = rs[r].gram;
+    auto gam = [&](int a, int b) -> double {
+      if (a > b) std::swap(a, b);
+      // row-major upper triangle index
+      const int idx = a * m - a * (a - 1) / 2 + (b - a);
+      return gm[idx];
+    };
+    const dense::zc w[3] = {dense::zc(1.0, 0.0), dense::zc(sig.re, sig.im), dense::zc(sp, 0.0)};
+    std::vector<dense::zc> G((size_t)k * k);
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i < k; ++i) {
+        dense::zc s(0.0, 0.0);
+        for (int t = 0; t < 3; ++t)
+          for (int u = 0; u < 3; ++u) s += std::conj(w[t]) * w[u] * gam(t * k + i, u * k + j);
+        G[i + (size_t)k * j] = s;
+      }
+    if (!dense::chol_herm(k, G, Lf))
+      return fail(HYDOT_EDEVICE, "solve: per-wavelength deflation Gram matrix is not positive definite");
+    return HYDOT_OK;
+  }
+
+  // ----------------------------------------------------------- one batch
+  template <typename S>
+  void launch_cycle(const Ctx<S>& c, const ReduceArgs& ra, int nb) {
+    dim3 gv(p.nchunks, nb), gr(nb);
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, c.counter);
+    hipLaunchKernelGGL(k_inner_resid<S>, gv, dim3(kBlock), 0, stream, c);
+    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0);
+    hipLaunchKernelGGL(k_defl_start<S>, gv, dim3(kBlock), 0, stream, c);
+    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0);
+    hipLaunchKernelGGL(k_scale_v0<S>, gv, dim3(kBlock), 0, stream, c);
+    for (int j = 0; j < p.mk; ++j) {
+      hipLaunchKernelGGL(k_step_dots<S>, gv, dim3(kBlock), 0, stream, c, j);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j);
+      hipLaunchKernelGGL(k_step_update<S>, gv, dim3(kBlock), 0, stream, c, j);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j);
+      if (j + 1 < p.mk) hipLaunchKernelGGL(k_step_finish<S>, gv, dim3(kBlock), 0, stream, c, j);
+    }
+    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_CYCLE_END, 0);
+    hipLaunchKernelGGL(k_cycle_update<S>, gv, dim3(kBlock), 0, stream, c);
+  }
+
+  template <typename S>
+  hydot_status run_batch(const std::vector<int>& sys_r, const std::vector<int>& sys_l, int buf_rhs_base,
+                         void* phi, hydot_dtype phi_dtype, std::vector<int32_t>& iters,
+                         std::vector<double>& res) {
+    const int nb = (int)sys_r.size();
+    const size_t N = (size_t)p.N;
+    const double h3 = op->grid.h_mm * op->grid.h_mm * op->grid.h_mm;
+    std::vector<SysParam> prm(nb);
+    std::vector<SysState> st(nb);
+    const int lc_len = p.k * p.k + p.nl;
+    std::vector<cd> lcy((size_t)nb * std::max(lc_len, 1), cd{0.0, 0.0});
+    for (int i = 0; i < nb; ++i) {
+      const int r = sys_r[i], l = sys_l[i];
+      SysParam& q = prm[i];
+      std::memset(&q, 0, sizeof(q));
+      q.sig = op->sigma[l];
+      q.sigp_abs = op->sigp[l];
+      q.sigp_rel = op->sigp[l] - sigp_mean();
+      q.out_scale = 1.0 / (op->D[l] * h3);
+      q.rhs = r - buf_rhs_base;
+      q.voxel = (int32_t)rhs_vox[r];
+      q.lam = l;
+      q.gsys = l * p.R + r;
+      std::memset(&st[i], 0, sizeof(SysState));
+      st[i].in_sweep = 1;
+      cd* dst = lcy.data() + (size_t)i * lc_len;
+      if (p.k > 0) {
+        std::vector<dense::zc> Lf;
+        hydot_status s = gram_factor(r, q.sig, q.sigp_rel, Lf);
+        if (s != HYDOT_OK) return s;
+        for (int t = 0; t < p.k * p.k; ++t) dst[t] = cd{Lf[t].real(), Lf[t].imag()};
+      }
+      if (p.nl > 0) {
+        std::vector<dense::zc> y;
+        dense::shifted_ls(p.nl, rs[r].Hbar, dense::zc(q.sig.re, q.sig.im), 1.0, y);
+        for (int t = 0; t < p.nl; ++t) dst[p.k * p.k + t] = cd{y[t].real(), y[t].imag()};
+      }
+    }
+    HYDOT_HIP(hipMemcpyAsync(at<SysParam>(p.o_prm), prm.data(), nb * sizeof(SysParam), hipMemcpyHostToDevice, stream));
+    HYDOT_HIP(hipMemcpyAsync(at<SysState>(p.o_st), st.data(), nb * sizeof(SysState), hipMemcpyHostToDevice, stream));
+    if (lc_len > 0)
+      HYDOT_HIP(hipMemcpy2DAsync(at<cd>(p.o_small) + p.sl.Lc, p.sl.total * sizeof(cd), lcy.data(), lc_len * sizeof(cd),
+                                 lc_len * sizeof(cd), nb, hipMemcpyHostToDevice, stream));
+    Ctx<S> c = ctx<S>(p.k, false);
+    Ctx<cd> c64 = ctx<cd>(p.k, false);   // FP64 views for residual and output kernels
+    ReduceArgs ra{};
+    ra.tol = o->rel_tol;
+    ra.inner_floor = p.prec == HYDOT_PREC_MIXED ? o->inner_tol : 0.0;
+    ra.max_iter = o->max_iter;
+    ra.max_sweeps = p.prec == HYDOT_PREC_MIXED ? 40 : 20;
+    ra.mk = p.mk;
+    ra.lanczos = 0;
+    ra.final_res = at<double>(p.o_final);
+    dim3 gv(p.nchunks, nb), gr(nb);
+    if (p.nl > 0)
+      hipLaunchKernelGGL(k_combine_x0<S>, gv, dim3(kBlock), 0, stream, c, at<cd>(p.o_VL), p.nl + 1, p.nl);
+    else
+      hipLaunchKernelGGL(k_zero_x<S>, gv, dim3(kBlock), 0, stream, c);
+    HYDOT_HIP(hipGetLastError());
+
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int cnt[2] = {0, 0};
+    const int max_cycles = o->max_iter / std::max(p.mk, 1) + 2;
+    hydot_status status = HYDOT_OK;
+    for (int sweep = 0; sweep < ra.max_sweeps + 2 && status == HYDOT_OK; ++sweep) {
+      hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, c.counter);
+      hipLaunchKernelGGL(k_outer_resid<S>, gv, dim3(kBlock), 0, stream, c, 0);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_OUTER, 0);
+      HYDOT_HIP(hipGetLastError());
+      if ((status = read_counters(cnt)) != HYDOT_OK) break;
+      if (cnt[0] == 0) break;
+      hipLaunchKernelGGL(k_rhs_in<S>, gv, dim3(kBlock), 0, stream, c);
+      for (int cyc = 0; cyc < max_cycles; ++cyc) {
+        if (p.graph) {
+          if (!gexec) {
+            HYDOT_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            launch_cycle<S>(c, ra, nb);
+            HYDOT_HIP(hipStreamEndCapture(stream, &graph));
+            HYDOT_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+          }
+          HYDOT_HIP(hipGraphLaunch(gexec, stream));
+        } else {
+          launch_cycle<S>(c, ra, nb);
+        }
+        HYDOT_HIP(hipGetLastError());
+        if ((status = read_counters(cnt)) != HYDOT_OK) break;
+        if (cnt[1] == 0) break;
+      }
+      hipLaunchKernelGGL(k_outer_update<S>, gv, dim3(kBlock), 0, stream, c);
+    }
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (status != HYDOT_OK) return status;
+    // output fields and the FP64 residual of the FP64 iterate
+    if (phi_dtype == HYDOT_C128)
+      hipLaunchKernelGGL((k_output<cd, cd>), gv, dim3(kBlock), 0, stream, c64, (cd*)phi);
+    else
+      hipLaunchKernelGGL((k_output<cd, cf>), gv, dim3(kBlock), 0, stream, c64, (cf*)phi);
+    hipLaunchKernelGGL(k_outer_resid<cd>, gv, dim3(kBlock), 0, stream, c64, 1);
+    hipLaunchKernelGGL(k_reduce<cd>, gr, dim3(64), 0, stream, c64, ra, (int)PH_FINAL, 0);
+    HYDOT_HIP(hipGetLastError());
+    std::vector<SysState> so(nb);
+    std::vector<double> fr(nb);
+    HYDOT_HIP(hipMemcpyAsync(so.data(), at<SysState>(p.o_st), nb * sizeof(SysState), hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipMemcpyAsync(fr.data(), at<double>(p.o_final), nb * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipStreamSynchronize(stream));
+    for (int i = 0; i < nb; ++i) {
+      const int g = prm[i].gsys;
+      iters[g] = so[i].total_iters;
+      res[g] = fr[i];
+    }
+    (void)N;
+    return HYDOT_OK;
+  }
+
+  template <typename S>
+  hydot_status solve_all(void* phi, hydot_dtype phi_dtype, std::vector<int32_t>& iters, std::vector<double>& res) {
+    rs.assign(p.R, RhsSetup());
+    if (p.per_system) {
+      for (int r = 0; r < p.R; ++r) {
+        if (p.recycle) {
+          hydot_status s = setup_rhs(r, 1, 0);
+          if (s != HYDOT_OK) return s;
+        }
+        for (int l = 0; l < p.L; ++l) {
+          hydot_status s = run_batch<S>({r}, {l}, r, phi, phi_dtype, iters, res);
+          if (s != HYDOT_OK) return s;
+        }
+      }
+      return HYDOT_OK;
+    }
+    if (p.recycle) {
+      hydot_status s = setup_rhs(0, p.R, 0);
+      if (s != HYDOT_OK) return s;
+    }
+    // rhs-major system order; batches of nb
+    const int total = p.R * p.L;
+    for (int s0 = 0; s0 < total; s0 += p.nb) {
+      const int nb = std::min(p.nb, total - s0);
+      std::vector<int> sr(nb), sl(nb);
+      for (int i = 0; i < nb; ++i) {
+        sr[i] = (s0 + i) / p.L;
+        sl[i] = (s0 + i) % p.L;
+      }
+      hydot_status s = run_batch<S>(sr, sl, 0, phi, phi_dtype, iters, res);
+      if (s != HYDOT_OK) return s;
+    }
+    return HYDOT_OK;
+  }
+};
+
+}  // namespace
+}  // namespace hydot
+
+using namespace hydot;
+
+extern "C" {
+
+hydot_status hydot_solve_workspace_bytes(const hydot_operator* op, int32_t n_rhs, const hydot_solve_opts* opts,
+                                         size_t* bytes) {
+  if (!bytes) return fail(HYDOT_EINVAL, "solve_workspace_bytes: null output");
+  Plan p;
+  hydot_status s = make_plan(op, n_rhs, opts, p);
+  if (s != HYDOT_OK) return s;
+  *bytes = p.total;
+  return HYDOT_OK;
+}
+
+hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
+                                const hydot_solve_opts* opts, void* phi, hydot_dtype phi_dtype, void* workspace,
+                                size_t ws_bytes, int32_t* iters, double* rel_res, hipStream_t stream) {
+  Plan p;
+  hydot_status s = make_plan(op, n_rhs, opts, p);
+  if (s != HYDOT_OK) return s;
+  if (!rhs_voxel || !phi || !workspace) return fail(HYDOT_EINVAL, "solve: null pointer argument");
+  if (phi_dtype != HYDOT_C128 && phi_dtype != HYDOT_C64) return fail(HYDOT_EUNSUPPORTED, "solve: phi_dtype must be C128 or C64");
+  if (((uintptr_t)workspace & 255u) != 0) return fail(HYDOT_EINVAL, "solve: workspace must be 256-byte aligned");
+  if (ws_bytes < p.total) return fail(HYDOT_ENOMEM, "solve: workspace smaller than hydot_solve_workspace_bytes");
+  for (int r = 0; r < n_rhs; ++r)
+    if (rhs_voxel[r] < 0 || rhs_voxel[r] >= (int64_t)p.N) return fail(HYDOT_EINVAL, "solve: rhs voxel out of range");
+  hipStream_t st = stream;
+  bool own = false;
+  if (p.graph && st == nullptr) {  // capture needs a non-legacy stream
+    HYDOT_HIP(hipStreamCreate(&st));
+    own = true;
+  }
+  Solver sv;
+  sv.op = op;
+  sv.p = p;
+  sv.ws = (char*)workspace;
+  sv.stream = st;
+  sv.o = opts;
+  sv.rhs_vox = rhs_voxel;
+  std::vector<int32_t> it((size_t)p.R * p.L, 0);
+  std::vector<double> rr((size_t)p.R * p.L, 0.0);
+  if (p.prec == HYDOT_PREC_FP64)
+    s = sv.solve_all<cd>(phi, phi_dtype, it, rr);
+  else
+    s = sv.solve_all<cf>(phi, phi_dtype, it, rr);
+  if (own) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  if (s != HYDOT_OK) return s;
+  bool all = true;
+  for (size_t i = 0; i < rr.size(); ++i)
+    if (!(rr[i] <= opts->rel_tol)) all = false;
+  if (iters) std::memcpy(iters, it.data(), it.size() * sizeof(int32_t));
+  if (rel_res) std::memcpy(rel_res, rr.data(), rr.size() * sizeof(double));
+  if (!all) return fail(HYDOT_ENOCONV, "solve: some systems did not reach rel_tol (see rel_res)");
+  return HYDOT_OK;
+}
+
+}  // extern "C"

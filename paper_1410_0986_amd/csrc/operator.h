@@ -1,0 +1,25 @@
+// Internal definition of the opaque operator handle.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+struct hydot_operator {
+  hydot_grid grid;
+  hydot::GridP gp;
+  int L = 0;                      // wavelengths
+  int nsp = 0;                    // chromophore species
+  double omega_over_nu = 0.0;
+  std::vector<double> ext;        // [nsp][L] extinction
+  std::vector<double> conc;       // [nsp] background concentrations
+  std::vector<double> D;          // [L] diffusion coefficient D_lambda = 1/(3 mu_s')
+  std::vector<double> mua;        // [L] background absorption
+  std::vector<hydot::cd> sigma;   // [L] (mu_a + i omega/nu)/D
+  std::vector<double> sigp;       // [L] 1/(2 A_R D)
+  double sigp_mean = 0.0;         // mean of sigma' over wavelengths
+};
+
+namespace hydot {
+GridP make_gridp(const hydot_grid& g);
+}

@@ -1,0 +1,177 @@
+"""C-ABI tests that need no GPU: the library loads, exports every declared symbol,
+validates its arguments before any launch, and its host-side optical model agrees
+with the oracle's independent one."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import model
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hydot.h")
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import paper_1410_0986_amd as hd
+    return hd
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hydot_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ("hydot_assemble_operator", "hydot_solve_fields", "hydot_born_apply", "hydot_born_apply_adjoint"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol(hd):
+    lib = ctypes.CDLL(hd.library_path())
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    assert "gfx950" in hd.version()
+
+
+def _op(hd, w):
+    return hd.Operator.from_workload(w)
+
+
+def test_optical_model_matches_oracle(hd):
+    w = workloads.config("medium")
+    op = _op(hd, w)
+    D, mua = op.optics()
+    Do, muao, _ = model.optics(w)
+    np.testing.assert_allclose(D, Do, rtol=1e-15)
+    np.testing.assert_allclose(mua, muao, rtol=1e-14)
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("h", 0.0), ("h", -1.0), ("A_R", 0.0),
+                                         ("robin_faces", 0x40)])
+def test_assemble_rejects_bad_grid(hd, field, value):
+    w = workloads.config("tiny")
+    setattr(w, field, value)
+    with pytest.raises(hd.HydotError) as e:
+        _op(hd, w)
+    assert e.value.status == hd.EINVAL
+
+
+def test_assemble_rejects_bad_optics(hd):
+    w = workloads.config("tiny")
+    w.mus_prime = w.mus_prime.copy()
+    w.mus_prime[3] = float("nan")
+    with pytest.raises(hd.HydotError) as e:
+        _op(hd, w)
+    assert e.value.status == hd.EINVAL
+    w = workloads.config("tiny")
+    with pytest.raises(hd.HydotError):
+        hd.Operator(4, 4, 4, 2.0, 2.5, 0x3F, w.mus_prime, np.zeros((9, w.L)), np.zeros(9), w.omega_over_nu)
+
+
+def test_workspace_size_grows_with_batch_and_precision(hd):
+    w = workloads.config("tiny")
+    op = _op(hd, w)
+    o64 = hd.SolveOptions(restart_m=40, recycle_k=10, lanczos_n=40)
+    o32 = hd.SolveOptions(restart_m=40, recycle_k=10, lanczos_n=40, precision=hd.PREC_MIXED)
+    b64 = hd.solve_workspace_bytes(op, 8, o64)
+    b32 = hd.solve_workspace_bytes(op, 8, o32)
+    assert b64 > 0 and b32 > 0
+    # the Krylov basis alone: systems x (m-k+1) x N x 16 bytes
+    assert b64 >= 8 * w.L * 31 * w.N * 16
+    assert b32 < b64
+    per = hd.solve_workspace_bytes(op, 8, hd.SolveOptions(flags=hd.FLAG_PER_SYSTEM | hd.FLAG_MEAN_SHIFT))
+    assert per < b64
+
+
+@pytest.mark.parametrize("kw", [dict(recycle_k=40), dict(recycle_k=10, lanczos_n=10), dict(restart_m=5, recycle_k=10),
+                                dict(rel_tol=0.0), dict(max_iter=0), dict(precision=7), dict(flags=0x100),
+                                dict(precision=1, inner_tol=0.0), dict(restart_m=400, recycle_k=0)])
+def test_solve_options_validated(hd, kw):
+    w = workloads.config("tiny")
+    op = _op(hd, w)
+    with pytest.raises(hd.HydotError) as e:
+        hd.solve_workspace_bytes(op, 8, hd.SolveOptions(**kw))
+    assert e.value.status == hd.EINVAL
+
+
+def _raw(hd):
+    return ctypes.CDLL(hd.library_path())
+
+
+def test_solve_fields_validates_before_launch(hd):
+    from paper_1410_0986_amd._binding import _SolveOpts
+    lib = _raw(hd)
+    w = workloads.config("tiny")
+    op = _op(hd, w)
+    o = _SolveOpts(1e-8, 100, 40, 10, 40, 0, 0, 1e-5, 0)
+    need = hd.solve_workspace_bytes(op, 8, hd.SolveOptions())
+    vox = np.ascontiguousarray(w.rhs_voxels)
+    vp = vox.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    f = lib.hydot_solve_fields
+    f.restype = ctypes.c_int32
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    fake = ctypes.c_void_p(0x7F0000000000)      # never dereferenced: validation fails first
+    # null phi
+    assert f(op.handle, 8, vp, ctypes.byref(o), None, 0, fake, need, None, None, None) == hd.EINVAL
+    # misaligned workspace
+    assert f(op.handle, 8, vp, ctypes.byref(o), fake, 0, ctypes.c_void_p(0x7F0000000010), need, None, None,
+             None) == hd.EINVAL
+    # workspace too small
+    assert f(op.handle, 8, vp, ctypes.byref(o), fake, 0, fake, need - 1, None, None, None) == hd.ENOMEM
+    # voxel out of range
+    bad = vox.copy()
+    bad[2] = w.N
+    assert f(op.handle, 8, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(o), fake, 0, fake, need,
+             None, None, None) == hd.EINVAL
+    # unsupported output dtype
+    assert f(op.handle, 8, vp, ctypes.byref(o), fake, 3, fake, need, None, None, None) == hd.EUNSUPPORTED
+    assert "dtype" in hd._binding._last_error().decode()
+
+
+def test_born_validates_before_launch(hd):
+    lib = _raw(hd)
+    w = workloads.config("tiny")
+    op = _op(hd, w)
+    f = lib.hydot_born_apply
+    f.restype = ctypes.c_int32
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    fake = ctypes.c_void_p(0x7F0000000000)
+    assert f(op.handle, fake, 0, fake, 4, 8, 0, fake, 1, fake, None) == hd.EINVAL        # S = 0
+    assert f(op.handle, fake, 65, fake, 4, 80, 0, fake, 1, fake, None) == hd.EINVAL      # S > 64
+    assert f(op.handle, fake, 4, fake, 4, 3, 0, fake, 1, fake, None) == hd.EINVAL        # lam_stride < S
+    assert f(op.handle, fake, 4, fake, 4, 8, 0, fake, 0, fake, None) == hd.EINVAL        # n_v = 0
+    assert f(op.handle, fake, 4, fake, 4, 8, 4, fake, 1, fake, None) == hd.EUNSUPPORTED  # real dtype
+    g = lib.hydot_born_apply_adjoint
+    g.restype = ctypes.c_int32
+    g.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert g(op.handle, None, 4, fake, 4, 8, 0, fake, fake, None) == hd.EINVAL
+
+
+def test_pals_and_misfit_validate(hd):
+    w = workloads.config("tiny")
+    op = _op(hd, w)
+    lib = _raw(hd)
+    from paper_1410_0986_amd._binding import _PalsOpts
+    f = lib.hydot_pals_shape
+    f.restype = ctypes.c_int32
+    f.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_int32, ctypes.c_void_p]
+    p = np.zeros(5 * 40)
+    pp = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    po = _PalsOpts(0.5, 0.5, 1e-3)
+    fake = ctypes.c_void_p(0x7F0000000000)
+    assert f(op.handle, pp, 40, ctypes.byref(po), fake, 3, None) == hd.EINVAL   # too many bumps
+    po_bad = _PalsOpts(0.5, 0.0, 1e-3)
+    assert f(op.handle, pp, 8, ctypes.byref(po_bad), fake, 3, None) == hd.EINVAL  # eps = 0
+    assert f(op.handle, pp, 8, ctypes.byref(po), fake, 0, None) == hd.EUNSUPPORTED  # complex mu
+    assert lib.hydot_misfit_workspace_bytes(op.handle, 4, 4) > 0

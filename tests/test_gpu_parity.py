@@ -1,0 +1,296 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: FP64 path 1e-8 and mixed path 1e-4, normwise relative error per
+system for fields, over all (lambda, s, d) for J v, over all voxels for J^H w.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import born as oborn
+from oracle import fields as ofields
+from oracle import model as omodel
+from oracle import pals as opals
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import paper_1410_0986_amd as hd
+    return hd
+
+
+def normwise(a, b, axis=-1):
+    return np.linalg.norm(a - b, axis=axis) / np.linalg.norm(b, axis=axis)
+
+
+def oracle_fields(w):
+    return ofields.solve_banded(w)
+
+
+# ------------------------------------------------------------------ operator
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-14), (torch.complex64, 2e-6)])
+@pytest.mark.parametrize("faces", [0x3F, 0x0C])
+def test_apply_operator_matches_sparse_matvec(hd, dtype, tol, faces):
+    w = workloads.config("tiny", nx=20, ny=13, nz=7)      # ragged: N = 1820
+    w.robin_faces = faces
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(1)
+    lam = np.array([0, 3, 7, 7, 2])
+    x = rng.standard_normal((5, w.N)) + 1j * rng.standard_normal((5, w.N))
+    y = hd.apply_operator(op, lam, torch.from_numpy(x).to(dtype).to(DEV)).cpu().numpy()
+    for i, l in enumerate(lam):
+        ref = omodel.operator(w, int(l)) @ x[i]
+        assert normwise(y[i], ref) < tol
+
+
+# ------------------------------------------------------------------- solves
+def _check_fields(w, phi, rel, tol_field, tol_res, ref=None):
+    ref = oracle_fields(w) if ref is None else ref
+    err = normwise(phi, ref)
+    assert err.max() < tol_field, (err.max(), np.unravel_index(err.argmax(), err.shape))
+    assert rel.max() <= tol_res
+    return ref
+
+
+def test_solve_tiny_unrecycled_gmres30(hd):
+    w = workloads.config("tiny")
+    op = hd.Operator.from_workload(w)
+    o = hd.SolveOptions(rel_tol=1e-10, restart_m=30, recycle_k=0, flags=hd.FLAG_NO_RECYCLE, max_iter=5000)
+    phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, device=DEV)
+    assert st == hd.OK
+    phi = phi.cpu().numpy()
+    _check_fields(w, phi, rel, 1e-8, 1e-10)
+    # the reported residual is the residual of the returned fields
+    for (l, r) in [(0, 0), (5, 6)]:
+        rr = omodel.relative_residual(w, l, w.rhs_voxels[r], phi[l, r])
+        assert rr <= 1.01e-10
+    assert it.min() > 10
+
+
+@pytest.mark.parametrize("mean_shift", [True, False])
+def test_solve_tiny_recycled_fp64(hd, mean_shift):
+    w = workloads.config("tiny")
+    op = hd.Operator.from_workload(w)
+    flags = hd.FLAG_MEAN_SHIFT if mean_shift else 0
+    o = hd.SolveOptions(rel_tol=1e-11, restart_m=40, recycle_k=10, lanczos_n=40, flags=flags)
+    phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, device=DEV)
+    assert st == hd.OK
+    _check_fields(w, phi.cpu().numpy(), rel, 1e-8, 1e-11)
+
+
+def test_solve_ragged_grid_mixed_faces_fp64(hd):
+    w = workloads.config("tiny", nx=21, ny=11, nz=9, n_lambda=5)   # N = 2079: two chunks, ragged tail
+    w.robin_faces = 0x33
+    w.src_voxels = np.array([5, 100, 2000], dtype=np.int64)
+    w.det_voxels = np.array([2078, 0], dtype=np.int64)
+    op = hd.Operator.from_workload(w)
+    o = hd.SolveOptions(rel_tol=1e-11, restart_m=30, recycle_k=6, lanczos_n=24)
+    phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, device=DEV)
+    assert st == hd.OK
+    _check_fields(w, phi.cpu().numpy(), rel, 1e-8, 1e-11)
+
+
+def test_solve_mixed_precision(hd):
+    w = workloads.config("tiny")
+    op = hd.Operator.from_workload(w)
+    o = hd.SolveOptions(rel_tol=1e-8, restart_m=40, recycle_k=10, lanczos_n=40, precision=hd.PREC_MIXED,
+                        inner_tol=1e-5)
+    ref = oracle_fields(w)
+    phi32, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, out_dtype=torch.complex64, device=DEV)
+    assert st == hd.OK
+    _check_fields(w, phi32.cpu().numpy().astype(np.complex128), rel, 1e-4, 1e-8, ref)
+    phi64, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, out_dtype=torch.complex128, device=DEV)
+    _check_fields(w, phi64.cpu().numpy(), rel, 1e-6, 1e-8, ref)
+
+
+def test_per_system_and_graph_modes_agree(hd):
+    w = workloads.config("tiny", n_lambda=3)
+    op = hd.Operator.from_workload(w)
+    base = dict(rel_tol=1e-11, restart_m=40, recycle_k=8, lanczos_n=32)
+    ref = oracle_fields(w)
+    for flags in (hd.FLAG_MEAN_SHIFT | hd.FLAG_PER_SYSTEM, hd.FLAG_MEAN_SHIFT | hd.FLAG_GRAPH):
+        phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, hd.SolveOptions(flags=flags, **base), device=DEV)
+        assert st == hd.OK
+        _check_fields(w, phi.cpu().numpy(), rel, 1e-8, 1e-11, ref)
+    # graph capture on a user stream, mixed precision, several batches
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        o = hd.SolveOptions(precision=hd.PREC_MIXED, flags=hd.FLAG_MEAN_SHIFT | hd.FLAG_GRAPH, max_batch=7,
+                            rel_tol=1e-8, restart_m=40, recycle_k=8, lanczos_n=32)
+        phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, device=DEV)
+    s.synchronize()
+    assert st == hd.OK
+    _check_fields(w, phi.cpu().numpy(), rel, 1e-6, 1e-8, ref)
+
+
+def test_recycling_reduces_iterations(hd):
+    w = workloads.config("tiny", nx=32, ny=32, nz=16, n_lambda=6)
+    op = hd.Operator.from_workload(w)
+    vox = w.rhs_voxels[:2]
+    common = dict(rel_tol=1e-8, restart_m=40, lanczos_n=40, flags=hd.FLAG_MEAN_SHIFT)
+    _, it0, rel0, _ = hd.solve_fields(op, vox, hd.SolveOptions(recycle_k=0, **common), device=DEV)
+    _, it10, rel10, _ = hd.solve_fields(op, vox, hd.SolveOptions(recycle_k=10, **common), device=DEV)
+    assert rel0.max() <= 1e-8 and rel10.max() <= 1e-8
+    assert it10.sum() < it0.sum()
+
+
+def test_enoconv_reported_with_fields_written(hd):
+    w = workloads.config("tiny", n_lambda=2)
+    op = hd.Operator.from_workload(w)
+    o = hd.SolveOptions(rel_tol=1e-12, max_iter=3, restart_m=13, recycle_k=0, flags=hd.FLAG_NO_RECYCLE)
+    phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, device=DEV)
+    assert st == hd.ENOCONV
+    assert np.all(rel > 1e-12) and np.all(np.isfinite(rel))
+    assert np.all(it <= 3 + 13)
+    assert torch.isfinite(phi).all()
+
+
+# --------------------------------------------------------------------- Born
+def _born_case(w, dtype):
+    P = oracle_fields(w)
+    Ps, Pd = P[:, :w.S], P[:, w.S:]
+    t = torch.from_numpy(P).to(dtype).to(DEV)
+    return P, Ps, Pd, t
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
+def test_born_apply_matches_oracle(hd, dtype, tol):
+    w = workloads.config("tiny")
+    op = hd.Operator.from_workload(w)
+    P, Ps, Pd, t = _born_case(w, dtype)
+    v = workloads.born_v(w, n_v=3)
+    # inputs as the device sees them (FP32 fields are rounded before the product)
+    Pr = t.cpu().numpy().astype(np.complex128)
+    rdt = torch.float64 if dtype == torch.complex128 else torch.float32
+    vt = torch.from_numpy(v).to(rdt)
+    ref = oborn.born_apply(Pr[:, :w.S], Pr[:, w.S:], vt.double().numpy(), w.h)
+    y = hd.born_apply(op, t[:, :w.S], t[:, w.S:], vt.to(DEV)).cpu().numpy()
+    assert normwise(y.reshape(3, -1), ref.reshape(3, -1)).max() < tol
+    # against the FP64 oracle without input rounding, within the path's tolerance
+    ref64 = oborn.born_apply(Ps, Pd, v, w.h)
+    assert normwise(y.reshape(-1), ref64.reshape(-1)) < (1e-8 if dtype == torch.complex128 else 1e-4)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
+def test_born_adjoint_matches_oracle(hd, dtype, tol):
+    w = workloads.config("tiny")
+    op = hd.Operator.from_workload(w)
+    P, Ps, Pd, t = _born_case(w, dtype)
+    wv = workloads.born_w(w)
+    Pr = t.cpu().numpy().astype(np.complex128)
+    wt = torch.from_numpy(wv).to(dtype)
+    ref = oborn.born_apply_adjoint(Pr[:, :w.S], Pr[:, w.S:], wt.cpu().numpy().astype(np.complex128), w.h)
+    g = hd.born_apply_adjoint(op, t[:, :w.S], t[:, w.S:], wt.to(DEV)).cpu().numpy()
+    assert normwise(g, ref) < tol
+
+
+@pytest.mark.parametrize("S,D", [(3, 5), (9, 2), (24, 24), (64, 64)])
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
+def test_born_shapes(hd, S, D, dtype, tol):
+    """Padding (S, D not multiples of 8), several tiles per wave, the 64 x 64 maximum, ragged N."""
+    w = workloads.config("tiny", nx=10, ny=9, nz=7, n_lambda=3)    # N = 630
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(S * 100 + D)
+    R = S + D
+    P = (rng.standard_normal((w.L, R, w.N)) + 1j * rng.standard_normal((w.L, R, w.N))) * 1e-3
+    t = torch.from_numpy(P).to(dtype).to(DEV)
+    Pr = t.cpu().numpy().astype(np.complex128)
+    v = rng.standard_normal((2, w.N))
+    rdt = torch.float64 if dtype == torch.complex128 else torch.float32
+    vt = torch.from_numpy(v).to(rdt)
+    y = hd.born_apply(op, t[:, :S], t[:, S:], vt.to(DEV)).cpu().numpy()
+    ref = oborn.born_apply(Pr[:, :S], Pr[:, S:], vt.double().numpy(), w.h)
+    assert normwise(y.reshape(2, -1), ref.reshape(2, -1)).max() < tol
+    wv = rng.standard_normal((w.L, S, D)) + 1j * rng.standard_normal((w.L, S, D))
+    wt = torch.from_numpy(wv).to(dtype)
+    g = hd.born_apply_adjoint(op, t[:, :S], t[:, S:], wt.to(DEV)).cpu().numpy()
+    refg = oborn.born_apply_adjoint(Pr[:, :S], Pr[:, S:], wt.numpy().astype(np.complex128), w.h)
+    assert normwise(g, refg) < tol
+
+
+def test_born_dot_test_on_device(hd):
+    w = workloads.config("tiny")
+    op = hd.Operator.from_workload(w)
+    P, Ps, Pd, t = _born_case(w, torch.complex128)
+    v = workloads.born_v(w)
+    wv = workloads.born_w(w)
+    y = hd.born_apply(op, t[:, :w.S], t[:, w.S:], torch.from_numpy(v).to(DEV)).cpu().numpy()[0]
+    g = hd.born_apply_adjoint(op, t[:, :w.S], t[:, w.S:], torch.from_numpy(wv).to(DEV)).cpu().numpy()
+    lhs = np.vdot(wv.reshape(-1), y.reshape(-1))
+    rhs = np.vdot(g, v[0])
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(wv) * np.linalg.norm(y)
+
+
+# ------------------------------------------------------------ differentiation
+def test_pals_shape_and_vjp(hd):
+    w = workloads.config("tiny", nx=24, ny=20, nz=12, n_lambda=3)
+    op = hd.Operator.from_workload(w)
+    p_true, _ = workloads.pals_truth(w)
+    p, _ = workloads.pals_perturbed(w, p_true, np.ones(2))
+    tau, eps, nu = workloads.PALS_TAU, workloads.PALS_EPS, workloads.PALS_NU
+    mu = hd.pals_shape(op, p, device=DEV).cpu().numpy()
+    ref = opals.shape(w, p, tau, eps, nu)
+    np.testing.assert_allclose(mu, ref, rtol=1e-12, atol=1e-13)
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(w.N)
+    gp = hd.pals_shape_vjp(op, p, torch.from_numpy(g).to(DEV))
+    refp = opals.shape_jacobian(w, p, tau, eps, nu).T @ g
+    np.testing.assert_allclose(gp, refp, rtol=1e-10, atol=1e-10 * np.abs(refp).max())
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-9), (torch.complex64, 1e-4)])
+def test_misfit_gradient_matches_oracle(hd, dtype, tol):
+    w = workloads.config("tiny", nx=24, ny=20, nz=12, n_lambda=4)
+    op = hd.Operator.from_workload(w)
+    P = ofields.solve_separable(w)
+    Ps, Pd = P[:, :w.S], P[:, w.S:]
+    tau, eps, nu = workloads.PALS_TAU, workloads.PALS_EPS, workloads.PALS_NU
+    p_true, dc_true = workloads.pals_truth(w)
+    _, _, _, y_true = opals.misfit(w, Ps, Pd, p_true, dc_true, 0.0, tau, eps, nu)
+    y_obs = y_true + workloads.observed_noise(y_true.shape, 0.03 * np.linalg.norm(y_true) / np.sqrt(y_true.size))
+    p, dc = workloads.pals_perturbed(w, p_true, dc_true)
+    f, gdc, gp, _ = opals.misfit(w, Ps, Pd, p, dc, y_obs, tau, eps, nu)
+    t = torch.from_numpy(P).to(dtype).to(DEV)
+    dct = torch.tensor(dc, dtype=torch.float64, requires_grad=True)
+    pt = torch.tensor(p, dtype=torch.float64, requires_grad=True)
+    yo = torch.from_numpy(y_obs).to(dtype).to(DEV)
+    fv = hd.BornMisfit.apply(dct, pt, op, t[:, :w.S], t[:, w.S:], yo)
+    fv.backward()
+    assert abs(fv.item() - f) <= tol * abs(f)
+    g_all = np.concatenate([dct.grad.numpy(), pt.grad.numpy()])
+    ref_all = np.concatenate([gdc, gp])
+    assert np.linalg.norm(g_all - ref_all) <= tol * 10 * np.linalg.norm(ref_all)
+
+
+def test_misfit_gradient_finite_differences_fp64(hd):
+    w = workloads.config("tiny", nx=24, ny=20, nz=12, n_lambda=3)
+    op = hd.Operator.from_workload(w)
+    P = ofields.solve_separable(w)
+    t = torch.from_numpy(P).to(DEV)
+    p_true, dc_true = workloads.pals_truth(w)
+    rng = np.random.default_rng(9)
+    y_obs = torch.from_numpy(rng.standard_normal((w.L, w.S, w.D)) * 1e-7 + 0j).to(DEV)
+    p, dc = workloads.pals_perturbed(w, p_true, dc_true)
+
+    def f_of(x):
+        return hd.BornMisfit.apply(torch.tensor(x[:2]), torch.tensor(x[2:]), op, t[:, :w.S], t[:, w.S:],
+                                   y_obs).item()
+
+    x = np.concatenate([dc, p])
+    xt = torch.tensor(x, requires_grad=True)
+    fv = hd.BornMisfit.apply(xt[:2], xt[2:], op, t[:, :w.S], t[:, w.S:], y_obs)
+    fv.backward()
+    g = xt.grad.numpy()
+    for i in (0, 1, 2, 10, 18, 26, 34, 41):
+        st = 1e-6 * max(1.0, abs(x[i]))
+        xu, xd = x.copy(), x.copy()
+        xu[i] += st
+        xd[i] -= st
+        fd = (f_of(xu) - f_of(xd)) / (2 * st)
+        assert abs(fd - g[i]) <= 1e-5 * np.abs(g).max() + 1e-6 * abs(g[i])
