@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput of the hyperspectral DOT Born hot path on one MI355X.
+
+One step = the whole hot path over one synthetic workload:
+  fields for every source and detector at every wavelength (Algorithm 1 with a
+  recycled deflation space, all systems batched, complex FP32 Krylov with FP64
+  residual refinement to rel-res 1e-8) -> Born J v -> Born J^H w -> PaLS misfit
+  value and gradient (forward + adjoint).
+
+Prints one JSON line.  value = RHS x wavelength solves per second of whole steps.
+Extra fields: Born J v GFLOP/s, the plain per-system FP64 solver's rate on a
+subsample (one right-hand side, every wavelength), the roofline of the dominant
+kernel (HIP events inside the library, on the solve stream), and the CPU oracle
+timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+WORKLOAD_TEXT = {
+    "medium": "medium: 64x64x32 grid (131072 voxels, h=2 mm), 16 sources + 16 detectors, 32 wavelengths 650-900 nm",
+    "batch": "batch: 64x64x32 grid (131072 voxels, h=2 mm), 32 sources + 32 detectors, 64 wavelengths 650-900 nm",
+    "tiny": "tiny: 16x16x8 grid (2048 voxels, h=2 mm), 4 sources + 4 detectors, 8 wavelengths 650-860 nm",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wname: str, n_sys: int):
+    """Unrecycled GMRES(30) of the FP64 oracle on a bounded sample of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import workloads
+    from oracle import fields as ofields
+    from oracle import model as omodel
+
+    w = workloads.config(wname)
+    lams = list(range(0, w.L, max(1, w.L // n_sys)))[:n_sys]
+    t0 = time.perf_counter()
+    iters = 0
+    for l in lams:
+        A = omodel.operator(w, l)
+        _, it, rr = ofields.gmres(A, omodel.rhs(w, w.rhs_voxels[0]), tol=1e-8, m=30, max_iter=20000)
+        iters += it
+    dt = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {"value": len(lams) / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(lams)} systems (source 0 at wavelengths {lams}) of the {wname} workload, "
+                      f"unrecycled GMRES(30) FP64 to 1e-8, {iters} iterations, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="medium", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-system FP64 comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=10, help="systems in the CPU oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the hot path is measured on one GPU's share; see the sharding notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1410_0986_amd as hd
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)     # default priority
+    w = workloads.config(args.config)
+    op = hd.Operator.from_workload(w)
+    S, D, L, N = w.S, w.D, w.L, w.N
+    R = S + D
+    vox = w.rhs_voxels
+    opts = hd.SolveOptions(rel_tol=1e-8, restart_m=40, recycle_k=10, lanczos_n=40, precision=hd.PREC_MIXED,
+                           inner_tol=1e-5, flags=hd.FLAG_MEAN_SHIFT | hd.FLAG_GRAPH, max_iter=5000)
+    v = torch.from_numpy(workloads.born_v(w, dtype=np.float32)).to(dev)
+    wv = torch.from_numpy(workloads.born_w(w)).to(torch.complex64).to(dev)
+    p_true, dc_true = workloads.pals_truth(w)
+    p_eval, dc_eval = workloads.pals_perturbed(w, p_true, dc_true)
+
+    with torch.cuda.stream(stream):
+        phi = torch.empty((L, R, N), dtype=torch.complex64, device=dev)
+
+        def solve():
+            return hd.solve_fields(op, vox, opts, out=phi)
+
+        # observed data of the PaLS model at the truth (set-up, not timed)
+        solve()
+        mu_t = hd.pals_shape(op, p_true, dtype=torch.float32, device=dev)
+        Jmu = hd.born_apply(op, phi[:, :S], phi[:, S:], mu_t[None])[0]
+        ebar = torch.from_numpy(dc_true @ w.extinction).to(dev).to(torch.float32)
+        y_obs = (ebar[:, None, None] * Jmu).contiguous()
+
+        def step():
+            _, it, rel, st = solve()
+            y = hd.born_apply(op, phi[:, :S], phi[:, S:], v)
+            g = hd.born_apply_adjoint(op, phi[:, :S], phi[:, S:], wv)
+            dct = torch.tensor(dc_eval, requires_grad=True)
+            pt = torch.tensor(p_eval, requires_grad=True)
+            f = hd.BornMisfit.apply(dct, pt, op, phi[:, :S], phi[:, S:], y_obs)
+            f.backward()
+            return it, rel, st, y, g
+
+        for i in range(args.warmup):
+            step()
+            log(f"warmup step {i + 1}/{args.warmup} done")
+        torch.cuda.synchronize()
+        hd.profile_enable(True)
+        t0 = time.perf_counter()
+        its, rels = [], []
+        for i in range(args.steps):
+            it, rel, st, _, _ = step()
+            its.append(it)
+            rels.append(rel)
+            log(f"timed step {i + 1}/{args.steps} done")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = hd.profile_read()
+        hd.profile_enable(False)
+
+        # Born J v alone (GFLOP/s) and J^H w alone, HIP events on this stream
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        hd.born_apply(op, phi[:, :S], phi[:, S:], v)
+        e0.record(stream)
+        for _ in range(reps):
+            hd.born_apply(op, phi[:, :S], phi[:, S:], v)
+        e1.record(stream)
+        e1.synchronize()
+        jv_ms = e0.elapsed_time(e1) / reps
+        e0.record(stream)
+        for _ in range(reps):
+            hd.born_apply_adjoint(op, phi[:, :S], phi[:, S:], wv)
+        e1.record(stream)
+        e1.synchronize()
+        jhw_ms = e0.elapsed_time(e1) / reps
+        log("born timing done")
+
+        plain = None
+        if not args.no_plain:
+            w1 = workloads.Workload(**{**w.__dict__, "src_voxels": w.src_voxels[:1],
+                                       "det_voxels": w.det_voxels[:0], "extra": {}})
+            op1 = hd.Operator.from_workload(w1)
+            po = hd.SolveOptions(rel_tol=1e-8, restart_m=40, recycle_k=10, lanczos_n=40, precision=hd.PREC_FP64,
+                                 flags=hd.FLAG_MEAN_SHIFT | hd.FLAG_PER_SYSTEM, max_iter=5000)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, pit, prel, pst = hd.solve_fields(op1, w1.rhs_voxels, po, device=dev)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            plain = {"solves_per_s": L / (tb - ta), "sample": f"1 right-hand side x {L} wavelengths",
+                     "max_rel_res": float(prel.max()), "mean_iters": float(pit.mean())}
+            log("plain path done")
+
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    solves_per_s = R * L * args.steps / elapsed
+    rel_all = np.stack(rels)
+    it_all = np.stack(its)
+    jv_flops = 8.0 * S * D * N * L
+    # dominant kernel by time
+    name, (launches, kms, kbytes) = max(prof.items(), key=lambda kv: kv[1][1])
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+            "launches": launches, "avg_launch_ms": round(kms / max(launches, 1), 4),
+            "algorithmic_bytes_per_launch": kbytes / max(launches, 1),
+            "all_step_kernels": {k: {"launches": a, "ms": round(b, 2), "GB/s": round(c / (b * 1e-3) / 1e9, 1)
+                                     if b > 0 else 0.0} for k, (a, b, c) in prof.items()}}
+    out = {
+        "metric": "RHS x wavelength solves/sec at rel-res 1e-8 (+ Born Jv GFLOP/s), batched vs plain",
+        "value": round(solves_per_s, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 Krylov + f64 refinement",
+        "data": "synthetic (seeded)",
+        "config": {"workload": WORKLOAD_TEXT[args.config], "systems_per_step": R * L,
+                   "solver": "batched recycled GMRES, m=40, k=10, n=40, mean shift, FP32 inner to 1e-5",
+                   "max_rel_res": float(rel_all.max()), "mean_iters": float(it_all.mean())},
+        "born_jv_gflops": round(jv_flops / (jv_ms * 1e-3) / 1e9, 1),
+        "born_jv_ms": round(jv_ms, 4),
+        "born_jv_mfma_frac_fp32": round(jv_flops / (jv_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+        "born_adjoint_ms": round(jhw_ms, 4),
+        "plain_fp64": plain,
+        "speedup_vs_plain": round(solves_per_s / plain["solves_per_s"], 2) if plain else None,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_sample)
+        log("cpu baseline done")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -25,7 +25,10 @@
  *
  * Conventions for every call:
  *   - Device buffers are allocated and owned by the caller; the library never
- *     frees caller memory.  The library owns only the opaque operator.
+ *     frees caller memory.  The library owns only the opaque operator.  The one
+ *     internal device allocation is the FP64 split-K scratch of hydot_born_apply,
+ *     taken and released stream-ordered (hipMallocAsync/hipFreeAsync) on the
+ *     caller's stream.
  *   - Complex data are interleaved (re, im) pairs: HYDOT_C128 = 2 x double,
  *     HYDOT_C64 = 2 x float.  All arrays are densely packed, C order.
  *   - Work is enqueued on the caller's stream (NULL = default stream).  Calls
@@ -138,7 +141,8 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
                                 void* workspace, size_t ws_bytes, int32_t* iters, double* rel_res,
                                 hipStream_t stream);
 
-/* Born products (Sec. 2.1 integral equation; rows of H in eq. measurement), never forming J:
+/* Born products (Sec. 2.1 integral equation; rows of H in eq. measurement), never forming J.
+ * Scratch: n_v * n_lambda * ceil(N / split) * (2*pad8(S)) * (2*pad8(D)) doubles, stream-ordered.
  *   y[c][l][s][d] = -h^3 sum_k phi_src[l][s][k] * v[c][k] * phi_det[l][d][k]   (no conjugation)
  * phi_src: device, source s at wavelength l at phi_src + (l*lam_stride + s)*N elements;
  * phi_det: likewise with d.  lam_stride >= max(S, D) counts N-vectors between wavelengths
@@ -192,6 +196,25 @@ hydot_status hydot_misfit(const hydot_operator* op, int32_t S, int32_t D, const 
                           const void* Jmu, const void* y_obs, const void* weights, hydot_dtype dtype,
                           void* w_adj, double* f, double* grad_dconc, void* workspace,
                           size_t ws_bytes, hipStream_t stream);
+
+/* Measurement instrumentation (not part of the method).  While enabled, hydot_solve_fields
+ * records HIP events on its stream around every launch of the three Arnoldi step kernels
+ * (first-pass dots with the operator, CGS2 update, normalisation) and accumulates, per
+ * kernel, launches, elapsed milliseconds and algorithmic HBM bytes: for step j with
+ * storage b bytes per complex, k deflation vectors and A systems stepping,
+ *   dots A*N*b*(j+2+k), update A*N*b*(j+3+k), finish A*N*b*(j+3+k)
+ * (each unique vector read once, plus the written vector; C and U are real, b/2 each).
+ * Enabling resets the counters; the graph flag is ignored while enabled (launches are
+ * timed one by one).  Process-wide; not thread-safe. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double total_bytes;
+} hydot_kernel_profile;
+hydot_status hydot_profile_enable(int32_t on);
+/* Writes up to max_records records; returns the number written (records available if out == NULL). */
+int32_t hydot_profile_read(hydot_kernel_profile* out, int32_t max_records);
 
 const char* hydot_last_error(void);
 const char* hydot_version(void);

@@ -23,6 +23,8 @@ from ._binding import (  # noqa: F401
     BornMisfit,
     library_path,
     version,
+    profile_enable,
+    profile_read,
     C128, C64, F64, F32,
     PREC_FP64, PREC_MIXED,
     FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM,

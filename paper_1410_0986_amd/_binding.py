@@ -77,6 +77,15 @@ _pals_vjp = _proto("hydot_pals_shape_vjp", c_int32, c_void_p, POINTER(c_double),
 _misfit_ws = _proto("hydot_misfit_workspace_bytes", c_size_t, c_void_p, c_int32, c_int32)
 _misfit = _proto("hydot_misfit", c_int32, c_void_p, c_int32, c_int32, POINTER(c_double), c_void_p, c_void_p,
                  c_void_p, c_int32, c_void_p, POINTER(c_double), POINTER(c_double), c_void_p, c_size_t, c_void_p)
+
+
+class _KProf(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int64), ("total_ms", c_double),
+                ("total_bytes", c_double)]
+
+
+_prof_enable = _proto("hydot_profile_enable", c_int32, c_int32)
+_prof_read = _proto("hydot_profile_read", c_int32, POINTER(_KProf), c_int32)
 _last_error = _proto("hydot_last_error", ctypes.c_char_p)
 _version = _proto("hydot_version", ctypes.c_char_p)
 
@@ -87,6 +96,20 @@ def library_path() -> str:
 
 def version() -> str:
     return _version().decode()
+
+
+def profile_enable(on: bool = True) -> None:
+    """Turn on (and reset) or off the event timing of the Arnoldi step kernels."""
+    _check(_prof_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms, algorithmic bytes)} accumulated since profile_enable(True)."""
+    n = _prof_read(None, 0)
+    recs = (_KProf * n)()
+    m = _prof_read(recs, n)
+    return {recs[i].name.decode(): (int(recs[i].launches), float(recs[i].total_ms), float(recs[i].total_bytes))
+            for i in range(m)}
 
 
 def _check(st: int, allow_noconv: bool = False) -> int:

@@ -99,6 +99,19 @@ __global__ void k_gram_reduce(const double* part, int nchunks, int npairs, int n
 
 namespace {
 
+// ------------------------------------------------------------ measurement
+// Optional per-kernel timing of the Arnoldi step kernels with HIP events on the
+// solve stream, plus their algorithmic bytes (unique data each launch must move
+// for the systems it actually processes).
+struct ProfRec {
+  const char* name;
+  int64_t launches;
+  double ms;
+  double bytes;
+};
+bool g_prof = false;
+ProfRec g_rec[3] = {{"k_step_dots", 0, 0.0, 0.0}, {"k_step_update", 0, 0.0, 0.0}, {"k_step_finish", 0, 0.0, 0.0}};
+
 struct Plan {
   int R, L, N;
   int k, mk, nl, mkmax;
@@ -183,7 +196,7 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   p.o_Rout = take((size_t)p.nb * N * sizeof(cd));
   p.o_part = take((size_t)ns * p.nchunks * p.ndots * sizeof(cd));
   p.o_small = take((size_t)ns * p.sl.total * sizeof(cd));
-  p.o_cnt = take(64);
+  p.o_cnt = take(kCounters * sizeof(int));
   p.o_final = take((size_t)ns * sizeof(double));
   p.total = off;
   return HYDOT_OK;
@@ -241,8 +254,39 @@ struct Solver {
   }
 
   hydot_status read_counters(int* h) {
-    HYDOT_HIP(hipMemcpyAsync(h, at<int>(p.o_cnt), 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipMemcpyAsync(h, at<int>(p.o_cnt), kCounters * sizeof(int), hipMemcpyDeviceToHost, stream));
     HYDOT_HIP(hipStreamSynchronize(stream));
+    return HYDOT_OK;
+  }
+
+  // event pairs around the step kernels of one cycle (profiling only)
+  std::vector<hipEvent_t> ev;
+  hydot_status prof_events() {
+    if (!ev.empty()) return HYDOT_OK;
+    ev.resize(2 * 3 * kMaxMK, nullptr);
+    for (auto& e : ev) HYDOT_HIP(hipEventCreate(&e));
+    return HYDOT_OK;
+  }
+  void prof_free() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    ev.clear();
+  }
+  // accumulate the timings of the cycle just synchronised
+  hydot_status prof_collect(const int* cnt, int k) {
+    const double N = (double)p.N, b = (double)p.esz;
+    for (int j = 0; j < p.mk; ++j) {
+      const double act = (double)cnt[2 + j];
+      const double extra[3] = {(double)(j + 2 + k), (double)(j + 3 + k), (double)(j + 3 + k)};
+      for (int kind = 0; kind < 3; ++kind) {
+        if (kind == 2 && j + 1 >= p.mk) continue;   // no finish after the last step
+        float ms = 0.f;
+        HYDOT_HIP(hipEventElapsedTime(&ms, ev[2 * (3 * j + kind)], ev[2 * (3 * j + kind) + 1]));
+        g_rec[kind].launches += 1;
+        g_rec[kind].ms += ms;
+        g_rec[kind].bytes += act * N * b * extra[kind];
+      }
+    }
     return HYDOT_OK;
   }
 
@@ -381,20 +425,31 @@ struct Solver {
 
   // ----------------------------------------------------------- one batch
   template <typename S>
-  void launch_cycle(const Ctx<S>& c, const ReduceArgs& ra, int nb) {
+  void launch_cycle(const Ctx<S>& c, const ReduceArgs& ra, int nb, bool prof) {
     dim3 gv(p.nchunks, nb), gr(nb);
-    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, c.counter);
+    auto rec = [&](int j, int kind, int edge) {
+      if (prof) (void)hipEventRecord(ev[2 * (3 * j + kind) + edge], stream);
+    };
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, stream, c.counter);
     hipLaunchKernelGGL(k_inner_resid<S>, gv, dim3(kBlock), 0, stream, c);
     hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0);
     hipLaunchKernelGGL(k_defl_start<S>, gv, dim3(kBlock), 0, stream, c);
     hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0);
     hipLaunchKernelGGL(k_scale_v0<S>, gv, dim3(kBlock), 0, stream, c);
     for (int j = 0; j < p.mk; ++j) {
+      rec(j, 0, 0);
       hipLaunchKernelGGL(k_step_dots<S>, gv, dim3(kBlock), 0, stream, c, j);
+      rec(j, 0, 1);
       hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j);
+      rec(j, 1, 0);
       hipLaunchKernelGGL(k_step_update<S>, gv, dim3(kBlock), 0, stream, c, j);
+      rec(j, 1, 1);
       hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j);
-      if (j + 1 < p.mk) hipLaunchKernelGGL(k_step_finish<S>, gv, dim3(kBlock), 0, stream, c, j);
+      if (j + 1 < p.mk) {
+        rec(j, 2, 0);
+        hipLaunchKernelGGL(k_step_finish<S>, gv, dim3(kBlock), 0, stream, c, j);
+        rec(j, 2, 1);
+      }
     }
     hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_CYCLE_END, 0);
     hipLaunchKernelGGL(k_cycle_update<S>, gv, dim3(kBlock), 0, stream, c);
@@ -462,11 +517,16 @@ struct Solver {
 
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
-    int cnt[2] = {0, 0};
+    int cnt[kCounters] = {0};
+    const bool prof = g_prof;
+    if (prof) {
+      hydot_status ps = prof_events();
+      if (ps != HYDOT_OK) return ps;
+    }
     const int max_cycles = o->max_iter / std::max(p.mk, 1) + 2;
     hydot_status status = HYDOT_OK;
     for (int sweep = 0; sweep < ra.max_sweeps + 2 && status == HYDOT_OK; ++sweep) {
-      hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, c.counter);
+      hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, stream, c.counter);
       hipLaunchKernelGGL(k_outer_resid<S>, gv, dim3(kBlock), 0, stream, c, 0);
       hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_OUTER, 0);
       HYDOT_HIP(hipGetLastError());
@@ -474,19 +534,20 @@ struct Solver {
       if (cnt[0] == 0) break;
       hipLaunchKernelGGL(k_rhs_in<S>, gv, dim3(kBlock), 0, stream, c);
       for (int cyc = 0; cyc < max_cycles; ++cyc) {
-        if (p.graph) {
+        if (p.graph && !prof) {
           if (!gexec) {
             HYDOT_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-            launch_cycle<S>(c, ra, nb);
+            launch_cycle<S>(c, ra, nb, false);
             HYDOT_HIP(hipStreamEndCapture(stream, &graph));
             HYDOT_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
           }
           HYDOT_HIP(hipGraphLaunch(gexec, stream));
         } else {
-          launch_cycle<S>(c, ra, nb);
+          launch_cycle<S>(c, ra, nb, prof);
         }
         HYDOT_HIP(hipGetLastError());
         if ((status = read_counters(cnt)) != HYDOT_OK) break;
+        if (prof && (status = prof_collect(cnt, p.k)) != HYDOT_OK) break;
         if (cnt[1] == 0) break;
       }
       hipLaunchKernelGGL(k_outer_update<S>, gv, dim3(kBlock), 0, stream, c);
@@ -559,6 +620,31 @@ using namespace hydot;
 
 extern "C" {
 
+hydot_status hydot_profile_enable(int32_t on) {
+  g_prof = on != 0;
+  if (g_prof)
+    for (auto& r : g_rec) {
+      r.launches = 0;
+      r.ms = 0.0;
+      r.bytes = 0.0;
+    }
+  return HYDOT_OK;
+}
+
+int32_t hydot_profile_read(hydot_kernel_profile* out, int32_t max_records) {
+  const int n = 3;
+  if (!out) return n;
+  const int m = std::min(n, (int)max_records);
+  for (int i = 0; i < m; ++i) {
+    std::memset(&out[i], 0, sizeof(hydot_kernel_profile));
+    std::strncpy(out[i].name, g_rec[i].name, sizeof(out[i].name) - 1);
+    out[i].launches = g_rec[i].launches;
+    out[i].total_ms = g_rec[i].ms;
+    out[i].total_bytes = g_rec[i].bytes;
+  }
+  return m;
+}
+
 hydot_status hydot_solve_workspace_bytes(const hydot_operator* op, int32_t n_rhs, const hydot_solve_opts* opts,
                                          size_t* bytes) {
   if (!bytes) return fail(HYDOT_EINVAL, "solve_workspace_bytes: null output");
@@ -600,6 +686,7 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
     s = sv.solve_all<cd>(phi, phi_dtype, it, rr);
   else
     s = sv.solve_all<cf>(phi, phi_dtype, it, rr);
+  sv.prof_free();
   if (own) {
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);

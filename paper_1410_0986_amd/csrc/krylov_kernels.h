@@ -93,7 +93,7 @@ struct Ctx {
   int ndots;
   cd* small;        // [nb][sl.total]
   Small sl;
-  int* counter;     // [2]
+  int* counter;     // [2 + kMaxMK]: in_sweep count, in_inner count, systems stepping at step j
 };
 
 // slots of the partial sums
@@ -576,8 +576,10 @@ __global__ __launch_bounds__(kBlock) void k_output(Ctx<S> c, O* phi) {
     if (ch.ok[q]) out[ch.n[q]] = Store<O>::from(p.out_scale * x[ch.n[q]]);
 }
 
+constexpr int kCounters = 2 + kMaxMK;
+
 __global__ void k_zero_counters(int* counter) {
-  if (threadIdx.x < 2) counter[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kCounters; i += blockDim.x) counter[i] = 0;
 }
 
 // ----------------------------------------------------------- reduce phases
@@ -738,6 +740,7 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
       break;
     }
     case PH_STEP_A: {
+      atomicAdd(&c.counter[2 + j], 1);
       cd* H = sm + c.sl.H;
       const int ldh = c.mkmax + 1;
       cd* coef = sm + c.sl.coefA;
@@ -784,7 +787,8 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
       st->total_iters += 1;
       st->nsteps = j + 1;
       if (ra.lanczos) {
-        if (breakdown || j + 1 >= ra.mk) st->in_cycle = 0;
+        // the last step still writes V_{n+1}: C = V_{n+1} Q needs it
+        if (breakdown) st->in_cycle = 0;
         break;
       }
       // apply the previous rotations to column j, then a new one
