@@ -5,11 +5,13 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <type_traits>
 #include <cstring>
 #include <vector>
 
 #include "common.h"
 #include "krylov_kernels.h"
+#include "krylov_tiled.h"
 #include "operator.h"
 #include "small_dense.h"
 
@@ -259,6 +261,9 @@ struct Solver {
     return HYDOT_OK;
   }
 
+  // systems per block group of the tiled kernels (see krylov_tiled.h)
+  int tile_grp = 1;
+
   // event pairs around the step kernels of one cycle (profiling only)
   std::vector<hipEvent_t> ev;
   hydot_status prof_events() {
@@ -424,6 +429,35 @@ struct Solver {
   }
 
   // ----------------------------------------------------------- one batch
+  // Arnoldi step kernels: kind 0 = operator + first dots, 1 = CGS2 update + dots,
+  // 2 = second projection + normalisation.  Complex FP32 storage with k <= 16 and
+  // at most 32 basis vectors uses the LDS-tiled kernels; everything else the generic ones.
+  template <typename S>
+  void step_kernel(int kind, const Ctx<S>& c, int j, int nb) {
+    dim3 gv(p.nchunks, nb);
+    if constexpr (std::is_same<S, cf>::value) {
+      if (c.k <= kTK && j + 1 <= kTNV) {
+        const dim3 gt((unsigned)(nb * p.nchunks));
+        const int grp = tile_grp;
+        const bool small = j + 1 <= 16;
+        if (kind == 0) {
+          if (small) hipLaunchKernelGGL(k_step_dots_t<16>, gt, dim3(kTSub), 0, stream, c, j, grp);
+          else hipLaunchKernelGGL(k_step_dots_t<32>, gt, dim3(kTSub), 0, stream, c, j, grp);
+        } else if (kind == 1) {
+          if (small) hipLaunchKernelGGL(k_step_update_t<16>, gt, dim3(kTSub), 0, stream, c, j, grp);
+          else hipLaunchKernelGGL(k_step_update_t<32>, gt, dim3(kTSub), 0, stream, c, j, grp);
+        } else {
+          if (small) hipLaunchKernelGGL(k_step_finish_t<16>, gt, dim3(kTSub), 0, stream, c, j, grp);
+          else hipLaunchKernelGGL(k_step_finish_t<32>, gt, dim3(kTSub), 0, stream, c, j, grp);
+        }
+        return;
+      }
+    }
+    if (kind == 0) hipLaunchKernelGGL(k_step_dots<S>, gv, dim3(kBlock), 0, stream, c, j);
+    else if (kind == 1) hipLaunchKernelGGL(k_step_update<S>, gv, dim3(kBlock), 0, stream, c, j);
+    else hipLaunchKernelGGL(k_step_finish<S>, gv, dim3(kBlock), 0, stream, c, j);
+  }
+
   template <typename S>
   void launch_cycle(const Ctx<S>& c, const ReduceArgs& ra, int nb, bool prof) {
     dim3 gv(p.nchunks, nb), gr(nb);
@@ -438,16 +472,16 @@ struct Solver {
     hipLaunchKernelGGL(k_scale_v0<S>, gv, dim3(kBlock), 0, stream, c);
     for (int j = 0; j < p.mk; ++j) {
       rec(j, 0, 0);
-      hipLaunchKernelGGL(k_step_dots<S>, gv, dim3(kBlock), 0, stream, c, j);
+      step_kernel<S>(0, c, j, nb);
       rec(j, 0, 1);
       hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j);
       rec(j, 1, 0);
-      hipLaunchKernelGGL(k_step_update<S>, gv, dim3(kBlock), 0, stream, c, j);
+      step_kernel<S>(1, c, j, nb);
       rec(j, 1, 1);
       hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j);
       if (j + 1 < p.mk) {
         rec(j, 2, 0);
-        hipLaunchKernelGGL(k_step_finish<S>, gv, dim3(kBlock), 0, stream, c, j);
+        step_kernel<S>(2, c, j, nb);
         rec(j, 2, 1);
       }
     }
@@ -500,6 +534,13 @@ struct Solver {
                                  lc_len * sizeof(cd), nb, hipMemcpyHostToDevice, stream));
     Ctx<S> c = ctx<S>(p.k, false);
     Ctx<cd> c64 = ctx<cd>(p.k, false);   // FP64 views for residual and output kernels
+    // group the wavelengths of one right-hand side when the batch holds whole ones
+    tile_grp = 1;
+    if (nb % p.L == 0) {
+      bool aligned = true;
+      for (int i = 0; i < nb && aligned; ++i) aligned = sys_l[i] == i % p.L && sys_r[i] == sys_r[i - i % p.L];
+      if (aligned) tile_grp = p.L;
+    }
     ReduceArgs ra{};
     ra.tol = o->rel_tol;
     ra.inner_floor = p.prec == HYDOT_PREC_MIXED ? o->inner_tol : 0.0;

@@ -1,0 +1,249 @@
+// Register-resident Arnoldi step kernels for complex FP32 storage (the batched
+// mixed path).  A block walks its chunk in sub-tiles of kTSub voxels, one voxel
+// per thread: the thread reads V_0..V_j, C and U of its voxel once from HBM into
+// registers, applies the operator or the projection there, and writes one
+// product per inner product into an LDS tile; the tile is then summed row by
+// row (4 threads per row, FP64), so every lane stays busy and no per-product
+// wave reduction is needed.  One HBM read of the basis per kernel replaces the
+// double read of the generic CGS2 update.
+//
+// Grid: one dimension of nb * nchunks blocks, ordered in groups of grp systems
+// (the wavelengths of one right-hand side when the batch holds whole
+// right-hand sides): block b -> group b / (grp * nchunks), chunk
+// (b / grp) % nchunks, system group * grp + b % grp.  Consecutive blocks then
+// share the right-hand side's U, C chunk in L2, and the stencil halo chunks
+// (2 * grp blocks away, the same XCD when grp is a multiple of 4) are still
+// resident when they are read.
+#pragma once
+
+#include "krylov_kernels.h"
+
+namespace hydot {
+
+constexpr int kTSub = 128;                  // voxels per sub-tile = threads per block
+constexpr int kTK = 10;                     // largest deflation dimension handled here (3k+1 <= 32 rows)
+constexpr int kTNV = 32;                    // largest basis count handled here
+constexpr int kTRows = 32;                  // rows of the product tile
+constexpr int kTRP = kTSub + 4;             // padded product row
+static_assert(kChunk % kTSub == 0, "chunk must hold whole sub-tiles");
+static_assert(3 * kTK + 1 <= kTRows && kTNV <= kTRows, "product tile too small");
+
+// Products of one sub-tile, one row per inner product, then reduced row-wise:
+// thread t owns row t/4 and sums its columns t%4, t%4+4, ... (FP64), keeping a
+// running sum over the sub-tiles of the chunk.
+struct ProdTile {
+  cf p[kTRows * kTRP];
+};
+
+__device__ inline void row_reduce(const ProdTile& pt, int nrows, cd& acc) {
+  const int t = threadIdx.x, row = t >> 2, seg = t & 3;
+  if (row >= nrows) return;
+  const cf* r = pt.p + row * kTRP;
+  double re = 0.0, im = 0.0;
+#pragma unroll 8
+  for (int i = 0; i < kTSub / 4; ++i) {
+    const cf x = r[seg + 4 * i];
+    re += (double)x.re;
+    im += (double)x.im;
+  }
+  acc.re += re;
+  acc.im += im;
+}
+
+struct TileIdx {
+  int sys, chunk;
+};
+__device__ inline TileIdx tile_idx(int nchunks, int grp) {
+  const int b = blockIdx.x;
+  const int per = grp * nchunks;
+  const int g = b / per, rem = b - g * per;
+  return TileIdx{g * grp + rem % grp, rem / grp};
+}
+
+// finish the 4-thread row sums and store them as the chunk's partial sums;
+// rows map to partial slots through slot0 (+row), the norm row to its own slot
+__device__ inline void row_flush(const Ctx<cf>& c, int sys, int chunk, int nrows, int slot0, int norm_row, cd acc) {
+  acc.re += __shfl_xor(acc.re, 1, 64);
+  acc.im += __shfl_xor(acc.im, 1, 64);
+  acc.re += __shfl_xor(acc.re, 2, 64);
+  acc.im += __shfl_xor(acc.im, 2, 64);
+  const int t = threadIdx.x, row = t >> 2;
+  if ((t & 3) != 0 || row >= nrows) return;
+  const int slot = row == norm_row ? slot_norm(c.k, c.mkmax) : slot0 + row;
+  c.part[((size_t)sys * c.nchunks + chunk) * c.ndots + slot] = acc;
+}
+
+template <int NV>
+__device__ inline void load_basis(const cf* Vsys, size_t N, uint32_t n, bool ok, int nv, cf* vr) {
+#pragma unroll
+  for (int l = 0; l < NV; ++l) vr[l] = (l < nv && ok) ? Vsys[(size_t)l * N + n] : cf{0.f, 0.f};
+}
+
+__device__ inline void load_cu(const Ctx<cf>& c, int r, size_t N, uint32_t n, bool ok, float* cr, float* ur) {
+#pragma unroll
+  for (int i = 0; i < kTK; ++i) {
+    const bool on = i < c.k && ok;
+    cr[i] = on ? c.C[((size_t)r * c.k + i) * N + n] : 0.f;
+    ur[i] = on ? c.U[((size_t)r * c.k + i) * N + n] : 0.f;
+  }
+}
+
+// w - C'g - sum_l h_l V_l for one voxel, from registers
+template <int NV>
+__device__ inline cf project_voxel(cf w, const cf* vr, const float* cr, const float* ur, const cf* g,
+                                   const cf* h, int k, int nv, cd shift) {
+  if (k > 0) {
+    float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
+#pragma unroll
+    for (int i = 0; i < kTK; ++i) {
+      if (i < k) {
+        ar += cr[i] * g[i].re;
+        ai += cr[i] * g[i].im;
+        br += ur[i] * g[i].re;
+        bi += ur[i] * g[i].im;
+      }
+    }
+    const float sr = (float)shift.re, si = (float)shift.im;
+    w.re -= ar + (sr * br - si * bi);
+    w.im -= ai + (sr * bi + si * br);
+  }
+#pragma unroll
+  for (int l = 0; l < NV; ++l) {
+    if (l < nv) {
+      const cf v = vr[l], hl = h[l];
+      w.re -= hl.re * v.re - hl.im * v.im;
+      w.im -= hl.re * v.im + hl.im * v.re;
+    }
+  }
+  return w;
+}
+
+// Product rows of one voxel: round 0 -> conj(V_l) w for l < nv;
+// round 1 -> C_i w, U_i w, rho U_i w (rows 3i..3i+2) and |w|^2 (row 3k) if with_norm.
+template <int NV>
+__device__ inline void write_products(ProdTile& pt, int round, const cf* vr, const float* cr, const float* ur,
+                                      float rho, cf w, int k, int nv, bool with_norm) {
+  const int t = threadIdx.x;
+  if (round == 0) {
+#pragma unroll
+    for (int l = 0; l < NV; ++l)
+      if (l < nv) {
+        const cf v = vr[l];
+        pt.p[l * kTRP + t] = cf{v.re * w.re + v.im * w.im, v.re * w.im - v.im * w.re};
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTK; ++i)
+      if (i < k) {
+        pt.p[(3 * i) * kTRP + t] = cf{cr[i] * w.re, cr[i] * w.im};
+        pt.p[(3 * i + 1) * kTRP + t] = cf{ur[i] * w.re, ur[i] * w.im};
+        const float ru = ur[i] * rho;
+        pt.p[(3 * i + 2) * kTRP + t] = cf{ru * w.re, ru * w.im};
+      }
+    if (with_norm) pt.p[(3 * k) * kTRP + t] = cf{w.re * w.re + w.im * w.im, 0.f};
+  }
+}
+
+// Shared body of the dots (kind 0) and update (kind 1) kernels.
+template <int NV, int KIND>
+__device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
+  __shared__ ProdTile pt;
+  const int sys = ti.sys;
+  const size_t N = (size_t)c.g.N;
+  const int k = c.k, nv = j + 1, t = threadIdx.x;
+  const SysParam p = c.prm[sys];
+  const cf* Vsys = c.V + (size_t)sys * c.vdim * N;
+  cf* wv = c.W + (size_t)sys * N;
+  cf g[kTK], h[NV];
+  if (KIND == 1) {
+    const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefA;
+#pragma unroll
+    for (int i = 0; i < kTK; ++i) g[i] = i < k ? Store<cf>::from(coef[i]) : cf{0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l < NV; ++l) h[l] = l < nv ? Store<cf>::from(coef[k + l]) : cf{0.f, 0.f};
+  }
+  const bool with_norm = KIND == 1;
+  const int drows = 3 * k + (with_norm ? 1 : 0);
+  cd accv{0.0, 0.0}, accd{0.0, 0.0};
+  for (int sub = 0; sub < kChunk / kTSub; ++sub) {
+    const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
+    const bool ok = n < (uint32_t)c.g.N;
+    cf vr[NV];
+    float cr[kTK], ur[kTK];
+    load_basis<NV>(Vsys, N, n, ok, nv, vr);
+    load_cu(c, p.rhs, N, n, ok, cr, ur);
+    float rho = 0.f;
+    cf w{0.f, 0.f};
+    if (ok) {
+      const VoxelInfo vi = voxel_info(c.g, n);
+      rho = (float)((double)vi.nrobin * c.g.inv_h);
+      if (KIND == 0) {
+        w = apply_op<cf>(c.g, Vsys + (size_t)j * N, n, vi, p.sig, p.sigp_abs);
+      } else {
+        w = project_voxel<NV>(wv[n], vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
+      }
+      wv[n] = w;
+    }
+    write_products<NV>(pt, 0, vr, cr, ur, rho, w, k, nv, with_norm);
+    __syncthreads();
+    row_reduce(pt, nv, accv);
+    __syncthreads();
+    if (drows > 0) {
+      write_products<NV>(pt, 1, vr, cr, ur, rho, w, k, nv, with_norm);
+      __syncthreads();
+      row_reduce(pt, drows, accd);
+      __syncthreads();
+    }
+  }
+  row_flush(c, sys, ti.chunk, nv, slot_v(k, 0), -1, accv);
+  if (drows > 0) row_flush(c, sys, ti.chunk, drows, 0, with_norm ? 3 * k : -1, accd);
+}
+
+// W = A_hat V_j and first-pass inner products (tiled form of k_step_dots).
+template <int NV>
+__global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp) {
+  const TileIdx ti = tile_idx(c.nchunks, grp);
+  if (!c.st[ti.sys].in_cycle) return;
+  tiled_step<NV, 0>(c, j, ti);
+}
+
+// CGS2 first projection + second-pass inner products (tiled form of k_step_update).
+template <int NV>
+__global__ __launch_bounds__(kTSub) void k_step_update_t(Ctx<cf> c, int j, int grp) {
+  const TileIdx ti = tile_idx(c.nchunks, grp);
+  if (!c.st[ti.sys].in_cycle) return;
+  tiled_step<NV, 1>(c, j, ti);
+}
+
+// Second projection and normalisation (k_step_finish with the system-fastest grid).
+template <int NV>
+__global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int grp) {
+  const TileIdx ti = tile_idx(c.nchunks, grp);
+  const int sys = ti.sys;
+  if (!c.st[sys].in_cycle) return;
+  const size_t N = (size_t)c.g.N;
+  const int k = c.k, nv = j + 1, t = threadIdx.x;
+  const SysParam p = c.prm[sys];
+  cf* Vsys = c.V + (size_t)sys * c.vdim * N;
+  const cf* wv = c.W + (size_t)sys * N;
+  const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefB;
+  const float inv_eta = (float)coef[k + c.mkmax + 1].re;
+  cf g[kTK], h[NV];
+#pragma unroll
+  for (int i = 0; i < kTK; ++i) g[i] = i < k ? Store<cf>::from(coef[i]) : cf{0.f, 0.f};
+#pragma unroll
+  for (int l = 0; l < NV; ++l) h[l] = l < nv ? Store<cf>::from(coef[k + l]) : cf{0.f, 0.f};
+  for (int sub = 0; sub < kChunk / kTSub; ++sub) {
+    const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
+    if (n >= (uint32_t)c.g.N) break;
+    cf vr[NV];
+    float cr[kTK], ur[kTK];
+    load_basis<NV>(Vsys, N, n, true, nv, vr);
+    load_cu(c, p.rhs, N, n, true, cr, ur);
+    const double rho = (double)voxel_info(c.g, n).nrobin * c.g.inv_h;
+    cf w = project_voxel<NV>(wv[n], vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
+    Vsys[(size_t)(j + 1) * N + n] = cf{w.re * inv_eta, w.im * inv_eta};
+  }
+}
+
+}  // namespace hydot
