@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-system FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=10, help="systems in the CPU oracle sample")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="finish with one device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -172,6 +174,16 @@ def main():
             plain = {"solves_per_s": L / (tb - ta), "sample": f"1 right-hand side x {L} wavelengths",
                      "max_rel_res": float(prel.max()), "mean_iters": float(pit.mean())}
             log("plain path done")
+
+    if args.copy_gib > 0:
+        nbytes = int(args.copy_gib * (1 << 30))
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {nbytes} bytes done")
+        del a, b
 
     elapsed = t1 - t0
     ms_step = 1e3 * elapsed / args.steps

@@ -1,0 +1,173 @@
+"""Full-size parity: the workloads at their real shapes, in the launch configuration
+bench.py times, checked on outputs the oracle computes one by one (whole fields of
+sampled systems by fast diagonalisation, Born products at sampled wavelengths and
+voxels) and on properties that hold at any size (every FP64 residual, the adjoint
+identity, finite differences of the misfit)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import born as oborn
+from oracle import fields as ofields
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import paper_1410_0986_amd as hd
+    return hd
+
+
+def bench_opts(hd, **kw):
+    base = dict(rel_tol=1e-8, restart_m=40, recycle_k=10, lanczos_n=40, precision=hd.PREC_MIXED, inner_tol=1e-5,
+                flags=hd.FLAG_MEAN_SHIFT | hd.FLAG_GRAPH, max_iter=5000)
+    base.update(kw)
+    return hd.SolveOptions(**base)
+
+
+def normwise(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def medium(hd):
+    w = workloads.config("medium")
+    op = hd.Operator.from_workload(w)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, bench_opts(hd), out_dtype=torch.complex64, device=DEV)
+    s.synchronize()
+    return w, op, phi, it, rel, st
+
+
+def test_medium_every_system_meets_tolerance(hd, medium):
+    w, op, phi, it, rel, st = medium
+    assert st == hd.OK
+    assert rel.shape == (w.L, w.S + w.D)
+    assert rel.max() <= 1e-8
+    assert np.all(it > 0)
+
+
+@pytest.mark.parametrize("lam,r", [(0, 0), (31, 31), (7, 16), (19, 5), (24, 27)])
+def test_medium_sampled_fields(hd, medium, lam, r):
+    w, op, phi, it, rel, st = medium
+    ref = ofields.solve_separable(w, voxels=[w.rhs_voxels[r]], lam_idx=[lam])[0, 0]
+    got = phi[lam, r].cpu().numpy().astype(np.complex128)
+    assert normwise(got, ref) < 1e-4
+
+
+def test_medium_born_sampled(hd, medium):
+    w, op, phi, it, rel, st = medium
+    S = w.S
+    v = workloads.born_v(w, dtype=np.float32)
+    y = hd.born_apply(op, phi[:, :S], phi[:, S:], torch.from_numpy(v).to(DEV)).cpu().numpy()[0]
+    for lam in (3, 29):
+        P = ofields.solve_separable(w, lam_idx=[lam])
+        yref = oborn.born_apply(P[:, :S], P[:, S:], v.astype(np.float64), w.h)[0, 0]
+        assert normwise(y[lam].astype(np.complex128), yref) < 1e-4
+    # J^H w at sampled voxels: every (lambda, rhs) field evaluated there one by one
+    wv = workloads.born_w(w)
+    g = hd.born_apply_adjoint(op, phi[:, :S], phi[:, S:], torch.from_numpy(wv).to(torch.complex64).to(DEV))
+    g = g.cpu().numpy().astype(np.complex128)
+    pts = np.array([w.src_voxels[5], w.det_voxels[9], w.N // 2 + 17, w.N // 3])
+    F = np.empty((w.L, w.S + w.D, len(pts)), dtype=np.complex128)
+    for lam in range(w.L):
+        for r, vox in enumerate(w.rhs_voxels):
+            F[lam, r] = ofields.separable_at(w, lam, int(vox), pts)
+    gref = oborn.born_apply_adjoint(F[:, :S], F[:, S:], wv, w.h)
+    assert np.abs(g[pts] - gref).max() <= 1e-4 * np.abs(gref).max()
+    # adjoint identity over the whole grid (both products from the device)
+    lhs = np.vdot(wv.reshape(-1), y.reshape(-1).astype(np.complex128))
+    rhs = np.vdot(g, v[0].astype(np.float64))
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+
+
+def test_medium_plain_fp64_subset(hd):
+    """The plain per-system FP64 path at full grid size: one source at 4 wavelengths, 1e-8 field parity."""
+    w = workloads.subset_lambdas(workloads.config("medium"), [0, 10, 20, 31])
+    w.src_voxels = w.src_voxels[3:4]
+    w.det_voxels = w.det_voxels[:0]
+    op = hd.Operator.from_workload(w)
+    o = hd.SolveOptions(rel_tol=1e-11, restart_m=40, recycle_k=10, lanczos_n=40,
+                        flags=hd.FLAG_MEAN_SHIFT | hd.FLAG_PER_SYSTEM)
+    phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, device=DEV)
+    assert st == hd.OK and rel.max() <= 1e-11
+    ref = ofields.solve_separable(w)
+    got = phi.cpu().numpy()
+    for lam in range(w.L):
+        assert normwise(got[lam, 0], ref[lam, 0]) < 1e-8
+
+
+def test_batch_config_sampled(hd):
+    """64 right-hand sides x 64 wavelengths in one batched launch."""
+    torch.cuda.empty_cache()
+    w = workloads.config("batch")
+    op = hd.Operator.from_workload(w)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, bench_opts(hd), out_dtype=torch.complex64, device=DEV)
+    s.synchronize()
+    assert st == hd.OK and rel.max() <= 1e-8
+    for lam, r in [(0, 63), (40, 2), (63, 31)]:
+        ref = ofields.solve_separable(w, voxels=[w.rhs_voxels[r]], lam_idx=[lam])[0, 0]
+        assert normwise(phi[lam, r].cpu().numpy().astype(np.complex128), ref) < 1e-4
+    S = w.S
+    v = workloads.born_v(w, dtype=np.float32)
+    y = hd.born_apply(op, phi[:, :S], phi[:, S:], torch.from_numpy(v).to(DEV)).cpu().numpy()[0]
+    P = ofields.solve_separable(w, lam_idx=[50])
+    yref = oborn.born_apply(P[:, :S], P[:, S:], v.astype(np.float64), w.h)[0, 0]
+    assert normwise(y[50].astype(np.complex128), yref) < 1e-4
+
+
+def test_diff_config_fields_and_gradient(hd):
+    """96x96x48 grid, 24+24 optodes, 48 wavelengths in two batches; misfit gradient by the
+    adjoint kernels against central finite differences of the device misfit (FP64 fields)."""
+    torch.cuda.empty_cache()
+    w = workloads.config("diff")
+    op = hd.Operator.from_workload(w)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, bench_opts(hd, max_batch=w.L * 24),
+                                           out_dtype=torch.complex64, device=DEV)
+    s.synchronize()
+    assert st == hd.OK and rel.max() <= 1e-8
+    for lam, r in [(0, 0), (47, 47), (23, 30)]:
+        ref = ofields.solve_separable(w, voxels=[w.rhs_voxels[r]], lam_idx=[lam])[0, 0]
+        assert normwise(phi[lam, r].cpu().numpy().astype(np.complex128), ref) < 1e-4
+    S = w.S
+    p_true, dc_true = workloads.pals_truth(w)
+    p, dc = workloads.pals_perturbed(w, p_true, dc_true)
+    ph = phi.to(torch.complex128)
+    mu_t = hd.pals_shape(op, p_true, device=DEV)
+    Jmu = hd.born_apply(op, ph[:, :S], ph[:, S:], mu_t[None])[0]
+    ebar = torch.from_numpy(dc_true @ w.extinction).to(DEV)
+    y_obs = ebar[:, None, None] * Jmu
+    x = np.concatenate([dc, p])
+    xt = torch.tensor(x, requires_grad=True)
+    f = hd.BornMisfit.apply(xt[:2], xt[2:], op, ph[:, :S], ph[:, S:], y_obs)
+    f.backward()
+    g = xt.grad.numpy()
+    assert f.item() > 0
+
+    def f_of(xx):
+        return hd.BornMisfit.apply(torch.tensor(xx[:2]), torch.tensor(xx[2:]), op, ph[:, :S], ph[:, S:],
+                                   y_obs).item()
+
+    for i in (0, 1, 2, 9, 17, 25, 33, 41):
+        st_ = 1e-6 * max(1.0, abs(x[i]))
+        xu, xd = x.copy(), x.copy()
+        xu[i] += st_
+        xd[i] -= st_
+        fd = (f_of(xu) - f_of(xd)) / (2 * st_)
+        assert abs(fd - g[i]) <= 1e-5 * np.abs(g).max() + 1e-5 * abs(g[i])
+    # zero gradient at the truth (noise-free data)
+    xt0 = torch.tensor(np.concatenate([dc_true, p_true]), requires_grad=True)
+    f0 = hd.BornMisfit.apply(xt0[:2], xt0[2:], op, ph[:, :S], ph[:, S:], y_obs)
+    f0.backward()
+    assert f0.item() <= 1e-12 * f.item()
+    assert np.abs(xt0.grad.numpy()).max() <= 1e-6 * np.abs(g).max()
