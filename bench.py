@@ -28,6 +28,22 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
+# Calibrated HBM bytes per dispatch of the Arnoldi step kernels on the medium workload,
+# from the FETCH_SIZE / WRITE_SIZE runs summarised in profiles/step_kernels_medium_traffic.md.
+# They belong to the kernel sources with this SHA-256 (common.h, krylov_kernels.h,
+# krylov_tiled.h); after any change to those the traffic is reported as null.
+TRAFFIC_SOURCES_SHA256 = "bd4b2b8c300c2e6a7a99a3541136986342f41687668a15d0e94ee4af5e7abaac"
+TRAFFIC_BYTES_PER_LAUNCH = {"k_step_dots_t": 11.438e9, "k_step_update_t": 11.956e9, "k_step_finish_t": 11.768e9}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("common.h", "krylov_kernels.h", "krylov_tiled.h"):
+        with open(os.path.join(ROOT, "paper_1410_0986_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 WORKLOAD_TEXT = {
     "medium": "medium: 64x64x32 grid (131072 voxels, h=2 mm), 16 sources + 16 detectors, 32 wavelengths 650-900 nm",
     "batch": "batch: 64x64x32 grid (131072 voxels, h=2 mm), 32 sources + 32 detectors, 64 wavelengths 650-900 nm",
@@ -194,8 +210,12 @@ def main():
     # dominant kernel by time
     name, (launches, kms, kbytes) = max(prof.items(), key=lambda kv: kv[1][1])
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    traffic = None
+    if args.config == "medium" and kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256:
+        traffic = TRAFFIC_BYTES_PER_LAUNCH.get(name)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
+            "kernel": name,
             "launches": launches, "avg_launch_ms": round(kms / max(launches, 1), 4),
             "algorithmic_bytes_per_launch": kbytes / max(launches, 1),
             "all_step_kernels": {k: {"launches": a, "ms": round(b, 2), "GB/s": round(c / (b * 1e-3) / 1e9, 1)

@@ -113,6 +113,8 @@ struct ProfRec {
 };
 bool g_prof = false;
 ProfRec g_rec[3] = {{"k_step_dots", 0, 0.0, 0.0}, {"k_step_update", 0, 0.0, 0.0}, {"k_step_finish", 0, 0.0, 0.0}};
+const char* kTiledNames[3] = {"k_step_dots_t", "k_step_update_t", "k_step_finish_t"};
+const char* kGenericNames[3] = {"k_step_dots", "k_step_update", "k_step_finish"};
 
 struct Plan {
   int R, L, N;
@@ -263,6 +265,7 @@ struct Solver {
 
   // systems per block group of the tiled kernels (see krylov_tiled.h)
   int tile_grp = 1;
+  bool used_tiled = false;   // the last cycle ran the register-resident FP32 kernels
 
   // event pairs around the step kernels of one cycle (profiling only)
   std::vector<hipEvent_t> ev;
@@ -287,6 +290,7 @@ struct Solver {
         if (kind == 2 && j + 1 >= p.mk) continue;   // no finish after the last step
         float ms = 0.f;
         HYDOT_HIP(hipEventElapsedTime(&ms, ev[2 * (3 * j + kind)], ev[2 * (3 * j + kind) + 1]));
+        g_rec[kind].name = used_tiled ? kTiledNames[kind] : kGenericNames[kind];
         g_rec[kind].launches += 1;
         g_rec[kind].ms += ms;
         g_rec[kind].bytes += act * N * b * extra[kind];
@@ -437,6 +441,7 @@ struct Solver {
     dim3 gv(p.nchunks, nb);
     if constexpr (std::is_same<S, cf>::value) {
       if (c.k <= kTK && j + 1 <= kTNV) {
+        used_tiled = true;
         const dim3 gt((unsigned)(nb * p.nchunks));
         const int grp = tile_grp;
         const bool small = j + 1 <= 16;
@@ -453,6 +458,7 @@ struct Solver {
         return;
       }
     }
+    used_tiled = false;
     if (kind == 0) hipLaunchKernelGGL(k_step_dots<S>, gv, dim3(kBlock), 0, stream, c, j);
     else if (kind == 1) hipLaunchKernelGGL(k_step_update<S>, gv, dim3(kBlock), 0, stream, c, j);
     else hipLaunchKernelGGL(k_step_finish<S>, gv, dim3(kBlock), 0, stream, c, j);
