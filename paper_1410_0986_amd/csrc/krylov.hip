@@ -330,9 +330,9 @@ struct Solver {
     hipLaunchKernelGGL(k_unit_v0<cd>, gv, dim3(kBlock), 0, stream, c);
     for (int j = 0; j < nl; ++j) {
       hipLaunchKernelGGL(k_step_dots<cd>, gv, dim3(kBlock), 0, stream, c, j);
-      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j);
+      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j, 0);
       hipLaunchKernelGGL(k_step_update<cd>, gv, dim3(kBlock), 0, stream, c, j);
-      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j);
+      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j, 0);
       hipLaunchKernelGGL(k_step_finish<cd>, gv, dim3(kBlock), 0, stream, c, j);
     }
     HYDOT_HIP(hipGetLastError());
@@ -472,26 +472,26 @@ struct Solver {
     };
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, stream, c.counter);
     hipLaunchKernelGGL(k_inner_resid<S>, gv, dim3(kBlock), 0, stream, c);
-    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0);
+    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0, 0);
     hipLaunchKernelGGL(k_defl_start<S>, gv, dim3(kBlock), 0, stream, c);
-    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0);
+    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0, 0);
     hipLaunchKernelGGL(k_scale_v0<S>, gv, dim3(kBlock), 0, stream, c);
     for (int j = 0; j < p.mk; ++j) {
       rec(j, 0, 0);
       step_kernel<S>(0, c, j, nb);
       rec(j, 0, 1);
-      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j, used_tiled ? 1 : 0);
       rec(j, 1, 0);
       step_kernel<S>(1, c, j, nb);
       rec(j, 1, 1);
-      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j, used_tiled ? 1 : 0);
       if (j + 1 < p.mk) {
         rec(j, 2, 0);
         step_kernel<S>(2, c, j, nb);
         rec(j, 2, 1);
       }
     }
-    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_CYCLE_END, 0);
+    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_CYCLE_END, 0, 0);
     hipLaunchKernelGGL(k_cycle_update<S>, gv, dim3(kBlock), 0, stream, c);
   }
 
@@ -575,7 +575,7 @@ struct Solver {
     for (int sweep = 0; sweep < ra.max_sweeps + 2 && status == HYDOT_OK; ++sweep) {
       hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, stream, c.counter);
       hipLaunchKernelGGL(k_outer_resid<S>, gv, dim3(kBlock), 0, stream, c, 0);
-      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_OUTER, 0);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_OUTER, 0, 0);
       HYDOT_HIP(hipGetLastError());
       if ((status = read_counters(cnt)) != HYDOT_OK) break;
       if (cnt[0] == 0) break;
@@ -608,7 +608,7 @@ struct Solver {
     else
       hipLaunchKernelGGL((k_output<cd, cf>), gv, dim3(kBlock), 0, stream, c64, (cf*)phi);
     hipLaunchKernelGGL(k_outer_resid<cd>, gv, dim3(kBlock), 0, stream, c64, 1);
-    hipLaunchKernelGGL(k_reduce<cd>, gr, dim3(64), 0, stream, c64, ra, (int)PH_FINAL, 0);
+    hipLaunchKernelGGL(k_reduce<cd>, gr, dim3(64), 0, stream, c64, ra, (int)PH_FINAL, 0, 0);
     HYDOT_HIP(hipGetLastError());
     std::vector<SysState> so(nb);
     std::vector<double> fr(nb);

@@ -619,8 +619,11 @@ __device__ inline void gsolve(int k, const cd* L, const cd* f, cd* g) {
   }
 }
 
+// fdirect: the deflation partials of this phase hold f_i = C'_i^H w directly in
+// slot_defl(i, 0) (register-resident FP32 kernels) instead of the three real
+// products C_i^T w, U_i^T w, (rho U_i)^T w.
 template <typename S>
-__global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phase, int j) {
+__global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phase, int j, int fdirect) {
   __shared__ cd sum[kMaxDots];
   __shared__ cd tmp[2 * kMaxK + kMaxMK + 4];
   const int sys = blockIdx.x;
@@ -653,7 +656,8 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
   }
   const int sn = slot_norm(k, c.mkmax);
   for (int s = threadIdx.x; s < c.ndots; s += 64) {
-    const bool want = (need_defl && s < 3 * k) || (s >= lo && s < hi) || (need_norm && s == sn);
+    const bool want = (need_defl && s < 3 * k && (!fdirect || s % 3 == 0)) || (s >= lo && s < hi) ||
+                      (need_norm && s == sn);
     cd a{0.0, 0.0};
     if (want)
       for (int ck = 0; ck < c.nchunks; ++ck) a = a + part[(size_t)ck * c.ndots + s];
@@ -669,8 +673,12 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
   // f_i = C_i^T w + conj(sigma) U_i^T w + sigma'_rel (rho U_i)^T w   (= C'^H w)
   auto make_f = [&]() {
     for (int i = 0; i < k; ++i) {
-      const cd cw = sum[slot_defl(i, 0)], uw = sum[slot_defl(i, 1)], rw = sum[slot_defl(i, 2)];
-      f[i] = cw + conj(sig) * uw + spr * rw;
+      if (fdirect) {
+        f[i] = sum[slot_defl(i, 0)];
+      } else {
+        const cd cw = sum[slot_defl(i, 0)], uw = sum[slot_defl(i, 1)], rw = sum[slot_defl(i, 2)];
+        f[i] = cw + conj(sig) * uw + spr * rw;
+      }
     }
   };
   const cd* Lc = sm + c.sl.Lc;

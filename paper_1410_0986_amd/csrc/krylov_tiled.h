@@ -3,7 +3,7 @@
 // per thread: the thread reads V_0..V_j, C and U of its voxel once from HBM into
 // registers, applies the operator or the projection there, and writes one
 // product per inner product into an LDS tile; the tile is then summed row by
-// row (4 threads per row, FP64), so every lane stays busy and no per-product
+// row (4-8 threads per row, FP64), so every lane stays busy and no per-product
 // wave reduction is needed.  One HBM read of the basis per kernel replaces the
 // double read of the generic CGS2 update.
 //
@@ -35,14 +35,15 @@ struct ProdTile {
   cf p[kTRows * kTRP];
 };
 
+template <int TPR>
 __device__ inline void row_reduce(const ProdTile& pt, int nrows, cd& acc) {
-  const int t = threadIdx.x, row = t >> 2, seg = t & 3;
+  const int t = threadIdx.x, row = t / TPR, seg = t % TPR;
   if (row >= nrows) return;
   const cf* r = pt.p + row * kTRP;
   double re = 0.0, im = 0.0;
 #pragma unroll 8
-  for (int i = 0; i < kTSub / 4; ++i) {
-    const cf x = r[seg + 4 * i];
+  for (int i = 0; i < kTSub / TPR; ++i) {
+    const cf x = r[seg + TPR * i];
     re += (double)x.re;
     im += (double)x.im;
   }
@@ -60,17 +61,31 @@ __device__ inline TileIdx tile_idx(int nchunks, int grp) {
   return TileIdx{g * grp + rem % grp, rem / grp};
 }
 
-// finish the 4-thread row sums and store them as the chunk's partial sums;
+// finish the TPR-thread row sums and store them as the chunk's partial sums;
 // rows map to partial slots through slot0 (+row), the norm row to its own slot
+template <int TPR>
 __device__ inline void row_flush(const Ctx<cf>& c, int sys, int chunk, int nrows, int slot0, int norm_row, cd acc) {
-  acc.re += __shfl_xor(acc.re, 1, 64);
-  acc.im += __shfl_xor(acc.im, 1, 64);
-  acc.re += __shfl_xor(acc.re, 2, 64);
-  acc.im += __shfl_xor(acc.im, 2, 64);
-  const int t = threadIdx.x, row = t >> 2;
-  if ((t & 3) != 0 || row >= nrows) return;
-  const int slot = row == norm_row ? slot_norm(c.k, c.mkmax) : slot0 + row;
+#pragma unroll
+  for (int off = 1; off < TPR; off <<= 1) {
+    acc.re += __shfl_xor(acc.re, off, 64);
+    acc.im += __shfl_xor(acc.im, off, 64);
+  }
+  const int t = threadIdx.x, row = t / TPR;
+  if ((t % TPR) != 0 || row >= nrows) return;
+  const int slot = row == norm_row ? slot_norm(c.k, c.mkmax) : slot0 + 3 * row;
   c.part[((size_t)sys * c.nchunks + chunk) * c.ndots + slot] = acc;
+}
+
+template <int TPR>
+__device__ inline void row_flush_v(const Ctx<cf>& c, int sys, int chunk, int nrows, cd acc) {
+#pragma unroll
+  for (int off = 1; off < TPR; off <<= 1) {
+    acc.re += __shfl_xor(acc.re, off, 64);
+    acc.im += __shfl_xor(acc.im, off, 64);
+  }
+  const int t = threadIdx.x, row = t / TPR;
+  if ((t % TPR) != 0 || row >= nrows) return;
+  c.part[((size_t)sys * c.nchunks + chunk) * c.ndots + slot_v(c.k, row)] = acc;
 }
 
 template <int NV>
@@ -118,11 +133,13 @@ __device__ inline cf project_voxel(cf w, const cf* vr, const float* cr, const fl
   return w;
 }
 
-// Product rows of one voxel: round 0 -> conj(V_l) w for l < nv;
-// round 1 -> C_i w, U_i w, rho U_i w (rows 3i..3i+2) and |w|^2 (row 3k) if with_norm.
+// Product rows of one voxel: round 0 -> conj(V_l) w for l < nv; round 1 ->
+// conj(C'_i) w (row i) with C'_i = C_i + (sigma + sigma'_rel rho) U_i formed per
+// voxel, so f = C'^H w arrives directly (k rows instead of C^T w, U^T w,
+// (rho U)^T w), and |w|^2 (row k) if with_norm.
 template <int NV>
 __device__ inline void write_products(ProdTile& pt, int round, const cf* vr, const float* cr, const float* ur,
-                                      float rho, cf w, int k, int nv, bool with_norm) {
+                                      cd shift, cf w, int k, int nv, bool with_norm) {
   const int t = threadIdx.x;
   if (round == 0) {
 #pragma unroll
@@ -132,15 +149,14 @@ __device__ inline void write_products(ProdTile& pt, int round, const cf* vr, con
         pt.p[l * kTRP + t] = cf{v.re * w.re + v.im * w.im, v.re * w.im - v.im * w.re};
       }
   } else {
+    const float sr = (float)shift.re, si = -(float)shift.im;   // conj(shift)
 #pragma unroll
     for (int i = 0; i < kTK; ++i)
       if (i < k) {
-        pt.p[(3 * i) * kTRP + t] = cf{cr[i] * w.re, cr[i] * w.im};
-        pt.p[(3 * i + 1) * kTRP + t] = cf{ur[i] * w.re, ur[i] * w.im};
-        const float ru = ur[i] * rho;
-        pt.p[(3 * i + 2) * kTRP + t] = cf{ru * w.re, ru * w.im};
+        const float ar = cr[i] + sr * ur[i], ai = si * ur[i];
+        pt.p[i * kTRP + t] = cf{ar * w.re - ai * w.im, ar * w.im + ai * w.re};
       }
-    if (with_norm) pt.p[(3 * k) * kTRP + t] = cf{w.re * w.re + w.im * w.im, 0.f};
+    if (with_norm) pt.p[k * kTRP + t] = cf{w.re * w.re + w.im * w.im, 0.f};
   }
 }
 
@@ -163,7 +179,7 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
     for (int l = 0; l < NV; ++l) h[l] = l < nv ? Store<cf>::from(coef[k + l]) : cf{0.f, 0.f};
   }
   const bool with_norm = KIND == 1;
-  const int drows = 3 * k + (with_norm ? 1 : 0);
+  const int drows = k + (with_norm ? 1 : 0);
   cd accv{0.0, 0.0}, accd{0.0, 0.0};
   for (int sub = 0; sub < kChunk / kTSub; ++sub) {
     const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
@@ -172,11 +188,11 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
     float cr[kTK], ur[kTK];
     load_basis<NV>(Vsys, N, n, ok, nv, vr);
     load_cu(c, p.rhs, N, n, ok, cr, ur);
-    float rho = 0.f;
+    double rho = 0.0;
     cf w{0.f, 0.f};
     if (ok) {
       const VoxelInfo vi = voxel_info(c.g, n);
-      rho = (float)((double)vi.nrobin * c.g.inv_h);
+      rho = (double)vi.nrobin * c.g.inv_h;
       if (KIND == 0) {
         w = apply_op<cf>(c.g, Vsys + (size_t)j * N, n, vi, p.sig, p.sigp_abs);
       } else {
@@ -184,19 +200,22 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
       }
       wv[n] = w;
     }
-    write_products<NV>(pt, 0, vr, cr, ur, rho, w, k, nv, with_norm);
+    const cd shift{p.sig.re + p.sigp_rel * rho, p.sig.im};
+    write_products<NV>(pt, 0, vr, cr, ur, shift, w, k, nv, with_norm);
     __syncthreads();
-    row_reduce(pt, nv, accv);
+    if (NV <= 16) row_reduce<8>(pt, nv, accv);
+    else row_reduce<4>(pt, nv, accv);
     __syncthreads();
     if (drows > 0) {
-      write_products<NV>(pt, 1, vr, cr, ur, rho, w, k, nv, with_norm);
+      write_products<NV>(pt, 1, vr, cr, ur, shift, w, k, nv, with_norm);
       __syncthreads();
-      row_reduce(pt, drows, accd);
+      row_reduce<8>(pt, drows, accd);
       __syncthreads();
     }
   }
-  row_flush(c, sys, ti.chunk, nv, slot_v(k, 0), -1, accv);
-  if (drows > 0) row_flush(c, sys, ti.chunk, drows, 0, with_norm ? 3 * k : -1, accd);
+  if (NV <= 16) row_flush_v<8>(c, sys, ti.chunk, nv, accv);
+  else row_flush_v<4>(c, sys, ti.chunk, nv, accv);
+  if (drows > 0) row_flush<8>(c, sys, ti.chunk, drows, 0, with_norm ? k : -1, accd);
 }
 
 // W = A_hat V_j and first-pass inner products (tiled form of k_step_dots).
