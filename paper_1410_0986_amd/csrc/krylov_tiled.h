@@ -26,6 +26,7 @@ constexpr int kTNV = 32;                    // largest basis count handled here
 constexpr int kTRows = 32;                  // rows of the product tile
 constexpr int kTRP = kTSub + 4;             // padded product row
 static_assert(kChunk % kTSub == 0, "chunk must hold whole sub-tiles");
+static_assert(16 + kTK + 1 <= kTRows, "single-round tile must hold 16 basis rows, k deflation rows and the norm");
 static_assert(3 * kTK + 1 <= kTRows && kTNV <= kTRows, "product tile too small");
 
 // Products of one sub-tile, one row per inner product, then reduced row-wise:
@@ -55,7 +56,13 @@ struct TileIdx {
   int sys, chunk;
 };
 __device__ inline TileIdx tile_idx(int nchunks, int grp) {
-  const int b = blockIdx.x;
+  // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
+  // Give each XCD a contiguous range of the logical order so that one XCD runs
+  // all wavelengths of a (right-hand side, chunk) group and, soon after, the
+  // neighbouring chunks whose planes form the stencil halo (its own L2).
+  const int nblk = gridDim.x;
+  int b = blockIdx.x;
+  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
   const int per = grp * nchunks;
   const int g = b / per, rem = b - g * per;
   return TileIdx{g * grp + rem % grp, rem / grp};
@@ -86,6 +93,24 @@ __device__ inline void row_flush_v(const Ctx<cf>& c, int sys, int chunk, int nro
   const int t = threadIdx.x, row = t / TPR;
   if ((t % TPR) != 0 || row >= nrows) return;
   c.part[((size_t)sys * c.nchunks + chunk) * c.ndots + slot_v(c.k, row)] = acc;
+}
+
+// Single-round form (at most 16 basis vectors): rows [0, nv) V dots, [nv, nv+k)
+// f = C'^H w, row nv+k the norm; all in one tile, flushed to their slots.
+template <int TPR>
+__device__ inline void row_flush_all(const Ctx<cf>& c, int sys, int chunk, int nv, int nrows, cd acc) {
+#pragma unroll
+  for (int off = 1; off < TPR; off <<= 1) {
+    acc.re += __shfl_xor(acc.re, off, 64);
+    acc.im += __shfl_xor(acc.im, off, 64);
+  }
+  const int t = threadIdx.x, row = t / TPR;
+  if ((t % TPR) != 0 || row >= nrows) return;
+  int slot;
+  if (row < nv) slot = slot_v(c.k, row);
+  else if (row < nv + c.k) slot = slot_defl(row - nv, 0);
+  else slot = slot_norm(c.k, c.mkmax);
+  c.part[((size_t)sys * c.nchunks + chunk) * c.ndots + slot] = acc;
 }
 
 template <int NV>
@@ -139,7 +164,7 @@ __device__ inline cf project_voxel(cf w, const cf* vr, const float* cr, const fl
 // (rho U)^T w), and |w|^2 (row k) if with_norm.
 template <int NV>
 __device__ inline void write_products(ProdTile& pt, int round, const cf* vr, const float* cr, const float* ur,
-                                      cd shift, cf w, int k, int nv, bool with_norm) {
+                                      cd shift, cf w, int k, int nv, bool with_norm, int row0 = 0) {
   const int t = threadIdx.x;
   if (round == 0) {
 #pragma unroll
@@ -154,9 +179,9 @@ __device__ inline void write_products(ProdTile& pt, int round, const cf* vr, con
     for (int i = 0; i < kTK; ++i)
       if (i < k) {
         const float ar = cr[i] + sr * ur[i], ai = si * ur[i];
-        pt.p[i * kTRP + t] = cf{ar * w.re - ai * w.im, ar * w.im + ai * w.re};
+        pt.p[(row0 + i) * kTRP + t] = cf{ar * w.re - ai * w.im, ar * w.im + ai * w.re};
       }
-    if (with_norm) pt.p[k * kTRP + t] = cf{w.re * w.re + w.im * w.im, 0.f};
+    if (with_norm) pt.p[(row0 + k) * kTRP + t] = cf{w.re * w.re + w.im * w.im, 0.f};
   }
 }
 
@@ -181,13 +206,29 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
   const bool with_norm = KIND == 1;
   const int drows = k + (with_norm ? 1 : 0);
   cd accv{0.0, 0.0}, accd{0.0, 0.0};
-  for (int sub = 0; sub < kChunk / kTSub; ++sub) {
+  // Register double buffer (instances with at most 16 basis vectors): the next
+  // sub-tile's loads are issued before this sub-tile's barriers and row sums,
+  // which wait on LDS only, so HBM traffic overlaps the reduction.
+  constexpr bool kPre = NV <= 16;
+  constexpr int nsub = kChunk / kTSub;
+  cf vr[NV];
+  float cr[kTK], ur[kTK];
+  cf wpre{0.f, 0.f};
+  {
+    const uint32_t n0 = ti.chunk * kChunk + t;
+    const bool ok0 = n0 < (uint32_t)c.g.N;
+    load_basis<NV>(Vsys, N, n0, ok0, nv, vr);
+    load_cu(c, p.rhs, N, n0, ok0, cr, ur);
+    if (KIND == 1 && ok0) wpre = wv[n0];
+  }
+  for (int sub = 0; sub < nsub; ++sub) {
     const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
     const bool ok = n < (uint32_t)c.g.N;
-    cf vr[NV];
-    float cr[kTK], ur[kTK];
-    load_basis<NV>(Vsys, N, n, ok, nv, vr);
-    load_cu(c, p.rhs, N, n, ok, cr, ur);
+    if (!kPre && sub > 0) {
+      load_basis<NV>(Vsys, N, n, ok, nv, vr);
+      load_cu(c, p.rhs, N, n, ok, cr, ur);
+      if (KIND == 1 && ok) wpre = wv[n];
+    }
     double rho = 0.0;
     cf w{0.f, 0.f};
     if (ok) {
@@ -196,26 +237,44 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
       if (KIND == 0) {
         w = apply_op<cf>(c.g, Vsys + (size_t)j * N, n, vi, p.sig, p.sigp_abs);
       } else {
-        w = project_voxel<NV>(wv[n], vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
+        w = project_voxel<NV>(wpre, vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
       }
       wv[n] = w;
     }
     const cd shift{p.sig.re + p.sigp_rel * rho, p.sig.im};
-    write_products<NV>(pt, 0, vr, cr, ur, shift, w, k, nv, with_norm);
-    __syncthreads();
-    if (NV <= 16) row_reduce<8>(pt, nv, accv);
-    else row_reduce<4>(pt, nv, accv);
-    __syncthreads();
-    if (drows > 0) {
-      write_products<NV>(pt, 1, vr, cr, ur, shift, w, k, nv, with_norm);
+    if constexpr (NV <= 16) {
+      // one round: V rows, then the deflation rows and the norm row below them
+      write_products<NV>(pt, 0, vr, cr, ur, shift, w, k, nv, with_norm);
+      if (drows > 0) write_products<NV>(pt, 1, vr, cr, ur, shift, w, k, nv, with_norm, nv);
+      if (kPre && sub + 1 < nsub) {
+        const uint32_t nn = n + kTSub;
+        const bool okn = nn < (uint32_t)c.g.N;
+        load_basis<NV>(Vsys, N, nn, okn, nv, vr);
+        load_cu(c, p.rhs, N, nn, okn, cr, ur);
+        if (KIND == 1 && okn) wpre = wv[nn];
+      }
       __syncthreads();
-      row_reduce<8>(pt, drows, accd);
+      row_reduce<4>(pt, nv + drows, accv);
       __syncthreads();
+    } else {
+      write_products<NV>(pt, 0, vr, cr, ur, shift, w, k, nv, with_norm);
+      __syncthreads();
+      row_reduce<4>(pt, nv, accv);
+      __syncthreads();
+      if (drows > 0) {
+        write_products<NV>(pt, 1, vr, cr, ur, shift, w, k, nv, with_norm);
+        __syncthreads();
+        row_reduce<8>(pt, drows, accd);
+        __syncthreads();
+      }
     }
   }
-  if (NV <= 16) row_flush_v<8>(c, sys, ti.chunk, nv, accv);
-  else row_flush_v<4>(c, sys, ti.chunk, nv, accv);
-  if (drows > 0) row_flush<8>(c, sys, ti.chunk, drows, 0, with_norm ? k : -1, accd);
+  if constexpr (NV <= 16) {
+    row_flush_all<4>(c, sys, ti.chunk, nv, nv + drows, accv);
+  } else {
+    row_flush_v<4>(c, sys, ti.chunk, nv, accv);
+    if (drows > 0) row_flush<8>(c, sys, ti.chunk, drows, 0, with_norm ? k : -1, accd);
+  }
 }
 
 // W = A_hat V_j and first-pass inner products (tiled form of k_step_dots).
