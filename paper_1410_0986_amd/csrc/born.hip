@@ -9,6 +9,11 @@
 // partial products of the complex one.  FP32 fields use
 // v_mfma_f32_16x16x4_f32 with per-stage FP64 accumulation and FP64 split-K
 // sums; FP64 fields use v_mfma_f64_16x16x4_f64.
+//
+// J v stages coalesced row segments of Phi_s v and Phi_d through LDS (the MFMA
+// operand layout puts 16 different rows in the lanes of one k-slot).  J^H w feeds
+// its MFMA operands straight from global memory with no LDS and no barrier: the
+// 16 lanes of a k-slot read 16 consecutive voxels of one source row.
 #include <algorithm>
 #include <cmath>
 
@@ -39,7 +44,7 @@ template <> struct Mfma<double> {
   __device__ static inline int out_row(int lane, int r) { return 4 * r + (lane >> 4); }
 };
 
-constexpr size_t kLdsCap = 64 * 1024;   // LDS budget per block
+constexpr size_t kLdsCap = 64 * 1024;   // LDS budget per block of J v
 
 inline int pad8(int x) { return (x + 7) / 8 * 8; }
 
@@ -150,79 +155,72 @@ __global__ void k_born_apply_finish(int S, int D, int Sp, int Dp, int nsplit, in
 }
 
 // ---------------------------------------------------------------- J^H w
-// Block = WAVES waves, 16 voxels per wave; loops over all wavelengths and keeps
-// g for its voxels in registers.  Per wavelength, T = A'' B'' on MFMA with
+// Each wave owns 16 voxels and loops over all wavelengths, keeping g for its
+// voxels in FP64 registers.  Per wavelength, T = A'' B'' on MFMA with
 // A'' = [Re phi_s | Im phi_s] (voxels x 2Sp) and B'' = [[Re w, Im w], [Im w, -Re w]]
-// (2Sp x 2Dp), giving [Re T | Im T] with T = conj(Phi_s)^T-weighted sums; the
-// epilogue contracts T with conj(phi_d) per voxel.
-template <typename T, int WAVES, int TBM>
-__global__ __launch_bounds__(64 * WAVES) void k_born_adjoint(int N, int S, int D, int Sp, int Dp, int64_t lam_stride,
-                                                            int L, const cplx<T>* __restrict__ phs,
-                                                            const cplx<T>* __restrict__ phd,
-                                                            const cplx<T>* __restrict__ w, double scale,
-                                                            cplx<T>* __restrict__ g) {
-  constexpr int VB = 16 * WAVES;      // voxels per block
-  constexpr int VP = VB + 4;          // padded
-  extern __shared__ unsigned char smem_raw[];
-  T* As = (T*)smem_raw;                          // [2Sp][VP]
-  T* Ds = As + 2 * Sp * VP;                      // [2Dp][VP]  (Re rows, then Im rows)
+// (2Sp x 2Dp), giving [Re T | Im T] with T[k][d] = sum_s conj(phi_s(k)) w[s][d];
+// the epilogue contracts T with conj(phi_d) per voxel.  Lane (voxel i = lane%16,
+// slot gq = lane/16) loads the sources s = gq (mod 4) of its voxel once and uses
+// their real parts for k-index s and imaginary parts for k-index Sp + s.
+template <typename T, int TBM, int SQ>
+__global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, int Sp, int Dp, int64_t lam_stride,
+                                                        int L, const cplx<T>* __restrict__ phs,
+                                                        const cplx<T>* __restrict__ phd,
+                                                        const cplx<T>* __restrict__ w, double scale,
+                                                        cplx<T>* __restrict__ g) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int vbase = blockIdx.x * VB;
+  const int i16 = lane & 15, gq = lane >> 4;
+  const int vox0 = (blockIdx.x * 4 + wave) * 16;
   const int TB = 2 * Dp / 16;
+  const int vox = vox0 + i16;
+  const bool vok = vox < N;
   using MA = typename Mfma<T>::acc;
   double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
   for (int l = 0; l < L; ++l) {
     const cplx<T>* ps = phs + (size_t)l * lam_stride * N;
     const cplx<T>* pd = phd + (size_t)l * lam_stride * N;
-    for (int i = threadIdx.x; i < Sp * VB; i += 64 * WAVES) {
-      const int s = i / VB, vv = i % VB;
-      cplx<T> z{0, 0};
-      if (s < S && vbase + vv < N) z = ps[(size_t)s * N + vbase + vv];
-      As[s * VP + vv] = z.re;
-      As[(Sp + s) * VP + vv] = z.im;
-    }
-    for (int i = threadIdx.x; i < Dp * VB; i += 64 * WAVES) {
-      const int d = i / VB, vv = i % VB;
-      cplx<T> z{0, 0};
-      if (d < D && vbase + vv < N) z = pd[(size_t)d * N + vbase + vv];
-      Ds[d * VP + vv] = z.re;
-      Ds[(Dp + d) * VP + vv] = z.im;
-    }
     const cplx<T>* wl = w + (size_t)l * S * D;
-    __syncthreads();
+    cplx<T> z[SQ];   // phi_s[s][vox] for s = gq + 4q
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      const int s = gq + 4 * q;
+      z[q] = (q < Sp / 4 && s < S && vok) ? ps[(size_t)s * N + vox] : cplx<T>{0, 0};
+    }
     MA acc[TBM];
 #pragma unroll
     for (int t = 0; t < TBM; ++t) acc[t] = MA{0, 0, 0, 0};
-    const int vox = wave * 16 + (lane & 15);
-    for (int kk = 0; kk < 2 * Sp; kk += 4) {
-      const int kidx = kk + (lane >> 4);
-      const T a = As[kidx * VP + vox];
-      const bool brow = kidx >= Sp;             // rows of Im phi_s
-      const int s = brow ? kidx - Sp : kidx;
+    // k-index s = gq + 4q uses Re z[q], k-index Sp + s uses Im z[q]
 #pragma unroll
-      for (int t = 0; t < TBM; ++t) {
-        if (t < TB) {
-          const int col = t * 16 + (lane & 15);
-          const bool imcol = col >= Dp;
-          const int d = imcol ? col - Dp : col;
-          const cplx<T> ww = (s < S && d < D) ? wl[s * D + d] : cplx<T>{0, 0};
-          // B'' = [[Re w, Im w], [Im w, -Re w]]
-          const T b = brow ? (imcol ? -ww.re : ww.im) : (imcol ? ww.im : ww.re);
-          acc[t] = Mfma<T>::step(a, b, acc[t]);
+    for (int q = 0; q < SQ; ++q) {
+      if (q < Sp / 4) {
+        const int s = gq + 4 * q;
+#pragma unroll
+        for (int t = 0; t < TBM; ++t) {
+          if (t < TB) {
+            const int col = t * 16 + i16;
+            const bool imcol = col >= Dp;
+            const int d = imcol ? col - Dp : col;
+            const cplx<T> ww = (s < S && d < D) ? wl[s * D + d] : cplx<T>{0, 0};
+            // B'' = [[Re w, Im w], [Im w, -Re w]]: rows of Re phi_s, then rows of Im phi_s
+            acc[t] = Mfma<T>::step(z[q].re, imcol ? ww.im : ww.re, acc[t]);
+            acc[t] = Mfma<T>::step(z[q].im, imcol ? -ww.re : ww.im, acc[t]);
+          }
         }
       }
     }
-    // epilogue: lane holds T[voxel = wave*16 + out_row(lane, r)][col = t*16 + lane%16]
+    // epilogue: lane holds T[voxel vox0 + out_row(lane, r)][col t*16 + lane%16]
 #pragma unroll
     for (int t = 0; t < TBM; ++t) {
       if (t < TB) {
-        const int col = t * 16 + (lane & 15);
+        const int col = t * 16 + i16;
         const bool imcol = col >= Dp;
         const int d = imcol ? col - Dp : col;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int vv = wave * 16 + Mfma<T>::out_row(lane, r);
-          const double e = Ds[d * VP + vv], f = Ds[(Dp + d) * VP + vv];
+          const int vv = vox0 + Mfma<T>::out_row(lane, r);
+          cplx<T> ph{0, 0};
+          if (d < D && vv < N) ph = pd[(size_t)d * N + vv];
+          const double e = ph.re, f = ph.im;
           const double tv = (double)acc[t][r];
           if (!imcol) {          // Re T column
             gre[r] += e * tv;
@@ -234,7 +232,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_born_adjoint(int N, int S, int D
         }
       }
     }
-    __syncthreads();
   }
   // reduce over the 16 lanes that share a voxel (lane & 15 varies)
 #pragma unroll
@@ -245,10 +242,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_born_adjoint(int N, int S, int D
       gim[r] += __shfl_xor(gim[r], off, 64);
     }
   }
-  if ((lane & 15) == 0) {
+  if (i16 == 0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int vv = vbase + wave * 16 + Mfma<T>::out_row(lane, r);
+      const int vv = vox0 + Mfma<T>::out_row(lane, r);
       if (vv < N) g[vv] = cplx<T>{(T)(scale * gre[r]), (T)(scale * gim[r])};
     }
   }
@@ -261,7 +258,8 @@ hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, c
   const int Sp = pad8(S), Dp = pad8(D);
   const int T_all = (2 * Sp / 16) * (2 * Dp / 16);
   const int tpw = (T_all + 3) / 4;
-  // voxels per LDS stage: 32 when the staged rows fit the LDS budget, else 16
+  // voxels per LDS stage: 32 when the staged rows fit the LDS budget, else 16 (larger
+  // stages lower the number of resident blocks per CU and measure slower)
   const int kt = (size_t)(2 * Sp + 2 * Dp) * 36 * sizeof(T) + 32 * sizeof(T) <= kLdsCap ? 32 : 16;
   // split-K so the grid has a few thousand blocks
   const int max_split = (N + kt - 1) / kt;
@@ -296,37 +294,28 @@ hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, c
   return HYDOT_OK;
 }
 
-template <typename T, int WAVES>
-hydot_status born_adjoint_launch(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
-                                 int64_t ls, const void* w, void* g, hipStream_t stream) {
-  const int N = op->gp.N, L = op->L;
-  const int Sp = pad8(S), Dp = pad8(D);
-  const int TB = 2 * Dp / 16;
-  constexpr int VB = 16 * WAVES, VP = VB + 4;
-  const size_t lds = (size_t)(2 * Sp + 2 * Dp) * VP * sizeof(T);
-  dim3 grid((N + VB - 1) / VB);
-  const double h = op->grid.h_mm;
-  const double sc = -h * h * h;
-#define HYDOT_BJ(TBM)                                                                                     \
-  hipLaunchKernelGGL((k_born_adjoint<T, WAVES, TBM>), grid, dim3(64 * WAVES), lds, stream, N, S, D, Sp, Dp, \
-                     ls, L, (const cplx<T>*)phs, (const cplx<T>*)phd, (const cplx<T>*)w, sc, (cplx<T>*)g)
-  if (TB <= 1) HYDOT_BJ(1);
-  else if (TB <= 2) HYDOT_BJ(2);
-  else if (TB <= 4) HYDOT_BJ(4);
-  else HYDOT_BJ(8);
-#undef HYDOT_BJ
-  HYDOT_HIP(hipGetLastError());
-  return HYDOT_OK;
-}
-
-// waves per block: as many as fit the LDS budget (16 voxels each)
 template <typename T>
 hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
                                int64_t ls, const void* w, void* g, hipStream_t stream) {
-  const size_t rows = (size_t)(2 * pad8(S) + 2 * pad8(D));
-  if (rows * 68 * sizeof(T) <= kLdsCap) return born_adjoint_launch<T, 4>(op, phs, S, phd, D, ls, w, g, stream);
-  if (rows * 36 * sizeof(T) <= kLdsCap) return born_adjoint_launch<T, 2>(op, phs, S, phd, D, ls, w, g, stream);
-  return born_adjoint_launch<T, 1>(op, phs, S, phd, D, ls, w, g, stream);
+  const int N = op->gp.N, L = op->L;
+  const int Sp = pad8(S), Dp = pad8(D);
+  const int TB = 2 * Dp / 16;
+  dim3 grid((N + 63) / 64);
+  const double h = op->grid.h_mm;
+  const double sc = -h * h * h;
+#define HYDOT_BJ(TBM, SQ)                                                                                   \
+  hipLaunchKernelGGL((k_born_adjoint<T, TBM, SQ>), grid, dim3(kBlock), 0, stream, N, S, D, Sp, Dp, ls, L,   \
+                     (const cplx<T>*)phs, (const cplx<T>*)phd, (const cplx<T>*)w, sc, (cplx<T>*)g)
+#define HYDOT_BJ_S(TBM) \
+  if (Sp <= 16) HYDOT_BJ(TBM, 4); else if (Sp <= 32) HYDOT_BJ(TBM, 8); else HYDOT_BJ(TBM, 16);
+  if (TB <= 1) { HYDOT_BJ_S(1) }
+  else if (TB <= 2) { HYDOT_BJ_S(2) }
+  else if (TB <= 4) { HYDOT_BJ_S(4) }
+  else { HYDOT_BJ_S(8) }
+#undef HYDOT_BJ_S
+#undef HYDOT_BJ
+  HYDOT_HIP(hipGetLastError());
+  return HYDOT_OK;
 }
 
 static hydot_status born_check(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
