@@ -158,6 +158,47 @@ __device__ inline cf project_voxel(cf w, const cf* vr, const float* cr, const fl
   return w;
 }
 
+// Stencil operands of voxel n of x, gathered into registers ahead of use: the
+// centre and the six face neighbours (zero where the neighbour is outside).
+struct StencilRegs {
+  cf xc, m[6];
+};
+__device__ inline void gather_stencil(const GridP& g, const cf* __restrict__ x, uint32_t n, bool ok,
+                                      const VoxelInfo& vi, StencilRegs& sr) {
+  // every load reads a valid address (voxel 0 stands in for a missing neighbour)
+  // and the unwanted values are zeroed afterwards, so the loads stay unconditional
+  const uint32_t sy = (uint32_t)g.nx, sz = (uint32_t)g.nx * (uint32_t)g.ny;
+  const bool has[6] = {ok && vi.i > 0, ok && vi.i < g.nx - 1, ok && vi.j > 0,
+                       ok && vi.j < g.ny - 1, ok && vi.k > 0, ok && vi.k < g.nz - 1};
+  const uint32_t nb[6] = {n - 1, n + 1, n - sy, n + sy, n - sz, n + sz};
+  const cf c = x[ok ? n : 0u];
+  sr.xc = ok ? c : cf{0.f, 0.f};
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const cf m = x[has[f] ? nb[f] : 0u];
+    sr.m[f] = has[f] ? m : cf{0.f, 0.f};
+  }
+}
+// (A_hat x)_n from gathered operands: the same arithmetic as apply_op.
+__device__ inline cf stencil_apply(const GridP& g, const StencilRegs& sr, const VoxelInfo& vi, cd sig,
+                                   double sigp) {
+  const int nn = 6 - (vi.i == 0) - (vi.i == g.nx - 1) - (vi.j == 0) - (vi.j == g.ny - 1) - (vi.k == 0) -
+                 (vi.k == g.nz - 1);
+  float ar = 0.f, ai = 0.f;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    ar -= sr.m[f].re;
+    ai -= sr.m[f].im;
+  }
+  const float diag_k = (float)(nn + 2 * vi.ndir);
+  const float ih2 = (float)g.inv_h2;
+  const float dr = (float)(sig.re + sigp * (double)vi.nrobin * g.inv_h);
+  const float di = (float)sig.im;
+  const cf xc = sr.xc;
+  return cf{ih2 * (diag_k * xc.re + ar) + (dr * xc.re - di * xc.im),
+            ih2 * (diag_k * xc.im + ai) + (dr * xc.im + di * xc.re)};
+}
+
 // Product rows of one voxel: round 0 -> conj(V_l) w for l < nv; round 1 ->
 // conj(C'_i) w (row i) with C'_i = C_i + (sigma + sigma'_rel rho) U_i formed per
 // voxel, so f = C'^H w arrives directly (k rows instead of C^T w, U^T w,
@@ -214,11 +255,16 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
   cf vr[NV];
   float cr[kTK], ur[kTK];
   cf wpre{0.f, 0.f};
+  const cf* vj = Vsys + (size_t)j * N;
+  StencilRegs sreg;
+  VoxelInfo vinf;
   {
     const uint32_t n0 = ti.chunk * kChunk + t;
     const bool ok0 = n0 < (uint32_t)c.g.N;
     load_basis<NV>(Vsys, N, n0, ok0, nv, vr);
     load_cu(c, p.rhs, N, n0, ok0, cr, ur);
+    vinf = voxel_info(c.g, ok0 ? n0 : 0u);
+    if (KIND == 0) gather_stencil(c.g, vj, n0, ok0, vinf, sreg);
     if (KIND == 1 && ok0) wpre = wv[n0];
   }
   for (int sub = 0; sub < nsub; ++sub) {
@@ -227,15 +273,17 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
     if (!kPre && sub > 0) {
       load_basis<NV>(Vsys, N, n, ok, nv, vr);
       load_cu(c, p.rhs, N, n, ok, cr, ur);
+      vinf = voxel_info(c.g, ok ? n : 0u);
+      if (KIND == 0) gather_stencil(c.g, vj, n, ok, vinf, sreg);
       if (KIND == 1 && ok) wpre = wv[n];
     }
     double rho = 0.0;
     cf w{0.f, 0.f};
     if (ok) {
-      const VoxelInfo vi = voxel_info(c.g, n);
+      const VoxelInfo vi = vinf;
       rho = (double)vi.nrobin * c.g.inv_h;
       if (KIND == 0) {
-        w = apply_op<cf>(c.g, Vsys + (size_t)j * N, n, vi, p.sig, p.sigp_abs);
+        w = stencil_apply(c.g, sreg, vi, p.sig, p.sigp_abs);
       } else {
         w = project_voxel<NV>(wpre, vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
       }
@@ -251,6 +299,8 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
         const bool okn = nn < (uint32_t)c.g.N;
         load_basis<NV>(Vsys, N, nn, okn, nv, vr);
         load_cu(c, p.rhs, N, nn, okn, cr, ur);
+        vinf = voxel_info(c.g, okn ? nn : 0u);
+        if (KIND == 0) gather_stencil(c.g, vj, nn, okn, vinf, sreg);
         if (KIND == 1 && okn) wpre = wv[nn];
       }
       __syncthreads();
