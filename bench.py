@@ -128,8 +128,17 @@ def main():
         def solve():
             return hd.solve_fields(op, vox, opts, out=phi)
 
+        # launch shapes: the autotuner times its candidates on this problem (set-up, not timed)
+        solve_trials = hd.autotune_solve(op, vox, opts, out=phi)
+        log(f"autotune of the step kernels done ({len(solve_trials)} candidates)")
+        for t, ms in solve_trials:
+            log(f"  presum {t['step_presum']} order {t['step_order']} group {t['step_group']}: {ms:.1f} ms")
         # observed data of the PaLS model at the truth (set-up, not timed)
         solve()
+        born_trials = hd.autotune_born(op, phi[:, :S], phi[:, S:], v)
+        log(f"autotune of J v done ({len(born_trials)} candidates)")
+        for t, ms in born_trials:
+            log(f"  stage {t['born_stage']} blocks {t['born_blocks']}: {ms:.4f} ms")
         mu_t = hd.pals_shape(op, p_true, dtype=torch.float32, device=dev)
         Jmu = hd.born_apply(op, phi[:, :S], phi[:, S:], mu_t[None])[0]
         ebar = torch.from_numpy(dc_true @ w.extinction).to(dev).to(torch.float32)
@@ -250,6 +259,8 @@ def main():
         "plain_fp64": plain,
         "speedup_vs_plain": round(solves_per_s / plain["solves_per_s"], 2) if plain else None,
         "roofline": roof,
+        "tuning": {**hd.get_tuning(op), "solve_candidates": len(solve_trials),
+                   "born_candidates": len(born_trials)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_sample)

@@ -197,6 +197,51 @@ hydot_status hydot_misfit(const hydot_operator* op, int32_t S, int32_t D, const 
                           void* w_adj, double* f, double* grad_dconc, void* workspace,
                           size_t ws_bytes, hipStream_t stream);
 
+/* Launch shapes of the hot kernels, held by the operator and used by every later call on it.
+ * They change only the speed and the FP32 summation order (so results within the tolerance of
+ * the precision in use), never the method.  A field set to 0 selects the library default.
+ *   step_presum  Arnoldi step kernels of the complex FP32 path: number of neighbouring lanes
+ *                (1, 2 or 4) whose inner-product terms are summed in registers before the LDS
+ *                product tile; 2 and 4 shrink the tile so more blocks fit a CU (default 4).
+ *   step_order   1: blocks ordered so each XCD runs a contiguous range of (system, chunk) tiles;
+ *                2: plain dispatch order (default 1).
+ *   step_group   1: consecutive blocks walk the wavelengths of one right-hand side at one chunk
+ *                (shared recycled basis in L2); 2: no grouping (default 1).
+ *   born_stage   J v voxels per LDS stage: 16 or 32 (default: 32 where the stage fits 64 KB).
+ *   born_blocks  J v target grid size in blocks (split over voxels), 256..65536 (default 4096). */
+typedef struct {
+  int32_t step_presum, step_order, step_group;
+  int32_t born_stage, born_blocks;
+} hydot_tuning;
+hydot_status hydot_get_tuning(const hydot_operator* op, hydot_tuning* out);   /* resolved values */
+hydot_status hydot_set_tuning(hydot_operator* op, const hydot_tuning* t);      /* EINVAL if out of range */
+
+/* Autotuner.  Each trial is one candidate hydot_tuning and its measured time in ms. */
+typedef struct {
+  hydot_tuning t;
+  double ms;
+} hydot_tune_trial;
+
+/* Times every candidate (step_presum x step_order x step_group) on the caller's problem: a
+ * hydot_solve_fields call with the given arguments whose total inner iterations are capped at
+ * two restart cycles, timed by HIP events around the Arnoldi step kernels only.  The fastest
+ * candidate is stored in the operator.  phi receives the (unconverged) fields of the last trial.
+ * trials: host [max_trials] or NULL; n_trials: host, number of candidates timed.
+ * Synchronises the stream.  Not thread-safe (uses the process-wide instrumentation). */
+hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
+                                  const hydot_solve_opts* opts, void* phi, hydot_dtype phi_dtype,
+                                  void* workspace, size_t ws_bytes, hydot_tune_trial* trials,
+                                  int32_t max_trials, int32_t* n_trials, hipStream_t stream);
+
+/* Times every J v candidate (born_stage x born_blocks) on the given arguments (the median of
+ * 5 calls of hydot_born_apply each) and stores the fastest in the operator; y receives the
+ * product.  Arguments as hydot_born_apply; trials and n_trials as hydot_autotune_solve.
+ * Synchronises the stream. */
+hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
+                                 int32_t D, int64_t lam_stride, hydot_dtype field_dtype, const void* v,
+                                 int32_t n_v, void* y, hydot_tune_trial* trials, int32_t max_trials,
+                                 int32_t* n_trials, hipStream_t stream);
+
 /* Measurement instrumentation (not part of the method).  While enabled, hydot_solve_fields
  * records HIP events on its stream around every launch of the three Arnoldi step kernels
  * (first-pass dots with the operator, CGS2 update, normalisation) and accumulates, per

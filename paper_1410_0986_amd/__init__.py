@@ -25,6 +25,10 @@ from ._binding import (  # noqa: F401
     version,
     profile_enable,
     profile_read,
+    get_tuning,
+    set_tuning,
+    autotune_solve,
+    autotune_born,
     C128, C64, F64, F32,
     PREC_FP64, PREC_MIXED,
     FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM,

@@ -79,6 +79,24 @@ _misfit = _proto("hydot_misfit", c_int32, c_void_p, c_int32, c_int32, POINTER(c_
                  c_void_p, c_int32, c_void_p, POINTER(c_double), POINTER(c_double), c_void_p, c_size_t, c_void_p)
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("step_presum", c_int32), ("step_order", c_int32), ("step_group", c_int32),
+                ("born_stage", c_int32), ("born_blocks", c_int32)]
+
+
+class _Trial(ctypes.Structure):
+    _fields_ = [("t", _Tuning), ("ms", c_double)]
+
+
+_get_tuning = _proto("hydot_get_tuning", c_int32, c_void_p, POINTER(_Tuning))
+_set_tuning = _proto("hydot_set_tuning", c_int32, c_void_p, POINTER(_Tuning))
+_tune_solve = _proto("hydot_autotune_solve", c_int32, c_void_p, c_int32, POINTER(c_int64), POINTER(_SolveOpts),
+                     c_void_p, c_int32, c_void_p, c_size_t, POINTER(_Trial), c_int32, POINTER(c_int32), c_void_p)
+_tune_born = _proto("hydot_autotune_born", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32,
+                    c_void_p, c_int32, c_void_p, POINTER(_Trial), c_int32, POINTER(c_int32), c_void_p)
+_TUNE_FIELDS = ("step_presum", "step_order", "step_group", "born_stage", "born_blocks")
+
+
 class _KProf(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int64), ("total_ms", c_double),
                 ("total_bytes", c_double)]
@@ -259,6 +277,71 @@ def solve_fields(op: Operator, rhs_voxels, opts: SolveOptions | None = None, out
     _check(st, allow_noconv=True)
     del buf
     return out, iters.reshape(op.L, R), rel.reshape(op.L, R), st
+
+
+def get_tuning(op: Operator) -> dict:
+    """Launch shapes the operator uses (hydot_get_tuning), defaults resolved."""
+    t = _Tuning()
+    _check(_get_tuning(op.handle, ctypes.byref(t)))
+    return {f: int(getattr(t, f)) for f in _TUNE_FIELDS}
+
+
+def set_tuning(op: Operator, **fields) -> None:
+    """Set launch shapes (hydot_set_tuning); unnamed fields keep their current value."""
+    cur = get_tuning(op)
+    for f in fields:
+        if f not in _TUNE_FIELDS:
+            raise ValueError(f"unknown tuning field {f}")
+    cur.update(fields)
+    t = _Tuning(*(int(cur[f]) for f in _TUNE_FIELDS))
+    _check(_set_tuning(op.handle, ctypes.byref(t)))
+
+
+def _trials(arr, n):
+    return [({f: int(getattr(arr[i].t, f)) for f in _TUNE_FIELDS}, float(arr[i].ms)) for i in range(n)]
+
+
+def autotune_solve(op: Operator, rhs_voxels, opts: SolveOptions | None = None, out_dtype=torch.complex64,
+                   device="cuda", out: torch.Tensor | None = None) -> list:
+    """Time every Arnoldi step-kernel candidate on this problem (hydot_autotune_solve) and keep the
+    fastest in the operator.  Returns [(tuning dict, step-kernel ms), ...]."""
+    opts = opts or SolveOptions()
+    vox = np.ascontiguousarray(rhs_voxels, dtype=np.int64)
+    R = int(vox.shape[0])
+    if out is None:
+        out = torch.empty((op.L, R, op.N), dtype=out_dtype, device=device)
+    _need_cuda(out, "out")
+    if not out.is_contiguous() or tuple(out.shape) != (op.L, R, op.N):
+        raise ValueError("out must be a contiguous [L, n_rhs, N] tensor")
+    o = opts._c()
+    nbytes = solve_workspace_bytes(op, R, opts)
+    buf, wptr = _ws(nbytes, out.device)
+    arr = (_Trial * 64)()
+    n = c_int32(0)
+    _check(_tune_solve(op.handle, R, vox.ctypes.data_as(POINTER(c_int64)), ctypes.byref(o), c_void_p(out.data_ptr()),
+                       _cdtype(out), c_void_p(wptr), c_size_t(nbytes), arr, 64, ctypes.byref(n),
+                       _stream(out.device)))
+    del buf
+    return _trials(arr, n.value)
+
+
+def autotune_born(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, v: torch.Tensor) -> list:
+    """Time every J v candidate on these fields (hydot_autotune_born) and keep the fastest in the
+    operator.  Returns [(tuning dict, median ms), ...]."""
+    ps, S, ls = _field_view(op, phi_src, "phi_src")
+    pd, D, ld = _field_view(op, phi_det, "phi_det")
+    if ls != ld or phi_src.dtype != phi_det.dtype:
+        raise ValueError("phi_src and phi_det must share the wavelength stride and dtype")
+    dt = _cdtype(phi_src)
+    rdt = torch.float64 if dt == C128 else torch.float32
+    _need_cuda(v, "v")
+    v = v.reshape(-1, op.N).to(rdt).contiguous()
+    y = torch.empty((v.shape[0], op.L, S, D), dtype=phi_src.dtype, device=phi_src.device)
+    arr = (_Trial * 64)()
+    n = c_int32(0)
+    _check(_tune_born(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt, c_void_p(v.data_ptr()), int(v.shape[0]),
+                      c_void_p(y.data_ptr()), arr, 64, ctypes.byref(n), _stream(phi_src.device)))
+    return _trials(arr, n.value)
 
 
 def _field_view(op: Operator, t: torch.Tensor, name: str):

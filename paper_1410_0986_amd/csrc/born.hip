@@ -258,12 +258,14 @@ hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, c
   const int Sp = pad8(S), Dp = pad8(D);
   const int T_all = (2 * Sp / 16) * (2 * Dp / 16);
   const int tpw = (T_all + 3) / 4;
-  // voxels per LDS stage: 32 when the staged rows fit the LDS budget, else 16 (larger
-  // stages lower the number of resident blocks per CU and measure slower)
-  const int kt = (size_t)(2 * Sp + 2 * Dp) * 36 * sizeof(T) + 32 * sizeof(T) <= kLdsCap ? 32 : 16;
-  // split-K so the grid has a few thousand blocks
+  // voxels per LDS stage: 32 when the staged rows fit the LDS budget (unless the tuning
+  // asks for 16), else 16; larger stages lower the resident blocks per CU and measure slower
+  const hydot_tuning tu = resolved_tuning(op->tune);
+  const bool fits32 = (size_t)(2 * Sp + 2 * Dp) * 36 * sizeof(T) + 32 * sizeof(T) <= kLdsCap;
+  const int kt = fits32 && tu.born_stage != 16 ? 32 : 16;
+  // split-K over voxels so the grid has about born_blocks blocks
   const int max_split = (N + kt - 1) / kt;
-  int nsplit = std::max(1, std::min(max_split, (4096 + L * n_v - 1) / (L * n_v)));
+  int nsplit = std::max(1, std::min(max_split, (tu.born_blocks + L * n_v - 1) / (L * n_v)));
   int kb = (N + nsplit - 1) / nsplit;
   kb = (kb + kt - 1) / kt * kt;
   nsplit = (N + kb - 1) / kb;
@@ -353,6 +355,60 @@ hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_
   if (!w || !g) return fail(HYDOT_EINVAL, "born_apply_adjoint: null w or g");
   if (field_dtype == HYDOT_C128) return born_adjoint_impl<double>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
   return born_adjoint_impl<float>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
+}
+
+hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det, int32_t D,
+                                 int64_t lam_stride, hydot_dtype field_dtype, const void* v, int32_t n_v, void* y,
+                                 hydot_tune_trial* trials, int32_t max_trials, int32_t* n_trials, hipStream_t stream) {
+  if (!op) return fail(HYDOT_EINVAL, "autotune_born: null operator");
+  if (max_trials < 0 || (max_trials > 0 && !trials)) return fail(HYDOT_EINVAL, "autotune_born: bad trials buffer");
+  const hydot_tuning keep = op->tune;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HYDOT_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(HYDOT_EDEVICE, "autotune_born: event create");
+  }
+  const int stages[2] = {16, 32};
+  const int blocks[5] = {1024, 2048, 4096, 8192, 16384};
+  int count = 0;
+  double best = 1e300;
+  hydot_tuning best_t = resolved_tuning(keep);
+  hydot_status err = HYDOT_OK;
+  for (int is = 0; is < 2 && err == HYDOT_OK; ++is)
+    for (int ib = 0; ib < 5 && err == HYDOT_OK; ++ib) {
+      hydot_tuning t = resolved_tuning(keep);
+      t.born_stage = stages[is];
+      t.born_blocks = blocks[ib];
+      op->tune = t;
+      float ms[5];
+      for (int rep = 0; rep < 6 && err == HYDOT_OK; ++rep) {   // first call warms up
+        if (hipEventRecord(e0, stream) != hipSuccess) err = fail(HYDOT_EDEVICE, "autotune_born: event record");
+        if (err == HYDOT_OK)
+          err = hydot_born_apply(op, phi_src, S, phi_det, D, lam_stride, field_dtype, v, n_v, y, stream);
+        if (err == HYDOT_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+          err = fail(HYDOT_EDEVICE, "autotune_born: event wait");
+        if (err == HYDOT_OK && rep > 0 && hipEventElapsedTime(&ms[rep - 1], e0, e1) != hipSuccess)
+          err = fail(HYDOT_EDEVICE, "autotune_born: elapsed time");
+      }
+      if (err != HYDOT_OK) break;
+      std::sort(ms, ms + 5);
+      if (count < max_trials) trials[count] = hydot_tune_trial{t, (double)ms[2]};
+      ++count;
+      if (ms[2] < best) {
+        best = ms[2];
+        best_t = t;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != HYDOT_OK) {
+    op->tune = keep;
+    return err;
+  }
+  op->tune = best_t;
+  if (n_trials) *n_trials = count;
+  return HYDOT_OK;
 }
 
 }  // extern "C"

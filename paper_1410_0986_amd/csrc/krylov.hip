@@ -444,17 +444,24 @@ struct Solver {
         used_tiled = true;
         const dim3 gt((unsigned)(nb * p.nchunks));
         const int grp = tile_grp;
+        const hydot_tuning tu = resolved_tuning(op->tune);
+        const int fl = tu.step_order == 1 ? 1 : 0;
         const bool small = j + 1 <= 16;
+#define HYDOT_STEP_T(KER, NV, P) hipLaunchKernelGGL((KER<NV, P>), gt, dim3(kTSub), 0, stream, c, j, grp, fl)
+#define HYDOT_STEP_P(KER, NV)                                   \
+  if (tu.step_presum == 4) HYDOT_STEP_T(KER, NV, 4);            \
+  else if (tu.step_presum == 2) HYDOT_STEP_T(KER, NV, 2);       \
+  else HYDOT_STEP_T(KER, NV, 1);
         if (kind == 0) {
-          if (small) hipLaunchKernelGGL(k_step_dots_t<16>, gt, dim3(kTSub), 0, stream, c, j, grp);
-          else hipLaunchKernelGGL(k_step_dots_t<32>, gt, dim3(kTSub), 0, stream, c, j, grp);
+          if (small) { HYDOT_STEP_P(k_step_dots_t, 16) } else { HYDOT_STEP_P(k_step_dots_t, 32) }
         } else if (kind == 1) {
-          if (small) hipLaunchKernelGGL(k_step_update_t<16>, gt, dim3(kTSub), 0, stream, c, j, grp);
-          else hipLaunchKernelGGL(k_step_update_t<32>, gt, dim3(kTSub), 0, stream, c, j, grp);
+          if (small) { HYDOT_STEP_P(k_step_update_t, 16) } else { HYDOT_STEP_P(k_step_update_t, 32) }
         } else {
-          if (small) hipLaunchKernelGGL(k_step_finish_t<16>, gt, dim3(kTSub), 0, stream, c, j, grp);
-          else hipLaunchKernelGGL(k_step_finish_t<32>, gt, dim3(kTSub), 0, stream, c, j, grp);
+          if (small) hipLaunchKernelGGL(k_step_finish_t<16>, gt, dim3(kTSub), 0, stream, c, j, grp, fl);
+          else hipLaunchKernelGGL(k_step_finish_t<32>, gt, dim3(kTSub), 0, stream, c, j, grp, fl);
         }
+#undef HYDOT_STEP_P
+#undef HYDOT_STEP_T
         return;
       }
     }
@@ -542,7 +549,7 @@ struct Solver {
     Ctx<cd> c64 = ctx<cd>(p.k, false);   // FP64 views for residual and output kernels
     // group the wavelengths of one right-hand side when the batch holds whole ones
     tile_grp = 1;
-    if (nb % p.L == 0) {
+    if (nb % p.L == 0 && resolved_tuning(op->tune).step_group == 1) {
       bool aligned = true;
       for (int i = 0; i < nb && aligned; ++i) aligned = sys_l[i] == i % p.L && sys_r[i] == sys_r[i - i % p.L];
       if (aligned) tile_grp = p.L;
@@ -745,6 +752,57 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
   if (iters) std::memcpy(iters, it.data(), it.size() * sizeof(int32_t));
   if (rel_res) std::memcpy(rel_res, rr.data(), rr.size() * sizeof(double));
   if (!all) return fail(HYDOT_ENOCONV, "solve: some systems did not reach rel_tol (see rel_res)");
+  return HYDOT_OK;
+}
+
+hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
+                                  const hydot_solve_opts* opts, void* phi, hydot_dtype phi_dtype, void* workspace,
+                                  size_t ws_bytes, hydot_tune_trial* trials, int32_t max_trials, int32_t* n_trials,
+                                  hipStream_t stream) {
+  if (!op || !opts) return fail(HYDOT_EINVAL, "autotune_solve: null argument");
+  if (max_trials < 0 || (max_trials > 0 && !trials)) return fail(HYDOT_EINVAL, "autotune_solve: bad trials buffer");
+  hydot_solve_opts o = *opts;
+  o.max_iter = 2 * std::max(o.restart_m - (o.flags & HYDOT_FLAG_NO_RECYCLE ? 0 : o.recycle_k), 1);
+  const hydot_tuning keep = op->tune;
+  const bool prof_keep = g_prof;
+  const ProfRec rec_keep[3] = {g_rec[0], g_rec[1], g_rec[2]};
+  const int presums[3] = {1, 2, 4};
+  int count = 0;
+  double best = 1e300;
+  hydot_tuning best_t = resolved_tuning(keep);
+  hydot_status err = HYDOT_OK;
+  for (int ig = 1; ig <= 2 && err == HYDOT_OK; ++ig)
+    for (int io = 1; io <= 2 && err == HYDOT_OK; ++io)
+      for (int ip = 0; ip < 3 && err == HYDOT_OK; ++ip) {
+        hydot_tuning t = resolved_tuning(keep);
+        t.step_presum = presums[ip];
+        t.step_order = io;
+        t.step_group = ig;
+        op->tune = t;
+        (void)hydot_profile_enable(1);
+        hydot_status s = hydot_solve_fields(op, n_rhs, rhs_voxel, &o, phi, phi_dtype, workspace, ws_bytes, nullptr,
+                                            nullptr, stream);
+        if (s < 0) {
+          err = s;
+          break;
+        }
+        double ms = 0.0;
+        for (auto& r : g_rec) ms += r.ms;
+        if (count < max_trials) trials[count] = hydot_tune_trial{t, ms};
+        ++count;
+        if (ms < best) {
+          best = ms;
+          best_t = t;
+        }
+      }
+  g_prof = prof_keep;
+  for (int i = 0; i < 3; ++i) g_rec[i] = rec_keep[i];
+  if (err != HYDOT_OK) {
+    op->tune = keep;
+    return err;
+  }
+  op->tune = best_t;
+  if (n_trials) *n_trials = count;
   return HYDOT_OK;
 }
 

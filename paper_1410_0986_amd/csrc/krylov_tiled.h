@@ -24,26 +24,58 @@ constexpr int kTSub = 128;                  // voxels per sub-tile = threads per
 constexpr int kTK = 10;                     // largest deflation dimension handled here (3k+1 <= 32 rows)
 constexpr int kTNV = 32;                    // largest basis count handled here
 constexpr int kTRows = 32;                  // rows of the product tile
-constexpr int kTRP = kTSub + 4;             // padded product row
 static_assert(kChunk % kTSub == 0, "chunk must hold whole sub-tiles");
 static_assert(16 + kTK + 1 <= kTRows, "single-round tile must hold 16 basis rows, k deflation rows and the norm");
 static_assert(3 * kTK + 1 <= kTRows && kTNV <= kTRows, "product tile too small");
 
 // Products of one sub-tile, one row per inner product, then reduced row-wise:
-// thread t owns row t/4 and sums its columns t%4, t%4+4, ... (FP64), keeping a
-// running sum over the sub-tiles of the chunk.
+// thread t owns row t/TPR and sums its columns t%TPR, t%TPR+TPR, ... (FP64), keeping a
+// running sum over the sub-tiles of the chunk.  With P > 1 the products of P
+// neighbouring lanes are first summed across lanes (DPP, FP32) and one lane of
+// each group writes the sum, so the tile has kTSub/P columns: a smaller tile
+// lets more blocks share a CU's LDS.
+template <int P>
 struct ProdTile {
-  cf p[kTRows * kTRP];
+  static constexpr int cols = kTSub / P;
+  static constexpr int pitch = cols + 4;
+  cf p[kTRows * pitch];
 };
 
-template <int TPR>
-__device__ inline void row_reduce(const ProdTile& pt, int nrows, cd& acc) {
+// x + (x of lane t^1) and x + (x of lane t^2) within each quad of lanes
+__device__ inline float dpp_add_xor1(float x) {
+  return x + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+__device__ inline float dpp_add_xor2(float x) {
+  return x + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, false));
+}
+
+// product v of this lane for tile row `row`; every lane of the block must call this
+template <int P>
+__device__ inline void put_product(ProdTile<P>& pt, int row, cf v) {
+  const int t = threadIdx.x;
+  if constexpr (P >= 2) {
+    v.re = dpp_add_xor1(v.re);
+    v.im = dpp_add_xor1(v.im);
+  }
+  if constexpr (P >= 4) {
+    v.re = dpp_add_xor2(v.re);
+    v.im = dpp_add_xor2(v.im);
+  }
+  if constexpr (P == 1) {
+    pt.p[row * ProdTile<P>::pitch + t] = v;
+  } else {
+    if ((t & (P - 1)) == 0) pt.p[row * ProdTile<P>::pitch + t / P] = v;
+  }
+}
+
+template <int TPR, int P>
+__device__ inline void row_reduce(const ProdTile<P>& pt, int nrows, cd& acc) {
   const int t = threadIdx.x, row = t / TPR, seg = t % TPR;
   if (row >= nrows) return;
-  const cf* r = pt.p + row * kTRP;
+  const cf* r = pt.p + row * ProdTile<P>::pitch;
   double re = 0.0, im = 0.0;
 #pragma unroll 8
-  for (int i = 0; i < kTSub / TPR; ++i) {
+  for (int i = 0; i < ProdTile<P>::cols / TPR; ++i) {
     const cf x = r[seg + TPR * i];
     re += (double)x.re;
     im += (double)x.im;
@@ -55,14 +87,14 @@ __device__ inline void row_reduce(const ProdTile& pt, int nrows, cd& acc) {
 struct TileIdx {
   int sys, chunk;
 };
-__device__ inline TileIdx tile_idx(int nchunks, int grp) {
+__device__ inline TileIdx tile_idx(int nchunks, int grp, bool remap) {
   // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
   // Give each XCD a contiguous range of the logical order so that one XCD runs
   // all wavelengths of a (right-hand side, chunk) group and, soon after, the
   // neighbouring chunks whose planes form the stencil halo (its own L2).
   const int nblk = gridDim.x;
   int b = blockIdx.x;
-  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  if (remap && (nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
   const int per = grp * nchunks;
   const int g = b / per, rem = b - g * per;
   return TileIdx{g * grp + rem % grp, rem / grp};
@@ -203,16 +235,15 @@ __device__ inline cf stencil_apply(const GridP& g, const StencilRegs& sr, const 
 // conj(C'_i) w (row i) with C'_i = C_i + (sigma + sigma'_rel rho) U_i formed per
 // voxel, so f = C'^H w arrives directly (k rows instead of C^T w, U^T w,
 // (rho U)^T w), and |w|^2 (row k) if with_norm.
-template <int NV>
-__device__ inline void write_products(ProdTile& pt, int round, const cf* vr, const float* cr, const float* ur,
+template <int NV, int P>
+__device__ inline void write_products(ProdTile<P>& pt, int round, const cf* vr, const float* cr, const float* ur,
                                       cd shift, cf w, int k, int nv, bool with_norm, int row0 = 0) {
-  const int t = threadIdx.x;
   if (round == 0) {
 #pragma unroll
     for (int l = 0; l < NV; ++l)
       if (l < nv) {
         const cf v = vr[l];
-        pt.p[l * kTRP + t] = cf{v.re * w.re + v.im * w.im, v.re * w.im - v.im * w.re};
+        put_product<P>(pt, l, cf{v.re * w.re + v.im * w.im, v.re * w.im - v.im * w.re});
       }
   } else {
     const float sr = (float)shift.re, si = -(float)shift.im;   // conj(shift)
@@ -220,16 +251,16 @@ __device__ inline void write_products(ProdTile& pt, int round, const cf* vr, con
     for (int i = 0; i < kTK; ++i)
       if (i < k) {
         const float ar = cr[i] + sr * ur[i], ai = si * ur[i];
-        pt.p[(row0 + i) * kTRP + t] = cf{ar * w.re - ai * w.im, ar * w.im + ai * w.re};
+        put_product<P>(pt, row0 + i, cf{ar * w.re - ai * w.im, ar * w.im + ai * w.re});
       }
-    if (with_norm) pt.p[(row0 + k) * kTRP + t] = cf{w.re * w.re + w.im * w.im, 0.f};
+    if (with_norm) put_product<P>(pt, row0 + k, cf{w.re * w.re + w.im * w.im, 0.f});
   }
 }
 
 // Shared body of the dots (kind 0) and update (kind 1) kernels.
-template <int NV, int KIND>
+template <int NV, int KIND, int P>
 __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
-  __shared__ ProdTile pt;
+  __shared__ ProdTile<P> pt;
   const int sys = ti.sys;
   const size_t N = (size_t)c.g.N;
   const int k = c.k, nv = j + 1, t = threadIdx.x;
@@ -292,8 +323,8 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
     const cd shift{p.sig.re + p.sigp_rel * rho, p.sig.im};
     if constexpr (NV <= 16) {
       // one round: V rows, then the deflation rows and the norm row below them
-      write_products<NV>(pt, 0, vr, cr, ur, shift, w, k, nv, with_norm);
-      if (drows > 0) write_products<NV>(pt, 1, vr, cr, ur, shift, w, k, nv, with_norm, nv);
+      write_products<NV, P>(pt, 0, vr, cr, ur, shift, w, k, nv, with_norm);
+      if (drows > 0) write_products<NV, P>(pt, 1, vr, cr, ur, shift, w, k, nv, with_norm, nv);
       if (kPre && sub + 1 < nsub) {
         const uint32_t nn = n + kTSub;
         const bool okn = nn < (uint32_t)c.g.N;
@@ -304,17 +335,17 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
         if (KIND == 1 && okn) wpre = wv[nn];
       }
       __syncthreads();
-      row_reduce<4>(pt, nv + drows, accv);
+      row_reduce<4, P>(pt, nv + drows, accv);
       __syncthreads();
     } else {
-      write_products<NV>(pt, 0, vr, cr, ur, shift, w, k, nv, with_norm);
+      write_products<NV, P>(pt, 0, vr, cr, ur, shift, w, k, nv, with_norm);
       __syncthreads();
-      row_reduce<4>(pt, nv, accv);
+      row_reduce<4, P>(pt, nv, accv);
       __syncthreads();
       if (drows > 0) {
-        write_products<NV>(pt, 1, vr, cr, ur, shift, w, k, nv, with_norm);
+        write_products<NV, P>(pt, 1, vr, cr, ur, shift, w, k, nv, with_norm);
         __syncthreads();
-        row_reduce<8>(pt, drows, accd);
+        row_reduce<8, P>(pt, drows, accd);
         __syncthreads();
       }
     }
@@ -328,25 +359,26 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
 }
 
 // W = A_hat V_j and first-pass inner products (tiled form of k_step_dots).
-template <int NV>
-__global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp) {
-  const TileIdx ti = tile_idx(c.nchunks, grp);
+// flags bit 0: XCD-contiguous block order.
+template <int NV, int P>
+__global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp, int flags) {
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
   if (!c.st[ti.sys].in_cycle) return;
-  tiled_step<NV, 0>(c, j, ti);
+  tiled_step<NV, 0, P>(c, j, ti);
 }
 
 // CGS2 first projection + second-pass inner products (tiled form of k_step_update).
-template <int NV>
-__global__ __launch_bounds__(kTSub) void k_step_update_t(Ctx<cf> c, int j, int grp) {
-  const TileIdx ti = tile_idx(c.nchunks, grp);
+template <int NV, int P>
+__global__ __launch_bounds__(kTSub) void k_step_update_t(Ctx<cf> c, int j, int grp, int flags) {
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
   if (!c.st[ti.sys].in_cycle) return;
-  tiled_step<NV, 1>(c, j, ti);
+  tiled_step<NV, 1, P>(c, j, ti);
 }
 
 // Second projection and normalisation (k_step_finish with the system-fastest grid).
 template <int NV>
-__global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int grp) {
-  const TileIdx ti = tile_idx(c.nchunks, grp);
+__global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int grp, int flags) {
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
   const int sys = ti.sys;
   if (!c.st[sys].in_cycle) return;
   const size_t N = (size_t)c.g.N;

@@ -18,8 +18,11 @@ struct hydot_operator {
   std::vector<hydot::cd> sigma;   // [L] (mu_a + i omega/nu)/D
   std::vector<double> sigp;       // [L] 1/(2 A_R D)
   double sigp_mean = 0.0;         // mean of sigma' over wavelengths
+  hydot_tuning tune{0, 0, 0, 0, 0};  // launch shapes; 0 = library default
 };
 
 namespace hydot {
 GridP make_gridp(const hydot_grid& g);
+// launch shapes with defaults filled in
+hydot_tuning resolved_tuning(const hydot_tuning& t);
 }

@@ -61,6 +61,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_op(GridP g, const S* __restric
   y[(size_t)v * g.N + n] = scale(a, prm.scl[v]);
 }
 
+hydot_tuning resolved_tuning(const hydot_tuning& t) {
+  hydot_tuning r = t;
+  if (r.step_presum == 0) r.step_presum = 4;
+  if (r.step_order == 0) r.step_order = 1;
+  if (r.step_group == 0) r.step_group = 1;
+  if (r.born_blocks == 0) r.born_blocks = 4096;
+  return r;   // born_stage 0 stays: chosen per call from the LDS footprint
+}
+
 }  // namespace hydot
 
 using namespace hydot;
@@ -125,6 +134,23 @@ hydot_status hydot_assemble_operator(const hydot_grid* grid, const hydot_optics*
 }
 
 void hydot_free_operator(hydot_operator* op) { delete op; }
+
+hydot_status hydot_get_tuning(const hydot_operator* op, hydot_tuning* out) {
+  if (!op || !out) return hydot::fail(HYDOT_EINVAL, "get_tuning: null argument");
+  *out = hydot::resolved_tuning(op->tune);
+  return HYDOT_OK;
+}
+
+hydot_status hydot_set_tuning(hydot_operator* op, const hydot_tuning* t) {
+  if (!op || !t) return hydot::fail(HYDOT_EINVAL, "set_tuning: null argument");
+  const bool ok = (t->step_presum == 0 || t->step_presum == 1 || t->step_presum == 2 || t->step_presum == 4) &&
+                  (t->step_order >= 0 && t->step_order <= 2) && (t->step_group >= 0 && t->step_group <= 2) &&
+                  (t->born_stage == 0 || t->born_stage == 16 || t->born_stage == 32) &&
+                  (t->born_blocks == 0 || (t->born_blocks >= 256 && t->born_blocks <= 65536));
+  if (!ok) return hydot::fail(HYDOT_EINVAL, "set_tuning: field out of range");
+  op->tune = *t;
+  return HYDOT_OK;
+}
 
 hydot_status hydot_operator_optics(const hydot_operator* op, double* D_out, double* mua_out) {
   if (!op) return fail(HYDOT_EINVAL, "operator_optics: null operator");

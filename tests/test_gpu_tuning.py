@@ -1,0 +1,99 @@
+"""Launch-shape variants and the autotuner: every variant of the Arnoldi step kernels and
+of J v gives oracle-parity results, and the autotuner keeps the fastest candidate."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import born as oborn
+from oracle import fields as ofields
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import paper_1410_0986_amd as hd
+    return hd
+
+
+def normwise(a, b, axis=-1):
+    return np.linalg.norm(a - b, axis=axis) / np.linalg.norm(b, axis=axis)
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # ragged grid (N = 1820: a partial chunk and a partial sub-tile), 4 wavelengths
+    w = workloads.config("tiny", nx=20, ny=13, nz=7, n_lambda=4)
+    return w, ofields.solve_banded(w)
+
+
+def mixed_opts(hd):
+    return hd.SolveOptions(rel_tol=1e-8, restart_m=20, recycle_k=5, lanczos_n=24, precision=hd.PREC_MIXED,
+                           inner_tol=1e-5, flags=hd.FLAG_MEAN_SHIFT | hd.FLAG_GRAPH)
+
+
+@pytest.mark.parametrize("presum,order,group", list(itertools.product((1, 2, 4), (1, 2), (1, 2))))
+def test_every_step_variant_meets_tolerance(hd, ragged, presum, order, group):
+    w, ref = ragged
+    op = hd.Operator.from_workload(w)
+    hd.set_tuning(op, step_presum=presum, step_order=order, step_group=group)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, mixed_opts(hd), out_dtype=torch.complex64, device=DEV)
+    s.synchronize()
+    assert st == hd.OK and rel.max() <= 1e-8
+    err = normwise(phi.cpu().numpy().astype(np.complex128), ref)
+    assert err.max() < 1e-4
+
+
+def test_variant_with_basis_beyond_16_vectors(hd, ragged):
+    # restart length 30 without recycling: steps j >= 16 run the 32-vector instances
+    w, ref = ragged
+    op = hd.Operator.from_workload(w)
+    o = hd.SolveOptions(rel_tol=1e-8, restart_m=30, recycle_k=0, lanczos_n=0, precision=hd.PREC_MIXED,
+                        inner_tol=1e-5, flags=hd.FLAG_NO_RECYCLE)
+    for presum in (1, 2, 4):
+        hd.set_tuning(op, step_presum=presum)
+        phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, out_dtype=torch.complex64, device=DEV)
+        assert st == hd.OK and rel.max() <= 1e-8 and it.max() > 16
+        assert normwise(phi.cpu().numpy().astype(np.complex128), ref).max() < 1e-4
+
+
+def test_autotune_solve_keeps_the_fastest(hd, ragged):
+    w, ref = ragged
+    op = hd.Operator.from_workload(w)
+    trials = hd.autotune_solve(op, w.rhs_voxels, mixed_opts(hd))
+    assert len(trials) == 12
+    assert len({tuple(sorted(t.items())) for t, _ in trials}) == 12
+    assert all(ms > 0 for _, ms in trials)
+    best = min(trials, key=lambda tm: tm[1])[0]
+    assert hd.get_tuning(op) == best
+    phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, mixed_opts(hd), out_dtype=torch.complex64, device=DEV)
+    assert st == hd.OK and rel.max() <= 1e-8
+    assert normwise(phi.cpu().numpy().astype(np.complex128), ref).max() < 1e-4
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
+def test_autotune_born_keeps_the_fastest(hd, dtype, tol):
+    w = workloads.config("tiny")
+    op = hd.Operator.from_workload(w)
+    P = ofields.solve_banded(w)
+    t = torch.from_numpy(P).to(dtype).to(DEV)
+    rdt = torch.float64 if dtype == torch.complex128 else torch.float32
+    v = torch.from_numpy(workloads.born_v(w, n_v=2)).to(rdt)
+    trials = hd.autotune_born(op, t[:, :w.S], t[:, w.S:], v.to(DEV))
+    assert len(trials) == 10
+    best = min(trials, key=lambda tm: tm[1])[0]
+    assert hd.get_tuning(op) == best
+    Pr = t.cpu().numpy().astype(np.complex128)
+    ref = oborn.born_apply(Pr[:, :w.S], Pr[:, w.S:], v.double().numpy(), w.h)
+    for stage, blocks in ((16, 256), (32, 65536), (0, 0)):
+        hd.set_tuning(op, born_stage=stage, born_blocks=blocks)
+        y = hd.born_apply(op, t[:, :w.S], t[:, w.S:], v.to(DEV)).cpu().numpy()
+        assert normwise(y.reshape(2, -1), ref.reshape(2, -1)).max() < tol
