@@ -88,6 +88,10 @@ typedef struct {
 #define HYDOT_FLAG_MEAN_SHIFT  0x2u  /* K <- K + mean(sigma') R, sigma'_j <- sigma'_j - mean (Sec. 6.1) */
 #define HYDOT_FLAG_GRAPH       0x4u  /* capture each restart cycle in a hipGraph and replay it */
 #define HYDOT_FLAG_PER_SYSTEM  0x8u  /* plain mode: one (rhs, lambda) system at a time, per-call launches */
+#define HYDOT_FLAG_FULL_REORTH 0x10u /* mixed only: apply the second Gram-Schmidt pass at every step.
+                                        Default: the FP32 inner Arnoldi skips it for a system whose
+                                        second-pass projection is below 1e-4 ||w'|| (orthogonal to
+                                        working precision); the FP64 path always applies it. */
 
 #define HYDOT_PREC_FP64  0           /* Krylov basis and operator in complex FP64 */
 #define HYDOT_PREC_MIXED 1           /* complex FP32 Krylov inner solves, FP64 residual refinement */
@@ -247,8 +251,9 @@ hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_
  * (first-pass dots with the operator, CGS2 update, normalisation) and accumulates, per
  * kernel, launches, elapsed milliseconds and algorithmic HBM bytes: for step j with
  * storage b bytes per complex, k deflation vectors and A systems stepping,
- *   dots A*N*b*(j+2+k), update A*N*b*(j+3+k), finish A*N*b*(j+3+k)
- * (each unique vector read once, plus the written vector; C and U are real, b/2 each).
+ *   dots A*N*b*(j+2+k), update A*N*b*(j+3+k), finish A'*N*b*(j+3+k)
+ * with A' the systems whose second Gram-Schmidt pass is applied at step j (each unique
+ * vector read once, plus the written vector; C and U are real, b/2 each).
  * Enabling resets the counters; the graph flag is ignored while enabled (launches are
  * timed one by one).  Process-wide; not thread-safe. */
 typedef struct {

@@ -31,6 +31,6 @@ from ._binding import (  # noqa: F401
     autotune_born,
     C128, C64, F64, F32,
     PREC_FP64, PREC_MIXED,
-    FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM,
+    FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH,
     OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED,
 )

@@ -20,7 +20,7 @@ _lib = ctypes.CDLL(_LIBPATH)
 OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4
 C128, C64, F64, F32 = 0, 1, 3, 4
 PREC_FP64, PREC_MIXED = 0, 1
-FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM = 0x1, 0x2, 0x4, 0x8
+FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH = 0x1, 0x2, 0x4, 0x8, 0x10
 
 
 class HydotError(RuntimeError):

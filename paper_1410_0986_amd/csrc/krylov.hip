@@ -142,7 +142,7 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   if (o->max_iter < 1) return fail(HYDOT_EINVAL, "solve: max_iter must be >= 1");
   if (o->precision != HYDOT_PREC_FP64 && o->precision != HYDOT_PREC_MIXED)
     return fail(HYDOT_EINVAL, "solve: precision must be HYDOT_PREC_FP64 or HYDOT_PREC_MIXED");
-  if (o->flags & ~0xFu) return fail(HYDOT_EINVAL, "solve: unknown flag bits");
+  if (o->flags & ~0x1Fu) return fail(HYDOT_EINVAL, "solve: unknown flag bits");
   p.recycle = !(o->flags & HYDOT_FLAG_NO_RECYCLE);
   p.k = p.recycle ? o->recycle_k : 0;
   if (p.k < 0 || p.k > kMaxK) return fail(HYDOT_EINVAL, "solve: recycle_k must be in [0, 32]");
@@ -284,7 +284,7 @@ struct Solver {
   hydot_status prof_collect(const int* cnt, int k) {
     const double N = (double)p.N, b = (double)p.esz;
     for (int j = 0; j < p.mk; ++j) {
-      const double act = (double)cnt[2 + j];
+      const double act_k[3] = {(double)cnt[2 + j], (double)cnt[2 + j], (double)cnt[2 + kMaxMK + j]};
       const double extra[3] = {(double)(j + 2 + k), (double)(j + 3 + k), (double)(j + 3 + k)};
       for (int kind = 0; kind < 3; ++kind) {
         if (kind == 2 && j + 1 >= p.mk) continue;   // no finish after the last step
@@ -293,7 +293,7 @@ struct Solver {
         g_rec[kind].name = used_tiled ? kTiledNames[kind] : kGenericNames[kind];
         g_rec[kind].launches += 1;
         g_rec[kind].ms += ms;
-        g_rec[kind].bytes += act * N * b * extra[kind];
+        g_rec[kind].bytes += act_k[kind] * N * b * extra[kind];
       }
     }
     return HYDOT_OK;
@@ -561,6 +561,7 @@ struct Solver {
     ra.max_sweeps = p.prec == HYDOT_PREC_MIXED ? 40 : 20;
     ra.mk = p.mk;
     ra.lanczos = 0;
+    ra.cgs_tau = p.prec == HYDOT_PREC_MIXED && !(o->flags & HYDOT_FLAG_FULL_REORTH) ? 1e-4 : 0.0;
     ra.final_res = at<double>(p.o_final);
     dim3 gv(p.nchunks, nb), gr(nb);
     if (p.nl > 0)

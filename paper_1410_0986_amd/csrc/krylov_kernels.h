@@ -41,7 +41,7 @@ struct SysState {
   int32_t converged;    // FP64 residual met the tolerance
   int32_t sweeps;       // outer sweeps started
   int32_t stalls;       // sweeps that failed to reduce the outer residual
-  int32_t pad0;
+  int32_t reorth;       // the second Gram-Schmidt pass of the current step is applied
   double rnorm_outer;   // ||b - A x|| (FP64) at the start of the sweep
   double target_in;     // absolute target of the inner residual (inner rhs has norm 1)
   double beta;          // ||deflated residual|| at cycle start
@@ -52,7 +52,7 @@ struct SysState {
 
 // Offsets (in cd units) inside one system's small block.
 struct Small {
-  int coefA, coefB, H, cs, sn, gam, Fp, Lc, y0, total;
+  int coefA, coefB, H, cs, sn, gam, Fp, vs, Lc, y0, total;
 };
 
 inline Small make_small(int k, int mkmax, int nl) {
@@ -65,6 +65,7 @@ inline Small make_small(int k, int mkmax, int nl) {
   s.sn = o; o += mkmax;
   s.gam = o; o += mkmax + 1;
   s.Fp = o; o += k * mkmax;
+  s.vs = o; o += mkmax + 2;      // basis scales: v_l = vs[l] * (stored V_l)
   s.Lc = o; o += k * k;          // y0 follows Lc directly (one host copy fills both)
   s.y0 = o; o += (nl > 0 ? nl : 1);
   s.total = (o + 15) & ~15;
@@ -93,7 +94,8 @@ struct Ctx {
   int ndots;
   cd* small;        // [nb][sl.total]
   Small sl;
-  int* counter;     // [2 + kMaxMK]: in_sweep count, in_inner count, systems stepping at step j
+  int* counter;     // [2 + 2 kMaxMK]: in_sweep count, in_inner count, systems stepping at step j,
+                    // systems re-orthogonalising at step j
 };
 
 // slots of the partial sums
@@ -241,7 +243,7 @@ __device__ inline void load_rho(const GridP& g, const Chunk<S>& ch, double* rho)
 
 // ------------------------------------------------------------------ kernels
 
-// V_0 = e_voxel for the Lanczos (shift-invariant Krylov) runs.
+// V_0 = e_voxel (unit scale) for the Lanczos (shift-invariant Krylov) runs.
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_unit_v0(Ctx<S> c) {
   const int sys = blockIdx.y;
@@ -255,6 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_unit_v0(Ctx<S> c) {
     if (ch.n[q] == vox) z.re = 1;
     v0[ch.n[q]] = z;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) c.small[(size_t)sys * c.sl.total + c.sl.vs] = cd{1.0, 0.0};
 }
 
 // X = 0 (no initial guess)
@@ -438,6 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dots(Ctx<S> c, int j) {
   const S* Vsys = c.V + (size_t)sys * c.vdim * N;
   const S* vj = Vsys + (size_t)j * N;
   S* wv = c.W + (size_t)sys * N;
+  const double sj = c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re;   // v_j = sj * stored V_j
   S w[kVPT];
   double rho[kVPT];
 #pragma unroll
@@ -447,13 +451,13 @@ __global__ __launch_bounds__(kBlock) void k_step_dots(Ctx<S> c, int j) {
     if (!ch.ok[q]) continue;
     const VoxelInfo vi = voxel_info(c.g, ch.n[q]);
     rho[q] = (double)vi.nrobin * c.g.inv_h;
-    w[q] = apply_op<S>(c.g, vj, ch.n[q], vi, p.sig, p.sigp_abs);
+    w[q] = scale(apply_op<S>(c.g, vj, ch.n[q], vi, p.sig, p.sigp_abs), sj);
     wv[ch.n[q]] = w[q];
   }
   chunk_dots<S>(c, sys, ch, w, rho, Vsys, j + 1, false, lds);
 }
 
-// Arnoldi step j, first projection and second-pass dots (CGS2).
+// Arnoldi step j, first projection and second-pass dots (CGS2); w' is stored as V_{j+1}.
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_step_update(Ctx<S> c, int j) {
   __shared__ cd lds[kWaves * kMaxDots];
@@ -462,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_step_update(Ctx<S> c, int j) {
   const Chunk<S> ch(c.g);
   const size_t N = (size_t)c.g.N;
   const S* Vsys = c.V + (size_t)sys * c.vdim * N;
-  S* wv = c.W + (size_t)sys * N;
+  const S* wv = c.W + (size_t)sys * N;
   const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefA;
   S w[kVPT];
   double rho[kVPT];
@@ -470,30 +474,31 @@ __global__ __launch_bounds__(kBlock) void k_step_update(Ctx<S> c, int j) {
 #pragma unroll
   for (int q = 0; q < kVPT; ++q) w[q] = ch.ok[q] ? wv[ch.n[q]] : Store<S>::zero();
   chunk_project<S>(c, sys, ch, w, rho, Vsys, j + 1, coef, nullptr);
+  S* vn = c.V + ((size_t)sys * c.vdim + j + 1) * N;   // w' becomes V_{j+1} (scaled or re-orthogonalised later)
 #pragma unroll
   for (int q = 0; q < kVPT; ++q)
-    if (ch.ok[q]) wv[ch.n[q]] = w[q];
+    if (ch.ok[q]) vn[ch.n[q]] = w[q];
   chunk_dots<S>(c, sys, ch, w, rho, Vsys, j + 1, true, lds);
 }
 
-// Arnoldi step j, second projection and normalisation: V_{j+1} = (W - C'g2 - V h2)/eta.
+// Arnoldi step j, second projection and normalisation, for the systems whose
+// second Gram-Schmidt pass is applied: V_{j+1} = (w' - C'g2 - V h2)/eta in place.
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_step_finish(Ctx<S> c, int j) {
   const int sys = blockIdx.y;
-  if (!c.st[sys].in_cycle) return;
+  if (!c.st[sys].in_cycle || !c.st[sys].reorth) return;
   const Chunk<S> ch(c.g);
   const size_t N = (size_t)c.g.N;
   S* Vsys = c.V + (size_t)sys * c.vdim * N;
-  const S* wv = c.W + (size_t)sys * N;
+  S* vn = Vsys + (size_t)(j + 1) * N;
   const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefB;
   const double inv_eta = coef[c.k + c.mkmax + 1].re;
   S w[kVPT];
   double rho[kVPT];
   load_rho<S>(c.g, ch, rho);
 #pragma unroll
-  for (int q = 0; q < kVPT; ++q) w[q] = ch.ok[q] ? wv[ch.n[q]] : Store<S>::zero();
+  for (int q = 0; q < kVPT; ++q) w[q] = ch.ok[q] ? vn[ch.n[q]] : Store<S>::zero();
   chunk_project<S>(c, sys, ch, w, rho, Vsys, j + 1, coef, nullptr);
-  S* vn = Vsys + (size_t)(j + 1) * N;
 #pragma unroll
   for (int q = 0; q < kVPT; ++q)
     if (ch.ok[q]) vn[ch.n[q]] = scale(w[q], inv_eta);
@@ -576,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_output(Ctx<S> c, O* phi) {
     if (ch.ok[q]) out[ch.n[q]] = Store<O>::from(p.out_scale * x[ch.n[q]]);
 }
 
-constexpr int kCounters = 2 + kMaxMK;
+constexpr int kCounters = 2 + 2 * kMaxMK;
 
 __global__ void k_zero_counters(int* counter) {
   for (int i = threadIdx.x; i < kCounters; i += blockDim.x) counter[i] = 0;
@@ -600,6 +605,8 @@ struct ReduceArgs {
   int max_sweeps;
   int mk;              // Arnoldi steps per cycle
   int lanczos;         // 1: plain Arnoldi/Lanczos recording, no Givens, no stopping test
+  double cgs_tau;      // > 0: skip the second Gram-Schmidt pass when its projection is below
+                       // cgs_tau * ||w'|| (the basis is then orthogonal to working precision)
   double* final_res;   // PH_FINAL: per-system residual norms (device)
 };
 
@@ -737,6 +744,7 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
       cd* gam = sm + c.sl.gam;
       for (int i = 0; i <= ra.mk; ++i) gam[i] = cd{0.0, 0.0};
       gam[0] = cd{beta, 0.0};
+      sm[c.sl.vs] = cd{1.0, 0.0};   // V_0 is normalised in place
       if (beta > 0.0 && beta > 1e-300) {
         st->in_cycle = 1;
         st->resid_est = beta;
@@ -759,9 +767,11 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
         gsolve(k, Lc, f, g);
         for (int i = 0; i < k; ++i) coef[i] = g[i];
       }
+      const cd* vs = sm + c.sl.vs;
       for (int l = 0; l <= j; ++l) {
-        const cd h = sum[slot_v(k, l)];
-        coef[k + l] = h;
+        const double sl = vs[l].re;
+        const cd h = sl * sum[slot_v(k, l)];   // v_l^H w from the stored V_l
+        coef[k + l] = sl * h;                  // multiplier of the stored V_l
         H[l + ldh * j] = h;
       }
       break;
@@ -770,25 +780,44 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
       cd* H = sm + c.sl.H;
       const int ldh = c.mkmax + 1;
       cd* coef = sm + c.sl.coefB;
+      cd* vs = sm + c.sl.vs;
+      // second-pass coefficients (f2 -> g2, h2) and the norm of their projection
       double proj = 0.0;
       if (k > 0) {
         make_f();
-        cd* Fp = sm + c.sl.Fp;
-        for (int i = 0; i < k; ++i) Fp[i + k * j] = Fp[i + k * j] + f[i];
         gsolve(k, Lc, f, g);
-        for (int i = 0; i < k; ++i) {
-          coef[i] = g[i];
-          proj += (conj(f[i]) * g[i]).re;
-        }
+        for (int i = 0; i < k; ++i) proj += (conj(f[i]) * g[i]).re;
       }
+      cd* h2 = tmp + 2 * kMaxK;
       for (int l = 0; l <= j; ++l) {
-        const cd h = sum[slot_v(k, l)];
-        coef[k + l] = h;
-        H[l + ldh * j] = H[l + ldh * j] + h;
-        proj += norm2(h);
+        h2[l] = vs[l].re * sum[slot_v(k, l)];
+        proj += norm2(h2[l]);
       }
-      const double e2 = sum[sn].re - proj;
-      const double eta = e2 > 0.0 ? sqrt(e2) : 0.0;
+      const double w2 = sum[sn].re;   // ||w'||^2 after the first pass
+      double eta;
+      if (ra.cgs_tau > 0.0 && proj <= ra.cgs_tau * ra.cgs_tau * w2) {
+        // w' is orthogonal to working precision: keep it unnormalised as V_{j+1}
+        st->reorth = 0;
+        eta = w2 > 0.0 ? sqrt(w2) : 0.0;
+        vs[j + 1] = cd{eta > 1e-300 ? 1.0 / eta : 0.0, 0.0};
+      } else {
+        st->reorth = 1;
+        atomicAdd(&c.counter[2 + kMaxMK + j], 1);
+        if (k > 0) {
+          cd* Fp = sm + c.sl.Fp;
+          for (int i = 0; i < k; ++i) {
+            Fp[i + k * j] = Fp[i + k * j] + f[i];
+            coef[i] = g[i];
+          }
+        }
+        for (int l = 0; l <= j; ++l) {
+          coef[k + l] = vs[l].re * h2[l];
+          H[l + ldh * j] = H[l + ldh * j] + h2[l];
+        }
+        const double e2 = w2 - proj;
+        eta = e2 > 0.0 ? sqrt(e2) : 0.0;
+        vs[j + 1] = cd{1.0, 0.0};       // the second pass writes V_{j+1} normalised
+      }
       H[j + 1 + ldh * j] = cd{eta, 0.0};
       const bool breakdown = !(eta > 1e-300);
       coef[k + c.mkmax + 1] = cd{breakdown ? 0.0 : 1.0 / eta, 0.0};
@@ -862,7 +891,8 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
         gsolve(k, Lc, f, g);
         for (int i = 0; i < k; ++i) coef[i] = cd{-g[i].re, -g[i].im};
       }
-      for (int q = 0; q < ns; ++q) coef[k + q] = y[q];
+      const cd* vs = sm + c.sl.vs;
+      for (int q = 0; q < ns; ++q) coef[k + q] = vs[q].re * y[q];
       if (st->resid_est <= st->target_in || st->total_iters >= ra.max_iter || ns == 0) st->in_inner = 0;
       if (st->in_inner) atomicAdd(&c.counter[1], 1);
       break;

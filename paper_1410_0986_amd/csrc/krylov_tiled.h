@@ -287,6 +287,8 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
   float cr[kTK], ur[kTK];
   cf wpre{0.f, 0.f};
   const cf* vj = Vsys + (size_t)j * N;
+  cf* vnext = c.V + ((size_t)sys * c.vdim + j + 1) * N;   // the update stores w' as V_{j+1}
+  const float sj = KIND == 0 ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
   StencilRegs sreg;
   VoxelInfo vinf;
   {
@@ -315,10 +317,13 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
       rho = (double)vi.nrobin * c.g.inv_h;
       if (KIND == 0) {
         w = stencil_apply(c.g, sreg, vi, p.sig, p.sigp_abs);
+        w.re *= sj;   // v_j = sj * stored V_j
+        w.im *= sj;
       } else {
         w = project_voxel<NV>(wpre, vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
       }
-      wv[n] = w;
+      if (KIND == 0) wv[n] = w;
+      else vnext[n] = w;
     }
     const cd shift{p.sig.re + p.sigp_rel * rho, p.sig.im};
     if constexpr (NV <= 16) {
@@ -375,17 +380,18 @@ __global__ __launch_bounds__(kTSub) void k_step_update_t(Ctx<cf> c, int j, int g
   tiled_step<NV, 1, P>(c, j, ti);
 }
 
-// Second projection and normalisation (k_step_finish with the system-fastest grid).
+// Second projection and normalisation in place of V_{j+1}, for the systems whose
+// second Gram-Schmidt pass is applied (tiled form of k_step_finish).
 template <int NV>
 __global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int grp, int flags) {
   const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
   const int sys = ti.sys;
-  if (!c.st[sys].in_cycle) return;
+  if (!c.st[sys].in_cycle || !c.st[sys].reorth) return;
   const size_t N = (size_t)c.g.N;
   const int k = c.k, nv = j + 1, t = threadIdx.x;
   const SysParam p = c.prm[sys];
   cf* Vsys = c.V + (size_t)sys * c.vdim * N;
-  const cf* wv = c.W + (size_t)sys * N;
+  cf* vn = Vsys + (size_t)(j + 1) * N;
   const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefB;
   const float inv_eta = (float)coef[k + c.mkmax + 1].re;
   cf g[kTK], h[NV];
@@ -401,8 +407,8 @@ __global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int g
     load_basis<NV>(Vsys, N, n, true, nv, vr);
     load_cu(c, p.rhs, N, n, true, cr, ur);
     const double rho = (double)voxel_info(c.g, n).nrobin * c.g.inv_h;
-    cf w = project_voxel<NV>(wv[n], vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
-    Vsys[(size_t)(j + 1) * N + n] = cf{w.re * inv_eta, w.im * inv_eta};
+    cf w = project_voxel<NV>(vn[n], vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
+    vn[n] = cf{w.re * inv_eta, w.im * inv_eta};
   }
 }
 

@@ -97,3 +97,20 @@ def test_autotune_born_keeps_the_fastest(hd, dtype, tol):
         hd.set_tuning(op, born_stage=stage, born_blocks=blocks)
         y = hd.born_apply(op, t[:, :w.S], t[:, w.S:], v.to(DEV)).cpu().numpy()
         assert normwise(y.reshape(2, -1), ref.reshape(2, -1)).max() < tol
+
+
+def test_selective_second_pass_matches_full_cgs2(hd, ragged):
+    """The FP32 inner Arnoldi skips the second Gram-Schmidt pass where it is below working
+    precision; with FLAG_FULL_REORTH it always applies it.  Both reach the FP64 tolerance and the
+    oracle fields, with iteration counts within a few steps of each other."""
+    w, ref = ragged
+    op = hd.Operator.from_workload(w)
+    out = {}
+    for extra in (0, hd.FLAG_FULL_REORTH):
+        o = mixed_opts(hd)
+        o.flags |= extra
+        phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, out_dtype=torch.complex128, device=DEV)
+        assert st == hd.OK and rel.max() <= 1e-8
+        assert normwise(phi.cpu().numpy(), ref).max() < 1e-6
+        out[extra] = it
+    assert abs(out[0].mean() - out[hd.FLAG_FULL_REORTH].mean()) <= 0.1 * out[hd.FLAG_FULL_REORTH].mean() + 2
