@@ -12,6 +12,7 @@
 #include "common.h"
 #include "krylov_kernels.h"
 #include "krylov_tiled.h"
+#include "lanczos.h"
 #include "operator.h"
 #include "small_dense.h"
 
@@ -19,21 +20,21 @@ namespace hydot {
 
 // Shift-invariant basis -> U (from V_n) and C (from V_{n+1}) for each right-hand side:
 // U[r][i] = sum_l VL[r][l] cu[r][l][i], C[r][i] = sum_l VL[r][l] cu[r][l][k+i].
-template <int KM>
-__global__ __launch_bounds__(kBlock) void k_combine_uc(GridP g, const cd* VL, int vldim, int nl1,
+template <int KM, typename VT>
+__global__ __launch_bounds__(kBlock) void k_combine_uc(GridP g, const VT* VL, int vldim, int nl1,
                                                       const double* ucoef, int k, double* U64, double* C64,
                                                       float* U32, float* C32, int rhs_off) {
   const int r = blockIdx.y;
   const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= (uint32_t)g.N) return;
   const size_t N = (size_t)g.N;
-  const cd* Vb = VL + (size_t)r * vldim * N;
+  const VT* Vb = VL + (size_t)r * vldim * N;
   const double* cf = ucoef + (size_t)r * nl1 * 2 * k;
   double acc[2 * KM];
 #pragma unroll
   for (int i = 0; i < 2 * KM; ++i) acc[i] = 0.0;
   for (int l = 0; l < nl1; ++l) {
-    const double v = Vb[(size_t)l * N + n].re;
+    const double v = (double)Vb[(size_t)l * N + n];
 #pragma unroll
     for (int i = 0; i < 2 * KM; ++i)
       if (i < 2 * k) acc[i] += v * cf[l * 2 * k + i];
@@ -183,7 +184,8 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
   p.o_prm = take((size_t)ns * sizeof(SysParam));
   p.o_st = take((size_t)ns * sizeof(SysState));
-  p.o_VL = take(p.recycle ? (size_t)p.rl * (p.nl + 1) * N * sizeof(cd) : 0);
+  // real Lanczos basis: FP32 for the mixed path, FP64 for the FP64 path
+  p.o_VL = take(p.recycle ? (size_t)p.rl * (p.nl + 1) * N * (p.prec == HYDOT_PREC_MIXED ? sizeof(float) : sizeof(double)) : 0);
   const size_t ucount = (size_t)p.rl * p.k * N;
   p.o_U64 = take(ucount * sizeof(double));
   p.o_C64 = take(ucount * sizeof(double));
@@ -300,6 +302,34 @@ struct Solver {
   }
 
   // ---------------------------------------------------------------- Lanczos
+  // nl steps of the real Lanczos process for the nr right-hand sides of the buffer
+  template <typename T>
+  void lanczos_run(const Ctx<cd>& c, const ReduceArgs& ra, int nr) {
+    LzCtx<T> lc;
+    lc.g = op->gp;
+    lc.nchunks = p.nchunks;
+    lc.vdim = p.nl + 1;
+    lc.ndots = p.ndots;
+    lc.sigp = sigp_mean();
+    lc.prm = c.prm;
+    lc.st = c.st;
+    lc.V = at<T>(p.o_VL);
+    lc.W = at<T>(p.o_W);
+    lc.part = c.part;
+    lc.small = c.small;
+    lc.sl = c.sl;
+    lc.mkmax = p.mkmax;
+    const dim3 gv(p.nchunks, nr);
+    hipLaunchKernelGGL(k_lz_v0<T>, gv, dim3(kBlock), 0, stream, lc, c.small);
+    for (int j = 0; j < p.nl; ++j) {
+      hipLaunchKernelGGL(k_lz_dots<T>, gv, dim3(kBlock), 0, stream, lc, j);
+      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j, 0);
+      hipLaunchKernelGGL(k_lz_update<T>, gv, dim3(kBlock), 0, stream, lc, j);
+      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j, 0);
+      hipLaunchKernelGGL(k_lz_finish<T>, gv, dim3(kBlock), 0, stream, lc, j);
+    }
+  }
+
   // Shift-invariant Krylov basis of K_hat for right-hand sides [r0, r0+nr) (Alg. 1 step 1),
   // then U, C (steps 2-4) and the Gram blocks used by the per-wavelength update (Sec. 3.2).
   hydot_status setup_rhs(int r0, int nr, int buf_off) {
@@ -321,20 +351,13 @@ struct Solver {
     }
     HYDOT_HIP(hipMemcpyAsync(at<SysParam>(p.o_prm), prm.data(), nr * sizeof(SysParam), hipMemcpyHostToDevice, stream));
     HYDOT_HIP(hipMemcpyAsync(at<SysState>(p.o_st), st.data(), nr * sizeof(SysState), hipMemcpyHostToDevice, stream));
-    Ctx<cd> c = ctx<cd>(0, true);
+    Ctx<cd> c = ctx<cd>(0, true);   // partials, coefficients and state for k_reduce
     ReduceArgs ra{};
     ra.mk = nl;
     ra.lanczos = 1;
     ra.max_iter = 1 << 30;
-    dim3 gv(p.nchunks, nr);
-    hipLaunchKernelGGL(k_unit_v0<cd>, gv, dim3(kBlock), 0, stream, c);
-    for (int j = 0; j < nl; ++j) {
-      hipLaunchKernelGGL(k_step_dots<cd>, gv, dim3(kBlock), 0, stream, c, j);
-      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j, 0);
-      hipLaunchKernelGGL(k_step_update<cd>, gv, dim3(kBlock), 0, stream, c, j);
-      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j, 0);
-      hipLaunchKernelGGL(k_step_finish<cd>, gv, dim3(kBlock), 0, stream, c, j);
-    }
+    if (p.prec == HYDOT_PREC_MIXED) lanczos_run<float>(c, ra, nr);
+    else lanczos_run<double>(c, ra, nr);
     HYDOT_HIP(hipGetLastError());
     // Hessenberg matrices back to the host
     std::vector<cd> smalls((size_t)nr * p.sl.total);
@@ -386,13 +409,15 @@ struct Solver {
     const bool mixed = p.prec == HYDOT_PREC_MIXED;
     float* U32 = mixed ? at<float>(p.o_U32) : nullptr;
     float* C32 = mixed ? at<float>(p.o_C32) : nullptr;
-    const cd* VL = at<cd>(p.o_VL);
-#define HYDOT_UC(KM)                                                                                          \
-  hipLaunchKernelGGL(k_combine_uc<KM>, gu, dim3(kBlock), 0, stream, op->gp, VL, nl + 1, nl + 1,               \
+#define HYDOT_UC(KM, VT)                                                                                      \
+  hipLaunchKernelGGL((k_combine_uc<KM, VT>), gu, dim3(kBlock), 0, stream, op->gp, at<VT>(p.o_VL), nl + 1, nl + 1, \
                      at<double>(p.o_ucoef), k, at<double>(p.o_U64), at<double>(p.o_C64), U32, C32, buf_off)
-    if (k <= 8) HYDOT_UC(8);
-    else if (k <= 16) HYDOT_UC(16);
-    else HYDOT_UC(32);
+#define HYDOT_UC_T(VT)                 \
+  if (k <= 8) HYDOT_UC(8, VT);         \
+  else if (k <= 16) HYDOT_UC(16, VT);  \
+  else HYDOT_UC(32, VT);
+    if (mixed) { HYDOT_UC_T(float) } else { HYDOT_UC_T(double) }
+#undef HYDOT_UC_T
 #undef HYDOT_UC
     hipLaunchKernelGGL(k_gram, dim3(p.nchunks, nr), dim3(kBlock), 0, stream, op->gp, at<double>(p.o_U64),
                        at<double>(p.o_C64), k, buf_off, at<double>(p.o_gpart), p.nchunks);
@@ -565,7 +590,8 @@ struct Solver {
     ra.final_res = at<double>(p.o_final);
     dim3 gv(p.nchunks, nb), gr(nb);
     if (p.nl > 0)
-      hipLaunchKernelGGL(k_combine_x0<S>, gv, dim3(kBlock), 0, stream, c, at<cd>(p.o_VL), p.nl + 1, p.nl);
+      hipLaunchKernelGGL((k_combine_x0<S, typename Store<S>::real>), gv, dim3(kBlock), 0, stream, c,
+                         at<typename Store<S>::real>(p.o_VL), p.nl + 1, p.nl);
     else
       hipLaunchKernelGGL(k_zero_x<S>, gv, dim3(kBlock), 0, stream, c);
     HYDOT_HIP(hipGetLastError());

@@ -273,23 +273,23 @@ __global__ __launch_bounds__(kBlock) void k_zero_x(Ctx<S> c) {
 
 // X = V_L[rhs][0..nl) y0 (multi-shift initial guess, Alg. 1 step 5); VL holds
 // the real shift-invariant basis as complex vectors with zero imaginary part.
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_combine_x0(Ctx<S> c, const cd* VL, int vldim, int nl) {
+template <typename S, typename VT>
+__global__ __launch_bounds__(kBlock) void k_combine_x0(Ctx<S> c, const VT* VL, int vldim, int nl) {
   const int sys = blockIdx.y;
   const Chunk<S> ch(c.g);
   const size_t N = (size_t)c.g.N;
   const cd* y0 = c.small + (size_t)sys * c.sl.total + c.sl.y0;
-  const cd* Vb = VL + (size_t)c.prm[sys].rhs * vldim * N;
+  const VT* Vb = VL + (size_t)c.prm[sys].rhs * vldim * N;
   cd acc[kVPT];
 #pragma unroll
   for (int q = 0; q < kVPT; ++q) acc[q] = cd{0.0, 0.0};
   for (int l = 0; l < nl; ++l) {
     const cd yl = y0[l];
-    const cd* Vl = Vb + (size_t)l * N;
+    const VT* Vl = Vb + (size_t)l * N;
 #pragma unroll
     for (int q = 0; q < kVPT; ++q)
       if (ch.ok[q]) {
-        const double v = Vl[ch.n[q]].re;
+        const double v = (double)Vl[ch.n[q]];
         acc[q].re += v * yl.re;
         acc[q].im += v * yl.im;
       }
