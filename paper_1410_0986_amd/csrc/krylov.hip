@@ -477,14 +477,27 @@ struct Solver {
   if (tu.step_presum == 4) HYDOT_STEP_T(KER, NV, 4);            \
   else if (tu.step_presum == 2) HYDOT_STEP_T(KER, NV, 2);       \
   else HYDOT_STEP_T(KER, NV, 1);
+// exact basis-count instances for j + 1 <= 16
+#define HYDOT_STEP_NV(KER)                                                                               \
+  switch (j + 1) {                                                                                       \
+    case 1: { HYDOT_STEP_P(KER, 1) } break;   case 2: { HYDOT_STEP_P(KER, 2) } break;                     \
+    case 3: { HYDOT_STEP_P(KER, 3) } break;   case 4: { HYDOT_STEP_P(KER, 4) } break;                     \
+    case 5: { HYDOT_STEP_P(KER, 5) } break;   case 6: { HYDOT_STEP_P(KER, 6) } break;                     \
+    case 7: { HYDOT_STEP_P(KER, 7) } break;   case 8: { HYDOT_STEP_P(KER, 8) } break;                     \
+    case 9: { HYDOT_STEP_P(KER, 9) } break;   case 10: { HYDOT_STEP_P(KER, 10) } break;                   \
+    case 11: { HYDOT_STEP_P(KER, 11) } break; case 12: { HYDOT_STEP_P(KER, 12) } break;                   \
+    case 13: { HYDOT_STEP_P(KER, 13) } break; case 14: { HYDOT_STEP_P(KER, 14) } break;                   \
+    case 15: { HYDOT_STEP_P(KER, 15) } break; default: { HYDOT_STEP_P(KER, 16) } break;                   \
+  }
         if (kind == 0) {
-          if (small) { HYDOT_STEP_P(k_step_dots_t, 16) } else { HYDOT_STEP_P(k_step_dots_t, 32) }
+          if (small) { HYDOT_STEP_NV(k_step_dots_t) } else { HYDOT_STEP_P(k_step_dots_t, 32) }
         } else if (kind == 1) {
-          if (small) { HYDOT_STEP_P(k_step_update_t, 16) } else { HYDOT_STEP_P(k_step_update_t, 32) }
+          if (small) { HYDOT_STEP_NV(k_step_update_t) } else { HYDOT_STEP_P(k_step_update_t, 32) }
         } else {
           if (small) hipLaunchKernelGGL(k_step_finish_t<16>, gt, dim3(kTSub), 0, stream, c, j, grp, fl);
           else hipLaunchKernelGGL(k_step_finish_t<32>, gt, dim3(kTSub), 0, stream, c, j, grp, fl);
         }
+#undef HYDOT_STEP_NV
 #undef HYDOT_STEP_P
 #undef HYDOT_STEP_T
         return;

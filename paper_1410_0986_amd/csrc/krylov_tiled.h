@@ -145,18 +145,50 @@ __device__ inline void row_flush_all(const Ctx<cf>& c, int sys, int chunk, int n
   c.part[((size_t)sys * c.nchunks + chunk) * c.ndots + slot] = acc;
 }
 
-template <int NV>
-__device__ inline void load_basis(const cf* Vsys, size_t N, uint32_t n, bool ok, int nv, cf* vr) {
-#pragma unroll
-  for (int l = 0; l < NV; ++l) vr[l] = (l < nv && ok) ? Vsys[(size_t)l * N + n] : cf{0.f, 0.f};
+// Buffer-resource access (raw buffer loads): one 32-bit voxel byte offset in a VGPR
+// serves every vector of a system, the vector's byte offset rides in an SGPR, and an
+// offset past the end of the resource reads zero.  Each system's basis (and each
+// right-hand side's C, U) must stay below 2 GiB; the host checks this.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr uint32_t kOutside = 0x80000000u;   // voxel offset beyond every resource
+__device__ inline Rsrc make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline cf ld_cf(Rsrc r, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(cf, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+__device__ inline float ld_f(Rsrc r, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
 }
 
-__device__ inline void load_cu(const Ctx<cf>& c, int r, size_t N, uint32_t n, bool ok, float* cr, float* ur) {
+struct SysBuf {
+  Rsrc V, C, U, W;
+  uint32_t sv, sc;   // bytes between basis vectors, between C (U) vectors
+};
+__device__ inline SysBuf sys_buf(const Ctx<cf>& c, int sys, int rhs) {
+  const uint32_t N = (uint32_t)c.g.N;
+  SysBuf b;
+  b.sv = N * 8u;
+  b.sc = N * 4u;
+  b.V = make_rsrc(c.V + (size_t)sys * c.vdim * N, (uint32_t)c.vdim * b.sv);
+  b.C = make_rsrc(c.C + (size_t)rhs * c.k * N, (uint32_t)c.k * b.sc);
+  b.U = make_rsrc(c.U + (size_t)rhs * c.k * N, (uint32_t)c.k * b.sc);
+  b.W = make_rsrc(c.W + (size_t)sys * N, b.sv);
+  return b;
+}
+
+template <int NV>
+__device__ inline void load_basis(const SysBuf& b, uint32_t vo8, int nv, cf* vr) {
+#pragma unroll
+  for (int l = 0; l < NV; ++l) vr[l] = l < nv ? ld_cf(b.V, vo8, (uint32_t)l * b.sv) : cf{0.f, 0.f};
+}
+
+__device__ inline void load_cu(const SysBuf& b, int k, uint32_t vo4, float* cr, float* ur) {
 #pragma unroll
   for (int i = 0; i < kTK; ++i) {
-    const bool on = i < c.k && ok;
-    cr[i] = on ? c.C[((size_t)r * c.k + i) * N + n] : 0.f;
-    ur[i] = on ? c.U[((size_t)r * c.k + i) * N + n] : 0.f;
+    const bool on = i < k;
+    cr[i] = on ? ld_f(b.C, vo4, (uint32_t)i * b.sc) : 0.f;
+    ur[i] = on ? ld_f(b.U, vo4, (uint32_t)i * b.sc) : 0.f;
   }
 }
 
@@ -195,21 +227,18 @@ __device__ inline cf project_voxel(cf w, const cf* vr, const float* cr, const fl
 struct StencilRegs {
   cf xc, m[6];
 };
-__device__ inline void gather_stencil(const GridP& g, const cf* __restrict__ x, uint32_t n, bool ok,
+__device__ inline void gather_stencil(const GridP& g, const SysBuf& b, int j, uint32_t n, bool ok,
                                       const VoxelInfo& vi, StencilRegs& sr) {
-  // every load reads a valid address (voxel 0 stands in for a missing neighbour)
-  // and the unwanted values are zeroed afterwards, so the loads stay unconditional
+  // missing neighbours read past the resource (zero)
   const uint32_t sy = (uint32_t)g.nx, sz = (uint32_t)g.nx * (uint32_t)g.ny;
-  const bool has[6] = {ok && vi.i > 0, ok && vi.i < g.nx - 1, ok && vi.j > 0,
-                       ok && vi.j < g.ny - 1, ok && vi.k > 0, ok && vi.k < g.nz - 1};
-  const uint32_t nb[6] = {n - 1, n + 1, n - sy, n + sy, n - sz, n + sz};
-  const cf c = x[ok ? n : 0u];
-  sr.xc = ok ? c : cf{0.f, 0.f};
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    const cf m = x[has[f] ? nb[f] : 0u];
-    sr.m[f] = has[f] ? m : cf{0.f, 0.f};
-  }
+  const uint32_t so = (uint32_t)j * b.sv;
+  sr.xc = ld_cf(b.V, ok ? n * 8u : kOutside, so);
+  sr.m[0] = ld_cf(b.V, ok && vi.i > 0 ? (n - 1) * 8u : kOutside, so);
+  sr.m[1] = ld_cf(b.V, ok && vi.i < g.nx - 1 ? (n + 1) * 8u : kOutside, so);
+  sr.m[2] = ld_cf(b.V, ok && vi.j > 0 ? (n - sy) * 8u : kOutside, so);
+  sr.m[3] = ld_cf(b.V, ok && vi.j < g.ny - 1 ? (n + sy) * 8u : kOutside, so);
+  sr.m[4] = ld_cf(b.V, ok && vi.k > 0 ? (n - sz) * 8u : kOutside, so);
+  sr.m[5] = ld_cf(b.V, ok && vi.k < g.nz - 1 ? (n + sz) * 8u : kOutside, so);
 }
 // (A_hat x)_n from gathered operands: the same arithmetic as apply_op.
 __device__ inline cf stencil_apply(const GridP& g, const StencilRegs& sr, const VoxelInfo& vi, cd sig,
@@ -263,7 +292,9 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
   __shared__ ProdTile<P> pt;
   const int sys = ti.sys;
   const size_t N = (size_t)c.g.N;
-  const int k = c.k, nv = j + 1, t = threadIdx.x;
+  // NV <= 16: instance for exactly NV = j + 1 basis vectors (no per-vector guards);
+  // NV = 32: any 17..32 vectors
+  const int k = c.k, nv = NV <= 16 ? NV : j + 1, t = threadIdx.x;
   const SysParam p = c.prm[sys];
   const cf* Vsys = c.V + (size_t)sys * c.vdim * N;
   cf* wv = c.W + (size_t)sys * N;
@@ -286,7 +317,7 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
   cf vr[NV];
   float cr[kTK], ur[kTK];
   cf wpre{0.f, 0.f};
-  const cf* vj = Vsys + (size_t)j * N;
+  const SysBuf bf = sys_buf(c, sys, p.rhs);
   cf* vnext = c.V + ((size_t)sys * c.vdim + j + 1) * N;   // the update stores w' as V_{j+1}
   const float sj = KIND == 0 ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
   StencilRegs sreg;
@@ -294,21 +325,21 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
   {
     const uint32_t n0 = ti.chunk * kChunk + t;
     const bool ok0 = n0 < (uint32_t)c.g.N;
-    load_basis<NV>(Vsys, N, n0, ok0, nv, vr);
-    load_cu(c, p.rhs, N, n0, ok0, cr, ur);
+    load_basis<NV>(bf, ok0 ? n0 * 8u : kOutside, nv, vr);
+    load_cu(bf, k, ok0 ? n0 * 4u : kOutside, cr, ur);
     vinf = voxel_info(c.g, ok0 ? n0 : 0u);
-    if (KIND == 0) gather_stencil(c.g, vj, n0, ok0, vinf, sreg);
-    if (KIND == 1 && ok0) wpre = wv[n0];
+    if (KIND == 0) gather_stencil(c.g, bf, j, n0, ok0, vinf, sreg);
+    if (KIND == 1) wpre = ld_cf(bf.W, ok0 ? n0 * 8u : kOutside, 0u);
   }
   for (int sub = 0; sub < nsub; ++sub) {
     const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
     const bool ok = n < (uint32_t)c.g.N;
     if (!kPre && sub > 0) {
-      load_basis<NV>(Vsys, N, n, ok, nv, vr);
-      load_cu(c, p.rhs, N, n, ok, cr, ur);
+      load_basis<NV>(bf, ok ? n * 8u : kOutside, nv, vr);
+      load_cu(bf, k, ok ? n * 4u : kOutside, cr, ur);
       vinf = voxel_info(c.g, ok ? n : 0u);
-      if (KIND == 0) gather_stencil(c.g, vj, n, ok, vinf, sreg);
-      if (KIND == 1 && ok) wpre = wv[n];
+      if (KIND == 0) gather_stencil(c.g, bf, j, n, ok, vinf, sreg);
+      if (KIND == 1) wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
     }
     double rho = 0.0;
     cf w{0.f, 0.f};
@@ -333,11 +364,11 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
       if (kPre && sub + 1 < nsub) {
         const uint32_t nn = n + kTSub;
         const bool okn = nn < (uint32_t)c.g.N;
-        load_basis<NV>(Vsys, N, nn, okn, nv, vr);
-        load_cu(c, p.rhs, N, nn, okn, cr, ur);
+        load_basis<NV>(bf, okn ? nn * 8u : kOutside, nv, vr);
+        load_cu(bf, k, okn ? nn * 4u : kOutside, cr, ur);
         vinf = voxel_info(c.g, okn ? nn : 0u);
-        if (KIND == 0) gather_stencil(c.g, vj, nn, okn, vinf, sreg);
-        if (KIND == 1 && okn) wpre = wv[nn];
+        if (KIND == 0) gather_stencil(c.g, bf, j, nn, okn, vinf, sreg);
+        if (KIND == 1) wpre = ld_cf(bf.W, okn ? nn * 8u : kOutside, 0u);
       }
       __syncthreads();
       row_reduce<4, P>(pt, nv + drows, accv);
@@ -394,6 +425,7 @@ __global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int g
   cf* vn = Vsys + (size_t)(j + 1) * N;
   const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefB;
   const float inv_eta = (float)coef[k + c.mkmax + 1].re;
+  const SysBuf bf = sys_buf(c, sys, p.rhs);
   cf g[kTK], h[NV];
 #pragma unroll
   for (int i = 0; i < kTK; ++i) g[i] = i < k ? Store<cf>::from(coef[i]) : cf{0.f, 0.f};
@@ -404,8 +436,8 @@ __global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int g
     if (n >= (uint32_t)c.g.N) break;
     cf vr[NV];
     float cr[kTK], ur[kTK];
-    load_basis<NV>(Vsys, N, n, true, nv, vr);
-    load_cu(c, p.rhs, N, n, true, cr, ur);
+    load_basis<NV>(bf, n * 8u, nv, vr);
+    load_cu(bf, k, n * 4u, cr, ur);
     const double rho = (double)voxel_info(c.g, n).nrobin * c.g.inv_h;
     cf w = project_voxel<NV>(vn[n], vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
     vn[n] = cf{w.re * inv_eta, w.im * inv_eta};
