@@ -60,6 +60,7 @@ typedef enum {
 typedef enum {
   HYDOT_C128 = 0,           /* complex FP64 (re, im) */
   HYDOT_C64 = 1,            /* complex FP32 (re, im) */
+  HYDOT_CBF16 = 2,          /* complex BF16 (re, im): 2 x bfloat16, rounded to nearest even */
   HYDOT_F64 = 3,            /* real FP64 */
   HYDOT_F32 = 4             /* real FP32 */
 } hydot_dtype;
@@ -134,11 +135,12 @@ hydot_status hydot_solve_workspace_bytes(const hydot_operator* op, int32_t n_rhs
  * rhs_voxel: host [n_rhs] voxel indices; right-hand side r is a unit injection
  *   into that voxel (S = S0 delta(r - r_s) with S0 = 1).  Sources and detectors
  *   (adjoint fields, Sec. 2.1) are both passed here; slice the output.
- * phi: device [n_lambda][n_rhs][N], the physical fields (not D*phi), dtype C128 or C64.
+ * phi: device [n_lambda][n_rhs][N], the physical fields (not D*phi), dtype C128, C64 or
+ *   CBF16 (rounded from the FP64 iterate; the storage the BF16 Born products read).
  * workspace: device, >= the size from hydot_solve_workspace_bytes, 256-byte aligned.
  * iters: host [n_lambda*n_rhs] (lambda-major) Arnoldi steps per system, or NULL.
  * rel_res: host [n_lambda*n_rhs] final FP64-recomputed ||b - A phi||/||b|| of the
- *   FP64 iterate (before any conversion to C64), or NULL.
+ *   FP64 iterate (before any conversion to C64 or CBF16), or NULL.
  * Returns HYDOT_ENOCONV (fields still written) if any system stays above rel_tol. */
 hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
                                 const hydot_solve_opts* opts, void* phi, hydot_dtype phi_dtype,
@@ -151,16 +153,30 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
  * phi_src: device, source s at wavelength l at phi_src + (l*lam_stride + s)*N elements;
  * phi_det: likewise with d.  lam_stride >= max(S, D) counts N-vectors between wavelengths
  * (S for a packed source array, n_rhs for slices of the hydot_solve_fields output).
- * field_dtype C128: v is FP64, y is C128.  C64: v is FP32, y is C64 (FP32 MFMA, FP64 split-K sums).
+ * field_dtype C128: v is FP64, y is C128 (FP64 MFMA).
+ *             C64:  v is FP32, y is C64 (FP32 MFMA, FP64 sums across 32-voxel stages and splits).
+ *             CBF16: v is FP32, y is C64; both operands (phi_src v formed in FP32, and phi_det)
+ *                   rounded to BF16 for the BF16 MFMA, FP32 accumulation within a stage, FP64
+ *                   beyond.  Relative error of order 1e-2 (a stated-error variant).
  * v: device [n_v][N] real.  y: device [n_v][n_lambda][S][D].  1 <= S, D <= 64, 1 <= n_v <= 64. */
 hydot_status hydot_born_apply(const hydot_operator* op, const void* phi_src, int32_t S,
                               const void* phi_det, int32_t D, int64_t lam_stride,
                               hydot_dtype field_dtype, const void* v, int32_t n_v, void* y,
                               hipStream_t stream);
 
+/* Arithmetic of the J v products.  HYDOT_BORN_SPLIT_BF16 (C64 fields only): each FP32 operand
+ * x is split into hi = bf16(x) and lo = bf16(x - hi) and the product accumulates
+ * hi*hi + hi*lo + lo*hi on the BF16 MFMA (relative error of order 1e-5, FP32 field bytes). */
+typedef enum { HYDOT_BORN_NATIVE = 0, HYDOT_BORN_SPLIT_BF16 = 1 } hydot_born_compute;
+hydot_status hydot_born_apply_ex(const hydot_operator* op, const void* phi_src, int32_t S,
+                                 const void* phi_det, int32_t D, int64_t lam_stride,
+                                 hydot_dtype field_dtype, hydot_born_compute compute, const void* v,
+                                 int32_t n_v, void* y, hipStream_t stream);
+
 /* Adjoint product summed over wavelengths:
  *   g[k] = sum_{l,s,d} conj(J_l[s,d,k]) w[l][s][d] = -h^3 sum conj(phi_src[l][s][k] phi_det[l][d][k]) w[l][s][d]
- * w: device [n_lambda][S][D] complex and g: device [N] complex, both of field_dtype. */
+ * w: device [n_lambda][S][D] complex and g: device [N] complex, both C128 for C128 fields and C64
+ * for C64 or CBF16 fields (CBF16 fields are widened exactly to FP32 for the FP32 MFMA). */
 hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_src, int32_t S,
                                       const void* phi_det, int32_t D, int64_t lam_stride,
                                       hydot_dtype field_dtype, const void* w, void* g,
@@ -250,10 +266,12 @@ hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_
  * records HIP events on its stream around every launch of the three Arnoldi step kernels
  * (first-pass dots with the operator, CGS2 update, normalisation) and accumulates, per
  * kernel, launches, elapsed milliseconds and algorithmic HBM bytes: for step j with
- * storage b bytes per complex, k deflation vectors and A systems stepping,
- *   dots A*N*b*(j+2+k), update A*N*b*(j+3+k), finish A'*N*b*(j+3+k)
- * with A' the systems whose second Gram-Schmidt pass is applied at step j (each unique
- * vector read once, plus the written vector; C and U are real, b/2 each).
+ * storage b bytes per complex, k deflation vectors, A systems stepping and R' distinct
+ * right-hand sides among them,
+ *   dots (A*(j+2) + R'*k)*N*b, update (A*(j+3) + R'*k)*N*b, finish (A'*(j+3) + min(A', R')*k)*N*b
+ * with A' the systems whose second Gram-Schmidt pass is applied at step j: each unique
+ * vector is read once and the written vector counted; C and U (real, b/2 each) are
+ * shared by the wavelengths of a right-hand side, so they count once per right-hand side.
  * Enabling resets the counters; the graph flag is ignored while enabled (launches are
  * timed one by one).  Process-wide; not thread-safe. */
 typedef struct {

@@ -29,7 +29,8 @@ from ._binding import (  # noqa: F401
     set_tuning,
     autotune_solve,
     autotune_born,
-    C128, C64, F64, F32,
+    C128, C64, CBF16, F64, F32,
+    BORN_NATIVE, BORN_SPLIT_BF16,
     PREC_FP64, PREC_MIXED,
     FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH,
     OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED,

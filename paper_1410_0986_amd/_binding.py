@@ -18,7 +18,8 @@ if not os.path.exists(_LIBPATH):
 _lib = ctypes.CDLL(_LIBPATH)
 
 OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4
-C128, C64, F64, F32 = 0, 1, 3, 4
+C128, C64, CBF16, F64, F32 = 0, 1, 2, 3, 4
+BORN_NATIVE, BORN_SPLIT_BF16 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH = 0x1, 0x2, 0x4, 0x8, 0x10
 
@@ -67,6 +68,8 @@ _solve = _proto("hydot_solve_fields", c_int32, c_void_p, c_int32, POINTER(c_int6
                 c_int32, c_void_p, c_size_t, POINTER(c_int32), POINTER(c_double), c_void_p)
 _born = _proto("hydot_born_apply", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32,
                c_void_p, c_int32, c_void_p, c_void_p)
+_born_ex = _proto("hydot_born_apply_ex", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32,
+                  c_int32, c_void_p, c_int32, c_void_p, c_void_p)
 _born_adj = _proto("hydot_born_apply_adjoint", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64,
                    c_int32, c_void_p, c_void_p, c_void_p)
 _pals = _proto("hydot_pals_shape", c_int32, c_void_p, POINTER(c_double), c_int32, POINTER(_PalsOpts), c_void_p,
@@ -224,11 +227,19 @@ class Operator:
 
 
 def _cdtype(t: torch.Tensor) -> int:
+    """Library dtype of a field tensor; complex BF16 fields are bfloat16 tensors whose last
+    dimension (size 2) holds (re, im)."""
     if t.dtype == torch.complex128:
         return C128
     if t.dtype == torch.complex64:
         return C64
-    raise ValueError("complex tensors must be complex128 or complex64")
+    if t.dtype == torch.bfloat16 and t.dim() >= 1 and t.shape[-1] == 2:
+        return CBF16
+    raise ValueError("fields must be complex128, complex64 or bfloat16 [..., 2] (re, im) tensors")
+
+
+def _field_shape(op, count, dtype):
+    return (op.L, count, op.N, 2) if dtype == torch.bfloat16 else (op.L, count, op.N)
 
 
 def apply_operator(op: Operator, lam_index, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
@@ -262,10 +273,10 @@ def solve_fields(op: Operator, rhs_voxels, opts: SolveOptions | None = None, out
     vox = np.ascontiguousarray(rhs_voxels, dtype=np.int64)
     R = int(vox.shape[0])
     if out is None:
-        out = torch.empty((op.L, R, op.N), dtype=out_dtype, device=device)
+        out = torch.empty(_field_shape(op, R, out_dtype), dtype=out_dtype, device=device)
     _need_cuda(out, "out")
-    if not out.is_contiguous() or tuple(out.shape) != (op.L, R, op.N):
-        raise ValueError("out must be a contiguous [L, n_rhs, N] tensor")
+    if not out.is_contiguous() or tuple(out.shape) != _field_shape(op, R, out.dtype):
+        raise ValueError("out must be a contiguous [L, n_rhs, N] tensor ([L, n_rhs, N, 2] for bfloat16)")
     o = opts._c()
     nbytes = solve_workspace_bytes(op, R, opts)
     buf, wptr = _ws(nbytes, out.device)
@@ -336,7 +347,7 @@ def autotune_born(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, v:
     rdt = torch.float64 if dt == C128 else torch.float32
     _need_cuda(v, "v")
     v = v.reshape(-1, op.N).to(rdt).contiguous()
-    y = torch.empty((v.shape[0], op.L, S, D), dtype=phi_src.dtype, device=phi_src.device)
+    y = torch.empty((v.shape[0], op.L, S, D), dtype=_out_complex(dt), device=phi_src.device)
     arr = (_Trial * 64)()
     n = c_int32(0)
     _check(_tune_born(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt, c_void_p(v.data_ptr()), int(v.shape[0]),
@@ -345,16 +356,29 @@ def autotune_born(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, v:
 
 
 def _field_view(op: Operator, t: torch.Tensor, name: str):
+    """(pointer, count, wavelength stride in N-vectors) of an [L, count, N] field slice
+    (or [L, count, N, 2] bfloat16)."""
     _need_cuda(t, name)
-    if t.dim() != 3 or t.shape[0] != op.L or t.shape[2] != op.N:
-        raise ValueError(f"{name} must be [L, count, N]")
-    if t.stride(2) != 1 or (t.shape[1] > 1 and t.stride(1) != op.N) or t.stride(0) % op.N != 0:
+    pair = 2 if t.dtype == torch.bfloat16 else 1
+    if t.dim() != (4 if pair == 2 else 3) or t.shape[0] != op.L or t.shape[2] != op.N:
+        raise ValueError(f"{name} must be [L, count, N] ([L, count, N, 2] for bfloat16)")
+    if pair == 2 and (t.shape[3] != 2 or t.stride(3) != 1):
+        raise ValueError(f"{name}: bfloat16 fields need a contiguous (re, im) last dimension")
+    vec = op.N * pair
+    if t.stride(2) != pair or (t.shape[1] > 1 and t.stride(1) != vec) or t.stride(0) % vec != 0:
         raise ValueError(f"{name} must have N-contiguous rows (a slice of an [L, R, N] field array)")
-    return t.data_ptr(), int(t.shape[1]), t.stride(0) // op.N
+    return t.data_ptr(), int(t.shape[1]), t.stride(0) // vec
 
 
-def born_apply(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
-    """y[c, l, s, d] = -h^3 sum_k phi_src[l,s,k] v[c,k] phi_det[l,d,k] (hydot_born_apply)."""
+def _out_complex(dt):
+    return torch.complex128 if dt == C128 else torch.complex64
+
+
+def born_apply(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, v: torch.Tensor,
+               split_bf16: bool = False) -> torch.Tensor:
+    """y[c, l, s, d] = -h^3 sum_k phi_src[l,s,k] v[c,k] phi_det[l,d,k] (hydot_born_apply_ex).
+
+    split_bf16: complex64 fields only; products by split-BF16 MFMA (hi*hi + hi*lo + lo*hi)."""
     ps, S, ls = _field_view(op, phi_src, "phi_src")
     pd, D, ld = _field_view(op, phi_det, "phi_det")
     if ls != ld:
@@ -365,9 +389,10 @@ def born_apply(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, v: to
     rdt = torch.float64 if dt == C128 else torch.float32
     _need_cuda(v, "v")
     v = v.reshape(-1, op.N).to(rdt).contiguous()
-    y = torch.empty((v.shape[0], op.L, S, D), dtype=phi_src.dtype, device=phi_src.device)
-    _check(_born(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt, c_void_p(v.data_ptr()), int(v.shape[0]),
-                 c_void_p(y.data_ptr()), _stream(phi_src.device)))
+    y = torch.empty((v.shape[0], op.L, S, D), dtype=_out_complex(dt), device=phi_src.device)
+    _check(_born_ex(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt,
+                    BORN_SPLIT_BF16 if split_bf16 else BORN_NATIVE, c_void_p(v.data_ptr()), int(v.shape[0]),
+                    c_void_p(y.data_ptr()), _stream(phi_src.device)))
     return y
 
 
@@ -379,10 +404,10 @@ def born_apply_adjoint(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tenso
         raise ValueError("phi_src and phi_det must share the wavelength stride")
     dt = _cdtype(phi_src)
     _need_cuda(w, "w")
-    w = w.to(phi_src.dtype).contiguous()
+    w = w.to(_out_complex(dt)).contiguous()
     if tuple(w.shape) != (op.L, S, D):
         raise ValueError("w must be [L, S, D]")
-    g = torch.empty(op.N, dtype=phi_src.dtype, device=phi_src.device)
+    g = torch.empty(op.N, dtype=_out_complex(dt), device=phi_src.device)
     _check(_born_adj(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt, c_void_p(w.data_ptr()),
                      c_void_p(g.data_ptr()), _stream(phi_src.device)))
     return g

@@ -16,6 +16,7 @@
 // 16 lanes of a k-slot read 16 consecutive voxels of one source row.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 #include "operator.h"
@@ -49,85 +50,197 @@ constexpr size_t kLdsCap = 64 * 1024;   // LDS budget per block of J v
 inline int pad8(int x) { return (x + 7) / 8 * 8; }
 
 // ---------------------------------------------------------------- J v
-// Block = 4 waves on one (split, wavelength, probe vector).  Rows of the real
-// product: a < Sp -> Re(phi_s v), a >= Sp -> Im(phi_s v); columns b < Dp ->
-// Re phi_d, b >= Dp -> Im phi_d.  Wave w owns output tiles w, w+4, ...
-template <typename T, int TPW, int kKT>
-__global__ __launch_bounds__(kBlock) void k_born_apply(int N, int S, int D, int Sp, int Dp, int64_t lam_stride,
-                                                      const cplx<T>* __restrict__ phs,
-                                                      const cplx<T>* __restrict__ phd,
-                                                      const T* __restrict__ v, int kb, int L,
-                                                      double* __restrict__ part) {
-  constexpr int kKTP = kKT + 4;         // padded LDS row
+// Field storage: complex FP64, complex FP32 or complex BF16 (widened on load).
+template <typename TS> struct Field;
+template <> struct Field<cd> {
+  using real = double;
+  __device__ static inline cd get(const cd* p, size_t i) { return p[i]; }
+};
+template <> struct Field<cf> {
+  using real = float;
+  __device__ static inline cf get(const cf* p, size_t i) { return p[i]; }
+};
+template <> struct Field<cbf> {
+  using real = float;
+  __device__ static inline cf get(const cbf* p, size_t i) {
+    const cbf z = p[i];
+    return cf{bf16_value(z.re), bf16_value(z.im)};
+  }
+};
+
+// Products of J v: CM_F64 / CM_F32 run the MFMA of the storage precision; CM_BF16
+// rounds both operands (phi_s v formed in FP32, and phi_d) to BF16 for
+// v_mfma_f32_16x16x32_bf16; CM_SPLIT splits each FP32 operand into hi + lo BF16 parts
+// and accumulates hi*hi + hi*lo + lo*hi (three BF16 MFMAs).
+enum BornCompute { CM_F64 = 0, CM_F32 = 1, CM_BF16 = 2, CM_SPLIT = 3 };
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline bf16x8 to_bf16x8(const float* x) {
+  bf16x8 r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = (__bf16)x[i];
+  return r;
+}
+__device__ inline bf16x8 bf16_residual(const float* x, bf16x8 hi) {
+  bf16x8 r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = (__bf16)(x[i] - (float)hi[i]);
+  return r;
+}
+
+// Block = 4 waves on one (split over voxels, wavelength, group of NVB probe vectors).
+// Each stage of KT voxels stages the real-ified rows [Re; Im] of Phi_s (2Sp rows) and
+// Phi_d (2Dp rows) and the NVB probe-vector segments in LDS once; every probe vector
+// of the group then reuses them (v_c is applied to the A operand in registers).  The
+// next stage's global loads are issued before this stage's MFMAs.  Wave w owns output
+// tiles w, w+4, ... of the (2Sp x 2Dp) real product, per probe vector.
+template <typename TS, int CM, int TPW, int NVB, int KT, int EM>
+__global__ __launch_bounds__(kBlock) void k_born_jv(int N, int S, int D, int Sp, int Dp, int64_t lam_stride,
+                                                   const TS* __restrict__ phs, const TS* __restrict__ phd,
+                                                   const typename Field<TS>::real* __restrict__ v, int n_v, int kb,
+                                                   int L, double* __restrict__ part) {
+  using R = typename Field<TS>::real;   // LDS and operand precision before the BF16 rounding
+  constexpr int KTP = KT + 4;           // padded LDS row
+  constexpr int kMaxE = EM;             // staged elements per thread per row set (>= pad8(S)*KT/kBlock)
+  constexpr bool kFold = NVB == 1;      // one probe vector: fold v into the staged Phi_s rows
+  static_assert(CM == CM_F64 || CM == CM_F32 || KT == 32, "BF16 products take 32 voxels per MFMA");
   extern __shared__ unsigned char smem_raw[];
-  T* As = (T*)smem_raw;                 // [2Sp][kKTP]
-  T* Bs = As + 2 * Sp * kKTP;           // [2Dp][kKTP]
-  T* vs = Bs + 2 * Dp * kKTP;           // [kKT]
-  const int split = blockIdx.x, l = blockIdx.y, c = blockIdx.z;
+  R* As = (R*)smem_raw;                 // [2Sp][KTP]
+  R* Bs = As + 2 * Sp * KTP;            // [2Dp][KTP]
+  R* Vs = Bs + 2 * Dp * KTP;            // [NVB][KT]
+  const int split = blockIdx.x, l = blockIdx.y, cv0 = blockIdx.z * NVB;
   const int nsplit = gridDim.x;
   const int k0 = split * kb, k1 = min(N, k0 + kb);
-  const int TA = 2 * Sp / 16, TB = 2 * Dp / 16, T_all = TA * TB;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const cplx<T>* ps = phs + (size_t)l * lam_stride * N;
-  const cplx<T>* pd = phd + (size_t)l * lam_stride * N;
-  const T* vc = v + (size_t)c * N;
-  using MA = typename Mfma<T>::acc;
-  MA acc[TPW];
-  f64x4 tot[TPW];
+  const int TB = 2 * Dp / 16, T_all = (2 * Sp / 16) * TB;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const TS* ps = phs + (size_t)l * lam_stride * N;
+  const TS* pd = phd + (size_t)l * lam_stride * N;
+  const int ns = Sp * KT, nd = Dp * KT;   // staged (row, voxel) pairs of each row set
+  const int es = (ns + kBlock - 1) / kBlock, ed = (nd + kBlock - 1) / kBlock;
+  using CM_ACC = typename std::conditional<CM == CM_F64, f64x4, f32x4>::type;
+  CM_ACC acc[TPW][NVB];
+  f64x4 tot[TPW][NVB];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    acc[t] = MA{0, 0, 0, 0};
-    tot[t] = f64x4{0, 0, 0, 0};
-  }
-  for (int kbase = k0; kbase < k1; kbase += kKT) {
-    const int kn = min(kKT, k1 - kbase);
-    for (int i = threadIdx.x; i < kKT; i += kBlock) vs[i] = i < kn ? vc[kbase + i] : (T)0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < Sp * kKT; i += kBlock) {
-      const int s = i / kKT, kk = i % kKT;
-      cplx<T> z{0, 0};
-      if (s < S && kk < kn) z = ps[(size_t)s * N + kbase + kk];
-      const T vv = vs[kk];
-      As[s * kKTP + kk] = z.re * vv;
-      As[(Sp + s) * kKTP + kk] = z.im * vv;
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int c = 0; c < NVB; ++c) {
+      acc[t][c] = CM_ACC{0, 0, 0, 0};
+      tot[t][c] = f64x4{0, 0, 0, 0};
     }
-    for (int i = threadIdx.x; i < Dp * kKT; i += kBlock) {
-      const int d = i / kKT, kk = i % kKT;
-      cplx<T> z{0, 0};
-      if (d < D && kk < kn) z = pd[(size_t)d * N + kbase + kk];
-      Bs[d * kKTP + kk] = z.re;
-      Bs[(Dp + d) * kKTP + kk] = z.im;
+  // register stage: element e of this thread is row i / KT, voxel i % KT with i = tid + e * kBlock
+  cplx<R> rs[kMaxE], rd[kMaxE];
+  R rv = 0;
+  auto fetch = [&](int kbase) {
+    const int kn = min(KT, k1 - kbase);
+#pragma unroll
+    for (int e = 0; e < kMaxE; ++e) {
+      if (e < es && tid + e * kBlock < ns) {
+        const int i = tid + e * kBlock, row = i / KT, kk = i % KT;
+        rs[e] = row < S && kk < kn ? Field<TS>::get(ps, (size_t)row * N + kbase + kk) : cplx<R>{0, 0};
+      }
+      if (e < ed && tid + e * kBlock < nd) {
+        const int i = tid + e * kBlock, row = i / KT, kk = i % KT;
+        rd[e] = row < D && kk < kn ? Field<TS>::get(pd, (size_t)row * N + kbase + kk) : cplx<R>{0, 0};
+      }
     }
+    if (kFold) {
+#pragma unroll
+      for (int e = 0; e < kMaxE; ++e)
+        if (e < es && tid + e * kBlock < ns) {
+          const int kk = (tid + e * kBlock) % KT;
+          const R vv = cv0 < n_v && kk < kn ? v[(size_t)cv0 * N + kbase + kk] : (R)0;
+          rs[e].re *= vv;
+          rs[e].im *= vv;
+        }
+    } else if (tid < NVB * KT) {
+      const int c = tid / KT, kk = tid % KT;
+      rv = cv0 + c < n_v && kk < kn ? v[(size_t)(cv0 + c) * N + kbase + kk] : (R)0;
+    }
+  };
+  fetch(k0);
+  for (int kbase = k0; kbase < k1; kbase += KT) {
+#pragma unroll
+    for (int e = 0; e < kMaxE; ++e) {
+      if (e < es && tid + e * kBlock < ns) {
+        const int i = tid + e * kBlock, row = i / KT, kk = i % KT;
+        As[row * KTP + kk] = rs[e].re;
+        As[(Sp + row) * KTP + kk] = rs[e].im;
+      }
+      if (e < ed && tid + e * kBlock < nd) {
+        const int i = tid + e * kBlock, row = i / KT, kk = i % KT;
+        Bs[row * KTP + kk] = rd[e].re;
+        Bs[(Dp + row) * KTP + kk] = rd[e].im;
+      }
+    }
+    if (!kFold && tid < NVB * KT) Vs[tid] = rv;
     __syncthreads();
+    if (kbase + KT < k1) fetch(kbase + KT);   // in flight during the products
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const int tile = wave + 4 * t;
       if (tile < T_all) {
         const int ta = tile / TB, tb = tile % TB;
-        const T* arow = As + (ta * 16 + (lane & 15)) * kKTP + (lane >> 4);
-        const T* brow = Bs + (tb * 16 + (lane & 15)) * kKTP + (lane >> 4);
+        const int g = lane >> 4;
+        const R* arow = As + (ta * 16 + (lane & 15)) * KTP;
+        const R* brow = Bs + (tb * 16 + (lane & 15)) * KTP;
+        if constexpr (CM == CM_F64 || CM == CM_F32) {
 #pragma unroll
-        for (int kk = 0; kk < kKT; kk += 4) acc[t] = Mfma<T>::step(arow[kk], brow[kk], acc[t]);
-        // FP64 accumulation across stages
+          for (int kk = 0; kk < KT; kk += 4) {
+            const R a = arow[kk + g], b = brow[kk + g];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) tot[t][r] += (double)acc[t][r];
-        acc[t] = MA{0, 0, 0, 0};
+            for (int c = 0; c < NVB; ++c)
+              acc[t][c] = Mfma<R>::step(kFold ? a : a * Vs[c * KT + kk + g], b, acc[t][c]);
+          }
+        } else {
+          float bx[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) bx[i] = brow[8 * g + i];
+          const bf16x8 bh = to_bf16x8(bx);
+          bf16x8 bl;
+          if constexpr (CM == CM_SPLIT) bl = bf16_residual(bx, bh);
+#pragma unroll
+          for (int c = 0; c < NVB; ++c) {
+            float ax[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) ax[i] = kFold ? arow[8 * g + i] : arow[8 * g + i] * Vs[c * KT + 8 * g + i];
+            const bf16x8 ah = to_bf16x8(ax);
+            acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[t][c], 0, 0, 0);
+            if constexpr (CM == CM_SPLIT) {
+              const bf16x8 al = bf16_residual(ax, ah);
+              acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[t][c], 0, 0, 0);
+              acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[t][c], 0, 0, 0);
+            }
+          }
+        }
+        if constexpr (CM != CM_F64) {   // FP64 accumulation across stages
+#pragma unroll
+          for (int c = 0; c < NVB; ++c) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot[t][c][r] += (double)acc[t][c][r];
+            acc[t][c] = CM_ACC{0, 0, 0, 0};
+          }
+        }
       }
     }
     __syncthreads();
   }
   // partial tile sums: part[((c*L + l)*nsplit + split)][2Sp][2Dp]
-  double* out = part + ((size_t)(c * L + l) * nsplit + split) * (size_t)(2 * Sp) * (2 * Dp);
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int tile = wave + 4 * t;
-    if (tile < T_all) {
-      const int ta = tile / TB, tb = tile % TB;
-      const int col = tb * 16 + (lane & 15);
+  for (int c = 0; c < NVB; ++c) {
+    if (cv0 + c >= n_v) break;
+    double* out = part + ((size_t)((cv0 + c) * L + l) * nsplit + split) * (size_t)(2 * Sp) * (2 * Dp);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = ta * 16 + Mfma<T>::out_row(lane, r);
-        out[(size_t)row * (2 * Dp) + col] = tot[t][r];
+    for (int t = 0; t < TPW; ++t) {
+      const int tile = wave + 4 * t;
+      if (tile < T_all) {
+        const int ta = tile / TB, tb = tile % TB;
+        const int col = tb * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = ta * 16 + Mfma<R>::out_row(lane, r);
+          out[(size_t)row * (2 * Dp) + col] = CM == CM_F64 ? (double)acc[t][c][r] : tot[t][c][r];
+        }
       }
     }
   }
@@ -162,12 +275,13 @@ __global__ void k_born_apply_finish(int S, int D, int Sp, int Dp, int nsplit, in
 // the epilogue contracts T with conj(phi_d) per voxel.  Lane (voxel i = lane%16,
 // slot gq = lane/16) loads the sources s = gq (mod 4) of its voxel once and uses
 // their real parts for k-index s and imaginary parts for k-index Sp + s.
-template <typename T, int TBM, int SQ>
+template <typename TS, int TBM, int SQ>
 __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, int Sp, int Dp, int64_t lam_stride,
-                                                        int L, const cplx<T>* __restrict__ phs,
-                                                        const cplx<T>* __restrict__ phd,
-                                                        const cplx<T>* __restrict__ w, double scale,
-                                                        cplx<T>* __restrict__ g) {
+                                                        int L, const TS* __restrict__ phs,
+                                                        const TS* __restrict__ phd,
+                                                        const cplx<typename Field<TS>::real>* __restrict__ w,
+                                                        double scale, cplx<typename Field<TS>::real>* __restrict__ g) {
+  using T = typename Field<TS>::real;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, gq = lane >> 4;
   const int vox0 = (blockIdx.x * 4 + wave) * 16;
@@ -177,14 +291,14 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, in
   using MA = typename Mfma<T>::acc;
   double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
   for (int l = 0; l < L; ++l) {
-    const cplx<T>* ps = phs + (size_t)l * lam_stride * N;
-    const cplx<T>* pd = phd + (size_t)l * lam_stride * N;
+    const TS* ps = phs + (size_t)l * lam_stride * N;
+    const TS* pd = phd + (size_t)l * lam_stride * N;
     const cplx<T>* wl = w + (size_t)l * S * D;
     cplx<T> z[SQ];   // phi_s[s][vox] for s = gq + 4q
 #pragma unroll
     for (int q = 0; q < SQ; ++q) {
       const int s = gq + 4 * q;
-      z[q] = (q < Sp / 4 && s < S && vok) ? ps[(size_t)s * N + vox] : cplx<T>{0, 0};
+      z[q] = (q < Sp / 4 && s < S && vok) ? Field<TS>::get(ps, (size_t)s * N + vox) : cplx<T>{0, 0};
     }
     MA acc[TBM];
 #pragma unroll
@@ -219,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, in
         for (int r = 0; r < 4; ++r) {
           const int vv = vox0 + Mfma<T>::out_row(lane, r);
           cplx<T> ph{0, 0};
-          if (d < D && vv < N) ph = pd[(size_t)d * N + vv];
+          if (d < D && vv < N) ph = Field<TS>::get(pd, (size_t)d * N + vv);
           const double e = ph.re, f = ph.im;
           const double tv = (double)acc[t][r];
           if (!imcol) {          // Re T column
@@ -251,44 +365,65 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, in
   }
 }
 
-template <typename T>
+template <typename TS, int CM>
 hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
                              int64_t ls, const void* v, int n_v, void* y, hipStream_t stream) {
+  using R = typename Field<TS>::real;
   const int N = op->gp.N, L = op->L;
   const int Sp = pad8(S), Dp = pad8(D);
   const int T_all = (2 * Sp / 16) * (2 * Dp / 16);
-  const int tpw = (T_all + 3) / 4;
-  // voxels per LDS stage: 32 when the staged rows fit the LDS budget (unless the tuning
-  // asks for 16), else 16; larger stages lower the resident blocks per CU and measure slower
+  const int tpw_need = (T_all + 3) / 4;
+  const int tpw = tpw_need <= 1 ? 1 : tpw_need <= 2 ? 2 : tpw_need <= 4 ? 4 : tpw_need <= 8 ? 8 : 16;
+  // probe vectors per block: up to 8, with tiles-per-wave x vectors <= 8 (accumulator registers)
+  int nvb = 1;
+  while (nvb < 8 && nvb < n_v && tpw * nvb * 2 <= 8) nvb *= 2;
+  // voxels per LDS stage: 32 when the staged rows fit the LDS budget (unless the tuning asks for
+  // 16 on an FP32/FP64 product), else 16; BF16 products always take 32
   const hydot_tuning tu = resolved_tuning(op->tune);
-  const bool fits32 = (size_t)(2 * Sp + 2 * Dp) * 36 * sizeof(T) + 32 * sizeof(T) <= kLdsCap;
-  const int kt = fits32 && tu.born_stage != 16 ? 32 : 16;
-  // split-K over voxels so the grid has about born_blocks blocks
+  auto lds_bytes = [&](int kt) {
+    return (size_t)(2 * Sp + 2 * Dp) * (kt + 4) * sizeof(R) + (nvb > 1 ? (size_t)nvb * kt * sizeof(R) : 0);
+  };
+  const bool bf = CM == CM_BF16 || CM == CM_SPLIT;
+  const int kt = bf ? 32 : (lds_bytes(32) <= kLdsCap && tu.born_stage != 16 ? 32 : 16);
+  const int ngroups = (n_v + nvb - 1) / nvb;
+  // split over voxels so the grid has about born_blocks blocks
   const int max_split = (N + kt - 1) / kt;
-  int nsplit = std::max(1, std::min(max_split, (tu.born_blocks + L * n_v - 1) / (L * n_v)));
+  int nsplit = std::max(1, std::min(max_split, (tu.born_blocks + L * ngroups - 1) / (L * ngroups)));
   int kb = (N + nsplit - 1) / nsplit;
   kb = (kb + kt - 1) / kt * kt;
   nsplit = (N + kb - 1) / kb;
   const size_t pbytes = (size_t)n_v * L * nsplit * (2 * Sp) * (2 * Dp) * sizeof(double);
   void* part = nullptr;
   HYDOT_HIP(hipMallocAsync(&part, pbytes, stream));
-  const size_t lds = (size_t)(2 * Sp + 2 * Dp) * (kt + 4) * sizeof(T) + kt * sizeof(T);
-  dim3 grid(nsplit, L, n_v);
-#define HYDOT_BA(TP, KT)                                                                                      \
-  hipLaunchKernelGGL((k_born_apply<T, TP, KT>), grid, dim3(kBlock), lds, stream, N, S, D, Sp, Dp, ls,        \
-                     (const cplx<T>*)phs, (const cplx<T>*)phd, (const T*)v, kb, L, (double*)part)
-#define HYDOT_BA_T(TP) \
-  if (kt == 32) HYDOT_BA(TP, 32); else HYDOT_BA(TP, 16);
-  if (tpw <= 1) { HYDOT_BA_T(1) }
-  else if (tpw <= 2) { HYDOT_BA_T(2) }
-  else if (tpw <= 4) { HYDOT_BA_T(4) }
-  else if (tpw <= 8) { HYDOT_BA_T(8) }
-  else { HYDOT_BA_T(16) }
-#undef HYDOT_BA_T
+  const size_t lds = lds_bytes(kt);
+  dim3 grid(nsplit, L, ngroups);
+  // staged elements per thread: 2 covers up to 16 rows at 32 voxels per stage, 8 covers 64
+  const bool em2 = std::max(Sp, Dp) * kt <= 2 * kBlock;
+#define HYDOT_BA_E(TP, NB, KT, EM)                                                                               \
+  hipLaunchKernelGGL((k_born_jv<TS, CM, TP, NB, KT, EM>), grid, dim3(kBlock), lds, stream, N, S, D, Sp, Dp, ls, \
+                     (const TS*)phs, (const TS*)phd, (const R*)v, n_v, kb, L, (double*)part)
+#define HYDOT_BA(TP, NB, KT) \
+  if (em2) { HYDOT_BA_E(TP, NB, KT, 2); } else { HYDOT_BA_E(TP, NB, KT, (64 * KT / kBlock)); }
+#define HYDOT_BA_K(TP, NB) \
+  if (kt == 32) { HYDOT_BA(TP, NB, 32); } else if constexpr (!(CM == CM_BF16 || CM == CM_SPLIT)) { HYDOT_BA(TP, NB, 16); }
+  if (tpw == 1) {
+    if (nvb == 8) { HYDOT_BA_K(1, 8) } else if (nvb == 4) { HYDOT_BA_K(1, 4) }
+    else if (nvb == 2) { HYDOT_BA_K(1, 2) } else { HYDOT_BA_K(1, 1) }
+  } else if (tpw == 2) {
+    if (nvb == 4) { HYDOT_BA_K(2, 4) } else if (nvb == 2) { HYDOT_BA_K(2, 2) } else { HYDOT_BA_K(2, 1) }
+  } else if (tpw == 4) {
+    if (nvb == 2) { HYDOT_BA_K(4, 2) } else { HYDOT_BA_K(4, 1) }
+  } else if (tpw == 8) {
+    HYDOT_BA_K(8, 1)
+  } else {
+    HYDOT_BA_K(16, 1)
+  }
+#undef HYDOT_BA_K
 #undef HYDOT_BA
+#undef HYDOT_BA_E
   const double h = op->grid.h_mm;
-  hipLaunchKernelGGL((k_born_apply_finish<cplx<T>>), dim3(n_v * L), dim3(256), 0, stream, S, D, Sp, Dp, nsplit, L,
-                     (const double*)part, -h * h * h, (cplx<T>*)y);
+  hipLaunchKernelGGL((k_born_apply_finish<cplx<R>>), dim3(n_v * L), dim3(256), 0, stream, S, D, Sp, Dp, nsplit, L,
+                     (const double*)part, -h * h * h, (cplx<R>*)y);
   hipError_t e = hipGetLastError();
   hipError_t e2 = hipFreeAsync(part, stream);
   if (e != hipSuccess) return hip_check(e, "born_apply launch");
@@ -296,9 +431,10 @@ hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, c
   return HYDOT_OK;
 }
 
-template <typename T>
+template <typename TS>
 hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
                                int64_t ls, const void* w, void* g, hipStream_t stream) {
+  using R = typename Field<TS>::real;
   const int N = op->gp.N, L = op->L;
   const int Sp = pad8(S), Dp = pad8(D);
   const int TB = 2 * Dp / 16;
@@ -306,8 +442,8 @@ hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S,
   const double h = op->grid.h_mm;
   const double sc = -h * h * h;
 #define HYDOT_BJ(TBM, SQ)                                                                                   \
-  hipLaunchKernelGGL((k_born_adjoint<T, TBM, SQ>), grid, dim3(kBlock), 0, stream, N, S, D, Sp, Dp, ls, L,   \
-                     (const cplx<T>*)phs, (const cplx<T>*)phd, (const cplx<T>*)w, sc, (cplx<T>*)g)
+  hipLaunchKernelGGL((k_born_adjoint<TS, TBM, SQ>), grid, dim3(kBlock), 0, stream, N, S, D, Sp, Dp, ls, L,  \
+                     (const TS*)phs, (const TS*)phd, (const cplx<R>*)w, sc, (cplx<R>*)g)
 #define HYDOT_BJ_S(TBM) \
   if (Sp <= 16) HYDOT_BJ(TBM, 4); else if (Sp <= 32) HYDOT_BJ(TBM, 8); else HYDOT_BJ(TBM, 16);
   if (TB <= 1) { HYDOT_BJ_S(1) }
@@ -326,7 +462,8 @@ static hydot_status born_check(const hydot_operator* op, const void* phs, int S,
   if (!phs || !phd) return fail(HYDOT_EINVAL, "born: null field pointer");
   if (S < 1 || S > 64 || D < 1 || D > 64) return fail(HYDOT_EINVAL, "born: S and D must be in [1, 64]");
   if (ls < std::max(S, D)) return fail(HYDOT_EINVAL, "born: lam_stride must be >= max(S, D)");
-  if (dt != HYDOT_C128 && dt != HYDOT_C64) return fail(HYDOT_EUNSUPPORTED, "born: field_dtype must be C128 or C64");
+  if (dt != HYDOT_C128 && dt != HYDOT_C64 && dt != HYDOT_CBF16)
+    return fail(HYDOT_EUNSUPPORTED, "born: field_dtype must be C128, C64 or CBF16");
   return HYDOT_OK;
 }
 
@@ -336,15 +473,31 @@ using namespace hydot;
 
 extern "C" {
 
-hydot_status hydot_born_apply(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
-                              int32_t D, int64_t lam_stride, hydot_dtype field_dtype, const void* v, int32_t n_v,
-                              void* y, hipStream_t stream) {
+hydot_status hydot_born_apply_ex(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
+                                 int32_t D, int64_t lam_stride, hydot_dtype field_dtype, hydot_born_compute compute,
+                                 const void* v, int32_t n_v, void* y, hipStream_t stream) {
   hydot_status s = born_check(op, phi_src, S, phi_det, D, lam_stride, field_dtype);
   if (s != HYDOT_OK) return s;
   if (!v || !y) return fail(HYDOT_EINVAL, "born_apply: null v or y");
   if (n_v < 1 || n_v > 64) return fail(HYDOT_EINVAL, "born_apply: n_v must be in [1, 64]");
-  if (field_dtype == HYDOT_C128) return born_apply_impl<double>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
-  return born_apply_impl<float>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
+  if (compute != HYDOT_BORN_NATIVE && compute != HYDOT_BORN_SPLIT_BF16)
+    return fail(HYDOT_EINVAL, "born_apply: unknown compute mode");
+  if (compute == HYDOT_BORN_SPLIT_BF16 && field_dtype != HYDOT_C64)
+    return fail(HYDOT_EUNSUPPORTED, "born_apply: split-BF16 products take C64 fields");
+  if (field_dtype == HYDOT_C128)
+    return born_apply_impl<cd, CM_F64>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
+  if (field_dtype == HYDOT_CBF16)
+    return born_apply_impl<cbf, CM_BF16>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
+  if (compute == HYDOT_BORN_SPLIT_BF16)
+    return born_apply_impl<cf, CM_SPLIT>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
+  return born_apply_impl<cf, CM_F32>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
+}
+
+hydot_status hydot_born_apply(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
+                              int32_t D, int64_t lam_stride, hydot_dtype field_dtype, const void* v, int32_t n_v,
+                              void* y, hipStream_t stream) {
+  return hydot_born_apply_ex(op, phi_src, S, phi_det, D, lam_stride, field_dtype, HYDOT_BORN_NATIVE, v, n_v, y,
+                             stream);
 }
 
 hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
@@ -353,8 +506,9 @@ hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_
   hydot_status s = born_check(op, phi_src, S, phi_det, D, lam_stride, field_dtype);
   if (s != HYDOT_OK) return s;
   if (!w || !g) return fail(HYDOT_EINVAL, "born_apply_adjoint: null w or g");
-  if (field_dtype == HYDOT_C128) return born_adjoint_impl<double>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
-  return born_adjoint_impl<float>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
+  if (field_dtype == HYDOT_C128) return born_adjoint_impl<cd>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
+  if (field_dtype == HYDOT_CBF16) return born_adjoint_impl<cbf>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
+  return born_adjoint_impl<cf>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
 }
 
 hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det, int32_t D,

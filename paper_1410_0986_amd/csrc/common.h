@@ -53,6 +53,19 @@ template <> struct Store<cf> {
   __device__ static inline cd to_cd(cf a) { return cd{(double)a.re, (double)a.im}; }
 };
 
+// complex BF16 storage (re, im) of fields: written with round-to-nearest-even from
+// FP32 and widened exactly on load
+struct alignas(4) cbf {
+  uint16_t re, im;
+};
+__device__ inline uint16_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ inline float bf16_value(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+template <> struct Store<cbf> {
+  using real = float;
+  __device__ static inline cbf from(cd a) { return cbf{bf16_bits((float)a.re), bf16_bits((float)a.im)}; }
+  __device__ static inline cd to_cd(cbf a) { return cd{(double)bf16_value(a.re), (double)bf16_value(a.im)}; }
+};
+
 template <typename S>
 __device__ inline S sub(S a, S b) { return S{a.re - b.re, a.im - b.im}; }
 template <typename S>

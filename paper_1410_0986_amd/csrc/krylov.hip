@@ -286,8 +286,11 @@ struct Solver {
   hydot_status prof_collect(const int* cnt, int k) {
     const double N = (double)p.N, b = (double)p.esz;
     for (int j = 0; j < p.mk; ++j) {
+      // per system: the basis vectors read plus the vector written; per right-hand side: C, U
       const double act_k[3] = {(double)cnt[2 + j], (double)cnt[2 + j], (double)cnt[2 + kMaxMK + j]};
-      const double extra[3] = {(double)(j + 2 + k), (double)(j + 3 + k), (double)(j + 3 + k)};
+      const double rhs = (double)cnt[2 + 2 * kMaxMK + j];
+      const double rhs_k[3] = {rhs, rhs, std::min(rhs, act_k[2])};
+      const double extra[3] = {(double)(j + 2), (double)(j + 3), (double)(j + 3)};
       for (int kind = 0; kind < 3; ++kind) {
         if (kind == 2 && j + 1 >= p.mk) continue;   // no finish after the last step
         float ms = 0.f;
@@ -295,7 +298,7 @@ struct Solver {
         g_rec[kind].name = used_tiled ? kTiledNames[kind] : kGenericNames[kind];
         g_rec[kind].launches += 1;
         g_rec[kind].ms += ms;
-        g_rec[kind].bytes += act_k[kind] * N * b * extra[kind];
+        g_rec[kind].bytes += (act_k[kind] * extra[kind] + rhs_k[kind] * k) * N * b;
       }
     }
     return HYDOT_OK;
@@ -637,7 +640,9 @@ struct Solver {
           }
           HYDOT_HIP(hipGraphLaunch(gexec, stream));
         } else {
-          launch_cycle<S>(c, ra, nb, prof);
+          ReduceArgs rp = ra;
+          rp.count_rhs = prof ? 1 : 0;
+          launch_cycle<S>(c, rp, nb, prof);
         }
         HYDOT_HIP(hipGetLastError());
         if ((status = read_counters(cnt)) != HYDOT_OK) break;
@@ -652,8 +657,10 @@ struct Solver {
     // output fields and the FP64 residual of the FP64 iterate
     if (phi_dtype == HYDOT_C128)
       hipLaunchKernelGGL((k_output<cd, cd>), gv, dim3(kBlock), 0, stream, c64, (cd*)phi);
-    else
+    else if (phi_dtype == HYDOT_C64)
       hipLaunchKernelGGL((k_output<cd, cf>), gv, dim3(kBlock), 0, stream, c64, (cf*)phi);
+    else
+      hipLaunchKernelGGL((k_output<cd, cbf>), gv, dim3(kBlock), 0, stream, c64, (cbf*)phi);
     hipLaunchKernelGGL(k_outer_resid<cd>, gv, dim3(kBlock), 0, stream, c64, 1);
     hipLaunchKernelGGL(k_reduce<cd>, gr, dim3(64), 0, stream, c64, ra, (int)PH_FINAL, 0, 0);
     HYDOT_HIP(hipGetLastError());
@@ -756,7 +763,8 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
   hydot_status s = make_plan(op, n_rhs, opts, p);
   if (s != HYDOT_OK) return s;
   if (!rhs_voxel || !phi || !workspace) return fail(HYDOT_EINVAL, "solve: null pointer argument");
-  if (phi_dtype != HYDOT_C128 && phi_dtype != HYDOT_C64) return fail(HYDOT_EUNSUPPORTED, "solve: phi_dtype must be C128 or C64");
+  if (phi_dtype != HYDOT_C128 && phi_dtype != HYDOT_C64 && phi_dtype != HYDOT_CBF16)
+    return fail(HYDOT_EUNSUPPORTED, "solve: phi_dtype must be C128, C64 or CBF16");
   if (((uintptr_t)workspace & 255u) != 0) return fail(HYDOT_EINVAL, "solve: workspace must be 256-byte aligned");
   if (ws_bytes < p.total) return fail(HYDOT_ENOMEM, "solve: workspace smaller than hydot_solve_workspace_bytes");
   for (int r = 0; r < n_rhs; ++r)

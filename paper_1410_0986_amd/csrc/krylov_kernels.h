@@ -94,8 +94,8 @@ struct Ctx {
   int ndots;
   cd* small;        // [nb][sl.total]
   Small sl;
-  int* counter;     // [2 + 2 kMaxMK]: in_sweep count, in_inner count, systems stepping at step j,
-                    // systems re-orthogonalising at step j
+  int* counter;     // [2 + 3 kMaxMK]: in_sweep count, in_inner count, systems stepping at step j,
+                    // systems re-orthogonalising at step j, right-hand sides stepping at step j
 };
 
 // slots of the partial sums
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_output(Ctx<S> c, O* phi) {
     if (ch.ok[q]) out[ch.n[q]] = Store<O>::from(p.out_scale * x[ch.n[q]]);
 }
 
-constexpr int kCounters = 2 + 2 * kMaxMK;
+constexpr int kCounters = 2 + 3 * kMaxMK;
 
 __global__ void k_zero_counters(int* counter) {
   for (int i = threadIdx.x; i < kCounters; i += blockDim.x) counter[i] = 0;
@@ -608,6 +608,7 @@ struct ReduceArgs {
   double cgs_tau;      // > 0: skip the second Gram-Schmidt pass when its projection is below
                        // cgs_tau * ||w'|| (the basis is then orthogonal to working precision)
   double* final_res;   // PH_FINAL: per-system residual norms (device)
+  int count_rhs;       // PH_STEP_A: also count the distinct right-hand sides stepping (measurement)
 };
 
 // g = G^-1 f with G = L L^H (lower L, column-major k x k)
@@ -648,6 +649,22 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
     default: act = true; break;
   }
   if (!act) return;
+  if (phase == PH_STEP_A && ra.count_rhs) {
+    // count this system if it is the first stepping system of its right-hand side (the
+    // systems of one right-hand side are contiguous in a batch)
+    const int lane = threadIdx.x, r = p.rhs;
+    bool earlier = false;
+    for (int s0 = sys - 1; s0 >= 0; s0 -= 64) {
+      const int s = s0 - lane;
+      const bool same = s >= 0 && c.prm[s].rhs == r;
+      if (__any(same && c.st[s].in_cycle)) {
+        earlier = true;
+        break;
+      }
+      if (!__all(same)) break;
+    }
+    if (lane == 0 && !earlier) atomicAdd(&c.counter[2 + 2 * kMaxMK + j], 1);
+  }
   cd* sm = c.small + (size_t)sys * c.sl.total;
   const cd* part = c.part + (size_t)sys * c.nchunks * c.ndots;
   const int k = c.k;

@@ -1,0 +1,167 @@
+"""Born products from BF16 field storage, split-BF16 products, and blocks of probe vectors.
+
+BF16 operands are checked two ways: against the oracle applied to exactly the operands the
+kernel rounds to (phi_src v formed in FP32 then rounded to BF16, phi_det rounded to BF16),
+which pins the arithmetic to FP32-accumulation accuracy, and against the unrounded FP64
+oracle, which states the variant's error.  Rounding to BF16 on the host uses torch's CPU
+conversion (round to nearest even), independent of the library."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import born as oborn
+from oracle import fields as ofields
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import paper_1410_0986_amd as hd
+    return hd
+
+
+def normwise(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def to_bf16_pairs(P):
+    """complex array -> bfloat16 [..., 2] (re, im), rounded to nearest even from FP32"""
+    return torch.view_as_real(torch.from_numpy(np.ascontiguousarray(P)).to(torch.complex64)).to(torch.bfloat16)
+
+
+def from_bf16_pairs(t):
+    return torch.view_as_complex(t.float().contiguous()).numpy().astype(np.complex128)
+
+
+def bf16_round_real(x32):
+    """FP32 array -> the FP64 value of its BF16 rounding"""
+    return torch.from_numpy(np.ascontiguousarray(x32, dtype=np.float32)).to(torch.bfloat16).double().numpy()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = workloads.config("tiny")
+    return w, ofields.solve_banded(w)
+
+
+def test_solver_writes_bf16_fields(hd, tiny):
+    w, ref = tiny
+    op = hd.Operator.from_workload(w)
+    o = hd.SolveOptions(rel_tol=1e-8, restart_m=18, recycle_k=5, lanczos_n=24, precision=hd.PREC_MIXED,
+                        inner_tol=1e-5)
+    phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, out_dtype=torch.bfloat16, device=DEV)
+    assert st == hd.OK and rel.max() <= 1e-8
+    assert tuple(phi.shape) == (w.L, w.S + w.D, w.N, 2)
+    got = phi.cpu().float().numpy().astype(np.float64)
+    r = np.stack([ref.real, ref.imag], axis=-1)
+    # one rounding to BF16 of the FP64 iterate, whose error is normwise (within 1e-5 of each
+    # field's 2-norm: residual 1e-8 times the condition number of the tiny operator)
+    scale = np.linalg.norm(ref, axis=-1)[..., None, None]
+    excess = np.abs(got - r) - (2.0 ** -8 * np.abs(r) + 1e-5 * scale)
+    assert excess.max() <= 0, (excess.max(), np.unravel_index(excess.argmax(), excess.shape))
+    # round to nearest: almost every element equals the BF16 rounding of the oracle value
+    rne = torch.from_numpy(r.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    assert np.mean(got == rne) > 0.99, np.mean(got == rne)
+
+
+def _bf16_expected(Ps, Pd, v, h):
+    """oracle J v on the operands the BF16 kernel multiplies: A = bf16(fp32(phi_s) * v), B = bf16(phi_d)"""
+    Psr = Ps.real.astype(np.float32), Ps.imag.astype(np.float32)
+    A_re = bf16_round_real(Psr[0][None] * v.astype(np.float32)[:, None, None, :])
+    A_im = bf16_round_real(Psr[1][None] * v.astype(np.float32)[:, None, None, :])
+    B = bf16_round_real(Pd.real.astype(np.float32)) + 1j * bf16_round_real(Pd.imag.astype(np.float32))
+    out = []
+    for c in range(v.shape[0]):
+        A = A_re[c] + 1j * A_im[c]
+        out.append(oborn.born_apply(A, B, np.ones((1, v.shape[1])), h)[0])
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("S,D,n_v", [(4, 4, 1), (16, 16, 3), (33, 20, 2), (24, 24, 10)])
+def test_born_bf16_fields(hd, S, D, n_v):
+    w = workloads.config("tiny", nx=20, ny=13, nz=7, n_lambda=3)     # N = 1820, ragged stages
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(7 + S + D)
+    P = rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))
+    t = to_bf16_pairs(P).to(DEV)
+    Pr = from_bf16_pairs(t.cpu())                       # the stored operands, exactly
+    v = workloads.born_v(w, n_v=n_v, dtype=np.float32)
+    y = hd.born_apply(op, t[:, :S], t[:, S:], torch.from_numpy(v).to(DEV)).cpu().numpy().astype(np.complex128)
+    exp = _bf16_expected(Pr[:, :S], Pr[:, S:], v, w.h)
+    assert normwise(y, exp) < 2e-6
+    # stated error of the variant against the unrounded FP64 products
+    ref = oborn.born_apply(P[:, :S], P[:, S:], v.astype(np.float64), w.h)
+    assert normwise(y, ref) < 2e-2
+
+
+def test_born_bf16_on_solver_fields(hd, tiny):
+    w, ref = tiny
+    op = hd.Operator.from_workload(w)
+    o = hd.SolveOptions(rel_tol=1e-8, restart_m=18, recycle_k=5, lanczos_n=24, precision=hd.PREC_MIXED,
+                        inner_tol=1e-5)
+    phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, out_dtype=torch.bfloat16, device=DEV)
+    v = workloads.born_v(w, dtype=np.float32)
+    y = hd.born_apply(op, phi[:, :w.S], phi[:, w.S:], torch.from_numpy(v).to(DEV)).cpu().numpy()
+    yref = oborn.born_apply(ref[:, :w.S], ref[:, w.S:], v.astype(np.float64), w.h)
+    err = normwise(y.astype(np.complex128), yref)
+    assert err < 2e-2
+    # adjoint from BF16 fields: exact widening, FP32 products
+    wv = workloads.born_w(w)
+    g = hd.born_apply_adjoint(op, phi[:, :w.S], phi[:, w.S:], torch.from_numpy(wv).to(DEV)).cpu().numpy()
+    Pr = from_bf16_pairs(phi.cpu())
+    gexp = oborn.born_apply_adjoint(Pr[:, :w.S], Pr[:, w.S:], wv, w.h)
+    assert normwise(g.astype(np.complex128), gexp) < 1e-5
+    gref = oborn.born_apply_adjoint(ref[:, :w.S], ref[:, w.S:], wv, w.h)
+    assert normwise(g.astype(np.complex128), gref) < 2e-2
+
+
+@pytest.mark.parametrize("S,D,n_v", [(4, 4, 1), (16, 16, 2), (33, 20, 1), (64, 64, 1)])
+def test_born_split_bf16(hd, S, D, n_v):
+    w = workloads.config("tiny", nx=20, ny=13, nz=7, n_lambda=2)
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(11 + S + D)
+    P = rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))
+    t = torch.from_numpy(P).to(torch.complex64).to(DEV)
+    Pr = t.cpu().numpy().astype(np.complex128)
+    v = workloads.born_v(w, n_v=n_v, dtype=np.float32)
+    y = hd.born_apply(op, t[:, :S], t[:, S:], torch.from_numpy(v).to(DEV), split_bf16=True)
+    y = y.cpu().numpy().astype(np.complex128)
+    ref = oborn.born_apply(Pr[:, :S], Pr[:, S:], v.astype(np.float64), w.h)
+    assert normwise(y, ref) < 1e-4
+    # three BF16 products keep the error far below a single BF16 product
+    y1 = hd.born_apply(op, t[:, :S], t[:, S:], torch.from_numpy(v).to(DEV)).cpu().numpy().astype(np.complex128)
+    assert normwise(y1, ref) < 1e-5
+
+
+def test_split_bf16_rejects_other_fields(hd, tiny):
+    w, ref = tiny
+    op = hd.Operator.from_workload(w)
+    t = torch.from_numpy(ref).to(DEV)
+    v = torch.ones(w.N, dtype=torch.float64, device=DEV)
+    with pytest.raises(hd.HydotError) as e:
+        hd.born_apply(op, t[:, :w.S], t[:, w.S:], v, split_bf16=True)
+    assert e.value.status == hd.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 2e-6)])
+@pytest.mark.parametrize("S,D", [(4, 4), (16, 16), (24, 24)])
+def test_born_probe_vector_block(hd, tiny, dtype, tol, S, D):
+    """42 probe vectors (the Jacobian block of 2 contrasts + 40 shape parameters): groups of up
+    to 8 vectors share each staged field tile, with a partial last group."""
+    w = workloads.config("tiny", n_lambda=2)
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(3 + S)
+    P = rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))
+    t = torch.from_numpy(P).to(dtype).to(DEV)
+    Pr = t.cpu().numpy().astype(np.complex128)
+    rdt = torch.float64 if dtype == torch.complex128 else torch.float32
+    v = torch.from_numpy(workloads.born_v(w, n_v=42)).to(rdt)
+    y = hd.born_apply(op, t[:, :S], t[:, S:], v.to(DEV)).cpu().numpy().astype(np.complex128)
+    ref = oborn.born_apply(Pr[:, :S], Pr[:, S:], v.double().numpy(), w.h)
+    for c in range(42):
+        assert normwise(y[c], ref[c]) < tol, c
