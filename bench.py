@@ -32,6 +32,9 @@ RECYCLE_K, RESTART_M, LANCZOS_N = 5, 18, 32
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0   # dense MFMA
+N_JAC = 42                  # Jacobian block: 2 chromophore contrasts + 40 PaLS parameters
 
 # Calibrated HBM bytes per dispatch of the Arnoldi step kernels on the medium workload,
 # from the FETCH_SIZE / WRITE_SIZE runs summarised in profiles/step_kernels_medium_traffic.md.
@@ -190,6 +193,40 @@ def main():
         jhw_ms = e0.elapsed_time(e1) / reps
         log("born timing done")
 
+        # Born variants (not part of the step): FP32 / BF16-stored / split-BF16 products for one
+        # probe vector and for the Jacobian block, each against the FP64 products of the same fields
+        phi_bf = torch.empty((L, R, N, 2), dtype=torch.bfloat16, device=dev)
+        hd.solve_fields(op, vox, opts, out=phi_bf)
+        phi64 = phi.to(torch.complex128)
+        vj = torch.from_numpy(workloads.born_v(w, n_v=N_JAC, seed=2024, dtype=np.float32)).to(dev)
+
+        def timed(fn, nrep=10):
+            fn()
+            e0.record(stream)
+            for _ in range(nrep):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / nrep
+
+        variants = {}
+        for nv, vv in (("1", v), (str(N_JAC), vj)):
+            ref = hd.born_apply(op, phi64[:, :S], phi64[:, S:], vv.double())
+            cases = [("fp32", phi, False, FP32_PEAK_TFLOPS, 8), ("split_bf16", phi, True, BF16_PEAK_TFLOPS, 8),
+                     ("bf16_fields", phi_bf, False, BF16_PEAK_TFLOPS, 4)]
+            for name, f, split, peak, bpc in cases:
+                ms = timed(lambda: hd.born_apply(op, f[:, :S], f[:, S:], vv, split_bf16=split))
+                y = hd.born_apply(op, f[:, :S], f[:, S:], vv, split_bf16=split)
+                fl = 8.0 * S * D * N * L * vv.shape[0]
+                err = float(torch.linalg.vector_norm(y.to(torch.complex128) - ref) / torch.linalg.vector_norm(ref))
+                variants[f"{name}_nv{nv}"] = {
+                    "ms": round(ms, 4), "tflops": round(fl / (ms * 1e-3) / 1e12, 2),
+                    "mfma_frac": round(fl / (ms * 1e-3) / 1e12 / peak, 4), "mfma_peak_tflops": peak,
+                    "field_GBps": round((S + D) * N * L * bpc / (ms * 1e-3) / 1e9, 1),
+                    "rel_err_vs_fp64_products": float(f"{err:.3g}")}
+        del phi_bf, phi64
+        log("born variants done")
+
         plain = None
         if not args.no_plain:
             w1 = workloads.Workload(**{**w.__dict__, "src_voxels": w.src_voxels[:1],
@@ -257,6 +294,7 @@ def main():
         "born_jv_ms": round(jv_ms, 4),
         "born_jv_mfma_frac_fp32": round(jv_flops / (jv_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
         "born_adjoint_ms": round(jhw_ms, 4),
+        "born_variants": variants,
         "plain_fp64": plain,
         "speedup_vs_plain": round(solves_per_s / plain["solves_per_s"], 2) if plain else None,
         "roofline": roof,

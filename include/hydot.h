@@ -244,8 +244,9 @@ typedef struct {
 
 /* Times every candidate (step_presum x step_order x step_group) on the caller's problem: a
  * hydot_solve_fields call with the given arguments whose total inner iterations are capped at
- * two restart cycles, timed by HIP events around the Arnoldi step kernels only.  The fastest
- * candidate is stored in the operator.  phi receives the (unconverged) fields of the last trial.
+ * two restart cycles, timed by HIP events around the Arnoldi step kernels only.  Candidates are
+ * tried with the library default first; a later one replaces the best only when it is more than
+ * 1% faster (timing noise keeps the default).  The chosen candidate is stored in the operator.  phi receives the (unconverged) fields of the last trial.
  * trials: host [max_trials] or NULL; n_trials: host, number of candidates timed.
  * Synchronises the stream.  Not thread-safe (uses the process-wide instrumentation). */
 hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
@@ -254,8 +255,8 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
                                   int32_t max_trials, int32_t* n_trials, hipStream_t stream);
 
 /* Times every J v candidate (born_stage x born_blocks) on the given arguments (the median of
- * 5 calls of hydot_born_apply each) and stores the fastest in the operator; y receives the
- * product.  Arguments as hydot_born_apply; trials and n_trials as hydot_autotune_solve.
+ * 5 calls of hydot_born_apply each; default first, a later candidate must be more than 2%
+ * faster) and stores the chosen one in the operator; y receives the product.  Arguments as hydot_born_apply; trials and n_trials as hydot_autotune_solve.
  * Synchronises the stream. */
 hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
                                  int32_t D, int64_t lam_stride, hydot_dtype field_dtype, const void* v,

@@ -523,8 +523,9 @@ hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_
     (void)hipEventDestroy(e0);
     return fail(HYDOT_EDEVICE, "autotune_born: event create");
   }
-  const int stages[2] = {16, 32};
-  const int blocks[5] = {1024, 2048, 4096, 8192, 16384};
+  // default first; later candidates must be more than 2% faster to replace the best
+  const int stages[2] = {32, 16};
+  const int blocks[5] = {4096, 2048, 8192, 1024, 16384};
   int count = 0;
   double best = 1e300;
   hydot_tuning best_t = resolved_tuning(keep);
@@ -549,7 +550,7 @@ hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_
       std::sort(ms, ms + 5);
       if (count < max_trials) trials[count] = hydot_tune_trial{t, (double)ms[2]};
       ++count;
-      if (ms[2] < best) {
+      if (ms[2] < 0.98 * best) {
         best = ms[2];
         best_t = t;
       }
