@@ -72,8 +72,10 @@ def test_autotune_solve_keeps_the_fastest(hd, ragged):
     assert len(trials) == 12
     assert len({tuple(sorted(t.items())) for t, _ in trials}) == 12
     assert all(ms > 0 for _, ms in trials)
-    best = min(trials, key=lambda tm: tm[1])[0]
-    assert hd.get_tuning(op) == best
+    # the chosen candidate is one of the trials and within the 1% margin of the fastest
+    chosen = [ms for t, ms in trials if t == hd.get_tuning(op)]
+    assert len(chosen) == 1 and chosen[0] <= min(ms for _, ms in trials) / 0.99
+    assert trials[0][0]["step_presum"] == 4 and trials[0][0]["step_order"] == 1   # default tried first
     phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, mixed_opts(hd), out_dtype=torch.complex64, device=DEV)
     assert st == hd.OK and rel.max() <= 1e-8
     assert normwise(phi.cpu().numpy().astype(np.complex128), ref).max() < 1e-4
@@ -89,8 +91,8 @@ def test_autotune_born_keeps_the_fastest(hd, dtype, tol):
     v = torch.from_numpy(workloads.born_v(w, n_v=2)).to(rdt)
     trials = hd.autotune_born(op, t[:, :w.S], t[:, w.S:], v.to(DEV))
     assert len(trials) == 10
-    best = min(trials, key=lambda tm: tm[1])[0]
-    assert hd.get_tuning(op) == best
+    chosen = [ms for t, ms in trials if t == hd.get_tuning(op)]
+    assert len(chosen) == 1 and chosen[0] <= min(ms for _, ms in trials) / 0.98
     Pr = t.cpu().numpy().astype(np.complex128)
     ref = oborn.born_apply(Pr[:, :w.S], Pr[:, w.S:], v.double().numpy(), w.h)
     for stage, blocks in ((16, 256), (32, 65536), (0, 0)):
