@@ -40,8 +40,8 @@ N_JAC = 42                  # Jacobian block: 2 chromophore contrasts + 40 PaLS 
 # from the FETCH_SIZE / WRITE_SIZE runs summarised in profiles/step_kernels_medium_traffic.md.
 # They belong to the kernel sources with this SHA-256 (common.h, krylov_kernels.h,
 # krylov_tiled.h); after any change to those the traffic is reported as null.
-TRAFFIC_SOURCES_SHA256 = "bd4b2b8c300c2e6a7a99a3541136986342f41687668a15d0e94ee4af5e7abaac"
-TRAFFIC_BYTES_PER_LAUNCH = {"k_step_dots_t": 11.438e9, "k_step_update_t": 11.956e9, "k_step_finish_t": 11.768e9}
+TRAFFIC_SOURCES_SHA256 = "bedc69c90329be4e23389b1dfc32a5f7d68bfd4e67cc318cf8935ddac0cd472f"
+TRAFFIC_BYTES_PER_LAUNCH = {"k_step_dots_t": 6.704e9, "k_step_update_t": 7.049e9, "k_step_finish_t": 8.3e4}
 
 
 def kernel_sources_sha256() -> str:

@@ -224,7 +224,7 @@ hydot_status hydot_misfit(const hydot_operator* op, int32_t S, int32_t D, const 
  *                (1, 2 or 4) whose inner-product terms are summed in registers before the LDS
  *                product tile; 2 and 4 shrink the tile so more blocks fit a CU (default 4).
  *   step_order   1: blocks ordered so each XCD runs a contiguous range of (system, chunk) tiles;
- *                2: plain dispatch order (default 1).
+ *                2: plain dispatch order (default 2).
  *   step_group   1: consecutive blocks walk the wavelengths of one right-hand side at one chunk
  *                (shared recycled basis in L2); 2: no grouping (default 1).
  *   born_stage   J v voxels per LDS stage: 16 or 32 (default: 32 where the stage fits 64 KB).

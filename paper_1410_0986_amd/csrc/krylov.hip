@@ -822,7 +822,7 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
   hydot_tuning best_t = resolved_tuning(keep);
   hydot_status err = HYDOT_OK;
   for (int ig = 1; ig <= 2 && err == HYDOT_OK; ++ig)
-    for (int io = 1; io <= 2 && err == HYDOT_OK; ++io)
+    for (int io = 2; io >= 1 && err == HYDOT_OK; --io)
       for (int ip = 0; ip < 3 && err == HYDOT_OK; ++ip) {
         hydot_tuning t = resolved_tuning(keep);
         t.step_presum = presums[ip];

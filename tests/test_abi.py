@@ -180,17 +180,17 @@ def test_pals_and_misfit_validate(hd):
 def test_tuning_defaults_and_validation(hd):
     op = _op(hd, workloads.config("tiny"))
     t = hd.get_tuning(op)
-    assert t == {"step_presum": 4, "step_order": 1, "step_group": 1, "born_stage": 0, "born_blocks": 4096}
-    hd.set_tuning(op, step_presum=4, step_order=2, born_stage=16, born_blocks=1024)
+    assert t == {"step_presum": 4, "step_order": 2, "step_group": 1, "born_stage": 0, "born_blocks": 4096}
+    hd.set_tuning(op, step_presum=4, step_order=1, born_stage=16, born_blocks=1024)
     t = hd.get_tuning(op)
-    assert (t["step_presum"], t["step_order"], t["born_stage"], t["born_blocks"]) == (4, 2, 16, 1024)
+    assert (t["step_presum"], t["step_order"], t["born_stage"], t["born_blocks"]) == (4, 1, 16, 1024)
     for bad in (dict(step_presum=3), dict(step_order=3), dict(step_group=-1), dict(born_stage=64),
                 dict(born_blocks=100), dict(born_blocks=1 << 17)):
         with pytest.raises(hd.HydotError) as e:
             hd.set_tuning(op, **bad)
         assert e.value.status == hd.EINVAL
-    assert hd.get_tuning(op)["step_order"] == 2   # a rejected call changes nothing
+    assert hd.get_tuning(op)["step_order"] == 1   # a rejected call changes nothing
     hd.set_tuning(op, step_presum=1, step_order=0, born_stage=0, born_blocks=0)
-    assert hd.get_tuning(op)["step_presum"] == 1 and hd.get_tuning(op)["step_order"] == 1
+    assert hd.get_tuning(op)["step_presum"] == 1 and hd.get_tuning(op)["step_order"] == 2
     hd.set_tuning(op, step_presum=0)
     assert hd.get_tuning(op)["step_presum"] == 4
