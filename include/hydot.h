@@ -226,7 +226,7 @@ hydot_status hydot_misfit(const hydot_operator* op, int32_t S, int32_t D, const 
  *   step_order   1: blocks ordered so each XCD runs a contiguous range of (system, chunk) tiles;
  *                2: plain dispatch order (default 2).
  *   step_group   1: consecutive blocks walk the wavelengths of one right-hand side at one chunk
- *                (shared recycled basis in L2); 2: no grouping (default 1).
+ *                (shared recycled basis in L2); 2: no grouping (default 2).
  *   born_stage   J v voxels per LDS stage: 16 or 32 (default: 32 where the stage fits 64 KB).
  *   born_blocks  J v target grid size in blocks (split over voxels), 256..65536 (default 4096). */
 typedef struct {
@@ -242,11 +242,11 @@ typedef struct {
   double ms;
 } hydot_tune_trial;
 
-/* Times every candidate (step_presum x step_order x step_group) on the caller's problem: a
- * hydot_solve_fields call with the given arguments whose total inner iterations are capped at
- * two restart cycles, timed by HIP events around the Arnoldi step kernels only.  Candidates are
- * tried with the library default first; a later one replaces the best only when it is more than
- * 1% faster (timing noise keeps the default).  The chosen candidate is stored in the operator.  phi receives the (unconverged) fields of the last trial.
+/* Times every candidate (step_presum x step_order x step_group) on the caller's problem: each
+ * trial is the hydot_solve_fields call with these arguments, timed by HIP events around the
+ * Arnoldi step kernels only.  Candidates are tried with the library default first; a later one
+ * replaces the best only when it is more than 1% faster (timing noise keeps the default).  The
+ * chosen candidate is stored in the operator and phi holds the fields of the last trial.
  * trials: host [max_trials] or NULL; n_trials: host, number of candidates timed.
  * Synchronises the stream.  Not thread-safe (uses the process-wide instrumentation). */
 hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,

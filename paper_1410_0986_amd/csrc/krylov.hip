@@ -512,6 +512,26 @@ struct Solver {
     else hipLaunchKernelGGL(k_step_finish<S>, gv, dim3(kBlock), 0, stream, c, j);
   }
 
+  // Cycle start (Alg. 1 step 9) with the register-resident FP32 kernels; false if the
+  // generic kernels must run (FP64 storage or k above the tiled limit).
+  template <typename S>
+  bool cycle_start_tiled(const Ctx<S>& c, const ReduceArgs& ra, int nb) {
+    if constexpr (std::is_same<S, cf>::value) {
+      if (c.k > kTK) return false;
+      const dim3 gt((unsigned)(nb * p.nchunks)), gr(nb);
+      const hydot_tuning tu = resolved_tuning(op->tune);
+      const int fl = tu.step_order == 1 ? 1 : 0;
+      if (tu.step_presum == 4) hipLaunchKernelGGL(k_inner_resid_t<4>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
+      else if (tu.step_presum == 2) hipLaunchKernelGGL(k_inner_resid_t<2>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
+      else hipLaunchKernelGGL(k_inner_resid_t<1>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0, 1);
+      hipLaunchKernelGGL(k_defl_start_t, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0, 0);
+      return true;
+    }
+    return false;
+  }
+
   template <typename S>
   void launch_cycle(const Ctx<S>& c, const ReduceArgs& ra, int nb, bool prof) {
     dim3 gv(p.nchunks, nb), gr(nb);
@@ -519,11 +539,12 @@ struct Solver {
       if (prof) (void)hipEventRecord(ev[2 * (3 * j + kind) + edge], stream);
     };
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, stream, c.counter);
-    hipLaunchKernelGGL(k_inner_resid<S>, gv, dim3(kBlock), 0, stream, c);
-    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0, 0);
-    hipLaunchKernelGGL(k_defl_start<S>, gv, dim3(kBlock), 0, stream, c);
-    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0, 0);
-    hipLaunchKernelGGL(k_scale_v0<S>, gv, dim3(kBlock), 0, stream, c);
+    if (!cycle_start_tiled(c, ra, nb)) {
+      hipLaunchKernelGGL(k_inner_resid<S>, gv, dim3(kBlock), 0, stream, c);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0, 0);
+      hipLaunchKernelGGL(k_defl_start<S>, gv, dim3(kBlock), 0, stream, c);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0, 0);
+    }
     for (int j = 0; j < p.mk; ++j) {
       rec(j, 0, 0);
       step_kernel<S>(0, c, j, nb);
@@ -809,8 +830,9 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
                                   hipStream_t stream) {
   if (!op || !opts) return fail(HYDOT_EINVAL, "autotune_solve: null argument");
   if (max_trials < 0 || (max_trials > 0 && !trials)) return fail(HYDOT_EINVAL, "autotune_solve: bad trials buffer");
-  hydot_solve_opts o = *opts;
-  o.max_iter = 2 * std::max(o.restart_m - (o.flags & HYDOT_FLAG_NO_RECYCLE ? 0 : o.recycle_k), 1);
+  // each trial is the caller's whole solve: systems converge and drop out over the cycles,
+  // which changes which launch shape is fastest (a short sample does not show it)
+  const hydot_solve_opts o = *opts;
   const hydot_tuning keep = op->tune;
   const bool prof_keep = g_prof;
   const ProfRec rec_keep[3] = {g_rec[0], g_rec[1], g_rec[2]};
@@ -821,7 +843,7 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
   double best = 1e300;
   hydot_tuning best_t = resolved_tuning(keep);
   hydot_status err = HYDOT_OK;
-  for (int ig = 1; ig <= 2 && err == HYDOT_OK; ++ig)
+  for (int ig = 2; ig >= 1 && err == HYDOT_OK; --ig)
     for (int io = 2; io >= 1 && err == HYDOT_OK; --io)
       for (int ip = 0; ip < 3 && err == HYDOT_OK; ++ip) {
         hydot_tuning t = resolved_tuning(keep);

@@ -416,18 +416,6 @@ __global__ __launch_bounds__(kBlock) void k_defl_start(Ctx<S> c) {
   }
 }
 
-// V_0 *= 1/beta
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_scale_v0(Ctx<S> c) {
-  const int sys = blockIdx.y;
-  if (!c.st[sys].in_cycle) return;
-  const Chunk<S> ch(c.g);
-  const double inv = c.small[(size_t)sys * c.sl.total + c.sl.coefB].re;
-  S* v0 = c.V + (size_t)sys * c.vdim * c.g.N;
-#pragma unroll
-  for (int q = 0; q < kVPT; ++q)
-    if (ch.ok[q]) v0[ch.n[q]] = scale(v0[ch.n[q]], inv);
-}
 
 // Arnoldi step j, first pass: W = A_hat V_j; dots against C', V_0..V_j.
 template <typename S>
@@ -761,11 +749,10 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
       cd* gam = sm + c.sl.gam;
       for (int i = 0; i <= ra.mk; ++i) gam[i] = cd{0.0, 0.0};
       gam[0] = cd{beta, 0.0};
-      sm[c.sl.vs] = cd{1.0, 0.0};   // V_0 is normalised in place
       if (beta > 0.0 && beta > 1e-300) {
         st->in_cycle = 1;
         st->resid_est = beta;
-        sm[c.sl.coefB] = cd{1.0 / beta, 0.0};
+        sm[c.sl.vs] = cd{1.0 / beta, 0.0};   // V_0 stays unnormalised: v_0 = V_0 / beta
       } else {
         st->in_cycle = 0;
         st->resid_est = 0.0;

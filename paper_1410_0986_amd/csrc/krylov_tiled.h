@@ -227,18 +227,17 @@ __device__ inline cf project_voxel(cf w, const cf* vr, const float* cr, const fl
 struct StencilRegs {
   cf xc, m[6];
 };
-__device__ inline void gather_stencil(const GridP& g, const SysBuf& b, int j, uint32_t n, bool ok,
-                                      const VoxelInfo& vi, StencilRegs& sr) {
+__device__ inline void gather_stencil(const GridP& g, Rsrc r, uint32_t so, uint32_t n, bool ok, const VoxelInfo& vi,
+                                      StencilRegs& sr) {
   // missing neighbours read past the resource (zero)
   const uint32_t sy = (uint32_t)g.nx, sz = (uint32_t)g.nx * (uint32_t)g.ny;
-  const uint32_t so = (uint32_t)j * b.sv;
-  sr.xc = ld_cf(b.V, ok ? n * 8u : kOutside, so);
-  sr.m[0] = ld_cf(b.V, ok && vi.i > 0 ? (n - 1) * 8u : kOutside, so);
-  sr.m[1] = ld_cf(b.V, ok && vi.i < g.nx - 1 ? (n + 1) * 8u : kOutside, so);
-  sr.m[2] = ld_cf(b.V, ok && vi.j > 0 ? (n - sy) * 8u : kOutside, so);
-  sr.m[3] = ld_cf(b.V, ok && vi.j < g.ny - 1 ? (n + sy) * 8u : kOutside, so);
-  sr.m[4] = ld_cf(b.V, ok && vi.k > 0 ? (n - sz) * 8u : kOutside, so);
-  sr.m[5] = ld_cf(b.V, ok && vi.k < g.nz - 1 ? (n + sz) * 8u : kOutside, so);
+  sr.xc = ld_cf(r, ok ? n * 8u : kOutside, so);
+  sr.m[0] = ld_cf(r, ok && vi.i > 0 ? (n - 1) * 8u : kOutside, so);
+  sr.m[1] = ld_cf(r, ok && vi.i < g.nx - 1 ? (n + 1) * 8u : kOutside, so);
+  sr.m[2] = ld_cf(r, ok && vi.j > 0 ? (n - sy) * 8u : kOutside, so);
+  sr.m[3] = ld_cf(r, ok && vi.j < g.ny - 1 ? (n + sy) * 8u : kOutside, so);
+  sr.m[4] = ld_cf(r, ok && vi.k > 0 ? (n - sz) * 8u : kOutside, so);
+  sr.m[5] = ld_cf(r, ok && vi.k < g.nz - 1 ? (n + sz) * 8u : kOutside, so);
 }
 // (A_hat x)_n from gathered operands: the same arithmetic as apply_op.
 __device__ inline cf stencil_apply(const GridP& g, const StencilRegs& sr, const VoxelInfo& vi, cd sig,
@@ -328,7 +327,7 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
     load_basis<NV>(bf, ok0 ? n0 * 8u : kOutside, nv, vr);
     load_cu(bf, k, ok0 ? n0 * 4u : kOutside, cr, ur);
     vinf = voxel_info(c.g, ok0 ? n0 : 0u);
-    if (KIND == 0) gather_stencil(c.g, bf, j, n0, ok0, vinf, sreg);
+    if (KIND == 0) gather_stencil(c.g, bf.V, (uint32_t)j * bf.sv, n0, ok0, vinf, sreg);
     if (KIND == 1) wpre = ld_cf(bf.W, ok0 ? n0 * 8u : kOutside, 0u);
   }
   for (int sub = 0; sub < nsub; ++sub) {
@@ -338,7 +337,7 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
       load_basis<NV>(bf, ok ? n * 8u : kOutside, nv, vr);
       load_cu(bf, k, ok ? n * 4u : kOutside, cr, ur);
       vinf = voxel_info(c.g, ok ? n : 0u);
-      if (KIND == 0) gather_stencil(c.g, bf, j, n, ok, vinf, sreg);
+      if (KIND == 0) gather_stencil(c.g, bf.V, (uint32_t)j * bf.sv, n, ok, vinf, sreg);
       if (KIND == 1) wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
     }
     double rho = 0.0;
@@ -367,7 +366,7 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
         load_basis<NV>(bf, okn ? nn * 8u : kOutside, nv, vr);
         load_cu(bf, k, okn ? nn * 4u : kOutside, cr, ur);
         vinf = voxel_info(c.g, okn ? nn : 0u);
-        if (KIND == 0) gather_stencil(c.g, bf, j, nn, okn, vinf, sreg);
+        if (KIND == 0) gather_stencil(c.g, bf.V, (uint32_t)j * bf.sv, nn, okn, vinf, sreg);
         if (KIND == 1) wpre = ld_cf(bf.W, okn ? nn * 8u : kOutside, 0u);
       }
       __syncthreads();
@@ -441,6 +440,111 @@ __global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int g
     const double rho = (double)voxel_info(c.g, n).nrobin * c.g.inv_h;
     cf w = project_voxel<NV>(vn[n], vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
     vn[n] = cf{w.re * inv_eta, w.im * inv_eta};
+  }
+}
+
+// Cycle start, first half (tiled form of k_inner_resid): W = Rin - A_hat Din, then
+// f = C'^H W (k rows, C' formed per voxel) and |W|^2 as chunk partials.
+template <int P>
+__global__ __launch_bounds__(kTSub) void k_inner_resid_t(Ctx<cf> c, int grp, int flags) {
+  __shared__ ProdTile<P> pt;
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
+  const int sys = ti.sys;
+  if (!c.st[sys].in_inner) return;
+  const size_t N = (size_t)c.g.N;
+  const int k = c.k, t = threadIdx.x;
+  const SysParam p = c.prm[sys];
+  const SysBuf bf = sys_buf(c, sys, p.rhs);
+  const Rsrc rD = make_rsrc(c.Din + (size_t)sys * N, bf.sv), rR = make_rsrc(c.Rin + (size_t)sys * N, bf.sv);
+  cf* wv = c.W + (size_t)sys * N;
+  constexpr int nsub = kChunk / kTSub;
+  float cr[kTK], ur[kTK];
+  StencilRegs sreg;
+  VoxelInfo vinf;
+  cf rin;
+  auto fetch = [&](uint32_t n, bool ok) {
+    load_cu(bf, k, ok ? n * 4u : kOutside, cr, ur);
+    vinf = voxel_info(c.g, ok ? n : 0u);
+    gather_stencil(c.g, rD, 0u, n, ok, vinf, sreg);
+    rin = ld_cf(rR, ok ? n * 8u : kOutside, 0u);
+  };
+  cd acc{0.0, 0.0};
+  {
+    const uint32_t n0 = ti.chunk * kChunk + t;
+    fetch(n0, n0 < (uint32_t)c.g.N);
+  }
+  for (int sub = 0; sub < nsub; ++sub) {
+    const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
+    const bool ok = n < (uint32_t)c.g.N;
+    const double rho = ok ? (double)vinf.nrobin * c.g.inv_h : 0.0;
+    cf w{0.f, 0.f};
+    if (ok) {
+      const cf ad = stencil_apply(c.g, sreg, vinf, p.sig, p.sigp_abs);
+      w = cf{rin.re - ad.re, rin.im - ad.im};
+      wv[n] = w;
+    }
+    const cd shift{p.sig.re + p.sigp_rel * rho, p.sig.im};
+    write_products<1, P>(pt, 1, nullptr, cr, ur, shift, w, k, 0, true, 0);
+    if (sub + 1 < nsub) {
+      const uint32_t nn = n + kTSub;
+      fetch(nn, nn < (uint32_t)c.g.N);
+    }
+    __syncthreads();
+    row_reduce<4, P>(pt, k + 1, acc);
+    __syncthreads();
+  }
+  row_flush_all<4>(c, sys, ti.chunk, 0, k + 1, acc);
+}
+
+// Cycle start, second half (tiled form of k_defl_start): with g = G^-1 f,
+// W <- W - C'g, Din += U g, V_0 = W (stored unnormalised), |V_0|^2 as chunk partials.
+__global__ __launch_bounds__(kTSub) void k_defl_start_t(Ctx<cf> c, int grp, int flags) {
+  __shared__ double wsum[kTSub / 64];
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
+  const int sys = ti.sys;
+  if (!c.st[sys].cyc_ran) return;
+  const size_t N = (size_t)c.g.N;
+  const int k = c.k, t = threadIdx.x;
+  const SysParam p = c.prm[sys];
+  const SysBuf bf = sys_buf(c, sys, p.rhs);
+  const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefA;
+  cf g[kTK];
+#pragma unroll
+  for (int i = 0; i < kTK; ++i) g[i] = i < k ? Store<cf>::from(coef[i]) : cf{0.f, 0.f};
+  cf* wv = c.W + (size_t)sys * N;
+  cf* din = c.Din + (size_t)sys * N;
+  cf* v0 = c.V + (size_t)sys * c.vdim * N;
+  double nrm = 0.0;
+  for (int sub = 0; sub < kChunk / kTSub; ++sub) {
+    const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
+    if (n >= (uint32_t)c.g.N) break;
+    float cr[kTK], ur[kTK];
+    load_cu(bf, k, n * 4u, cr, ur);
+    const cf w0 = ld_cf(bf.W, n * 8u, 0u);
+    const double rho = (double)voxel_info(c.g, n).nrobin * c.g.inv_h;
+    float br = 0.f, bi = 0.f;   // (U g)_n
+#pragma unroll
+    for (int i = 0; i < kTK; ++i)
+      if (i < k) {
+        br += ur[i] * g[i].re;
+        bi += ur[i] * g[i].im;
+      }
+    const cf w = project_voxel<1>(w0, nullptr, cr, ur, g, nullptr, k, 0, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
+    v0[n] = w;
+    if (k > 0) {
+      const cf d = din[n];
+      din[n] = cf{d.re + br, d.im + bi};
+    }
+    nrm += (double)w.re * (double)w.re + (double)w.im * (double)w.im;
+  }
+  nrm = wave_sum(nrm);
+  if ((t & 63) == 0) wsum[t >> 6] = nrm;
+  __syncthreads();
+  if (t == 0) {
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < kTSub / 64; ++w) a += wsum[w];
+    c.part[((size_t)sys * c.nchunks + ti.chunk) * c.ndots + slot_norm(c.k, c.mkmax)] = cd{a, 0.0};
   }
 }
 

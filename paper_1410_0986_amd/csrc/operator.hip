@@ -65,7 +65,7 @@ hydot_tuning resolved_tuning(const hydot_tuning& t) {
   hydot_tuning r = t;
   if (r.step_presum == 0) r.step_presum = 4;
   if (r.step_order == 0) r.step_order = 2;
-  if (r.step_group == 0) r.step_group = 1;
+  if (r.step_group == 0) r.step_group = 2;
   if (r.born_blocks == 0) r.born_blocks = 4096;
   return r;   // born_stage 0 stays: chosen per call from the LDS footprint
 }

@@ -180,7 +180,7 @@ def test_pals_and_misfit_validate(hd):
 def test_tuning_defaults_and_validation(hd):
     op = _op(hd, workloads.config("tiny"))
     t = hd.get_tuning(op)
-    assert t == {"step_presum": 4, "step_order": 2, "step_group": 1, "born_stage": 0, "born_blocks": 4096}
+    assert t == {"step_presum": 4, "step_order": 2, "step_group": 2, "born_stage": 0, "born_blocks": 4096}
     hd.set_tuning(op, step_presum=4, step_order=1, born_stage=16, born_blocks=1024)
     t = hd.get_tuning(op)
     assert (t["step_presum"], t["step_order"], t["born_stage"], t["born_blocks"]) == (4, 1, 16, 1024)
