@@ -136,7 +136,8 @@ def main():
         solve_trials = hd.autotune_solve(op, vox, opts, out=phi)
         log(f"autotune of the step kernels done ({len(solve_trials)} candidates)")
         for t, ms in solve_trials:
-            log(f"  presum {t['step_presum']} order {t['step_order']} group {t['step_group']}: {ms:.1f} ms")
+            log(f"  presum {t['step_presum']} vx {t['step_vx']} order {t['step_order']} group {t['step_group']}: "
+                f"{ms:.1f} ms")
         # observed data of the PaLS model at the truth (set-up, not timed)
         solve()
         born_trials = hd.autotune_born(op, phi[:, :S], phi[:, S:], v)

@@ -228,10 +228,14 @@ hydot_status hydot_misfit(const hydot_operator* op, int32_t S, int32_t D, const 
  *   step_group   1: consecutive blocks walk the wavelengths of one right-hand side at one chunk
  *                (shared recycled basis in L2); 2: no grouping (default 2).
  *   born_stage   J v voxels per LDS stage: 16 or 32 (default: 32 where the stage fits 64 KB).
- *   born_blocks  J v target grid size in blocks (split over voxels), 256..65536 (default 4096). */
+ *   born_blocks  J v target grid size in blocks (split over voxels), 256..65536 (default 4096).
+ *   step_vx      Arnoldi step kernels, up to 16 basis vectors: voxels per thread per sub-tile,
+ *                1 or 2 (2 only with step_presum 4); their terms are summed in registers before
+ *                the pre-sum (default 1). */
 typedef struct {
   int32_t step_presum, step_order, step_group;
   int32_t born_stage, born_blocks;
+  int32_t step_vx;
 } hydot_tuning;
 hydot_status hydot_get_tuning(const hydot_operator* op, hydot_tuning* out);   /* resolved values */
 hydot_status hydot_set_tuning(hydot_operator* op, const hydot_tuning* t);      /* EINVAL if out of range */
@@ -242,7 +246,8 @@ typedef struct {
   double ms;
 } hydot_tune_trial;
 
-/* Times every candidate (step_presum x step_order x step_group) on the caller's problem: each
+/* Times every candidate ((step_presum, step_vx) in {(4,1), (2,1), (1,1), (4,2)} x step_order x
+ * step_group) on the caller's problem: each
  * trial is the hydot_solve_fields call with these arguments, timed by HIP events around the
  * Arnoldi step kernels only.  Candidates are tried with the library default first; a later one
  * replaces the best only when it is more than 1% faster (timing noise keeps the default).  The

@@ -84,7 +84,7 @@ _misfit = _proto("hydot_misfit", c_int32, c_void_p, c_int32, c_int32, POINTER(c_
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("step_presum", c_int32), ("step_order", c_int32), ("step_group", c_int32),
-                ("born_stage", c_int32), ("born_blocks", c_int32)]
+                ("born_stage", c_int32), ("born_blocks", c_int32), ("step_vx", c_int32)]
 
 
 class _Trial(ctypes.Structure):
@@ -97,7 +97,7 @@ _tune_solve = _proto("hydot_autotune_solve", c_int32, c_void_p, c_int32, POINTER
                      c_void_p, c_int32, c_void_p, c_size_t, POINTER(_Trial), c_int32, POINTER(c_int32), c_void_p)
 _tune_born = _proto("hydot_autotune_born", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32,
                     c_void_p, c_int32, c_void_p, POINTER(_Trial), c_int32, POINTER(c_int32), c_void_p)
-_TUNE_FIELDS = ("step_presum", "step_order", "step_group", "born_stage", "born_blocks")
+_TUNE_FIELDS = ("step_presum", "step_order", "step_group", "born_stage", "born_blocks", "step_vx")
 
 
 class _KProf(ctypes.Structure):

@@ -475,10 +475,12 @@ struct Solver {
         const hydot_tuning tu = resolved_tuning(op->tune);
         const int fl = tu.step_order == 1 ? 1 : 0;
         const bool small = j + 1 <= 16;
-#define HYDOT_STEP_T(KER, NV, P) hipLaunchKernelGGL((KER<NV, P>), gt, dim3(kTSub), 0, stream, c, j, grp, fl)
-#define HYDOT_STEP_P(KER, NV)                                   \
-  if (tu.step_presum == 4) HYDOT_STEP_T(KER, NV, 4);            \
-  else if (tu.step_presum == 2) HYDOT_STEP_T(KER, NV, 2);       \
+#define HYDOT_STEP_T(KER, NV, P) hipLaunchKernelGGL((KER<NV, P, 1>), gt, dim3(kTSub), 0, stream, c, j, grp, fl)
+#define HYDOT_STEP_P(KER, NV)                                                                           \
+  if (tu.step_presum == 4 && tu.step_vx == 2 && NV <= 16)                                               \
+    hipLaunchKernelGGL((KER<NV, 4, (NV <= 16 ? 2 : 1)>), gt, dim3(kTSub), 0, stream, c, j, grp, fl);   \
+  else if (tu.step_presum == 4) HYDOT_STEP_T(KER, NV, 4);                                               \
+  else if (tu.step_presum == 2) HYDOT_STEP_T(KER, NV, 2);                                               \
   else HYDOT_STEP_T(KER, NV, 1);
 // exact basis-count instances for j + 1 <= 16
 #define HYDOT_STEP_NV(KER)                                                                               \
@@ -838,16 +840,17 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
   const ProfRec rec_keep[3] = {g_rec[0], g_rec[1], g_rec[2]};
   // candidates in order of preference (library default first); a later candidate replaces the
   // best only when it is more than 1% faster, so timing noise keeps the earlier choice
-  const int presums[3] = {4, 2, 1};
+  const int presums[4] = {4, 2, 1, 4}, vxs[4] = {1, 1, 1, 2};
   int count = 0;
   double best = 1e300;
   hydot_tuning best_t = resolved_tuning(keep);
   hydot_status err = HYDOT_OK;
   for (int ig = 2; ig >= 1 && err == HYDOT_OK; --ig)
     for (int io = 2; io >= 1 && err == HYDOT_OK; --io)
-      for (int ip = 0; ip < 3 && err == HYDOT_OK; ++ip) {
+      for (int ip = 0; ip < 4 && err == HYDOT_OK; ++ip) {
         hydot_tuning t = resolved_tuning(keep);
         t.step_presum = presums[ip];
+        t.step_vx = vxs[ip];
         t.step_order = io;
         t.step_group = ig;
         op->tune = t;

@@ -393,21 +393,140 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
   }
 }
 
+// Products of VX voxels per thread, summed in registers before the lane pre-sum:
+// rows [0, nv) conj(V_l) w, rows nv + i conj(C'_i) w, row nv + k |w|^2 (with_norm).
+template <int NV, int P, int VX>
+__device__ inline void write_products_x(ProdTile<P>& pt, const cf (*vr)[NV], const float (*cr)[kTK],
+                                        const float (*ur)[kTK], const cd* shift, const cf* w, int k, int nv,
+                                        bool with_norm) {
+#pragma unroll
+  for (int l = 0; l < NV; ++l)
+    if (l < nv) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int x = 0; x < VX; ++x) {
+        const cf v = vr[x][l];
+        re += v.re * w[x].re + v.im * w[x].im;
+        im += v.re * w[x].im - v.im * w[x].re;
+      }
+      put_product<P>(pt, l, cf{re, im});
+    }
+#pragma unroll
+  for (int i = 0; i < kTK; ++i)
+    if (i < k) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int x = 0; x < VX; ++x) {
+        const float ar = cr[x][i] + (float)shift[x].re * ur[x][i], ai = -(float)shift[x].im * ur[x][i];
+        re += ar * w[x].re - ai * w[x].im;
+        im += ar * w[x].im + ai * w[x].re;
+      }
+      put_product<P>(pt, nv + i, cf{re, im});
+    }
+  if (with_norm) {
+    float a = 0.f;
+#pragma unroll
+    for (int x = 0; x < VX; ++x) a += w[x].re * w[x].re + w[x].im * w[x].im;
+    put_product<P>(pt, nv + k, cf{a, 0.f});
+  }
+}
+
+// Single-round body of the dots (kind 0) and update (kind 1) kernels for exactly NV <= 16
+// basis vectors, VX voxels per thread per sub-tile (sub-tile = VX * kTSub voxels, the
+// thread's voxels kTSub apart so each load stays coalesced).  The next sub-tile's
+// loads are issued before this sub-tile's barriers and row sums.
+template <int NV, int KIND, int P, int VX>
+__device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
+  static_assert(NV <= 16, "single-round instances hold at most 16 basis vectors");
+  __shared__ ProdTile<P> pt;
+  const int sys = ti.sys;
+  const size_t N = (size_t)c.g.N;
+  const int k = c.k, nv = NV, t = threadIdx.x;
+  const SysParam p = c.prm[sys];
+  cf* wv = c.W + (size_t)sys * N;
+  cf g[kTK], h[NV];
+  if (KIND == 1) {
+    const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefA;
+#pragma unroll
+    for (int i = 0; i < kTK; ++i) g[i] = i < k ? Store<cf>::from(coef[i]) : cf{0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l < NV; ++l) h[l] = Store<cf>::from(coef[k + l]);
+  }
+  const bool with_norm = KIND == 1;
+  const int nrows = nv + k + (with_norm ? 1 : 0);
+  constexpr int kSub = kTSub * VX, nsub = kChunk / kSub;
+  static_assert(kChunk % kSub == 0, "chunk must hold whole sub-tiles");
+  const SysBuf bf = sys_buf(c, sys, p.rhs);
+  cf* vnext = c.V + ((size_t)sys * c.vdim + j + 1) * N;   // the update stores w' as V_{j+1}
+  const float sj = KIND == 0 ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
+  cf vr[VX][NV];
+  float cr[VX][kTK], ur[VX][kTK];
+  cf wpre[VX];
+  StencilRegs sreg[VX];
+  VoxelInfo vinf[VX];
+  auto fetch = [&](uint32_t base) {
+#pragma unroll
+    for (int x = 0; x < VX; ++x) {
+      const uint32_t n = base + x * kTSub + t;
+      const bool ok = n < (uint32_t)c.g.N;
+      load_basis<NV>(bf, ok ? n * 8u : kOutside, nv, vr[x]);
+      load_cu(bf, k, ok ? n * 4u : kOutside, cr[x], ur[x]);
+      vinf[x] = voxel_info(c.g, ok ? n : 0u);
+      if (KIND == 0) gather_stencil(c.g, bf.V, (uint32_t)j * bf.sv, n, ok, vinf[x], sreg[x]);
+      if (KIND == 1) wpre[x] = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
+    }
+  };
+  cd acc{0.0, 0.0};
+  fetch(ti.chunk * kChunk);
+  for (int sub = 0; sub < nsub; ++sub) {
+    const uint32_t base = ti.chunk * kChunk + sub * kSub;
+    cf w[VX];
+    cd shift[VX];
+#pragma unroll
+    for (int x = 0; x < VX; ++x) {
+      const uint32_t n = base + x * kTSub + t;
+      const bool ok = n < (uint32_t)c.g.N;
+      const double rho = ok ? (double)vinf[x].nrobin * c.g.inv_h : 0.0;
+      shift[x] = cd{p.sig.re + p.sigp_rel * rho, p.sig.im};
+      w[x] = cf{0.f, 0.f};
+      if (ok) {
+        if (KIND == 0) {
+          w[x] = stencil_apply(c.g, sreg[x], vinf[x], p.sig, p.sigp_abs);
+          w[x].re *= sj;   // v_j = sj * stored V_j
+          w[x].im *= sj;
+          wv[n] = w[x];
+        } else {
+          w[x] = project_voxel<NV>(wpre[x], vr[x], cr[x], ur[x], g, h, k, nv, shift[x]);
+          vnext[n] = w[x];
+        }
+      }
+    }
+    write_products_x<NV, P, VX>(pt, vr, cr, ur, shift, w, k, nv, with_norm);
+    if (sub + 1 < nsub) fetch(base + kSub);
+    __syncthreads();
+    row_reduce<4, P>(pt, nrows, acc);
+    __syncthreads();
+  }
+  row_flush_all<4>(c, sys, ti.chunk, nv, nrows, acc);
+}
+
 // W = A_hat V_j and first-pass inner products (tiled form of k_step_dots).
-// flags bit 0: XCD-contiguous block order.
-template <int NV, int P>
+// flags bit 0: XCD-contiguous block order.  VX voxels per thread per sub-tile (NV <= 16).
+template <int NV, int P, int VX>
 __global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp, int flags) {
   const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
   if (!c.st[ti.sys].in_cycle) return;
-  tiled_step<NV, 0, P>(c, j, ti);
+  if constexpr (NV <= 16) tiled_step_x<NV, 0, P, VX>(c, j, ti);
+  else tiled_step<NV, 0, P>(c, j, ti);
 }
 
-// CGS2 first projection + second-pass inner products (tiled form of k_step_update).
-template <int NV, int P>
+// First projection (w' stored as V_{j+1}) + second-pass inner products (tiled form of k_step_update).
+template <int NV, int P, int VX>
 __global__ __launch_bounds__(kTSub) void k_step_update_t(Ctx<cf> c, int j, int grp, int flags) {
   const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
   if (!c.st[ti.sys].in_cycle) return;
-  tiled_step<NV, 1, P>(c, j, ti);
+  if constexpr (NV <= 16) tiled_step_x<NV, 1, P, VX>(c, j, ti);
+  else tiled_step<NV, 1, P>(c, j, ti);
 }
 
 // Second projection and normalisation in place of V_{j+1}, for the systems whose

@@ -18,7 +18,7 @@ struct hydot_operator {
   std::vector<hydot::cd> sigma;   // [L] (mu_a + i omega/nu)/D
   std::vector<double> sigp;       // [L] 1/(2 A_R D)
   double sigp_mean = 0.0;         // mean of sigma' over wavelengths
-  hydot_tuning tune{0, 0, 0, 0, 0};  // launch shapes; 0 = library default
+  hydot_tuning tune{0, 0, 0, 0, 0, 0};  // launch shapes; 0 = library default
 };
 
 namespace hydot {

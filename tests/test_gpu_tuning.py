@@ -38,11 +38,13 @@ def mixed_opts(hd):
                            inner_tol=1e-5, flags=hd.FLAG_MEAN_SHIFT | hd.FLAG_GRAPH)
 
 
-@pytest.mark.parametrize("presum,order,group", list(itertools.product((1, 2, 4), (1, 2), (1, 2))))
-def test_every_step_variant_meets_tolerance(hd, ragged, presum, order, group):
+@pytest.mark.parametrize("presum,vx,order,group",
+                         [(p, 1, o, g) for p, o, g in itertools.product((1, 2, 4), (1, 2), (1, 2))] +
+                         [(4, 2, o, g) for o, g in itertools.product((1, 2), (1, 2))])
+def test_every_step_variant_meets_tolerance(hd, ragged, presum, vx, order, group):
     w, ref = ragged
     op = hd.Operator.from_workload(w)
-    hd.set_tuning(op, step_presum=presum, step_order=order, step_group=group)
+    hd.set_tuning(op, step_presum=presum, step_vx=vx, step_order=order, step_group=group)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, mixed_opts(hd), out_dtype=torch.complex64, device=DEV)
@@ -58,8 +60,8 @@ def test_variant_with_basis_beyond_16_vectors(hd, ragged):
     op = hd.Operator.from_workload(w)
     o = hd.SolveOptions(rel_tol=1e-8, restart_m=30, recycle_k=0, lanczos_n=0, precision=hd.PREC_MIXED,
                         inner_tol=1e-5, flags=hd.FLAG_NO_RECYCLE)
-    for presum in (1, 2, 4):
-        hd.set_tuning(op, step_presum=presum)
+    for presum, vx in ((1, 1), (2, 1), (4, 1), (4, 2)):
+        hd.set_tuning(op, step_presum=presum, step_vx=vx)
         phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, out_dtype=torch.complex64, device=DEV)
         assert st == hd.OK and rel.max() <= 1e-8 and it.max() > 16
         assert normwise(phi.cpu().numpy().astype(np.complex128), ref).max() < 1e-4
@@ -69,13 +71,14 @@ def test_autotune_solve_keeps_the_fastest(hd, ragged):
     w, ref = ragged
     op = hd.Operator.from_workload(w)
     trials = hd.autotune_solve(op, w.rhs_voxels, mixed_opts(hd))
-    assert len(trials) == 12
-    assert len({tuple(sorted(t.items())) for t, _ in trials}) == 12
+    assert len(trials) == 16
+    assert len({tuple(sorted(t.items())) for t, _ in trials}) == 16
     assert all(ms > 0 for _, ms in trials)
     # the chosen candidate is one of the trials and within the 1% margin of the fastest
     chosen = [ms for t, ms in trials if t == hd.get_tuning(op)]
     assert len(chosen) == 1 and chosen[0] <= min(ms for _, ms in trials) / 0.99
-    assert trials[0][0] == {**hd.get_tuning(op), "step_presum": 4, "step_order": 2, "step_group": 2}  # default first
+    assert trials[0][0] == {**hd.get_tuning(op), "step_presum": 4, "step_order": 2, "step_group": 2,
+                            "step_vx": 1}  # default first
     phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, mixed_opts(hd), out_dtype=torch.complex64, device=DEV)
     assert st == hd.OK and rel.max() <= 1e-8
     assert normwise(phi.cpu().numpy().astype(np.complex128), ref).max() < 1e-4
