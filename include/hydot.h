@@ -127,6 +127,17 @@ hydot_status hydot_operator_optics(const hydot_operator* op, double* D_out, doub
 hydot_status hydot_apply_operator(const hydot_operator* op, int32_t n_vec, const int32_t* lam_index,
                                   const void* x, void* y, hydot_dtype dtype, hipStream_t stream);
 
+/* Heterogeneous absorption (Sec. 2.1 diffusion equation with mu_a varying in space; eq.
+ * perturbation): mu_a(k, lambda_l) = mu_a(lambda_l) + scale[l] * shape[k], so A(lambda_l) gains
+ * h^3 diag(scale_l shape) -- the full forward model the Born approximation linearises.  Every
+ * later hydot_apply_operator and hydot_solve_fields call on this operator includes it; the
+ * recycled solver still applies (the perturbation is one more per-wavelength diagonal shift; its
+ * mean over wavelengths joins K_hat with HYDOT_FLAG_MEAN_SHIFT).  The Born calls do not use it.
+ * shape: host [N] (e.g. a PaLS shape), scale: host [n_lambda] in mm^-1 (ebar_l = sum over species
+ * of eps(lambda_l) dconc).  shape = NULL clears the perturbation.  The operator keeps device
+ * copies of the shape (FP64 and FP32), freed with the operator.  Synchronous. */
+hydot_status hydot_set_absorption_perturbation(hydot_operator* op, const double* shape, const double* scale);
+
 /* Bytes of device workspace hydot_solve_fields needs for n_rhs right-hand sides. */
 hydot_status hydot_solve_workspace_bytes(const hydot_operator* op, int32_t n_rhs,
                                          const hydot_solve_opts* opts, size_t* bytes);

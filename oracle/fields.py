@@ -8,6 +8,8 @@ oracle uses the plain definition and several independent routes to it:
 
 * ``solve_dense``     - LU of the assembled matrix (small grids);
 * ``solve_banded``    - banded LU with the largest axis slowest;
+  both also take ``pert = (shape, scale)``, the heterogeneous absorption
+  mu_a(k) + scale_j shape(k) of the full (nonlinear) forward model;
 * ``solve_separable`` - fast diagonalisation of the homogeneous box
                         (Lynch, Rice and Thomas 1964): exact at any size, and
                         ``separable_at`` evaluates single points cheaply;
@@ -33,14 +35,19 @@ def _lams(w, lam_idx):
     return range(w.L) if lam_idx is None else list(lam_idx)
 
 
-def solve_dense(w, voxels=None, lam_idx=None) -> np.ndarray:
+def _op(w, j, pert):
+    """A(lambda_j), or its heterogeneous-absorption form for pert = (shape, scale)."""
+    return model.operator(w, j) if pert is None else model.operator_perturbed(w, j, *pert)
+
+
+def solve_dense(w, voxels=None, lam_idx=None, pert=None) -> np.ndarray:
     vox = _rhs_list(w, voxels)
     lams = _lams(w, lam_idx)
     out = np.empty((len(lams), len(vox), w.N), dtype=np.complex128)
     Bm = np.zeros((w.N, len(vox)), dtype=np.complex128)
     Bm[vox, np.arange(len(vox))] = 1.0
     for a, j in enumerate(lams):
-        A = model.operator(w, j).toarray()
+        A = _op(w, j, pert).toarray()
         out[a] = np.linalg.solve(A, Bm).T
     return out
 
@@ -57,7 +64,7 @@ def _band_permutation(w):
     return new, bw
 
 
-def solve_banded(w, voxels=None, lam_idx=None) -> np.ndarray:
+def solve_banded(w, voxels=None, lam_idx=None, pert=None) -> np.ndarray:
     vox = _rhs_list(w, voxels)
     lams = _lams(w, lam_idx)
     new, bw = _band_permutation(w)
@@ -65,7 +72,7 @@ def solve_banded(w, voxels=None, lam_idx=None) -> np.ndarray:
     Bm = np.zeros((w.N, len(vox)), dtype=np.complex128)
     Bm[new[vox], np.arange(len(vox))] = 1.0
     for a, j in enumerate(lams):
-        A = model.operator(w, j).tocoo()
+        A = _op(w, j, pert).tocoo()
         r, c = new[A.row], new[A.col]
         ab = np.zeros((2 * bw + 1, w.N), dtype=np.complex128)
         ab[bw + r - c, c] = A.data

@@ -122,6 +122,14 @@ def operator(w, lam_idx: int) -> sp.csr_matrix:
     return (D[lam_idx] * K + B / (2.0 * w.A_R) + (s[lam_idx] * w.h ** 3) * I).astype(np.complex128).tocsr()
 
 
+def operator_perturbed(w, lam_idx: int, shape, scale) -> sp.csr_matrix:
+    """A(lambda_j) for the heterogeneous absorption mu_a(k) = mu_a(lambda_j) + scale_j * shape(k)
+    (Sec. 2.1 diffusion equation with mu_a varying in space; eq. perturbation): the absorption
+    term integrated over each voxel adds h^3 * scale_j * shape(k) to the diagonal."""
+    extra = w.h ** 3 * float(scale[lam_idx]) * np.asarray(shape, dtype=np.float64)
+    return (operator(w, lam_idx) + sp.diags(extra.astype(np.complex128), 0)).tocsr()
+
+
 def rhs(w, voxel: int) -> np.ndarray:
     """Unit injection into one voxel (S = S0 delta(r - r_s) with S0 = 1)."""
     b = np.zeros(w.N, dtype=np.complex128)
@@ -136,8 +144,9 @@ def voxel_centres(w) -> np.ndarray:
                      (k.reshape(-1) + 0.5) * w.h], axis=1)
 
 
-def relative_residual(w, lam_idx: int, voxel: int, phi: np.ndarray) -> float:
-    """||b - A phi||_2 / ||b||_2 of the unscaled system."""
-    A = operator(w, lam_idx)
+def relative_residual(w, lam_idx: int, voxel: int, phi: np.ndarray, pert=None) -> float:
+    """||b - A phi||_2 / ||b||_2 of the unscaled system (pert = (shape, scale) for the
+    heterogeneous operator)."""
+    A = operator(w, lam_idx) if pert is None else operator_perturbed(w, lam_idx, *pert)
     b = rhs(w, voxel)
     return float(np.linalg.norm(b - A @ phi) / np.linalg.norm(b))

@@ -61,6 +61,7 @@ def _proto(name, restype, *argtypes):
 _assemble = _proto("hydot_assemble_operator", c_int32, POINTER(_Grid), POINTER(_Optics), POINTER(c_void_p))
 _free = _proto("hydot_free_operator", None, c_void_p)
 _optics = _proto("hydot_operator_optics", c_int32, c_void_p, POINTER(c_double), POINTER(c_double))
+_set_pert = _proto("hydot_set_absorption_perturbation", c_int32, c_void_p, POINTER(c_double), POINTER(c_double))
 _apply = _proto("hydot_apply_operator", c_int32, c_void_p, c_int32, POINTER(c_int32), c_void_p, c_void_p,
                 c_int32, c_void_p)
 _ws_bytes = _proto("hydot_solve_workspace_bytes", c_int32, c_void_p, c_int32, POINTER(_SolveOpts), POINTER(c_size_t))
@@ -218,6 +219,18 @@ class Operator:
         mua = np.empty(self.L)
         _check(_optics(self._h, _dptr(D), _dptr(mua)))
         return D, mua
+
+    def set_absorption_perturbation(self, shape, scale) -> None:
+        """mu_a(k, lambda_l) += scale[l] * shape[k] in every later solve and operator apply
+        (hydot_set_absorption_perturbation); shape=None clears it."""
+        if shape is None:
+            _check(_set_pert(self.handle, None, None))
+            return
+        sh = np.ascontiguousarray(shape, dtype=np.float64).reshape(-1)
+        sc = np.ascontiguousarray(scale, dtype=np.float64).reshape(-1)
+        if sh.shape[0] != self.N or sc.shape[0] != self.L:
+            raise ValueError("shape must have N entries and scale n_lambda entries")
+        _check(_set_pert(self.handle, _dptr(sh), _dptr(sc)))
 
     def __del__(self):
         h = getattr(self, "_h", None)

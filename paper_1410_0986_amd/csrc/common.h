@@ -168,10 +168,11 @@ __host__ __device__ inline VoxelInfo voxel_info(const GridP& g, uint32_t n) {
   return v;
 }
 
-// (A_hat x)_n for a system with shift sig (complex) and absolute Robin shift sigp.
+// (A_hat x)_n for a system with shift sig (complex), absolute Robin shift sigp and an
+// extra real diagonal term at this voxel (the absorption perturbation, 0 without one).
 template <typename S>
 __device__ inline S apply_op(const GridP& g, const S* __restrict__ x, uint32_t n,
-                             const VoxelInfo& vi, cd sig, double sigp) {
+                             const VoxelInfo& vi, cd sig, double sigp, double extra = 0.0) {
   using R = typename Store<S>::real;
   const S xc = x[n];
   R ar = 0, ai = 0;   // sum over neighbours of (x_n - x_m)
@@ -186,7 +187,7 @@ __device__ inline S apply_op(const GridP& g, const S* __restrict__ x, uint32_t n
   const R diag_k = (R)(nn + 2 * vi.ndir);
   const R ih2 = (R)g.inv_h2;
   // diagonal shift: sigma + sigp * rho
-  const R dr = (R)(sig.re + sigp * (double)vi.nrobin * g.inv_h);
+  const R dr = (R)(sig.re + sigp * (double)vi.nrobin * g.inv_h + extra);
   const R di = (R)sig.im;
   S y;
   y.re = ih2 * (diag_k * xc.re + ar) + (dr * xc.re - di * xc.im);

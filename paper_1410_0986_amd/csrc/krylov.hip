@@ -52,12 +52,13 @@ __global__ __launch_bounds__(kBlock) void k_combine_uc(GridP g, const VT* VL, in
 
 // Partial Gram sums of X = [C_0..C_{k-1}, U_0.., rho U_0..] per (chunk, rhs):
 // out[r][chunk][p] for pairs p = (a <= b) in row-major upper-triangle order.
-__global__ __launch_bounds__(kBlock) void k_gram(GridP g, const double* U64, const double* C64, int k,
-                                                int rhs_off, double* part, int nchunks) {
+// Gram of [C, U, rho U] (ng = 3) or [C, U, rho U, mu U] (ng = 4, absorption perturbation mu)
+__global__ __launch_bounds__(kBlock) void k_gram(GridP g, const double* U64, const double* C64, int k, int ng,
+                                                const double* mu, int rhs_off, double* part, int nchunks) {
   const int r = blockIdx.y + rhs_off;
   const int chunk = blockIdx.x;
   const size_t N = (size_t)g.N;
-  const int m = 3 * k;
+  const int m = ng * k;
   const int npairs = m * (m + 1) / 2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t base = chunk * kChunk;
@@ -77,12 +78,14 @@ __global__ __launch_bounds__(kBlock) void k_gram(GridP g, const double* U64, con
         const double* src = t == 0 ? C64 : U64;
         va = src[((size_t)r * k + i) * N + n];
         if (t == 2) va *= (double)voxel_info(g, n).nrobin * g.inv_h;
+        if (t == 3) va *= mu[n];
       }
       {
         const int t = b / k, i = b % k;
         const double* src = t == 0 ? C64 : U64;
         vb = src[((size_t)r * k + i) * N + n];
         if (t == 2) vb *= (double)voxel_info(g, n).nrobin * g.inv_h;
+        if (t == 3) vb *= mu[n];
       }
       acc += va * vb;
     }
@@ -126,6 +129,7 @@ struct Plan {
   int rl;       // right-hand sides per Lanczos batch (and in the U/C buffers)
   int nchunks, ndots;
   int npairs;
+  int ng;       // Gram vector blocks: 3 ([C, U, rho U]) or 4 (+ mu U with an absorption perturbation)
   Small sl;
   size_t esz;   // inner storage bytes per complex
   // byte offsets
@@ -175,7 +179,8 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   if (p.nb > 65535 || p.rl > 65535) return fail(HYDOT_EINVAL, "solve: batch above 65535 systems; set max_batch");
   p.nchunks = (p.N + kChunk - 1) / kChunk;
   p.ndots = 3 * p.k + p.mkmax + 2;
-  p.npairs = 3 * p.k * (3 * p.k + 1) / 2;
+  p.ng = op->has_pert ? 4 : 3;
+  p.npairs = p.ng * p.k * (p.ng * p.k + 1) / 2;
   p.sl = make_small(p.k, p.mkmax, p.nl);
   p.esz = p.prec == HYDOT_PREC_FP64 ? sizeof(cd) : sizeof(cf);
   const size_t N = (size_t)p.N;
@@ -226,6 +231,8 @@ struct Solver {
   template <typename T> T* at(size_t off) const { return (T*)(ws + off); }
 
   double sigp_mean() const { return p.mean_shift ? op->sigp_mean : 0.0; }
+  // part of the absorption perturbation moved into K_hat (its mean, with the mean shift)
+  double tau_shift() const { return p.mean_shift && op->has_pert ? op->tau_mean : 0.0; }
 
   template <typename S>
   Ctx<S> ctx(int k, bool lanczos) const {
@@ -251,6 +258,7 @@ struct Solver {
       c.C = (const R*)at<float>(p.o_C32);
       c.U = (const R*)at<float>(p.o_U32);
     }
+    c.mu = op->has_pert ? (sizeof(R) == sizeof(double) ? (const R*)op->mu64 : (const R*)op->mu32) : nullptr;
     c.part = at<cd>(p.o_part);
     c.ndots = p.ndots;
     c.small = at<cd>(p.o_small);
@@ -314,6 +322,8 @@ struct Solver {
     lc.vdim = p.nl + 1;
     lc.ndots = p.ndots;
     lc.sigp = sigp_mean();
+    lc.tau = tau_shift();
+    lc.mu = op->has_pert ? (sizeof(T) == sizeof(double) ? (const T*)op->mu64 : (const T*)op->mu32) : nullptr;
     lc.prm = c.prm;
     lc.st = c.st;
     lc.V = at<T>(p.o_VL);
@@ -326,9 +336,9 @@ struct Solver {
     hipLaunchKernelGGL(k_lz_v0<T>, gv, dim3(kBlock), 0, stream, lc, c.small);
     for (int j = 0; j < p.nl; ++j) {
       hipLaunchKernelGGL(k_lz_dots<T>, gv, dim3(kBlock), 0, stream, lc, j);
-      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j, 0);
+      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j);
       hipLaunchKernelGGL(k_lz_update<T>, gv, dim3(kBlock), 0, stream, lc, j);
-      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j, 0);
+      hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j);
       hipLaunchKernelGGL(k_lz_finish<T>, gv, dim3(kBlock), 0, stream, lc, j);
     }
   }
@@ -346,6 +356,8 @@ struct Solver {
       q.sig = cd{0.0, 0.0};
       q.sigp_abs = sigp_mean();
       q.sigp_rel = 0.0;
+      q.tau_abs = tau_shift();
+      q.tau_rel = 0.0;
       q.rhs = i;
       q.voxel = (int32_t)rhs_vox[r0 + i];
       std::memset(&st[i], 0, sizeof(SysState));
@@ -423,7 +435,7 @@ struct Solver {
 #undef HYDOT_UC_T
 #undef HYDOT_UC
     hipLaunchKernelGGL(k_gram, dim3(p.nchunks, nr), dim3(kBlock), 0, stream, op->gp, at<double>(p.o_U64),
-                       at<double>(p.o_C64), k, buf_off, at<double>(p.o_gpart), p.nchunks);
+                       at<double>(p.o_C64), k, p.ng, (const double*)(op->has_pert ? op->mu64 : nullptr), buf_off, at<double>(p.o_gpart), p.nchunks);
     hipLaunchKernelGGL(k_gram_reduce, dim3(nr), dim3(256), 0, stream, at<double>(p.o_gpart), p.nchunks, p.npairs, nr,
                        at<double>(p.o_gram));
     HYDOT_HIP(hipGetLastError());
@@ -437,8 +449,8 @@ struct Solver {
   // Per-wavelength deflation basis (Alg. 1 steps 7-8 with the Gram update of Sec. 3.2):
   // G_j = C_j'^H C_j' from the Gram of [C, U, rho U] with weights (1, sigma, sigma'_rel);
   // returns its lower Cholesky factor.
-  hydot_status gram_factor(int r, cd sig, double sp, std::vector<dense::zc>& Lf) {
-    const int k = p.k, m = 3 * k;
+  hydot_status gram_factor(int r, cd sig, double sp, double tr, std::vector<dense::zc>& Lf) {
+    const int k = p.k, m = p.ng * k;
     const std::vector<double>& gm = rs[r].gram;
     auto gam = [&](int a, int b) -> double {
       if (a > b) std::swap(a, b);
@@ -446,13 +458,14 @@ struct Solver {
       const int idx = a * m - a * (a - 1) / 2 + (b - a);
       return gm[idx];
     };
-    const dense::zc w[3] = {dense::zc(1.0, 0.0), dense::zc(sig.re, sig.im), dense::zc(sp, 0.0)};
+    // C' = C + sigma U + sigma'_rel (rho U) + tau_rel (mu U)
+    const dense::zc w[4] = {dense::zc(1.0, 0.0), dense::zc(sig.re, sig.im), dense::zc(sp, 0.0), dense::zc(tr, 0.0)};
     std::vector<dense::zc> G((size_t)k * k);
     for (int j = 0; j < k; ++j)
       for (int i = 0; i < k; ++i) {
         dense::zc s(0.0, 0.0);
-        for (int t = 0; t < 3; ++t)
-          for (int u = 0; u < 3; ++u) s += std::conj(w[t]) * w[u] * gam(t * k + i, u * k + j);
+        for (int t = 0; t < p.ng; ++t)
+          for (int u = 0; u < p.ng; ++u) s += std::conj(w[t]) * w[u] * gam(t * k + i, u * k + j);
         G[i + (size_t)k * j] = s;
       }
     if (!dense::chol_herm(k, G, Lf))
@@ -526,9 +539,9 @@ struct Solver {
       if (tu.step_presum == 4) hipLaunchKernelGGL(k_inner_resid_t<4>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
       else if (tu.step_presum == 2) hipLaunchKernelGGL(k_inner_resid_t<2>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
       else hipLaunchKernelGGL(k_inner_resid_t<1>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
-      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0, 1);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0);
       hipLaunchKernelGGL(k_defl_start_t, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
-      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0, 0);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0);
       return true;
     }
     return false;
@@ -543,26 +556,26 @@ struct Solver {
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, stream, c.counter);
     if (!cycle_start_tiled(c, ra, nb)) {
       hipLaunchKernelGGL(k_inner_resid<S>, gv, dim3(kBlock), 0, stream, c);
-      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0, 0);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0);
       hipLaunchKernelGGL(k_defl_start<S>, gv, dim3(kBlock), 0, stream, c);
-      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0, 0);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0);
     }
     for (int j = 0; j < p.mk; ++j) {
       rec(j, 0, 0);
       step_kernel<S>(0, c, j, nb);
       rec(j, 0, 1);
-      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j, used_tiled ? 1 : 0);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j);
       rec(j, 1, 0);
       step_kernel<S>(1, c, j, nb);
       rec(j, 1, 1);
-      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j, used_tiled ? 1 : 0);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j);
       if (j + 1 < p.mk) {
         rec(j, 2, 0);
         step_kernel<S>(2, c, j, nb);
         rec(j, 2, 1);
       }
     }
-    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_CYCLE_END, 0, 0);
+    hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_CYCLE_END, 0);
     hipLaunchKernelGGL(k_cycle_update<S>, gv, dim3(kBlock), 0, stream, c);
   }
 
@@ -584,6 +597,8 @@ struct Solver {
       q.sig = op->sigma[l];
       q.sigp_abs = op->sigp[l];
       q.sigp_rel = op->sigp[l] - sigp_mean();
+      q.tau_abs = op->has_pert ? op->tau[l] : 0.0;
+      q.tau_rel = q.tau_abs - tau_shift();
       q.out_scale = 1.0 / (op->D[l] * h3);
       q.rhs = r - buf_rhs_base;
       q.voxel = (int32_t)rhs_vox[r];
@@ -594,7 +609,7 @@ struct Solver {
       cd* dst = lcy.data() + (size_t)i * lc_len;
       if (p.k > 0) {
         std::vector<dense::zc> Lf;
-        hydot_status s = gram_factor(r, q.sig, q.sigp_rel, Lf);
+        hydot_status s = gram_factor(r, q.sig, q.sigp_rel, q.tau_rel, Lf);
         if (s != HYDOT_OK) return s;
         for (int t = 0; t < p.k * p.k; ++t) dst[t] = cd{Lf[t].real(), Lf[t].imag()};
       }
@@ -648,7 +663,7 @@ struct Solver {
     for (int sweep = 0; sweep < ra.max_sweeps + 2 && status == HYDOT_OK; ++sweep) {
       hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, stream, c.counter);
       hipLaunchKernelGGL(k_outer_resid<S>, gv, dim3(kBlock), 0, stream, c, 0);
-      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_OUTER, 0, 0);
+      hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_OUTER, 0);
       HYDOT_HIP(hipGetLastError());
       if ((status = read_counters(cnt)) != HYDOT_OK) break;
       if (cnt[0] == 0) break;
@@ -685,7 +700,7 @@ struct Solver {
     else
       hipLaunchKernelGGL((k_output<cd, cbf>), gv, dim3(kBlock), 0, stream, c64, (cbf*)phi);
     hipLaunchKernelGGL(k_outer_resid<cd>, gv, dim3(kBlock), 0, stream, c64, 1);
-    hipLaunchKernelGGL(k_reduce<cd>, gr, dim3(64), 0, stream, c64, ra, (int)PH_FINAL, 0, 0);
+    hipLaunchKernelGGL(k_reduce<cd>, gr, dim3(64), 0, stream, c64, ra, (int)PH_FINAL, 0);
     HYDOT_HIP(hipGetLastError());
     std::vector<SysState> so(nb);
     std::vector<double> fr(nb);

@@ -25,6 +25,8 @@ struct SysParam {
   double sigp_abs;   // sigma'_j (Robin shift in the operator)
   double sigp_rel;   // sigma'_j - mean sigma' (Robin shift relative to K_hat = K + mean R)
   double out_scale;  // 1/(D_j h^3): phi = x * out_scale
+  double tau_abs;    // absorption-perturbation weight in the operator (0 without one)
+  double tau_rel;    // tau_abs minus the part included in K_hat
   int32_t rhs;       // index of the right-hand side in the U/C buffers
   int32_t voxel;     // injection voxel
   int32_t lam;       // wavelength index
@@ -88,6 +90,7 @@ struct Ctx {
   S* Rin;           // [nb][N] inner right-hand side
   cd* X;            // [nb][N] FP64 iterate
   cd* Rout;         // [nb][N] FP64 residual
+  const R* mu;      // [N] absorption-perturbation shape, or null
   const R* C;       // [n_rhs][k][N]
   const R* U;       // [n_rhs][k][N]
   cd* part;         // [nb][nchunks][ndots]
@@ -132,30 +135,31 @@ struct Chunk {
   }
 };
 
-// Deflation dots [C^T w, U^T w, (rho U)^T w] and basis dots V_l^H w for l < nv,
-// plus optionally ||w||^2, written as this chunk's partial sums.
+// Deflation dots f_i = C'_i^H w with C'_i = C_i + (sigma + xs) U_i formed per voxel (xs the
+// voxel's relative real shift), basis dots V_l^H w for l < nv, and optionally ||w||^2,
+// written as this chunk's partial sums.
 template <typename S>
 __device__ inline void chunk_dots(const Ctx<S>& c, int sys, const Chunk<S>& ch, const S* w,
-                                  const double* rho, const S* Vsys, int nv, bool with_norm,
+                                  const double* xs, const S* Vsys, int nv, bool with_norm,
                                   cd* lds) {
   const size_t N = (size_t)c.g.N;
   if (c.k > 0) {
     const int r = c.prm[sys].rhs;
+    const cd sig = c.prm[sys].sig;
     for (int i = 0; i < c.k; ++i) {
       const auto* Ci = c.C + ((size_t)r * c.k + i) * N;
       const auto* Ui = c.U + ((size_t)r * c.k + i) * N;
-      cd ac{0, 0}, au{0, 0}, ar{0, 0};
+      cd a{0, 0};
 #pragma unroll
       for (int q = 0; q < kVPT; ++q) {
         if (!ch.ok[q]) continue;
         const double cv = (double)Ci[ch.n[q]], uv = (double)Ui[ch.n[q]];
-        rdot_acc(ac, cv, w[q]);
-        rdot_acc(au, uv, w[q]);
-        rdot_acc(ar, uv * rho[q], w[q]);
+        const double ar = cv + (sig.re + xs[q]) * uv, ai = -sig.im * uv;   // conj(C'_i) at this voxel
+        const double wr = (double)w[q].re, wi = (double)w[q].im;
+        a.re += ar * wr - ai * wi;
+        a.im += ar * wi + ai * wr;
       }
-      wave_store(ac, slot_defl(i, 0), lds);
-      wave_store(au, slot_defl(i, 1), lds);
-      wave_store(ar, slot_defl(i, 2), lds);
+      wave_store(a, slot_defl(i, 0), lds);
     }
   }
   for (int l = 0; l < nv; ++l) {
@@ -175,23 +179,27 @@ __device__ inline void chunk_dots(const Ctx<S>& c, int sys, const Chunk<S>& ch, 
   }
   __syncthreads();
   cd* out = c.part + ((size_t)sys * c.nchunks + blockIdx.x) * c.ndots;
-  if (c.k > 0) block_flush(lds, 0, 3 * c.k, out);
+  for (int i = threadIdx.x; i < c.k; i += kBlock) {
+    cd a{0.0, 0.0};
+#pragma unroll
+    for (int wv = 0; wv < kWaves; ++wv) a = a + lds[wv * kMaxDots + slot_defl(i, 0)];
+    out[slot_defl(i, 0)] = a;
+  }
   block_flush(lds, slot_v(c.k, 0), slot_v(c.k, nv), out);
   if (with_norm) block_flush(lds, slot_norm(c.k, c.mkmax), slot_norm(c.k, c.mkmax) + 1, out);
 }
 
-// w <- w - C' g - sum_l V_l h_l, where C' g = C g + (sigma + sigma'_rel rho) U g and
+// w <- w - C' g - sum_l V_l h_l, where C' g = C g + (sigma + xs) U g per voxel and
 // (optionally) acc_u += U g.  coef = [g (k), h (nv)] in FP64.
 template <typename S>
 __device__ inline void chunk_project(const Ctx<S>& c, int sys, const Chunk<S>& ch, S* w,
-                                     const double* rho, const S* Vsys, int nv, const cd* coef,
+                                     const double* xs, const S* Vsys, int nv, const cd* coef,
                                      S* ug) {
   using R = typename Store<S>::real;
   const size_t N = (size_t)c.g.N;
   if (c.k > 0) {
     const int r = c.prm[sys].rhs;
     const cd sig = c.prm[sys].sig;
-    const double sp = c.prm[sys].sigp_rel;
     S a[kVPT], b[kVPT];
 #pragma unroll
     for (int q = 0; q < kVPT; ++q) {
@@ -215,7 +223,7 @@ __device__ inline void chunk_project(const Ctx<S>& c, int sys, const Chunk<S>& c
     }
 #pragma unroll
     for (int q = 0; q < kVPT; ++q) {
-      const cd shift{sig.re + sp * rho[q], sig.im};
+      const cd shift{sig.re + xs[q], sig.im};
       // w -= a + shift * b
       w[q] = sub(w[q], a[q]);
       w[q] = axpy_neg(w[q], shift, b[q]);
@@ -231,13 +239,14 @@ __device__ inline void chunk_project(const Ctx<S>& c, int sys, const Chunk<S>& c
   }
 }
 
+// relative real shift of each voxel of the chunk: sigma'_rel rho + tau_rel mu
 template <typename S>
-__device__ inline void load_rho(const GridP& g, const Chunk<S>& ch, double* rho) {
+__device__ inline void load_xs(const Ctx<S>& c, const SysParam& p, const Chunk<S>& ch, double* xs) {
 #pragma unroll
   for (int q = 0; q < kVPT; ++q) {
-    if (!ch.ok[q]) { rho[q] = 0.0; continue; }
-    const VoxelInfo vi = voxel_info(g, ch.n[q]);
-    rho[q] = (double)vi.nrobin * g.inv_h;
+    if (!ch.ok[q]) { xs[q] = 0.0; continue; }
+    const VoxelInfo vi = voxel_info(c.g, ch.n[q]);
+    xs[q] = p.sigp_rel * (double)vi.nrobin * c.g.inv_h + (c.mu ? p.tau_rel * (double)c.mu[ch.n[q]] : 0.0);
   }
 }
 
@@ -316,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_resid(Ctx<S> c, int force) {
   for (int q = 0; q < kVPT; ++q) {
     if (!ch.ok[q]) continue;
     const VoxelInfo vi = voxel_info(c.g, ch.n[q]);
-    cd ax = apply_op<cd>(c.g, x, ch.n[q], vi, p.sig, p.sigp_abs);
+    cd ax = apply_op<cd>(c.g, x, ch.n[q], vi, p.sig, p.sigp_abs, c.mu ? p.tau_abs * (double)c.mu[ch.n[q]] : 0.0);
     cd rr{-ax.re, -ax.im};
     if (ch.n[q] == (uint32_t)p.voxel) rr.re += 1.0;
     r[ch.n[q]] = rr;
@@ -363,19 +372,20 @@ __global__ __launch_bounds__(kBlock) void k_inner_resid(Ctx<S> c) {
   const S* ri = c.Rin + (size_t)sys * N;
   S* wv = c.W + (size_t)sys * N;
   S w[kVPT];
-  double rho[kVPT];
+  double xs[kVPT];
 #pragma unroll
   for (int q = 0; q < kVPT; ++q) {
-    rho[q] = 0.0;
+    xs[q] = 0.0;
     w[q] = Store<S>::zero();
     if (!ch.ok[q]) continue;
     const VoxelInfo vi = voxel_info(c.g, ch.n[q]);
-    rho[q] = (double)vi.nrobin * c.g.inv_h;
-    const S ad = apply_op<S>(c.g, d, ch.n[q], vi, p.sig, p.sigp_abs);
+    const double mu = c.mu ? (double)c.mu[ch.n[q]] : 0.0;
+    xs[q] = p.sigp_rel * (double)vi.nrobin * c.g.inv_h + p.tau_rel * mu;
+    const S ad = apply_op<S>(c.g, d, ch.n[q], vi, p.sig, p.sigp_abs, p.tau_abs * mu);
     w[q] = sub(ri[ch.n[q]], ad);
     wv[ch.n[q]] = w[q];
   }
-  chunk_dots<S>(c, sys, ch, w, rho, nullptr, 0, true, lds);
+  chunk_dots<S>(c, sys, ch, w, xs, nullptr, 0, true, lds);
 }
 
 // Initial deflation (Alg. 1 step 9): Din += U g, W -= C' g, V_0 = W; ||V_0||^2.
@@ -391,14 +401,14 @@ __global__ __launch_bounds__(kBlock) void k_defl_start(Ctx<S> c) {
   S* d = c.Din + (size_t)sys * N;
   S* v0 = c.V + (size_t)sys * c.vdim * N;
   S w[kVPT], ug[kVPT];
-  double rho[kVPT];
-  load_rho<S>(c.g, ch, rho);
+  double xs[kVPT];
+  load_xs<S>(c, c.prm[sys], ch, xs);
 #pragma unroll
   for (int q = 0; q < kVPT; ++q) {
     w[q] = ch.ok[q] ? wv[ch.n[q]] : Store<S>::zero();
     ug[q] = Store<S>::zero();
   }
-  chunk_project<S>(c, sys, ch, w, rho, nullptr, 0, coef, ug);
+  chunk_project<S>(c, sys, ch, w, xs, nullptr, 0, coef, ug);
   double a = 0.0;
 #pragma unroll
   for (int q = 0; q < kVPT; ++q) {
@@ -431,18 +441,19 @@ __global__ __launch_bounds__(kBlock) void k_step_dots(Ctx<S> c, int j) {
   S* wv = c.W + (size_t)sys * N;
   const double sj = c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re;   // v_j = sj * stored V_j
   S w[kVPT];
-  double rho[kVPT];
+  double xs[kVPT];
 #pragma unroll
   for (int q = 0; q < kVPT; ++q) {
-    rho[q] = 0.0;
+    xs[q] = 0.0;
     w[q] = Store<S>::zero();
     if (!ch.ok[q]) continue;
     const VoxelInfo vi = voxel_info(c.g, ch.n[q]);
-    rho[q] = (double)vi.nrobin * c.g.inv_h;
-    w[q] = scale(apply_op<S>(c.g, vj, ch.n[q], vi, p.sig, p.sigp_abs), sj);
+    const double mu = c.mu ? (double)c.mu[ch.n[q]] : 0.0;
+    xs[q] = p.sigp_rel * (double)vi.nrobin * c.g.inv_h + p.tau_rel * mu;
+    w[q] = scale(apply_op<S>(c.g, vj, ch.n[q], vi, p.sig, p.sigp_abs, p.tau_abs * mu), sj);
     wv[ch.n[q]] = w[q];
   }
-  chunk_dots<S>(c, sys, ch, w, rho, Vsys, j + 1, false, lds);
+  chunk_dots<S>(c, sys, ch, w, xs, Vsys, j + 1, false, lds);
 }
 
 // Arnoldi step j, first projection and second-pass dots (CGS2); w' is stored as V_{j+1}.
@@ -457,16 +468,16 @@ __global__ __launch_bounds__(kBlock) void k_step_update(Ctx<S> c, int j) {
   const S* wv = c.W + (size_t)sys * N;
   const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefA;
   S w[kVPT];
-  double rho[kVPT];
-  load_rho<S>(c.g, ch, rho);
+  double xs[kVPT];
+  load_xs<S>(c, c.prm[sys], ch, xs);
 #pragma unroll
   for (int q = 0; q < kVPT; ++q) w[q] = ch.ok[q] ? wv[ch.n[q]] : Store<S>::zero();
-  chunk_project<S>(c, sys, ch, w, rho, Vsys, j + 1, coef, nullptr);
+  chunk_project<S>(c, sys, ch, w, xs, Vsys, j + 1, coef, nullptr);
   S* vn = c.V + ((size_t)sys * c.vdim + j + 1) * N;   // w' becomes V_{j+1} (scaled or re-orthogonalised later)
 #pragma unroll
   for (int q = 0; q < kVPT; ++q)
     if (ch.ok[q]) vn[ch.n[q]] = w[q];
-  chunk_dots<S>(c, sys, ch, w, rho, Vsys, j + 1, true, lds);
+  chunk_dots<S>(c, sys, ch, w, xs, Vsys, j + 1, true, lds);
 }
 
 // Arnoldi step j, second projection and normalisation, for the systems whose
@@ -482,11 +493,11 @@ __global__ __launch_bounds__(kBlock) void k_step_finish(Ctx<S> c, int j) {
   const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefB;
   const double inv_eta = coef[c.k + c.mkmax + 1].re;
   S w[kVPT];
-  double rho[kVPT];
-  load_rho<S>(c.g, ch, rho);
+  double xs[kVPT];
+  load_xs<S>(c, c.prm[sys], ch, xs);
 #pragma unroll
   for (int q = 0; q < kVPT; ++q) w[q] = ch.ok[q] ? vn[ch.n[q]] : Store<S>::zero();
-  chunk_project<S>(c, sys, ch, w, rho, Vsys, j + 1, coef, nullptr);
+  chunk_project<S>(c, sys, ch, w, xs, Vsys, j + 1, coef, nullptr);
 #pragma unroll
   for (int q = 0; q < kVPT; ++q)
     if (ch.ok[q]) vn[ch.n[q]] = scale(w[q], inv_eta);
@@ -615,11 +626,9 @@ __device__ inline void gsolve(int k, const cd* L, const cd* f, cd* g) {
   }
 }
 
-// fdirect: the deflation partials of this phase hold f_i = C'_i^H w directly in
-// slot_defl(i, 0) (register-resident FP32 kernels) instead of the three real
-// products C_i^T w, U_i^T w, (rho U_i)^T w.
+// The deflation partials hold f_i = C'_i^H w in slot_defl(i, 0).
 template <typename S>
-__global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phase, int j, int fdirect) {
+__global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phase, int j) {
   __shared__ cd sum[kMaxDots];
   __shared__ cd tmp[2 * kMaxK + kMaxMK + 4];
   const int sys = blockIdx.x;
@@ -668,7 +677,7 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
   }
   const int sn = slot_norm(k, c.mkmax);
   for (int s = threadIdx.x; s < c.ndots; s += 64) {
-    const bool want = (need_defl && s < 3 * k && (!fdirect || s % 3 == 0)) || (s >= lo && s < hi) ||
+    const bool want = (need_defl && s < 3 * k && s % 3 == 0) || (s >= lo && s < hi) ||
                       (need_norm && s == sn);
     cd a{0.0, 0.0};
     if (want)
@@ -678,20 +687,10 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
   __syncthreads();
   if (threadIdx.x != 0) return;
 
-  const cd sig = p.sig;
-  const double spr = p.sigp_rel;
   cd* f = tmp;            // k
   cd* g = tmp + kMaxK;    // k
-  // f_i = C_i^T w + conj(sigma) U_i^T w + sigma'_rel (rho U_i)^T w   (= C'^H w)
-  auto make_f = [&]() {
-    for (int i = 0; i < k; ++i) {
-      if (fdirect) {
-        f[i] = sum[slot_defl(i, 0)];
-      } else {
-        const cd cw = sum[slot_defl(i, 0)], uw = sum[slot_defl(i, 1)], rw = sum[slot_defl(i, 2)];
-        f[i] = cw + conj(sig) * uw + spr * rw;
-      }
-    }
+  auto make_f = [&]() {   // f = C'^H w
+    for (int i = 0; i < k; ++i) f[i] = sum[slot_defl(i, 0)];
   };
   const cd* Lc = sm + c.sl.Lc;
 

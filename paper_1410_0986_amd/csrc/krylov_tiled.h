@@ -162,8 +162,9 @@ __device__ inline float ld_f(Rsrc r, uint32_t vo, uint32_t so) {
 }
 
 struct SysBuf {
-  Rsrc V, C, U, W;
-  uint32_t sv, sc;   // bytes between basis vectors, between C (U) vectors
+  Rsrc V, C, U, W, M;   // M: absorption-perturbation shape (no records without one)
+  uint32_t sv, sc;      // bytes between basis vectors, between C (U) vectors
+  bool pert;
 };
 __device__ inline SysBuf sys_buf(const Ctx<cf>& c, int sys, int rhs) {
   const uint32_t N = (uint32_t)c.g.N;
@@ -174,7 +175,15 @@ __device__ inline SysBuf sys_buf(const Ctx<cf>& c, int sys, int rhs) {
   b.C = make_rsrc(c.C + (size_t)rhs * c.k * N, (uint32_t)c.k * b.sc);
   b.U = make_rsrc(c.U + (size_t)rhs * c.k * N, (uint32_t)c.k * b.sc);
   b.W = make_rsrc(c.W + (size_t)sys * N, b.sv);
+  b.pert = c.mu != nullptr;
+  b.M = make_rsrc(c.mu, b.pert ? N * 4u : 0u);
   return b;
+}
+// shape value of voxel byte offset vo4 (0 without a perturbation)
+__device__ inline float mu_at(const SysBuf& b, uint32_t vo4) { return b.pert ? ld_f(b.M, vo4, 0u) : 0.f; }
+// per-voxel shift of C'_j: sigma + sigma'_rel rho + tau_rel mu
+__device__ inline cd voxel_shift(const SysParam& p, double rho, float mu) {
+  return cd{p.sig.re + p.sigp_rel * rho + p.tau_rel * (double)mu, p.sig.im};
 }
 
 template <int NV>
@@ -241,7 +250,7 @@ __device__ inline void gather_stencil(const GridP& g, Rsrc r, uint32_t so, uint3
 }
 // (A_hat x)_n from gathered operands: the same arithmetic as apply_op.
 __device__ inline cf stencil_apply(const GridP& g, const StencilRegs& sr, const VoxelInfo& vi, cd sig,
-                                   double sigp) {
+                                   double sigp, double extra) {
   const int nn = 6 - (vi.i == 0) - (vi.i == g.nx - 1) - (vi.j == 0) - (vi.j == g.ny - 1) - (vi.k == 0) -
                  (vi.k == g.nz - 1);
   float ar = 0.f, ai = 0.f;
@@ -252,7 +261,7 @@ __device__ inline cf stencil_apply(const GridP& g, const StencilRegs& sr, const 
   }
   const float diag_k = (float)(nn + 2 * vi.ndir);
   const float ih2 = (float)g.inv_h2;
-  const float dr = (float)(sig.re + sigp * (double)vi.nrobin * g.inv_h);
+  const float dr = (float)(sig.re + sigp * (double)vi.nrobin * g.inv_h + extra);
   const float di = (float)sig.im;
   const cf xc = sr.xc;
   return cf{ih2 * (diag_k * xc.re + ar) + (dr * xc.re - di * xc.im),
@@ -341,21 +350,23 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
       if (KIND == 1) wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
     }
     double rho = 0.0;
+    float muv = 0.f;
     cf w{0.f, 0.f};
     if (ok) {
       const VoxelInfo vi = vinf;
       rho = (double)vi.nrobin * c.g.inv_h;
+      muv = mu_at(bf, n * 4u);
       if (KIND == 0) {
-        w = stencil_apply(c.g, sreg, vi, p.sig, p.sigp_abs);
+        w = stencil_apply(c.g, sreg, vi, p.sig, p.sigp_abs, p.tau_abs * (double)muv);
         w.re *= sj;   // v_j = sj * stored V_j
         w.im *= sj;
       } else {
-        w = project_voxel<NV>(wpre, vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
+        w = project_voxel<NV>(wpre, vr, cr, ur, g, h, k, nv, voxel_shift(p, rho, muv));
       }
       if (KIND == 0) wv[n] = w;
       else vnext[n] = w;
     }
-    const cd shift{p.sig.re + p.sigp_rel * rho, p.sig.im};
+    const cd shift = voxel_shift(p, rho, muv);
     if constexpr (NV <= 16) {
       // one round: V rows, then the deflation rows and the norm row below them
       write_products<NV, P>(pt, 0, vr, cr, ur, shift, w, k, nv, with_norm);
@@ -464,6 +475,7 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
   cf wpre[VX];
   StencilRegs sreg[VX];
   VoxelInfo vinf[VX];
+  float muv[VX];
   auto fetch = [&](uint32_t base) {
 #pragma unroll
     for (int x = 0; x < VX; ++x) {
@@ -472,6 +484,7 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
       load_basis<NV>(bf, ok ? n * 8u : kOutside, nv, vr[x]);
       load_cu(bf, k, ok ? n * 4u : kOutside, cr[x], ur[x]);
       vinf[x] = voxel_info(c.g, ok ? n : 0u);
+      muv[x] = mu_at(bf, ok ? n * 4u : kOutside);
       if (KIND == 0) gather_stencil(c.g, bf.V, (uint32_t)j * bf.sv, n, ok, vinf[x], sreg[x]);
       if (KIND == 1) wpre[x] = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
     }
@@ -487,11 +500,11 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
       const uint32_t n = base + x * kTSub + t;
       const bool ok = n < (uint32_t)c.g.N;
       const double rho = ok ? (double)vinf[x].nrobin * c.g.inv_h : 0.0;
-      shift[x] = cd{p.sig.re + p.sigp_rel * rho, p.sig.im};
+      shift[x] = voxel_shift(p, rho, muv[x]);
       w[x] = cf{0.f, 0.f};
       if (ok) {
         if (KIND == 0) {
-          w[x] = stencil_apply(c.g, sreg[x], vinf[x], p.sig, p.sigp_abs);
+          w[x] = stencil_apply(c.g, sreg[x], vinf[x], p.sig, p.sigp_abs, p.tau_abs * (double)muv[x]);
           w[x].re *= sj;   // v_j = sj * stored V_j
           w[x].im *= sj;
           wv[n] = w[x];
@@ -557,7 +570,7 @@ __global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int g
     load_basis<NV>(bf, n * 8u, nv, vr);
     load_cu(bf, k, n * 4u, cr, ur);
     const double rho = (double)voxel_info(c.g, n).nrobin * c.g.inv_h;
-    cf w = project_voxel<NV>(vn[n], vr, cr, ur, g, h, k, nv, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
+    cf w = project_voxel<NV>(vn[n], vr, cr, ur, g, h, k, nv, voxel_shift(p, rho, mu_at(bf, n * 4u)));
     vn[n] = cf{w.re * inv_eta, w.im * inv_eta};
   }
 }
@@ -581,9 +594,11 @@ __global__ __launch_bounds__(kTSub) void k_inner_resid_t(Ctx<cf> c, int grp, int
   StencilRegs sreg;
   VoxelInfo vinf;
   cf rin;
+  float muv = 0.f;
   auto fetch = [&](uint32_t n, bool ok) {
     load_cu(bf, k, ok ? n * 4u : kOutside, cr, ur);
     vinf = voxel_info(c.g, ok ? n : 0u);
+    muv = mu_at(bf, ok ? n * 4u : kOutside);
     gather_stencil(c.g, rD, 0u, n, ok, vinf, sreg);
     rin = ld_cf(rR, ok ? n * 8u : kOutside, 0u);
   };
@@ -598,11 +613,11 @@ __global__ __launch_bounds__(kTSub) void k_inner_resid_t(Ctx<cf> c, int grp, int
     const double rho = ok ? (double)vinf.nrobin * c.g.inv_h : 0.0;
     cf w{0.f, 0.f};
     if (ok) {
-      const cf ad = stencil_apply(c.g, sreg, vinf, p.sig, p.sigp_abs);
+      const cf ad = stencil_apply(c.g, sreg, vinf, p.sig, p.sigp_abs, p.tau_abs * (double)muv);
       w = cf{rin.re - ad.re, rin.im - ad.im};
       wv[n] = w;
     }
-    const cd shift{p.sig.re + p.sigp_rel * rho, p.sig.im};
+    const cd shift = voxel_shift(p, rho, muv);
     write_products<1, P>(pt, 1, nullptr, cr, ur, shift, w, k, 0, true, 0);
     if (sub + 1 < nsub) {
       const uint32_t nn = n + kTSub;
@@ -648,7 +663,7 @@ __global__ __launch_bounds__(kTSub) void k_defl_start_t(Ctx<cf> c, int grp, int 
         br += ur[i] * g[i].re;
         bi += ur[i] * g[i].im;
       }
-    const cf w = project_voxel<1>(w0, nullptr, cr, ur, g, nullptr, k, 0, cd{p.sig.re + p.sigp_rel * rho, p.sig.im});
+    const cf w = project_voxel<1>(w0, nullptr, cr, ur, g, nullptr, k, 0, voxel_shift(p, rho, mu_at(bf, n * 4u)));
     v0[n] = w;
     if (k > 0) {
       const cf d = din[n];

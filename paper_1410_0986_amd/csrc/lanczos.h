@@ -16,6 +16,8 @@ struct LzCtx {
   GridP g;
   int nchunks, vdim, ndots;
   double sigp;          // Robin shift of K_hat (absolute)
+  double tau;           // absorption-perturbation weight in K_hat (its mean over wavelengths)
+  const T* mu;          // [N] perturbation shape, or null
   const SysParam* prm;  // injection voxel
   const SysState* st;
   T* V;                 // [nr][vdim][N]
@@ -26,10 +28,10 @@ struct LzCtx {
   int mkmax;
 };
 
-// (K_hat x)_n, real: the stencil of apply_op with sigma = 0
+// (K_hat x)_n, real: the stencil of apply_op with sigma = 0 and an extra real diagonal term
 template <typename T>
 __device__ inline double lz_apply(const GridP& g, const T* __restrict__ x, uint32_t n, const VoxelInfo& vi,
-                                  double sigp) {
+                                  double sigp, double extra) {
   const double xc = (double)x[n];
   double a = 0.0;
   int nn = 0;
@@ -40,7 +42,7 @@ __device__ inline double lz_apply(const GridP& g, const T* __restrict__ x, uint3
   if (vi.j < g.ny - 1) { a -= (double)x[n + sy]; ++nn; }
   if (vi.k > 0) { a -= (double)x[n - sz]; ++nn; }
   if (vi.k < g.nz - 1) { a -= (double)x[n + sz]; ++nn; }
-  return g.inv_h2 * ((double)(nn + 2 * vi.ndir) * xc + a) + sigp * (double)vi.nrobin * g.inv_h * xc;
+  return g.inv_h2 * ((double)(nn + 2 * vi.ndir) * xc + a) + (sigp * (double)vi.nrobin * g.inv_h + extra) * xc;
 }
 
 // per-wave FP64 sums of slots [0, ns) to LDS, then per-block partials to part
@@ -95,7 +97,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_dots(LzCtx<T> c, int j) {
     w[q] = (T)0;
     if (!ch.ok[q]) continue;
     const VoxelInfo vi = voxel_info(c.g, ch.n[q]);
-    w[q] = (T)(sj * lz_apply<T>(c.g, Vs + (size_t)j * N, ch.n[q], vi, c.sigp));
+    const double extra = c.mu ? c.tau * (double)c.mu[ch.n[q]] : 0.0;
+    w[q] = (T)(sj * lz_apply<T>(c.g, Vs + (size_t)j * N, ch.n[q], vi, c.sigp, extra));
     wv[ch.n[q]] = w[q];
   }
   for (int l = 0; l <= j; ++l) {

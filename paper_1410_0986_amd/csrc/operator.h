@@ -18,6 +18,14 @@ struct hydot_operator {
   std::vector<hydot::cd> sigma;   // [L] (mu_a + i omega/nu)/D
   std::vector<double> sigp;       // [L] 1/(2 A_R D)
   double sigp_mean = 0.0;         // mean of sigma' over wavelengths
+  // absorption perturbation dmua_l(k) = scale_l * shape(k): tau_l = scale_l / D_l enters the
+  // scaled operator as tau_l * diag(shape); device copies of the shape in FP64 and FP32
+  bool has_pert = false;
+  std::vector<double> tau;        // [L]
+  double tau_mean = 0.0;
+  double* mu64 = nullptr;         // device [N]
+  float* mu32 = nullptr;          // device [N]
+  ~hydot_operator();
   hydot_tuning tune{0, 0, 0, 0, 0, 0};  // launch shapes; 0 = library default
 };
 

@@ -46,18 +46,19 @@ struct ApplyParams {
   cd sig[kApplyBatch];
   double sigp[kApplyBatch];
   double scl[kApplyBatch];
+  double tau[kApplyBatch];   // absorption perturbation weight (0 without one)
 };
 
 // y = scl * A_hat x with A_hat = A(lambda)/(D h^3); scl = D h^3 gives A x.
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_apply_op(GridP g, const S* __restrict__ x, S* __restrict__ y,
-                                                    ApplyParams prm) {
+                                                    ApplyParams prm, const double* __restrict__ mu) {
   const int v = blockIdx.y;
   const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= (uint32_t)g.N) return;
   const S* xv = x + (size_t)v * g.N;
   const VoxelInfo vi = voxel_info(g, n);
-  const S a = apply_op<S>(g, xv, n, vi, prm.sig[v], prm.sigp[v]);
+  const S a = apply_op<S>(g, xv, n, vi, prm.sig[v], prm.sigp[v], mu ? prm.tau[v] * mu[n] : 0.0);
   y[(size_t)v * g.N + n] = scale(a, prm.scl[v]);
 }
 
@@ -72,6 +73,11 @@ hydot_tuning resolved_tuning(const hydot_tuning& t) {
 }
 
 }  // namespace hydot
+
+hydot_operator::~hydot_operator() {
+  if (mu64) (void)hipFree(mu64);
+  if (mu32) (void)hipFree(mu32);
+}
 
 using namespace hydot;
 
@@ -136,6 +142,42 @@ hydot_status hydot_assemble_operator(const hydot_grid* grid, const hydot_optics*
 
 void hydot_free_operator(hydot_operator* op) { delete op; }
 
+hydot_status hydot_set_absorption_perturbation(hydot_operator* op, const double* shape, const double* scale) {
+  if (!op) return hydot::fail(HYDOT_EINVAL, "set_absorption_perturbation: null operator");
+  if (!shape) {   // clear
+    op->has_pert = false;
+    return HYDOT_OK;
+  }
+  if (!scale) return hydot::fail(HYDOT_EINVAL, "set_absorption_perturbation: null scale");
+  const size_t N = (size_t)op->gp.N;
+  for (size_t n = 0; n < N; ++n)
+    if (!std::isfinite(shape[n])) return hydot::fail(HYDOT_EINVAL, "set_absorption_perturbation: non-finite shape");
+  std::vector<double> tau(op->L);
+  double mean = 0.0;
+  for (int l = 0; l < op->L; ++l) {
+    if (!std::isfinite(scale[l])) return hydot::fail(HYDOT_EINVAL, "set_absorption_perturbation: non-finite scale");
+    tau[l] = scale[l] / op->D[l];
+    mean += tau[l];
+  }
+  if (!op->mu64) {
+    if (hipMalloc(&op->mu64, N * sizeof(double)) != hipSuccess) {
+      op->mu64 = nullptr;
+      return hydot::fail(HYDOT_EDEVICE, "set_absorption_perturbation: device allocation");
+    }
+    if (hipMalloc(&op->mu32, N * sizeof(float)) != hipSuccess) {
+      op->mu32 = nullptr;
+      return hydot::fail(HYDOT_EDEVICE, "set_absorption_perturbation: device allocation");
+    }
+  }
+  std::vector<float> s32(shape, shape + N);
+  HYDOT_HIP(hipMemcpy(op->mu64, shape, N * sizeof(double), hipMemcpyHostToDevice));
+  HYDOT_HIP(hipMemcpy(op->mu32, s32.data(), N * sizeof(float), hipMemcpyHostToDevice));
+  op->tau = tau;
+  op->tau_mean = mean / op->L;
+  op->has_pert = true;
+  return HYDOT_OK;
+}
+
 hydot_status hydot_get_tuning(const hydot_operator* op, hydot_tuning* out) {
   if (!op || !out) return hydot::fail(HYDOT_EINVAL, "get_tuning: null argument");
   *out = hydot::resolved_tuning(op->tune);
@@ -187,14 +229,15 @@ hydot_status hydot_apply_operator(const hydot_operator* op, int32_t n_vec, const
       prm.sig[v] = op->sigma[l];
       prm.sigp[v] = op->sigp[l];
       prm.scl[v] = op->D[l] * h3;
+      prm.tau[v] = op->has_pert ? op->tau[l] : 0.0;
     }
     dim3 grid((unsigned)((N + kBlock - 1) / kBlock), (unsigned)nb);
     if (dtype == HYDOT_C128)
       hipLaunchKernelGGL(k_apply_op<cd>, grid, dim3(kBlock), 0, stream, op->gp,
-                         (const cd*)x + (size_t)v0 * N, (cd*)y + (size_t)v0 * N, prm);
+                         (const cd*)x + (size_t)v0 * N, (cd*)y + (size_t)v0 * N, prm, (const double*)op->mu64);
     else
       hipLaunchKernelGGL(k_apply_op<cf>, grid, dim3(kBlock), 0, stream, op->gp,
-                         (const cf*)x + (size_t)v0 * N, (cf*)y + (size_t)v0 * N, prm);
+                         (const cf*)x + (size_t)v0 * N, (cf*)y + (size_t)v0 * N, prm, (const double*)op->mu64);
     HYDOT_HIP(hipGetLastError());
   }
   return HYDOT_OK;

@@ -309,3 +309,43 @@ def test_operator_is_complex_symmetric_with_spd_real_part():
     assert abs(A - A.T).max() == 0.0
     ev = np.linalg.eigvalsh(A.real.toarray())
     assert ev.min() > 0
+
+
+def test_uniform_perturbation_equals_raised_background():
+    """shape = 1 with scale s_l is a homogeneous medium with mu_a + s_l: the perturbed operator's
+    banded LU must match fast diagonalisation of a workload whose background absorption carries an
+    extra chromophore with extinction s_l (two independent routes)."""
+    w = workloads.config("tiny", n_lambda=3)
+    s = np.array([0.004, 0.011, 0.02])
+    got = fields.solve_banded(w, pert=(np.ones(w.N), s))
+    w2 = workloads.config("tiny", n_lambda=3)
+    w2.extinction = np.vstack([w2.extinction, s[None, :]])
+    w2.conc_uM = np.concatenate([w2.conc_uM, [1.0]])
+    ref = fields.solve_separable(w2)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+    # and the perturbation really changes the fields
+    base = fields.solve_banded(w)
+    assert np.abs(got - base).max() > 1e-3 * np.abs(base).max()
+
+
+def test_perturbed_fields_reciprocity_and_born_limit():
+    """The heterogeneous operator stays complex symmetric (reciprocity between optodes), and
+    phi(mu_a + t*s*shape) - phi(mu_a) - t * s_l * J shape = O(t^2) (the Born approximation is the
+    first-order term of the full forward model)."""
+    w = workloads.config("tiny", n_lambda=2)
+    p, _ = workloads.pals_truth(w)
+    shape = pals.shape(w, p, workloads.PALS_TAU, workloads.PALS_EPS, workloads.PALS_NU)
+    s = np.array([0.01, 0.02])
+    P = fields.solve_banded(w, pert=(shape, s))
+    S = w.S
+    for a in range(S):
+        for b in range(w.D):
+            np.testing.assert_allclose(P[:, a, w.det_voxels[b]], P[:, S + b, w.src_voxels[a]], rtol=1e-9)
+    base = fields.solve_banded(w)
+    y = born.born_apply(base[:, :S], base[:, S:], shape[None], w.h)[0]      # [L, S, D]
+    rem = []
+    for t in (0.2, 0.1):
+        Pt = fields.solve_banded(w, pert=(shape, t * s))
+        diff = Pt[:, :S][:, :, w.det_voxels] - base[:, :S][:, :, w.det_voxels]
+        rem.append(np.abs(diff - t * s[:, None, None] * y).max())
+    assert 3.5 < rem[0] / rem[1] < 4.5
