@@ -89,6 +89,9 @@ typedef struct {
 #define HYDOT_FLAG_MEAN_SHIFT  0x2u  /* K <- K + mean(sigma') R, sigma'_j <- sigma'_j - mean (Sec. 6.1) */
 #define HYDOT_FLAG_GRAPH       0x4u  /* capture each restart cycle in a hipGraph and replay it */
 #define HYDOT_FLAG_PER_SYSTEM  0x8u  /* plain mode: one (rhs, lambda) system at a time, per-call launches */
+#define HYDOT_FLAG_SHIFT_MIN   0x20u /* like MEAN_SHIFT with min_j sigma'_j in K_hat (Sec. 6.1 variants) */
+#define HYDOT_FLAG_SHIFT_MAX   0x40u /* like MEAN_SHIFT with max_j sigma'_j in K_hat; at most one of
+                                        MEAN_SHIFT, SHIFT_MIN, SHIFT_MAX */
 #define HYDOT_FLAG_FULL_REORTH 0x10u /* mixed only: apply the second Gram-Schmidt pass at every step.
                                         Default: the FP32 inner Arnoldi skips it for a system whose
                                         second-pass projection is below 1e-4 ||w'|| (orthogonal to

@@ -33,5 +33,6 @@ from ._binding import (  # noqa: F401
     BORN_NATIVE, BORN_SPLIT_BF16,
     PREC_FP64, PREC_MIXED,
     FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH,
+    FLAG_SHIFT_MIN, FLAG_SHIFT_MAX,
     OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED,
 )

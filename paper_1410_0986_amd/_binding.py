@@ -22,6 +22,7 @@ C128, C64, CBF16, F64, F32 = 0, 1, 2, 3, 4
 BORN_NATIVE, BORN_SPLIT_BF16 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH = 0x1, 0x2, 0x4, 0x8, 0x10
+FLAG_SHIFT_MIN, FLAG_SHIFT_MAX = 0x20, 0x40
 
 
 class HydotError(RuntimeError):

@@ -125,6 +125,7 @@ struct Plan {
   int k, mk, nl, mkmax;
   int prec;
   bool recycle, per_system, graph, mean_shift;
+  int shift_kind;   // sigma' moved into K_hat: 0 mean, 1 min, 2 max (when mean_shift)
   int nb;       // systems per batch
   int rl;       // right-hand sides per Lanczos batch (and in the U/C buffers)
   int nchunks, ndots;
@@ -147,7 +148,11 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   if (o->max_iter < 1) return fail(HYDOT_EINVAL, "solve: max_iter must be >= 1");
   if (o->precision != HYDOT_PREC_FP64 && o->precision != HYDOT_PREC_MIXED)
     return fail(HYDOT_EINVAL, "solve: precision must be HYDOT_PREC_FP64 or HYDOT_PREC_MIXED");
-  if (o->flags & ~0x1Fu) return fail(HYDOT_EINVAL, "solve: unknown flag bits");
+  if (o->flags & ~0x7Fu) return fail(HYDOT_EINVAL, "solve: unknown flag bits");
+  {
+    const uint32_t sh = o->flags & (HYDOT_FLAG_MEAN_SHIFT | HYDOT_FLAG_SHIFT_MIN | HYDOT_FLAG_SHIFT_MAX);
+    if (sh & (sh - 1)) return fail(HYDOT_EINVAL, "solve: at most one of MEAN_SHIFT, SHIFT_MIN, SHIFT_MAX");
+  }
   p.recycle = !(o->flags & HYDOT_FLAG_NO_RECYCLE);
   p.k = p.recycle ? o->recycle_k : 0;
   if (p.k < 0 || p.k > kMaxK) return fail(HYDOT_EINVAL, "solve: recycle_k must be in [0, 32]");
@@ -166,7 +171,8 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   p.prec = o->precision;
   p.per_system = (o->flags & HYDOT_FLAG_PER_SYSTEM) != 0;
   p.graph = (o->flags & HYDOT_FLAG_GRAPH) != 0;
-  p.mean_shift = (o->flags & HYDOT_FLAG_MEAN_SHIFT) != 0;
+  p.mean_shift = (o->flags & (HYDOT_FLAG_MEAN_SHIFT | HYDOT_FLAG_SHIFT_MIN | HYDOT_FLAG_SHIFT_MAX)) != 0;
+  p.shift_kind = (o->flags & HYDOT_FLAG_SHIFT_MIN) ? 1 : (o->flags & HYDOT_FLAG_SHIFT_MAX) ? 2 : 0;
   p.mkmax = std::max(p.mk, p.nl);
   const int total_sys = p.R * p.L;
   if (p.per_system) {
@@ -230,7 +236,11 @@ struct Solver {
 
   template <typename T> T* at(size_t off) const { return (T*)(ws + off); }
 
-  double sigp_mean() const { return p.mean_shift ? op->sigp_mean : 0.0; }
+  // Robin shift moved into K_hat (Sec. 6.1): the mean, minimum or maximum of sigma'_j, or none
+  double sigp_mean() const {
+    if (!p.mean_shift) return 0.0;
+    return p.shift_kind == 1 ? op->sigp_min : p.shift_kind == 2 ? op->sigp_max : op->sigp_mean;
+  }
   // part of the absorption perturbation moved into K_hat (its mean, with the mean shift)
   double tau_shift() const { return p.mean_shift && op->has_pert ? op->tau_mean : 0.0; }
 

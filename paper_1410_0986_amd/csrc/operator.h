@@ -18,6 +18,7 @@ struct hydot_operator {
   std::vector<hydot::cd> sigma;   // [L] (mu_a + i omega/nu)/D
   std::vector<double> sigp;       // [L] 1/(2 A_R D)
   double sigp_mean = 0.0;         // mean of sigma' over wavelengths
+  double sigp_min = 0.0, sigp_max = 0.0;
   // absorption perturbation dmua_l(k) = scale_l * shape(k): tau_l = scale_l / D_l enters the
   // scaled operator as tau_l * diag(shape); device copies of the shape in FP64 and FP32
   bool has_pert = false;

@@ -136,6 +136,8 @@ hydot_status hydot_assemble_operator(const hydot_grid* grid, const hydot_optics*
     mean += op->sigp[l];
   }
   op->sigp_mean = mean / L;                          // mean-shift transform, Sec. 6.1
+  op->sigp_min = *std::min_element(op->sigp.begin(), op->sigp.end());
+  op->sigp_max = *std::max_element(op->sigp.begin(), op->sigp.end());
   *out = op;
   return HYDOT_OK;
 }

@@ -195,3 +195,12 @@ def test_tuning_defaults_and_validation(hd):
     assert hd.get_tuning(op)["step_presum"] == 1 and hd.get_tuning(op)["step_order"] == 2
     hd.set_tuning(op, step_presum=0)
     assert hd.get_tuning(op)["step_presum"] == 4
+
+
+def test_shift_flags_are_exclusive(hd):
+    op = _op(hd, workloads.config("tiny"))
+    for fl in (hd.FLAG_MEAN_SHIFT | hd.FLAG_SHIFT_MIN, hd.FLAG_SHIFT_MIN | hd.FLAG_SHIFT_MAX):
+        with pytest.raises(hd.HydotError) as e:
+            hd.solve_workspace_bytes(op, 4, hd.SolveOptions(flags=fl))
+        assert e.value.status == hd.EINVAL
+    assert hd.solve_workspace_bytes(op, 4, hd.SolveOptions(flags=hd.FLAG_SHIFT_MAX)) > 0
