@@ -231,3 +231,22 @@ def observed_noise(shape, scale: float, seed: int = 33) -> np.ndarray:
     rng = np.random.default_rng(seed)
     s = scale / math.sqrt(2.0)
     return rng.normal(0.0, s, size=shape) + 1j * rng.normal(0.0, s, size=shape)
+
+
+# ---------------------------------------------------------------- randomized compression
+COMPRESS_SEED = 4242
+
+
+def gaussian_test_matrix(n: int, cols: int, seed: int = COMPRESS_SEED) -> np.ndarray:
+    """The i.i.d. N(0,1) test matrix of the randomized range finder, [n, cols]; a run that needs
+    fewer columns uses the leading ones, so both implementations see the same draws."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, cols))
+
+
+def optode_xy(w: Workload, voxels) -> np.ndarray:
+    """(x, y) voxel-centre coordinates in mm of optode voxels on the top plate, [count, 2]."""
+    v = np.asarray(voxels, dtype=np.int64)
+    i = v % w.nx
+    j = (v // w.nx) % w.ny
+    return np.stack([(i + 0.5) * w.h, (j + 0.5) * w.h], axis=1)
