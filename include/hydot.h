@@ -196,6 +196,15 @@ hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_
                                       hydot_dtype field_dtype, const void* w, void* g,
                                       hipStream_t stream);
 
+/* Block form of the adjoint product: g[c] = sum_l J_l^H w[c][l] for c < n_w, 1 <= n_w <= 1024
+ * (the products with the transpose of H that the randomized compression of Sec. 4 and its
+ * appendix need).  w: device [n_w][n_lambda][S][D], g: device [n_w][N], dtypes as
+ * hydot_born_apply_adjoint. */
+hydot_status hydot_born_apply_adjoint_ex(const hydot_operator* op, const void* phi_src, int32_t S,
+                                         const void* phi_det, int32_t D, int64_t lam_stride,
+                                         hydot_dtype field_dtype, const void* w, int32_t n_w, void* g,
+                                         hipStream_t stream);
+
 /* PaLS shape (Sec. 5, eq. pals) at the voxel centres ((i+1/2)h, (j+1/2)h, (k+1/2)h):
  *   mu(r) = H_eps(varphi(r) - tau),  varphi(r) = sum_b alpha_b exp(-(beta_b ||r - chi_b||_dag)^2),
  *   ||x||_dag = sqrt(||x||^2 + nu^2),  H_eps the C^1 sine-smoothed Heaviside of half-width eps.

@@ -72,6 +72,8 @@ _born = _proto("hydot_born_apply", c_int32, c_void_p, c_void_p, c_int32, c_void_
                c_void_p, c_int32, c_void_p, c_void_p)
 _born_ex = _proto("hydot_born_apply_ex", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32,
                   c_int32, c_void_p, c_int32, c_void_p, c_void_p)
+_born_adj_ex = _proto("hydot_born_apply_adjoint_ex", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32,
+                      c_int64, c_int32, c_void_p, c_int32, c_void_p, c_void_p)
 _born_adj = _proto("hydot_born_apply_adjoint", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64,
                    c_int32, c_void_p, c_void_p, c_void_p)
 _pals = _proto("hydot_pals_shape", c_int32, c_void_p, POINTER(c_double), c_int32, POINTER(_PalsOpts), c_void_p,
@@ -411,7 +413,9 @@ def born_apply(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, v: to
 
 
 def born_apply_adjoint(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
-    """g[k] = sum_{l,s,d} conj(J_l[s,d,k]) w[l,s,d] (hydot_born_apply_adjoint)."""
+    """g[k] = sum_{l,s,d} conj(J_l[s,d,k]) w[l,s,d] (hydot_born_apply_adjoint_ex).
+
+    w: [L, S, D] -> g [N]; or a block [n_w, L, S, D] -> g [n_w, N]."""
     ps, S, ls = _field_view(op, phi_src, "phi_src")
     pd, D, ld = _field_view(op, phi_det, "phi_det")
     if ls != ld:
@@ -419,12 +423,14 @@ def born_apply_adjoint(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tenso
     dt = _cdtype(phi_src)
     _need_cuda(w, "w")
     w = w.to(_out_complex(dt)).contiguous()
-    if tuple(w.shape) != (op.L, S, D):
-        raise ValueError("w must be [L, S, D]")
-    g = torch.empty(op.N, dtype=_out_complex(dt), device=phi_src.device)
-    _check(_born_adj(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt, c_void_p(w.data_ptr()),
-                     c_void_p(g.data_ptr()), _stream(phi_src.device)))
-    return g
+    single = w.dim() == 3
+    wb = w[None] if single else w
+    if wb.dim() != 4 or tuple(wb.shape[1:]) != (op.L, S, D):
+        raise ValueError("w must be [L, S, D] or [n_w, L, S, D]")
+    g = torch.empty((wb.shape[0], op.N), dtype=_out_complex(dt), device=phi_src.device)
+    _check(_born_adj_ex(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt, c_void_p(wb.data_ptr()),
+                        int(wb.shape[0]), c_void_p(g.data_ptr()), _stream(phi_src.device)))
+    return g[0] if single else g
 
 
 def pals_shape(op: Operator, p, popts: PalsOptions | None = None, dtype=torch.float64, device="cuda") -> torch.Tensor:

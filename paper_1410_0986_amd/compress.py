@@ -1,0 +1,233 @@
+"""Randomized recursive low-rank compression of the Born operator H (Sec. 4, with the randomized
+SVD of the appendix on low-rank representations).
+
+H has one row per measurement and one column per voxel, H[(s, l, d), k] = J_l[s, d, k]
+(source s, wavelength l, detector d; rows source-major).  Its row blocks H_s (one per source,
+L*D x N) are never formed: the randomized range finder only needs the products H_s Omega and
+H_s^H Q, which are the library's Born products with blocks of probe vectors
+(``born_apply`` with n_v columns, ``born_apply_adjoint`` with n_w data vectors) on the fields
+of source s.  The small dense steps (QR and SVD of matrices with a few dozen columns) run on the
+GPU in FP64 through torch.linalg.
+
+* ``bisection_tree``   - the geometric bisection of the source positions on the plate
+  (Alg. geom): split the box across its longest side at the midpoint; a part with more than two
+  sources is split again.
+* ``randsvd``          - adaptive randomized SVD of one row block (Alg. randsvd): rank r from 1,
+  doubled until the estimate ||A Omega_2 - Q Q^H A Omega_2|| <= eps * S_r(1, 1), oversampling p,
+  k estimator columns.
+* ``agglomerate``      - two (or more) children H_i ~ U_i V_i^H combine as
+  blockdiag(U_i) [V_1^H; V_2^H]; the stacked right factors are recompressed to tolerance eps
+  (a truncated SVD through a thin QR) and the left factor is formed explicitly.
+* ``compress``         - RecursiveLowRank over the tree (Alg. recursive), returning H ~ U V^H.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _binding as B
+
+
+# ------------------------------------------------------------------------- tree
+def bisection_tree(xy: np.ndarray, lo, hi, indices=None):
+    """Alg. geom on the 2-D source positions xy [S, 2] inside the box [lo, hi].
+
+    Returns a node: a list of source indices (a leaf, at most two sources) or a tuple of
+    children.  A split that leaves one side empty is not a node: the non-empty side is split
+    again inside its half of the box (the sources are distinct, so this ends)."""
+    idx = list(range(len(xy))) if indices is None else list(indices)
+    lo = np.asarray(lo, dtype=np.float64).copy()
+    hi = np.asarray(hi, dtype=np.float64).copy()
+    while True:
+        if len(idx) <= 2:
+            return idx
+        j = int(np.argmax(hi - lo))                  # direction of maximum expanse
+        if hi[j] - lo[j] <= 1e-12 * max(1.0, abs(hi[j])):
+            return idx                               # coincident positions: one leaf
+        gamma = 0.5 * (lo[j] + hi[j])
+        t1 = [i for i in idx if xy[i, j] <= gamma]
+        t2 = [i for i in idx if xy[i, j] > gamma]
+        hi1, lo2 = hi.copy(), lo.copy()
+        hi1[j] = gamma
+        lo2[j] = gamma
+        if t1 and t2:
+            return (bisection_tree(xy, lo, hi1, t1), bisection_tree(xy, lo2, hi, t2))
+        if t1:
+            hi = hi1
+        else:
+            lo = lo2
+
+
+def tree_leaves(node) -> list:
+    """Sources of a node in the order of its row blocks."""
+    return list(node) if isinstance(node, list) else [s for ch in node for s in tree_leaves(ch)]
+
+
+# -------------------------------------------------------------------- products
+@dataclass
+class BornBlock:
+    """Row block H_tau of the Born operator for the sources tau, products through the library."""
+    op: B.Operator
+    phi_src: torch.Tensor      # [L, S, N] all sources (complex)
+    phi_det: torch.Tensor      # [L, D, N]
+    sources: list
+
+    @property
+    def m(self) -> int:
+        return len(self.sources) * self.op.L * self.phi_det.shape[1]
+
+    def _src(self, s):
+        return self.phi_src[:, s:s + 1]
+
+    def matmat(self, omega: torch.Tensor) -> torch.Tensor:
+        """H_tau @ omega for real omega [N, c] -> [m, c] complex128 (rows (s, l, d))."""
+        rdt = torch.float64 if self.phi_src.dtype == torch.complex128 else torch.float32
+        out = []
+        for s in self.sources:
+            cols = []
+            for c0 in range(0, omega.shape[1], 64):
+                v = omega[:, c0:c0 + 64].T.to(rdt).contiguous()
+                y = B.born_apply(self.op, self._src(s), self.phi_det, v)      # [c, L, 1, D]
+                cols.append(y.reshape(v.shape[0], -1).T.to(torch.complex128))
+            out.append(torch.cat(cols, dim=1))
+        return torch.cat(out, dim=0)
+
+    def rmatmat(self, q: torch.Tensor) -> torch.Tensor:
+        """H_tau^H @ q for q [m, c] complex -> [N, c] complex128."""
+        L, D = self.op.L, self.phi_det.shape[1]
+        cdt = torch.complex128 if self.phi_src.dtype == torch.complex128 else torch.complex64
+        acc = None
+        for a, s in enumerate(self.sources):
+            qs = q[a * L * D:(a + 1) * L * D]                              # rows (l, d) of source s
+            w = qs.T.reshape(q.shape[1], L, 1, D).to(cdt).contiguous()
+            g = B.born_apply_adjoint(self.op, self._src(s), self.phi_det, w)   # [c, N]
+            g = g.T.to(torch.complex128)
+            acc = g if acc is None else acc + g
+        return acc
+
+
+# ------------------------------------------------------------- randomized SVD
+@dataclass
+class LowRank:
+    """H_tau ~ U V^H with U [m, r] (singular values folded in) and V [N, r] orthonormal columns."""
+    U: torch.Tensor
+    V: torch.Tensor
+    sources: list
+    products: int = 0          # columns of H products spent (both directions)
+    history: list = field(default_factory=list)
+
+    @property
+    def rank(self) -> int:
+        return self.U.shape[1]
+
+
+def randsvd(A: BornBlock, eps: float, omega1: torch.Tensor, omega2: torch.Tensor, p: int = 20) -> LowRank:
+    """Alg. randsvd on one row block; omega1 [N, >= r+p] and omega2 [N, k] are the test matrices
+    (the leading r+p columns of omega1 are used at rank r)."""
+    m = A.m
+    Z = A.matmat(omega2)                                             # A Omega_2, [m, k]
+    used = omega2.shape[1]
+    r = 1
+    hist = []
+    while True:
+        cols = min(r + p, omega1.shape[1])
+        Y = A.matmat(omega1[:, :cols])
+        used += cols
+        Ur, Sr, _ = torch.linalg.svd(Y, full_matrices=False)
+        rr = min(r, Ur.shape[1])
+        Q = Ur[:, :rr]
+        e = torch.linalg.matrix_norm(Z - Q @ (Q.conj().T @ Z), ord=2).item()
+        hist.append((rr, e, Sr[0].item()))
+        if e > eps * Sr[0].item() and rr < min(m, omega1.shape[1] - p):
+            r = min(2 * r, m, omega1.shape[1] - p)                    # rank doubled
+            continue
+        BH = A.rmatmat(Q)                                            # A^H Q = B^H, [N, r]
+        used += rr
+        U1, S, Vh = torch.linalg.svd(BH.conj().T, full_matrices=False)
+        return LowRank(U=(Q @ U1) * S[None, :], V=Vh.conj().T, sources=list(A.sources), products=used, history=hist)
+
+
+def agglomerate(parts: list, eps: float) -> LowRank:
+    """blockdiag(U_i) [V_1^H; V_2^H; ...] recompressed to relative tolerance eps."""
+    if len(parts) == 1:
+        return parts[0]
+    W_H = torch.cat([pt.V for pt in parts], dim=1)                  # [N, sum r_i] = W^H
+    Qw, Rw = torch.linalg.qr(W_H)                                  # W = Rw^H Qw^H
+    Us, Sw, Vsh = torch.linalg.svd(Rw.conj().T)
+    keep = max(1, int((Sw > eps * Sw[0]).sum().item()))
+    X = Us[:, :keep] * Sw[None, :keep]                              # W ~ X (Qw Vs)^H
+    V = Qw @ Vsh[:keep].conj().T
+    rows, off = [], 0
+    for pt in parts:                                               # blockdiag(U_i) @ X
+        rows.append(pt.U @ X[off:off + pt.rank])
+        off += pt.rank
+    return LowRank(U=torch.cat(rows, dim=0), V=V, sources=[s for pt in parts for s in pt.sources],
+                   products=sum(pt.products for pt in parts))
+
+
+# -------------------------------------------------------------------- driver
+@dataclass
+class CompressedBorn:
+    U: torch.Tensor            # [S*L*D, R], rows source-major (s, l, d) in natural source order
+    V: torch.Tensor            # [N, R]
+    tree: object
+    level_ranks: dict          # tree depth -> ranks of the nodes at that depth
+    seconds: float
+    products: int
+
+    @property
+    def rank(self) -> int:
+        return self.U.shape[1]
+
+    def matvec(self, v: torch.Tensor) -> torch.Tensor:
+        """H v for real v [n_v, N] -> [n_v, S*L*D] (rows (s, l, d))."""
+        return (self.U @ (self.V.conj().T @ v.to(torch.complex128).T)).T
+
+
+def compress(op: B.Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, src_xy: np.ndarray, eps: float,
+             omega1: np.ndarray, omega2: np.ndarray, box_lo=None, box_hi=None, p: int = 20) -> CompressedBorn:
+    """RecursiveLowRank (Alg. recursive) of H over the bisection tree of the source positions.
+
+    omega1 [N, c1] and omega2 [N, k]: Gaussian test matrices shared by every leaf (c1 bounds the
+    leaf rank plus oversampling).  box_lo/box_hi: the plate box (default: the sources' bounding box)."""
+    t0 = time.perf_counter()
+    dev = phi_src.device
+    lo = src_xy.min(axis=0) if box_lo is None else box_lo
+    hi = src_xy.max(axis=0) if box_hi is None else box_hi
+    tree = bisection_tree(np.asarray(src_xy, dtype=np.float64), lo, hi)
+    o1 = torch.from_numpy(np.ascontiguousarray(omega1)).to(dev)
+    o2 = torch.from_numpy(np.ascontiguousarray(omega2)).to(dev)
+    levels: dict = {}
+
+    def rec(node, depth):
+        if isinstance(node, list):      # leaf: one randomized SVD per source, then agglomerate
+            parts = [randsvd(BornBlock(op, phi_src, phi_det, [s]), eps, o1, o2, p) for s in node]
+            if len(parts) > 1:
+                levels.setdefault(depth + 1, []).extend(pt.rank for pt in parts)
+        else:
+            parts = [rec(ch, depth + 1) for ch in node]
+        out = agglomerate(parts, eps)
+        levels.setdefault(depth, []).append(out.rank)
+        return out
+
+    lr = rec(tree, 0)
+    # row blocks back to the natural source order
+    L, D = op.L, phi_det.shape[1]
+    blk = L * D
+    pos = {s: a for a, s in enumerate(lr.sources)}
+    U = torch.cat([lr.U[pos[s] * blk:(pos[s] + 1) * blk] for s in range(len(src_xy))], dim=0)
+    torch.cuda.synchronize(dev)
+    return CompressedBorn(U=U, V=lr.V, tree=tree, level_ranks=levels, seconds=time.perf_counter() - t0,
+                          products=lr.products)
+
+
+def randsvd_direct(op: B.Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, eps: float, omega1: np.ndarray,
+                   omega2: np.ndarray, p: int = 20) -> LowRank:
+    """The 'direct' comparison of Sec. 4: one adaptive randomized SVD of the whole H."""
+    dev = phi_src.device
+    o1 = torch.from_numpy(np.ascontiguousarray(omega1)).to(dev)
+    o2 = torch.from_numpy(np.ascontiguousarray(omega2)).to(dev)
+    return randsvd(BornBlock(op, phi_src, phi_det, list(range(phi_src.shape[1]))), eps, o1, o2, p)

@@ -275,73 +275,91 @@ __global__ void k_born_apply_finish(int S, int D, int Sp, int Dp, int nsplit, in
 // the epilogue contracts T with conj(phi_d) per voxel.  Lane (voxel i = lane%16,
 // slot gq = lane/16) loads the sources s = gq (mod 4) of its voxel once and uses
 // their real parts for k-index s and imaginary parts for k-index Sp + s.
-template <typename TS, int TBM, int SQ>
+template <typename TS, int TBM, int SQ, int NW>
 __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, int Sp, int Dp, int64_t lam_stride,
                                                         int L, const TS* __restrict__ phs,
                                                         const TS* __restrict__ phd,
                                                         const cplx<typename Field<TS>::real>* __restrict__ w,
-                                                        double scale, cplx<typename Field<TS>::real>* __restrict__ g) {
+                                                        int n_w, double scale,
+                                                        cplx<typename Field<TS>::real>* __restrict__ g) {
+  // NW data vectors w_c per block (blockIdx.y selects the group): the fields of each voxel
+  // tile are loaded once per wavelength and serve all of them
   using T = typename Field<TS>::real;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, gq = lane >> 4;
   const int vox0 = (blockIdx.x * 4 + wave) * 16;
+  const int c0 = blockIdx.y * NW;
   const int TB = 2 * Dp / 16;
   const int vox = vox0 + i16;
   const bool vok = vox < N;
   using MA = typename Mfma<T>::acc;
-  double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
+  double gre[NW][4], gim[NW][4];
+#pragma unroll
+  for (int c = 0; c < NW; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gre[c][r] = gim[c][r] = 0.0;
   for (int l = 0; l < L; ++l) {
     const TS* ps = phs + (size_t)l * lam_stride * N;
     const TS* pd = phd + (size_t)l * lam_stride * N;
-    const cplx<T>* wl = w + (size_t)l * S * D;
     cplx<T> z[SQ];   // phi_s[s][vox] for s = gq + 4q
 #pragma unroll
     for (int q = 0; q < SQ; ++q) {
       const int s = gq + 4 * q;
       z[q] = (q < Sp / 4 && s < S && vok) ? Field<TS>::get(ps, (size_t)s * N + vox) : cplx<T>{0, 0};
     }
-    MA acc[TBM];
+    cplx<T> ph[TBM][4];   // phi_d at the voxels and detectors of this lane's accumulator entries
 #pragma unroll
-    for (int t = 0; t < TBM; ++t) acc[t] = MA{0, 0, 0, 0};
-    // k-index s = gq + 4q uses Re z[q], k-index Sp + s uses Im z[q]
+    for (int t = 0; t < TBM; ++t) {
+      const int col = t * 16 + i16;
+      const int d = col >= Dp ? col - Dp : col;
 #pragma unroll
-    for (int q = 0; q < SQ; ++q) {
-      if (q < Sp / 4) {
-        const int s = gq + 4 * q;
+      for (int r = 0; r < 4; ++r) {
+        const int vv = vox0 + Mfma<T>::out_row(lane, r);
+        ph[t][r] = (t < TB && d < D && vv < N) ? Field<TS>::get(pd, (size_t)d * N + vv) : cplx<T>{0, 0};
+      }
+    }
 #pragma unroll
-        for (int t = 0; t < TBM; ++t) {
-          if (t < TB) {
-            const int col = t * 16 + i16;
-            const bool imcol = col >= Dp;
-            const int d = imcol ? col - Dp : col;
-            const cplx<T> ww = (s < S && d < D) ? wl[s * D + d] : cplx<T>{0, 0};
-            // B'' = [[Re w, Im w], [Im w, -Re w]]: rows of Re phi_s, then rows of Im phi_s
-            acc[t] = Mfma<T>::step(z[q].re, imcol ? ww.im : ww.re, acc[t]);
-            acc[t] = Mfma<T>::step(z[q].im, imcol ? -ww.re : ww.im, acc[t]);
+    for (int c = 0; c < NW; ++c) {
+      if (c0 + c >= n_w) break;
+      const cplx<T>* wl = w + ((size_t)(c0 + c) * L + l) * S * D;
+      MA acc[TBM];
+#pragma unroll
+      for (int t = 0; t < TBM; ++t) acc[t] = MA{0, 0, 0, 0};
+      // k-index s = gq + 4q uses Re z[q], k-index Sp + s uses Im z[q]
+#pragma unroll
+      for (int q = 0; q < SQ; ++q) {
+        if (q < Sp / 4) {
+          const int s = gq + 4 * q;
+#pragma unroll
+          for (int t = 0; t < TBM; ++t) {
+            if (t < TB) {
+              const int col = t * 16 + i16;
+              const bool imcol = col >= Dp;
+              const int d = imcol ? col - Dp : col;
+              const cplx<T> ww = (s < S && d < D) ? wl[s * D + d] : cplx<T>{0, 0};
+              // B'' = [[Re w, Im w], [Im w, -Re w]]: rows of Re phi_s, then rows of Im phi_s
+              acc[t] = Mfma<T>::step(z[q].re, imcol ? ww.im : ww.re, acc[t]);
+              acc[t] = Mfma<T>::step(z[q].im, imcol ? -ww.re : ww.im, acc[t]);
+            }
           }
         }
       }
-    }
-    // epilogue: lane holds T[voxel vox0 + out_row(lane, r)][col t*16 + lane%16]
+      // epilogue: lane holds T[voxel vox0 + out_row(lane, r)][col t*16 + lane%16]
 #pragma unroll
-    for (int t = 0; t < TBM; ++t) {
-      if (t < TB) {
-        const int col = t * 16 + i16;
-        const bool imcol = col >= Dp;
-        const int d = imcol ? col - Dp : col;
+      for (int t = 0; t < TBM; ++t) {
+        if (t < TB) {
+          const bool imcol = t * 16 + i16 >= Dp;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int vv = vox0 + Mfma<T>::out_row(lane, r);
-          cplx<T> ph{0, 0};
-          if (d < D && vv < N) ph = Field<TS>::get(pd, (size_t)d * N + vv);
-          const double e = ph.re, f = ph.im;
-          const double tv = (double)acc[t][r];
-          if (!imcol) {          // Re T column
-            gre[r] += e * tv;
-            gim[r] -= f * tv;
-          } else {               // Im T column
-            gre[r] += f * tv;
-            gim[r] += e * tv;
+          for (int r = 0; r < 4; ++r) {
+            const double e = ph[t][r].re, f = ph[t][r].im;
+            const double tv = (double)acc[t][r];
+            if (!imcol) {          // Re T column
+              gre[c][r] += e * tv;
+              gim[c][r] -= f * tv;
+            } else {               // Im T column
+              gre[c][r] += f * tv;
+              gim[c][r] += e * tv;
+            }
           }
         }
       }
@@ -349,18 +367,22 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, in
   }
   // reduce over the 16 lanes that share a voxel (lane & 15 varies)
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      gre[r] += __shfl_xor(gre[r], off, 64);
-      gim[r] += __shfl_xor(gim[r], off, 64);
-    }
-  }
-  if (i16 == 0) {
+  for (int c = 0; c < NW; ++c) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int vv = vox0 + Mfma<T>::out_row(lane, r);
-      if (vv < N) g[vv] = cplx<T>{(T)(scale * gre[r]), (T)(scale * gim[r])};
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        gre[c][r] += __shfl_xor(gre[c][r], off, 64);
+        gim[c][r] += __shfl_xor(gim[c][r], off, 64);
+      }
+    }
+    if (i16 == 0 && c0 + c < n_w) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int vv = vox0 + Mfma<T>::out_row(lane, r);
+        if (vv < N)
+          g[(size_t)(c0 + c) * N + vv] = cplx<T>{(T)(scale * gre[c][r]), (T)(scale * gim[c][r])};
+      }
     }
   }
 }
@@ -433,23 +455,25 @@ hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, c
 
 template <typename TS>
 hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
-                               int64_t ls, const void* w, void* g, hipStream_t stream) {
+                               int64_t ls, const void* w, int n_w, void* g, hipStream_t stream) {
   using R = typename Field<TS>::real;
   const int N = op->gp.N, L = op->L;
   const int Sp = pad8(S), Dp = pad8(D);
   const int TB = 2 * Dp / 16;
-  dim3 grid((N + 63) / 64);
+  // four data vectors per block when the detector tiles are few (register budget)
+  const int nw = n_w > 1 && TB <= 2 ? 4 : 1;
+  dim3 grid((N + 63) / 64, (n_w + nw - 1) / nw);
   const double h = op->grid.h_mm;
   const double sc = -h * h * h;
-#define HYDOT_BJ(TBM, SQ)                                                                                   \
-  hipLaunchKernelGGL((k_born_adjoint<TS, TBM, SQ>), grid, dim3(kBlock), 0, stream, N, S, D, Sp, Dp, ls, L,  \
-                     (const TS*)phs, (const TS*)phd, (const cplx<R>*)w, sc, (cplx<R>*)g)
-#define HYDOT_BJ_S(TBM) \
-  if (Sp <= 16) HYDOT_BJ(TBM, 4); else if (Sp <= 32) HYDOT_BJ(TBM, 8); else HYDOT_BJ(TBM, 16);
-  if (TB <= 1) { HYDOT_BJ_S(1) }
-  else if (TB <= 2) { HYDOT_BJ_S(2) }
-  else if (TB <= 4) { HYDOT_BJ_S(4) }
-  else { HYDOT_BJ_S(8) }
+#define HYDOT_BJ(TBM, SQ, NW)                                                                                  \
+  hipLaunchKernelGGL((k_born_adjoint<TS, TBM, SQ, NW>), grid, dim3(kBlock), 0, stream, N, S, D, Sp, Dp, ls, L, \
+                     (const TS*)phs, (const TS*)phd, (const cplx<R>*)w, n_w, sc, (cplx<R>*)g)
+#define HYDOT_BJ_S(TBM, NW) \
+  if (Sp <= 16) HYDOT_BJ(TBM, 4, NW); else if (Sp <= 32) HYDOT_BJ(TBM, 8, NW); else HYDOT_BJ(TBM, 16, NW);
+  if (TB <= 1) { if (nw == 4) { HYDOT_BJ_S(1, 4) } else { HYDOT_BJ_S(1, 1) } }
+  else if (TB <= 2) { if (nw == 4) { HYDOT_BJ_S(2, 4) } else { HYDOT_BJ_S(2, 1) } }
+  else if (TB <= 4) { HYDOT_BJ_S(4, 1) }
+  else { HYDOT_BJ_S(8, 1) }
 #undef HYDOT_BJ_S
 #undef HYDOT_BJ
   HYDOT_HIP(hipGetLastError());
@@ -500,15 +524,24 @@ hydot_status hydot_born_apply(const hydot_operator* op, const void* phi_src, int
                              stream);
 }
 
-hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
-                                      int32_t D, int64_t lam_stride, hydot_dtype field_dtype, const void* w, void* g,
-                                      hipStream_t stream) {
+hydot_status hydot_born_apply_adjoint_ex(const hydot_operator* op, const void* phi_src, int32_t S,
+                                         const void* phi_det, int32_t D, int64_t lam_stride, hydot_dtype field_dtype,
+                                         const void* w, int32_t n_w, void* g, hipStream_t stream) {
   hydot_status s = born_check(op, phi_src, S, phi_det, D, lam_stride, field_dtype);
   if (s != HYDOT_OK) return s;
   if (!w || !g) return fail(HYDOT_EINVAL, "born_apply_adjoint: null w or g");
-  if (field_dtype == HYDOT_C128) return born_adjoint_impl<cd>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
-  if (field_dtype == HYDOT_CBF16) return born_adjoint_impl<cbf>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
-  return born_adjoint_impl<cf>(op, phi_src, S, phi_det, D, lam_stride, w, g, stream);
+  if (n_w < 1 || n_w > 1024) return fail(HYDOT_EINVAL, "born_apply_adjoint: n_w must be in [1, 1024]");
+  if (field_dtype == HYDOT_C128)
+    return born_adjoint_impl<cd>(op, phi_src, S, phi_det, D, lam_stride, w, n_w, g, stream);
+  if (field_dtype == HYDOT_CBF16)
+    return born_adjoint_impl<cbf>(op, phi_src, S, phi_det, D, lam_stride, w, n_w, g, stream);
+  return born_adjoint_impl<cf>(op, phi_src, S, phi_det, D, lam_stride, w, n_w, g, stream);
+}
+
+hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
+                                      int32_t D, int64_t lam_stride, hydot_dtype field_dtype, const void* w, void* g,
+                                      hipStream_t stream) {
+  return hydot_born_apply_adjoint_ex(op, phi_src, S, phi_det, D, lam_stride, field_dtype, w, 1, g, stream);
 }
 
 hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det, int32_t D,
