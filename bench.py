@@ -277,6 +277,34 @@ def main():
         del opb
         log("boundary/shift study done")
 
+        # randomized compression of H (Sec. 4): recursive over the source bisection tree against one
+        # randomized SVD of the whole H, tolerance 1e-3, error measured with fresh probe vectors
+        from paper_1410_0986_amd import compress as hcompress
+        hd.solve_fields(op, vox, opts, out=phi)
+        xy = workloads.optode_xy(w, w.src_voxels)
+        om1 = workloads.gaussian_test_matrix(N, 700)
+        om2 = workloads.gaussian_test_matrix(N, 10, seed=workloads.COMPRESS_SEED + 1)
+        vprobe = torch.from_numpy(workloads.born_v(w, n_v=8, seed=99, dtype=np.float32)).to(dev)
+        yprobe = hd.born_apply(op, phi[:, :S], phi[:, S:], vprobe).permute(0, 2, 1, 3).reshape(8, -1)
+        yprobe = yprobe.to(torch.complex128)
+        cb = hcompress.compress(op, phi[:, :S], phi[:, S:], xy, 1e-3, om1[:, :300], om2)
+        cerr = float(torch.linalg.vector_norm(cb.matvec(vprobe) - yprobe) / torch.linalg.vector_norm(yprobe))
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        lr = hcompress.randsvd_direct(op, phi[:, :S], phi[:, S:], 1e-3, om1, om2)
+        torch.cuda.synchronize()
+        tdir = time.perf_counter() - td
+        dy = (lr.U @ (lr.V.conj().T @ vprobe.to(torch.complex128).T)).T
+        derr = float(torch.linalg.vector_norm(dy - yprobe) / torch.linalg.vector_norm(yprobe))
+        compression = {"eps": 1e-3, "rows": S * L * D, "cols": N,
+                       "recursive": {"seconds": round(cb.seconds, 3), "rank": cb.rank,
+                                     "level_ranks": {str(k): v for k, v in sorted(cb.level_ranks.items())},
+                                     "probe_rel_err": float(f"{cerr:.3g}"), "H_columns_applied": cb.products},
+                       "direct_randsvd": {"seconds": round(tdir, 3), "rank": lr.rank,
+                                          "probe_rel_err": float(f"{derr:.3g}"), "H_columns_applied": lr.products}}
+        del cb, lr, om1
+        log("compression done")
+
 
         plain = None
         if not args.no_plain:
@@ -348,6 +376,7 @@ def main():
         "born_variants": variants,
         "forward_heterogeneous": forward,
         "boundary_shift_study": study,
+        "compression": compression,
         "plain_fp64": plain,
         "speedup_vs_plain": round(solves_per_s / plain["solves_per_s"], 2) if plain else None,
         "roofline": roof,

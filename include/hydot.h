@@ -225,6 +225,14 @@ hydot_status hydot_pals_shape_vjp(const hydot_operator* op, const double* p, int
                                   double* grad_p, void* workspace, size_t ws_bytes,
                                   hipStream_t stream);
 
+/* Shape Jacobian (Sec. 5, the derivative of eq. pals used by the Levenberg-Marquardt step of
+ * Alg. opt): jac[i][k] = d mu_k / d p_i for the 5*n_bumps parameters in the order of p, as a
+ * device [5*n_bumps][N] array of dtype F64 or F32 -- a block of probe vectors for
+ * hydot_born_apply, whose product gives H d mu / d p. */
+hydot_status hydot_pals_shape_jacobian(const hydot_operator* op, const double* p, int32_t n_bumps,
+                                       const hydot_pals_opts* popts, void* jac, hydot_dtype jac_dtype,
+                                       hipStream_t stream);
+
 /* Data misfit of the Born model with co-located chromophores (eq. measurement, eq. minimization):
  *   ebar_l = sum_species eps(lambda_l) dconc,  yhat = ebar_l * Jmu,  r = yhat - y_obs,
  *   f = 1/2 sum weights^2 |r|^2,

@@ -3,7 +3,7 @@
 Argument marshalling only: every step runs inside the HIP library
 (``libhydot.so``, C ABI in ``include/hydot.h``).  PyTorch provides device
 memory and streams.  Importing this package loads the library and fails
-loudly if it has not been built (``python -m paper_1410_0986_amd.build``).
+loudly if it has not been built (``python paper_1410_0986_amd/build.py``).
 """
 from __future__ import annotations
 
@@ -19,6 +19,7 @@ from ._binding import (  # noqa: F401
     born_apply_adjoint,
     pals_shape,
     pals_shape_vjp,
+    pals_shape_jacobian,
     misfit,
     BornMisfit,
     library_path,

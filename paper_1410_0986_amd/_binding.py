@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libhydot.so")
 
 if not os.path.exists(_LIBPATH):
-    raise ImportError(f"{_LIBPATH} is not built; run `python -m paper_1410_0986_amd.build` "
+    raise ImportError(f"{_LIBPATH} is not built; run `python paper_1410_0986_amd/build.py` "
                       "(or __graft_entry__.build()) first")
 _lib = ctypes.CDLL(_LIBPATH)
 
@@ -79,6 +79,8 @@ _born_adj = _proto("hydot_born_apply_adjoint", c_int32, c_void_p, c_void_p, c_in
 _pals = _proto("hydot_pals_shape", c_int32, c_void_p, POINTER(c_double), c_int32, POINTER(_PalsOpts), c_void_p,
                c_int32, c_void_p)
 _pals_ws = _proto("hydot_pals_workspace_bytes", c_size_t, c_void_p, c_int32)
+_pals_jac = _proto("hydot_pals_shape_jacobian", c_int32, c_void_p, POINTER(c_double), c_int32, POINTER(_PalsOpts),
+                   c_void_p, c_int32, c_void_p)
 _pals_vjp = _proto("hydot_pals_shape_vjp", c_int32, c_void_p, POINTER(c_double), c_int32, POINTER(_PalsOpts),
                    c_void_p, c_int32, POINTER(c_double), c_void_p, c_size_t, c_void_p)
 _misfit_ws = _proto("hydot_misfit_workspace_bytes", c_size_t, c_void_p, c_int32, c_int32)
@@ -442,6 +444,19 @@ def pals_shape(op: Operator, p, popts: PalsOptions | None = None, dtype=torch.fl
     o = popts._c()
     _check(_pals(op.handle, _dptr(pv), nb, ctypes.byref(o), c_void_p(mu.data_ptr()), dt, _stream(mu.device)))
     return mu
+
+
+def pals_shape_jacobian(op: Operator, p, popts: PalsOptions | None = None, dtype=torch.float64,
+                        device="cuda") -> torch.Tensor:
+    """d mu / d p as a device [5*n_bumps, N] tensor (hydot_pals_shape_jacobian)."""
+    popts = popts or PalsOptions()
+    pn = np.ascontiguousarray(p, dtype=np.float64)
+    nb = pn.shape[0] // 5
+    jac = torch.empty((5 * nb, op.N), dtype=dtype, device=device)
+    o = popts._c()
+    _check(_pals_jac(op.handle, _dptr(pn), nb, ctypes.byref(o), c_void_p(jac.data_ptr()),
+                     F64 if dtype == torch.float64 else F32, _stream(jac.device)))
+    return jac
 
 
 def pals_shape_vjp(op: Operator, p, g: torch.Tensor, popts: PalsOptions | None = None) -> np.ndarray:

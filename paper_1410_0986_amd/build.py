@@ -1,6 +1,6 @@
 """Build libhydot.so (HIP for gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1410_0986_amd.build [--jobs N]
+Usage: python paper_1410_0986_amd/build.py [--jobs N]   (runs without importing the package)
 """
 from __future__ import annotations
 

@@ -108,6 +108,40 @@ __global__ __launch_bounds__(kBlock) void k_pals_vjp(GridP g, PalsP p, const G* 
   }
 }
 
+// Columns of the shape Jacobian: jac[i][n] = d mu_n / d p_i for the 5*nb parameters in the order
+// [alpha, beta, chi_x, chi_y, chi_z] (one row of N per parameter: a block of probe vectors).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_pals_jacobian(GridP g, PalsP p, R* jac) {
+  const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= (uint32_t)g.N) return;
+  const size_t N = (size_t)g.N;
+  double x, y, z;
+  voxel_centre(g, n, p.h, x, y, z);
+  const double s = level(p, x, y, z) - p.tau;
+  const double delta = (s >= -p.eps && s <= p.eps) ? (1.0 + cos(M_PI * s / p.eps)) / (2.0 * p.eps) : 0.0;
+  for (int b = 0; b < p.nb; ++b) {
+    double da = 0, dbeta = 0, dcx = 0, dcy = 0, dcz = 0;
+    if (delta != 0.0) {
+      const double dx = x - p.cx[b], dy = y - p.cy[b], dz = z - p.cz[b];
+      const double dist = sqrt(dx * dx + dy * dy + dz * dz + p.nu * p.nu);
+      const double t = p.beta[b] * dist;
+      const double psi = exp(-t * t);
+      const double dpsi = -2.0 * t * psi;            // psi'(t)
+      da = delta * psi;
+      dbeta = delta * p.alpha[b] * dpsi * dist;
+      const double common = delta * p.alpha[b] * dpsi * p.beta[b] / dist;
+      dcx = -common * dx;
+      dcy = -common * dy;
+      dcz = -common * dz;
+    }
+    jac[(size_t)b * N + n] = (R)da;
+    jac[(size_t)(p.nb + b) * N + n] = (R)dbeta;
+    jac[(size_t)(2 * p.nb + b) * N + n] = (R)dcx;
+    jac[(size_t)(3 * p.nb + b) * N + n] = (R)dcy;
+    jac[(size_t)(4 * p.nb + b) * N + n] = (R)dcz;
+  }
+}
+
 __global__ void k_sum_rows(const double* part, int nrows, int ncols, double* out) {
   for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
     double a = 0.0;
@@ -195,6 +229,25 @@ hydot_status hydot_pals_shape(const hydot_operator* op, const double* p, int32_t
     hipLaunchKernelGGL(k_pals_shape<float>, grid, dim3(kBlock), 0, stream, op->gp, pp, (float*)mu);
   else
     return fail(HYDOT_EUNSUPPORTED, "pals_shape: mu_dtype must be F64 or F32");
+  HYDOT_HIP(hipGetLastError());
+  return HYDOT_OK;
+}
+
+hydot_status hydot_pals_shape_jacobian(const hydot_operator* op, const double* p, int32_t n_bumps,
+                                       const hydot_pals_opts* popts, void* jac, hydot_dtype jac_dtype,
+                                       hipStream_t stream) {
+  PalsP pp;
+  hydot_status s = make_pals(op, p, n_bumps, popts, pp);
+  if (s != HYDOT_OK) return s;
+  if (!jac) return fail(HYDOT_EINVAL, "pals_shape_jacobian: null jac");
+  const int N = op->gp.N;
+  dim3 grid((N + kBlock - 1) / kBlock);
+  if (jac_dtype == HYDOT_F64)
+    hipLaunchKernelGGL(k_pals_jacobian<double>, grid, dim3(kBlock), 0, stream, op->gp, pp, (double*)jac);
+  else if (jac_dtype == HYDOT_F32)
+    hipLaunchKernelGGL(k_pals_jacobian<float>, grid, dim3(kBlock), 0, stream, op->gp, pp, (float*)jac);
+  else
+    return fail(HYDOT_EUNSUPPORTED, "pals_shape_jacobian: jac_dtype must be F64 or F32");
   HYDOT_HIP(hipGetLastError());
   return HYDOT_OK;
 }
