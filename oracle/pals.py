@@ -4,9 +4,11 @@ Test infrastructure (see the package docstring); never used by the product.
 
 Shape (Sec. 5, eq. pals): chi(r) = H(varphi(r) - tau) with
 varphi(r) = sum_k alpha_k psi(beta_k ||r - chi_k||_dagger),
-||x||_dagger = sqrt(||x||^2 + nu^2).  The paper leaves psi, nu, tau and the
-smoothed Heaviside open; the readings used here are
-psi(t) = exp(-t^2), nu = 1e-3 mm, tau = 0.5 and the C^1 smoothed Heaviside
+||x||_dagger = sqrt(||x||^2 + nu^2).  The paper names compactly supported radial
+basis functions (those of the PaLS method it builds on) and leaves nu, tau and the
+smoothed Heaviside open; the readings used here are Wendland's C^2 function
+psi(t) = (1 - t)^4 (4t + 1) for t < 1, 0 beyond, nu = 1e-3 mm, tau = 0.5 and the
+C^1 smoothed Heaviside
 
     H_eps(x) = 0 (x < -eps), 1 (x > eps), (1 + x/eps + sin(pi x/eps)/pi)/2 otherwise,
     delta_eps(x) = (1 + cos(pi x/eps))/(2 eps) on |x| <= eps, 0 outside,
@@ -45,15 +47,25 @@ def _split(p):
     return n, p[:n], p[n:2 * n], np.stack([p[2 * n:3 * n], p[3 * n:4 * n], p[4 * n:5 * n]], axis=1)
 
 
+def psi(t):
+    t = np.asarray(t, dtype=np.float64)
+    return np.where(t < 1.0, (1.0 - t) ** 4 * (4.0 * t + 1.0), 0.0)
+
+
+def dpsi(t):
+    t = np.asarray(t, dtype=np.float64)
+    return np.where(t < 1.0, -20.0 * t * (1.0 - t) ** 3, 0.0)
+
+
 def level_function(r, p, nu):
     """varphi at points r [P, 3]; also returns per-bump pieces for the derivative."""
     n, alpha, beta, centre = _split(p)
     diff = r[:, None, :] - centre[None, :, :]               # [P, n, 3]
     dist = np.sqrt(np.sum(diff ** 2, axis=2) + nu ** 2)     # [P, n]
     t = beta[None, :] * dist
-    psi = np.exp(-t ** 2)
-    phi = psi @ alpha
-    return phi, (diff, dist, t, psi, alpha, beta)
+    ps = psi(t)
+    phi = ps @ alpha
+    return phi, (diff, dist, t, ps, alpha, beta)
 
 
 def shape(w, p, tau, eps, nu):
@@ -66,9 +78,9 @@ def shape(w, p, tau, eps, nu):
 def shape_jacobian(w, p, tau, eps, nu):
     """d mu / d p as a dense [N, 5n] matrix (chain rule of the definitions above)."""
     r = model.voxel_centres(w)
-    phi, (diff, dist, t, psi, alpha, beta) = level_function(r, p, nu)
-    dpsi_dt = -2.0 * t * psi                                 # psi'(t)
-    d_alpha = psi
+    phi, (diff, dist, t, ps, alpha, beta) = level_function(r, p, nu)
+    dpsi_dt = dpsi(t)
+    d_alpha = ps
     d_beta = alpha[None, :] * dpsi_dt * dist
     # d dist / d centre = -(r - centre)/dist
     common = alpha[None, :] * dpsi_dt * beta[None, :] / dist

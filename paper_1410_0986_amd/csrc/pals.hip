@@ -3,7 +3,9 @@
 // eq. measurement with co-located chromophores.
 //
 // Shape: mu(r) = H_eps(varphi(r) - tau), varphi(r) = sum_b alpha_b psi(beta_b ||r - chi_b||_dag),
-// psi(t) = exp(-t^2), ||x||_dag = sqrt(||x||^2 + nu^2), and the C^1 smoothed Heaviside
+// psi the compactly supported radial basis function of Wendland, psi(t) = (1 - t)^4 (4 t + 1) for
+// t < 1 and 0 beyond (C^2, support radius 1/beta_b), ||x||_dag = sqrt(||x||^2 + nu^2), and the C^1
+// smoothed Heaviside
 // H_eps(x) = (1 + x/eps + sin(pi x/eps)/pi)/2 on |x| <= eps (0 below, 1 above) whose
 // derivative is delta_eps(x) = (1 + cos(pi x/eps))/(2 eps).
 #include <algorithm>
@@ -30,12 +32,25 @@ __device__ inline void voxel_centre(const GridP& g, uint32_t n, double h, double
   z = (vi.k + 0.5) * h;
 }
 
+__device__ inline double rbf(double t) {
+  if (t >= 1.0) return 0.0;
+  const double u = 1.0 - t, u2 = u * u;
+  return u2 * u2 * (4.0 * t + 1.0);
+}
+
+// psi'(t) = -20 t (1 - t)^3 on t < 1.
+__device__ inline double rbf_deriv(double t) {
+  if (t >= 1.0) return 0.0;
+  const double u = 1.0 - t;
+  return -20.0 * t * u * u * u;
+}
+
 __device__ inline double level(const PalsP& p, double x, double y, double z) {
   double phi = 0.0;
   for (int b = 0; b < p.nb; ++b) {
     const double dx = x - p.cx[b], dy = y - p.cy[b], dz = z - p.cz[b];
-    const double d2 = dx * dx + dy * dy + dz * dz + p.nu * p.nu;
-    phi += p.alpha[b] * exp(-p.beta[b] * p.beta[b] * d2);
+    const double dist = sqrt(dx * dx + dy * dy + dz * dz + p.nu * p.nu);
+    phi += p.alpha[b] * rbf(p.beta[b] * dist);
   }
   return phi;
 }
@@ -78,8 +93,8 @@ __global__ __launch_bounds__(kBlock) void k_pals_vjp(GridP g, PalsP p, const G* 
       const double dx = x - p.cx[b], dy = y - p.cy[b], dz = z - p.cz[b];
       const double dist = sqrt(dx * dx + dy * dy + dz * dz + p.nu * p.nu);
       const double t = p.beta[b] * dist;
-      const double psi = exp(-t * t);
-      const double dpsi = -2.0 * t * psi;            // psi'(t)
+      const double psi = rbf(t);
+      const double dpsi = rbf_deriv(t);
       da = wgt * psi;
       dbeta = wgt * p.alpha[b] * dpsi * dist;
       const double common = wgt * p.alpha[b] * dpsi * p.beta[b] / dist;
@@ -125,8 +140,8 @@ __global__ __launch_bounds__(kBlock) void k_pals_jacobian(GridP g, PalsP p, R* j
       const double dx = x - p.cx[b], dy = y - p.cy[b], dz = z - p.cz[b];
       const double dist = sqrt(dx * dx + dy * dy + dz * dz + p.nu * p.nu);
       const double t = p.beta[b] * dist;
-      const double psi = exp(-t * t);
-      const double dpsi = -2.0 * t * psi;            // psi'(t)
+      const double psi = rbf(t);
+      const double dpsi = rbf_deriv(t);
       da = delta * psi;
       dbeta = delta * p.alpha[b] * dpsi * dist;
       const double common = delta * p.alpha[b] * dpsi * p.beta[b] / dist;

@@ -201,20 +201,20 @@ def pals_truth(w: Workload, n_bumps: int = PALS_BUMPS, seed: int = 2014):
     """Seeded 'true' PaLS parameters and contrasts.
 
     Returns (p, dconc) with p = [alpha(n), beta(n), cx(n), cy(n), cz(n)]:
-    centres U[1/3, 2/3] of the extent per axis, widths U[3, 8] mm (beta = 1/width),
+    centres U[1/3, 2/3] of the extent per axis, support radii U[8, 20] mm (beta = 1/radius),
     weights +-1 (Rademacher); dconc = (+8, +8) uM.
     """
     rng = np.random.default_rng(seed)
     ext = np.array([w.nx * w.h, w.ny * w.h, w.nz * w.h])
     centres = rng.uniform(1.0 / 3.0, 2.0 / 3.0, size=(n_bumps, 3)) * ext
-    widths = rng.uniform(3.0, 8.0, size=n_bumps)
+    widths = rng.uniform(8.0, 20.0, size=n_bumps)
     alpha = rng.choice([-1.0, 1.0], size=n_bumps)
     p = np.concatenate([alpha, 1.0 / widths, centres[:, 0], centres[:, 1], centres[:, 2]])
     return p, np.asarray(TRUTH_DCONC_UM, dtype=np.float64)
 
 
 def pals_perturbed(w: Workload, p_true: np.ndarray, dconc_true: np.ndarray, seed: int = 2015):
-    """Evaluation point away from the truth: centres +-2 mm, widths x(1+-0.1), alpha x0.9, dconc x0.8."""
+    """Evaluation point away from the truth: centres +-2 mm, radii x(1+-0.1), alpha x0.9, dconc x0.8."""
     n = p_true.shape[0] // 5
     rng = np.random.default_rng(seed)
     alpha = p_true[:n] * 0.9
