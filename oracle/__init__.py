@@ -19,7 +19,12 @@ Fantini, "Fast algorithms for hyperspectral diffuse optical tomography"):
                 model) and its products J v and J^H w;
 * ``pals``    - the parametric level-set shape (Sec. 5, eq. pals), its
                 derivative, the data misfit (Sec. 5, eq. minimization) and its
-                gradient.
+                gradient;
+* ``compress``    - the recursive randomized compression of an explicit H
+                    (Sec. 4 and its appendix);
+* ``reconstruct`` - Alg. opt on an explicit H: contrast least squares and
+                    Levenberg-Marquardt steps on the PaLS parameters with
+                    discrepancy-principle stopping (Sec. 5).
 
 Every pin against the paper and the mathematics lives in ``tests/``.
 """
