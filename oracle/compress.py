@@ -9,7 +9,9 @@ Test infrastructure (see the package docstring); never used by the product.
                      columns of one Gaussian matrix Omega_1 at rank r, and Omega_2 fixed;
 * ``agglomerate``  - blockdiag(U_i) [V_1^H; V_2^H] with the stacked right factors truncated
                      by a full SVD at relative tolerance eps;
-* ``recursive``    - Alg. recursive over the tree.
+* ``recursive``    - Alg. recursive over the tree;
+* ``recompress``   - the closing recompression of U V^H (Sec. 4, accuracy of the recursion):
+                     thin QR of both factors, SVD of R_U R_V^H, truncation at eps.
 
 Readings shared with the library: the rank is doubled when the error estimate fails ("increment
 r"), a leaf of the tree (at most two sources) factors each source's block and then agglomerates
@@ -104,3 +106,13 @@ def recursive(blocks, node, eps, omega1, omega2, p=20, ranks=None):
             ranks.setdefault(depth, []).append(U.shape[1])
         return U, V, order
     return go(node, 0)
+
+
+def recompress(U, V, eps):
+    """U V^H -> (Q_U U'_r, Q_V V'_r S'_r) keeping the singular values of R_U R_V^H above
+    eps times the largest."""
+    Qu, Ru = np.linalg.qr(U)
+    Qv, Rv = np.linalg.qr(V)
+    Up, sp, Vph = np.linalg.svd(Ru @ Rv.conj().T)
+    keep = max(1, int(np.sum(sp > eps * sp[0])))
+    return Qu @ Up[:, :keep], (Qv @ Vph[:keep].conj().T) * sp[None, :keep]

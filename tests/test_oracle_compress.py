@@ -97,3 +97,23 @@ def test_recursive_compression_of_born_matrix_against_svd():
         assert np.linalg.norm(Hr - U @ V.conj().T, 2) <= 10 * eps * sH[0]
         eps_rank = int(np.sum(sH > eps * sH[0]))
         assert U.shape[1] <= 2 * eps_rank + 4
+
+
+def test_recompress_is_the_truncated_svd_of_the_product():
+    """The QR-based recompression must give the best rank-k approximation of U V^H, i.e. the
+    dense product's own truncated SVD (a textbook routine on the formed matrix)."""
+    rng = np.random.default_rng(4)
+    m, n, r = 90, 150, 24
+    s = 10.0 ** -np.linspace(0, 8, r)
+    U = (rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r))) * s[None, :]
+    V = rng.standard_normal((n, r)) + 1j * rng.standard_normal((n, r))
+    A = U @ V.conj().T
+    Ua, sa, Vah = np.linalg.svd(A, full_matrices=False)
+    for eps in (1e-3, 1e-6):
+        U2, V2 = compress.recompress(U, V, eps)
+        k = int(np.sum(sa > eps * sa[0]))
+        assert U2.shape[1] == k
+        best = (Ua[:, :k] * sa[:k]) @ Vah[:k]
+        assert np.linalg.norm(U2 @ V2.conj().T - best) <= 1e-9 * sa[0]
+        np.testing.assert_allclose(U2.conj().T @ U2, np.eye(k), atol=1e-12)
+        np.testing.assert_allclose(np.linalg.norm(V2, axis=0), sa[:k], rtol=1e-9)
