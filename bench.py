@@ -298,12 +298,49 @@ def main():
         derr = float(torch.linalg.vector_norm(dy - yprobe) / torch.linalg.vector_norm(yprobe))
         compression = {"eps": 1e-3, "rows": S * L * D, "cols": N,
                        "recursive": {"seconds": round(cb.seconds, 3), "rank": cb.rank,
+                                     "rank_before_recompression": cb.recursive_rank,
                                      "level_ranks": {str(k): v for k, v in sorted(cb.level_ranks.items())},
                                      "probe_rel_err": float(f"{cerr:.3g}"), "H_columns_applied": cb.products},
                        "direct_randsvd": {"seconds": round(tdir, 3), "rank": lr.rank,
                                           "probe_rel_err": float(f"{derr:.3g}"), "H_columns_applied": lr.products}}
-        del cb, lr, om1
+        del lr
         log("compression done")
+
+        # reconstruction (Sec. 5, Alg. opt) on these fields: Exp. 1 analogue (3 bumps, known
+        # contrasts, 33 dB, full H against H compressed at 1e-3 and 1e-6) and Exp. 2 analogue
+        # (contrasts too, 30 dB, random start, H compressed at 1e-6); data from the full H
+        from paper_1410_0986_amd import reconstruct as hrec
+        cbs = {1e-3: cb, 1e-6: hcompress.compress(op, phi[:, :S], phi[:, S:], xy, 1e-6, om1, om2)}
+        del om1
+        p3, _ = workloads.pals_truth(w, n_bumps=3)
+        mu3 = hd.pals_shape(op, p3, dtype=torch.float32, device=dev)
+        full_model = hrec.BornModel(op, phi[:, :S], phi[:, S:], w.extinction)
+        y_clean = (dc_true @ w.extinction)[:, None, None] * full_model.H(mu3[None])[0]
+        mu3_np = mu3.double().cpu().numpy()
+
+        def recon(model, snr_db, p0, fix_c):
+            eta = workloads.observed_noise(y_clean.shape, 10 ** (-snr_db / 20) * np.linalg.norm(y_clean)
+                                           / np.sqrt(y_clean.size), seed=34 + int(snr_db))
+            r = hrec.reconstruct(model, y_clean + eta, p0, c0=dc_true if fix_c else None,
+                                 noise_norm=float(np.linalg.norm(eta)), fix_c=fix_c, max_outer=300)
+            mu_r = hd.pals_shape(op, r.p, device=dev).cpu().numpy()
+            l2, dice = hrec.shape_errors(mu3_np, mu_r)
+            return {"L2_err": round(l2, 4), "dice": round(dice, 3), "seconds": round(r.seconds, 3),
+                    "outer": r.outer, "lm_steps": r.lm_steps, "stopped_by": r.stopped_by,
+                    "conc_rel_err": [round(abs(a - b) / abs(b), 4) for a, b in zip(r.c, dc_true)]}
+
+        p_start, _ = workloads.pals_perturbed(w, p3, dc_true)
+        exp1 = {"full_H": recon(full_model, 33.0, p_start, True)}
+        for e_, cbe in cbs.items():
+            mdl = hrec.BornModel(op, phi[:, :S], phi[:, S:], w.extinction, compressed=cbe)
+            exp1[f"{e_:g}"] = {"rank": cbe.rank, "compress_seconds": round(cbe.seconds, 3),
+                               **recon(mdl, 33.0, p_start, True)}
+        mdl6 = hrec.BornModel(op, phi[:, :S], phi[:, S:], w.extinction, compressed=cbs[1e-6])
+        exp2 = recon(mdl6, 30.0, workloads.pals_random_start(w, 3), False)
+        reconstruction = {"measurements": S * D * L, "n_p": 15, "exp1_shape_only_33dB": exp1,
+                          "exp2_shape_and_conc_30dB_random_start_eps1e-6": exp2}
+        del cb, cbs, mdl6
+        log("reconstruction done")
 
 
         plain = None
@@ -377,6 +414,7 @@ def main():
         "forward_heterogeneous": forward,
         "boundary_shift_study": study,
         "compression": compression,
+        "reconstruction": reconstruction,
         "plain_fp64": plain,
         "speedup_vs_plain": round(solves_per_s / plain["solves_per_s"], 2) if plain else None,
         "roofline": roof,

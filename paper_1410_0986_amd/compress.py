@@ -18,7 +18,10 @@ GPU in FP64 through torch.linalg.
 * ``agglomerate``      - two (or more) children H_i ~ U_i V_i^H combine as
   blockdiag(U_i) [V_1^H; V_2^H]; the stacked right factors are recompressed to tolerance eps
   (a truncated SVD through a thin QR) and the left factor is formed explicitly.
-* ``compress``         - RecursiveLowRank over the tree (Alg. recursive), returning H ~ U V^H.
+* ``recompress``       - the closing step of Sec. 4 (accuracy of the recursion): thin QR of both
+  factors, SVD of R_U R_V^H and truncation, which can lower the rank the local truncations left.
+* ``compress``         - RecursiveLowRank over the tree (Alg. recursive) followed by
+  ``recompress``, returning H ~ U V^H.
 """
 from __future__ import annotations
 
@@ -168,6 +171,16 @@ def agglomerate(parts: list, eps: float) -> LowRank:
                    products=sum(pt.products for pt in parts))
 
 
+def recompress(U: torch.Tensor, V: torch.Tensor, eps: float):
+    """U V^H -> (Q_U U'_r, Q_V V'_r S'_r): the singular values of R_U R_V^H above eps times the
+    largest are kept (folded into the right factor)."""
+    Qu, Ru = torch.linalg.qr(U)
+    Qv, Rv = torch.linalg.qr(V)
+    Up, sp, Vph = torch.linalg.svd(Ru @ Rv.conj().T)
+    keep = max(1, int((sp > eps * sp[0]).sum().item()))
+    return Qu @ Up[:, :keep], (Qv @ Vph[:keep].conj().T) * sp[None, :keep].to(V.dtype)
+
+
 # -------------------------------------------------------------------- driver
 @dataclass
 class CompressedBorn:
@@ -177,22 +190,29 @@ class CompressedBorn:
     level_ranks: dict          # tree depth -> ranks of the nodes at that depth
     seconds: float
     products: int
+    recursive_rank: int = 0    # rank before the closing recompression
 
     @property
     def rank(self) -> int:
         return self.U.shape[1]
 
     def matvec(self, v: torch.Tensor) -> torch.Tensor:
-        """H v for real v [n_v, N] -> [n_v, S*L*D] (rows (s, l, d))."""
-        return (self.U @ (self.V.conj().T @ v.to(torch.complex128).T)).T
+        """H v for real v [n_v, N] -> [n_v, S*L*D] (rows (s, l, d)).  For real v,
+        V^H v = conj(V^T v): the transposed view goes to the GEMM as is, so the conjugate of the
+        N x R factor is never formed."""
+        if v.is_complex():
+            raise ValueError("matvec takes real probe vectors")
+        return (self.U @ (self.V.T @ v.to(self.V.dtype).T).conj()).T
 
 
 def compress(op: B.Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, src_xy: np.ndarray, eps: float,
-             omega1: np.ndarray, omega2: np.ndarray, box_lo=None, box_hi=None, p: int = 20) -> CompressedBorn:
+             omega1: np.ndarray, omega2: np.ndarray, box_lo=None, box_hi=None, p: int = 20,
+             final_recompress: bool = True) -> CompressedBorn:
     """RecursiveLowRank (Alg. recursive) of H over the bisection tree of the source positions.
 
     omega1 [N, c1] and omega2 [N, k]: Gaussian test matrices shared by every leaf (c1 bounds the
-    leaf rank plus oversampling).  box_lo/box_hi: the plate box (default: the sources' bounding box)."""
+    leaf rank plus oversampling).  box_lo/box_hi: the plate box (default: the sources' bounding box).
+    final_recompress: apply ``recompress`` at eps to the root's factors."""
     t0 = time.perf_counter()
     dev = phi_src.device
     lo = src_xy.min(axis=0) if box_lo is None else box_lo
@@ -219,9 +239,12 @@ def compress(op: B.Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, src_x
     blk = L * D
     pos = {s: a for a, s in enumerate(lr.sources)}
     U = torch.cat([lr.U[pos[s] * blk:(pos[s] + 1) * blk] for s in range(len(src_xy))], dim=0)
+    V = lr.V
+    if final_recompress:
+        U, V = recompress(U, V, eps)
     torch.cuda.synchronize(dev)
-    return CompressedBorn(U=U, V=lr.V, tree=tree, level_ranks=levels, seconds=time.perf_counter() - t0,
-                          products=lr.products)
+    return CompressedBorn(U=U, V=V, tree=tree, level_ranks=levels, seconds=time.perf_counter() - t0,
+                          products=lr.products, recursive_rank=lr.rank)
 
 
 def randsvd_direct(op: B.Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, eps: float, omega1: np.ndarray,

@@ -66,7 +66,8 @@ def _oracle(w, P, eps, om1, om2):
     pos = {s: a for a, s in enumerate(order)}
     blk = w.L * w.D
     Un = np.concatenate([U[pos[s] * blk:(pos[s] + 1) * blk] for s in range(S)], axis=0)
-    return tree, ranks, Un @ V.conj().T, H
+    Ur, Vr = ocompress.recompress(Un, V, eps)
+    return tree, ranks, (Un @ V.conj().T, U.shape[1]), (Ur @ Vr.conj().T, Ur.shape[1]), H
 
 
 @pytest.mark.parametrize("eps", [1e-2, 1e-4])
@@ -75,14 +76,21 @@ def test_compression_matches_oracle_fp64(hd, case, eps):
     w, P = case
     S = w.S
     om1, om2 = workloads.gaussian_test_matrix(w.N, 40), workloads.gaussian_test_matrix(w.N, 10, seed=5)
-    tree, ranks, UVo, H = _oracle(w, P, eps, om1, om2)
+    tree, ranks, (UVo, ro), (UVf, rf), H = _oracle(w, P, eps, om1, om2)
     t = torch.from_numpy(P).to(DEV)
     xy = workloads.optode_xy(w, w.src_voxels)
-    cb = compress.compress(hd_op(hd, w), t[:, :S], t[:, S:], xy, eps, om1, om2)
+    op = hd_op(hd, w)
+    cb = compress.compress(op, t[:, :S], t[:, S:], xy, eps, om1, om2, final_recompress=False)
     assert cb.tree == tree
     assert {k: sorted(v) for k, v in cb.level_ranks.items()} == {k: sorted(v) for k, v in ranks.items()}
+    assert cb.rank == ro
     UV = (cb.U @ cb.V.conj().T).cpu().numpy()
     assert np.linalg.norm(UV - UVo) <= 1e-9 * np.linalg.norm(UVo)
+    assert np.linalg.norm(H - UV, 2) <= 10 * eps * np.linalg.norm(H, 2)
+    cf = compress.compress(op, t[:, :S], t[:, S:], xy, eps, om1, om2)       # with the closing recompression
+    assert cf.rank == rf and cf.recursive_rank == ro and rf <= ro
+    UV = (cf.U @ cf.V.conj().T).cpu().numpy()
+    assert np.linalg.norm(UV - UVf) <= 1e-9 * np.linalg.norm(UVf)
     assert np.linalg.norm(H - UV, 2) <= 10 * eps * np.linalg.norm(H, 2)
 
 

@@ -226,6 +226,16 @@ def pals_perturbed(w: Workload, p_true: np.ndarray, dconc_true: np.ndarray, seed
     return p, np.asarray(dconc_true, dtype=np.float64) * 0.8
 
 
+def pals_random_start(w: Workload, n_bumps: int, seed: int = 2016) -> np.ndarray:
+    """Randomly initialised PaLS parameters: centres U[1/3, 2/3] of the extent, support radii
+    U[8, 20] mm, weights +1."""
+    rng = np.random.default_rng(seed)
+    ext = np.array([w.nx * w.h, w.ny * w.h, w.nz * w.h])
+    centres = rng.uniform(1.0 / 3.0, 2.0 / 3.0, size=(n_bumps, 3)) * ext
+    radii = rng.uniform(8.0, 20.0, size=n_bumps)
+    return np.concatenate([np.ones(n_bumps), 1.0 / radii, centres[:, 0], centres[:, 1], centres[:, 2]])
+
+
 def observed_noise(shape, scale: float, seed: int = 33) -> np.ndarray:
     """Complex Gaussian noise with per-component standard deviation scale/sqrt(2)."""
     rng = np.random.default_rng(seed)
