@@ -8,9 +8,13 @@ Readings (the algorithm box leaves these open or prints them garbled):
   (the stopping rule of the text); an outer pass also ends when its LM steps gained less than a
   relative 1e-6 (noise-free data never meet a zero target), and an inner pass after max_inner
   steps or a step that no damping could make descend;
-* the LM damping starts at 1e-3 max diag(J^T J), is divided by 10 after an accepted step
-  (floor 1e-12) and multiplied by 10 after a rejected one (at most 12 tries per step); a step
-  is accepted when it lowers the misfit at the current contrasts;
+* the damping term of the LM step is nu diag(J^T J) (Marquardt's scaling; the printed step
+  shows nu I, which is the same step in parameters scaled to unit curvature): the parameters
+  have unrelated units (alpha none, beta 1/mm, centres mm) and their Jacobian columns differ by
+  orders of magnitude, and with nu I the iteration stalls long before the discrepancy level;
+  nu starts at 1e-3, is divided by 10 after an accepted step (floor 1e-12) and multiplied by
+  10 after a rejected one (at most 12 tries per step); a step is accepted when it lowers the
+  misfit at the current contrasts;
 * the complex residual and Jacobian are split into real and imaginary parts, so the unknowns
   stay real;
 * after the discrepancy stop the contrasts are refitted once more at the final shape.
@@ -70,11 +74,12 @@ def reconstruct(H, w, ext, y, p0, c0=None, W=1.0, noise_norm=0.0, gamma=1.05, ma
             r = (W * (y - (c @ ext)[:, None, None] * Hmu)).ravel()
             e = np.concatenate([r.real, r.imag])
             JTJ = J.T @ J
+            scale = np.diag(JTJ.diagonal())
             if damp is None:
-                damp = 1e-3 * JTJ.diagonal().max()
+                damp = 1e-3
             ok = False
             for _ in range(12):
-                step = np.linalg.solve(JTJ + damp * np.eye(len(p)), -(J.T @ e))
+                step = np.linalg.solve(JTJ + damp * scale, -(J.T @ e))
                 _, Hm = forward_parts(H, w, p + step, tau, eps, nu)
                 ft = misfit(c, Hm)
                 if ft < f:

@@ -2,6 +2,10 @@
 Alg. opt): alternate the linear least-squares solve for the contrasts c with Levenberg-Marquardt
 steps for the shape parameters p, stopping by the discrepancy principle.
 
+The LM step is (J^T J + nu diag(J^T J)) dp = -J^T eps (Marquardt's scaling of the damping,
+which makes the step independent of the parameters' units), nu from 1e-3, /10 after an accepted
+step, x10 after a rejected one.
+
 Data model (eq. measurement, eq. minimization): y[l, s, d] = sum_i c_i eps_i(lambda_l) (H mu(p))[l, s, d]
 + noise, residual eps = W (y - D(p) c) with the columns of D(p) = E_i H mu(p).  The LM Jacobian is
 J = d eps / d p = -W Ebar H (d mu / d p): the shape Jacobian (hydot_pals_shape_jacobian) is a block
@@ -133,11 +137,12 @@ def reconstruct(model: BornModel, y: np.ndarray, p0: np.ndarray, c0=None, noise_
             e = _stack(r.reshape(-1)[None])[0]
             JTJ = J.T @ J
             g = J.T @ e
+            scale = np.diag(np.diag(JTJ))                          # Marquardt's scaling
             if nu is None:
-                nu = lm_nu0 * float(np.max(np.diag(JTJ)))
+                nu = lm_nu0
             accepted = False
             for _try in range(12):                                 # Levenberg-Marquardt damping
-                dp = np.linalg.solve(JTJ + nu * np.eye(JTJ.shape[0]), -g)
+                dp = np.linalg.solve(JTJ + nu * scale, -g)
                 p_try = p + dp
                 Hmu_try = model.Hmu(p_try)
                 r_try = residual(model, c, Hmu_try, y)
