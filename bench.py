@@ -40,8 +40,10 @@ N_JAC = 42                  # Jacobian block: 2 chromophore contrasts + 40 PaLS 
 # from the FETCH_SIZE / WRITE_SIZE runs summarised in profiles/step_kernels_medium_traffic.md.
 # They belong to the kernel sources with this SHA-256 (common.h, krylov_kernels.h,
 # krylov_tiled.h); after any change to those the traffic is reported as null.
-TRAFFIC_SOURCES_SHA256 = "bedc69c90329be4e23389b1dfc32a5f7d68bfd4e67cc318cf8935ddac0cd472f"
-TRAFFIC_BYTES_PER_LAUNCH = {"k_step_dots_t": 6.704e9, "k_step_update_t": 7.049e9, "k_step_finish_t": 8.3e4}
+# They also hold only for the launch shape they were taken with (TRAFFIC_TUNING).
+TRAFFIC_SOURCES_SHA256 = "4bcddb648b3149ac06e0850059fc2f447415bb6d30a6a7697c9ad60889c5cedf"
+TRAFFIC_TUNING = {"step_presum": 4, "step_order": 2, "step_group": 2, "step_vx": 1}
+TRAFFIC_BYTES_PER_LAUNCH = {"k_step_dots_t": 7.155e9, "k_step_update_t": 6.208e9, "k_step_finish_t": 1.18e6}
 
 
 def kernel_sources_sha256() -> str:
@@ -95,6 +97,11 @@ def main():
     ap.add_argument("--config", default="medium", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-system FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", default="",
+                    help="launch-shape fields set after the autotuner, e.g. step_order=3,step_group=2")
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip the secondary measurements after the Born variants (heterogeneous forward, "
+                         "boundary/shift study, compression, reconstruction), e.g. under a profiler")
     ap.add_argument("--cpu-sample", type=int, default=10, help="systems in the CPU oracle sample")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="finish with one device-to-device copy of this many GiB (counter calibration)")
@@ -138,6 +145,9 @@ def main():
         for t, ms in solve_trials:
             log(f"  presum {t['step_presum']} vx {t['step_vx']} order {t['step_order']} group {t['step_group']}: "
                 f"{ms:.1f} ms")
+        if args.tuning:
+            hd.set_tuning(op, **{k: int(x) for k, x in (kv.split("=") for kv in args.tuning.split(","))})
+            log(f"tuning set to {hd.get_tuning(op)}")
         # observed data of the PaLS model at the truth (set-up, not timed)
         solve()
         born_trials = hd.autotune_born(op, phi[:, :S], phi[:, S:], v)
@@ -228,119 +238,124 @@ def main():
         del phi_bf, phi64
         log("born variants done")
 
-        # full forward model with the PaLS anomaly at the true contrast (not part of the step):
-        # throughput of the recycled solver on the heterogeneous operator, and the Born validity
-        # (relative mismatch of the detector-data change against the Born prediction)
-        det = torch.from_numpy(np.asarray(w.det_voxels)).to(dev)
-        d0 = phi[:, :S][:, :, det].to(torch.complex128)
-        shape_t = hd.pals_shape(op, p_true, device=dev)
-        Jmu64 = hd.born_apply(op, phi[:, :S].to(torch.complex128), phi[:, S:].to(torch.complex128),
-                              shape_t[None])[0]
-        ebar_true = dc_true @ w.extinction
-        op.set_absorption_perturbation(shape_t.cpu().numpy(), ebar_true)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        _, fit, frel, fst = hd.solve_fields(op, vox, opts, out=phi)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        dfull = phi[:, :S][:, :, det].to(torch.complex128) - d0
-        pred = torch.from_numpy(ebar_true).to(dev)[:, None, None] * Jmu64
-        born_mismatch = float(torch.linalg.vector_norm(dfull - pred) / torch.linalg.vector_norm(dfull))
-        op.set_absorption_perturbation(None, None)
+        forward = study = compression = reconstruction = None
+        if not args.no_studies:
+            # full forward model with the PaLS anomaly at the true contrast (not part of the step):
+            # throughput of the recycled solver on the heterogeneous operator, and the Born validity
+            # (relative mismatch of the detector-data change against the Born prediction)
+            det = torch.from_numpy(np.asarray(w.det_voxels)).to(dev)
+            d0 = phi[:, :S][:, :, det].to(torch.complex128)
+            shape_t = hd.pals_shape(op, p_true, device=dev)
+            Jmu64 = hd.born_apply(op, phi[:, :S].to(torch.complex128), phi[:, S:].to(torch.complex128),
+                                  shape_t[None])[0]
+            ebar_true = dc_true @ w.extinction
+            op.set_absorption_perturbation(shape_t.cpu().numpy(), ebar_true)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, fit, frel, fst = hd.solve_fields(op, vox, opts, out=phi)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            dfull = phi[:, :S][:, :, det].to(torch.complex128) - d0
+            pred = torch.from_numpy(ebar_true).to(dev)[:, None, None] * Jmu64
+            born_mismatch = float(torch.linalg.vector_norm(dfull - pred) / torch.linalg.vector_norm(dfull))
+            op.set_absorption_perturbation(None, None)
 
-        forward = {"solves_per_s": round(R * L / (tb - ta), 1), "max_rel_res": float(frel.max()),
-                   "mean_iters": float(fit.mean()),
-                   "born_relative_mismatch_at_detectors": float(f"{born_mismatch:.3g}"),
-                   "anomaly": "PaLS truth (8 bumps), contrast dc = (8, 8) uM"}
-        log("heterogeneous forward done")
+            forward = {"solves_per_s": round(R * L / (tb - ta), 1), "max_rel_res": float(frel.max()),
+                       "mean_iters": float(fit.mean()),
+                       "born_relative_mismatch_at_detectors": float(f"{born_mismatch:.3g}"),
+                       "anomaly": "PaLS truth (8 bumps), contrast dc = (8, 8) uM"}
+            log("heterogeneous forward done")
 
-        # boundary split and shift-variant study (Sec. 6.1 setting): the paper's plates (Robin on
-        # the top and bottom faces, Dirichlet on the sides) with sigma' moved into K_hat as its mean,
-        # minimum, maximum or not at all, against the all-Robin box with the mean shift
-        study = {}
-        wb = workloads.config(args.config, robin_faces=0x30)
-        opb = hd.Operator.from_workload(wb)
-        for bname, bop, shifts in (("all_robin", op, ("mean",)), ("robin_top_bottom", opb, ("mean", "min", "max", "none"))):
-            for sname in shifts:
-                fl = {"mean": hd.FLAG_MEAN_SHIFT, "min": hd.FLAG_SHIFT_MIN, "max": hd.FLAG_SHIFT_MAX,
-                      "none": 0}[sname] | hd.FLAG_GRAPH
-                so = hd.SolveOptions(rel_tol=1e-8, restart_m=RESTART_M, recycle_k=RECYCLE_K, lanczos_n=LANCZOS_N,
-                                     precision=hd.PREC_MIXED, inner_tol=1e-5, flags=fl, max_iter=5000)
-                torch.cuda.synchronize()
-                ta = time.perf_counter()
-                _, sit, srel, sst = hd.solve_fields(bop, vox, so, out=phi)
-                torch.cuda.synchronize()
-                tb = time.perf_counter()
-                study[f"{bname}/{sname}"] = {"solves_per_s": round(R * L / (tb - ta), 1),
-                                             "mean_iters": round(float(sit.mean()), 2),
-                                             "max_rel_res": float(srel.max())}
-        del opb
-        log("boundary/shift study done")
+            # boundary split and shift-variant study (Sec. 6.1 setting): the paper's plates (Robin on
+            # the top and bottom faces, Dirichlet on the sides) with sigma' moved into K_hat as its mean,
+            # minimum, maximum or not at all, against the all-Robin box with the mean shift
+            study = {}
+            wb = workloads.config(args.config, robin_faces=0x30)
+            opb = hd.Operator.from_workload(wb)
+            for bname, bop, shifts in (("all_robin", op, ("mean",)), ("robin_top_bottom", opb, ("mean", "min", "max", "none"))):
+                for sname in shifts:
+                    fl = {"mean": hd.FLAG_MEAN_SHIFT, "min": hd.FLAG_SHIFT_MIN, "max": hd.FLAG_SHIFT_MAX,
+                          "none": 0}[sname] | hd.FLAG_GRAPH
+                    so = hd.SolveOptions(rel_tol=1e-8, restart_m=RESTART_M, recycle_k=RECYCLE_K, lanczos_n=LANCZOS_N,
+                                         precision=hd.PREC_MIXED, inner_tol=1e-5, flags=fl, max_iter=5000)
+                    torch.cuda.synchronize()
+                    ta = time.perf_counter()
+                    _, sit, srel, sst = hd.solve_fields(bop, vox, so, out=phi)
+                    torch.cuda.synchronize()
+                    tb = time.perf_counter()
+                    study[f"{bname}/{sname}"] = {"solves_per_s": round(R * L / (tb - ta), 1),
+                                                 "mean_iters": round(float(sit.mean()), 2),
+                                                 "max_rel_res": float(srel.max())}
+            del opb
+            log("boundary/shift study done")
 
-        # randomized compression of H (Sec. 4): recursive over the source bisection tree against one
-        # randomized SVD of the whole H, tolerance 1e-3, error measured with fresh probe vectors
-        from paper_1410_0986_amd import compress as hcompress
-        hd.solve_fields(op, vox, opts, out=phi)
-        xy = workloads.optode_xy(w, w.src_voxels)
-        om1 = workloads.gaussian_test_matrix(N, 700)
-        om2 = workloads.gaussian_test_matrix(N, 10, seed=workloads.COMPRESS_SEED + 1)
-        vprobe = torch.from_numpy(workloads.born_v(w, n_v=8, seed=99, dtype=np.float32)).to(dev)
-        yprobe = hd.born_apply(op, phi[:, :S], phi[:, S:], vprobe).permute(0, 2, 1, 3).reshape(8, -1)
-        yprobe = yprobe.to(torch.complex128)
-        cb = hcompress.compress(op, phi[:, :S], phi[:, S:], xy, 1e-3, om1[:, :300], om2)
-        cerr = float(torch.linalg.vector_norm(cb.matvec(vprobe) - yprobe) / torch.linalg.vector_norm(yprobe))
-        torch.cuda.synchronize()
-        td = time.perf_counter()
-        lr = hcompress.randsvd_direct(op, phi[:, :S], phi[:, S:], 1e-3, om1, om2)
-        torch.cuda.synchronize()
-        tdir = time.perf_counter() - td
-        dy = (lr.U @ (lr.V.conj().T @ vprobe.to(torch.complex128).T)).T
-        derr = float(torch.linalg.vector_norm(dy - yprobe) / torch.linalg.vector_norm(yprobe))
-        compression = {"eps": 1e-3, "rows": S * L * D, "cols": N,
-                       "recursive": {"seconds": round(cb.seconds, 3), "rank": cb.rank,
-                                     "rank_before_recompression": cb.recursive_rank,
-                                     "level_ranks": {str(k): v for k, v in sorted(cb.level_ranks.items())},
-                                     "probe_rel_err": float(f"{cerr:.3g}"), "H_columns_applied": cb.products},
-                       "direct_randsvd": {"seconds": round(tdir, 3), "rank": lr.rank,
-                                          "probe_rel_err": float(f"{derr:.3g}"), "H_columns_applied": lr.products}}
-        del lr
-        log("compression done")
+            # randomized compression of H (Sec. 4): recursive over the source bisection tree against one
+            # randomized SVD of the whole H, tolerance 1e-3, error measured with fresh probe vectors
+            from paper_1410_0986_amd import compress as hcompress
+            hd.solve_fields(op, vox, opts, out=phi)
+            xy = workloads.optode_xy(w, w.src_voxels)
+            om1 = workloads.gaussian_test_matrix(N, 700)
+            om2 = workloads.gaussian_test_matrix(N, 10, seed=workloads.COMPRESS_SEED + 1)
+            vprobe = torch.from_numpy(workloads.born_v(w, n_v=8, seed=99, dtype=np.float32)).to(dev)
+            yprobe = hd.born_apply(op, phi[:, :S], phi[:, S:], vprobe).permute(0, 2, 1, 3).reshape(8, -1)
+            yprobe = yprobe.to(torch.complex128)
+            cb = hcompress.compress(op, phi[:, :S], phi[:, S:], xy, 1e-3, om1[:, :300], om2)
+            cerr = float(torch.linalg.vector_norm(cb.matvec(vprobe) - yprobe) / torch.linalg.vector_norm(yprobe))
+            torch.cuda.synchronize()
+            td = time.perf_counter()
+            lr = hcompress.randsvd_direct(op, phi[:, :S], phi[:, S:], 1e-3, om1, om2)
+            torch.cuda.synchronize()
+            tdir = time.perf_counter() - td
+            dy = (lr.U @ (lr.V.conj().T @ vprobe.to(torch.complex128).T)).T
+            derr = float(torch.linalg.vector_norm(dy - yprobe) / torch.linalg.vector_norm(yprobe))
+            compression = {"eps": 1e-3, "rows": S * L * D, "cols": N,
+                           "recursive": {"seconds": round(cb.seconds, 3), "rank": cb.rank,
+                                         "rank_before_recompression": cb.recursive_rank,
+                                         "level_ranks": {str(k): v for k, v in sorted(cb.level_ranks.items())},
+                                         "probe_rel_err": float(f"{cerr:.3g}"), "H_columns_applied": cb.products},
+                           "direct_randsvd": {"seconds": round(tdir, 3), "rank": lr.rank,
+                                              "probe_rel_err": float(f"{derr:.3g}"), "H_columns_applied": lr.products}}
+            del lr
+            log("compression done")
 
-        # reconstruction (Sec. 5, Alg. opt) on these fields: Exp. 1 analogue (3 bumps, known
-        # contrasts, 33 dB, full H against H compressed at 1e-3 and 1e-6) and Exp. 2 analogue
-        # (contrasts too, 30 dB, random start, H compressed at 1e-6); data from the full H
-        from paper_1410_0986_amd import reconstruct as hrec
-        cbs = {1e-3: cb, 1e-6: hcompress.compress(op, phi[:, :S], phi[:, S:], xy, 1e-6, om1, om2)}
-        del om1
-        p3, _ = workloads.pals_truth(w, n_bumps=3)
-        mu3 = hd.pals_shape(op, p3, dtype=torch.float32, device=dev)
-        full_model = hrec.BornModel(op, phi[:, :S], phi[:, S:], w.extinction)
-        y_clean = (dc_true @ w.extinction)[:, None, None] * full_model.H(mu3[None])[0]
-        mu3_np = mu3.double().cpu().numpy()
+            # reconstruction (Sec. 5, Alg. opt) on these fields: Exp. 1 analogue (3 bumps, known
+            # contrasts, 33 dB, full H against H compressed at 1e-3 and 1e-6) and Exp. 2 analogue
+            # (contrasts too, 30 dB, random start, H compressed at 1e-6); data from the full H
+            from paper_1410_0986_amd import reconstruct as hrec
+            cbs = {1e-3: cb, 1e-6: hcompress.compress(op, phi[:, :S], phi[:, S:], xy, 1e-6, om1, om2)}
+            log("compression at 1e-6 done")
+            del om1
+            p3, _ = workloads.pals_truth(w, n_bumps=3)
+            mu3 = hd.pals_shape(op, p3, dtype=torch.float32, device=dev)
+            full_model = hrec.BornModel(op, phi[:, :S], phi[:, S:], w.extinction)
+            y_clean = (dc_true @ w.extinction)[:, None, None] * full_model.H(mu3[None])[0]
+            mu3_np = mu3.double().cpu().numpy()
 
-        def recon(model, snr_db, p0, fix_c):
-            eta = workloads.observed_noise(y_clean.shape, 10 ** (-snr_db / 20) * np.linalg.norm(y_clean)
-                                           / np.sqrt(y_clean.size), seed=34 + int(snr_db))
-            r = hrec.reconstruct(model, y_clean + eta, p0, c0=dc_true if fix_c else None,
-                                 noise_norm=float(np.linalg.norm(eta)), fix_c=fix_c, max_outer=300)
-            mu_r = hd.pals_shape(op, r.p, device=dev).cpu().numpy()
-            l2, dice = hrec.shape_errors(mu3_np, mu_r)
-            return {"L2_err": round(l2, 4), "dice": round(dice, 3), "seconds": round(r.seconds, 3),
-                    "outer": r.outer, "lm_steps": r.lm_steps, "stopped_by": r.stopped_by,
-                    "conc_rel_err": [round(abs(a - b) / abs(b), 4) for a, b in zip(r.c, dc_true)]}
+            def recon(model, snr_db, p0, fix_c):
+                eta = workloads.observed_noise(y_clean.shape, 10 ** (-snr_db / 20) * np.linalg.norm(y_clean)
+                                               / np.sqrt(y_clean.size), seed=34 + int(snr_db))
+                r = hrec.reconstruct(model, y_clean + eta, p0, c0=dc_true if fix_c else None,
+                                     noise_norm=float(np.linalg.norm(eta)), fix_c=fix_c, max_outer=300)
+                mu_r = hd.pals_shape(op, r.p, device=dev).cpu().numpy()
+                l2, dice = hrec.shape_errors(mu3_np, mu_r)
+                return {"L2_err": round(l2, 4), "dice": round(dice, 3), "seconds": round(r.seconds, 3),
+                        "outer": r.outer, "lm_steps": r.lm_steps, "stopped_by": r.stopped_by,
+                        "conc_rel_err": [round(abs(a - b) / abs(b), 4) for a, b in zip(r.c, dc_true)]}
 
-        p_start, _ = workloads.pals_perturbed(w, p3, dc_true)
-        exp1 = {"full_H": recon(full_model, 33.0, p_start, True)}
-        for e_, cbe in cbs.items():
-            mdl = hrec.BornModel(op, phi[:, :S], phi[:, S:], w.extinction, compressed=cbe)
-            exp1[f"{e_:g}"] = {"rank": cbe.rank, "compress_seconds": round(cbe.seconds, 3),
-                               **recon(mdl, 33.0, p_start, True)}
-        mdl6 = hrec.BornModel(op, phi[:, :S], phi[:, S:], w.extinction, compressed=cbs[1e-6])
-        exp2 = recon(mdl6, 30.0, workloads.pals_random_start(w, 3), False)
-        reconstruction = {"measurements": S * D * L, "n_p": 15, "exp1_shape_only_33dB": exp1,
-                          "exp2_shape_and_conc_30dB_random_start_eps1e-6": exp2}
-        del cb, cbs, mdl6
-        log("reconstruction done")
+            p_start, _ = workloads.pals_perturbed(w, p3, dc_true)
+            exp1 = {"full_H": recon(full_model, 33.0, p_start, True)}
+            log("reconstruction with the full H done")
+            for e_, cbe in cbs.items():
+                mdl = hrec.BornModel(op, phi[:, :S], phi[:, S:], w.extinction, compressed=cbe)
+                exp1[f"{e_:g}"] = {"rank": cbe.rank, "compress_seconds": round(cbe.seconds, 3),
+                                   **recon(mdl, 33.0, p_start, True)}
+                log(f"reconstruction with H compressed at {e_:g} done")
+            mdl6 = hrec.BornModel(op, phi[:, :S], phi[:, S:], w.extinction, compressed=cbs[1e-6])
+            exp2 = recon(mdl6, 30.0, workloads.pals_random_start(w, 3), False)
+            reconstruction = {"measurements": S * D * L, "n_p": 15, "exp1_shape_only_33dB": exp1,
+                              "exp2_shape_and_conc_30dB_random_start_eps1e-6": exp2}
+            del cb, cbs, mdl6
+            log("reconstruction done")
 
 
         plain = None
@@ -380,7 +395,9 @@ def main():
     name, (launches, kms, kbytes) = max(prof.items(), key=lambda kv: kv[1][1])
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
     traffic = None
-    if args.config == "medium" and kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256:
+    tuned = hd.get_tuning(op)
+    if args.config == "medium" and kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256 and \
+            all(tuned[k] == v for k, v in TRAFFIC_TUNING.items()):
         traffic = TRAFFIC_BYTES_PER_LAUNCH.get(name)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",

@@ -191,18 +191,34 @@ class CompressedBorn:
     seconds: float
     products: int
     recursive_rank: int = 0    # rank before the closing recompression
+    _vtb: torch.Tensor = field(default=None, repr=False)
 
     @property
     def rank(self) -> int:
         return self.U.shape[1]
 
+    def _vt_blocks(self) -> torch.Tensor:
+        """V^T as [nc, R, N/nc] contiguous blocks (built once): the product V^T v then runs as
+        a batched GEMM over nc voxel blocks plus a sum, instead of one GEMM with an N-long
+        inner dimension and an R x n_v output (too few output tiles to fill the GPU)."""
+        if self._vtb is None:
+            N, R = self.V.shape
+            nc = 64
+            while nc > 1 and N % nc:
+                nc //= 2
+            self._vtb = self.V.T.reshape(R, nc, N // nc).permute(1, 0, 2).contiguous()
+        return self._vtb
+
     def matvec(self, v: torch.Tensor) -> torch.Tensor:
         """H v for real v [n_v, N] -> [n_v, S*L*D] (rows (s, l, d)).  For real v,
-        V^H v = conj(V^T v): the transposed view goes to the GEMM as is, so the conjugate of the
-        N x R factor is never formed."""
+        V^H v = conj(V^T v)."""
         if v.is_complex():
             raise ValueError("matvec takes real probe vectors")
-        return (self.U @ (self.V.T @ v.to(self.V.dtype).T).conj()).T
+        vtb = self._vt_blocks()
+        nc, R, nb = vtb.shape
+        vb = v.to(vtb.dtype).reshape(v.shape[0], nc, nb).permute(1, 2, 0).contiguous()   # [nc, nb, n_v]
+        x = torch.bmm(vtb, vb).sum(dim=0).conj()                                           # V^H v, [R, n_v]
+        return (self.U @ x).T
 
 
 def compress(op: B.Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, src_xy: np.ndarray, eps: float,

@@ -496,7 +496,7 @@ struct Solver {
         const dim3 gt((unsigned)(nb * p.nchunks));
         const int grp = tile_grp;
         const hydot_tuning tu = resolved_tuning(op->tune);
-        const int fl = tu.step_order == 1 ? 1 : 0;
+        const int fl = tu.step_order == 1 ? 1 : tu.step_order == 3 ? 2 : 0;
         const bool small = j + 1 <= 16;
 #define HYDOT_STEP_T(KER, NV, P) hipLaunchKernelGGL((KER<NV, P, 1>), gt, dim3(kTSub), 0, stream, c, j, grp, fl)
 #define HYDOT_STEP_P(KER, NV)                                                                           \
@@ -545,7 +545,7 @@ struct Solver {
       if (c.k > kTK) return false;
       const dim3 gt((unsigned)(nb * p.nchunks)), gr(nb);
       const hydot_tuning tu = resolved_tuning(op->tune);
-      const int fl = tu.step_order == 1 ? 1 : 0;
+      const int fl = tu.step_order == 1 ? 1 : tu.step_order == 3 ? 2 : 0;
       if (tu.step_presum == 4) hipLaunchKernelGGL(k_inner_resid_t<4>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
       else if (tu.step_presum == 2) hipLaunchKernelGGL(k_inner_resid_t<2>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
       else hipLaunchKernelGGL(k_inner_resid_t<1>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
@@ -870,13 +870,14 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
   double best = 1e300;
   hydot_tuning best_t = resolved_tuning(keep);
   hydot_status err = HYDOT_OK;
+  const int orders[2] = {2, 3};
   for (int ig = 2; ig >= 1 && err == HYDOT_OK; --ig)
-    for (int io = 2; io >= 1 && err == HYDOT_OK; --io)
+    for (int io = 0; io < 2 && err == HYDOT_OK; ++io)
       for (int ip = 0; ip < 4 && err == HYDOT_OK; ++ip) {
         hydot_tuning t = resolved_tuning(keep);
         t.step_presum = presums[ip];
         t.step_vx = vxs[ip];
-        t.step_order = io;
+        t.step_order = orders[io];
         t.step_group = ig;
         op->tune = t;
         (void)hydot_profile_enable(1);

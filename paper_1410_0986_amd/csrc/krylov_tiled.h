@@ -87,17 +87,28 @@ __device__ inline void row_reduce(const ProdTile<P>& pt, int nrows, cd& acc) {
 struct TileIdx {
   int sys, chunk;
 };
-__device__ inline TileIdx tile_idx(int nchunks, int grp, bool remap) {
+// flags bit 0: XCD-contiguous order; bit 1: z-slab order.
+__device__ inline TileIdx tile_idx(int nchunks, int grp, int flags) {
   // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
-  // Give each XCD a contiguous range of the logical order so that one XCD runs
-  // all wavelengths of a (right-hand side, chunk) group and, soon after, the
-  // neighbouring chunks whose planes form the stencil halo (its own L2).
+  // XCD-contiguous: each XCD gets a contiguous range of the logical order (whole
+  // systems), at the price of reading a right-hand side's C and U on every XCD.
   const int nblk = gridDim.x;
   int b = blockIdx.x;
-  if (remap && (nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  if ((flags & 1) && (nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
   const int per = grp * nchunks;
   const int g = b / per, rem = b - g * per;
-  return TileIdx{g * grp + rem % grp, rem / grp};
+  int ch = rem / grp;
+  // z-slab: the logical chunk position q lands on XCD (q * grp + system) % 8, a class of
+  // q mod Q (Q = 8 / gcd(grp, 8)) when grp * nchunks is a multiple of 8.  Class x is given the
+  // x-th contiguous range of chunks, i.e. a slab of z-planes: the stencil's z-neighbour chunks
+  // are then read on the same XCD, by blocks a few dispatch slots apart, and hit its L2; the
+  // chunks of one right-hand side still stay on one XCD.
+  if (flags & 2) {
+    const int q8 = grp & 7;
+    const int Q = q8 == 0 ? 1 : (q8 & 1) ? 8 : (q8 & 3) ? 4 : 2;
+    if (Q > 1 && nchunks % Q == 0 && (per & 7) == 0) ch = (ch % Q) * (nchunks / Q) + ch / Q;
+  }
+  return TileIdx{g * grp + rem % grp, ch};
 }
 
 // finish the TPR-thread row sums and store them as the chunk's partial sums;
@@ -524,10 +535,10 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
 }
 
 // W = A_hat V_j and first-pass inner products (tiled form of k_step_dots).
-// flags bit 0: XCD-contiguous block order.  VX voxels per thread per sub-tile (NV <= 16).
+// flags: block order (tile_idx).  VX voxels per thread per sub-tile (NV <= 16).
 template <int NV, int P, int VX>
 __global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp, int flags) {
-  const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   if (!c.st[ti.sys].in_cycle) return;
   if constexpr (NV <= 16) tiled_step_x<NV, 0, P, VX>(c, j, ti);
   else tiled_step<NV, 0, P>(c, j, ti);
@@ -536,7 +547,7 @@ __global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp
 // First projection (w' stored as V_{j+1}) + second-pass inner products (tiled form of k_step_update).
 template <int NV, int P, int VX>
 __global__ __launch_bounds__(kTSub) void k_step_update_t(Ctx<cf> c, int j, int grp, int flags) {
-  const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   if (!c.st[ti.sys].in_cycle) return;
   if constexpr (NV <= 16) tiled_step_x<NV, 1, P, VX>(c, j, ti);
   else tiled_step<NV, 1, P>(c, j, ti);
@@ -546,7 +557,7 @@ __global__ __launch_bounds__(kTSub) void k_step_update_t(Ctx<cf> c, int j, int g
 // second Gram-Schmidt pass is applied (tiled form of k_step_finish).
 template <int NV>
 __global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int grp, int flags) {
-  const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   const int sys = ti.sys;
   if (!c.st[sys].in_cycle || !c.st[sys].reorth) return;
   const size_t N = (size_t)c.g.N;
@@ -580,7 +591,7 @@ __global__ __launch_bounds__(kTSub) void k_step_finish_t(Ctx<cf> c, int j, int g
 template <int P>
 __global__ __launch_bounds__(kTSub) void k_inner_resid_t(Ctx<cf> c, int grp, int flags) {
   __shared__ ProdTile<P> pt;
-  const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   const int sys = ti.sys;
   if (!c.st[sys].in_inner) return;
   const size_t N = (size_t)c.g.N;
@@ -634,7 +645,7 @@ __global__ __launch_bounds__(kTSub) void k_inner_resid_t(Ctx<cf> c, int grp, int
 // W <- W - C'g, Din += U g, V_0 = W (stored unnormalised), |V_0|^2 as chunk partials.
 __global__ __launch_bounds__(kTSub) void k_defl_start_t(Ctx<cf> c, int grp, int flags) {
   __shared__ double wsum[kTSub / 64];
-  const TileIdx ti = tile_idx(c.nchunks, grp, flags & 1);
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   const int sys = ti.sys;
   if (!c.st[sys].cyc_ran) return;
   const size_t N = (size_t)c.g.N;

@@ -189,7 +189,7 @@ hydot_status hydot_get_tuning(const hydot_operator* op, hydot_tuning* out) {
 hydot_status hydot_set_tuning(hydot_operator* op, const hydot_tuning* t) {
   if (!op || !t) return hydot::fail(HYDOT_EINVAL, "set_tuning: null argument");
   const bool ok = (t->step_presum == 0 || t->step_presum == 1 || t->step_presum == 2 || t->step_presum == 4) &&
-                  (t->step_order >= 0 && t->step_order <= 2) && (t->step_group >= 0 && t->step_group <= 2) &&
+                  (t->step_order >= 0 && t->step_order <= 3) && (t->step_group >= 0 && t->step_group <= 2) &&
                   (t->born_stage == 0 || t->born_stage == 16 || t->born_stage == 32) &&
                   (t->born_blocks == 0 || (t->born_blocks >= 256 && t->born_blocks <= 65536)) &&
                   (t->step_vx >= 0 && t->step_vx <= 2) && !(t->step_vx == 2 && t->step_presum != 4 && t->step_presum != 0);

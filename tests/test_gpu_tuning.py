@@ -39,8 +39,8 @@ def mixed_opts(hd):
 
 
 @pytest.mark.parametrize("presum,vx,order,group",
-                         [(p, 1, o, g) for p, o, g in itertools.product((1, 2, 4), (1, 2), (1, 2))] +
-                         [(4, 2, o, g) for o, g in itertools.product((1, 2), (1, 2))])
+                         [(p, 1, o, g) for p, o, g in itertools.product((1, 2, 4), (1, 2, 3), (1, 2))] +
+                         [(4, 2, o, g) for o, g in itertools.product((1, 2, 3), (1, 2))])
 def test_every_step_variant_meets_tolerance(hd, ragged, presum, vx, order, group):
     w, ref = ragged
     op = hd.Operator.from_workload(w)
@@ -119,3 +119,25 @@ def test_selective_second_pass_matches_full_cgs2(hd, ragged):
         assert normwise(phi.cpu().numpy(), ref).max() < 1e-6
         out[extra] = it
     assert abs(out[0].mean() - out[hd.FLAG_FULL_REORTH].mean()) <= 0.1 * out[hd.FLAG_FULL_REORTH].mean() + 2
+
+
+@pytest.mark.parametrize("group", [1, 2])
+def test_block_orders_give_identical_fields(hd, group):
+    """The block order only changes which workgroup computes a (system, chunk) tile: the
+    per-chunk partial sums and their reduction order are the same, so the fields must be
+    bitwise equal.  64 x 64 x 8 grid: 16 chunks, so the z-slab order permutes the chunks."""
+    w = workloads.config("tiny", nx=64, ny=64, nz=8, n_lambda=5)
+    out = []
+    for order in (2, 3, 1):
+        op = hd.Operator.from_workload(w)
+        hd.set_tuning(op, step_presum=4, step_vx=1, step_order=order, step_group=group)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, mixed_opts(hd), out_dtype=torch.complex64,
+                                               device=DEV)
+        s.synchronize()
+        assert st == hd.OK and rel.max() <= 1e-8
+        out.append((phi.cpu(), it))
+    for phi, it in out[1:]:
+        assert torch.equal(phi, out[0][0])
+        np.testing.assert_array_equal(it, out[0][1])
