@@ -207,12 +207,17 @@ hydot_status hydot_born_apply_adjoint_ex(const hydot_operator* op, const void* p
 
 /* PaLS shape (Sec. 5, eq. pals) at the voxel centres ((i+1/2)h, (j+1/2)h, (k+1/2)h):
  *   mu(r) = H_eps(varphi(r) - tau),  varphi(r) = sum_b alpha_b psi(beta_b ||r - chi_b||_dag),
- *   psi(t) = (1 - t)^4 (4t + 1) on t < 1 and 0 beyond (Wendland's compactly supported C^2
- *   radial basis function, support radius 1/beta_b), ||x||_dag = sqrt(||x||^2 + nu^2),
- *   H_eps the C^1 sine-smoothed Heaviside of half-width eps.
+ *   ||x||_dag = sqrt(||x||^2 + nu^2), H_eps the C^1 sine-smoothed Heaviside of half-width eps,
+ *   and psi chosen by basis: HYDOT_PALS_WENDLAND (the paper's compactly supported radial
+ *   functions, read as Wendland's C^2 psi(t) = (1 - t)^4 (4t + 1) on t < 1 and 0 beyond, support
+ *   radius 1/beta_b) or HYDOT_PALS_GAUSSIAN (psi(t) = exp(-t^2), width 1/beta_b).
  * p: host [5*n_bumps] = [alpha, beta, chi_x, chi_y, chi_z] (Sec. 5 ordering), 1 <= n_bumps <= 32.
  * mu: device [N] real of dtype F64 or F32. */
-typedef struct { double tau, eps, nu; } hydot_pals_opts;
+enum { HYDOT_PALS_WENDLAND = 0, HYDOT_PALS_GAUSSIAN = 1 };
+typedef struct {
+  double tau, eps, nu;
+  int32_t basis;   /* HYDOT_PALS_WENDLAND or HYDOT_PALS_GAUSSIAN; anything else is EINVAL */
+} hydot_pals_opts;
 
 hydot_status hydot_pals_shape(const hydot_operator* op, const double* p, int32_t n_bumps,
                               const hydot_pals_opts* popts, void* mu, hydot_dtype mu_dtype,

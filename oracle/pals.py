@@ -7,8 +7,9 @@ varphi(r) = sum_k alpha_k psi(beta_k ||r - chi_k||_dagger),
 ||x||_dagger = sqrt(||x||^2 + nu^2).  The paper names compactly supported radial
 basis functions (those of the PaLS method it builds on) and leaves nu, tau and the
 smoothed Heaviside open; the readings used here are Wendland's C^2 function
-psi(t) = (1 - t)^4 (4t + 1) for t < 1, 0 beyond, nu = 1e-3 mm, tau = 0.5 and the
-C^1 smoothed Heaviside
+psi(t) = (1 - t)^4 (4t + 1) for t < 1, 0 beyond (basis "wendland", the default; the
+Gaussian psi(t) = exp(-t^2) is the alternative basis "gaussian"), nu = 1e-3 mm,
+tau = 0.5 and the C^1 smoothed Heaviside
 
     H_eps(x) = 0 (x < -eps), 1 (x > eps), (1 + x/eps + sin(pi x/eps)/pi)/2 otherwise,
     delta_eps(x) = (1 + cos(pi x/eps))/(2 eps) on |x| <= eps, 0 outside,
@@ -47,39 +48,43 @@ def _split(p):
     return n, p[:n], p[n:2 * n], np.stack([p[2 * n:3 * n], p[3 * n:4 * n], p[4 * n:5 * n]], axis=1)
 
 
-def psi(t):
+def psi(t, basis="wendland"):
     t = np.asarray(t, dtype=np.float64)
+    if basis == "gaussian":
+        return np.exp(-t ** 2)
     return np.where(t < 1.0, (1.0 - t) ** 4 * (4.0 * t + 1.0), 0.0)
 
 
-def dpsi(t):
+def dpsi(t, basis="wendland"):
     t = np.asarray(t, dtype=np.float64)
+    if basis == "gaussian":
+        return -2.0 * t * np.exp(-t ** 2)
     return np.where(t < 1.0, -20.0 * t * (1.0 - t) ** 3, 0.0)
 
 
-def level_function(r, p, nu):
+def level_function(r, p, nu, basis="wendland"):
     """varphi at points r [P, 3]; also returns per-bump pieces for the derivative."""
     n, alpha, beta, centre = _split(p)
     diff = r[:, None, :] - centre[None, :, :]               # [P, n, 3]
     dist = np.sqrt(np.sum(diff ** 2, axis=2) + nu ** 2)     # [P, n]
     t = beta[None, :] * dist
-    ps = psi(t)
+    ps = psi(t, basis)
     phi = ps @ alpha
     return phi, (diff, dist, t, ps, alpha, beta)
 
 
-def shape(w, p, tau, eps, nu):
+def shape(w, p, tau, eps, nu, basis="wendland"):
     """mu = H_eps(varphi - tau) at every voxel centre, [N]."""
     r = model.voxel_centres(w)
-    phi, _ = level_function(r, p, nu)
+    phi, _ = level_function(r, p, nu, basis)
     return heaviside(phi - tau, eps)
 
 
-def shape_jacobian(w, p, tau, eps, nu):
+def shape_jacobian(w, p, tau, eps, nu, basis="wendland"):
     """d mu / d p as a dense [N, 5n] matrix (chain rule of the definitions above)."""
     r = model.voxel_centres(w)
-    phi, (diff, dist, t, ps, alpha, beta) = level_function(r, p, nu)
-    dpsi_dt = dpsi(t)
+    phi, (diff, dist, t, ps, alpha, beta) = level_function(r, p, nu, basis)
+    dpsi_dt = dpsi(t, basis)
     d_alpha = ps
     d_beta = alpha[None, :] * dpsi_dt * dist
     # d dist / d centre = -(r - centre)/dist
@@ -96,9 +101,9 @@ def ebar(extinction, dconc):
     return np.asarray(dconc, dtype=np.float64) @ np.asarray(extinction, dtype=np.float64)
 
 
-def misfit(w, phi_s, phi_d, p, dconc, y_obs, tau, eps, nu, weights=None):
+def misfit(w, phi_s, phi_d, p, dconc, y_obs, tau, eps, nu, weights=None, basis="wendland"):
     """f, df/d(dc) [n_species], df/dp [5n], plus yhat, for the Born data model."""
-    mu = shape(w, p, tau, eps, nu)
+    mu = shape(w, p, tau, eps, nu, basis)
     Jmu = born.born_apply(phi_s, phi_d, mu[None, :], w.h)[0]         # [L, S, D]
     e = ebar(w.extinction, dconc)
     yhat = e[:, None, None] * Jmu
@@ -109,5 +114,5 @@ def misfit(w, phi_s, phi_d, p, dconc, y_obs, tau, eps, nu, weights=None):
     g_dc = np.array([float(np.real(np.sum(np.conj(wr) * w.extinction[l][:, None, None] * Jmu)))
                      for l in range(w.extinction.shape[0])])
     g_mu = np.real(born.born_apply_adjoint(phi_s, phi_d, e[:, None, None] * wr, w.h))
-    g_p = shape_jacobian(w, p, tau, eps, nu).T @ g_mu
+    g_p = shape_jacobian(w, p, tau, eps, nu, basis).T @ g_mu
     return f, g_dc, g_p, yhat

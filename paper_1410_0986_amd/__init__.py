@@ -35,5 +35,6 @@ from ._binding import (  # noqa: F401
     PREC_FP64, PREC_MIXED,
     FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH,
     FLAG_SHIFT_MIN, FLAG_SHIFT_MAX,
+    PALS_WENDLAND, PALS_GAUSSIAN,
     OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED,
 )

@@ -49,7 +49,7 @@ class _SolveOpts(ctypes.Structure):
 
 
 class _PalsOpts(ctypes.Structure):
-    _fields_ = [("tau", c_double), ("eps", c_double), ("nu", c_double)]
+    _fields_ = [("tau", c_double), ("eps", c_double), ("nu", c_double), ("basis", c_int32)]
 
 
 def _proto(name, restype, *argtypes):
@@ -181,14 +181,18 @@ class SolveOptions:
                           self.precision, self.flags, self.inner_tol, self.max_batch)
 
 
+PALS_WENDLAND, PALS_GAUSSIAN = 0, 1
+
+
 @dataclass
 class PalsOptions:
     tau: float = 0.5
     eps: float = 0.5
     nu: float = 1e-3
+    basis: int = 0          # PALS_WENDLAND (the paper's compactly supported functions) or PALS_GAUSSIAN
 
     def _c(self) -> _PalsOpts:
-        return _PalsOpts(self.tau, self.eps, self.nu)
+        return _PalsOpts(self.tau, self.eps, self.nu, self.basis)
 
 
 class Operator:

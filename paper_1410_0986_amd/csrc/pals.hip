@@ -4,7 +4,8 @@
 //
 // Shape: mu(r) = H_eps(varphi(r) - tau), varphi(r) = sum_b alpha_b psi(beta_b ||r - chi_b||_dag),
 // psi the compactly supported radial basis function of Wendland, psi(t) = (1 - t)^4 (4 t + 1) for
-// t < 1 and 0 beyond (C^2, support radius 1/beta_b), ||x||_dag = sqrt(||x||^2 + nu^2), and the C^1
+// t < 1 and 0 beyond (C^2, support radius 1/beta_b; the paper's choice), or the Gaussian
+// psi(t) = exp(-t^2) (beta_b = 1/width), ||x||_dag = sqrt(||x||^2 + nu^2), and the C^1
 // smoothed Heaviside
 // H_eps(x) = (1 + x/eps + sin(pi x/eps)/pi)/2 on |x| <= eps (0 below, 1 above) whose
 // derivative is delta_eps(x) = (1 + cos(pi x/eps))/(2 eps).
@@ -20,7 +21,7 @@ namespace hydot {
 constexpr int kMaxBumps = 32;
 
 struct PalsP {
-  int nb;
+  int nb, basis;   // basis: HYDOT_PALS_WENDLAND or HYDOT_PALS_GAUSSIAN
   double tau, eps, nu, h;
   double alpha[kMaxBumps], beta[kMaxBumps], cx[kMaxBumps], cy[kMaxBumps], cz[kMaxBumps];
 };
@@ -32,14 +33,16 @@ __device__ inline void voxel_centre(const GridP& g, uint32_t n, double h, double
   z = (vi.k + 0.5) * h;
 }
 
-__device__ inline double rbf(double t) {
+__device__ inline double rbf(double t, int basis) {
+  if (basis == HYDOT_PALS_GAUSSIAN) return exp(-t * t);
   if (t >= 1.0) return 0.0;
   const double u = 1.0 - t, u2 = u * u;
   return u2 * u2 * (4.0 * t + 1.0);
 }
 
-// psi'(t) = -20 t (1 - t)^3 on t < 1.
-__device__ inline double rbf_deriv(double t) {
+// psi'(t): -20 t (1 - t)^3 on t < 1 (Wendland), -2 t exp(-t^2) (Gaussian).
+__device__ inline double rbf_deriv(double t, int basis) {
+  if (basis == HYDOT_PALS_GAUSSIAN) return -2.0 * t * exp(-t * t);
   if (t >= 1.0) return 0.0;
   const double u = 1.0 - t;
   return -20.0 * t * u * u * u;
@@ -50,7 +53,7 @@ __device__ inline double level(const PalsP& p, double x, double y, double z) {
   for (int b = 0; b < p.nb; ++b) {
     const double dx = x - p.cx[b], dy = y - p.cy[b], dz = z - p.cz[b];
     const double dist = sqrt(dx * dx + dy * dy + dz * dz + p.nu * p.nu);
-    phi += p.alpha[b] * rbf(p.beta[b] * dist);
+    phi += p.alpha[b] * rbf(p.beta[b] * dist, p.basis);
   }
   return phi;
 }
@@ -93,8 +96,8 @@ __global__ __launch_bounds__(kBlock) void k_pals_vjp(GridP g, PalsP p, const G* 
       const double dx = x - p.cx[b], dy = y - p.cy[b], dz = z - p.cz[b];
       const double dist = sqrt(dx * dx + dy * dy + dz * dz + p.nu * p.nu);
       const double t = p.beta[b] * dist;
-      const double psi = rbf(t);
-      const double dpsi = rbf_deriv(t);
+      const double psi = rbf(t, p.basis);
+      const double dpsi = rbf_deriv(t, p.basis);
       da = wgt * psi;
       dbeta = wgt * p.alpha[b] * dpsi * dist;
       const double common = wgt * p.alpha[b] * dpsi * p.beta[b] / dist;
@@ -140,8 +143,8 @@ __global__ __launch_bounds__(kBlock) void k_pals_jacobian(GridP g, PalsP p, R* j
       const double dx = x - p.cx[b], dy = y - p.cy[b], dz = z - p.cz[b];
       const double dist = sqrt(dx * dx + dy * dy + dz * dz + p.nu * p.nu);
       const double t = p.beta[b] * dist;
-      const double psi = rbf(t);
-      const double dpsi = rbf_deriv(t);
+      const double psi = rbf(t, p.basis);
+      const double dpsi = rbf_deriv(t, p.basis);
       da = delta * psi;
       dbeta = delta * p.alpha[b] * dpsi * dist;
       const double common = delta * p.alpha[b] * dpsi * p.beta[b] / dist;
@@ -205,11 +208,13 @@ static hydot_status make_pals(const hydot_operator* op, const double* p, int nb,
   if (!op) return fail(HYDOT_EINVAL, "pals: null operator");
   if (!p || !po) return fail(HYDOT_EINVAL, "pals: null parameters");
   if (nb < 1 || nb > kMaxBumps) return fail(HYDOT_EINVAL, "pals: n_bumps must be in [1, 32]");
-  if (!(po->eps > 0.0) || !(po->nu >= 0.0) || !std::isfinite(po->tau))
+  if (!(po->eps > 0.0) || !(po->nu >= 0.0) || !std::isfinite(po->tau) ||
+      (po->basis != HYDOT_PALS_WENDLAND && po->basis != HYDOT_PALS_GAUSSIAN))
     return fail(HYDOT_EINVAL, "pals: need eps > 0, nu >= 0, finite tau");
   for (int i = 0; i < 5 * nb; ++i)
     if (!std::isfinite(p[i])) return fail(HYDOT_EINVAL, "pals: non-finite parameter");
   pp.nb = nb;
+  pp.basis = po->basis;
   pp.tau = po->tau;
   pp.eps = po->eps;
   pp.nu = po->nu;

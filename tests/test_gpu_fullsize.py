@@ -142,23 +142,25 @@ def test_diff_config_fields_and_gradient(hd):
         ref = ofields.solve_separable(w, voxels=[w.rhs_voxels[r]], lam_idx=[lam])[0, 0]
         assert normwise(phi[lam, r].cpu().numpy().astype(np.complex128), ref) < 1e-4
     S = w.S
-    p_true, dc_true = workloads.pals_truth(w)
+    # the differentiation workload's anomaly: 8 Gaussian bumps, widths 3-8 mm
+    po = hd.PalsOptions(basis=hd.PALS_GAUSSIAN)
+    p_true, dc_true = workloads.pals_truth(w, basis="gaussian")
     p, dc = workloads.pals_perturbed(w, p_true, dc_true)
     ph = phi.to(torch.complex128)
-    mu_t = hd.pals_shape(op, p_true, device=DEV)
+    mu_t = hd.pals_shape(op, p_true, po, device=DEV)
     Jmu = hd.born_apply(op, ph[:, :S], ph[:, S:], mu_t[None])[0]
     ebar = torch.from_numpy(dc_true @ w.extinction).to(DEV)
     y_obs = ebar[:, None, None] * Jmu
     x = np.concatenate([dc, p])
     xt = torch.tensor(x, requires_grad=True)
-    f = hd.BornMisfit.apply(xt[:2], xt[2:], op, ph[:, :S], ph[:, S:], y_obs)
+    f = hd.BornMisfit.apply(xt[:2], xt[2:], op, ph[:, :S], ph[:, S:], y_obs, po)
     f.backward()
     g = xt.grad.numpy()
     assert f.item() > 0
 
     def f_of(xx):
         return hd.BornMisfit.apply(torch.tensor(xx[:2]), torch.tensor(xx[2:]), op, ph[:, :S], ph[:, S:],
-                                   y_obs).item()
+                                   y_obs, po).item()
 
     for i in (0, 1, 2, 9, 17, 25, 33, 41):
         st_ = 1e-6 * max(1.0, abs(x[i]))
@@ -169,7 +171,7 @@ def test_diff_config_fields_and_gradient(hd):
         assert abs(fd - g[i]) <= 1e-5 * np.abs(g).max() + 1e-5 * abs(g[i])
     # zero gradient at the truth (noise-free data)
     xt0 = torch.tensor(np.concatenate([dc_true, p_true]), requires_grad=True)
-    f0 = hd.BornMisfit.apply(xt0[:2], xt0[2:], op, ph[:, :S], ph[:, S:], y_obs)
+    f0 = hd.BornMisfit.apply(xt0[:2], xt0[2:], op, ph[:, :S], ph[:, S:], y_obs, po)
     f0.backward()
     assert f0.item() <= 1e-12 * f.item()
     assert np.abs(xt0.grad.numpy()).max() <= 1e-6 * np.abs(g).max()

@@ -228,39 +228,61 @@ def test_born_dot_test_on_device(hd):
 
 
 # ------------------------------------------------------------ differentiation
-def test_pals_shape_and_vjp(hd):
+BASES = [("wendland", 0), ("gaussian", 1)]
+
+
+@pytest.mark.parametrize("basis,bcode", BASES)
+def test_pals_shape_vjp_and_jacobian(hd, basis, bcode):
     w = workloads.config("tiny", nx=24, ny=20, nz=12, n_lambda=3)
     op = hd.Operator.from_workload(w)
-    p_true, _ = workloads.pals_truth(w)
+    po = hd.PalsOptions(basis=bcode)
+    p_true, _ = workloads.pals_truth(w, basis=basis)
     p, _ = workloads.pals_perturbed(w, p_true, np.ones(2))
     tau, eps, nu = workloads.PALS_TAU, workloads.PALS_EPS, workloads.PALS_NU
-    mu = hd.pals_shape(op, p, device=DEV).cpu().numpy()
-    ref = opals.shape(w, p, tau, eps, nu)
+    mu = hd.pals_shape(op, p, po, device=DEV).cpu().numpy()
+    ref = opals.shape(w, p, tau, eps, nu, basis)
+    assert 0 < (ref > 0.5).sum() < w.N
     np.testing.assert_allclose(mu, ref, rtol=1e-12, atol=1e-13)
     rng = np.random.default_rng(3)
     g = rng.standard_normal(w.N)
-    gp = hd.pals_shape_vjp(op, p, torch.from_numpy(g).to(DEV))
-    refp = opals.shape_jacobian(w, p, tau, eps, nu).T @ g
+    gp = hd.pals_shape_vjp(op, p, torch.from_numpy(g).to(DEV), po)
+    Jref = opals.shape_jacobian(w, p, tau, eps, nu, basis)
+    refp = Jref.T @ g
     np.testing.assert_allclose(gp, refp, rtol=1e-10, atol=1e-10 * np.abs(refp).max())
+    jac = hd.pals_shape_jacobian(op, p, po, device=DEV).cpu().numpy()
+    assert jac.shape == (p.shape[0], w.N)
+    np.testing.assert_allclose(jac, Jref.T, rtol=1e-11, atol=1e-12 * np.abs(Jref).max())
+    jac32 = hd.pals_shape_jacobian(op, p, po, dtype=torch.float32, device=DEV).cpu().numpy()
+    np.testing.assert_allclose(jac32, Jref.T, rtol=1e-6, atol=1e-6 * np.abs(Jref).max())
 
 
+def test_pals_rejects_unknown_basis(hd):
+    w = workloads.config("tiny")
+    op = hd.Operator.from_workload(w)
+    p, _ = workloads.pals_truth(w)
+    with pytest.raises(hd.HydotError) as e:
+        hd.pals_shape(op, p, hd.PalsOptions(basis=2), device=DEV)
+    assert e.value.status == hd.EINVAL
+
+
+@pytest.mark.parametrize("basis,bcode", BASES)
 @pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-9), (torch.complex64, 1e-4)])
-def test_misfit_gradient_matches_oracle(hd, dtype, tol):
+def test_misfit_gradient_matches_oracle(hd, dtype, tol, basis, bcode):
     w = workloads.config("tiny", nx=24, ny=20, nz=12, n_lambda=4)
     op = hd.Operator.from_workload(w)
     P = ofields.solve_separable(w)
     Ps, Pd = P[:, :w.S], P[:, w.S:]
     tau, eps, nu = workloads.PALS_TAU, workloads.PALS_EPS, workloads.PALS_NU
-    p_true, dc_true = workloads.pals_truth(w)
-    _, _, _, y_true = opals.misfit(w, Ps, Pd, p_true, dc_true, 0.0, tau, eps, nu)
+    p_true, dc_true = workloads.pals_truth(w, basis=basis)
+    _, _, _, y_true = opals.misfit(w, Ps, Pd, p_true, dc_true, 0.0, tau, eps, nu, basis=basis)
     y_obs = y_true + workloads.observed_noise(y_true.shape, 0.03 * np.linalg.norm(y_true) / np.sqrt(y_true.size))
     p, dc = workloads.pals_perturbed(w, p_true, dc_true)
-    f, gdc, gp, _ = opals.misfit(w, Ps, Pd, p, dc, y_obs, tau, eps, nu)
+    f, gdc, gp, _ = opals.misfit(w, Ps, Pd, p, dc, y_obs, tau, eps, nu, basis=basis)
     t = torch.from_numpy(P).to(dtype).to(DEV)
     dct = torch.tensor(dc, dtype=torch.float64, requires_grad=True)
     pt = torch.tensor(p, dtype=torch.float64, requires_grad=True)
     yo = torch.from_numpy(y_obs).to(dtype).to(DEV)
-    fv = hd.BornMisfit.apply(dct, pt, op, t[:, :w.S], t[:, w.S:], yo)
+    fv = hd.BornMisfit.apply(dct, pt, op, t[:, :w.S], t[:, w.S:], yo, hd.PalsOptions(basis=bcode))
     fv.backward()
     assert abs(fv.item() - f) <= tol * abs(f)
     g_all = np.concatenate([dct.grad.numpy(), pt.grad.numpy()])

@@ -246,37 +246,49 @@ def test_heaviside_and_delta():
     np.testing.assert_allclose(fd, d[1:-1], atol=1e-5)
 
 
-def _pals_case():
+def _pals_case(basis):
     w = workloads.config("tiny", nx=12, ny=12, nz=8, n_lambda=3)
-    p_true, dc_true = workloads.pals_truth(w)
+    p_true, dc_true = workloads.pals_truth(w, basis=basis)
     return w, p_true, dc_true
 
 
-def test_shape_jacobian_matches_finite_differences():
-    w, p_true, _ = _pals_case()
+@pytest.mark.parametrize("basis", ["wendland", "gaussian"])
+def test_shape_jacobian_matches_finite_differences(basis):
+    # the two radial functions of the PaLS basis, pinned to their closed forms at a few points
+    t = np.array([0.0, 0.25, 0.5, 0.99, 1.0, 1.5])
+    if basis == "wendland":
+        np.testing.assert_allclose(pals.psi(t), [1.0, 0.75 ** 4 * 2.0, 0.0625 * 3.0, 1e-8 * 4.96, 0.0, 0.0],
+                                   rtol=1e-12, atol=1e-20)
+    else:
+        np.testing.assert_allclose(pals.psi(t, basis), np.exp(-t * t), rtol=1e-15)
+    fdp = (pals.psi(t[1:4] + 1e-7, basis) - pals.psi(t[1:4] - 1e-7, basis)) / 2e-7
+    np.testing.assert_allclose(pals.dpsi(t[1:4], basis), fdp, rtol=1e-6, atol=1e-12)
+    w, p_true, _ = _pals_case(basis)
     p, _ = workloads.pals_perturbed(w, p_true, np.ones(2))
     tau, eps, nu = workloads.PALS_TAU, workloads.PALS_EPS, workloads.PALS_NU
-    Jp = pals.shape_jacobian(w, p, tau, eps, nu)
+    Jp = pals.shape_jacobian(w, p, tau, eps, nu, basis)
+    assert np.abs(Jp).max() > 0
     for i in range(p.shape[0]):
         st = 1e-6 * max(1.0, abs(p[i]))
         pu, pd = p.copy(), p.copy()
         pu[i] += st
         pd[i] -= st
-        fd = (pals.shape(w, pu, tau, eps, nu) - pals.shape(w, pd, tau, eps, nu)) / (2 * st)
+        fd = (pals.shape(w, pu, tau, eps, nu, basis) - pals.shape(w, pd, tau, eps, nu, basis)) / (2 * st)
         np.testing.assert_allclose(fd, Jp[:, i], atol=2e-6 * max(1.0, np.abs(Jp[:, i]).max()))
 
 
-def test_misfit_gradient_matches_finite_differences_and_vanishes_at_truth():
-    w, p_true, dc_true = _pals_case()
+@pytest.mark.parametrize("basis", ["wendland", "gaussian"])
+def test_misfit_gradient_matches_finite_differences_and_vanishes_at_truth(basis):
+    w, p_true, dc_true = _pals_case(basis)
     P = fields.solve_separable(w)
     Ps, Pd = P[:, :w.S], P[:, w.S:]
     tau, eps, nu = workloads.PALS_TAU, workloads.PALS_EPS, workloads.PALS_NU
-    _, _, _, y_obs = pals.misfit(w, Ps, Pd, p_true, dc_true, 0.0, tau, eps, nu)
-    f0, gdc0, gp0, _ = pals.misfit(w, Ps, Pd, p_true, dc_true, y_obs, tau, eps, nu)
+    _, _, _, y_obs = pals.misfit(w, Ps, Pd, p_true, dc_true, 0.0, tau, eps, nu, basis=basis)
+    f0, gdc0, gp0, _ = pals.misfit(w, Ps, Pd, p_true, dc_true, y_obs, tau, eps, nu, basis=basis)
     assert f0 == 0.0
     assert np.abs(gp0).max() == 0.0 and np.abs(gdc0).max() == 0.0
     p, dc = workloads.pals_perturbed(w, p_true, dc_true)
-    f, gdc, gp, _ = pals.misfit(w, Ps, Pd, p, dc, y_obs, tau, eps, nu)
+    f, gdc, gp, _ = pals.misfit(w, Ps, Pd, p, dc, y_obs, tau, eps, nu, basis=basis)
     assert f > 0
     x = np.concatenate([dc, p])
     g = np.concatenate([gdc, gp])
@@ -286,8 +298,8 @@ def test_misfit_gradient_matches_finite_differences_and_vanishes_at_truth():
         xu, xd = x.copy(), x.copy()
         xu[i] += st
         xd[i] -= st
-        fu = pals.misfit(w, Ps, Pd, xu[2:], xu[:2], y_obs, tau, eps, nu)[0]
-        fdn = pals.misfit(w, Ps, Pd, xd[2:], xd[:2], y_obs, tau, eps, nu)[0]
+        fu = pals.misfit(w, Ps, Pd, xu[2:], xu[:2], y_obs, tau, eps, nu, basis=basis)[0]
+        fdn = pals.misfit(w, Ps, Pd, xd[2:], xd[:2], y_obs, tau, eps, nu, basis=basis)[0]
         fd[i] = (fu - fdn) / (2 * st)
     np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6 * np.abs(g).max())
 

@@ -197,17 +197,20 @@ PALS_NU = 1.0e-3        # smoothing of the distance [mm]
 TRUTH_DCONC_UM = (8.0, 8.0)
 
 
-def pals_truth(w: Workload, n_bumps: int = PALS_BUMPS, seed: int = 2014):
+def pals_truth(w: Workload, n_bumps: int = PALS_BUMPS, seed: int = 2014, basis: str = "wendland"):
     """Seeded 'true' PaLS parameters and contrasts.
 
     Returns (p, dconc) with p = [alpha(n), beta(n), cx(n), cy(n), cz(n)]:
-    centres U[1/3, 2/3] of the extent per axis, support radii U[8, 20] mm (beta = 1/radius),
-    weights +-1 (Rademacher); dconc = (+8, +8) uM.
+    centres U[1/3, 2/3] of the extent per axis, weights +-1 (Rademacher), and
+    beta = 1/radius with support radii U[8, 20] mm for the compactly supported basis
+    ("wendland") or beta = 1/width with widths U[3, 8] mm for the Gaussian basis
+    ("gaussian"; the 0.5-level shapes of the two are of similar size); dconc = (+8, +8) uM.
     """
     rng = np.random.default_rng(seed)
     ext = np.array([w.nx * w.h, w.ny * w.h, w.nz * w.h])
     centres = rng.uniform(1.0 / 3.0, 2.0 / 3.0, size=(n_bumps, 3)) * ext
-    widths = rng.uniform(8.0, 20.0, size=n_bumps)
+    lo, hi = (3.0, 8.0) if basis == "gaussian" else (8.0, 20.0)
+    widths = rng.uniform(lo, hi, size=n_bumps)
     alpha = rng.choice([-1.0, 1.0], size=n_bumps)
     p = np.concatenate([alpha, 1.0 / widths, centres[:, 0], centres[:, 1], centres[:, 2]])
     return p, np.asarray(TRUTH_DCONC_UM, dtype=np.float64)
