@@ -92,6 +92,15 @@ typedef struct {
 #define HYDOT_FLAG_SHIFT_MIN   0x20u /* like MEAN_SHIFT with min_j sigma'_j in K_hat (Sec. 6.1 variants) */
 #define HYDOT_FLAG_SHIFT_MAX   0x40u /* like MEAN_SHIFT with max_j sigma'_j in K_hat; at most one of
                                         MEAN_SHIFT, SHIFT_MIN, SHIFT_MAX */
+#define HYDOT_FLAG_PRECOND_SEP 0x80u /* mixed batched path only: right preconditioner
+                                        P_j = K_hat + sigma_j I, inverted exactly on the box by
+                                        three 1-D eigenvector transforms per axis pass (a GPU
+                                        replacement for the ILU of K_hat used in Sec. 6.1);
+                                        K_hat includes the sigma*' of the shift flag in use */
+#define HYDOT_FLAG_PRECOND_SEP_FIXED 0x100u /* as PRECOND_SEP with one shift for every system: the
+                                        mean of sigma_j over the wavelengths; at most one of the two.
+                                        Both need recycle_k <= 10, restart_m - recycle_k <= 32 and
+                                        grid axes of at most 256 cells (else EUNSUPPORTED) */
 #define HYDOT_FLAG_FULL_REORTH 0x10u /* mixed only: apply the second Gram-Schmidt pass at every step.
                                         Default: the FP32 inner Arnoldi skips it for a system whose
                                         second-pass projection is below 1e-4 ||w'|| (orthogonal to
@@ -129,6 +138,20 @@ hydot_status hydot_operator_optics(const hydot_operator* op, double* D_out, doub
  * lam_index: host [n_vec], each in [0, n_lambda). x and y must not overlap. */
 hydot_status hydot_apply_operator(const hydot_operator* op, int32_t n_vec, const int32_t* lam_index,
                                   const void* x, void* y, hydot_dtype dtype, hipStream_t stream);
+
+/* The separable preconditioner of HYDOT_FLAG_PRECOND_SEP(_FIXED) on its own (Sec. 6.1 uses an
+ * ILU of the mean-shifted matrix in its place): y_v = (K_hat + sigma I)^{-1} x_v in the scaled
+ * form of eq. multipleshifted, A(lambda_j) / (D_j h^3) = K / h^3 + sigma'_j B / h^3 + sigma_j I, with
+ * K_hat = K / h^3 + sigma*' B / h^3, sigma*' the mean, minimum or maximum of sigma'_j per
+ * the shift flag in `flags` (0 without one), sigma = sigma_{lam_index} with PRECOND_SEP or the mean
+ * of sigma_j with PRECOND_SEP_FIXED (exactly one of the two in flags).  Exact on the box up to FP32
+ * rounding; any absorption perturbation of the operator is not included.
+ * x, y: device [count][N] complex FP32 (HYDOT_C64); y may equal x (in place), other overlaps are
+ * not allowed.  1 <= count <= 65535; grid axes of at most 256 cells (else EUNSUPPORTED).  The
+ * first call for a given sigma*' builds the axis eigen-decompositions (host, then one
+ * synchronous copy into an operator-owned device buffer). */
+hydot_status hydot_apply_preconditioner(const hydot_operator* op, uint32_t flags, int32_t lam_index,
+                                        const void* x, void* y, int32_t count, hipStream_t stream);
 
 /* Heterogeneous absorption (Sec. 2.1 diffusion equation with mu_a varying in space; eq.
  * perturbation): mu_a(k, lambda_l) = mu_a(lambda_l) + scale[l] * shape[k], so A(lambda_l) gains

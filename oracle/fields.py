@@ -15,7 +15,11 @@ oracle uses the plain definition and several independent routes to it:
                         ``separable_at`` evaluates single points cheaply;
 * ``gmres``           - textbook restarted GMRES(m) (Saad and Schultz 1986),
                         unrecycled, unpreconditioned, MGS with one
-                        re-orthogonalisation, complex Givens rotations.
+                        re-orthogonalisation, complex Givens rotations;
+* ``precond_solve``   - (K_hat + sigma I)^-1 x in the scaled form of eq.
+                        multipleshifted: the matrix a preconditioner replacing the
+                        paper's ILU of the mean-shifted K (Sec. 6.1) inverts, by
+                        sparse LU of the assembled matrix.
 
 Output layout: [L][R][N] complex128 with N contiguous.
 """
@@ -202,3 +206,17 @@ def solve_gmres(w, voxels=None, lam_idx=None, tol=1e-10, m=30, max_iter=20000):
             x, it, rr = gmres(A, model.rhs(w, v), tol=tol, m=m, max_iter=max_iter)
             out[a, r], its[a, r], rel[a, r] = x, it, rr
     return out, its, rel
+
+
+def precond_solve(w, x, sigp_star: float, sigma: complex) -> np.ndarray:
+    """y = (K / h^3 + sigp_star B / h^3 + sigma I)^-1 x for x [count, N] (the scaled form
+    A(lambda_j) / (D_j h^3) = K / h^3 + sigma'_j B / h^3 + sigma_j I with sigma'_j replaced by
+    sigp_star; Sec. 3.1 and the mean-shift transform of Sec. 6.1)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    h3 = w.h ** 3
+    P = (model.assemble_K(w) / h3 + (sigp_star / h3) * model.assemble_B(w)
+         + sigma * sp.identity(w.N, format="csc")).astype(np.complex128).tocsc()
+    lu = spl.splu(P)
+    x = np.atleast_2d(np.asarray(x, dtype=np.complex128))
+    return np.stack([lu.solve(v) for v in x])

@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     SolveOptions,
     PalsOptions,
     apply_operator,
+    apply_preconditioner,
     solve_workspace_bytes,
     solve_fields,
     born_apply,
@@ -34,7 +35,7 @@ from ._binding import (  # noqa: F401
     BORN_NATIVE, BORN_SPLIT_BF16,
     PREC_FP64, PREC_MIXED,
     FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH,
-    FLAG_SHIFT_MIN, FLAG_SHIFT_MAX,
+    FLAG_SHIFT_MIN, FLAG_SHIFT_MAX, FLAG_PRECOND_SEP, FLAG_PRECOND_SEP_FIXED,
     PALS_WENDLAND, PALS_GAUSSIAN,
     OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED,
 )

@@ -23,6 +23,7 @@ BORN_NATIVE, BORN_SPLIT_BF16 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH = 0x1, 0x2, 0x4, 0x8, 0x10
 FLAG_SHIFT_MIN, FLAG_SHIFT_MAX = 0x20, 0x40
+FLAG_PRECOND_SEP, FLAG_PRECOND_SEP_FIXED = 0x80, 0x100
 
 
 class HydotError(RuntimeError):
@@ -65,6 +66,8 @@ _optics = _proto("hydot_operator_optics", c_int32, c_void_p, POINTER(c_double), 
 _set_pert = _proto("hydot_set_absorption_perturbation", c_int32, c_void_p, POINTER(c_double), POINTER(c_double))
 _apply = _proto("hydot_apply_operator", c_int32, c_void_p, c_int32, POINTER(c_int32), c_void_p, c_void_p,
                 c_int32, c_void_p)
+_precond = _proto("hydot_apply_preconditioner", c_int32, c_void_p, ctypes.c_uint32, c_int32, c_void_p, c_void_p,
+                  c_int32, c_void_p)
 _ws_bytes = _proto("hydot_solve_workspace_bytes", c_int32, c_void_p, c_int32, POINTER(_SolveOpts), POINTER(c_size_t))
 _solve = _proto("hydot_solve_fields", c_int32, c_void_p, c_int32, POINTER(c_int64), POINTER(_SolveOpts), c_void_p,
                 c_int32, c_void_p, c_size_t, POINTER(c_int32), POINTER(c_double), c_void_p)
@@ -262,6 +265,24 @@ def _cdtype(t: torch.Tensor) -> int:
 
 def _field_shape(op, count, dtype):
     return (op.L, count, op.N, 2) if dtype == torch.bfloat16 else (op.L, count, op.N)
+
+
+def apply_preconditioner(op: Operator, lam_index: int, x: torch.Tensor, flags: int = FLAG_PRECOND_SEP | FLAG_MEAN_SHIFT,
+                         out: torch.Tensor | None = None) -> torch.Tensor:
+    """y = (K_hat + sigma I)^{-1} x (hydot_apply_preconditioner); x: [count, N] complex64 CUDA tensor.
+    out may be x itself (in place)."""
+    _need_cuda(x, "x")
+    if x.dtype != torch.complex64:
+        raise ValueError("x must be complex64")
+    x2 = x.reshape(-1, op.N)
+    if not x2.is_contiguous():
+        raise ValueError("x must be contiguous")
+    y = torch.empty_like(x2) if out is None else out.reshape(-1, op.N)
+    if y.shape != x2.shape or y.dtype != torch.complex64 or not y.is_contiguous():
+        raise ValueError("out must be a contiguous complex64 tensor shaped like x")
+    _check(_precond(op.handle, int(flags), int(lam_index), c_void_p(x2.data_ptr()), c_void_p(y.data_ptr()),
+                    int(x2.shape[0]), _stream(x.device)))
+    return y.reshape(x.shape)
 
 
 def apply_operator(op: Operator, lam_index, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:

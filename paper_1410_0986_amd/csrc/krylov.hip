@@ -13,6 +13,7 @@
 #include "krylov_kernels.h"
 #include "krylov_tiled.h"
 #include "lanczos.h"
+#include "precond.h"
 #include "operator.h"
 #include "small_dense.h"
 
@@ -131,11 +132,12 @@ struct Plan {
   int nchunks, ndots;
   int npairs;
   int ng;       // Gram vector blocks: 3 ([C, U, rho U]) or 4 (+ mu U with an absorption perturbation)
+  int precond;  // 0 none, 1 separable P_j = K_hat + sigma_j I, 2 one shift (the mean sigma) for all
   Small sl;
   size_t esz;   // inner storage bytes per complex
   // byte offsets
   size_t o_prm, o_st, o_VL, o_U64, o_C64, o_U32, o_C32, o_gpart, o_gram, o_ucoef;
-  size_t o_V, o_W, o_Din, o_Rin, o_X, o_Rout, o_part, o_small, o_cnt, o_final, total;
+  size_t o_V, o_W, o_Din, o_Rin, o_X, o_Rout, o_part, o_small, o_cnt, o_final, o_Z, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -148,7 +150,9 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   if (o->max_iter < 1) return fail(HYDOT_EINVAL, "solve: max_iter must be >= 1");
   if (o->precision != HYDOT_PREC_FP64 && o->precision != HYDOT_PREC_MIXED)
     return fail(HYDOT_EINVAL, "solve: precision must be HYDOT_PREC_FP64 or HYDOT_PREC_MIXED");
-  if (o->flags & ~0x7Fu) return fail(HYDOT_EINVAL, "solve: unknown flag bits");
+  if (o->flags & ~0x1FFu) return fail(HYDOT_EINVAL, "solve: unknown flag bits");
+  if ((o->flags & HYDOT_FLAG_PRECOND_SEP) && (o->flags & HYDOT_FLAG_PRECOND_SEP_FIXED))
+    return fail(HYDOT_EINVAL, "solve: at most one of PRECOND_SEP, PRECOND_SEP_FIXED");
   {
     const uint32_t sh = o->flags & (HYDOT_FLAG_MEAN_SHIFT | HYDOT_FLAG_SHIFT_MIN | HYDOT_FLAG_SHIFT_MAX);
     if (sh & (sh - 1)) return fail(HYDOT_EINVAL, "solve: at most one of MEAN_SHIFT, SHIFT_MIN, SHIFT_MAX");
@@ -174,6 +178,16 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   p.mean_shift = (o->flags & (HYDOT_FLAG_MEAN_SHIFT | HYDOT_FLAG_SHIFT_MIN | HYDOT_FLAG_SHIFT_MAX)) != 0;
   p.shift_kind = (o->flags & HYDOT_FLAG_SHIFT_MIN) ? 1 : (o->flags & HYDOT_FLAG_SHIFT_MAX) ? 2 : 0;
   p.mkmax = std::max(p.mk, p.nl);
+  p.precond = (o->flags & HYDOT_FLAG_PRECOND_SEP) ? 1 : (o->flags & HYDOT_FLAG_PRECOND_SEP_FIXED) ? 2 : 0;
+  if (p.precond) {
+    // right preconditioning lives in the register-resident FP32 step kernels only
+    if (o->precision != HYDOT_PREC_MIXED)
+      return fail(HYDOT_EUNSUPPORTED, "solve: the preconditioner needs the mixed-precision path");
+    if (p.k > kTK || p.mk > kTNV)
+      return fail(HYDOT_EUNSUPPORTED, "solve: the preconditioner needs recycle_k <= 10 and restart_m - recycle_k <= 32");
+    if (op->gp.nx > kPrecMaxN || op->gp.ny > kPrecMaxN || op->gp.nz > kPrecMaxN)
+      return fail(HYDOT_EUNSUPPORTED, "solve: the preconditioner needs grid axes of at most 256 cells");
+  }
   const int total_sys = p.R * p.L;
   if (p.per_system) {
     p.nb = 1;
@@ -215,6 +229,7 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   p.o_small = take((size_t)ns * p.sl.total * sizeof(cd));
   p.o_cnt = take(kCounters * sizeof(int));
   p.o_final = take((size_t)ns * sizeof(double));
+  p.o_Z = take(p.precond ? (size_t)p.nb * N * sizeof(cf) : 0);
   p.total = off;
   return HYDOT_OK;
 }
@@ -274,6 +289,7 @@ struct Solver {
     c.small = at<cd>(p.o_small);
     c.sl = p.sl;
     c.counter = at<int>(p.o_cnt);
+    if (p.precond && !lanczos && std::is_same<S, cf>::value) c.Z = at<S>(p.o_Z);
     return c;
   }
 
@@ -285,6 +301,25 @@ struct Solver {
 
   // systems per block group of the tiled kernels (see krylov_tiled.h)
   int tile_grp = 1;
+  PrecP pc{};   // separable preconditioner (p.precond != 0)
+
+  // P^{-1} applied to one vector per system: in (system stride in_stride) -> Z
+  template <typename S>
+  void precond_apply(const Ctx<S>& c, const S* in, size_t in_stride, int pred, int nb) {
+    if constexpr (std::is_same<S, cf>::value) {
+      PrecIO io{};
+      io.in = in;
+      io.out = c.Z;
+      io.in_stride = in_stride;
+      io.out_stride = (size_t)p.N;
+      io.st = c.st;
+      io.pred = pred;
+      io.prm = c.prm;
+      io.fixed = p.precond == 2 ? 1 : 0;
+      io.sig_fixed = op->sigma_mean;
+      prec_apply(pc, io, nb, stream);
+    }
+  }
   bool used_tiled = false;   // the last cycle ran the register-resident FP32 kernels
 
   // event pairs around the step kernels of one cycle (profiling only)
@@ -571,6 +606,7 @@ struct Solver {
       hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_B, 0);
     }
     for (int j = 0; j < p.mk; ++j) {
+      if (c.Z) precond_apply<S>(c, c.V + (size_t)j * p.N, (size_t)c.vdim * p.N, 1, nb);   // Z = P^{-1} V_j
       rec(j, 0, 0);
       step_kernel<S>(0, c, j, nb);
       rec(j, 0, 1);
@@ -586,6 +622,10 @@ struct Solver {
       }
     }
     hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_CYCLE_END, 0);
+    if (c.Z) {   // Din += U z + P^{-1} (V y2)
+      hipLaunchKernelGGL(k_cycle_vy<S>, gv, dim3(kBlock), 0, stream, c, c.Z);
+      precond_apply<S>(c, c.Z, (size_t)p.N, 2, nb);
+    }
     hipLaunchKernelGGL(k_cycle_update<S>, gv, dim3(kBlock), 0, stream, c);
   }
 
@@ -830,6 +870,13 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
   sv.stream = st;
   sv.o = opts;
   sv.rhs_vox = rhs_voxel;
+  if (p.precond) {
+    s = prec_prepare(op, sv.sigp_mean(), sv.pc);
+    if (s != HYDOT_OK) {
+      if (own) (void)hipStreamDestroy(st);
+      return s;
+    }
+  }
   std::vector<int32_t> it((size_t)p.R * p.L, 0);
   std::vector<double> rr((size_t)p.R * p.L, 0.0);
   if (p.prec == HYDOT_PREC_FP64)
@@ -904,6 +951,126 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
   }
   op->tune = best_t;
   if (n_trials) *n_trials = count;
+  return HYDOT_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------------------
+// Separable preconditioner, host side: the eigen-decompositions of the three axis operators of
+// K_hat (cached in the operator) and the stand-alone application hydot_apply_preconditioner.
+namespace hydot {
+
+namespace {
+
+// T = (1/h^2) (path Laplacian with +2 per Dirichlet end) + (sigp_star / h) (Robin end indicator)
+void axis_operator(int n, bool robin_lo, bool robin_hi, double inv_h2, double inv_h, double sigp_star,
+                   std::vector<double>& T) {
+  T.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double d = 0.0;
+    if (i > 0) {
+      d += 1.0;
+      T[(size_t)i + (size_t)n * (i - 1)] = -inv_h2;
+    }
+    if (i < n - 1) {
+      d += 1.0;
+      T[(size_t)i + (size_t)n * (i + 1)] = -inv_h2;
+    }
+    double e = 0.0;
+    if (i == 0) (robin_lo ? e : d) += robin_lo ? 1.0 : 2.0;
+    if (i == n - 1) (robin_hi ? e : d) += robin_hi ? 1.0 : 2.0;
+    T[(size_t)i * (n + 1)] = d * inv_h2 + e * sigp_star * inv_h;
+  }
+}
+
+}  // namespace
+
+hydot_status prec_prepare(const hydot_operator* op, double sigp_star, PrecP& pp) {
+  const hydot::GridP& g = op->gp;
+  const int dims[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a)
+    if (dims[a] > kPrecMaxN) return fail(HYDOT_EUNSUPPORTED, "preconditioner: a grid axis is longer than 256");
+  int n4[3];
+  size_t off[3][3], total = 0;
+  for (int a = 0; a < 3; ++a) {
+    n4[a] = (dims[a] + 3) & ~3;
+    off[a][0] = total;
+    total += (size_t)dims[a] * n4[a];
+    off[a][1] = total;
+    total += (size_t)dims[a] * n4[a];
+    off[a][2] = total;
+    total += (size_t)n4[a];
+  }
+  if (!op->pc_valid || op->pc_sigp != sigp_star) {
+    std::vector<float> host(total, 0.0f);
+    for (int a = 0; a < 3; ++a) {
+      const int n = dims[a];
+      const bool rlo = (g.robin >> (2 * a)) & 1u, rhi = (g.robin >> (2 * a + 1)) & 1u;
+      std::vector<double> T, w, Q;
+      axis_operator(n, rlo, rhi, g.inv_h2, g.inv_h, sigp_star, T);
+      dense::sym_eig(n, T, w, Q);   // Q column-major: Q[i + n * c] = component i of eigenvector c
+      for (int c = 0; c < n; ++c) {
+        host[off[a][2] + c] = (float)w[c];
+        for (int i = 0; i < n; ++i) {
+          const float q = (float)Q[(size_t)i + (size_t)n * c];
+          host[off[a][0] + (size_t)i * n4[a] + c] = q;
+          host[off[a][1] + (size_t)c * n4[a] + i] = q;
+        }
+      }
+    }
+    if (!op->pc_dev) HYDOT_HIP(hipMalloc(&op->pc_dev, total * sizeof(float)));
+    HYDOT_HIP(hipMemcpy(op->pc_dev, host.data(), total * sizeof(float), hipMemcpyHostToDevice));
+    op->pc_sigp = sigp_star;
+    op->pc_valid = true;
+  }
+  pp.nx = g.nx;
+  pp.ny = g.ny;
+  pp.nz = g.nz;
+  for (int a = 0; a < 3; ++a) {
+    pp.ax[a].Qf = op->pc_dev + off[a][0];
+    pp.ax[a].Qi = op->pc_dev + off[a][1];
+    pp.ax[a].lam = op->pc_dev + off[a][2];
+    pp.ax[a].n = dims[a];
+    pp.ax[a].n4 = n4[a];
+  }
+  return HYDOT_OK;
+}
+
+}  // namespace hydot
+
+using namespace hydot;
+
+extern "C" {
+
+hydot_status hydot_apply_preconditioner(const hydot_operator* op, uint32_t flags, int32_t lam_index, const void* x,
+                                        void* y, int32_t count, hipStream_t stream) {
+  if (!op) return fail(HYDOT_EINVAL, "apply_preconditioner: null operator");
+  if (!x || !y) return fail(HYDOT_EINVAL, "apply_preconditioner: null vector");
+  if (count < 1 || count > 65535) return fail(HYDOT_EINVAL, "apply_preconditioner: count must be in [1, 65535]");
+  if (lam_index < 0 || lam_index >= op->L) return fail(HYDOT_EINVAL, "apply_preconditioner: lam_index out of range");
+  const uint32_t pc = flags & (HYDOT_FLAG_PRECOND_SEP | HYDOT_FLAG_PRECOND_SEP_FIXED);
+  const uint32_t sh = flags & (HYDOT_FLAG_MEAN_SHIFT | HYDOT_FLAG_SHIFT_MIN | HYDOT_FLAG_SHIFT_MAX);
+  if (flags & ~(pc | sh)) return fail(HYDOT_EINVAL, "apply_preconditioner: flags other than PRECOND_* and shift flags");
+  if (pc == 0 || (pc & (pc - 1))) return fail(HYDOT_EINVAL, "apply_preconditioner: exactly one PRECOND_* flag");
+  if (sh & (sh - 1)) return fail(HYDOT_EINVAL, "apply_preconditioner: at most one shift flag");
+  const double sigp_star = sh == HYDOT_FLAG_MEAN_SHIFT ? op->sigp_mean
+                           : sh == HYDOT_FLAG_SHIFT_MIN ? op->sigp_min
+                           : sh == HYDOT_FLAG_SHIFT_MAX ? op->sigp_max : 0.0;
+  PrecP pp;
+  hydot_status s = prec_prepare(op, sigp_star, pp);
+  if (s != HYDOT_OK) return s;
+  PrecIO io{};
+  io.in = (const cf*)x;
+  io.out = (cf*)y;
+  io.in_stride = io.out_stride = (size_t)op->gp.N;
+  io.st = nullptr;
+  io.pred = 0;
+  io.prm = nullptr;
+  io.fixed = 1;
+  io.sig_fixed = pc == HYDOT_FLAG_PRECOND_SEP ? op->sigma[lam_index] : op->sigma_mean;
+  prec_apply(pp, io, count, stream);
+  HYDOT_HIP(hipGetLastError());
   return HYDOT_OK;
 }
 

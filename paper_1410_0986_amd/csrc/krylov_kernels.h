@@ -99,6 +99,7 @@ struct Ctx {
   Small sl;
   int* counter;     // [2 + 3 kMaxMK]: in_sweep count, in_inner count, systems stepping at step j,
                     // systems re-orthogonalising at step j, right-hand sides stepping at step j
+  S* Z = nullptr;   // [nb][N] preconditioned vector P^{-1} V_j (right preconditioning), or null
 };
 
 // slots of the partial sums
@@ -535,13 +536,21 @@ __global__ __launch_bounds__(kBlock) void k_cycle_update(Ctx<S> c) {
         }
     }
   }
-  for (int l = 0; l < ns; ++l) {
-    const S* Vl = Vsys + (size_t)l * N;
-    const cd yl = coef[c.k + l];
-    const cd my{-yl.re, -yl.im};
+  if (c.Z != nullptr) {
+    // right preconditioning: the basis part of the update is P^{-1} (V y2), formed beforehand
+    const S* z = c.Z + (size_t)sys * N;
 #pragma unroll
     for (int q = 0; q < kVPT; ++q)
-      if (ch.ok[q]) acc[q] = axpy_neg(acc[q], my, Vl[ch.n[q]]);
+      if (ch.ok[q]) acc[q] = add(acc[q], z[ch.n[q]]);
+  } else {
+    for (int l = 0; l < ns; ++l) {
+      const S* Vl = Vsys + (size_t)l * N;
+      const cd yl = coef[c.k + l];
+      const cd my{-yl.re, -yl.im};
+#pragma unroll
+      for (int q = 0; q < kVPT; ++q)
+        if (ch.ok[q]) acc[q] = axpy_neg(acc[q], my, Vl[ch.n[q]]);
+    }
   }
 #pragma unroll
   for (int q = 0; q < kVPT; ++q)

@@ -174,8 +174,9 @@ __device__ inline float ld_f(Rsrc r, uint32_t vo, uint32_t so) {
 
 struct SysBuf {
   Rsrc V, C, U, W, M;   // M: absorption-perturbation shape (no records without one)
+  Rsrc S;               // stencil source of the dots kernel: the basis, or P^{-1} V_j when preconditioned
   uint32_t sv, sc;      // bytes between basis vectors, between C (U) vectors
-  bool pert;
+  bool pert, precond;
 };
 __device__ inline SysBuf sys_buf(const Ctx<cf>& c, int sys, int rhs) {
   const uint32_t N = (uint32_t)c.g.N;
@@ -188,6 +189,8 @@ __device__ inline SysBuf sys_buf(const Ctx<cf>& c, int sys, int rhs) {
   b.W = make_rsrc(c.W + (size_t)sys * N, b.sv);
   b.pert = c.mu != nullptr;
   b.M = make_rsrc(c.mu, b.pert ? N * 4u : 0u);
+  b.precond = c.Z != nullptr;
+  b.S = b.precond ? make_rsrc(c.Z + (size_t)sys * N, b.sv) : b.V;
   return b;
 }
 // shape value of voxel byte offset vo4 (0 without a perturbation)
@@ -347,7 +350,7 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
     load_basis<NV>(bf, ok0 ? n0 * 8u : kOutside, nv, vr);
     load_cu(bf, k, ok0 ? n0 * 4u : kOutside, cr, ur);
     vinf = voxel_info(c.g, ok0 ? n0 : 0u);
-    if (KIND == 0) gather_stencil(c.g, bf.V, (uint32_t)j * bf.sv, n0, ok0, vinf, sreg);
+    if (KIND == 0) gather_stencil(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n0, ok0, vinf, sreg);
     if (KIND == 1) wpre = ld_cf(bf.W, ok0 ? n0 * 8u : kOutside, 0u);
   }
   for (int sub = 0; sub < nsub; ++sub) {
@@ -357,7 +360,7 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
       load_basis<NV>(bf, ok ? n * 8u : kOutside, nv, vr);
       load_cu(bf, k, ok ? n * 4u : kOutside, cr, ur);
       vinf = voxel_info(c.g, ok ? n : 0u);
-      if (KIND == 0) gather_stencil(c.g, bf.V, (uint32_t)j * bf.sv, n, ok, vinf, sreg);
+      if (KIND == 0) gather_stencil(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf, sreg);
       if (KIND == 1) wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
     }
     double rho = 0.0;
@@ -388,7 +391,7 @@ __device__ inline void tiled_step(const Ctx<cf>& c, int j, TileIdx ti) {
         load_basis<NV>(bf, okn ? nn * 8u : kOutside, nv, vr);
         load_cu(bf, k, okn ? nn * 4u : kOutside, cr, ur);
         vinf = voxel_info(c.g, okn ? nn : 0u);
-        if (KIND == 0) gather_stencil(c.g, bf.V, (uint32_t)j * bf.sv, nn, okn, vinf, sreg);
+        if (KIND == 0) gather_stencil(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, nn, okn, vinf, sreg);
         if (KIND == 1) wpre = ld_cf(bf.W, okn ? nn * 8u : kOutside, 0u);
       }
       __syncthreads();
@@ -496,7 +499,7 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
       load_cu(bf, k, ok ? n * 4u : kOutside, cr[x], ur[x]);
       vinf[x] = voxel_info(c.g, ok ? n : 0u);
       muv[x] = mu_at(bf, ok ? n * 4u : kOutside);
-      if (KIND == 0) gather_stencil(c.g, bf.V, (uint32_t)j * bf.sv, n, ok, vinf[x], sreg[x]);
+      if (KIND == 0) gather_stencil(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf[x], sreg[x]);
       if (KIND == 1) wpre[x] = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
     }
   };

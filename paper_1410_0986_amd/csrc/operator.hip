@@ -77,6 +77,7 @@ hydot_tuning resolved_tuning(const hydot_tuning& t) {
 hydot_operator::~hydot_operator() {
   if (mu64) (void)hipFree(mu64);
   if (mu32) (void)hipFree(mu32);
+  if (pc_dev) (void)hipFree(pc_dev);
 }
 
 using namespace hydot;
@@ -138,6 +139,9 @@ hydot_status hydot_assemble_operator(const hydot_grid* grid, const hydot_optics*
   op->sigp_mean = mean / L;                          // mean-shift transform, Sec. 6.1
   op->sigp_min = *std::min_element(op->sigp.begin(), op->sigp.end());
   op->sigp_max = *std::max_element(op->sigp.begin(), op->sigp.end());
+  cd sm{0.0, 0.0};
+  for (int l = 0; l < L; ++l) sm = cd{sm.re + op->sigma[l].re / L, sm.im + op->sigma[l].im / L};
+  op->sigma_mean = sm;                               // one shift for the fixed preconditioner
   *out = op;
   return HYDOT_OK;
 }

@@ -91,7 +91,7 @@ def test_workspace_size_grows_with_batch_and_precision(hd):
 
 
 @pytest.mark.parametrize("kw", [dict(recycle_k=40), dict(recycle_k=10, lanczos_n=10), dict(restart_m=5, recycle_k=10),
-                                dict(rel_tol=0.0), dict(max_iter=0), dict(precision=7), dict(flags=0x100),
+                                dict(rel_tol=0.0), dict(max_iter=0), dict(precision=7), dict(flags=0x200),
                                 dict(precision=1, inner_tol=0.0), dict(restart_m=400, recycle_k=0)])
 def test_solve_options_validated(hd, kw):
     w = workloads.config("tiny")
@@ -204,3 +204,24 @@ def test_shift_flags_are_exclusive(hd):
             hd.solve_workspace_bytes(op, 4, hd.SolveOptions(flags=fl))
         assert e.value.status == hd.EINVAL
     assert hd.solve_workspace_bytes(op, 4, hd.SolveOptions(flags=hd.FLAG_SHIFT_MAX)) > 0
+
+
+def test_preconditioner_flag_validation(hd):
+    w = workloads.config("tiny")
+    op = hd.Operator.from_workload(w)
+    R = w.S + w.D
+    base = dict(rel_tol=1e-8, restart_m=18, recycle_k=5, lanczos_n=24, inner_tol=1e-5)
+    ok = hd.SolveOptions(precision=hd.PREC_MIXED, flags=hd.FLAG_MEAN_SHIFT | hd.FLAG_PRECOND_SEP, **base)
+    plain = hd.SolveOptions(precision=hd.PREC_MIXED, flags=hd.FLAG_MEAN_SHIFT, **base)
+    # the preconditioned plan holds one more vector per system
+    assert hd.solve_workspace_bytes(op, R, ok) >= hd.solve_workspace_bytes(op, R, plain) + R * w.L * w.N * 8
+    cases = [(dict(precision=hd.PREC_MIXED, flags=hd.FLAG_PRECOND_SEP | hd.FLAG_PRECOND_SEP_FIXED), hd.EINVAL),
+             (dict(precision=hd.PREC_FP64, flags=hd.FLAG_PRECOND_SEP), hd.EUNSUPPORTED)]
+    for kw, status in cases:
+        with pytest.raises(hd.HydotError) as e:
+            hd.solve_workspace_bytes(op, R, hd.SolveOptions(**{**base, **kw}))
+        assert e.value.status == status
+    big = dict(base, restart_m=45, recycle_k=5)
+    with pytest.raises(hd.HydotError) as e:
+        hd.solve_workspace_bytes(op, R, hd.SolveOptions(precision=hd.PREC_MIXED, flags=hd.FLAG_PRECOND_SEP, **big))
+    assert e.value.status == hd.EUNSUPPORTED

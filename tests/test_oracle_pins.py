@@ -361,3 +361,19 @@ def test_perturbed_fields_reciprocity_and_born_limit():
         diff = Pt[:, :S][:, :, w.det_voxels] - base[:, :S][:, :, w.det_voxels]
         rem.append(np.abs(diff - t * s[:, None, None] * y).max())
     assert 3.5 < rem[0] / rem[1] < 4.5
+
+
+def test_precond_solve_is_the_scaled_solve_for_one_wavelength():
+    """With a single wavelength the mean sigma' is that wavelength's, so (K_hat + sigma_0 I) is
+    exactly A(lambda_0) / (D_0 h^3): its solve must equal D_0 h^3 phi from the banded LU of the
+    unscaled operator (two independent routes)."""
+    w = workloads.config("tiny", nx=9, ny=7, nz=5, n_lambda=1)
+    sig, sigp = model.shifts(w)
+    D, _, _ = model.optics(w)
+    vox = [int(w.src_voxels[0]), 17, w.N - 1]
+    y = fields.precond_solve(w, np.eye(w.N)[vox], float(sigp.mean()), complex(sig[0]))
+    phi = fields.solve_banded(w, voxels=vox)[0]
+    np.testing.assert_allclose(y, D[0] * w.h ** 3 * phi, rtol=1e-10, atol=1e-12 * np.abs(y).max())
+    # with a different sigma'* the result changes only through the Robin faces
+    y2 = fields.precond_solve(w, np.eye(w.N)[vox], float(sigp.mean()) * 1.5, complex(sig[0]))
+    assert np.abs(y2 - y).max() > 1e-6 * np.abs(y).max()
