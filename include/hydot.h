@@ -342,6 +342,9 @@ hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_
  * with A' the systems whose second Gram-Schmidt pass is applied at step j: each unique
  * vector is read once and the written vector counted; C and U (real, b/2 each) are
  * shared by the wavelengths of a right-hand side, so they count once per right-hand side.
+ * The complex FP32 kernels for up to 16 basis vectors without a preconditioner keep the
+ * work vector W = A v_j out of memory (the update recomputes it from the stencil of V_j):
+ * there dots (A*(j+1) + R'*k)*N*b and update (A*(j+2) + R'*k)*N*b.
  * Enabling resets the counters; the graph flag is ignored while enabled (launches are
  * timed one by one).  Process-wide; not thread-safe. */
 typedef struct {

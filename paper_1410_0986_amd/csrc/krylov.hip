@@ -343,7 +343,10 @@ struct Solver {
       const double act_k[3] = {(double)cnt[2 + j], (double)cnt[2 + j], (double)cnt[2 + kMaxMK + j]};
       const double rhs = (double)cnt[2 + 2 * kMaxMK + j];
       const double rhs_k[3] = {rhs, rhs, std::min(rhs, act_k[2])};
-      const double extra[3] = {(double)(j + 2), (double)(j + 3), (double)(j + 3)};
+      // the register-resident instances for up to 16 basis vectors keep W out of HBM unless the
+      // preconditioner is on (the update recomputes A V_j from the stencil)
+      const bool w_free = used_tiled && !p.precond && j + 1 <= 16;
+      const double extra[3] = {(double)(j + (w_free ? 1 : 2)), (double)(j + (w_free ? 2 : 3)), (double)(j + 3)};
       for (int kind = 0; kind < 3; ++kind) {
         if (kind == 2 && j + 1 >= p.mk) continue;   // no finish after the last step
         float ms = 0.f;

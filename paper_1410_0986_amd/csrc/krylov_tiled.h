@@ -251,10 +251,10 @@ struct StencilRegs {
   cf xc, m[6];
 };
 __device__ inline void gather_stencil(const GridP& g, Rsrc r, uint32_t so, uint32_t n, bool ok, const VoxelInfo& vi,
-                                      StencilRegs& sr) {
-  // missing neighbours read past the resource (zero)
+                                      StencilRegs& sr, bool load_centre = true) {
+  // missing neighbours read past the resource (zero); the caller may supply the centre
   const uint32_t sy = (uint32_t)g.nx, sz = (uint32_t)g.nx * (uint32_t)g.ny;
-  sr.xc = ld_cf(r, ok ? n * 8u : kOutside, so);
+  if (load_centre) sr.xc = ld_cf(r, ok ? n * 8u : kOutside, so);
   sr.m[0] = ld_cf(r, ok && vi.i > 0 ? (n - 1) * 8u : kOutside, so);
   sr.m[1] = ld_cf(r, ok && vi.i < g.nx - 1 ? (n + 1) * 8u : kOutside, so);
   sr.m[2] = ld_cf(r, ok && vi.j > 0 ? (n - sy) * 8u : kOutside, so);
@@ -483,7 +483,12 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
   static_assert(kChunk % kSub == 0, "chunk must hold whole sub-tiles");
   const SysBuf bf = sys_buf(c, sys, p.rhs);
   cf* vnext = c.V + ((size_t)sys * c.vdim + j + 1) * N;   // the update stores w' as V_{j+1}
-  const float sj = KIND == 0 ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
+  // Without a preconditioner the update recomputes w = s_j A V_j from the stencil of V_j (the
+  // same arithmetic as the dots kernel, so the same value) instead of reading it back: the dots
+  // kernel then writes no W, and a step moves two vectors per system less.  With one, the
+  // stencil source P^{-1} V_j is not in the basis, and W is stored and read as before.
+  const bool stencil = KIND == 0 || !bf.precond;
+  const float sj = stencil ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
   cf vr[VX][NV];
   float cr[VX][kTK], ur[VX][kTK];
   cf wpre[VX];
@@ -499,8 +504,13 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
       load_cu(bf, k, ok ? n * 4u : kOutside, cr[x], ur[x]);
       vinf[x] = voxel_info(c.g, ok ? n : 0u);
       muv[x] = mu_at(bf, ok ? n * 4u : kOutside);
-      if (KIND == 0) gather_stencil(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf[x], sreg[x]);
-      if (KIND == 1) wpre[x] = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
+      if (stencil) {
+        // without a preconditioner the stencil centre is V_j, already loaded as the last basis vector
+        gather_stencil(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf[x], sreg[x], bf.precond);
+        if (!bf.precond) sreg[x].xc = vr[x][NV - 1];
+      } else {
+        wpre[x] = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
+      }
     }
   };
   cd acc{0.0, 0.0};
@@ -517,13 +527,15 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
       shift[x] = voxel_shift(p, rho, muv[x]);
       w[x] = cf{0.f, 0.f};
       if (ok) {
-        if (KIND == 0) {
+        if (stencil) {
           w[x] = stencil_apply(c.g, sreg[x], vinf[x], p.sig, p.sigp_abs, p.tau_abs * (double)muv[x]);
           w[x].re *= sj;   // v_j = sj * stored V_j
           w[x].im *= sj;
-          wv[n] = w[x];
+        }
+        if (KIND == 0) {
+          if (bf.precond) wv[n] = w[x];
         } else {
-          w[x] = project_voxel<NV>(wpre[x], vr[x], cr[x], ur[x], g, h, k, nv, shift[x]);
+          w[x] = project_voxel<NV>(stencil ? w[x] : wpre[x], vr[x], cr[x], ur[x], g, h, k, nv, shift[x]);
           vnext[n] = w[x];
         }
       }
