@@ -42,7 +42,7 @@ N_JAC = 42                  # Jacobian block: 2 chromophore contrasts + 40 PaLS 
 # krylov_tiled.h); after any change to those the traffic is reported as null.
 # They also hold only for the launch shape they were taken with (TRAFFIC_TUNING).
 TRAFFIC_SOURCES_SHA256 = "4bcddb648b3149ac06e0850059fc2f447415bb6d30a6a7697c9ad60889c5cedf"
-TRAFFIC_TUNING = {"step_presum": 4, "step_order": 2, "step_group": 2, "step_vx": 1}
+TRAFFIC_TUNING = {"step_presum": 16, "step_order": 2, "step_group": 2, "step_vx": 1}
 TRAFFIC_BYTES_PER_LAUNCH = {"k_step_dots_t": 7.155e9, "k_step_update_t": 6.208e9, "k_step_finish_t": 1.18e6}
 
 

@@ -283,7 +283,10 @@ hydot_status hydot_misfit(const hydot_operator* op, int32_t S, int32_t D, const 
  * the precision in use), never the method.  A field set to 0 selects the library default.
  *   step_presum  Arnoldi step kernels of the complex FP32 path: number of neighbouring lanes
  *                (1, 2 or 4) whose inner-product terms are summed in registers before the LDS
- *                product tile; 2 and 4 shrink the tile so more blocks fit a CU (default 4).
+ *                product tile of every 128-voxel sub-tile; 2 and 4 shrink the tile so more
+ *                blocks fit a CU; 16: each thread sums the terms of its 16 voxels of the chunk
+ *                in registers and the block reduces once per chunk (instances up to 16 basis
+ *                vectors; beyond, 4 is used) (default 16).
  *   step_order   1: blocks ordered so each XCD runs a contiguous range of (system, chunk) tiles;
  *                2: plain dispatch order; 3: z-slab order, each XCD runs a contiguous range of
  *                chunks (a slab of z-planes) of every system, so the stencil's z-neighbour
@@ -310,7 +313,7 @@ typedef struct {
   double ms;
 } hydot_tune_trial;
 
-/* Times every candidate ((step_presum, step_vx) in {(4,1), (2,1), (1,1), (4,2)} x step_order in
+/* Times every candidate ((step_presum, step_vx) in {(16,1), (4,1), (2,1), (4,2)} x step_order in
  * {2, 3} x step_group in {2, 1}) on the caller's problem: each
  * trial is the hydot_solve_fields call with these arguments, timed by HIP events around the
  * Arnoldi step kernels only.  Candidates are tried with the library default first; a later one

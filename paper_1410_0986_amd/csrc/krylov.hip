@@ -538,9 +538,10 @@ struct Solver {
         const bool small = j + 1 <= 16;
 #define HYDOT_STEP_T(KER, NV, P) hipLaunchKernelGGL((KER<NV, P, 1>), gt, dim3(kTSub), 0, stream, c, j, grp, fl)
 #define HYDOT_STEP_P(KER, NV)                                                                           \
-  if (tu.step_presum == 4 && tu.step_vx == 2 && NV <= 16)                                               \
+  if (tu.step_presum == 16 && NV <= 16) HYDOT_STEP_T(KER, NV, 16);                                      \
+  else if (tu.step_presum == 4 && tu.step_vx == 2 && NV <= 16)                                          \
     hipLaunchKernelGGL((KER<NV, 4, (NV <= 16 ? 2 : 1)>), gt, dim3(kTSub), 0, stream, c, j, grp, fl);   \
-  else if (tu.step_presum == 4) HYDOT_STEP_T(KER, NV, 4);                                               \
+  else if (tu.step_presum == 4 || tu.step_presum == 16) HYDOT_STEP_T(KER, NV, 4);                       \
   else if (tu.step_presum == 2) HYDOT_STEP_T(KER, NV, 2);                                               \
   else HYDOT_STEP_T(KER, NV, 1);
 // exact basis-count instances for j + 1 <= 16
@@ -584,7 +585,8 @@ struct Solver {
       const dim3 gt((unsigned)(nb * p.nchunks)), gr(nb);
       const hydot_tuning tu = resolved_tuning(op->tune);
       const int fl = tu.step_order == 1 ? 1 : tu.step_order == 3 ? 2 : 0;
-      if (tu.step_presum == 4) hipLaunchKernelGGL(k_inner_resid_t<4>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
+      if (tu.step_presum == 4 || tu.step_presum == 16)
+        hipLaunchKernelGGL(k_inner_resid_t<4>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
       else if (tu.step_presum == 2) hipLaunchKernelGGL(k_inner_resid_t<2>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
       else hipLaunchKernelGGL(k_inner_resid_t<1>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
       hipLaunchKernelGGL(k_reduce<S>, gr, dim3(64), 0, stream, c, ra, (int)PH_START_A, 0);
@@ -915,7 +917,7 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
   const ProfRec rec_keep[3] = {g_rec[0], g_rec[1], g_rec[2]};
   // candidates in order of preference (library default first); a later candidate replaces the
   // best only when it is more than 1% faster, so timing noise keeps the earlier choice
-  const int presums[4] = {4, 2, 1, 4}, vxs[4] = {1, 1, 1, 2};
+  const int presums[4] = {16, 4, 2, 4}, vxs[4] = {1, 1, 1, 2};
   int count = 0;
   double best = 1e300;
   hydot_tuning best_t = resolved_tuning(keep);

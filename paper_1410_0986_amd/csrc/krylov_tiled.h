@@ -549,14 +549,124 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
   row_flush_all<4>(c, sys, ti.chunk, nv, nrows, acc);
 }
 
+// Chunk-accumulating form of tiled_step_x (VX = 1): each thread keeps its running FP32 sums
+// of the inner-product terms of its 16 voxels in registers (4 FMA per row and voxel) and the
+// block reduces them once per chunk (4-lane DPP pre-sum, LDS tile, FP64 row sums), instead of
+// once per sub-tile.  The per-sub-tile reduction costs about as many VALU operations as the
+// products themselves, and these kernels are bound by VALU issue, not by HBM.  Each row sums
+// 64 terms in FP32 before FP64 (16 voxels times the pre-sum); the first-pass coefficients only
+// set the orthogonalisation, whose loss the second-pass test measures.
+template <int NV, int KIND>
+__device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
+  static_assert(NV <= 16, "chunk-accumulating instances hold at most 16 basis vectors");
+  __shared__ ProdTile<4> pt;
+  const int sys = ti.sys;
+  const size_t N = (size_t)c.g.N;
+  const int k = c.k, nv = NV, t = threadIdx.x;
+  const SysParam p = c.prm[sys];
+  cf* wv = c.W + (size_t)sys * N;
+  cf g[kTK], h[NV];
+  if (KIND == 1) {
+    const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefA;
+#pragma unroll
+    for (int i = 0; i < kTK; ++i) g[i] = i < k ? Store<cf>::from(coef[i]) : cf{0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l < NV; ++l) h[l] = Store<cf>::from(coef[k + l]);
+  }
+  const bool with_norm = KIND == 1;
+  const int nrows = nv + k + (with_norm ? 1 : 0);
+  constexpr int nsub = kChunk / kTSub;
+  const SysBuf bf = sys_buf(c, sys, p.rhs);
+  cf* vnext = c.V + ((size_t)sys * c.vdim + j + 1) * N;
+  const bool stencil = KIND == 0 || !bf.precond;
+  const float sj = stencil ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
+  cf vr[NV];
+  float cr[kTK], ur[kTK];
+  cf wpre{0.f, 0.f};
+  StencilRegs sreg;
+  VoxelInfo vinf;
+  float muv;
+  auto fetch = [&](uint32_t n) {
+    const bool ok = n < (uint32_t)c.g.N;
+    load_basis<NV>(bf, ok ? n * 8u : kOutside, nv, vr);
+    load_cu(bf, k, ok ? n * 4u : kOutside, cr, ur);
+    vinf = voxel_info(c.g, ok ? n : 0u);
+    muv = mu_at(bf, ok ? n * 4u : kOutside);
+    if (stencil) {
+      gather_stencil(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf, sreg, bf.precond);
+      if (!bf.precond) sreg.xc = vr[NV - 1];
+    } else {
+      wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
+    }
+  };
+  cf av[NV], ac[kTK], an{0.f, 0.f};
+#pragma unroll
+  for (int l = 0; l < NV; ++l) av[l] = cf{0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < kTK; ++i) ac[i] = cf{0.f, 0.f};
+  fetch(ti.chunk * kChunk + t);
+  for (int sub = 0; sub < nsub; ++sub) {
+    const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
+    const bool ok = n < (uint32_t)c.g.N;
+    if (ok) {
+      const double rho = (double)vinf.nrobin * c.g.inv_h;
+      const cd shift = voxel_shift(p, rho, muv);
+      cf w{0.f, 0.f};
+      if (stencil) {
+        w = stencil_apply(c.g, sreg, vinf, p.sig, p.sigp_abs, p.tau_abs * (double)muv);
+        w.re *= sj;   // v_j = sj * stored V_j
+        w.im *= sj;
+      }
+      if (KIND == 0) {
+        if (bf.precond) wv[n] = w;
+      } else {
+        w = project_voxel<NV>(stencil ? w : wpre, vr, cr, ur, g, h, k, nv, shift);
+        vnext[n] = w;
+      }
+#pragma unroll
+      for (int l = 0; l < NV; ++l) {
+        const cf v = vr[l];
+        av[l].re += v.re * w.re + v.im * w.im;
+        av[l].im += v.re * w.im - v.im * w.re;
+      }
+      const float sr = (float)shift.re, si = -(float)shift.im;   // conj(shift)
+#pragma unroll
+      for (int i = 0; i < kTK; ++i)
+        if (i < k) {
+          const float ar = cr[i] + sr * ur[i], ai = si * ur[i];
+          ac[i].re += ar * w.re - ai * w.im;
+          ac[i].im += ar * w.im + ai * w.re;
+        }
+      if (with_norm) an.re += w.re * w.re + w.im * w.im;
+    }
+    if (sub + 1 < nsub) fetch(n + kTSub);
+  }
+  // one block reduction per chunk: rows [0, nv) V, [nv, nv + k) C', nv + k the norm
+#pragma unroll
+  for (int l = 0; l < NV; ++l) put_product<4>(pt, l, av[l]);
+#pragma unroll
+  for (int i = 0; i < kTK; ++i)
+    if (i < k) put_product<4>(pt, nv + i, ac[i]);
+  if (with_norm) put_product<4>(pt, nv + k, an);
+  __syncthreads();
+  cd acc{0.0, 0.0};
+  row_reduce<4, 4>(pt, nrows, acc);
+  row_flush_all<4>(c, sys, ti.chunk, nv, nrows, acc);
+}
+
 // W = A_hat V_j and first-pass inner products (tiled form of k_step_dots).
 // flags: block order (tile_idx).  VX voxels per thread per sub-tile (NV <= 16).
 template <int NV, int P, int VX>
 __global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp, int flags) {
   const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   if (!c.st[ti.sys].in_cycle) return;
-  if constexpr (NV <= 16) tiled_step_x<NV, 0, P, VX>(c, j, ti);
-  else tiled_step<NV, 0, P>(c, j, ti);
+  if constexpr (P == 16) {
+    if constexpr (NV <= 16) tiled_step_acc<NV, 0>(c, j, ti);
+  } else if constexpr (NV <= 16) {
+    tiled_step_x<NV, 0, P, VX>(c, j, ti);
+  } else {
+    tiled_step<NV, 0, P>(c, j, ti);
+  }
 }
 
 // First projection (w' stored as V_{j+1}) + second-pass inner products (tiled form of k_step_update).
@@ -564,8 +674,13 @@ template <int NV, int P, int VX>
 __global__ __launch_bounds__(kTSub) void k_step_update_t(Ctx<cf> c, int j, int grp, int flags) {
   const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   if (!c.st[ti.sys].in_cycle) return;
-  if constexpr (NV <= 16) tiled_step_x<NV, 1, P, VX>(c, j, ti);
-  else tiled_step<NV, 1, P>(c, j, ti);
+  if constexpr (P == 16) {
+    if constexpr (NV <= 16) tiled_step_acc<NV, 1>(c, j, ti);
+  } else if constexpr (NV <= 16) {
+    tiled_step_x<NV, 1, P, VX>(c, j, ti);
+  } else {
+    tiled_step<NV, 1, P>(c, j, ti);
+  }
 }
 
 // Second projection and normalisation in place of V_{j+1}, for the systems whose

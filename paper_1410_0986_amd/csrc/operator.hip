@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_op(GridP g, const S* __restric
 
 hydot_tuning resolved_tuning(const hydot_tuning& t) {
   hydot_tuning r = t;
-  if (r.step_presum == 0) r.step_presum = 4;
+  if (r.step_presum == 0) r.step_presum = 16;
   if (r.step_order == 0) r.step_order = 2;
   if (r.step_group == 0) r.step_group = 2;
   if (r.born_blocks == 0) r.born_blocks = 4096;
@@ -192,11 +192,12 @@ hydot_status hydot_get_tuning(const hydot_operator* op, hydot_tuning* out) {
 
 hydot_status hydot_set_tuning(hydot_operator* op, const hydot_tuning* t) {
   if (!op || !t) return hydot::fail(HYDOT_EINVAL, "set_tuning: null argument");
-  const bool ok = (t->step_presum == 0 || t->step_presum == 1 || t->step_presum == 2 || t->step_presum == 4) &&
+  const bool ok = (t->step_presum == 0 || t->step_presum == 1 || t->step_presum == 2 || t->step_presum == 4 ||
+                   t->step_presum == 16) &&
                   (t->step_order >= 0 && t->step_order <= 3) && (t->step_group >= 0 && t->step_group <= 2) &&
                   (t->born_stage == 0 || t->born_stage == 16 || t->born_stage == 32) &&
                   (t->born_blocks == 0 || (t->born_blocks >= 256 && t->born_blocks <= 65536)) &&
-                  (t->step_vx >= 0 && t->step_vx <= 2) && !(t->step_vx == 2 && t->step_presum != 4 && t->step_presum != 0);
+                  (t->step_vx >= 0 && t->step_vx <= 2) && !(t->step_vx == 2 && t->step_presum != 4);
   if (!ok) return hydot::fail(HYDOT_EINVAL, "set_tuning: field out of range");
   op->tune = *t;
   return HYDOT_OK;

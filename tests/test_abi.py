@@ -180,7 +180,7 @@ def test_pals_and_misfit_validate(hd):
 def test_tuning_defaults_and_validation(hd):
     op = _op(hd, workloads.config("tiny"))
     t = hd.get_tuning(op)
-    assert t == {"step_presum": 4, "step_order": 2, "step_group": 2, "born_stage": 0, "born_blocks": 4096,
+    assert t == {"step_presum": 16, "step_order": 2, "step_group": 2, "born_stage": 0, "born_blocks": 4096,
                  "step_vx": 1}
     hd.set_tuning(op, step_presum=4, step_order=1, born_stage=16, born_blocks=1024)
     t = hd.get_tuning(op)
@@ -194,7 +194,10 @@ def test_tuning_defaults_and_validation(hd):
     hd.set_tuning(op, step_presum=1, step_order=0, born_stage=0, born_blocks=0)
     assert hd.get_tuning(op)["step_presum"] == 1 and hd.get_tuning(op)["step_order"] == 2
     hd.set_tuning(op, step_presum=0)
-    assert hd.get_tuning(op)["step_presum"] == 4
+    assert hd.get_tuning(op)["step_presum"] == 16
+    hd.set_tuning(op, step_presum=16, step_vx=1)
+    with pytest.raises(hd.HydotError):
+        hd.set_tuning(op, step_presum=16, step_vx=2)
 
 
 def test_shift_flags_are_exclusive(hd):

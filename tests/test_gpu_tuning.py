@@ -39,7 +39,7 @@ def mixed_opts(hd):
 
 
 @pytest.mark.parametrize("presum,vx,order,group",
-                         [(p, 1, o, g) for p, o, g in itertools.product((1, 2, 4), (1, 2, 3), (1, 2))] +
+                         [(p, 1, o, g) for p, o, g in itertools.product((1, 2, 4, 16), (1, 2, 3), (1, 2))] +
                          [(4, 2, o, g) for o, g in itertools.product((1, 2, 3), (1, 2))])
 def test_every_step_variant_meets_tolerance(hd, ragged, presum, vx, order, group):
     w, ref = ragged
@@ -60,7 +60,7 @@ def test_variant_with_basis_beyond_16_vectors(hd, ragged):
     op = hd.Operator.from_workload(w)
     o = hd.SolveOptions(rel_tol=1e-8, restart_m=30, recycle_k=0, lanczos_n=0, precision=hd.PREC_MIXED,
                         inner_tol=1e-5, flags=hd.FLAG_NO_RECYCLE)
-    for presum, vx in ((1, 1), (2, 1), (4, 1), (4, 2)):
+    for presum, vx in ((1, 1), (2, 1), (4, 1), (4, 2), (16, 1)):
         hd.set_tuning(op, step_presum=presum, step_vx=vx)
         phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, out_dtype=torch.complex64, device=DEV)
         assert st == hd.OK and rel.max() <= 1e-8 and it.max() > 16
@@ -77,7 +77,7 @@ def test_autotune_solve_keeps_the_fastest(hd, ragged):
     # the chosen candidate is one of the trials and within the 1% margin of the fastest
     chosen = [ms for t, ms in trials if t == hd.get_tuning(op)]
     assert len(chosen) == 1 and chosen[0] <= min(ms for _, ms in trials) / 0.99
-    assert trials[0][0] == {**hd.get_tuning(op), "step_presum": 4, "step_order": 2, "step_group": 2,
+    assert trials[0][0] == {**hd.get_tuning(op), "step_presum": 16, "step_order": 2, "step_group": 2,
                             "step_vx": 1}  # default first
     phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, mixed_opts(hd), out_dtype=torch.complex64, device=DEV)
     assert st == hd.OK and rel.max() <= 1e-8
