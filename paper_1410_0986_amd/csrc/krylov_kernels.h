@@ -54,7 +54,7 @@ struct SysState {
 
 // Offsets (in cd units) inside one system's small block.
 struct Small {
-  int coefA, coefB, H, cs, sn, gam, Fp, vs, Lc, y0, total;
+  int coefA, coefB, H, cs, sn, gam, Fp, vs, Lc, y0, cA32, total;
 };
 
 inline Small make_small(int k, int mkmax, int nl) {
@@ -70,6 +70,7 @@ inline Small make_small(int k, int mkmax, int nl) {
   s.vs = o; o += mkmax + 2;      // basis scales: v_l = vs[l] * (stored V_l)
   s.Lc = o; o += k * k;          // y0 follows Lc directly (one host copy fills both)
   s.y0 = o; o += (nl > 0 ? nl : 1);
+  s.cA32 = o; o += (k + mkmax + 3) / 2;   // FP32 copy of the step coefficients coefA (complex float)
   s.total = (o + 15) & ~15;
   return s;
 }
@@ -786,6 +787,9 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
         coef[k + l] = sl * h;                  // multiplier of the stored V_l
         H[l + ldh * j] = h;
       }
+      // FP32 copy for the complex FP32 update kernels (read as block-uniform scalars there)
+      cf* c32 = reinterpret_cast<cf*>(sm + c.sl.cA32);
+      for (int i = 0; i < k + j + 1; ++i) c32[i] = cf{(float)coef[i].re, (float)coef[i].im};
       break;
     }
     case PH_STEP_B: {

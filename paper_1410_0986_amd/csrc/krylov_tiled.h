@@ -282,6 +282,60 @@ __device__ inline cf stencil_apply(const GridP& g, const StencilRegs& sr, const 
             ih2 * (diag_k * xc.im + ai) + (dr * xc.im + di * xc.re)};
 }
 
+// FP32 forms for the chunk-accumulating kernels: the system's shifts converted once per block,
+// the per-voxel diagonal and C' shift formed in FP32 (the products are FP32 anyway).
+struct SysF {
+  float sig_re, sig_im, sigp_abs_h, sigp_rel_h, tau_abs, tau_rel;
+};
+__device__ inline SysF sys_f(const GridP& g, const SysParam& p) {
+  return SysF{(float)p.sig.re, (float)p.sig.im, (float)(p.sigp_abs * g.inv_h), (float)(p.sigp_rel * g.inv_h),
+              (float)p.tau_abs, (float)p.tau_rel};
+}
+__device__ inline cf stencil_apply_f(const GridP& g, const StencilRegs& sr, const VoxelInfo& vi, const SysF& q,
+                                     float mu) {
+  const int nn = 6 - (vi.i == 0) - (vi.i == g.nx - 1) - (vi.j == 0) - (vi.j == g.ny - 1) - (vi.k == 0) -
+                 (vi.k == g.nz - 1);
+  float ar = 0.f, ai = 0.f;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    ar -= sr.m[f].re;
+    ai -= sr.m[f].im;
+  }
+  const float diag_k = (float)(nn + 2 * vi.ndir);
+  const float ih2 = (float)g.inv_h2;
+  const float dr = q.sig_re + q.sigp_abs_h * (float)vi.nrobin + q.tau_abs * mu;
+  const float di = q.sig_im;
+  const cf xc = sr.xc;
+  return cf{ih2 * (diag_k * xc.re + ar) + (dr * xc.re - di * xc.im),
+            ih2 * (diag_k * xc.im + ai) + (dr * xc.im + di * xc.re)};
+}
+// w - C'g - sum_l h_l V_l with the per-voxel C' shift (sr, si) in FP32
+template <int NV>
+__device__ inline cf project_voxel_f(cf w, const cf* vr, const float* cr, const float* ur, const cf* g,
+                                     const cf* h, int k, float sr, float si) {
+  if (k > 0) {
+    float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
+#pragma unroll
+    for (int i = 0; i < kTK; ++i) {
+      if (i < k) {
+        ar += cr[i] * g[i].re;
+        ai += cr[i] * g[i].im;
+        br += ur[i] * g[i].re;
+        bi += ur[i] * g[i].im;
+      }
+    }
+    w.re -= ar + (sr * br - si * bi);
+    w.im -= ai + (sr * bi + si * br);
+  }
+#pragma unroll
+  for (int l = 0; l < NV; ++l) {
+    const cf v = vr[l], hl = h[l];
+    w.re -= hl.re * v.re - hl.im * v.im;
+    w.im -= hl.re * v.im + hl.im * v.re;
+  }
+  return w;
+}
+
 // Product rows of one voxel: round 0 -> conj(V_l) w for l < nv; round 1 ->
 // conj(C'_i) w (row i) with C'_i = C_i + (sigma + sigma'_rel rho) U_i formed per
 // voxel, so f = C'^H w arrives directly (k rows instead of C^T w, U^T w,
@@ -567,11 +621,12 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   cf* wv = c.W + (size_t)sys * N;
   cf g[kTK], h[NV];
   if (KIND == 1) {
-    const cd* coef = c.small + (size_t)sys * c.sl.total + c.sl.coefA;
+    // the FP32 copy of this step's coefficients: block-uniform loads kept in scalar registers
+    const cf* coef = reinterpret_cast<const cf*>(c.small + (size_t)sys * c.sl.total + c.sl.cA32);
 #pragma unroll
-    for (int i = 0; i < kTK; ++i) g[i] = i < k ? Store<cf>::from(coef[i]) : cf{0.f, 0.f};
+    for (int i = 0; i < kTK; ++i) g[i] = i < k ? coef[i] : cf{0.f, 0.f};
 #pragma unroll
-    for (int l = 0; l < NV; ++l) h[l] = Store<cf>::from(coef[k + l]);
+    for (int l = 0; l < NV; ++l) h[l] = coef[k + l];
   }
   const bool with_norm = KIND == 1;
   const int nrows = nv + k + (with_norm ? 1 : 0);
@@ -580,6 +635,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   cf* vnext = c.V + ((size_t)sys * c.vdim + j + 1) * N;
   const bool stencil = KIND == 0 || !bf.precond;
   const float sj = stencil ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
+  const SysF q = sys_f(c.g, p);
   cf vr[NV];
   float cr[kTK], ur[kTK];
   cf wpre{0.f, 0.f};
@@ -609,18 +665,18 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
     const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
     const bool ok = n < (uint32_t)c.g.N;
     if (ok) {
-      const double rho = (double)vinf.nrobin * c.g.inv_h;
-      const cd shift = voxel_shift(p, rho, muv);
+      // C' shift of this voxel: sigma + sigma'_rel rho + tau_rel mu
+      const float shr = q.sig_re + q.sigp_rel_h * (float)vinf.nrobin + q.tau_rel * muv, shi = q.sig_im;
       cf w{0.f, 0.f};
       if (stencil) {
-        w = stencil_apply(c.g, sreg, vinf, p.sig, p.sigp_abs, p.tau_abs * (double)muv);
+        w = stencil_apply_f(c.g, sreg, vinf, q, muv);
         w.re *= sj;   // v_j = sj * stored V_j
         w.im *= sj;
       }
       if (KIND == 0) {
         if (bf.precond) wv[n] = w;
       } else {
-        w = project_voxel<NV>(stencil ? w : wpre, vr, cr, ur, g, h, k, nv, shift);
+        w = project_voxel_f<NV>(stencil ? w : wpre, vr, cr, ur, g, h, k, shr, shi);
         vnext[n] = w;
       }
 #pragma unroll
@@ -629,7 +685,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
         av[l].re += v.re * w.re + v.im * w.im;
         av[l].im += v.re * w.im - v.im * w.re;
       }
-      const float sr = (float)shift.re, si = -(float)shift.im;   // conj(shift)
+      const float sr = shr, si = -shi;   // conj(shift)
 #pragma unroll
       for (int i = 0; i < kTK; ++i)
         if (i < k) {
