@@ -40,10 +40,13 @@ N_JAC = 42                  # Jacobian block: 2 chromophore contrasts + 40 PaLS 
 # from the FETCH_SIZE / WRITE_SIZE runs summarised in profiles/step_kernels_medium_traffic.md.
 # They belong to the kernel sources with this SHA-256 (common.h, krylov_kernels.h,
 # krylov_tiled.h); after any change to those the traffic is reported as null.
-# They also hold only for the launch shape they were taken with (TRAFFIC_TUNING).
-TRAFFIC_SOURCES_SHA256 = "4bcddb648b3149ac06e0850059fc2f447415bb6d30a6a7697c9ad60889c5cedf"
-TRAFFIC_TUNING = {"step_presum": 16, "step_order": 2, "step_group": 2, "step_vx": 1}
-TRAFFIC_BYTES_PER_LAUNCH = {"k_step_dots_t": 7.155e9, "k_step_update_t": 6.208e9, "k_step_finish_t": 1.18e6}
+# They also hold only for the launch shape they were taken with (TRAFFIC_TUNING), per block order.
+TRAFFIC_SOURCES_SHA256 = "6787bf5a959221aefd1a9a433b913b3a1369b923d8b26dd2811bd874d2ccc22a"
+TRAFFIC_TUNING = {"step_presum": 16, "step_group": 2, "step_vx": 1}
+TRAFFIC_BYTES_PER_LAUNCH = {   # step_order -> kernel -> calibrated HBM bytes per launch
+    3: {"k_step_dots_t": 5.324e9, "k_step_update_t": 6.054e9, "k_step_finish_t": 1.164e6},
+    2: {"k_step_dots_t": 6.346e9, "k_step_update_t": 7.088e9, "k_step_finish_t": 1.164e6},
+}
 
 
 def kernel_sources_sha256() -> str:
@@ -422,7 +425,7 @@ def main():
     tuned = hd.get_tuning(op)
     if args.config == "medium" and kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256 and \
             all(tuned[k] == v for k, v in TRAFFIC_TUNING.items()):
-        traffic = TRAFFIC_BYTES_PER_LAUNCH.get(name)
+        traffic = TRAFFIC_BYTES_PER_LAUNCH.get(tuned["step_order"], {}).get(name)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
             "kernel": name,

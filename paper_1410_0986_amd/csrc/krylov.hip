@@ -922,7 +922,7 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
   double best = 1e300;
   hydot_tuning best_t = resolved_tuning(keep);
   hydot_status err = HYDOT_OK;
-  const int orders[2] = {2, 3};
+  const int orders[2] = {3, 2};
   for (int ig = 2; ig >= 1 && err == HYDOT_OK; --ig)
     for (int io = 0; io < 2 && err == HYDOT_OK; ++io)
       for (int ip = 0; ip < 4 && err == HYDOT_OK; ++ip) {

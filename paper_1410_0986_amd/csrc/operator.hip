@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_op(GridP g, const S* __restric
 hydot_tuning resolved_tuning(const hydot_tuning& t) {
   hydot_tuning r = t;
   if (r.step_presum == 0) r.step_presum = 16;
-  if (r.step_order == 0) r.step_order = 2;
+  if (r.step_order == 0) r.step_order = 3;
   if (r.step_group == 0) r.step_group = 2;
   if (r.born_blocks == 0) r.born_blocks = 4096;
   if (r.step_vx == 0) r.step_vx = 1;

@@ -180,7 +180,7 @@ def test_pals_and_misfit_validate(hd):
 def test_tuning_defaults_and_validation(hd):
     op = _op(hd, workloads.config("tiny"))
     t = hd.get_tuning(op)
-    assert t == {"step_presum": 16, "step_order": 2, "step_group": 2, "born_stage": 0, "born_blocks": 4096,
+    assert t == {"step_presum": 16, "step_order": 3, "step_group": 2, "born_stage": 0, "born_blocks": 4096,
                  "step_vx": 1}
     hd.set_tuning(op, step_presum=4, step_order=1, born_stage=16, born_blocks=1024)
     t = hd.get_tuning(op)
@@ -192,7 +192,7 @@ def test_tuning_defaults_and_validation(hd):
         assert e.value.status == hd.EINVAL
     assert hd.get_tuning(op)["step_order"] == 1   # a rejected call changes nothing
     hd.set_tuning(op, step_presum=1, step_order=0, born_stage=0, born_blocks=0)
-    assert hd.get_tuning(op)["step_presum"] == 1 and hd.get_tuning(op)["step_order"] == 2
+    assert hd.get_tuning(op)["step_presum"] == 1 and hd.get_tuning(op)["step_order"] == 3
     hd.set_tuning(op, step_presum=0)
     assert hd.get_tuning(op)["step_presum"] == 16
     hd.set_tuning(op, step_presum=16, step_vx=1)

@@ -77,7 +77,7 @@ def test_autotune_solve_keeps_the_fastest(hd, ragged):
     # the chosen candidate is one of the trials and within the 1% margin of the fastest
     chosen = [ms for t, ms in trials if t == hd.get_tuning(op)]
     assert len(chosen) == 1 and chosen[0] <= min(ms for _, ms in trials) / 0.99
-    assert trials[0][0] == {**hd.get_tuning(op), "step_presum": 16, "step_order": 2, "step_group": 2,
+    assert trials[0][0] == {**hd.get_tuning(op), "step_presum": 16, "step_order": 3, "step_group": 2,
                             "step_vx": 1}  # default first
     phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, mixed_opts(hd), out_dtype=torch.complex64, device=DEV)
     assert st == hd.OK and rel.max() <= 1e-8
