@@ -4,16 +4,15 @@
 // registers, applies the operator or the projection there, and writes one
 // product per inner product into an LDS tile; the tile is then summed row by
 // row (4-8 threads per row, FP64), so every lane stays busy and no per-product
-// wave reduction is needed.  One HBM read of the basis per kernel replaces the
-// double read of the generic CGS2 update.
+// wave reduction is needed (the chunk-accumulating instances instead keep
+// per-thread FP32 sums over the chunk and reduce once).  One HBM read of the
+// basis per kernel replaces the double read of the generic CGS2 update.
 //
 // Grid: one dimension of nb * nchunks blocks, ordered in groups of grp systems
 // (the wavelengths of one right-hand side when the batch holds whole
 // right-hand sides): block b -> group b / (grp * nchunks), chunk
-// (b / grp) % nchunks, system group * grp + b % grp.  Consecutive blocks then
-// share the right-hand side's U, C chunk in L2, and the stencil halo chunks
-// (2 * grp blocks away, the same XCD when grp is a multiple of 4) are still
-// resident when they are read.
+// (b / grp) % nchunks, system group * grp + b % grp, with the chunk position
+// optionally permuted so that each XCD takes a slab of z-planes (tile_idx).
 #pragma once
 
 #include "krylov_kernels.h"
@@ -710,7 +709,8 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   row_flush_all<4>(c, sys, ti.chunk, nv, nrows, acc);
 }
 
-// W = A_hat V_j and first-pass inner products (tiled form of k_step_dots).
+// w = A_hat V_j and first-pass inner products (tiled form of k_step_dots); w is stored as W
+// only where the update cannot recompute it (preconditioner, more than 16 basis vectors).
 // flags: block order (tile_idx).  VX voxels per thread per sub-tile (NV <= 16).
 template <int NV, int P, int VX>
 __global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp, int flags) {
