@@ -298,16 +298,16 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, in
   for (int c = 0; c < NW; ++c)
 #pragma unroll
     for (int r = 0; r < 4; ++r) gre[c][r] = gim[c][r] = 0.0;
-  for (int l = 0; l < L; ++l) {
+  // the fields of one wavelength: phi_s[s][vox] for s = gq + 4q, and phi_d at the voxels and
+  // detectors of this lane's accumulator entries
+  auto load = [&](int l, cplx<T> (&z)[SQ], cplx<T> (&ph)[TBM][4]) {
     const TS* ps = phs + (size_t)l * lam_stride * N;
     const TS* pd = phd + (size_t)l * lam_stride * N;
-    cplx<T> z[SQ];   // phi_s[s][vox] for s = gq + 4q
 #pragma unroll
     for (int q = 0; q < SQ; ++q) {
       const int s = gq + 4 * q;
       z[q] = (q < Sp / 4 && s < S && vok) ? Field<TS>::get(ps, (size_t)s * N + vox) : cplx<T>{0, 0};
     }
-    cplx<T> ph[TBM][4];   // phi_d at the voxels and detectors of this lane's accumulator entries
 #pragma unroll
     for (int t = 0; t < TBM; ++t) {
       const int col = t * 16 + i16;
@@ -318,6 +318,18 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, in
         ph[t][r] = (t < TB && d < D && vv < N) ? Field<TS>::get(pd, (size_t)d * N + vv) : cplx<T>{0, 0};
       }
     }
+  };
+  cplx<T> zn[SQ], phn[TBM][4];   // the next wavelength's fields, loaded during this one's products
+  load(0, zn, phn);
+  for (int l = 0; l < L; ++l) {
+    cplx<T> z[SQ], ph[TBM][4];
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) z[q] = zn[q];
+#pragma unroll
+    for (int t = 0; t < TBM; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ph[t][r] = phn[t][r];
+    if (l + 1 < L) load(l + 1, zn, phn);
 #pragma unroll
     for (int c = 0; c < NW; ++c) {
       if (c0 + c >= n_w) break;
