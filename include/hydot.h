@@ -185,7 +185,13 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
                                 hipStream_t stream);
 
 /* Born products (Sec. 2.1 integral equation; rows of H in eq. measurement), never forming J.
- * Scratch: n_v * n_lambda * ceil(N / split) * (2*pad8(S)) * (2*pad8(D)) doubles, stream-ordered.
+ * Scratch (stream-ordered): n_v * n_lambda * splits * (2*pad8(S)) * (2*pad8(D)) doubles, where
+ * splits (the number of voxel ranges) follows the born_blocks tuning.
+ * With C128 or C64 fields and native products, blocks of n_v >= HYDOT_BORN_PAIRS_MIN_NV probe
+ * vectors are contracted over source-detector pairs instead: phi_src * phi_det formed once per
+ * pair and voxel (in the field precision) and multiplied with the probe block on MFMA (scratch
+ * n_v * n_lambda * splits * S * D * 2 doubles).  Same accumulation (FP64 across 32-voxel stages
+ * and splits); half the MFMA work per probe vector.
  *   y[c][l][s][d] = -h^3 sum_k phi_src[l][s][k] * v[c][k] * phi_det[l][d][k]   (no conjugation)
  * phi_src: device, source s at wavelength l at phi_src + (l*lam_stride + s)*N elements;
  * phi_det: likewise with d.  lam_stride >= max(S, D) counts N-vectors between wavelengths
@@ -200,6 +206,8 @@ hydot_status hydot_born_apply(const hydot_operator* op, const void* phi_src, int
                               const void* phi_det, int32_t D, int64_t lam_stride,
                               hydot_dtype field_dtype, const void* v, int32_t n_v, void* y,
                               hipStream_t stream);
+
+#define HYDOT_BORN_PAIRS_MIN_NV 12
 
 /* Arithmetic of the J v products.  HYDOT_BORN_SPLIT_BF16 (C64 fields only): each FP32 operand
  * x is split into hi = bf16(x) and lo = bf16(x - hi) and the product accumulates

@@ -32,7 +32,7 @@ from ._binding import (  # noqa: F401
     autotune_solve,
     autotune_born,
     C128, C64, CBF16, F64, F32,
-    BORN_NATIVE, BORN_SPLIT_BF16,
+    BORN_NATIVE, BORN_SPLIT_BF16, BORN_PAIRS_MIN_NV,
     PREC_FP64, PREC_MIXED,
     FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH,
     FLAG_SHIFT_MIN, FLAG_SHIFT_MAX, FLAG_PRECOND_SEP, FLAG_PRECOND_SEP_FIXED,

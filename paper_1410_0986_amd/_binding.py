@@ -20,6 +20,7 @@ _lib = ctypes.CDLL(_LIBPATH)
 OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4
 C128, C64, CBF16, F64, F32 = 0, 1, 2, 3, 4
 BORN_NATIVE, BORN_SPLIT_BF16 = 0, 1
+BORN_PAIRS_MIN_NV = 12   # HYDOT_BORN_PAIRS_MIN_NV: native J v of this many probe vectors or more contracts over pairs
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_NO_RECYCLE, FLAG_MEAN_SHIFT, FLAG_GRAPH, FLAG_PER_SYSTEM, FLAG_FULL_REORTH = 0x1, 0x2, 0x4, 0x8, 0x10
 FLAG_SHIFT_MIN, FLAG_SHIFT_MAX = 0x20, 0x40

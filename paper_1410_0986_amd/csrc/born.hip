@@ -267,6 +267,134 @@ __global__ void k_born_apply_finish(int S, int D, int Sp, int Dp, int nsplit, in
   }
 }
 
+// ---------------------------------------------------------------- J v, blocks of probe vectors
+// With many probe vectors the contraction is regrouped over source-detector pairs:
+//   y[c][l][s][d] = -h^3 sum_k P_l[s,d](k) v_c(k),   P_l[s,d](k) = phi_s(k) phi_d(k),
+// a product of the (S D x N) complex pair matrix with the (N x n_v) real probe block.  The
+// pair products are formed in registers, one complex multiply per pair and voxel shared by all
+// probe vectors, and the MFMA runs on the rows [Re P; Im P] against V: 4 S D N real
+// multiply-adds per probe vector where the real-ified complex product of k_born_jv takes
+// 8 S D N, at the cost of padding the probe vectors to a multiple of 16.
+// Block = 4 waves on (split over voxels, wavelength, tile of 8 sources x 8 detectors).  Wave w
+// owns the 16 pairs (2w + i/8, i%8), i < 16, of the tile as an Re tile and an Im tile of 16
+// rows, each against NCT tiles of 16 probe vectors.  Each stage of 32 voxels stages the 8 + 8
+// field rows and the probe-vector segments in LDS; the next stage's global loads are issued
+// before this stage's products.  FP32 products fold their stage sums into FP64 as k_born_jv.
+constexpr int kPairsMinNv = HYDOT_BORN_PAIRS_MIN_NV;   // fewer: the padding to 16 costs more than it saves
+
+template <typename TS, int NCT>
+__global__ __launch_bounds__(kBlock) void k_born_jv_pairs(int N, int S, int D, int64_t lam_stride,
+                                                         const TS* __restrict__ phs, const TS* __restrict__ phd,
+                                                         const typename Field<TS>::real* __restrict__ v, int n_v,
+                                                         int kb, int L, int ntd, double* __restrict__ part) {
+  using R = typename Field<TS>::real;
+  using C = cplx<R>;
+  using ACC = typename Mfma<R>::acc;
+  constexpr bool kFp32 = std::is_same<R, float>::value;
+  constexpr int KT = 32, CP = KT + 4, VP = KT + 4;   // voxels per stage, padded LDS rows
+  constexpr int NE = NCT * 16 * KT / kBlock;          // staged probe-vector elements per thread
+  __shared__ C Ps[8 * CP], Pd[8 * CP];
+  __shared__ R Vs[NCT * 16 * VP];
+  const int split = blockIdx.x, l = blockIdx.y, nsplit = gridDim.x;
+  const int s0 = (blockIdx.z / ntd) * 8, d0 = (blockIdx.z % ntd) * 8;
+  const int k0 = split * kb, k1 = min(N, k0 + kb);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const TS* ps = phs + (size_t)l * lam_stride * N;
+  const TS* pd = phd + (size_t)l * lam_stride * N;
+  ACC acc[2][NCT];
+  f64x4 tot[2][NCT];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      acc[t][c] = ACC{0, 0, 0, 0};
+      tot[t][c] = f64x4{0, 0, 0, 0};
+    }
+  // staging: thread tid holds voxel tid % 32 of field row tid / 32 (sources and detectors) and
+  // of probe vectors tid / 32 + 8 e
+  const int srow = tid >> 5, skk = tid & 31;
+  C rs, rd;
+  R rv[NE];
+  auto fetch = [&](int kbase) {
+    const bool ok = skk < k1 - kbase;
+    const size_t k = (size_t)kbase + skk;
+    rs = ok && s0 + srow < S ? Field<TS>::get(ps, (size_t)(s0 + srow) * N + k) : C{0, 0};
+    rd = ok && d0 + srow < D ? Field<TS>::get(pd, (size_t)(d0 + srow) * N + k) : C{0, 0};
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int col = srow + 8 * e;
+      rv[e] = ok && col < n_v ? v[(size_t)col * N + k] : (R)0;
+    }
+  };
+  const int i = lane & 15, g = lane >> 4;
+  const C* prs = Ps + (2 * wave + (i >> 3)) * CP + g;
+  const C* prd = Pd + (i & 7) * CP + g;
+  const R* pv = Vs + i * VP + g;
+  fetch(k0);
+  for (int kbase = k0; kbase < k1; kbase += KT) {
+    Ps[srow * CP + skk] = rs;
+    Pd[srow * CP + skk] = rd;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) Vs[(srow + 8 * e) * VP + skk] = rv[e];
+    __syncthreads();
+    if (kbase + KT < k1) fetch(kbase + KT);   // in flight during the products
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 4) {
+      const C a = prs[kk], b = prd[kk];
+      const R pre = a.re * b.re - a.im * b.im, pim = a.re * b.im + a.im * b.re;
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const R bv = pv[c * 16 * VP + kk];
+        acc[0][c] = Mfma<R>::step(pre, bv, acc[0][c]);
+        acc[1][c] = Mfma<R>::step(pim, bv, acc[1][c]);
+      }
+    }
+    if constexpr (kFp32) {   // FP64 accumulation across stages
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) tot[t][c][r] += (double)acc[t][c][r];
+          acc[t][c] = ACC{0, 0, 0, 0};
+        }
+    }
+    __syncthreads();
+  }
+  // partial sums: part[(((c * L + l) * nsplit + split) * S + s) * D + d] = (Re, Im)
+#pragma unroll
+  for (int c = 0; c < NCT; ++c) {
+    const int cv = c * 16 + i;
+    if (cv >= n_v) continue;
+    double* out = part + ((size_t)(cv * L + l) * nsplit + split) * (size_t)S * D * 2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = Mfma<R>::out_row(lane, r);
+      const int s = s0 + 2 * wave + (row >> 3), d = d0 + (row & 7);
+      if (s < S && d < D) {
+        const size_t o = ((size_t)s * D + d) * 2;
+        out[o] = kFp32 ? tot[0][c][r] : (double)acc[0][c][r];
+        out[o + 1] = kFp32 ? tot[1][c][r] : (double)acc[1][c][r];
+      }
+    }
+  }
+}
+
+// Sum the split partials of k_born_jv_pairs in a fixed order and scale by -h^3.
+template <typename O>
+__global__ void k_born_pairs_finish(int SD, int nsplit, int nout, const double* part, double scale, O* y) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;   // (c * L + l) * S D + pair
+  if (e >= nout) return;
+  const int cl = e / SD, pair = e - cl * SD;
+  double re = 0, im = 0;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const double* P = part + (((size_t)cl * nsplit + sp) * SD + pair) * 2;
+    re += P[0];
+    im += P[1];
+  }
+  y[e] = Store<O>::from(cd{scale * re, scale * im});
+}
+
 // ---------------------------------------------------------------- J^H w
 // Each wave owns 16 voxels and loops over all wavelengths, keeping g for its
 // voxels in FP64 registers.  Per wavelength, T = A'' B'' on MFMA with
@@ -399,9 +527,56 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, in
   }
 }
 
+template <typename TS, int NCT>
+void launch_jv_pairs(dim3 grid, hipStream_t stream, int N, int S, int D, int64_t ls, const void* phs, const void* phd,
+                     const void* v, int n_v, int kb, int L, int ntd, void* part) {
+  using R = typename Field<TS>::real;
+  hipLaunchKernelGGL((k_born_jv_pairs<TS, NCT>), grid, dim3(kBlock), 0, stream, N, S, D, ls, (const TS*)phs,
+                     (const TS*)phd, (const R*)v, n_v, kb, L, ntd, (double*)part);
+}
+
+// J v for blocks of at least kPairsMinNv probe vectors (FP32 and FP64 products).
+template <typename TS>
+hydot_status born_apply_pairs(const hydot_operator* op, const void* phs, int S, const void* phd, int D, int64_t ls,
+                              const void* v, int n_v, void* y, hipStream_t stream) {
+  using R = typename Field<TS>::real;
+  constexpr int KT = 32;
+  const int N = op->gp.N, L = op->L;
+  const int nts = (S + 7) / 8, ntd = (D + 7) / 8;
+  const int nct = (n_v + 15) / 16;   // 1..4 tiles of 16 probe vectors (n_v <= 64)
+  const hydot_tuning tu = resolved_tuning(op->tune);
+  // split over voxels so the grid has about born_blocks blocks
+  const int per_split = L * nts * ntd;
+  const int max_split = (N + KT - 1) / KT;
+  int nsplit = std::max(1, std::min(max_split, (tu.born_blocks + per_split - 1) / per_split));
+  int kb = (N + nsplit - 1) / nsplit;
+  kb = (kb + KT - 1) / KT * KT;
+  nsplit = (N + kb - 1) / kb;
+  const size_t pbytes = (size_t)n_v * L * nsplit * S * D * 2 * sizeof(double);
+  void* part = nullptr;
+  HYDOT_HIP(hipMallocAsync(&part, pbytes, stream));
+  const dim3 grid(nsplit, L, nts * ntd);
+  if (nct == 1) launch_jv_pairs<TS, 1>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
+  else if (nct == 2) launch_jv_pairs<TS, 2>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
+  else if (nct == 3) launch_jv_pairs<TS, 3>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
+  else launch_jv_pairs<TS, 4>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
+  const int nout = n_v * L * S * D;
+  const double h = op->grid.h_mm;
+  hipLaunchKernelGGL((k_born_pairs_finish<cplx<R>>), dim3((nout + 255) / 256), dim3(256), 0, stream, S * D, nsplit,
+                     nout, (const double*)part, -h * h * h, (cplx<R>*)y);
+  hipError_t e = hipGetLastError();
+  hipError_t e2 = hipFreeAsync(part, stream);
+  if (e != hipSuccess) return hip_check(e, "born_apply launch");
+  if (e2 != hipSuccess) return hip_check(e2, "born_apply free");
+  return HYDOT_OK;
+}
+
 template <typename TS, int CM>
 hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
                              int64_t ls, const void* v, int n_v, void* y, hipStream_t stream) {
+  if constexpr (CM == CM_F32 || CM == CM_F64) {
+    if (n_v >= kPairsMinNv) return born_apply_pairs<TS>(op, phs, S, phd, D, ls, v, n_v, y, stream);
+  }
   using R = typename Field<TS>::real;
   const int N = op->gp.N, L = op->L;
   const int Sp = pad8(S), Dp = pad8(D);

@@ -228,3 +228,9 @@ def test_preconditioner_flag_validation(hd):
     with pytest.raises(hd.HydotError) as e:
         hd.solve_workspace_bytes(op, R, hd.SolveOptions(precision=hd.PREC_MIXED, flags=hd.FLAG_PRECOND_SEP, **big))
     assert e.value.status == hd.EUNSUPPORTED
+
+
+def test_binding_constants_mirror_header(hd):
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+HYDOT_BORN_PAIRS_MIN_NV\s+(\d+)", text)
+    assert m and int(m.group(1)) == hd.BORN_PAIRS_MIN_NV

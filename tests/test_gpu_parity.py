@@ -214,6 +214,27 @@ def test_born_shapes(hd, S, D, dtype, tol):
     assert normwise(g, refg) < tol
 
 
+@pytest.mark.parametrize("S,D", [(3, 5), (9, 2), (24, 24), (64, 64)])
+@pytest.mark.parametrize("n_v", [12, 33, 64])
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
+def test_born_probe_blocks(hd, S, D, n_v, dtype, tol):
+    """Blocks of 12 or more probe vectors take the pair-product kernel: one to four tiles of 16
+    probe vectors (12, 33 and 64 leave partial tiles or none), partial source and detector
+    tiles, ragged N split over many blocks."""
+    w = workloads.config("tiny", nx=10, ny=9, nz=7, n_lambda=3)    # N = 630
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(S * 1000 + D * 10 + n_v)
+    P = (rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))) * 1e-3
+    t = torch.from_numpy(P).to(dtype).to(DEV)
+    Pr = t.cpu().numpy().astype(np.complex128)
+    rdt = torch.float64 if dtype == torch.complex128 else torch.float32
+    vt = torch.from_numpy(rng.standard_normal((n_v, w.N))).to(rdt)
+    y = hd.born_apply(op, t[:, :S], t[:, S:], vt.to(DEV)).cpu().numpy()
+    ref = oborn.born_apply(Pr[:, :S], Pr[:, S:], vt.double().numpy(), w.h)
+    assert y.shape == ref.shape == (n_v, w.L, S, D)
+    assert normwise(y.reshape(n_v, -1), ref.reshape(n_v, -1)).max() < tol
+
+
 def test_born_dot_test_on_device(hd):
     w = workloads.config("tiny")
     op = hd.Operator.from_workload(w)
