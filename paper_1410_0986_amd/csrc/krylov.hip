@@ -7,6 +7,7 @@
 #include <complex>
 #include <type_traits>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -18,6 +19,47 @@
 #include "small_dense.h"
 
 namespace hydot {
+
+// The small per-right-hand-side and per-system algebra of the set-up (harmonic Ritz pairs,
+// Gram Cholesky factors, multi-shift least squares) is independent between systems: it runs
+// on up to kHostThreads host threads while the GPU waits for it.  f(i) returns false on
+// failure; the result is the lowest failing index, or -1.
+constexpr int kHostThreads = 16;
+template <typename F>
+int host_parallel_for(int n, const F& f) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::min({n, kHostThreads, hw});
+  std::vector<int> bad(std::max(nt, 1), -1);
+  auto work = [&](int t) {
+    for (int i = t; i < n; i += nt)
+      if (!f(i)) {
+        bad[t] = i;
+        return;
+      }
+  };
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i)
+      if (!f(i)) return i;
+    return -1;
+  }
+  std::vector<std::thread> th;
+  std::vector<char> started(nt, 0);
+  for (int t = 1; t < nt; ++t) {
+    try {
+      th.emplace_back(work, t);
+      started[t] = 1;
+    } catch (...) {   // no thread available: that share runs on the calling thread
+    }
+  }
+  work(0);
+  for (int t = 1; t < nt; ++t)
+    if (!started[t]) work(t);
+  for (std::thread& x : th) x.join();
+  int first = -1;
+  for (int b : bad)
+    if (b >= 0 && (first < 0 || b < first)) first = b;
+  return first;
+}
 
 // Shift-invariant basis -> U (from V_n) and C (from V_{n+1}) for each right-hand side:
 // U[r][i] = sum_l VL[r][l] cu[r][l][i], C[r][i] = sum_l VL[r][l] cu[r][l][k+i].
@@ -430,18 +472,18 @@ struct Solver {
     HYDOT_HIP(hipStreamSynchronize(stream));
     const int ldh = p.mkmax + 1;
     std::vector<double> ucoef((size_t)nr * (nl + 1) * 2 * k, 0.0);
-    for (int i = 0; i < nr; ++i) {
+    for (int i = 0; i < nr; ++i)
       if (st_out[i].nsteps < nl)
         return fail(HYDOT_EUNSUPPORTED, "solve: shift-invariant Krylov space exhausted before lanczos_n steps; lower lanczos_n");
+    const int bad = host_parallel_for(nr, [&](int i) {
       RhsSetup& R = rs[r0 + i];
       R.Hbar.assign((size_t)(nl + 1) * nl, 0.0);
       const cd* H = smalls.data() + (size_t)i * p.sl.total + p.sl.H;
       for (int jj = 0; jj < nl; ++jj)
         for (int ii = 0; ii <= std::min(jj + 1, nl); ++ii) R.Hbar[ii + (size_t)(nl + 1) * jj] = H[ii + ldh * jj].re;
-      if (k == 0) continue;
+      if (k == 0) return true;
       std::vector<double> Zk, th;
-      if (!dense::harmonic_ritz(nl, k, R.Hbar, Zk, th))
-        return fail(HYDOT_EDEVICE, "solve: projected operator not positive definite in harmonic-Ritz step");
+      if (!dense::harmonic_ritz(nl, k, R.Hbar, Zk, th)) return false;
       // P = Hbar Zk, thin QR P = Qs Y, U = V_n Zk Y^-1, C = V_{n+1} Qs  (Alg. 1 steps 3-4)
       std::vector<double> P((size_t)(nl + 1) * k, 0.0);
       for (int cc = 0; cc < k; ++cc)
@@ -465,7 +507,9 @@ struct Solver {
           uc[l * 2 * k + cc] = l < nl ? ZY[l + (size_t)nl * cc] : 0.0;
           uc[l * 2 * k + k + cc] = Qs[l + (size_t)(nl + 1) * cc];
         }
-    }
+      return true;
+    });
+    if (bad >= 0) return fail(HYDOT_EDEVICE, "solve: projected operator not positive definite in harmonic-Ritz step");
     if (k == 0) return HYDOT_OK;
     HYDOT_HIP(hipMemcpyAsync(at<double>(p.o_ucoef), ucoef.data(), ucoef.size() * sizeof(double), hipMemcpyHostToDevice, stream));
     dim3 gu((p.N + kBlock - 1) / kBlock, nr);
@@ -496,8 +540,8 @@ struct Solver {
 
   // Per-wavelength deflation basis (Alg. 1 steps 7-8 with the Gram update of Sec. 3.2):
   // G_j = C_j'^H C_j' from the Gram of [C, U, rho U] with weights (1, sigma, sigma'_rel);
-  // returns its lower Cholesky factor.
-  hydot_status gram_factor(int r, cd sig, double sp, double tr, std::vector<dense::zc>& Lf) {
+  // returns its lower Cholesky factor (false if G_j is not positive definite).  Thread-safe.
+  bool gram_factor(int r, cd sig, double sp, double tr, std::vector<dense::zc>& Lf) const {
     const int k = p.k, m = p.ng * k;
     const std::vector<double>& gm = rs[r].gram;
     auto gam = [&](int a, int b) -> double {
@@ -516,9 +560,7 @@ struct Solver {
           for (int u = 0; u < p.ng; ++u) s += std::conj(w[t]) * w[u] * gam(t * k + i, u * k + j);
         G[i + (size_t)k * j] = s;
       }
-    if (!dense::chol_herm(k, G, Lf))
-      return fail(HYDOT_EDEVICE, "solve: per-wavelength deflation Gram matrix is not positive definite");
-    return HYDOT_OK;
+    return dense::chol_herm(k, G, Lf);
   }
 
   // ----------------------------------------------------------- one batch
@@ -661,11 +703,15 @@ struct Solver {
       q.gsys = l * p.R + r;
       std::memset(&st[i], 0, sizeof(SysState));
       st[i].in_sweep = 1;
+    }
+    // per system: Cholesky factor of G_j and the multi-shift initial-guess coefficients
+    const int bad = host_parallel_for(nb, [&](int i) {
+      const int r = sys_r[i];
+      const SysParam& q = prm[i];
       cd* dst = lcy.data() + (size_t)i * lc_len;
       if (p.k > 0) {
         std::vector<dense::zc> Lf;
-        hydot_status s = gram_factor(r, q.sig, q.sigp_rel, q.tau_rel, Lf);
-        if (s != HYDOT_OK) return s;
+        if (!gram_factor(r, q.sig, q.sigp_rel, q.tau_rel, Lf)) return false;
         for (int t = 0; t < p.k * p.k; ++t) dst[t] = cd{Lf[t].real(), Lf[t].imag()};
       }
       if (p.nl > 0) {
@@ -673,7 +719,9 @@ struct Solver {
         dense::shifted_ls(p.nl, rs[r].Hbar, dense::zc(q.sig.re, q.sig.im), 1.0, y);
         for (int t = 0; t < p.nl; ++t) dst[p.k * p.k + t] = cd{y[t].real(), y[t].imag()};
       }
-    }
+      return true;
+    });
+    if (bad >= 0) return fail(HYDOT_EDEVICE, "solve: per-wavelength deflation Gram matrix is not positive definite");
     HYDOT_HIP(hipMemcpyAsync(at<SysParam>(p.o_prm), prm.data(), nb * sizeof(SysParam), hipMemcpyHostToDevice, stream));
     HYDOT_HIP(hipMemcpyAsync(at<SysState>(p.o_st), st.data(), nb * sizeof(SysState), hipMemcpyHostToDevice, stream));
     if (lc_len > 0)
