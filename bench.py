@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--no-studies", action="store_true",
                     help="skip the secondary measurements after the Born variants (heterogeneous forward, "
                          "boundary/shift study, compression, reconstruction), e.g. under a profiler")
+    ap.add_argument("--born-only", action="store_true",
+                    help="only the Born J v variants (one solve for the fields, no autotuner, no timed steps)")
     ap.add_argument("--cpu-sample", type=int, default=10, help="systems in the CPU oracle sample")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="finish with one device-to-device copy of this many GiB (counter calibration)")
@@ -141,6 +143,61 @@ def main():
 
         def solve():
             return hd.solve_fields(op, vox, opts, out=phi)
+
+        def born_variants():
+            # Born variants (not part of the step): FP32 / BF16-stored / split-BF16 products for one
+            # probe vector and for the Jacobian block, each against the FP64 products of the same fields
+            phi_bf = torch.empty((L, R, N, 2), dtype=torch.bfloat16, device=dev)
+            hd.solve_fields(op, vox, opts, out=phi_bf)
+            phi64 = phi.to(torch.complex128)
+            vj = torch.from_numpy(workloads.born_v(w, n_v=N_JAC, seed=2024, dtype=np.float32)).to(dev)
+
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+            def timed(fn, nrep=10):
+                fn()
+                e0.record(stream)
+                for _ in range(nrep):
+                    fn()
+                e1.record(stream)
+                e1.synchronize()
+                return e0.elapsed_time(e1) / nrep
+
+            variants = {}
+            for nv, vv in (("1", v), (str(N_JAC), vj)):
+                ref = hd.born_apply(op, phi64[:, :S], phi64[:, S:], vv.double())
+                cases = [("fp32", phi, False, FP32_PEAK_TFLOPS, 8), ("split_bf16", phi, True, BF16_PEAK_TFLOPS, 8),
+                         ("bf16_fields", phi_bf, False, BF16_PEAK_TFLOPS, 4)]
+                for name, f, split, peak, bpc in cases:
+                    ms = timed(lambda: hd.born_apply(op, f[:, :S], f[:, S:], vv, split_bf16=split))
+                    y = hd.born_apply(op, f[:, :S], f[:, S:], vv, split_bf16=split)
+                    n_v = vv.shape[0]
+                    fl = 8.0 * S * D * N * L * n_v
+                    # MFMA work the kernel executes: the real-ified complex product (8 S D N per probe
+                    # vector, rows padded to 8), or with the pair-product kernel (native products of
+                    # hd.BORN_PAIRS_MIN_NV or more probe vectors) 4 S D N per probe vector, pairs in
+                    # tiles of 8 x 8 and probe vectors padded to a multiple of 16
+                    pairs = name == "fp32" and n_v >= hd.BORN_PAIRS_MIN_NV
+                    pad = lambda x, m: -(-x // m) * m
+                    fl_mfma = (4.0 * pad(S, 8) * pad(D, 8) * N * L * pad(n_v, 16) if pairs
+                               else 8.0 * pad(S, 8) * pad(D, 8) * N * L * n_v)
+                    err = float(torch.linalg.vector_norm(y.to(torch.complex128) - ref) / torch.linalg.vector_norm(ref))
+                    variants[f"{name}_nv{nv}"] = {
+                        "kernel": "k_born_jv_pairs" if pairs else "k_born_jv",
+                        "ms": round(ms, 4), "tflops": round(fl / (ms * 1e-3) / 1e12, 2),
+                        "mfma_tflops_executed": round(fl_mfma / (ms * 1e-3) / 1e12, 2),
+                        "mfma_frac": round(fl_mfma / (ms * 1e-3) / 1e12 / peak, 4), "mfma_peak_tflops": peak,
+                        "field_GBps": round((S + D) * N * L * bpc / (ms * 1e-3) / 1e9, 1),
+                        "rel_err_vs_fp64_products": float(f"{err:.3g}")}
+            del phi_bf, phi64
+            return variants
+
+        if args.born_only:
+            # the Born variants alone on the fields of one solve (default launch shapes), e.g. under
+            # a counter profiler
+            solve()
+            print(json.dumps({"born_variants": born_variants()}), flush=True)
+            return
 
         # launch shapes: the autotuner times its candidates on this problem (set-up, not timed)
         solve_trials = hd.autotune_solve(op, vox, opts, out=phi)
@@ -207,49 +264,7 @@ def main():
         jhw_ms = e0.elapsed_time(e1) / reps
         log("born timing done")
 
-        # Born variants (not part of the step): FP32 / BF16-stored / split-BF16 products for one
-        # probe vector and for the Jacobian block, each against the FP64 products of the same fields
-        phi_bf = torch.empty((L, R, N, 2), dtype=torch.bfloat16, device=dev)
-        hd.solve_fields(op, vox, opts, out=phi_bf)
-        phi64 = phi.to(torch.complex128)
-        vj = torch.from_numpy(workloads.born_v(w, n_v=N_JAC, seed=2024, dtype=np.float32)).to(dev)
-
-        def timed(fn, nrep=10):
-            fn()
-            e0.record(stream)
-            for _ in range(nrep):
-                fn()
-            e1.record(stream)
-            e1.synchronize()
-            return e0.elapsed_time(e1) / nrep
-
-        variants = {}
-        for nv, vv in (("1", v), (str(N_JAC), vj)):
-            ref = hd.born_apply(op, phi64[:, :S], phi64[:, S:], vv.double())
-            cases = [("fp32", phi, False, FP32_PEAK_TFLOPS, 8), ("split_bf16", phi, True, BF16_PEAK_TFLOPS, 8),
-                     ("bf16_fields", phi_bf, False, BF16_PEAK_TFLOPS, 4)]
-            for name, f, split, peak, bpc in cases:
-                ms = timed(lambda: hd.born_apply(op, f[:, :S], f[:, S:], vv, split_bf16=split))
-                y = hd.born_apply(op, f[:, :S], f[:, S:], vv, split_bf16=split)
-                n_v = vv.shape[0]
-                fl = 8.0 * S * D * N * L * n_v
-                # MFMA work the kernel executes: the real-ified complex product (8 S D N per probe
-                # vector, rows padded to 8), or with the pair-product kernel (native products of
-                # hd.BORN_PAIRS_MIN_NV or more probe vectors) 4 S D N per probe vector, pairs in
-                # tiles of 8 x 8 and probe vectors padded to a multiple of 16
-                pairs = name == "fp32" and n_v >= hd.BORN_PAIRS_MIN_NV
-                pad = lambda x, m: -(-x // m) * m
-                fl_mfma = (4.0 * pad(S, 8) * pad(D, 8) * N * L * pad(n_v, 16) if pairs
-                           else 8.0 * pad(S, 8) * pad(D, 8) * N * L * n_v)
-                err = float(torch.linalg.vector_norm(y.to(torch.complex128) - ref) / torch.linalg.vector_norm(ref))
-                variants[f"{name}_nv{nv}"] = {
-                    "kernel": "k_born_jv_pairs" if pairs else "k_born_jv",
-                    "ms": round(ms, 4), "tflops": round(fl / (ms * 1e-3) / 1e12, 2),
-                    "mfma_tflops_executed": round(fl_mfma / (ms * 1e-3) / 1e12, 2),
-                    "mfma_frac": round(fl_mfma / (ms * 1e-3) / 1e12 / peak, 4), "mfma_peak_tflops": peak,
-                    "field_GBps": round((S + D) * N * L * bpc / (ms * 1e-3) / 1e9, 1),
-                    "rel_err_vs_fp64_products": float(f"{err:.3g}")}
-        del phi_bf, phi64
+        variants = born_variants()
         log("born variants done")
 
         forward = study = compression = reconstruction = None
