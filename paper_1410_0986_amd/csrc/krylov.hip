@@ -61,6 +61,15 @@ int host_parallel_for(int n, const F& f) {
   return first;
 }
 
+// Per-system blocks uploaded contiguously ([nb][len]) into each system's small block at
+// offset `at`: one host copy instead of one row per system.
+__global__ void k_put_small(cd* small, int total, int at, const cd* src, int len, int nb) {
+  const int sys = blockIdx.y;
+  if (sys >= nb) return;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x)
+    small[(size_t)sys * total + at + e] = src[(size_t)sys * len + e];
+}
+
 // Shift-invariant basis -> U (from V_n) and C (from V_{n+1}) for each right-hand side:
 // U[r][i] = sum_l VL[r][l] cu[r][l][i], C[r][i] = sum_l VL[r][l] cu[r][l][k+i].
 template <int KM, typename VT>
@@ -179,7 +188,7 @@ struct Plan {
   size_t esz;   // inner storage bytes per complex
   // byte offsets
   size_t o_prm, o_st, o_VL, o_U64, o_C64, o_U32, o_C32, o_gpart, o_gram, o_ucoef;
-  size_t o_V, o_W, o_Din, o_Rin, o_X, o_Rout, o_part, o_small, o_cnt, o_final, o_Z, total;
+  size_t o_V, o_W, o_Din, o_Rin, o_X, o_Rout, o_part, o_small, o_lcy, o_cnt, o_final, o_Z, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -269,6 +278,7 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   p.o_Rout = take((size_t)p.nb * N * sizeof(cd));
   p.o_part = take((size_t)ns * p.nchunks * p.ndots * sizeof(cd));
   p.o_small = take((size_t)ns * p.sl.total * sizeof(cd));
+  p.o_lcy = take((size_t)ns * (p.k * p.k + p.nl) * sizeof(cd));   // staging of the per-system set-up
   p.o_cnt = take(kCounters * sizeof(int));
   p.o_final = take((size_t)ns * sizeof(double));
   p.o_Z = take(p.precond ? (size_t)p.nb * N * sizeof(cf) : 0);
@@ -724,9 +734,12 @@ struct Solver {
     if (bad >= 0) return fail(HYDOT_EDEVICE, "solve: per-wavelength deflation Gram matrix is not positive definite");
     HYDOT_HIP(hipMemcpyAsync(at<SysParam>(p.o_prm), prm.data(), nb * sizeof(SysParam), hipMemcpyHostToDevice, stream));
     HYDOT_HIP(hipMemcpyAsync(at<SysState>(p.o_st), st.data(), nb * sizeof(SysState), hipMemcpyHostToDevice, stream));
-    if (lc_len > 0)
-      HYDOT_HIP(hipMemcpy2DAsync(at<cd>(p.o_small) + p.sl.Lc, p.sl.total * sizeof(cd), lcy.data(), lc_len * sizeof(cd),
-                                 lc_len * sizeof(cd), nb, hipMemcpyHostToDevice, stream));
+    if (lc_len > 0) {
+      HYDOT_HIP(hipMemcpyAsync(at<cd>(p.o_lcy), lcy.data(), (size_t)nb * lc_len * sizeof(cd), hipMemcpyHostToDevice,
+                               stream));
+      hipLaunchKernelGGL(k_put_small, dim3((lc_len + 255) / 256, nb), dim3(256), 0, stream, at<cd>(p.o_small),
+                         p.sl.total, p.sl.Lc, (const cd*)at<cd>(p.o_lcy), lc_len, nb);
+    }
     Ctx<S> c = ctx<S>(p.k, false);
     Ctx<cd> c64 = ctx<cd>(p.k, false);   // FP64 views for residual and output kernels
     // group the wavelengths of one right-hand side when the batch holds whole ones
