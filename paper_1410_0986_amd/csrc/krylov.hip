@@ -589,8 +589,13 @@ struct Solver {
         const int fl = tu.step_order == 1 ? 1 : tu.step_order == 3 ? 2 : 0;
         const bool small = j + 1 <= 16;
 #define HYDOT_STEP_T(KER, NV, P) hipLaunchKernelGGL((KER<NV, P, 1>), gt, dim3(kTSub), 0, stream, c, j, grp, fl)
+// the chunk-accumulating instances come with exact deflation dimensions k = 5 and 10
+#define HYDOT_STEP_T16(KER, NV)                                                                                 \
+  if (c.k == 5) hipLaunchKernelGGL((KER<NV, 16, 1, 5>), gt, dim3(kTSub), 0, stream, c, j, grp, fl);           \
+  else if (c.k == 10) hipLaunchKernelGGL((KER<NV, 16, 1, 10>), gt, dim3(kTSub), 0, stream, c, j, grp, fl);    \
+  else HYDOT_STEP_T(KER, NV, 16);
 #define HYDOT_STEP_P(KER, NV)                                                                           \
-  if (tu.step_presum == 16 && NV <= 16) HYDOT_STEP_T(KER, NV, 16);                                      \
+  if (tu.step_presum == 16 && NV <= 16) { HYDOT_STEP_T16(KER, NV) }                                     \
   else if (tu.step_presum == 4 && tu.step_vx == 2 && NV <= 16)                                          \
     hipLaunchKernelGGL((KER<NV, 4, (NV <= 16 ? 2 : 1)>), gt, dim3(kTSub), 0, stream, c, j, grp, fl);   \
   else if (tu.step_presum == 4 || tu.step_presum == 16) HYDOT_STEP_T(KER, NV, 4);                       \
@@ -618,6 +623,7 @@ struct Solver {
         }
 #undef HYDOT_STEP_NV
 #undef HYDOT_STEP_P
+#undef HYDOT_STEP_T16
 #undef HYDOT_STEP_T
         return;
       }

@@ -205,6 +205,16 @@ __device__ inline void load_basis(const SysBuf& b, uint32_t vo8, int nv, cf* vr)
   for (int l = 0; l < NV; ++l) vr[l] = l < nv ? ld_cf(b.V, vo8, (uint32_t)l * b.sv) : cf{0.f, 0.f};
 }
 
+// C and U of one voxel into registers: KM slots, the first k live (all KM when EXACT)
+template <int KM, bool EXACT>
+__device__ inline void load_cu_k(const SysBuf& b, int k, uint32_t vo4, float* cr, float* ur) {
+#pragma unroll
+  for (int i = 0; i < KM; ++i) {
+    const bool on = EXACT || i < k;
+    cr[i] = on ? ld_f(b.C, vo4, (uint32_t)i * b.sc) : 0.f;
+    ur[i] = on ? ld_f(b.U, vo4, (uint32_t)i * b.sc) : 0.f;
+  }
+}
 __device__ inline void load_cu(const SysBuf& b, int k, uint32_t vo4, float* cr, float* ur) {
 #pragma unroll
   for (int i = 0; i < kTK; ++i) {
@@ -308,15 +318,16 @@ __device__ inline cf stencil_apply_f(const GridP& g, const StencilRegs& sr, cons
   return cf{ih2 * (diag_k * xc.re + ar) + (dr * xc.re - di * xc.im),
             ih2 * (diag_k * xc.im + ai) + (dr * xc.im + di * xc.re)};
 }
-// w - C'g - sum_l h_l V_l with the per-voxel C' shift (sr, si) in FP32
-template <int NV>
+// w - C'g - sum_l h_l V_l with the per-voxel C' shift (sr, si) in FP32 (KM slots of C, U and g,
+// the first k live; all KM when EXACT)
+template <int NV, int KM = kTK, bool EXACT = false>
 __device__ inline cf project_voxel_f(cf w, const cf* vr, const float* cr, const float* ur, const cf* g,
                                      const cf* h, int k, float sr, float si) {
   if (k > 0) {
     float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
 #pragma unroll
-    for (int i = 0; i < kTK; ++i) {
-      if (i < k) {
+    for (int i = 0; i < KM; ++i) {
+      if (EXACT || i < k) {
         ar += cr[i] * g[i].re;
         ai += cr[i] * g[i].im;
         br += ur[i] * g[i].re;
@@ -609,21 +620,26 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
 // products themselves, and these kernels are bound by VALU issue, not by HBM.  Each row sums
 // 64 terms in FP32 before FP64 (16 voxels times the pre-sum); the first-pass coefficients only
 // set the orthogonalisation, whose loss the second-pass test measures.
-template <int NV, int KIND>
+// KX > 0: an instance for exactly k = KX deflation vectors (no per-slot guards or selects);
+// KX = 0: any k <= kTK.
+template <int NV, int KIND, int KX>
 __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   static_assert(NV <= 16, "chunk-accumulating instances hold at most 16 basis vectors");
+  static_assert(KX >= 0 && KX <= kTK, "exact deflation dimension out of range");
+  constexpr bool EX = KX > 0;
+  constexpr int KM = EX ? KX : kTK;
   __shared__ ProdTile<4> pt;
   const int sys = ti.sys;
   const size_t N = (size_t)c.g.N;
-  const int k = c.k, nv = NV, t = threadIdx.x;
+  const int k = EX ? KX : c.k, nv = NV, t = threadIdx.x;
   const SysParam p = c.prm[sys];
   cf* wv = c.W + (size_t)sys * N;
-  cf g[kTK], h[NV];
+  cf g[KM], h[NV];
   if (KIND == 1) {
     // the FP32 copy of this step's coefficients: block-uniform loads kept in scalar registers
     const cf* coef = reinterpret_cast<const cf*>(c.small + (size_t)sys * c.sl.total + c.sl.cA32);
 #pragma unroll
-    for (int i = 0; i < kTK; ++i) g[i] = i < k ? coef[i] : cf{0.f, 0.f};
+    for (int i = 0; i < KM; ++i) g[i] = EX || i < k ? coef[i] : cf{0.f, 0.f};
 #pragma unroll
     for (int l = 0; l < NV; ++l) h[l] = coef[k + l];
   }
@@ -636,7 +652,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   const float sj = stencil ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
   const SysF q = sys_f(c.g, p);
   cf vr[NV];
-  float cr[kTK], ur[kTK];
+  float cr[KM], ur[KM];
   cf wpre{0.f, 0.f};
   StencilRegs sreg;
   VoxelInfo vinf;
@@ -644,7 +660,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   auto fetch = [&](uint32_t n) {
     const bool ok = n < (uint32_t)c.g.N;
     load_basis<NV>(bf, ok ? n * 8u : kOutside, nv, vr);
-    load_cu(bf, k, ok ? n * 4u : kOutside, cr, ur);
+    load_cu_k<KM, EX>(bf, k, ok ? n * 4u : kOutside, cr, ur);
     vinf = voxel_info(c.g, ok ? n : 0u);
     muv = mu_at(bf, ok ? n * 4u : kOutside);
     if (stencil) {
@@ -654,11 +670,11 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
       wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
     }
   };
-  cf av[NV], ac[kTK], an{0.f, 0.f};
+  cf av[NV], ac[KM], an{0.f, 0.f};
 #pragma unroll
   for (int l = 0; l < NV; ++l) av[l] = cf{0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < kTK; ++i) ac[i] = cf{0.f, 0.f};
+  for (int i = 0; i < KM; ++i) ac[i] = cf{0.f, 0.f};
   fetch(ti.chunk * kChunk + t);
   for (int sub = 0; sub < nsub; ++sub) {
     const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
@@ -675,7 +691,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
       if (KIND == 0) {
         if (bf.precond) wv[n] = w;
       } else {
-        w = project_voxel_f<NV>(stencil ? w : wpre, vr, cr, ur, g, h, k, shr, shi);
+        w = project_voxel_f<NV, KM, EX>(stencil ? w : wpre, vr, cr, ur, g, h, k, shr, shi);
         vnext[n] = w;
       }
 #pragma unroll
@@ -686,8 +702,8 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
       }
       const float sr = shr, si = -shi;   // conj(shift)
 #pragma unroll
-      for (int i = 0; i < kTK; ++i)
-        if (i < k) {
+      for (int i = 0; i < KM; ++i)
+        if (EX || i < k) {
           const float ar = cr[i] + sr * ur[i], ai = si * ur[i];
           ac[i].re += ar * w.re - ai * w.im;
           ac[i].im += ar * w.im + ai * w.re;
@@ -700,8 +716,8 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
 #pragma unroll
   for (int l = 0; l < NV; ++l) put_product<4>(pt, l, av[l]);
 #pragma unroll
-  for (int i = 0; i < kTK; ++i)
-    if (i < k) put_product<4>(pt, nv + i, ac[i]);
+  for (int i = 0; i < KM; ++i)
+    if (EX || i < k) put_product<4>(pt, nv + i, ac[i]);
   if (with_norm) put_product<4>(pt, nv + k, an);
   __syncthreads();
   cd acc{0.0, 0.0};
@@ -712,12 +728,12 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
 // w = A_hat V_j and first-pass inner products (tiled form of k_step_dots); w is stored as W
 // only where the update cannot recompute it (preconditioner, more than 16 basis vectors).
 // flags: block order (tile_idx).  VX voxels per thread per sub-tile (NV <= 16).
-template <int NV, int P, int VX>
+template <int NV, int P, int VX, int KX = 0>
 __global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp, int flags) {
   const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   if (!c.st[ti.sys].in_cycle) return;
   if constexpr (P == 16) {
-    if constexpr (NV <= 16) tiled_step_acc<NV, 0>(c, j, ti);
+    if constexpr (NV <= 16) tiled_step_acc<NV, 0, KX>(c, j, ti);
   } else if constexpr (NV <= 16) {
     tiled_step_x<NV, 0, P, VX>(c, j, ti);
   } else {
@@ -726,12 +742,12 @@ __global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp
 }
 
 // First projection (w' stored as V_{j+1}) + second-pass inner products (tiled form of k_step_update).
-template <int NV, int P, int VX>
+template <int NV, int P, int VX, int KX = 0>
 __global__ __launch_bounds__(kTSub) void k_step_update_t(Ctx<cf> c, int j, int grp, int flags) {
   const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   if (!c.st[ti.sys].in_cycle) return;
   if constexpr (P == 16) {
-    if constexpr (NV <= 16) tiled_step_acc<NV, 1>(c, j, ti);
+    if constexpr (NV <= 16) tiled_step_acc<NV, 1, KX>(c, j, ti);
   } else if constexpr (NV <= 16) {
     tiled_step_x<NV, 1, P, VX>(c, j, ti);
   } else {

@@ -89,6 +89,22 @@ def test_medium_born_sampled(hd, medium):
     assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
 
 
+def test_medium_born_jacobian_block_sampled(hd, medium):
+    """The 42-column block (2 contrasts + 40 PaLS parameters) takes the pair-product kernel at
+    the full medium shape: sampled wavelengths against the oracle's fields."""
+    w, op, phi, it, rel, st = medium
+    S = w.S
+    v = workloads.born_v(w, n_v=42, seed=2024, dtype=np.float32)
+    assert v.shape[0] >= hd.BORN_PAIRS_MIN_NV
+    y = hd.born_apply(op, phi[:, :S], phi[:, S:], torch.from_numpy(v).to(DEV)).cpu().numpy()
+    for lam in (0, 17):
+        P = ofields.solve_separable(w, lam_idx=[lam])
+        yref = oborn.born_apply(P[:, :S], P[:, S:], v.astype(np.float64), w.h)[:, 0]
+        got = y[:, lam].astype(np.complex128)
+        assert np.max(np.linalg.norm((got - yref).reshape(42, -1), axis=1)
+                      / np.linalg.norm(yref.reshape(42, -1), axis=1)) < 1e-4
+
+
 def test_medium_plain_fp64_subset(hd):
     """The plain per-system FP64 path at full grid size: one source at 4 wavelengths, 1e-8 field parity."""
     w = workloads.subset_lambdas(workloads.config("medium"), [0, 10, 20, 31])
