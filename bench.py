@@ -174,13 +174,13 @@ def main():
                     n_v = vv.shape[0]
                     fl = 8.0 * S * D * N * L * n_v
                     # MFMA work the kernel executes: the real-ified complex product (8 S D N per probe
-                    # vector, rows padded to 8), or with the pair-product kernel (native products of
-                    # hd.BORN_PAIRS_MIN_NV or more probe vectors) 4 S D N per probe vector, pairs in
-                    # tiles of 8 x 8 and probe vectors padded to a multiple of 16
-                    pairs = name == "fp32" and n_v >= hd.BORN_PAIRS_MIN_NV
+                    # vector, rows padded to 8), or with the pair-product kernel (hd.BORN_PAIRS_MIN_NV
+                    # or more probe vectors) 4 S D N per probe vector, pairs in tiles of 8 x 8 and
+                    # probe vectors padded to a multiple of 16; split-BF16 runs three BF16 products
+                    pairs = n_v >= hd.BORN_PAIRS_MIN_NV
                     pad = lambda x, m: -(-x // m) * m
                     fl_mfma = (4.0 * pad(S, 8) * pad(D, 8) * N * L * pad(n_v, 16) if pairs
-                               else 8.0 * pad(S, 8) * pad(D, 8) * N * L * n_v)
+                               else 8.0 * pad(S, 8) * pad(D, 8) * N * L * n_v) * (3 if split else 1)
                     err = float(torch.linalg.vector_norm(y.to(torch.complex128) - ref) / torch.linalg.vector_norm(ref))
                     variants[f"{name}_nv{nv}"] = {
                         "kernel": "k_born_jv_pairs" if pairs else "k_born_jv",

@@ -187,11 +187,12 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
 /* Born products (Sec. 2.1 integral equation; rows of H in eq. measurement), never forming J.
  * Scratch (stream-ordered): n_v * n_lambda * splits * (2*pad8(S)) * (2*pad8(D)) doubles, where
  * splits (the number of voxel ranges) follows the born_blocks tuning.
- * With C128 or C64 fields and native products, blocks of n_v >= HYDOT_BORN_PAIRS_MIN_NV probe
- * vectors are contracted over source-detector pairs instead: phi_src * phi_det formed once per
- * pair and voxel (in the field precision) and multiplied with the probe block on MFMA (scratch
- * n_v * n_lambda * splits * S * D * 2 doubles).  Same accumulation (FP64 across 32-voxel stages
- * and splits); half the MFMA work per probe vector.
+ * Blocks of n_v >= HYDOT_BORN_PAIRS_MIN_NV probe vectors are contracted over source-detector
+ * pairs instead: phi_src * phi_det formed once per pair and voxel (FP64 for C128 fields, FP32
+ * otherwise) and multiplied with the probe block on MFMA (scratch n_v * n_lambda * splits * S *
+ * D * 2 doubles).  Same accumulation (FP64 across 32-voxel stages and splits); half the MFMA
+ * work per probe vector.  With CBF16 fields it is the pair product and v that are rounded to
+ * BF16 (instead of phi_src v and phi_det); split-BF16 splits the pair product and v.
  *   y[c][l][s][d] = -h^3 sum_k phi_src[l][s][k] * v[c][k] * phi_det[l][d][k]   (no conjugation)
  * phi_src: device, source s at wavelength l at phi_src + (l*lam_stride + s)*N elements;
  * phi_det: likewise with d.  lam_stride >= max(S, D) counts N-vectors between wavelengths

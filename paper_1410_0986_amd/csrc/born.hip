@@ -280,9 +280,14 @@ __global__ void k_born_apply_finish(int S, int D, int Sp, int Dp, int nsplit, in
 // rows, each against NCT tiles of 16 probe vectors.  Each stage of 32 voxels stages the 8 + 8
 // field rows and the probe-vector segments in LDS; the next stage's global loads are issued
 // before this stage's products.  FP32 products fold their stage sums into FP64 as k_born_jv.
+// CM selects the product arithmetic as in k_born_jv: the MFMA of the field precision (CM_F32,
+// CM_F64), or P formed in FP32 and rounded with the probe vectors to BF16 for
+// v_mfma_f32_16x16x32_bf16 (CM_BF16; one MFMA k-step per 32-voxel stage, lane (i, g) supplying
+// the pair products of voxels 8g..8g+7), or both split into hi + lo BF16 parts with
+// hi*hi + hi*lo + lo*hi accumulated (CM_SPLIT).
 constexpr int kPairsMinNv = HYDOT_BORN_PAIRS_MIN_NV;   // fewer: the padding to 16 costs more than it saves
 
-template <typename TS, int NCT>
+template <typename TS, int CM, int NCT>
 __global__ __launch_bounds__(kBlock) void k_born_jv_pairs(int N, int S, int D, int64_t lam_stride,
                                                          const TS* __restrict__ phs, const TS* __restrict__ phd,
                                                          const typename Field<TS>::real* __restrict__ v, int n_v,
@@ -338,15 +343,48 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_pairs(int N, int S, int D, i
     for (int e = 0; e < NE; ++e) Vs[(srow + 8 * e) * VP + skk] = rv[e];
     __syncthreads();
     if (kbase + KT < k1) fetch(kbase + KT);   // in flight during the products
+    if constexpr (CM == CM_F32 || CM == CM_F64) {
 #pragma unroll
-    for (int kk = 0; kk < KT; kk += 4) {
-      const C a = prs[kk], b = prd[kk];
-      const R pre = a.re * b.re - a.im * b.im, pim = a.re * b.im + a.im * b.re;
+      for (int kk = 0; kk < KT; kk += 4) {
+        const C a = prs[kk], b = prd[kk];
+        const R pre = a.re * b.re - a.im * b.im, pim = a.re * b.im + a.im * b.re;
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+          const R bv = pv[c * 16 * VP + kk];
+          acc[0][c] = Mfma<R>::step(pre, bv, acc[0][c]);
+          acc[1][c] = Mfma<R>::step(pim, bv, acc[1][c]);
+        }
+      }
+    } else {
+      // voxels 8g .. 8g + 7 of the stage for this lane's pair (prs, prd, pv start at voxel g)
+      float pre[8], pim[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const C a = prs[7 * g + e], b = prd[7 * g + e];
+        pre[e] = a.re * b.re - a.im * b.im;
+        pim[e] = a.re * b.im + a.im * b.re;
+      }
+      const bf16x8 rh = to_bf16x8(pre), ih = to_bf16x8(pim);
+      bf16x8 rl, il;
+      if constexpr (CM == CM_SPLIT) {
+        rl = bf16_residual(pre, rh);
+        il = bf16_residual(pim, ih);
+      }
 #pragma unroll
       for (int c = 0; c < NCT; ++c) {
-        const R bv = pv[c * 16 * VP + kk];
-        acc[0][c] = Mfma<R>::step(pre, bv, acc[0][c]);
-        acc[1][c] = Mfma<R>::step(pim, bv, acc[1][c]);
+        float vb[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) vb[e] = pv[c * 16 * VP + 7 * g + e];
+        const bf16x8 vh = to_bf16x8(vb);
+        acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh, vh, acc[0][c], 0, 0, 0);
+        acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ih, vh, acc[1][c], 0, 0, 0);
+        if constexpr (CM == CM_SPLIT) {
+          const bf16x8 vl = bf16_residual(vb, vh);
+          acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh, vl, acc[0][c], 0, 0, 0);
+          acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl, vh, acc[0][c], 0, 0, 0);
+          acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ih, vl, acc[1][c], 0, 0, 0);
+          acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(il, vh, acc[1][c], 0, 0, 0);
+        }
       }
     }
     if constexpr (kFp32) {   // FP64 accumulation across stages
@@ -527,16 +565,16 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, in
   }
 }
 
-template <typename TS, int NCT>
+template <typename TS, int CM, int NCT>
 void launch_jv_pairs(dim3 grid, hipStream_t stream, int N, int S, int D, int64_t ls, const void* phs, const void* phd,
                      const void* v, int n_v, int kb, int L, int ntd, void* part) {
   using R = typename Field<TS>::real;
-  hipLaunchKernelGGL((k_born_jv_pairs<TS, NCT>), grid, dim3(kBlock), 0, stream, N, S, D, ls, (const TS*)phs,
+  hipLaunchKernelGGL((k_born_jv_pairs<TS, CM, NCT>), grid, dim3(kBlock), 0, stream, N, S, D, ls, (const TS*)phs,
                      (const TS*)phd, (const R*)v, n_v, kb, L, ntd, (double*)part);
 }
 
-// J v for blocks of at least kPairsMinNv probe vectors (FP32 and FP64 products).
-template <typename TS>
+// J v for blocks of at least kPairsMinNv probe vectors (every product arithmetic).
+template <typename TS, int CM>
 hydot_status born_apply_pairs(const hydot_operator* op, const void* phs, int S, const void* phd, int D, int64_t ls,
                               const void* v, int n_v, void* y, hipStream_t stream) {
   using R = typename Field<TS>::real;
@@ -556,10 +594,10 @@ hydot_status born_apply_pairs(const hydot_operator* op, const void* phs, int S, 
   void* part = nullptr;
   HYDOT_HIP(hipMallocAsync(&part, pbytes, stream));
   const dim3 grid(nsplit, L, nts * ntd);
-  if (nct == 1) launch_jv_pairs<TS, 1>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
-  else if (nct == 2) launch_jv_pairs<TS, 2>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
-  else if (nct == 3) launch_jv_pairs<TS, 3>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
-  else launch_jv_pairs<TS, 4>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
+  if (nct == 1) launch_jv_pairs<TS, CM, 1>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
+  else if (nct == 2) launch_jv_pairs<TS, CM, 2>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
+  else if (nct == 3) launch_jv_pairs<TS, CM, 3>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
+  else launch_jv_pairs<TS, CM, 4>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
   const int nout = n_v * L * S * D;
   const double h = op->grid.h_mm;
   hipLaunchKernelGGL((k_born_pairs_finish<cplx<R>>), dim3((nout + 255) / 256), dim3(256), 0, stream, S * D, nsplit,
@@ -574,9 +612,7 @@ hydot_status born_apply_pairs(const hydot_operator* op, const void* phs, int S, 
 template <typename TS, int CM>
 hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
                              int64_t ls, const void* v, int n_v, void* y, hipStream_t stream) {
-  if constexpr (CM == CM_F32 || CM == CM_F64) {
-    if (n_v >= kPairsMinNv) return born_apply_pairs<TS>(op, phs, S, phd, D, ls, v, n_v, y, stream);
-  }
+  if (n_v >= kPairsMinNv) return born_apply_pairs<TS, CM>(op, phs, S, phd, D, ls, v, n_v, y, stream);
   using R = typename Field<TS>::real;
   const int N = op->gp.N, L = op->L;
   const int Sp = pad8(S), Dp = pad8(D);

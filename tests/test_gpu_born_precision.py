@@ -99,6 +99,53 @@ def test_born_bf16_fields(hd, S, D, n_v):
     assert normwise(y, ref) < 2e-2
 
 
+def _bf16_pairs_expected(Ps, Pd, v, h):
+    """oracle J v on the operands of the pair-product BF16 kernel (12 or more probe vectors):
+    P = bf16(fp32(phi_s) * fp32(phi_d)) per pair and voxel, times bf16(v)"""
+    a_re, a_im = Ps.real.astype(np.float32), Ps.imag.astype(np.float32)
+    b_re, b_im = Pd.real.astype(np.float32), Pd.imag.astype(np.float32)
+    # P[l, s, d, k] in FP32, then rounded
+    P_re = a_re[:, :, None, :] * b_re[:, None, :, :] - a_im[:, :, None, :] * b_im[:, None, :, :]
+    P_im = a_re[:, :, None, :] * b_im[:, None, :, :] + a_im[:, :, None, :] * b_re[:, None, :, :]
+    P = bf16_round_real(P_re) + 1j * bf16_round_real(P_im)
+    vb = bf16_round_real(v.astype(np.float32))
+    return -(h ** 3) * np.einsum("lsdk,ck->clsd", P, vb)
+
+
+@pytest.mark.parametrize("S,D,n_v", [(4, 4, 12), (16, 16, 33), (33, 20, 64), (9, 64, 16)])
+def test_born_bf16_fields_probe_blocks(hd, S, D, n_v):
+    """12 or more probe vectors: the pair-product kernel with BF16 MFMA products."""
+    w = workloads.config("tiny", nx=20, ny=13, nz=7, n_lambda=2)     # N = 1820, ragged stages
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(17 + S + D + n_v)
+    P = rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))
+    t = to_bf16_pairs(P).to(DEV)
+    Pr = from_bf16_pairs(t.cpu())
+    v = workloads.born_v(w, n_v=n_v, dtype=np.float32)
+    assert n_v >= hd.BORN_PAIRS_MIN_NV
+    y = hd.born_apply(op, t[:, :S], t[:, S:], torch.from_numpy(v).to(DEV)).cpu().numpy().astype(np.complex128)
+    exp = _bf16_pairs_expected(Pr[:, :S], Pr[:, S:], v, w.h)
+    assert normwise(y, exp) < 2e-6
+    ref = oborn.born_apply(P[:, :S], P[:, S:], v.astype(np.float64), w.h)
+    assert normwise(y, ref) < 2e-2
+
+
+@pytest.mark.parametrize("S,D,n_v", [(4, 4, 12), (16, 16, 42), (33, 20, 64)])
+def test_born_split_bf16_probe_blocks(hd, S, D, n_v):
+    """12 or more probe vectors: pair products split into hi + lo BF16 parts (three MFMAs)."""
+    w = workloads.config("tiny", nx=20, ny=13, nz=7, n_lambda=2)
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(23 + S + D + n_v)
+    P = rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))
+    t = torch.from_numpy(P).to(torch.complex64).to(DEV)
+    Pr = t.cpu().numpy().astype(np.complex128)
+    v = workloads.born_v(w, n_v=n_v, dtype=np.float32)
+    y = hd.born_apply(op, t[:, :S], t[:, S:], torch.from_numpy(v).to(DEV), split_bf16=True)
+    y = y.cpu().numpy().astype(np.complex128)
+    ref = oborn.born_apply(Pr[:, :S], Pr[:, S:], v.astype(np.float64), w.h)
+    assert normwise(y.reshape(n_v, -1), ref.reshape(n_v, -1)).max() < 3e-5
+
+
 def test_born_bf16_on_solver_fields(hd, tiny):
     w, ref = tiny
     op = hd.Operator.from_workload(w)
