@@ -142,6 +142,56 @@ def test_batch_config_sampled(hd):
     assert normwise(y[50].astype(np.complex128), yref) < 1e-4
 
 
+@pytest.mark.timeout(900)
+def test_large_config_sampled(hd):
+    """128x128x64 grid (1048576 voxels), 64 + 64 right-hand sides, 128 wavelengths 650-1000 nm:
+    all 16384 systems in batches of 512, the fields stored in BF16 (the Born input of this
+    workload, 68.7 GB); sampled fields against the oracle's fast diagonalisation, and BF16 J v
+    at sampled source-detector pairs against the exact products of the stored fields."""
+    torch.cuda.empty_cache()
+    w = workloads.config("large")
+    op = hd.Operator.from_workload(w)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, bench_opts(hd, max_batch=512),
+                                           out_dtype=torch.bfloat16, device=DEV)
+    s.synchronize()
+    assert phi.shape == (w.L, w.S + w.D, w.N, 2)
+    assert st == hd.OK and rel.max() <= 1e-8
+
+    def field(lam, r):
+        return torch.view_as_complex(phi[lam, r].float().contiguous()).cpu().numpy().astype(np.complex128)
+
+    # one BF16 rounding of each element: 2^-9 relative at most
+    for lam, r in [(0, 0), (77, 100), (127, 63)]:
+        ref = ofields.solve_separable(w, voxels=[w.rhs_voxels[r]], lam_idx=[lam])[0, 0]
+        assert normwise(field(lam, r), ref) < 4e-3
+    # BF16 J v at wavelength 90 for sources (3, 50) and detectors (7, 60), probe vectors v = 1
+    # and a random +-v, against the exact products of the operands the kernel multiplies
+    # (bf16(phi_s v) and the stored phi_d), within the FP32 accumulation of 32-voxel stages.
+    # (Against the oracle's fields these entries are not a test of the kernel: pairs 100 mm
+    # apart depend on field tails 1e-10 below the peak, which a solve to a normwise residual of
+    # 1e-8 does not resolve.)
+    S, lam = w.S, 90
+    v = np.stack([np.ones(w.N, dtype=np.float32), workloads.born_v(w, dtype=np.float32)[0]])
+    with torch.cuda.stream(s):
+        y = hd.born_apply(op, phi[:, :S], phi[:, S:], torch.from_numpy(v).to(DEV))
+    s.synchronize()
+    src, det = [3, 50], [7, 60]
+    got = y.cpu().numpy()[:, lam][:, src][:, :, det].astype(np.complex128)
+    Ps = np.stack([field(lam, i) for i in src])[None]
+    Pd = np.stack([field(lam, S + j) for j in det])[None]
+    for c in range(2):
+        vb = torch.from_numpy(v[c])
+        A = (torch.from_numpy(Ps.real.astype(np.float32)) * vb).to(torch.bfloat16).double().numpy() + \
+            1j * (torch.from_numpy(Ps.imag.astype(np.float32)) * vb).to(torch.bfloat16).double().numpy()
+        exp = oborn.born_apply(A, Pd, np.ones((1, w.N)), w.h)[0, 0]
+        bound = w.h ** 3 * np.einsum("lsk,ldk->sd", np.abs(A), np.abs(Pd))
+        assert np.all(np.abs(got[c] - exp) <= 1e-5 * bound), (c, (np.abs(got[c] - exp) / bound).max())
+    del phi
+    torch.cuda.empty_cache()
+
+
 def test_diff_config_fields_and_gradient(hd):
     """96x96x48 grid, 24+24 optodes, 48 wavelengths in two batches; misfit gradient by the
     adjoint kernels against central finite differences of the device misfit (FP64 fields)."""
