@@ -192,6 +192,27 @@ def test_large_config_sampled(hd):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("name", ["large_g32", "large_g48", "large_g80"])
+def test_large_companion_grids(hd, name):
+    """The three smaller grids of the large workload (128 wavelengths 650-1000 nm), each a
+    separate operator solved in full by the batched path (complex FP32 output; at most 2048
+    systems per batch: the 80^3-class grid's 8192 systems would need a 333 GB workspace)."""
+    torch.cuda.empty_cache()
+    w = workloads.config(name)
+    op = hd.Operator.from_workload(w)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, bench_opts(hd, max_batch=2048),
+                                           out_dtype=torch.complex64, device=DEV)
+    s.synchronize()
+    assert st == hd.OK and rel.shape == (w.L, w.S + w.D) and rel.max() <= 1e-8
+    R = w.S + w.D
+    for lam, r in [(0, R - 1), (100, 1)]:
+        ref = ofields.solve_separable(w, voxels=[w.rhs_voxels[r]], lam_idx=[lam])[0, 0]
+        assert normwise(phi[lam, r].cpu().numpy().astype(np.complex128), ref) < 1e-4
+    del phi
+
+
 def test_diff_config_fields_and_gradient(hd):
     """96x96x48 grid, 24+24 optodes, 48 wavelengths in two batches; misfit gradient by the
     adjoint kernels against central finite differences of the device misfit (FP64 fields)."""
