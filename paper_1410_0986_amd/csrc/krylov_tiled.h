@@ -271,6 +271,42 @@ __device__ inline void gather_stencil(const GridP& g, Rsrc r, uint32_t so, uint3
   sr.m[4] = ld_cf(r, ok && vi.k > 0 ? (n - sz) * 8u : kOutside, so);
   sr.m[5] = ld_cf(r, ok && vi.k < g.nz - 1 ? (n + sz) * 8u : kOutside, so);
 }
+// Chunk-accumulating form: voxels are numbered consecutively across the lanes of a wave, so the
+// x - 1 and x + 1 neighbours of lanes 1..63 and 0..62 are the adjacent lanes' centres and come
+// by wave-wide DPP shifts once the centre is in a register (stencil_x_from_lanes).  Only lane 0
+// and lane 63 load theirs, and only when the neighbour is inside the grid (never for x rows of
+// 64 voxels); the y and z neighbours are loaded as in gather_stencil.
+__device__ inline void gather_stencil_yz(const GridP& g, Rsrc r, uint32_t so, uint32_t n, bool ok,
+                                         const VoxelInfo& vi, StencilRegs& sr, bool load_centre) {
+  const uint32_t sy = (uint32_t)g.nx, sz = (uint32_t)g.nx * (uint32_t)g.ny;
+  const int lane = threadIdx.x & 63;
+  if (load_centre) sr.xc = ld_cf(r, ok ? n * 8u : kOutside, so);
+  sr.m[0] = cf{0.f, 0.f};
+  sr.m[1] = cf{0.f, 0.f};
+  if (lane == 0 && ok && vi.i > 0) sr.m[0] = ld_cf(r, (n - 1) * 8u, so);
+  if (lane == 63 && ok && vi.i < g.nx - 1) sr.m[1] = ld_cf(r, (n + 1) * 8u, so);
+  sr.m[2] = ld_cf(r, ok && vi.j > 0 ? (n - sy) * 8u : kOutside, so);
+  sr.m[3] = ld_cf(r, ok && vi.j < g.ny - 1 ? (n + sy) * 8u : kOutside, so);
+  sr.m[4] = ld_cf(r, ok && vi.k > 0 ? (n - sz) * 8u : kOutside, so);
+  sr.m[5] = ld_cf(r, ok && vi.k < g.nz - 1 ? (n + sz) * 8u : kOutside, so);
+}
+// value of lane - 1 (0 in lane 0) and of lane + 1 (0 in lane 63): DPP wave_shr:1 / wave_shl:1
+__device__ inline float lane_prev(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xF, 0xF, true));
+}
+__device__ inline float lane_next(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xF, 0xF, true));
+}
+// x neighbours of the inner lanes from the centres; called by every lane of the wave
+__device__ inline void stencil_x_from_lanes(const GridP& g, const VoxelInfo& vi, StencilRegs& sr) {
+  const int lane = threadIdx.x & 63;
+  const cf prev{lane_prev(sr.xc.re), lane_prev(sr.xc.im)};
+  const cf next{lane_next(sr.xc.re), lane_next(sr.xc.im)};
+  const cf z{0.f, 0.f};
+  sr.m[0] = lane == 0 ? sr.m[0] : (vi.i > 0 ? prev : z);
+  sr.m[1] = lane == 63 ? sr.m[1] : (vi.i < g.nx - 1 ? next : z);
+}
+
 // (A_hat x)_n from gathered operands: the same arithmetic as apply_op.
 __device__ inline cf stencil_apply(const GridP& g, const StencilRegs& sr, const VoxelInfo& vi, cd sig,
                                    double sigp, double extra) {
@@ -664,7 +700,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
     vinf = voxel_info(c.g, ok ? n : 0u);
     muv = mu_at(bf, ok ? n * 4u : kOutside);
     if (stencil) {
-      gather_stencil(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf, sreg, bf.precond);
+      gather_stencil_yz(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf, sreg, bf.precond);
       if (!bf.precond) sreg.xc = vr[NV - 1];
     } else {
       wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
@@ -679,6 +715,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   for (int sub = 0; sub < nsub; ++sub) {
     const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
     const bool ok = n < (uint32_t)c.g.N;
+    if (stencil) stencil_x_from_lanes(c.g, vinf, sreg);   // every lane (no divergence yet)
     if (ok) {
       // C' shift of this voxel: sigma + sigma'_rel rho + tau_rel mu
       const float shr = q.sig_re + q.sigp_rel_h * (float)vinf.nrobin + q.tau_rel * muv, shi = q.sig_im;
