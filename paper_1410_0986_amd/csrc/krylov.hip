@@ -229,6 +229,12 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   p.mean_shift = (o->flags & (HYDOT_FLAG_MEAN_SHIFT | HYDOT_FLAG_SHIFT_MIN | HYDOT_FLAG_SHIFT_MAX)) != 0;
   p.shift_kind = (o->flags & HYDOT_FLAG_SHIFT_MIN) ? 1 : (o->flags & HYDOT_FLAG_SHIFT_MAX) ? 2 : 0;
   p.mkmax = std::max(p.mk, p.nl);
+  // the FP32 step kernels address each system's basis and each right-hand side's C and U
+  // through buffer resources of 32-bit byte offsets
+  if (o->precision == HYDOT_PREC_MIXED &&
+      ((uint64_t)(p.mk + 1) * (uint64_t)p.N * 8u >= (1ull << 31) || (uint64_t)p.k * (uint64_t)p.N * 4u >= (1ull << 31)))
+    return fail(HYDOT_EUNSUPPORTED, "solve: a system's Krylov basis or a right-hand side's C or U block would "
+                                    "exceed 2 GiB; lower restart_m or recycle_k");
   p.precond = (o->flags & HYDOT_FLAG_PRECOND_SEP) ? 1 : (o->flags & HYDOT_FLAG_PRECOND_SEP_FIXED) ? 2 : 0;
   if (p.precond) {
     // right preconditioning lives in the register-resident FP32 step kernels only
@@ -313,7 +319,7 @@ struct Solver {
 
   template <typename S>
   Ctx<S> ctx(int k, bool lanczos) const {
-    Ctx<S> c;
+    Ctx<S> c{};
     c.g = op->gp;
     c.k = k;
     c.mkmax = p.mkmax;

@@ -216,12 +216,7 @@ __device__ inline void load_cu_k(const SysBuf& b, int k, uint32_t vo4, float* cr
   }
 }
 __device__ inline void load_cu(const SysBuf& b, int k, uint32_t vo4, float* cr, float* ur) {
-#pragma unroll
-  for (int i = 0; i < kTK; ++i) {
-    const bool on = i < k;
-    cr[i] = on ? ld_f(b.C, vo4, (uint32_t)i * b.sc) : 0.f;
-    ur[i] = on ? ld_f(b.U, vo4, (uint32_t)i * b.sc) : 0.f;
-  }
+  load_cu_k<kTK, false>(b, k, vo4, cr, ur);
 }
 
 // w - C'g - sum_l h_l V_l for one voxel, from registers
@@ -849,7 +844,7 @@ __global__ __launch_bounds__(kTSub) void k_inner_resid_t(Ctx<cf> c, int grp, int
     load_cu(bf, k, ok ? n * 4u : kOutside, cr, ur);
     vinf = voxel_info(c.g, ok ? n : 0u);
     muv = mu_at(bf, ok ? n * 4u : kOutside);
-    gather_stencil(c.g, rD, 0u, n, ok, vinf, sreg);
+    gather_stencil_yz(c.g, rD, 0u, n, ok, vinf, sreg, true);
     rin = ld_cf(rR, ok ? n * 8u : kOutside, 0u);
   };
   cd acc{0.0, 0.0};
@@ -861,6 +856,7 @@ __global__ __launch_bounds__(kTSub) void k_inner_resid_t(Ctx<cf> c, int grp, int
     const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
     const bool ok = n < (uint32_t)c.g.N;
     const double rho = ok ? (double)vinf.nrobin * c.g.inv_h : 0.0;
+    stencil_x_from_lanes(c.g, vinf, sreg);   // every lane (no divergence yet)
     cf w{0.f, 0.f};
     if (ok) {
       const cf ad = stencil_apply(c.g, sreg, vinf, p.sig, p.sigp_abs, p.tau_abs * (double)muv);

@@ -234,3 +234,17 @@ def test_binding_constants_mirror_header(hd):
     text = open(HEADER).read()
     m = re.search(r"#define\s+HYDOT_BORN_PAIRS_MIN_NV\s+(\d+)", text)
     assert m and int(m.group(1)) == hd.BORN_PAIRS_MIN_NV
+
+
+def test_solve_rejects_basis_beyond_buffer_range(hd):
+    """The FP32 step kernels address a system's Krylov basis through 32-bit byte offsets: a
+    512 x 512 x 256 grid with restart_m - recycle_k = 4 needs 5 x 2^26 x 8 B > 2 GiB per system."""
+    w = workloads.config("tiny", nx=512, ny=512, nz=256, n_lambda=2)
+    op = _op(hd, w)
+    mixed = hd.SolveOptions(restart_m=8, recycle_k=4, lanczos_n=8, precision=hd.PREC_MIXED)
+    with pytest.raises(hd.HydotError) as e:
+        hd.solve_workspace_bytes(op, 2, mixed)
+    assert e.value.status == hd.EUNSUPPORTED
+    # the FP64 path has no such limit
+    assert hd.solve_workspace_bytes(op, 2, hd.SolveOptions(restart_m=8, recycle_k=4, lanczos_n=8,
+                                                           precision=hd.PREC_FP64)) > 0
