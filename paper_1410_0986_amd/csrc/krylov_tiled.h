@@ -271,8 +271,11 @@ __device__ inline void gather_stencil(const GridP& g, Rsrc r, uint32_t so, uint3
 // by wave-wide DPP shifts once the centre is in a register (stencil_x_from_lanes).  Only lane 0
 // and lane 63 load theirs, and only when the neighbour is inside the grid (never for x rows of
 // 64 voxels); the y and z neighbours are loaded as in gather_stencil.
+// y_lo_lds / y_hi_lds: the y - 1 / y + 1 neighbour is another thread's centre in the same
+// sub-tile and comes from LDS (stencil_y_from_tile) instead.
 __device__ inline void gather_stencil_yz(const GridP& g, Rsrc r, uint32_t so, uint32_t n, bool ok,
-                                         const VoxelInfo& vi, StencilRegs& sr, bool load_centre) {
+                                         const VoxelInfo& vi, StencilRegs& sr, bool load_centre,
+                                         bool y_lo_lds = false, bool y_hi_lds = false) {
   const uint32_t sy = (uint32_t)g.nx, sz = (uint32_t)g.nx * (uint32_t)g.ny;
   const int lane = threadIdx.x & 63;
   if (load_centre) sr.xc = ld_cf(r, ok ? n * 8u : kOutside, so);
@@ -280,8 +283,10 @@ __device__ inline void gather_stencil_yz(const GridP& g, Rsrc r, uint32_t so, ui
   sr.m[1] = cf{0.f, 0.f};
   if (lane == 0 && ok && vi.i > 0) sr.m[0] = ld_cf(r, (n - 1) * 8u, so);
   if (lane == 63 && ok && vi.i < g.nx - 1) sr.m[1] = ld_cf(r, (n + 1) * 8u, so);
-  sr.m[2] = ld_cf(r, ok && vi.j > 0 ? (n - sy) * 8u : kOutside, so);
-  sr.m[3] = ld_cf(r, ok && vi.j < g.ny - 1 ? (n + sy) * 8u : kOutside, so);
+  sr.m[2] = cf{0.f, 0.f};
+  sr.m[3] = cf{0.f, 0.f};
+  if (!y_lo_lds) sr.m[2] = ld_cf(r, ok && vi.j > 0 ? (n - sy) * 8u : kOutside, so);
+  if (!y_hi_lds) sr.m[3] = ld_cf(r, ok && vi.j < g.ny - 1 ? (n + sy) * 8u : kOutside, so);
   sr.m[4] = ld_cf(r, ok && vi.k > 0 ? (n - sz) * 8u : kOutside, so);
   sr.m[5] = ld_cf(r, ok && vi.k < g.nz - 1 ? (n + sz) * 8u : kOutside, so);
 }
@@ -300,6 +305,18 @@ __device__ inline void stencil_x_from_lanes(const GridP& g, const VoxelInfo& vi,
   const cf z{0.f, 0.f};
   sr.m[0] = lane == 0 ? sr.m[0] : (vi.i > 0 ? prev : z);
   sr.m[1] = lane == 63 ? sr.m[1] : (vi.i < g.nx - 1 ? next : z);
+}
+
+// y neighbours inside the sub-tile (x rows shorter than a sub-tile): every thread publishes its
+// centre in one of two LDS buffers (alternating by sub-tile, so one barrier per sub-tile
+// suffices) and takes the neighbour n - nx (n + nx) from thread t - nx (t + nx).  Called by
+// every thread of the block.
+__device__ inline void stencil_y_from_tile(const GridP& g, const VoxelInfo& vi, StencilRegs& sr, cf* xb, int t) {
+  xb[t] = sr.xc;
+  __syncthreads();
+  const cf z{0.f, 0.f};
+  if (t >= g.nx) sr.m[2] = vi.j > 0 ? xb[t - g.nx] : z;
+  if (t + g.nx < kTSub) sr.m[3] = vi.j < g.ny - 1 ? xb[t + g.nx] : z;
 }
 
 // (A_hat x)_n from gathered operands: the same arithmetic as apply_op.
@@ -660,6 +677,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   constexpr bool EX = KX > 0;
   constexpr int KM = EX ? KX : kTK;
   __shared__ ProdTile<4> pt;
+  __shared__ cf xs[2][kTSub];   // centres of the sub-tile, for the y neighbours
   const int sys = ti.sys;
   const size_t N = (size_t)c.g.N;
   const int k = EX ? KX : c.k, nv = NV, t = threadIdx.x;
@@ -680,6 +698,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   const SysBuf bf = sys_buf(c, sys, p.rhs);
   cf* vnext = c.V + ((size_t)sys * c.vdim + j + 1) * N;
   const bool stencil = KIND == 0 || !bf.precond;
+  const bool ytile = stencil && c.g.nx < kTSub;   // some y neighbours lie in the same sub-tile
   const float sj = stencil ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
   const SysF q = sys_f(c.g, p);
   cf vr[NV];
@@ -695,7 +714,8 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
     vinf = voxel_info(c.g, ok ? n : 0u);
     muv = mu_at(bf, ok ? n * 4u : kOutside);
     if (stencil) {
-      gather_stencil_yz(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf, sreg, bf.precond);
+      gather_stencil_yz(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf, sreg, bf.precond,
+                        ytile && t >= c.g.nx, ytile && t + c.g.nx < kTSub);
       if (!bf.precond) sreg.xc = vr[NV - 1];
     } else {
       wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
@@ -711,6 +731,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
     const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
     const bool ok = n < (uint32_t)c.g.N;
     if (stencil) stencil_x_from_lanes(c.g, vinf, sreg);   // every lane (no divergence yet)
+    if (ytile) stencil_y_from_tile(c.g, vinf, sreg, xs[sub & 1], t);
     if (ok) {
       // C' shift of this voxel: sigma + sigma'_rel rho + tau_rel mu
       const float shr = q.sig_re + q.sigp_rel_h * (float)vinf.nrobin + q.tau_rel * muv, shi = q.sig_im;
