@@ -307,16 +307,20 @@ __device__ inline void stencil_x_from_lanes(const GridP& g, const VoxelInfo& vi,
   sr.m[1] = lane == 63 ? sr.m[1] : (vi.i < g.nx - 1 ? next : z);
 }
 
-// y neighbours inside the sub-tile (x rows shorter than a sub-tile): every thread publishes its
-// centre in one of two LDS buffers (alternating by sub-tile, so one barrier per sub-tile
-// suffices) and takes the neighbour n - nx (n + nx) from thread t - nx (t + nx).  Called by
-// every thread of the block.
-__device__ inline void stencil_y_from_tile(const GridP& g, const VoxelInfo& vi, StencilRegs& sr, cf* xb, int t) {
-  xb[t] = sr.xc;
+// y neighbours from other threads' centres (x rows of at most one sub-tile): every thread
+// publishes its centre in the sub-tile's LDS row; three rows rotate, so that the previous
+// sub-tile's row is still intact while this one is read and one barrier per sub-tile suffices.
+// y - 1 comes from this row (t >= nx) or the previous one (later sub-tiles), y + 1 from this
+// row when it lies in the sub-tile; the rest was loaded (gather_stencil_yz).  Called by every
+// thread of the block.
+__device__ inline void stencil_y_from_tile(const GridP& g, const VoxelInfo& vi, StencilRegs& sr, cf* cur,
+                                           const cf* prev, bool has_prev, int t) {
+  cur[t] = sr.xc;
   __syncthreads();
   const cf z{0.f, 0.f};
-  if (t >= g.nx) sr.m[2] = vi.j > 0 ? xb[t - g.nx] : z;
-  if (t + g.nx < kTSub) sr.m[3] = vi.j < g.ny - 1 ? xb[t + g.nx] : z;
+  if (t >= g.nx) sr.m[2] = vi.j > 0 ? cur[t - g.nx] : z;
+  else if (has_prev) sr.m[2] = vi.j > 0 ? prev[t - g.nx + kTSub] : z;
+  if (t + g.nx < kTSub) sr.m[3] = vi.j < g.ny - 1 ? cur[t + g.nx] : z;
 }
 
 // (A_hat x)_n from gathered operands: the same arithmetic as apply_op.
@@ -677,7 +681,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   constexpr bool EX = KX > 0;
   constexpr int KM = EX ? KX : kTK;
   __shared__ ProdTile<4> pt;
-  __shared__ cf xs[2][kTSub];   // centres of the sub-tile, for the y neighbours
+  __shared__ cf xs[3][kTSub];   // centres of the last sub-tiles, for the y neighbours
   const int sys = ti.sys;
   const size_t N = (size_t)c.g.N;
   const int k = EX ? KX : c.k, nv = NV, t = threadIdx.x;
@@ -698,7 +702,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   const SysBuf bf = sys_buf(c, sys, p.rhs);
   cf* vnext = c.V + ((size_t)sys * c.vdim + j + 1) * N;
   const bool stencil = KIND == 0 || !bf.precond;
-  const bool ytile = stencil && c.g.nx < kTSub;   // some y neighbours lie in the same sub-tile
+  const bool ytile = stencil && c.g.nx <= kTSub;   // y neighbours in this or the previous sub-tile
   const float sj = stencil ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
   const SysF q = sys_f(c.g, p);
   cf vr[NV];
@@ -707,7 +711,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   StencilRegs sreg;
   VoxelInfo vinf;
   float muv;
-  auto fetch = [&](uint32_t n) {
+  auto fetch = [&](uint32_t n, bool first) {   // first: the chunk's first sub-tile
     const bool ok = n < (uint32_t)c.g.N;
     load_basis<NV>(bf, ok ? n * 8u : kOutside, nv, vr);
     load_cu_k<KM, EX>(bf, k, ok ? n * 4u : kOutside, cr, ur);
@@ -715,7 +719,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
     muv = mu_at(bf, ok ? n * 4u : kOutside);
     if (stencil) {
       gather_stencil_yz(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf, sreg, bf.precond,
-                        ytile && t >= c.g.nx, ytile && t + c.g.nx < kTSub);
+                        ytile && (t >= c.g.nx || !first), ytile && t + c.g.nx < kTSub);
       if (!bf.precond) sreg.xc = vr[NV - 1];
     } else {
       wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
@@ -726,12 +730,12 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   for (int l = 0; l < NV; ++l) av[l] = cf{0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < KM; ++i) ac[i] = cf{0.f, 0.f};
-  fetch(ti.chunk * kChunk + t);
+  fetch(ti.chunk * kChunk + t, true);
   for (int sub = 0; sub < nsub; ++sub) {
     const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
     const bool ok = n < (uint32_t)c.g.N;
     if (stencil) stencil_x_from_lanes(c.g, vinf, sreg);   // every lane (no divergence yet)
-    if (ytile) stencil_y_from_tile(c.g, vinf, sreg, xs[sub & 1], t);
+    if (ytile) stencil_y_from_tile(c.g, vinf, sreg, xs[sub % 3], xs[(sub + 2) % 3], sub > 0, t);
     if (ok) {
       // C' shift of this voxel: sigma + sigma'_rel rho + tau_rel mu
       const float shr = q.sig_re + q.sigp_rel_h * (float)vinf.nrobin + q.tau_rel * muv, shi = q.sig_im;
@@ -763,7 +767,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
         }
       if (with_norm) an.re += w.re * w.re + w.im * w.im;
     }
-    if (sub + 1 < nsub) fetch(n + kTSub);
+    if (sub + 1 < nsub) fetch(n + kTSub, false);
   }
   // one block reduction per chunk: rows [0, nv) V, [nv, nv + k) C', nv + k the norm
 #pragma unroll
