@@ -690,8 +690,18 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
     const bool want = (need_defl && s < 3 * k && s % 3 == 0) || (s >= lo && s < hi) ||
                       (need_norm && s == sn);
     cd a{0.0, 0.0};
-    if (want)
-      for (int ck = 0; ck < c.nchunks; ++ck) a = a + part[(size_t)ck * c.ndots + s];
+    if (want) {
+      // eight interleaved partial sums, so that the chunk loads overlap (fixed order)
+      cd q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = cd{0.0, 0.0};
+      int ck = 0;
+      for (; ck + 8 <= c.nchunks; ck += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = q[u] + part[(size_t)(ck + u) * c.ndots + s];
+      for (; ck < c.nchunks; ++ck) q[0] = q[0] + part[(size_t)ck * c.ndots + s];
+      a = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+    }
     sum[s] = a;
   }
   __syncthreads();
