@@ -41,7 +41,7 @@ N_JAC = 42                  # Jacobian block: 2 chromophore contrasts + 40 PaLS 
 # They belong to the kernel sources with this SHA-256 (common.h, krylov_kernels.h,
 # krylov_tiled.h); after any change to those the traffic is reported as null.
 # They also hold only for the launch shape they were taken with (TRAFFIC_TUNING), per block order.
-TRAFFIC_SOURCES_SHA256 = "8ddbc2c01594be87cbeae490d45ea45a9a9de02c1e90b22069cfe213c70e59c1"
+TRAFFIC_SOURCES_SHA256 = "db11902b439aa098e59265b181e4e63e2e154095c35ef4fa49d6b36b052d0287"
 TRAFFIC_TUNING = {"step_presum": 16, "step_group": 2, "step_vx": 1}
 TRAFFIC_BYTES_PER_LAUNCH = {   # step_order -> kernel -> calibrated HBM bytes per launch
     3: {"k_step_dots_t": 5.320e9, "k_step_update_t": 6.051e9, "k_step_finish_t": 1.208e6},
