@@ -109,6 +109,24 @@ def test_solve_mixed_precision(hd):
     _check_fields(w, phi64.cpu().numpy(), rel, 1e-6, 1e-8, ref)
 
 
+@pytest.mark.parametrize("dims", [(150, 5, 4), (128, 6, 4), (40, 7, 6)])
+@pytest.mark.parametrize("k", [5, 6])
+def test_solve_mixed_row_lengths(hd, dims, k):
+    """The step kernels take x neighbours from the adjacent lanes and y neighbours from LDS rows
+    of the block's centres when an x row fits a 128-voxel sub-tile: rows longer than a sub-tile
+    (150), exactly one (128) and rows straddling waves (40), with the exact-k (5) and the
+    runtime-k (6) instances."""
+    nx, ny, nz = dims
+    w = workloads.config("tiny", nx=nx, ny=ny, nz=nz, n_lambda=3)
+    op = hd.Operator.from_workload(w)
+    o = hd.SolveOptions(rel_tol=1e-8, restart_m=k + 13, recycle_k=k, lanczos_n=24, precision=hd.PREC_MIXED,
+                        inner_tol=1e-5, flags=hd.FLAG_MEAN_SHIFT)
+    phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, o, out_dtype=torch.complex64, device=DEV)
+    assert st == hd.OK and rel.max() <= 1e-8
+    ref = oracle_fields(w)
+    assert normwise(phi.cpu().numpy().astype(np.complex128), ref).max() < 1e-4
+
+
 def test_per_system_and_graph_modes_agree(hd):
     w = workloads.config("tiny", n_lambda=3)
     op = hd.Operator.from_workload(w)
