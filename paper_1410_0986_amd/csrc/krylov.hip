@@ -7,6 +7,7 @@
 #include <complex>
 #include <type_traits>
 #include <cstring>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -23,23 +24,31 @@ namespace hydot {
 // The small per-right-hand-side and per-system algebra of the set-up (harmonic Ritz pairs,
 // Gram Cholesky factors, multi-shift least squares) is independent between systems: it runs
 // on up to kHostThreads host threads while the GPU waits for it.  f(i) returns false on
-// failure; the result is the lowest failing index, or -1.
+// failure (an exception thrown by f counts as one); the result is the lowest failing index,
+// or -1.
 constexpr int kHostThreads = 16;
 template <typename F>
 int host_parallel_for(int n, const F& f) {
   const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
   const int nt = std::min({n, kHostThreads, hw});
   std::vector<int> bad(std::max(nt, 1), -1);
+  auto safe = [&](int i) {
+    try {
+      return f(i);
+    } catch (...) {
+      return false;
+    }
+  };
   auto work = [&](int t) {
     for (int i = t; i < n; i += nt)
-      if (!f(i)) {
+      if (!safe(i)) {
         bad[t] = i;
         return;
       }
   };
   if (nt <= 1) {
     for (int i = 0; i < n; ++i)
-      if (!f(i)) return i;
+      if (!safe(i)) return i;
     return -1;
   }
   std::vector<std::thread> th;
@@ -922,9 +931,10 @@ hydot_status hydot_solve_workspace_bytes(const hydot_operator* op, int32_t n_rhs
   return HYDOT_OK;
 }
 
-hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
-                                const hydot_solve_opts* opts, void* phi, hydot_dtype phi_dtype, void* workspace,
-                                size_t ws_bytes, int32_t* iters, double* rel_res, hipStream_t stream) {
+static hydot_status solve_fields_body(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
+                                      const hydot_solve_opts* opts, void* phi, hydot_dtype phi_dtype,
+                                      void* workspace, size_t ws_bytes, int32_t* iters, double* rel_res,
+                                      hipStream_t stream) {
   Plan p;
   hydot_status s = make_plan(op, n_rhs, opts, p);
   if (s != HYDOT_OK) return s;
@@ -974,6 +984,20 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
   if (rel_res) std::memcpy(rel_res, rr.data(), rr.size() * sizeof(double));
   if (!all) return fail(HYDOT_ENOCONV, "solve: some systems did not reach rel_tol (see rel_res)");
   return HYDOT_OK;
+}
+
+hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
+                                const hydot_solve_opts* opts, void* phi, hydot_dtype phi_dtype, void* workspace,
+                                size_t ws_bytes, int32_t* iters, double* rel_res, hipStream_t stream) {
+  // no C++ exception crosses the C boundary (host set-up allocates)
+  try {
+    return solve_fields_body(op, n_rhs, rhs_voxel, opts, phi, phi_dtype, workspace, ws_bytes, iters, rel_res,
+                             stream);
+  } catch (const std::bad_alloc&) {
+    return fail(HYDOT_ENOMEM, "solve: host allocation failed");
+  } catch (...) {
+    return fail(HYDOT_EDEVICE, "solve: unexpected host error");
+  }
 }
 
 hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
