@@ -52,7 +52,7 @@ typedef enum {
   HYDOT_OK = 0,
   HYDOT_ENOCONV = 1,        /* warning: some systems above tolerance; outputs written */
   HYDOT_EINVAL = -1,        /* invalid argument; nothing launched, outputs untouched */
-  HYDOT_ENOMEM = -2,        /* workspace too small */
+  HYDOT_ENOMEM = -2,        /* workspace too small, or a host allocation failed */
   HYDOT_EDEVICE = -3,       /* a HIP runtime call failed */
   HYDOT_EUNSUPPORTED = -4   /* valid but not supported combination (e.g. dtype) */
 } hydot_status;
@@ -178,7 +178,8 @@ hydot_status hydot_solve_workspace_bytes(const hydot_operator* op, int32_t n_rhs
  * iters: host [n_lambda*n_rhs] (lambda-major) Arnoldi steps per system, or NULL.
  * rel_res: host [n_lambda*n_rhs] final FP64-recomputed ||b - A phi||/||b|| of the
  *   FP64 iterate (before any conversion to C64 or CBF16), or NULL.
- * Returns HYDOT_ENOCONV (fields still written) if any system stays above rel_tol. */
+ * Returns HYDOT_ENOCONV (fields still written) if any system stays above rel_tol; HYDOT_ENOMEM if
+ * a host allocation of the set-up fails (work may then be left queued on the stream). */
 hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t* rhs_voxel,
                                 const hydot_solve_opts* opts, void* phi, hydot_dtype phi_dtype,
                                 void* workspace, size_t ws_bytes, int32_t* iters, double* rel_res,
