@@ -8,13 +8,17 @@ Readings (the algorithm box leaves these open or prints them garbled):
   (the stopping rule of the text); an outer pass also ends when its LM steps gained less than a
   relative 1e-6 (noise-free data never meet a zero target), and an inner pass after max_inner
   steps or a step that no damping could make descend;
-* the damping term of the LM step is nu diag(J^T J) (Marquardt's scaling; the printed step
-  shows nu I, which is the same step in parameters scaled to unit curvature): the parameters
-  have unrelated units (alpha none, beta 1/mm, centres mm) and their Jacobian columns differ by
-  orders of magnitude, and with nu I the iteration stalls long before the discrepancy level;
-  nu starts at 1e-3, is divided by 10 after an accepted step (floor 1e-12) and multiplied by
-  10 after a rejected one (at most 12 tries per step); a step is accepted when it lowers the
-  misfit at the current contrasts;
+* the LM step is the printed one, (J^T J + nu I) dp = -J^T eps (damping="identity", the
+  default), with nu starting at 1e-3 max diag(J^T J); damping="marquardt" takes Marquardt's
+  scaling nu diag(J^T J) instead, with nu starting at 1e-3 (the parameters have unrelated units
+  -- alpha none, beta 1/mm, centres mm -- and the scaled form is the printed step in parameters
+  scaled to unit curvature).  Either way nu is divided by 10 after an accepted step and
+  multiplied by 10 after a rejected one (at most 12 tries per step); a step is accepted when it
+  lowers the misfit at the current contrasts.  The floor of nu is 1e-12 for nu I and 1e-6 for
+  the scaled form: there nu is relative to each curvature entry, so below 1e-6 it no longer
+  changes the step, and the 12 tries must still reach a damping far above the curvature (from a
+  floor of 1e-12 they reach only nu = 1, too little where voxels cross the band of the smoothed
+  Heaviside, and the pass then ends without a step);
 * the complex residual and Jacobian are split into real and imaginary parts, so the unknowns
   stay real;
 * after the discrepancy stop the contrasts are refitted once more at the final shape.
@@ -51,7 +55,9 @@ def lm_jacobian(H, w, p, c, ext, W, tau, eps, nu):
 
 
 def reconstruct(H, w, ext, y, p0, c0=None, W=1.0, noise_norm=0.0, gamma=1.05, max_outer=20, max_inner=8,
-                tau=0.5, eps=0.5, nu=1e-3, fix_c=False):
+                tau=0.5, eps=0.5, nu=1e-3, fix_c=False, damping="identity"):
+    if damping not in ("identity", "marquardt"):
+        raise ValueError("damping must be 'identity' or 'marquardt'")
     p = np.array(p0, dtype=float)
     mu, Hmu = forward_parts(H, w, p, tau, eps, nu)
     c = np.array(c0, dtype=float) if c0 is not None else lstsq_contrasts(ext, Hmu, y, W)
@@ -74,9 +80,12 @@ def reconstruct(H, w, ext, y, p0, c0=None, W=1.0, noise_norm=0.0, gamma=1.05, ma
             r = (W * (y - (c @ ext)[:, None, None] * Hmu)).ravel()
             e = np.concatenate([r.real, r.imag])
             JTJ = J.T @ J
-            scale = np.diag(JTJ.diagonal())
+            if damping == "identity":
+                scale = np.eye(len(p))
+            else:
+                scale = np.diag(JTJ.diagonal())
             if damp is None:
-                damp = 1e-3
+                damp = 1e-3 * (JTJ.diagonal().max() if damping == "identity" else 1.0)
             ok = False
             for _ in range(12):
                 step = np.linalg.solve(JTJ + damp * scale, -(J.T @ e))
@@ -84,7 +93,7 @@ def reconstruct(H, w, ext, y, p0, c0=None, W=1.0, noise_norm=0.0, gamma=1.05, ma
                 ft = misfit(c, Hm)
                 if ft < f:
                     p, Hmu, f = p + step, Hm, ft
-                    damp = max(damp / 10.0, 1e-12)
+                    damp = max(damp / 10.0, 1e-12 if damping == "identity" else 1e-6)
                     ok = True
                     break
                 damp *= 10.0

@@ -2,9 +2,12 @@
 Alg. opt): alternate the linear least-squares solve for the contrasts c with Levenberg-Marquardt
 steps for the shape parameters p, stopping by the discrepancy principle.
 
-The LM step is (J^T J + nu diag(J^T J)) dp = -J^T eps (Marquardt's scaling of the damping,
-which makes the step independent of the parameters' units), nu from 1e-3, /10 after an accepted
-step, x10 after a rejected one.
+The LM step is the one Alg. opt prints, (J^T J + nu I) dp = -J^T eps, with nu from
+1e-3 max diag(J^T J) (floor 1e-12); damping="marquardt" selects Marquardt's scaling
+(J^T J + nu diag(J^T J)) dp = -J^T eps instead, which makes the step independent of the
+parameters' units, with nu from 1e-3 (floor 1e-6: nu is relative to each curvature entry there).
+Either way nu is divided by 10 after an accepted step and multiplied by 10 after a rejected
+one, at most 12 tries per step.
 
 Data model (eq. measurement, eq. minimization): y[l, s, d] = sum_i c_i eps_i(lambda_l) (H mu(p))[l, s, d]
 + noise, residual eps = W (y - D(p) c) with the columns of D(p) = E_i H mu(p).  The LM Jacobian is
@@ -108,10 +111,14 @@ class ReconResult:
 
 def reconstruct(model: BornModel, y: np.ndarray, p0: np.ndarray, c0=None, noise_norm: float = 0.0,
                 gamma: float = 1.05, max_outer: int = 20, max_inner: int = 8, fix_c: bool = False,
-                lm_nu0: float = 1e-3, rtol: float = 1e-6) -> ReconResult:
+                lm_nu0: float = 1e-3, rtol: float = 1e-6, damping: str = "identity") -> ReconResult:
     """Alg. opt.  y: [L, S, D] complex data; p0: initial PaLS parameters; noise_norm: ||W eta||
     for the discrepancy principle ||eps|| <= gamma ||W eta|| (0: noise-free, stop on stagnation).
-    fix_c: keep c = c0 (shape-only reconstruction, the paper's first experiment)."""
+    fix_c: keep c = c0 (shape-only reconstruction, the paper's first experiment).
+    damping: "identity" (the printed nu I) or "marquardt" (nu diag(J^T J))."""
+    if damping not in ("identity", "marquardt"):
+        raise ValueError("damping must be 'identity' or 'marquardt'")
+    nu_floor = 1e-12 if damping == "identity" else 1e-6
     t0 = time.perf_counter()
     p = np.array(p0, dtype=np.float64)
     Hmu = model.Hmu(p)
@@ -137,9 +144,12 @@ def reconstruct(model: BornModel, y: np.ndarray, p0: np.ndarray, c0=None, noise_
             e = _stack(r.reshape(-1)[None])[0]
             JTJ = J.T @ J
             g = J.T @ e
-            scale = np.diag(np.diag(JTJ))                          # Marquardt's scaling
+            if damping == "identity":
+                scale = np.eye(JTJ.shape[0])
+            else:
+                scale = np.diag(np.diag(JTJ))                      # Marquardt's scaling
             if nu is None:
-                nu = lm_nu0
+                nu = lm_nu0 * (JTJ.diagonal().max() if damping == "identity" else 1.0)
             accepted = False
             for _try in range(12):                                 # Levenberg-Marquardt damping
                 dp = np.linalg.solve(JTJ + nu * scale, -g)
@@ -149,7 +159,7 @@ def reconstruct(model: BornModel, y: np.ndarray, p0: np.ndarray, c0=None, noise_
                 f_try = np.linalg.norm(r_try)
                 if f_try < f:
                     p, Hmu, r, f = p_try, Hmu_try, r_try, f_try
-                    nu = max(nu / 10.0, 1e-12)
+                    nu = max(nu / 10.0, nu_floor)
                     accepted = True
                     break
                 nu *= 10.0

@@ -68,16 +68,18 @@ def test_lm_jacobian_and_contrasts_match_oracle(hd, case):
                                rtol=1e-9)
 
 
+@pytest.mark.parametrize("damping", ["identity", "marquardt"])
 @pytest.mark.parametrize("n_bumps,snr_db,fix_c", [(3, 30.0, False), (1, 30.0, False), (3, 33.0, True)])
-def test_reconstruction_matches_oracle(hd, case, n_bumps, snr_db, fix_c):
+def test_reconstruction_matches_oracle(hd, case, n_bumps, snr_db, fix_c, damping):
     from paper_1410_0986_amd import reconstruct as rec
     w, P, H, op, t = case
     p_true, dc_true, mu_true, y, nn = _data(w, H, n_bumps, snr_db)
     p0, _ = workloads.pals_perturbed(w, p_true, dc_true)
     c0 = dc_true if fix_c else None
-    r = rec.reconstruct(_model(hd, w, op, t), y, p0, c0=c0, noise_norm=nn, max_outer=60, fix_c=fix_c)
+    r = rec.reconstruct(_model(hd, w, op, t), y, p0, c0=c0, noise_norm=nn, max_outer=60, fix_c=fix_c,
+                        damping=damping)
     c_o, p_o, hist_o = orec.reconstruct(H, w, w.extinction, y, p0, c0=c0, noise_norm=nn, max_outer=60,
-                                        fix_c=fix_c)
+                                        fix_c=fix_c, damping=damping)
     assert r.stopped_by == "discrepancy"
     assert len(r.misfit_history) == len(hist_o)
     np.testing.assert_allclose(r.misfit_history, hist_o, rtol=1e-8)
