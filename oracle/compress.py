@@ -13,9 +13,9 @@ Test infrastructure (see the package docstring); never used by the product.
 * ``recompress``   - the closing recompression of U V^H (Sec. 4, accuracy of the recursion):
                      thin QR of both factors, SVD of R_U R_V^H, truncation at eps.
 
-Readings shared with the library: the rank is doubled when the error estimate fails ("increment
-r"), a leaf of the tree (at most two sources) factors each source's block and then agglomerates
-them, and the initial box is the sources' bounding box.
+Readings shared with the library: "increment r" is r + 1 (the first rank whose error estimate
+passes is kept), a leaf of the tree (at most two sources) factors each source's block and then
+agglomerates them, and the initial box is the sources' bounding box.
 """
 from __future__ import annotations
 
@@ -62,7 +62,7 @@ def randsvd(A, eps, omega1, omega2, p=20):
         err = np.linalg.norm(Z - Q @ (Q.conj().T @ Z), 2)
         hist.append((rr, err, sy[0]))
         if err > eps * sy[0] and rr < min(m, omega1.shape[1] - p):
-            r = min(2 * r, m, omega1.shape[1] - p)
+            r += 1
             continue
         Bm = Q.conj().T @ A
         U1, s, Vh = np.linalg.svd(Bm, full_matrices=False)

@@ -13,8 +13,8 @@ GPU in FP64 through torch.linalg.
   (Alg. geom): split the box across its longest side at the midpoint; a part with more than two
   sources is split again.
 * ``randsvd``          - adaptive randomized SVD of one row block (Alg. randsvd): rank r from 1,
-  doubled until the estimate ||A Omega_2 - Q Q^H A Omega_2|| <= eps * S_r(1, 1), oversampling p,
-  k estimator columns.
+  incremented by one until the estimate ||A Omega_2 - Q Q^H A Omega_2|| <= eps * S_r(1, 1),
+  oversampling p, k estimator columns.
 * ``agglomerate``      - two (or more) children H_i ~ U_i V_i^H combine as
   blockdiag(U_i) [V_1^H; V_2^H]; the stacked right factors are recompressed to tolerance eps
   (a truncated SVD through a thin QR) and the left factor is formed explicitly.
@@ -127,26 +127,53 @@ class LowRank:
         return self.U.shape[1]
 
 
-def randsvd(A: BornBlock, eps: float, omega1: torch.Tensor, omega2: torch.Tensor, p: int = 20) -> LowRank:
+def randsvd(A: BornBlock, eps: float, omega1: torch.Tensor, omega2: torch.Tensor, p: int = 20,
+            chunk: int = 16) -> LowRank:
     """Alg. randsvd on one row block; omega1 [N, >= r+p] and omega2 [N, k] are the test matrices
-    (the leading r+p columns of omega1 are used at rank r)."""
+    (the leading r+p columns of omega1 are used at rank r).  "Increment r" is r + 1: the first
+    rank whose error estimate passes is kept.
+
+    The columns Y = A omega1 are computed in blocks of ``chunk`` Born probe vectors and factored
+    once per block, Y = Q_Y R_Y (thin QR).  The leading r+p columns are then Q_Y[:, :t] R_Y[:t, :r+p]
+    with t = min(rank of Q_Y, r+p), so their left singular vectors are Q_Y[:, :t] times those of
+    the small R block, and the estimate ||Z - Q Q^H Z||_2 (Z = A omega2) splits into parts with
+    orthogonal column spaces: inside span Q_Y[:, :t], the rest of span Q_Y and its complement."""
     m = A.m
     Z = A.matmat(omega2)                                             # A Omega_2, [m, k]
     used = omega2.shape[1]
+    cmax = omega1.shape[1]
+    cap = min(m, cmax - p)
+    Y = None
+    ncols = 0
     r = 1
     hist = []
     while True:
-        cols = min(r + p, omega1.shape[1])
-        Y = A.matmat(omega1[:, :cols])
-        used += cols
-        Ur, Sr, _ = torch.linalg.svd(Y, full_matrices=False)
+        need = min(r + p, cmax)
+        if ncols < need:
+            new = min(cmax, max(need, ncols + chunk))
+            Yn = A.matmat(omega1[:, ncols:new])
+            used += new - ncols
+            Y = Yn if Y is None else torch.cat([Y, Yn], dim=1)
+            ncols = new
+            Qy, Ry = torch.linalg.qr(Y)                             # [m, K], [K, ncols]
+            Zc_d = Qy.conj().T @ Z                                   # [K, k]
+            Zp = Z - Qy @ Zc_d
+            Gp = (Zp.conj().T @ Zp).cpu().numpy()                    # complement of span Q_Y
+            Ry_h = Ry.cpu().numpy()
+            Zc = Zc_d.cpu().numpy()
+        t = min(Ry_h.shape[0], need)
+        Ur, Sr, _ = np.linalg.svd(Ry_h[:t, :need], full_matrices=False)
         rr = min(r, Ur.shape[1])
-        Q = Ur[:, :rr]
-        e = torch.linalg.matrix_norm(Z - Q @ (Q.conj().T @ Z), ord=2).item()
-        hist.append((rr, e, Sr[0].item()))
-        if e > eps * Sr[0].item() and rr < min(m, omega1.shape[1] - p):
-            r = min(2 * r, m, omega1.shape[1] - p)                    # rank doubled
+        Ut = Ur[:, :rr]
+        Ein = Zc[:t] - Ut @ (Ut.conj().T @ Zc[:t])
+        Eout = Zc[t:]
+        G = Ein.conj().T @ Ein + Eout.conj().T @ Eout + Gp
+        e = float(np.sqrt(max(np.linalg.eigvalsh(G)[-1], 0.0)))
+        hist.append((rr, e, float(Sr[0])))
+        if e > eps * Sr[0] and rr < cap:
+            r += 1
             continue
+        Q = Qy[:, :t] @ torch.from_numpy(np.ascontiguousarray(Ut)).to(Qy.device)
         BH = A.rmatmat(Q)                                            # A^H Q = B^H, [N, r]
         used += rr
         U1, S, Vh = torch.linalg.svd(BH.conj().T, full_matrices=False)

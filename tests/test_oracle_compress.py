@@ -47,9 +47,10 @@ def test_randsvd_recovers_exact_low_rank():
     A = (rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r))) @ rng.standard_normal((r, n))
     om1, om2 = workloads.gaussian_test_matrix(n, 80, seed=7), workloads.gaussian_test_matrix(n, 10, seed=8)
     U, V, hist = compress.randsvd(A, 1e-8, om1, om2)
-    assert r <= U.shape[1] <= 2 * r
+    assert U.shape[1] == r                                          # the first rank that passes
     assert np.linalg.norm(A - U @ V.conj().T, 2) <= 1e-10 * np.linalg.norm(A, 2)
-    assert [h[0] for h in hist] == [1, 2, 4, 8][:len(hist)]          # the rank doubles
+    assert [h[0] for h in hist] == list(range(1, r + 1))            # r incremented by one
+    assert all(h[1] > 1e-8 * h[2] for h in hist[:-1])
 
 
 def test_randsvd_meets_tolerance_on_decaying_spectrum():
@@ -63,6 +64,10 @@ def test_randsvd_meets_tolerance_on_decaying_spectrum():
     for eps in (1e-3, 1e-6):
         U, V, _ = compress.randsvd(A, eps, om1, om2)
         assert np.linalg.norm(A - U @ V.conj().T, 2) <= 10 * eps * s[0]
+        # the rank is the epsilon-rank of the block up to the slack of the randomized estimate
+        # (a few singular values, each a factor 2 here), not up to a factor 2 of it
+        eps_rank = int(np.sum(s > eps * s[0]))
+        assert eps_rank - 3 <= U.shape[1] <= eps_rank + 3
 
 
 def test_agglomerate_two_blocks():
