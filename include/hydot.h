@@ -24,11 +24,12 @@
  *   finite-volume form, which keeps the affine dependence on the wavelength).
  *
  * Conventions for every call:
- *   - Device buffers are allocated and owned by the caller; the library never
- *     frees caller memory.  The library owns only the opaque operator.  The one
- *     internal device allocation is the FP64 split-K scratch of hydot_born_apply,
- *     taken and released stream-ordered (hipMallocAsync/hipFreeAsync) on the
- *     caller's stream.
+ *   - Device buffers are allocated and owned by the caller, scratch included (each
+ *     call that needs device scratch takes a caller-owned workspace sized by its
+ *     *_workspace_bytes query); the library never allocates or frees device memory
+ *     in a call on the hot path and never frees caller memory.  The library owns
+ *     only the opaque operator (and the device copies it keeps for
+ *     hydot_set_absorption_perturbation and hydot_apply_preconditioner).
  *   - Complex data are interleaved (re, im) pairs: HYDOT_C128 = 2 x double,
  *     HYDOT_C64 = 2 x float.  All arrays are densely packed, C order.
  *   - Work is enqueued on the caller's stream (NULL = default stream).  Calls
@@ -185,16 +186,47 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
                                 void* workspace, size_t ws_bytes, int32_t* iters, double* rel_res,
                                 hipStream_t stream);
 
-/* Born products (Sec. 2.1 integral equation; rows of H in eq. measurement), never forming J.
- * Scratch (stream-ordered): n_v * n_lambda * splits * (2*pad8(S)) * (2*pad8(D)) doubles, where
- * splits (the number of voxel ranges) follows the born_blocks tuning.
- * Blocks of n_v >= HYDOT_BORN_PAIRS_MIN_NV probe vectors are contracted over source-detector
- * pairs instead: phi_src * phi_det formed once per pair and voxel (FP64 for C128 fields, FP32
- * otherwise) and multiplied with the probe block on MFMA (scratch n_v * n_lambda * splits * S *
- * D * 2 doubles).  Same accumulation (FP64 across 32-voxel stages and splits); half the MFMA
- * work per probe vector.  With CBF16 fields it is the pair product and v that are rounded to
- * BF16 (instead of phi_src v and phi_det); split-BF16 splits the pair product and v.
+/* Read-back of the solver's intermediates (Alg. 1) for tests and diagnosis, from the workspace
+ * of the last hydot_solve_fields call made with the same operator, n_rhs and opts (the workspace
+ * must not have been used since).  Synchronous host copies on `stream`.
+ *   HYDOT_INSPECT_U, HYDOT_INSPECT_C: index = right-hand side of the last Lanczos batch (every
+ *     right-hand side unless PER_SYSTEM); out: host [k][N] double, U and C of Alg. 1 steps 2-4
+ *     (real; in the scaled form of eq. multipleshifted K_hat U = C and C^T C = I, eq. gcr, with
+ *     K_hat = K/h^3 + sigma*' B/h^3 and sigma*' the shift moved into K_hat by the shift flag).
+ *   HYDOT_INSPECT_CHOL: index = system of the last batch (all R*L systems in right-hand-side-major
+ *     order when max_batch is 0; info->rhs and info->lam name it); out: host [k][k] complex
+ *     double, column-major lower factor F of G_j = C_j'^H C_j' = F F^H, C_j' = A_j U with
+ *     A_j = A(lambda_j)/(D_j h^3) (Alg. 1 steps 7-8: C_j = C_j' F^-H, U_j = U F^-H).
+ *   HYDOT_INSPECT_CYCLE: index as CHOL; the system's last restart cycle of m = info->nsteps
+ *     deflated Arnoldi steps (Alg. 1 step 10): out: host complex double, in order
+ *     F' [k][m] (F'[i][l] = (C_j' e_i)^H A_j v_l summed over both Gram-Schmidt passes),
+ *     Hbar [(m+1) x m] column-major (the Hessenberg matrix, Givens rotations undone),
+ *     V [(m+1)][N] (the basis v_0..v_m), so that A_j v_l = C_j' G_j^-1 F'[:, l] + sum_i Hbar[i][l] v_i
+ *     (the modified Arnoldi relation).  Needs 16 (k m + (m+1) m + (m+1) N) bytes.
+ * out = NULL fills only info (then out_bytes is ignored).  EINVAL for an index outside the last
+ * batch or an item the options do not have; ENOMEM if out_bytes is too small. */
+enum { HYDOT_INSPECT_U = 0, HYDOT_INSPECT_C = 1, HYDOT_INSPECT_CHOL = 2, HYDOT_INSPECT_CYCLE = 3 };
+typedef struct {
+  int32_t rhs, lam;   /* the right-hand side and wavelength the item belongs to (lam -1 for U, C) */
+  int32_t k;          /* deflation dimension */
+  int32_t nsteps;     /* CHOL, CYCLE: Arnoldi steps of the system's last restart cycle */
+} hydot_inspect_info;
+hydot_status hydot_solve_inspect(const hydot_operator* op, int32_t n_rhs, const hydot_solve_opts* opts,
+                                 const void* workspace, size_t ws_bytes, int32_t what, int32_t index,
+                                 void* out, size_t out_bytes, hydot_inspect_info* info, hipStream_t stream);
+
+#define HYDOT_BORN_PAIRS_MIN_NV 12
+
+/* Arithmetic of the J v products.  HYDOT_BORN_SPLIT_BF16 (C64 fields only): each FP32 operand
+ * x is split into hi = bf16(x) and lo = bf16(x - hi) and the product accumulates
+ * hi*hi + hi*lo + lo*hi on the BF16 MFMA (relative error of order 1e-5, FP32 field bytes). */
+typedef enum { HYDOT_BORN_NATIVE = 0, HYDOT_BORN_SPLIT_BF16 = 1 } hydot_born_compute;
+
+/* Born products (Sec. 2.1 integral equation with the adjoint field; the rows of H in eq.
+ * measurement), never forming J:
  *   y[c][l][s][d] = -h^3 sum_k phi_src[l][s][k] * v[c][k] * phi_det[l][d][k]   (no conjugation)
+ * the derivative of the detector reading of source s at wavelength l with respect to the
+ * absorption in voxel k, times v_c (Sec. 2.1, Born approximation).
  * phi_src: device, source s at wavelength l at phi_src + (l*lam_stride + s)*N elements;
  * phi_det: likewise with d.  lam_stride >= max(S, D) counts N-vectors between wavelengths
  * (S for a packed source array, n_rhs for slices of the hydot_solve_fields output).
@@ -203,27 +235,37 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
  *             CBF16: v is FP32, y is C64; both operands (phi_src v formed in FP32, and phi_det)
  *                   rounded to BF16 for the BF16 MFMA, FP32 accumulation within a stage, FP64
  *                   beyond.  Relative error of order 1e-2 (a stated-error variant).
- * v: device [n_v][N] real.  y: device [n_v][n_lambda][S][D].  1 <= S, D <= 64, 1 <= n_v <= 64. */
+ * Blocks of n_v >= HYDOT_BORN_PAIRS_MIN_NV probe vectors are contracted over source-detector
+ * pairs instead: phi_src * phi_det formed once per pair and voxel (FP64 for C128 fields, FP32
+ * otherwise) and multiplied with the probe block on MFMA.  Same accumulation; half the MFMA work
+ * per probe vector.  With CBF16 fields it is the pair product and v that are rounded to BF16.
+ * v: device [n_v][N] real.  y: device [n_v][n_lambda][S][D].  1 <= S, D <= 64, 1 <= n_v <= 64.
+ * workspace: device scratch for the FP64 partial sums over voxel ranges, 256-byte aligned, at
+ *   least the bytes hydot_born_workspace_bytes returns for the same operator (its current launch
+ *   shapes), S, D, field_dtype, compute and n_v; smaller is HYDOT_ENOMEM before any launch.
+ *   Its contents on entry do not matter; the call overwrites it.  Calls that overlap in time must
+ *   not share a workspace. */
+hydot_status hydot_born_workspace_bytes(const hydot_operator* op, int32_t S, int32_t D, hydot_dtype field_dtype,
+                                        hydot_born_compute compute, int32_t n_v, size_t* bytes);
 hydot_status hydot_born_apply(const hydot_operator* op, const void* phi_src, int32_t S,
                               const void* phi_det, int32_t D, int64_t lam_stride,
                               hydot_dtype field_dtype, const void* v, int32_t n_v, void* y,
-                              hipStream_t stream);
+                              void* workspace, size_t ws_bytes, hipStream_t stream);
 
-#define HYDOT_BORN_PAIRS_MIN_NV 12
-
-/* Arithmetic of the J v products.  HYDOT_BORN_SPLIT_BF16 (C64 fields only): each FP32 operand
- * x is split into hi = bf16(x) and lo = bf16(x - hi) and the product accumulates
- * hi*hi + hi*lo + lo*hi on the BF16 MFMA (relative error of order 1e-5, FP32 field bytes). */
-typedef enum { HYDOT_BORN_NATIVE = 0, HYDOT_BORN_SPLIT_BF16 = 1 } hydot_born_compute;
 hydot_status hydot_born_apply_ex(const hydot_operator* op, const void* phi_src, int32_t S,
                                  const void* phi_det, int32_t D, int64_t lam_stride,
                                  hydot_dtype field_dtype, hydot_born_compute compute, const void* v,
-                                 int32_t n_v, void* y, hipStream_t stream);
+                                 int32_t n_v, void* y, void* workspace, size_t ws_bytes,
+                                 hipStream_t stream);
 
-/* Adjoint product summed over wavelengths:
+/* Adjoint product summed over wavelengths: the product with the conjugate transpose of H that
+ * the gradient of the misfit needs (Sec. 5, the gradient of eq. minimization uses H^T; the
+ * Jacobian step of Alg. opt):
  *   g[k] = sum_{l,s,d} conj(J_l[s,d,k]) w[l][s][d] = -h^3 sum conj(phi_src[l][s][k] phi_det[l][d][k]) w[l][s][d]
  * w: device [n_lambda][S][D] complex and g: device [N] complex, both C128 for C128 fields and C64
- * for C64 or CBF16 fields (CBF16 fields are widened exactly to FP32 for the FP32 MFMA). */
+ * for C64 or CBF16 fields (CBF16 fields are widened exactly to FP32 for the FP32 MFMA).
+ * Field layout and lam_stride as hydot_born_apply.  Needs no scratch: each block owns a range of
+ * voxels and sums over every wavelength in registers, writing g once. */
 hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_src, int32_t S,
                                       const void* phi_det, int32_t D, int64_t lam_stride,
                                       hydot_dtype field_dtype, const void* w, void* g,
@@ -338,12 +380,17 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
 
 /* Times every J v candidate (born_stage x born_blocks) on the given arguments (the median of
  * 5 calls of hydot_born_apply each; default first, a later candidate must be more than 2%
- * faster) and stores the chosen one in the operator; y receives the product.  Arguments as hydot_born_apply; trials and n_trials as hydot_autotune_solve.
- * Synchronises the stream. */
+ * faster) and stores the chosen one in the operator; y receives the product.  Arguments as
+ * hydot_born_apply; the workspace must hold the largest candidate's scratch,
+ * hydot_autotune_born_workspace_bytes (else HYDOT_ENOMEM before any launch); trials and n_trials
+ * as hydot_autotune_solve.  Synchronises the stream. */
+hydot_status hydot_autotune_born_workspace_bytes(const hydot_operator* op, int32_t S, int32_t D,
+                                                 hydot_dtype field_dtype, int32_t n_v, size_t* bytes);
 hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
                                  int32_t D, int64_t lam_stride, hydot_dtype field_dtype, const void* v,
-                                 int32_t n_v, void* y, hydot_tune_trial* trials, int32_t max_trials,
-                                 int32_t* n_trials, hipStream_t stream);
+                                 int32_t n_v, void* y, void* workspace, size_t ws_bytes,
+                                 hydot_tune_trial* trials, int32_t max_trials, int32_t* n_trials,
+                                 hipStream_t stream);
 
 /* Measurement instrumentation (not part of the method).  While enabled, hydot_solve_fields
  * records HIP events on its stream around every launch of the three Arnoldi step kernels

@@ -16,7 +16,9 @@ from ._binding import (  # noqa: F401
     apply_preconditioner,
     solve_workspace_bytes,
     solve_fields,
+    SolveSession,
     born_apply,
+    born_workspace_bytes,
     born_apply_adjoint,
     pals_shape,
     pals_shape_vjp,

@@ -72,10 +72,19 @@ _precond = _proto("hydot_apply_preconditioner", c_int32, c_void_p, ctypes.c_uint
 _ws_bytes = _proto("hydot_solve_workspace_bytes", c_int32, c_void_p, c_int32, POINTER(_SolveOpts), POINTER(c_size_t))
 _solve = _proto("hydot_solve_fields", c_int32, c_void_p, c_int32, POINTER(c_int64), POINTER(_SolveOpts), c_void_p,
                 c_int32, c_void_p, c_size_t, POINTER(c_int32), POINTER(c_double), c_void_p)
+class _InspectInfo(ctypes.Structure):
+    _fields_ = [("rhs", c_int32), ("lam", c_int32), ("k", c_int32), ("nsteps", c_int32)]
+
+
+_inspect = _proto("hydot_solve_inspect", c_int32, c_void_p, c_int32, POINTER(_SolveOpts), c_void_p, c_size_t, c_int32,
+                  c_int32, c_void_p, c_size_t, POINTER(_InspectInfo), c_void_p)
+INSPECT_U, INSPECT_C, INSPECT_CHOL, INSPECT_CYCLE = 0, 1, 2, 3
 _born = _proto("hydot_born_apply", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32,
-               c_void_p, c_int32, c_void_p, c_void_p)
+               c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p)
 _born_ex = _proto("hydot_born_apply_ex", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32,
-                  c_int32, c_void_p, c_int32, c_void_p, c_void_p)
+                  c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p)
+_born_ws = _proto("hydot_born_workspace_bytes", c_int32, c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32,
+                  POINTER(c_size_t))
 _born_adj_ex = _proto("hydot_born_apply_adjoint_ex", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32,
                       c_int64, c_int32, c_void_p, c_int32, c_void_p, c_void_p)
 _born_adj = _proto("hydot_born_apply_adjoint", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64,
@@ -106,7 +115,10 @@ _set_tuning = _proto("hydot_set_tuning", c_int32, c_void_p, POINTER(_Tuning))
 _tune_solve = _proto("hydot_autotune_solve", c_int32, c_void_p, c_int32, POINTER(c_int64), POINTER(_SolveOpts),
                      c_void_p, c_int32, c_void_p, c_size_t, POINTER(_Trial), c_int32, POINTER(c_int32), c_void_p)
 _tune_born = _proto("hydot_autotune_born", c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32,
-                    c_void_p, c_int32, c_void_p, POINTER(_Trial), c_int32, POINTER(c_int32), c_void_p)
+                    c_void_p, c_int32, c_void_p, c_void_p, c_size_t, POINTER(_Trial), c_int32, POINTER(c_int32),
+                    c_void_p)
+_tune_born_ws = _proto("hydot_autotune_born_workspace_bytes", c_int32, c_void_p, c_int32, c_int32, c_int32, c_int32,
+                       POINTER(c_size_t))
 _TUNE_FIELDS = ("step_presum", "step_order", "step_group", "born_stage", "born_blocks", "step_vx")
 
 
@@ -334,6 +346,65 @@ def solve_fields(op: Operator, rhs_voxels, opts: SolveOptions | None = None, out
     return out, iters.reshape(op.L, R), rel.reshape(op.L, R), st
 
 
+class SolveSession:
+    """A solve whose workspace is kept for reading back the solver's intermediates
+    (hydot_solve_inspect): U, C, per-system Cholesky factors, the last restart cycle."""
+
+    def __init__(self, op: Operator, rhs_voxels, opts: SolveOptions, out_dtype=torch.complex128, device="cuda"):
+        self.op, self.opts = op, opts
+        self.vox = np.ascontiguousarray(rhs_voxels, dtype=np.int64)
+        self.R = int(self.vox.shape[0])
+        self.nbytes = solve_workspace_bytes(op, self.R, opts)
+        self.buf, self.wptr = _ws(self.nbytes, device)
+        self.device = device
+        self.phi = torch.empty(_field_shape(op, self.R, out_dtype), dtype=out_dtype, device=device)
+        o = opts._c()
+        self.iters = np.zeros(op.L * self.R, dtype=np.int32)
+        self.rel = np.zeros(op.L * self.R, dtype=np.float64)
+        st = _solve(op.handle, self.R, self.vox.ctypes.data_as(POINTER(c_int64)), ctypes.byref(o),
+                    c_void_p(self.phi.data_ptr()), _cdtype(self.phi), c_void_p(self.wptr), c_size_t(self.nbytes),
+                    self.iters.ctypes.data_as(POINTER(c_int32)), _dptr(self.rel), _stream(self.phi.device))
+        self.status = _check(st, allow_noconv=True)
+        self.iters = self.iters.reshape(op.L, self.R)
+        self.rel = self.rel.reshape(op.L, self.R)
+
+    def _call(self, what, index, out):
+        o = self.opts._c()
+        info = _InspectInfo()
+        ptr, nb = (None, 0) if out is None else (out.ctypes.data, out.nbytes)
+        _check(_inspect(self.op.handle, self.R, ctypes.byref(o), c_void_p(self.wptr), c_size_t(self.nbytes),
+                        int(what), int(index), c_void_p(ptr), c_size_t(nb), ctypes.byref(info),
+                        _stream(self.phi.device)))
+        return info
+
+    def basis_UC(self, r: int):
+        """(U, C) [k, N] real FP64 of right-hand side r."""
+        info = self._call(INSPECT_U, r, None)
+        U = np.empty((info.k, self.op.N))
+        C = np.empty((info.k, self.op.N))
+        self._call(INSPECT_U, r, U)
+        self._call(INSPECT_C, r, C)
+        return U, C
+
+    def chol(self, i: int):
+        """(rhs, lam, F [k, k] lower) of system i of the last batch."""
+        info = self._call(INSPECT_CHOL, i, None)
+        F = np.empty((info.k, info.k), dtype=np.complex128, order="F")
+        self._call(INSPECT_CHOL, i, F)
+        return info.rhs, info.lam, np.tril(F)
+
+    def cycle(self, i: int):
+        """(rhs, lam, F' [k, m], Hbar [m+1, m], V [m+1, N]) of system i's last restart cycle."""
+        info = self._call(INSPECT_CYCLE, i, None)
+        k, m, N = info.k, info.nsteps, self.op.N
+        buf = np.empty(k * m + (m + 1) * m + (m + 1) * N, dtype=np.complex128)
+        self._call(INSPECT_CYCLE, i, buf)
+        Fp = buf[:k * m].reshape(k, m)
+        Hb = buf[k * m:k * m + (m + 1) * m].reshape(m, m + 1).T
+        V = buf[k * m + (m + 1) * m:].reshape(m + 1, N)
+        return info.rhs, info.lam, Fp, Hb, V
+
+
 def get_tuning(op: Operator) -> dict:
     """Launch shapes the operator uses (hydot_get_tuning), defaults resolved."""
     t = _Tuning()
@@ -392,10 +463,15 @@ def autotune_born(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, v:
     _need_cuda(v, "v")
     v = v.reshape(-1, op.N).to(rdt).contiguous()
     y = torch.empty((v.shape[0], op.L, S, D), dtype=_out_complex(dt), device=phi_src.device)
+    nb = c_size_t()
+    _check(_tune_born_ws(op.handle, S, D, dt, int(v.shape[0]), ctypes.byref(nb)))
+    buf, wptr = _ws(nb.value, phi_src.device)
     arr = (_Trial * 64)()
     n = c_int32(0)
     _check(_tune_born(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt, c_void_p(v.data_ptr()), int(v.shape[0]),
-                      c_void_p(y.data_ptr()), arr, 64, ctypes.byref(n), _stream(phi_src.device)))
+                      c_void_p(y.data_ptr()), c_void_p(wptr), c_size_t(nb.value), arr, 64, ctypes.byref(n),
+                      _stream(phi_src.device)))
+    del buf
     return _trials(arr, n.value)
 
 
@@ -434,10 +510,22 @@ def born_apply(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, v: to
     _need_cuda(v, "v")
     v = v.reshape(-1, op.N).to(rdt).contiguous()
     y = torch.empty((v.shape[0], op.L, S, D), dtype=_out_complex(dt), device=phi_src.device)
-    _check(_born_ex(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt,
-                    BORN_SPLIT_BF16 if split_bf16 else BORN_NATIVE, c_void_p(v.data_ptr()), int(v.shape[0]),
-                    c_void_p(y.data_ptr()), _stream(phi_src.device)))
+    mode = BORN_SPLIT_BF16 if split_bf16 else BORN_NATIVE
+    nbytes = born_workspace_bytes(op, S, D, dt, mode, int(v.shape[0]))
+    buf, wptr = _ws(nbytes, phi_src.device)
+    _check(_born_ex(op.handle, c_void_p(ps), S, c_void_p(pd), D, ls, dt, mode, c_void_p(v.data_ptr()),
+                    int(v.shape[0]), c_void_p(y.data_ptr()), c_void_p(wptr), c_size_t(nbytes),
+                    _stream(phi_src.device)))
+    del buf
     return y
+
+
+def born_workspace_bytes(op: Operator, S: int, D: int, field_dtype: int, compute: int = BORN_NATIVE,
+                         n_v: int = 1) -> int:
+    """Device scratch of one J v call (hydot_born_workspace_bytes) at the operator's launch shapes."""
+    n = c_size_t()
+    _check(_born_ws(op.handle, int(S), int(D), int(field_dtype), int(compute), int(n_v), ctypes.byref(n)))
+    return int(n.value)
 
 
 def born_apply_adjoint(op: Operator, phi_src: torch.Tensor, phi_det: torch.Tensor, w: torch.Tensor) -> torch.Tensor:

@@ -573,75 +573,92 @@ void launch_jv_pairs(dim3 grid, hipStream_t stream, int N, int S, int D, int64_t
                      (const TS*)phd, (const R*)v, n_v, kb, L, ntd, (double*)part);
 }
 
+// Launch plan of one J v call: which kernel, its stage and probe-vector grouping, the split of
+// the voxels into ranges and the bytes of FP64 split partials it writes (the caller's scratch).
+struct JvPlan {
+  bool pairs = false;
+  int Sp = 0, Dp = 0;
+  int kt = 32, tpw = 1, nvb = 1, ngroups = 1;   // real-ified kernel
+  int nts = 1, ntd = 1, nct = 1;                // pair-product kernel
+  int nsplit = 1, kb = 0;
+  size_t part_bytes = 0;
+};
+
+inline bool bf16_compute(int cm) { return cm == CM_BF16 || cm == CM_SPLIT; }
+
+// max_part_bytes > 0 lowers the split count until the partials fit (the allocation-free entry
+// point); 0 keeps the split the tuning asks for.
+static JvPlan jv_plan(const hydot_operator* op, const hydot_tuning& tune, int S, int D, int n_v, int cm,
+                      size_t real_bytes, size_t max_part_bytes = 0) {
+  JvPlan P;
+  const int N = op->gp.N, L = op->L;
+  const hydot_tuning tu = resolved_tuning(tune);
+  P.Sp = pad8(S);
+  P.Dp = pad8(D);
+  if (n_v >= kPairsMinNv) {
+    P.pairs = true;
+    P.kt = 32;
+    P.nts = (S + 7) / 8;
+    P.ntd = (D + 7) / 8;
+    P.nct = (n_v + 15) / 16;   // 1..4 tiles of 16 probe vectors (n_v <= 64)
+    const int per_split = L * P.nts * P.ntd;
+    P.nsplit = std::max(1, (tu.born_blocks + per_split - 1) / per_split);
+  } else {
+    const int T_all = (2 * P.Sp / 16) * (2 * P.Dp / 16);
+    const int tpw_need = (T_all + 3) / 4;
+    P.tpw = tpw_need <= 1 ? 1 : tpw_need <= 2 ? 2 : tpw_need <= 4 ? 4 : tpw_need <= 8 ? 8 : 16;
+    // probe vectors per block: up to 8, with tiles-per-wave x vectors <= 8 (accumulator registers)
+    while (P.nvb < 8 && P.nvb < n_v && P.tpw * P.nvb * 2 <= 8) P.nvb *= 2;
+    // voxels per LDS stage: 32 when the staged rows fit the LDS budget (unless the tuning asks for
+    // 16 on an FP32/FP64 product), else 16; BF16 products always take 32
+    auto lds = [&](int kt) {
+      return (size_t)(2 * P.Sp + 2 * P.Dp) * (kt + 4) * real_bytes + (P.nvb > 1 ? (size_t)P.nvb * kt * real_bytes : 0);
+    };
+    P.kt = bf16_compute(cm) ? 32 : (lds(32) <= kLdsCap && tu.born_stage != 16 ? 32 : 16);
+    P.ngroups = (n_v + P.nvb - 1) / P.nvb;
+    P.nsplit = std::max(1, (tu.born_blocks + L * P.ngroups - 1) / (L * P.ngroups));
+  }
+  // split over voxels so the grid has about born_blocks blocks; ranges are whole stages
+  const int max_split = (N + P.kt - 1) / P.kt;
+  const size_t per_split_bytes = P.pairs ? (size_t)n_v * L * S * D * 2 * sizeof(double)
+                                         : (size_t)n_v * L * (2 * P.Sp) * (2 * P.Dp) * sizeof(double);
+  P.nsplit = std::min(P.nsplit, max_split);
+  if (max_part_bytes > 0) P.nsplit = (int)std::max<long long>(1, std::min<long long>(P.nsplit, (long long)(max_part_bytes / per_split_bytes)));
+  P.kb = (N + P.nsplit - 1) / P.nsplit;
+  P.kb = (P.kb + P.kt - 1) / P.kt * P.kt;
+  P.nsplit = (N + P.kb - 1) / P.kb;
+  P.part_bytes = (size_t)P.nsplit * per_split_bytes;
+  return P;
+}
+
 // J v for blocks of at least kPairsMinNv probe vectors (every product arithmetic).
 template <typename TS, int CM>
-hydot_status born_apply_pairs(const hydot_operator* op, const void* phs, int S, const void* phd, int D, int64_t ls,
-                              const void* v, int n_v, void* y, hipStream_t stream) {
+hydot_status born_apply_pairs(const hydot_operator* op, const JvPlan& P, const void* phs, int S, const void* phd,
+                              int D, int64_t ls, const void* v, int n_v, void* y, void* part, hipStream_t stream) {
   using R = typename Field<TS>::real;
-  constexpr int KT = 32;
   const int N = op->gp.N, L = op->L;
-  const int nts = (S + 7) / 8, ntd = (D + 7) / 8;
-  const int nct = (n_v + 15) / 16;   // 1..4 tiles of 16 probe vectors (n_v <= 64)
-  const hydot_tuning tu = resolved_tuning(op->tune);
-  // split over voxels so the grid has about born_blocks blocks
-  const int per_split = L * nts * ntd;
-  const int max_split = (N + KT - 1) / KT;
-  int nsplit = std::max(1, std::min(max_split, (tu.born_blocks + per_split - 1) / per_split));
-  int kb = (N + nsplit - 1) / nsplit;
-  kb = (kb + KT - 1) / KT * KT;
-  nsplit = (N + kb - 1) / kb;
-  const size_t pbytes = (size_t)n_v * L * nsplit * S * D * 2 * sizeof(double);
-  void* part = nullptr;
-  HYDOT_HIP(hipMallocAsync(&part, pbytes, stream));
-  const dim3 grid(nsplit, L, nts * ntd);
-  if (nct == 1) launch_jv_pairs<TS, CM, 1>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
-  else if (nct == 2) launch_jv_pairs<TS, CM, 2>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
-  else if (nct == 3) launch_jv_pairs<TS, CM, 3>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
-  else launch_jv_pairs<TS, CM, 4>(grid, stream, N, S, D, ls, phs, phd, v, n_v, kb, L, ntd, part);
+  const dim3 grid(P.nsplit, L, P.nts * P.ntd);
+  if (P.nct == 1) launch_jv_pairs<TS, CM, 1>(grid, stream, N, S, D, ls, phs, phd, v, n_v, P.kb, L, P.ntd, part);
+  else if (P.nct == 2) launch_jv_pairs<TS, CM, 2>(grid, stream, N, S, D, ls, phs, phd, v, n_v, P.kb, L, P.ntd, part);
+  else if (P.nct == 3) launch_jv_pairs<TS, CM, 3>(grid, stream, N, S, D, ls, phs, phd, v, n_v, P.kb, L, P.ntd, part);
+  else launch_jv_pairs<TS, CM, 4>(grid, stream, N, S, D, ls, phs, phd, v, n_v, P.kb, L, P.ntd, part);
   const int nout = n_v * L * S * D;
   const double h = op->grid.h_mm;
-  hipLaunchKernelGGL((k_born_pairs_finish<cplx<R>>), dim3((nout + 255) / 256), dim3(256), 0, stream, S * D, nsplit,
-                     nout, (const double*)part, -h * h * h, (cplx<R>*)y);
-  hipError_t e = hipGetLastError();
-  hipError_t e2 = hipFreeAsync(part, stream);
-  if (e != hipSuccess) return hip_check(e, "born_apply launch");
-  if (e2 != hipSuccess) return hip_check(e2, "born_apply free");
+  hipLaunchKernelGGL((k_born_pairs_finish<cplx<R>>), dim3((nout + 255) / 256), dim3(256), 0, stream, S * D,
+                     P.nsplit, nout, (const double*)part, -h * h * h, (cplx<R>*)y);
+  HYDOT_HIP(hipGetLastError());
   return HYDOT_OK;
 }
 
 template <typename TS, int CM>
-hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, const void* phd, int D,
-                             int64_t ls, const void* v, int n_v, void* y, hipStream_t stream) {
-  if (n_v >= kPairsMinNv) return born_apply_pairs<TS, CM>(op, phs, S, phd, D, ls, v, n_v, y, stream);
+hydot_status born_apply_impl(const hydot_operator* op, const JvPlan& P, const void* phs, int S, const void* phd,
+                             int D, int64_t ls, const void* v, int n_v, void* y, void* part, hipStream_t stream) {
+  if (P.pairs) return born_apply_pairs<TS, CM>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
   using R = typename Field<TS>::real;
   const int N = op->gp.N, L = op->L;
-  const int Sp = pad8(S), Dp = pad8(D);
-  const int T_all = (2 * Sp / 16) * (2 * Dp / 16);
-  const int tpw_need = (T_all + 3) / 4;
-  const int tpw = tpw_need <= 1 ? 1 : tpw_need <= 2 ? 2 : tpw_need <= 4 ? 4 : tpw_need <= 8 ? 8 : 16;
-  // probe vectors per block: up to 8, with tiles-per-wave x vectors <= 8 (accumulator registers)
-  int nvb = 1;
-  while (nvb < 8 && nvb < n_v && tpw * nvb * 2 <= 8) nvb *= 2;
-  // voxels per LDS stage: 32 when the staged rows fit the LDS budget (unless the tuning asks for
-  // 16 on an FP32/FP64 product), else 16; BF16 products always take 32
-  const hydot_tuning tu = resolved_tuning(op->tune);
-  auto lds_bytes = [&](int kt) {
-    return (size_t)(2 * Sp + 2 * Dp) * (kt + 4) * sizeof(R) + (nvb > 1 ? (size_t)nvb * kt * sizeof(R) : 0);
-  };
-  const bool bf = CM == CM_BF16 || CM == CM_SPLIT;
-  const int kt = bf ? 32 : (lds_bytes(32) <= kLdsCap && tu.born_stage != 16 ? 32 : 16);
-  const int ngroups = (n_v + nvb - 1) / nvb;
-  // split over voxels so the grid has about born_blocks blocks
-  const int max_split = (N + kt - 1) / kt;
-  int nsplit = std::max(1, std::min(max_split, (tu.born_blocks + L * ngroups - 1) / (L * ngroups)));
-  int kb = (N + nsplit - 1) / nsplit;
-  kb = (kb + kt - 1) / kt * kt;
-  nsplit = (N + kb - 1) / kb;
-  const size_t pbytes = (size_t)n_v * L * nsplit * (2 * Sp) * (2 * Dp) * sizeof(double);
-  void* part = nullptr;
-  HYDOT_HIP(hipMallocAsync(&part, pbytes, stream));
-  const size_t lds = lds_bytes(kt);
-  dim3 grid(nsplit, L, ngroups);
+  const int Sp = P.Sp, Dp = P.Dp, tpw = P.tpw, nvb = P.nvb, kt = P.kt, kb = P.kb;
+  const size_t lds = (size_t)(2 * Sp + 2 * Dp) * (kt + 4) * sizeof(R) + (nvb > 1 ? (size_t)nvb * kt * sizeof(R) : 0);
+  dim3 grid(P.nsplit, L, P.ngroups);
   // staged elements per thread: 2 covers up to 16 rows at 32 voxels per stage, 8 covers 64
   const bool em2 = std::max(Sp, Dp) * kt <= 2 * kBlock;
 #define HYDOT_BA_E(TP, NB, KT, EM)                                                                               \
@@ -667,12 +684,9 @@ hydot_status born_apply_impl(const hydot_operator* op, const void* phs, int S, c
 #undef HYDOT_BA
 #undef HYDOT_BA_E
   const double h = op->grid.h_mm;
-  hipLaunchKernelGGL((k_born_apply_finish<cplx<R>>), dim3(n_v * L), dim3(256), 0, stream, S, D, Sp, Dp, nsplit, L,
+  hipLaunchKernelGGL((k_born_apply_finish<cplx<R>>), dim3(n_v * L), dim3(256), 0, stream, S, D, Sp, Dp, P.nsplit, L,
                      (const double*)part, -h * h * h, (cplx<R>*)y);
-  hipError_t e = hipGetLastError();
-  hipError_t e2 = hipFreeAsync(part, stream);
-  if (e != hipSuccess) return hip_check(e, "born_apply launch");
-  if (e2 != hipSuccess) return hip_check(e2, "born_apply free");
+  HYDOT_HIP(hipGetLastError());
   return HYDOT_OK;
 }
 
@@ -714,37 +728,77 @@ static hydot_status born_check(const hydot_operator* op, const void* phs, int S,
   return HYDOT_OK;
 }
 
+// Validation of a J v call shared by the entry points (no launch).
+static hydot_status jv_check(const hydot_operator* op, const void* phs, int S, const void* phd, int D, int64_t ls,
+                             hydot_dtype dt, hydot_born_compute compute, int n_v) {
+  hydot_status s = born_check(op, phs, S, phd, D, ls, dt);
+  if (s != HYDOT_OK) return s;
+  if (n_v < 1 || n_v > 64) return fail(HYDOT_EINVAL, "born_apply: n_v must be in [1, 64]");
+  if (compute != HYDOT_BORN_NATIVE && compute != HYDOT_BORN_SPLIT_BF16)
+    return fail(HYDOT_EINVAL, "born_apply: unknown compute mode");
+  if (compute == HYDOT_BORN_SPLIT_BF16 && dt != HYDOT_C64)
+    return fail(HYDOT_EUNSUPPORTED, "born_apply: split-BF16 products take C64 fields");
+  return HYDOT_OK;
+}
+
+static int jv_cm(hydot_dtype dt, hydot_born_compute compute) {
+  if (dt == HYDOT_C128) return CM_F64;
+  if (dt == HYDOT_CBF16) return CM_BF16;
+  return compute == HYDOT_BORN_SPLIT_BF16 ? CM_SPLIT : CM_F32;
+}
+
+static size_t jv_real_bytes(hydot_dtype dt) { return dt == HYDOT_C128 ? sizeof(double) : sizeof(float); }
+
+// Launch J v with the scratch `part` (>= P.part_bytes, 256-byte aligned).
+static hydot_status jv_launch(const hydot_operator* op, const JvPlan& P, const void* phs, int S, const void* phd, int D,
+                              int64_t ls, hydot_dtype dt, int cm, const void* v, int n_v, void* y, void* part,
+                              hipStream_t stream) {
+  if (cm == CM_F64) return born_apply_impl<cd, CM_F64>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
+  if (cm == CM_BF16) return born_apply_impl<cbf, CM_BF16>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
+  if (cm == CM_SPLIT) return born_apply_impl<cf, CM_SPLIT>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
+  (void)dt;
+  return born_apply_impl<cf, CM_F32>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
+}
+
 }  // namespace hydot
 
 using namespace hydot;
 
 extern "C" {
 
+hydot_status hydot_born_workspace_bytes(const hydot_operator* op, int32_t S, int32_t D, hydot_dtype field_dtype,
+                                        hydot_born_compute compute, int32_t n_v, size_t* bytes) {
+  if (!bytes) return fail(HYDOT_EINVAL, "born_workspace_bytes: null bytes");
+  if (!op) return fail(HYDOT_EINVAL, "born_workspace_bytes: null operator");
+  if (S < 1 || S > 64 || D < 1 || D > 64) return fail(HYDOT_EINVAL, "born_workspace_bytes: S and D must be in [1, 64]");
+  if (n_v < 1 || n_v > 64) return fail(HYDOT_EINVAL, "born_workspace_bytes: n_v must be in [1, 64]");
+  if (field_dtype != HYDOT_C128 && field_dtype != HYDOT_C64 && field_dtype != HYDOT_CBF16)
+    return fail(HYDOT_EUNSUPPORTED, "born_workspace_bytes: field_dtype must be C128, C64 or CBF16");
+  if (compute != HYDOT_BORN_NATIVE && compute != HYDOT_BORN_SPLIT_BF16)
+    return fail(HYDOT_EINVAL, "born_workspace_bytes: unknown compute mode");
+  *bytes = jv_plan(op, op->tune, S, D, n_v, jv_cm(field_dtype, compute), jv_real_bytes(field_dtype)).part_bytes;
+  return HYDOT_OK;
+}
+
 hydot_status hydot_born_apply_ex(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
                                  int32_t D, int64_t lam_stride, hydot_dtype field_dtype, hydot_born_compute compute,
-                                 const void* v, int32_t n_v, void* y, hipStream_t stream) {
-  hydot_status s = born_check(op, phi_src, S, phi_det, D, lam_stride, field_dtype);
+                                 const void* v, int32_t n_v, void* y, void* workspace, size_t ws_bytes,
+                                 hipStream_t stream) {
+  hydot_status s = jv_check(op, phi_src, S, phi_det, D, lam_stride, field_dtype, compute, n_v);
   if (s != HYDOT_OK) return s;
   if (!v || !y) return fail(HYDOT_EINVAL, "born_apply: null v or y");
-  if (n_v < 1 || n_v > 64) return fail(HYDOT_EINVAL, "born_apply: n_v must be in [1, 64]");
-  if (compute != HYDOT_BORN_NATIVE && compute != HYDOT_BORN_SPLIT_BF16)
-    return fail(HYDOT_EINVAL, "born_apply: unknown compute mode");
-  if (compute == HYDOT_BORN_SPLIT_BF16 && field_dtype != HYDOT_C64)
-    return fail(HYDOT_EUNSUPPORTED, "born_apply: split-BF16 products take C64 fields");
-  if (field_dtype == HYDOT_C128)
-    return born_apply_impl<cd, CM_F64>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
-  if (field_dtype == HYDOT_CBF16)
-    return born_apply_impl<cbf, CM_BF16>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
-  if (compute == HYDOT_BORN_SPLIT_BF16)
-    return born_apply_impl<cf, CM_SPLIT>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
-  return born_apply_impl<cf, CM_F32>(op, phi_src, S, phi_det, D, lam_stride, v, n_v, y, stream);
+  if (!workspace || ((uintptr_t)workspace & 255u)) return fail(HYDOT_EINVAL, "born_apply: workspace must be a 256-byte aligned device pointer");
+  const int cm = jv_cm(field_dtype, compute);
+  const JvPlan P = jv_plan(op, op->tune, S, D, n_v, cm, jv_real_bytes(field_dtype));
+  if (ws_bytes < P.part_bytes) return fail(HYDOT_ENOMEM, "born_apply: workspace smaller than hydot_born_workspace_bytes");
+  return jv_launch(op, P, phi_src, S, phi_det, D, lam_stride, field_dtype, cm, v, n_v, y, workspace, stream);
 }
 
 hydot_status hydot_born_apply(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
                               int32_t D, int64_t lam_stride, hydot_dtype field_dtype, const void* v, int32_t n_v,
-                              void* y, hipStream_t stream) {
+                              void* y, void* workspace, size_t ws_bytes, hipStream_t stream) {
   return hydot_born_apply_ex(op, phi_src, S, phi_det, D, lam_stride, field_dtype, HYDOT_BORN_NATIVE, v, n_v, y,
-                             stream);
+                             workspace, ws_bytes, stream);
 }
 
 hydot_status hydot_born_apply_adjoint_ex(const hydot_operator* op, const void* phi_src, int32_t S,
@@ -767,11 +821,42 @@ hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_
   return hydot_born_apply_adjoint_ex(op, phi_src, S, phi_det, D, lam_stride, field_dtype, w, 1, g, stream);
 }
 
+static const int kTuneStages[2] = {32, 16};
+static const int kTuneBlocks[5] = {4096, 2048, 8192, 1024, 16384};
+
+hydot_status hydot_autotune_born_workspace_bytes(const hydot_operator* op, int32_t S, int32_t D,
+                                                 hydot_dtype field_dtype, int32_t n_v, size_t* bytes) {
+  if (!bytes || !op) return fail(HYDOT_EINVAL, "autotune_born_workspace_bytes: null argument");
+  size_t need = 0;
+  hydot_status s = hydot_born_workspace_bytes(op, S, D, field_dtype, HYDOT_BORN_NATIVE, n_v, &need);   // validates
+  if (s != HYDOT_OK) return s;
+  for (int is = 0; is < 2; ++is)
+    for (int ib = 0; ib < 5; ++ib) {
+      hydot_tuning t = resolved_tuning(op->tune);
+      t.born_stage = kTuneStages[is];
+      t.born_blocks = kTuneBlocks[ib];
+      need = std::max(need, jv_plan(op, t, S, D, n_v, jv_cm(field_dtype, HYDOT_BORN_NATIVE),
+                                    jv_real_bytes(field_dtype)).part_bytes);
+    }
+  *bytes = need;
+  return HYDOT_OK;
+}
+
 hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det, int32_t D,
                                  int64_t lam_stride, hydot_dtype field_dtype, const void* v, int32_t n_v, void* y,
-                                 hydot_tune_trial* trials, int32_t max_trials, int32_t* n_trials, hipStream_t stream) {
+                                 void* workspace, size_t ws_bytes, hydot_tune_trial* trials, int32_t max_trials,
+                                 int32_t* n_trials, hipStream_t stream) {
   if (!op) return fail(HYDOT_EINVAL, "autotune_born: null operator");
   if (max_trials < 0 || (max_trials > 0 && !trials)) return fail(HYDOT_EINVAL, "autotune_born: bad trials buffer");
+  {
+    hydot_status s = jv_check(op, phi_src, S, phi_det, D, lam_stride, field_dtype, HYDOT_BORN_NATIVE, n_v);
+    if (s != HYDOT_OK) return s;
+    size_t need = 0;
+    s = hydot_autotune_born_workspace_bytes(op, S, D, field_dtype, n_v, &need);
+    if (s != HYDOT_OK) return s;
+    if (!workspace || ((uintptr_t)workspace & 255u)) return fail(HYDOT_EINVAL, "autotune_born: workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(HYDOT_ENOMEM, "autotune_born: workspace smaller than hydot_autotune_born_workspace_bytes");
+  }
   const hydot_tuning keep = op->tune;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HYDOT_HIP(hipEventCreate(&e0));
@@ -780,8 +865,6 @@ hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_
     return fail(HYDOT_EDEVICE, "autotune_born: event create");
   }
   // default first; later candidates must be more than 2% faster to replace the best
-  const int stages[2] = {32, 16};
-  const int blocks[5] = {4096, 2048, 8192, 1024, 16384};
   int count = 0;
   double best = 1e300;
   hydot_tuning best_t = resolved_tuning(keep);
@@ -789,14 +872,15 @@ hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_
   for (int is = 0; is < 2 && err == HYDOT_OK; ++is)
     for (int ib = 0; ib < 5 && err == HYDOT_OK; ++ib) {
       hydot_tuning t = resolved_tuning(keep);
-      t.born_stage = stages[is];
-      t.born_blocks = blocks[ib];
+      t.born_stage = kTuneStages[is];
+      t.born_blocks = kTuneBlocks[ib];
       op->tune = t;
       float ms[5];
       for (int rep = 0; rep < 6 && err == HYDOT_OK; ++rep) {   // first call warms up
         if (hipEventRecord(e0, stream) != hipSuccess) err = fail(HYDOT_EDEVICE, "autotune_born: event record");
         if (err == HYDOT_OK)
-          err = hydot_born_apply(op, phi_src, S, phi_det, D, lam_stride, field_dtype, v, n_v, y, stream);
+          err = hydot_born_apply(op, phi_src, S, phi_det, D, lam_stride, field_dtype, v, n_v, y, workspace, ws_bytes,
+                                 stream);
         if (err == HYDOT_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
           err = fail(HYDOT_EDEVICE, "autotune_born: event wait");
         if (err == HYDOT_OK && rep > 0 && hipEventElapsedTime(&ms[rep - 1], e0, e1) != hipSuccess)

@@ -143,13 +143,33 @@ def test_born_validates_before_launch(hd):
     f = lib.hydot_born_apply
     f.restype = ctypes.c_int32
     f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
-                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                  ctypes.c_void_p]
     fake = ctypes.c_void_p(0x7F0000000000)
-    assert f(op.handle, fake, 0, fake, 4, 8, 0, fake, 1, fake, None) == hd.EINVAL        # S = 0
-    assert f(op.handle, fake, 65, fake, 4, 80, 0, fake, 1, fake, None) == hd.EINVAL      # S > 64
-    assert f(op.handle, fake, 4, fake, 4, 3, 0, fake, 1, fake, None) == hd.EINVAL        # lam_stride < S
-    assert f(op.handle, fake, 4, fake, 4, 8, 0, fake, 0, fake, None) == hd.EINVAL        # n_v = 0
-    assert f(op.handle, fake, 4, fake, 4, 8, 4, fake, 1, fake, None) == hd.EUNSUPPORTED  # real dtype
+    big = 1 << 40
+    assert f(op.handle, fake, 0, fake, 4, 8, 0, fake, 1, fake, fake, big, None) == hd.EINVAL        # S = 0
+    assert f(op.handle, fake, 65, fake, 4, 80, 0, fake, 1, fake, fake, big, None) == hd.EINVAL      # S > 64
+    assert f(op.handle, fake, 4, fake, 4, 3, 0, fake, 1, fake, fake, big, None) == hd.EINVAL        # lam_stride < S
+    assert f(op.handle, fake, 4, fake, 4, 8, 0, fake, 0, fake, fake, big, None) == hd.EINVAL        # n_v = 0
+    assert f(op.handle, fake, 4, fake, 4, 8, 4, fake, 1, fake, fake, big, None) == hd.EUNSUPPORTED  # real dtype
+    # caller-owned scratch: the query, then a missing, misaligned or short workspace
+    for dt in (hd.C128, hd.C64, hd.CBF16):
+        for nv in (1, 3, 12, 42):
+            need = hd._binding.born_workspace_bytes(op, 4, 4, dt, hd.BORN_NATIVE, nv)
+            assert need > 0 and need % 8 == 0
+            assert f(op.handle, fake, 4, fake, 4, 8, dt, fake, nv, fake, fake, need - 8, None) == hd.ENOMEM
+            assert "workspace" in hd._binding._last_error().decode()
+    assert f(op.handle, fake, 4, fake, 4, 8, 1, fake, 1, fake, None, big, None) == hd.EINVAL        # no workspace
+    assert f(op.handle, fake, 4, fake, 4, 8, 1, fake, 1, fake, ctypes.c_void_p(0x7F0000000008), big,
+             None) == hd.EINVAL                                                                     # misaligned
+    # the split partials grow with the requested grid size, and the plan is the same for the query
+    # and the call: a workspace of exactly the queried size passes validation
+    need1 = hd._binding.born_workspace_bytes(op, 4, 4, hd.C64, hd.BORN_NATIVE, 1)
+    hd.set_tuning(op, born_blocks=256)
+    need2 = hd._binding.born_workspace_bytes(op, 4, 4, hd.C64, hd.BORN_NATIVE, 1)
+    assert need2 < need1
+    with pytest.raises(hd.HydotError):
+        hd._binding.born_workspace_bytes(op, 4, 4, hd.C64, hd.BORN_SPLIT_BF16 + 5, 1)
     g = lib.hydot_born_apply_adjoint
     g.restype = ctypes.c_int32
     g.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
@@ -248,3 +268,30 @@ def test_solve_rejects_basis_beyond_buffer_range(hd):
     # the FP64 path has no such limit
     assert hd.solve_workspace_bytes(op, 2, hd.SolveOptions(restart_m=8, recycle_k=4, lanczos_n=8,
                                                            precision=hd.PREC_FP64)) > 0
+
+
+def test_solve_inspect_validates(hd):
+    """hydot_solve_inspect checks the item, the index and the buffers before any copy."""
+    from paper_1410_0986_amd import _binding as B
+    w = workloads.config("tiny")
+    op = _op(hd, w)
+    opts = hd.SolveOptions(rel_tol=1e-8, restart_m=18, recycle_k=5, lanczos_n=24)
+    need = hd.solve_workspace_bytes(op, 8, opts)
+    o = opts._c()
+    info = B._InspectInfo()
+    fake = ctypes.c_void_p(0x7F0000000000)
+    f = B._inspect
+    assert f(op.handle, 8, ctypes.byref(o), fake, need - 256, 0, 0, None, 0, ctypes.byref(info), None) == hd.ENOMEM
+    assert f(op.handle, 8, ctypes.byref(o), fake, need, 7, 0, None, 0, ctypes.byref(info), None) == hd.EINVAL
+    assert f(op.handle, 8, ctypes.byref(o), fake, need, B.INSPECT_U, 8, None, 0, ctypes.byref(info), None) == hd.EINVAL
+    assert f(op.handle, 8, ctypes.byref(o), fake, need, B.INSPECT_U, 3, None, 0, ctypes.byref(info), None) == hd.OK
+    assert info.k == 5 and info.rhs == 3
+    out = np.empty(10)
+    assert f(op.handle, 8, ctypes.byref(o), fake, need, B.INSPECT_C, 3, ctypes.c_void_p(out.ctypes.data), out.nbytes,
+             ctypes.byref(info), None) == hd.ENOMEM
+    assert f(op.handle, 8, ctypes.byref(o), ctypes.c_void_p(0x7F0000000008), need, B.INSPECT_U, 3, None, 0,
+             ctypes.byref(info), None) == hd.EINVAL
+    nr = hd.SolveOptions(rel_tol=1e-8, restart_m=18, recycle_k=5, lanczos_n=24, flags=hd.FLAG_NO_RECYCLE)
+    o2 = nr._c()
+    need2 = hd.solve_workspace_bytes(op, 8, nr)
+    assert f(op.handle, 8, ctypes.byref(o2), fake, need2, B.INSPECT_U, 0, None, 0, ctypes.byref(info), None) == hd.EINVAL
