@@ -921,6 +921,99 @@ int32_t hydot_profile_read(hydot_kernel_profile* out, int32_t max_records) {
   return m;
 }
 
+hydot_status hydot_solve_inspect(const hydot_operator* op, int32_t n_rhs, const hydot_solve_opts* opts,
+                                 const void* workspace, size_t ws_bytes, int32_t what, int32_t index, void* out,
+                                 size_t out_bytes, hydot_inspect_info* info, hipStream_t stream) {
+  Plan p;
+  hydot_status s = make_plan(op, n_rhs, opts, p);
+  if (s != HYDOT_OK) return s;
+  if (!workspace || ((uintptr_t)workspace & 255u)) return fail(HYDOT_EINVAL, "inspect: workspace must be 256-byte aligned");
+  if (ws_bytes < p.total) return fail(HYDOT_ENOMEM, "inspect: workspace smaller than hydot_solve_workspace_bytes");
+  if (!info) return fail(HYDOT_EINVAL, "inspect: null info");
+  const char* ws = (const char*)workspace;
+  const size_t N = (size_t)p.N;
+  const int total = p.R * p.L;
+  const int last_nb = total - p.nb * ((total - 1) / p.nb);   // systems of the last batch
+  std::memset(info, 0, sizeof(*info));
+  info->k = p.k;
+  if (what == HYDOT_INSPECT_U || what == HYDOT_INSPECT_C) {
+    if (!p.recycle || p.k == 0) return fail(HYDOT_EINVAL, "inspect: no deflation space (recycle_k = 0 or NO_RECYCLE)");
+    if (index < 0 || index >= p.rl) return fail(HYDOT_EINVAL, "inspect: right-hand side index outside the last Lanczos batch");
+    const size_t need = (size_t)p.k * N * sizeof(double);
+    info->rhs = p.per_system ? p.R - 1 : index;
+    info->lam = -1;
+    if (!out) return HYDOT_OK;
+    if (out_bytes < need) return fail(HYDOT_ENOMEM, "inspect: output buffer too small");
+    const size_t off = (what == HYDOT_INSPECT_U ? p.o_U64 : p.o_C64) + (size_t)index * p.k * N * sizeof(double);
+    HYDOT_HIP(hipMemcpyAsync(out, ws + off, need, hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipStreamSynchronize(stream));
+    return HYDOT_OK;
+  }
+  if (what != HYDOT_INSPECT_CHOL && what != HYDOT_INSPECT_CYCLE) return fail(HYDOT_EINVAL, "inspect: unknown item");
+  if (index < 0 || index >= last_nb) return fail(HYDOT_EINVAL, "inspect: system index outside the last batch");
+  SysParam prm;
+  SysState st;
+  HYDOT_HIP(hipMemcpyAsync(&prm, ws + p.o_prm + (size_t)index * sizeof(SysParam), sizeof prm, hipMemcpyDeviceToHost, stream));
+  HYDOT_HIP(hipMemcpyAsync(&st, ws + p.o_st + (size_t)index * sizeof(SysState), sizeof st, hipMemcpyDeviceToHost, stream));
+  std::vector<cd> sm((size_t)p.sl.total);
+  HYDOT_HIP(hipMemcpyAsync(sm.data(), ws + p.o_small + (size_t)index * p.sl.total * sizeof(cd), sm.size() * sizeof(cd),
+                           hipMemcpyDeviceToHost, stream));
+  HYDOT_HIP(hipStreamSynchronize(stream));
+  info->rhs = p.per_system ? p.R - 1 : prm.rhs;
+  info->lam = prm.lam;
+  info->nsteps = st.nsteps;
+  const int k = p.k, m = st.nsteps, ldh = p.mkmax + 1;
+  if (what == HYDOT_INSPECT_CHOL) {
+    if (k == 0) return fail(HYDOT_EINVAL, "inspect: no deflation space (recycle_k = 0 or NO_RECYCLE)");
+    if (!out) return HYDOT_OK;
+    if (out_bytes < (size_t)k * k * sizeof(cd)) return fail(HYDOT_ENOMEM, "inspect: output buffer too small");
+    std::memcpy(out, sm.data() + p.sl.Lc, (size_t)k * k * sizeof(cd));
+    return HYDOT_OK;
+  }
+  // last restart cycle: F' [k][m], the Hessenberg matrix with the Givens rotations undone
+  // [(m+1) x m, column-major], the scaled basis v_0..v_m [(m+1)][N]
+  const size_t need = ((size_t)k * m + (size_t)(m + 1) * m + (size_t)(m + 1) * N) * sizeof(cd);
+  if (!out) return HYDOT_OK;
+  if (out_bytes < need) return fail(HYDOT_ENOMEM, "inspect: output buffer too small");
+  cd* o = (cd*)out;
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < k; ++i) o[(size_t)i * m + j] = sm[p.sl.Fp + i + k * j];
+  cd* hb = o + (size_t)k * m;
+  const double* cs = (const double*)(sm.data() + p.sl.cs);   // cosines in the .re slots
+  const cd* sn = sm.data() + p.sl.sn;
+  for (int j = 0; j < m; ++j) {
+    std::vector<cd> col(m + 1, cd{0.0, 0.0});
+    for (int i = 0; i <= j + 1; ++i) col[i] = sm[p.sl.H + i + ldh * j];
+    // the rotations applied to column j were 0..j in order; undo them in reverse with the
+    // adjoint of [[c, s], [-conj(s), c]]
+    for (int i = j; i >= 0; --i) {
+      const double c = cs[2 * i];
+      const cd si = sn[i];
+      const cd a = col[i], b = col[i + 1];
+      col[i] = c * a - si * b;
+      col[i + 1] = conj(si) * a + c * b;
+    }
+    for (int i = 0; i <= m; ++i) hb[i + (size_t)(m + 1) * j] = col[i];
+  }
+  cd* vb = hb + (size_t)(m + 1) * m;
+  const char* V = ws + p.o_V + (size_t)index * (p.mk + 1) * N * p.esz;
+  const cd* vs = sm.data() + p.sl.vs;
+  if (p.prec == HYDOT_PREC_FP64) {
+    HYDOT_HIP(hipMemcpyAsync(vb, V, (size_t)(m + 1) * N * sizeof(cd), hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipStreamSynchronize(stream));
+  } else {
+    std::vector<cf> tmp((size_t)(m + 1) * N);
+    HYDOT_HIP(hipMemcpyAsync(tmp.data(), V, tmp.size() * sizeof(cf), hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipStreamSynchronize(stream));
+    for (size_t e = 0; e < tmp.size(); ++e) vb[e] = cd{(double)tmp[e].re, (double)tmp[e].im};
+  }
+  for (int l = 0; l <= m; ++l) {
+    const double sc = vs[l].re;
+    for (size_t n = 0; n < N; ++n) vb[(size_t)l * N + n] = sc * vb[(size_t)l * N + n];
+  }
+  return HYDOT_OK;
+}
+
 hydot_status hydot_solve_workspace_bytes(const hydot_operator* op, int32_t n_rhs, const hydot_solve_opts* opts,
                                          size_t* bytes) {
   if (!bytes) return fail(HYDOT_EINVAL, "solve_workspace_bytes: null output");
