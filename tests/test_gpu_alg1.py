@@ -1,0 +1,184 @@
+"""Algorithm 1's intermediates on the GPU path, read back from the solver's workspace
+(hydot_solve_inspect) and checked against identities the paper fixes, with the operator built
+by the oracle (its own sparse K, B and A(lambda)), not by the library:
+
+* the recycle space of Alg. 1 steps 2-4 (Sec. 3.1, eq. gcr): K_hat U = C and C^T C = I, with
+  K_hat = K/h^3 + sigma*' B/h^3 in the scaled form of eq. multipleshifted;
+* the per-wavelength basis of Alg. 1 steps 7-8: the Cholesky factor F of G_j = C_j'^H C_j' with
+  C_j' = A_j U, so that C_j = C_j' F^-H has C_j^H C_j = I and A_j U_j = C_j (U_j = U F^-H);
+* the deflated Arnoldi of Alg. 1 step 10, in the last restart cycle of each system: the modified
+  Arnoldi relation A_j V_m = C_j (C_j^H A_j V_m) + V_{m+1} Hbar_m, with V orthonormal and
+  orthogonal to C_j;
+* the shift-invariant special case (Sec. 3.1): with A_R -> infinity the Robin term vanishes,
+  every A(lambda_j) is a shift of one K_hat and the multi-shift initial guess of step 1 alone
+  meets the tolerance once the Krylov space of K_hat is large enough, so no system takes an
+  Arnoldi step.
+
+The end-to-end field tests cannot see a wrong U, C or Cholesky factor: the restarts and the FP64
+refinement converge anyway, only more slowly.  These tests can.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import fields as ofields
+from oracle import model
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import paper_1410_0986_amd as hd
+    return hd
+
+
+def _fro(a):
+    return float(np.linalg.norm(a))
+
+
+def _case(hd, w, **kw):
+    op = hd.Operator.from_workload(w)
+    base = dict(rel_tol=1e-11, restart_m=22, recycle_k=6, lanczos_n=24, precision=hd.PREC_FP64,
+                flags=hd.FLAG_MEAN_SHIFT, max_iter=5000)
+    base.update(kw)
+    opts = hd.SolveOptions(**base)
+    sess = hd.SolveSession(op, w.rhs_voxels, opts, out_dtype=torch.complex128, device=DEV)
+    torch.cuda.synchronize()
+    return op, opts, sess
+
+
+@pytest.fixture(scope="module", params=["tiny", "ragged"])
+def solved(hd, request):
+    if request.param == "tiny":
+        w = workloads.config("tiny")
+    else:   # axes that split into no whole chunk or wave, two wavelengths fewer
+        w = workloads.config("tiny", nx=13, ny=11, nz=7, n_lambda=6, n_src=2, n_det=4)
+    op, opts, sess = _case(hd, w)
+    assert sess.status == hd.OK and sess.rel.max() <= 1e-11
+    return w, op, opts, sess
+
+
+def _scaled_ops(w):
+    """A_j = A(lambda_j)/(D_j h^3) for every wavelength, and K_hat with the mean Robin shift."""
+    h3 = w.h ** 3
+    D, _, _ = model.optics(w)
+    _, sigp = model.shifts(w)
+    K = model.assemble_K(w)
+    B = model.assemble_B(w)
+    Khat = (K + sigp.mean() * B) / h3
+    A = [model.operator(w, l) / (D[l] * h3) for l in range(w.L)]
+    return Khat, A
+
+
+def test_recycle_space_satisfies_gcr_identities(hd, solved):
+    w, op, opts, sess = solved
+    Khat, _ = _scaled_ops(w)
+    for r in range(w.S + w.D):
+        U, C = sess.basis_UC(r)
+        assert U.shape == (opts.recycle_k, w.N)
+        assert _fro(Khat @ U.T - C.T) <= 1e-12 * _fro(C)
+        assert _fro(C @ C.T - np.eye(C.shape[0])) <= 1e-12
+
+
+def test_per_wavelength_cholesky_basis(hd, solved):
+    w, op, opts, sess = solved
+    Khat, A = _scaled_ops(w)
+    R = w.S + w.D
+    seen = set()
+    for i in range(R * w.L):
+        r, lam, F = sess.chol(i)
+        seen.add((r, lam))
+        U, _ = sess.basis_UC(r)
+        Cp = A[lam] @ U.T                                    # C_j' = A_j U, N x k
+        G = Cp.conj().T @ Cp
+        assert _fro(F @ F.conj().T - G) <= 1e-12 * _fro(G), (r, lam)
+        Finv_h = np.linalg.inv(F.conj().T)
+        Cj = Cp @ Finv_h
+        Uj = U.T @ Finv_h
+        assert _fro(Cj.conj().T @ Cj - np.eye(F.shape[0])) <= 1e-10, (r, lam)
+        assert _fro(A[lam] @ Uj - Cj) <= 1e-10 * _fro(Cj), (r, lam)
+    assert seen == {(r, l) for r in range(R) for l in range(w.L)}
+
+
+def test_modified_arnoldi_relation_of_last_cycle(hd, solved):
+    w, op, opts, sess = solved
+    _, A = _scaled_ops(w)
+    R = w.S + w.D
+    checked = 0
+    for i in range(0, R * w.L, 3):
+        r, lam, Fp, Hb, V = sess.cycle(i)
+        m = Hb.shape[1]
+        if m == 0:
+            continue
+        U, _ = sess.basis_UC(r)
+        Cp = A[lam] @ U.T
+        G = Cp.conj().T @ Cp
+        AV = A[lam] @ V[:m].T                                # N x m
+        rel = AV - Cp @ np.linalg.solve(G, Fp) - V.T @ Hb
+        assert _fro(rel) <= 1e-12 * _fro(AV), (r, lam, _fro(rel) / _fro(AV))
+        assert _fro(V.conj() @ V.T - np.eye(m + 1)) <= 1e-12, (r, lam)      # CGS2 on the FP64 path
+        assert _fro(Cp.conj().T @ V.T) <= 1e-12 * _fro(Cp), (r, lam)       # V orthogonal to C_j
+        assert np.allclose(np.tril(Hb, -2), 0.0)                             # upper Hessenberg
+        checked += 1
+    assert checked >= 4
+
+
+def test_shift_invariant_case_needs_only_the_initial_guess(hd):
+    """A_R -> infinity: no Robin term, A(lambda_j) = D_j (K_hat + sigma_j I) h^3; unrestarted GMRES
+    on this grid needs at most 78 iterations for 1e-8 at every wavelength and right-hand side
+    (oracle), so 96 steps of the shift-invariant Lanczos process give an initial guess that meets
+    the tolerance for every system, which then takes no Arnoldi step."""
+    w = workloads.config("tiny", A_R=1e12)
+    op, opts, sess = _case(hd, w, rel_tol=1e-8, lanczos_n=96, recycle_k=10, restart_m=40)
+    assert sess.status == hd.OK
+    assert sess.rel.max() <= 1e-8
+    assert sess.iters.max() == 0, sess.iters
+    ref = ofields.solve_banded(w)
+    got = sess.phi.cpu().numpy()
+    err = np.linalg.norm(got - ref, axis=2) / np.linalg.norm(ref, axis=2)
+    # A(lambda) is normal (real symmetric plus a complex multiple of I): the forward error is at
+    # most kappa_2 = max|mu + sigma| / min|mu + sigma| (mu the eigenvalues of K_hat) times rel-res
+    h3 = w.h ** 3
+    mu = np.linalg.eigvalsh((model.assemble_K(w) + model.shifts(w)[1].mean() * model.assemble_B(w)).toarray() / h3)
+    sig = model.shifts(w)[0]
+    kappa = np.array([np.abs(mu + s_).max() / np.abs(mu + s_).min() for s_ in sig])
+    assert np.all(err <= 1.01 * kappa[:, None] * sess.rel + 1e-13)
+    # with the Robin term of A_R = 2.5 the same Lanczos space is not enough
+    w2 = workloads.config("tiny")
+    _, _, sess2 = _case(hd, w2, rel_tol=1e-8, lanczos_n=96, recycle_k=10, restart_m=40)
+    assert sess2.iters.max() > 0
+
+
+def test_mixed_path_intermediates(hd):
+    """The complex FP32 inner solves of the mixed path: the same identities at FP32 level (the
+    Lanczos basis of step 1 is real FP32; the Arnoldi basis keeps its second Gram-Schmidt pass
+    only where the first leaves a projection above 1e-4 of the vector)."""
+    w = workloads.config("tiny", nx=13, ny=11, nz=7, n_lambda=6, n_src=2, n_det=4)
+    op, opts, sess = _case(hd, w, rel_tol=1e-8, precision=hd.PREC_MIXED, inner_tol=1e-5,
+                           restart_m=18, recycle_k=5, lanczos_n=32, flags=hd.FLAG_MEAN_SHIFT)
+    assert sess.status == hd.OK and sess.rel.max() <= 1e-8
+    Khat, A = _scaled_ops(w)
+    R = w.S + w.D
+    for r in range(R):
+        U, C = sess.basis_UC(r)
+        assert _fro(Khat @ U.T - C.T) <= 2e-5 * _fro(C)
+        assert _fro(C @ C.T - np.eye(C.shape[0])) <= 2e-5
+    checked = 0
+    for i in range(R * w.L):
+        r, lam, Fp, Hb, V = sess.cycle(i)
+        m = Hb.shape[1]
+        if m == 0:
+            continue
+        U, _ = sess.basis_UC(r)
+        Cp = A[lam] @ U.T
+        AV = A[lam] @ V[:m].T
+        rel = AV - Cp @ np.linalg.solve(Cp.conj().T @ Cp, Fp) - V.T @ Hb
+        assert _fro(rel) <= 1e-5 * _fro(AV), (r, lam, _fro(rel) / _fro(AV))
+        assert _fro(V.conj() @ V.T - np.eye(m + 1)) <= 1e-3, (r, lam)
+        checked += 1
+    assert checked >= 4
