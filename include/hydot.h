@@ -201,8 +201,10 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
  *     deflated Arnoldi steps (Alg. 1 step 10): out: host complex double, in order
  *     F' [k][m] (F'[i][l] = (C_j' e_i)^H A_j v_l summed over both Gram-Schmidt passes),
  *     Hbar [(m+1) x m] column-major (the Hessenberg matrix, Givens rotations undone),
- *     V [(m+1)][N] (the basis v_0..v_m), so that A_j v_l = C_j' G_j^-1 F'[:, l] + sum_i Hbar[i][l] v_i
- *     (the modified Arnoldi relation).  Needs 16 (k m + (m+1) m + (m+1) N) bytes.
+ *     V [m][N] (the basis v_0..v_{m-1}), so that A_j v_l = C_j' G_j^-1 F'[:, l] + sum_i Hbar[i][l] v_i
+ *     (the modified Arnoldi relation) with v_m = r / Hbar[m][m-1] for the residual r of the last
+ *     column: v_m itself is never formed (the cycle's update uses only v_0..v_{m-1}), so r has
+ *     norm |Hbar[m][m-1]| and is orthogonal to C_j and V.  Needs 16 (k m + (m+1) m + m N) bytes.
  * out = NULL fills only info (then out_bytes is ignored).  EINVAL for an index outside the last
  * batch or an item the options do not have; ENOMEM if out_bytes is too small. */
 enum { HYDOT_INSPECT_U = 0, HYDOT_INSPECT_C = 1, HYDOT_INSPECT_CHOL = 2, HYDOT_INSPECT_CYCLE = 3 };

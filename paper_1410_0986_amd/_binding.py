@@ -394,14 +394,15 @@ class SolveSession:
         return info.rhs, info.lam, np.tril(F)
 
     def cycle(self, i: int):
-        """(rhs, lam, F' [k, m], Hbar [m+1, m], V [m+1, N]) of system i's last restart cycle."""
+        """(rhs, lam, F' [k, m], Hbar [m+1, m], V [m, N]) of system i's last restart cycle
+        (v_m is not formed by the solver; see hydot_solve_inspect)."""
         info = self._call(INSPECT_CYCLE, i, None)
         k, m, N = info.k, info.nsteps, self.op.N
-        buf = np.empty(k * m + (m + 1) * m + (m + 1) * N, dtype=np.complex128)
+        buf = np.empty(k * m + (m + 1) * m + m * N, dtype=np.complex128)
         self._call(INSPECT_CYCLE, i, buf)
         Fp = buf[:k * m].reshape(k, m)
         Hb = buf[k * m:k * m + (m + 1) * m].reshape(m, m + 1).T
-        V = buf[k * m + (m + 1) * m:].reshape(m + 1, N)
+        V = buf[k * m + (m + 1) * m:].reshape(m, N)
         return info.rhs, info.lam, Fp, Hb, V
 
 

@@ -971,8 +971,9 @@ hydot_status hydot_solve_inspect(const hydot_operator* op, int32_t n_rhs, const 
     return HYDOT_OK;
   }
   // last restart cycle: F' [k][m], the Hessenberg matrix with the Givens rotations undone
-  // [(m+1) x m, column-major], the scaled basis v_0..v_m [(m+1)][N]
-  const size_t need = ((size_t)k * m + (size_t)(m + 1) * m + (size_t)(m + 1) * N) * sizeof(cd);
+  // [(m+1) x m, column-major], the scaled basis v_0..v_{m-1} [m][N].  v_m is never formed: the
+  // cycle's update needs only the first m vectors, so the last step skips its closing pass.
+  const size_t need = ((size_t)k * m + (size_t)(m + 1) * m + (size_t)m * N) * sizeof(cd);
   if (!out) return HYDOT_OK;
   if (out_bytes < need) return fail(HYDOT_ENOMEM, "inspect: output buffer too small");
   cd* o = (cd*)out;
@@ -999,15 +1000,15 @@ hydot_status hydot_solve_inspect(const hydot_operator* op, int32_t n_rhs, const 
   const char* V = ws + p.o_V + (size_t)index * (p.mk + 1) * N * p.esz;
   const cd* vs = sm.data() + p.sl.vs;
   if (p.prec == HYDOT_PREC_FP64) {
-    HYDOT_HIP(hipMemcpyAsync(vb, V, (size_t)(m + 1) * N * sizeof(cd), hipMemcpyDeviceToHost, stream));
+    HYDOT_HIP(hipMemcpyAsync(vb, V, (size_t)m * N * sizeof(cd), hipMemcpyDeviceToHost, stream));
     HYDOT_HIP(hipStreamSynchronize(stream));
   } else {
-    std::vector<cf> tmp((size_t)(m + 1) * N);
+    std::vector<cf> tmp((size_t)m * N);
     HYDOT_HIP(hipMemcpyAsync(tmp.data(), V, tmp.size() * sizeof(cf), hipMemcpyDeviceToHost, stream));
     HYDOT_HIP(hipStreamSynchronize(stream));
     for (size_t e = 0; e < tmp.size(); ++e) vb[e] = cd{(double)tmp[e].re, (double)tmp[e].im};
   }
-  for (int l = 0; l <= m; ++l) {
+  for (int l = 0; l < m; ++l) {
     const double sc = vs[l].re;
     for (size_t n = 0; n < N; ++n) vb[(size_t)l * N + n] = sc * vb[(size_t)l * N + n];
   }

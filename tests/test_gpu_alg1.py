@@ -118,14 +118,29 @@ def test_modified_arnoldi_relation_of_last_cycle(hd, solved):
         U, _ = sess.basis_UC(r)
         Cp = A[lam] @ U.T
         G = Cp.conj().T @ Cp
-        AV = A[lam] @ V[:m].T                                # N x m
-        rel = AV - Cp @ np.linalg.solve(G, Fp) - V.T @ Hb
-        assert _fro(rel) <= 1e-12 * _fro(AV), (r, lam, _fro(rel) / _fro(AV))
-        assert _fro(V.conj() @ V.T - np.eye(m + 1)) <= 1e-12, (r, lam)      # CGS2 on the FP64 path
+        AV = A[lam] @ V.T                                    # N x m
+        rel = AV - Cp @ np.linalg.solve(G, Fp) - V.T @ Hb[:m]
+        _check_last_column(rel, Hb, V, Cp, AV, 1e-12, (r, lam))
+        assert _fro(V.conj() @ V.T - np.eye(m)) <= 1e-12, (r, lam)          # CGS2 on the FP64 path
         assert _fro(Cp.conj().T @ V.T) <= 1e-12 * _fro(Cp), (r, lam)       # V orthogonal to C_j
         assert np.allclose(np.tril(Hb, -2), 0.0)                             # upper Hessenberg
         checked += 1
     assert checked >= 4
+
+
+def _check_last_column(rel, Hb, V, Cp, AV, tol, case, orth_tol=None):
+    """The modified Arnoldi relation A_j V_m = C_j (C_j^H A_j V_m) + V_{m+1} Hbar_m, given
+    v_0..v_{m-1}: the first m-1 columns close on the returned basis; the last one defines
+    v_m = r / Hbar[m, m-1], so its residual r must have norm |Hbar[m, m-1]| and be orthogonal to
+    C_j and to v_0..v_{m-1} (v_m is a unit vector orthogonal to both)."""
+    orth_tol = tol if orth_tol is None else orth_tol
+    m = V.shape[0]
+    assert _fro(rel[:, :m - 1]) <= tol * _fro(AV), (case, _fro(rel[:, :m - 1]) / _fro(AV))
+    r = rel[:, m - 1]
+    scale = _fro(AV[:, m - 1])
+    assert abs(_fro(r) - abs(Hb[m, m - 1])) <= tol * scale, (case, _fro(r), abs(Hb[m, m - 1]))
+    assert _fro(V.conj() @ r) <= orth_tol * scale, case
+    assert _fro(Cp.conj().T @ r) <= orth_tol * _fro(Cp) * scale, case
 
 
 def test_shift_invariant_case_needs_only_the_initial_guess(hd):
@@ -176,9 +191,9 @@ def test_mixed_path_intermediates(hd):
             continue
         U, _ = sess.basis_UC(r)
         Cp = A[lam] @ U.T
-        AV = A[lam] @ V[:m].T
-        rel = AV - Cp @ np.linalg.solve(Cp.conj().T @ Cp, Fp) - V.T @ Hb
-        assert _fro(rel) <= 1e-5 * _fro(AV), (r, lam, _fro(rel) / _fro(AV))
-        assert _fro(V.conj() @ V.T - np.eye(m + 1)) <= 1e-3, (r, lam)
+        AV = A[lam] @ V.T
+        rel = AV - Cp @ np.linalg.solve(Cp.conj().T @ Cp, Fp) - V.T @ Hb[:m]
+        _check_last_column(rel, Hb, V, Cp, AV, 1e-5, (r, lam), orth_tol=1e-3)
+        assert _fro(V.conj() @ V.T - np.eye(m)) <= 1e-3, (r, lam)
         checked += 1
     assert checked >= 4
