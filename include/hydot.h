@@ -260,6 +260,25 @@ hydot_status hydot_born_apply_ex(const hydot_operator* op, const void* phi_src, 
                                  int32_t n_v, void* y, void* workspace, size_t ws_bytes,
                                  hipStream_t stream);
 
+/* Allocation-free J v, for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same products, kernels and
+ * arguments as hydot_born_apply_ex, without the workspace.  The FP64 partial sums live in a
+ * static device array of HYDOT_BORN_NOALLOC_SCRATCH_BYTES that every GPU the library runs on
+ * holds until the process ends; the voxel split of the current launch shapes is lowered until
+ * the partials fit.  A call whose partials for a single voxel range (n_v * n_lambda * S * D
+ * complex FP64 values with the pair-product kernel, n_v * n_lambda * 2S' * 2D' FP64 values
+ * otherwise, S' and D' rounded up to 8) exceed the array returns HYDOT_ENOMEM before any launch.
+ * Calls no hipMalloc or hipFree and allocates no host memory on success (only an error path
+ * formats its message).  The first call on a device looks up that device's address of the
+ * array (hipGetSymbolAddress) and keeps it.  Works on the current device.  Every call
+ * on one GPU shares that GPU's array: calls that overlap in time on one GPU (other streams,
+ * other host threads) race and must be serialised by the caller. */
+#define HYDOT_BORN_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+hydot_status hydot_born_apply_noalloc(const hydot_operator* op, const void* phi_src, int32_t S,
+                                      const void* phi_det, int32_t D, int64_t lam_stride,
+                                      hydot_dtype field_dtype, hydot_born_compute compute,
+                                      const void* v, int32_t n_v, void* y, hipStream_t stream);
+
 /* Adjoint product summed over wavelengths: the product with the conjugate transpose of H that
  * the gradient of the misfit needs (Sec. 5, the gradient of eq. minimization uses H^T; the
  * Jacobian step of Alg. opt):

@@ -16,6 +16,8 @@
 // 16 lanes of a k-slot read 16 consecutive voxels of one source row.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "common.h"
@@ -760,6 +762,34 @@ static hydot_status jv_launch(const hydot_operator* op, const JvPlan& P, const v
   return born_apply_impl<cf, CM_F32>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
 }
 
+// ---------------------------------------------------------------- allocation-free J v
+// The FP64 split partials of hydot_born_apply_noalloc live in this file-scope device array: one
+// copy per GPU, held until the process ends.  Host code never passes the array's name to a
+// kernel or a copy (on the host it is only a stand-in symbol): the device address of each GPU's
+// copy is looked up once per device with hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr size_t kNoAllocScratchBytes = HYDOT_BORN_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's address of `scratch` (looked up on the first call on that device)
+static hydot_status noalloc_scratch(void** out) {
+  int dev = -1;
+  HYDOT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HYDOT_EUNSUPPORTED, "born_apply_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HYDOT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || ((uintptr_t)ptr & 255u)) return fail(HYDOT_EDEVICE, "born_apply_noalloc: scratch address lookup failed");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HYDOT_OK;
+}
+
 }  // namespace hydot
 
 using namespace hydot;
@@ -792,6 +822,26 @@ hydot_status hydot_born_apply_ex(const hydot_operator* op, const void* phi_src, 
   const JvPlan P = jv_plan(op, op->tune, S, D, n_v, cm, jv_real_bytes(field_dtype));
   if (ws_bytes < P.part_bytes) return fail(HYDOT_ENOMEM, "born_apply: workspace smaller than hydot_born_workspace_bytes");
   return jv_launch(op, P, phi_src, S, phi_det, D, lam_stride, field_dtype, cm, v, n_v, y, workspace, stream);
+}
+
+hydot_status hydot_born_apply_noalloc(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
+                                      int32_t D, int64_t lam_stride, hydot_dtype field_dtype,
+                                      hydot_born_compute compute, const void* v, int32_t n_v, void* y,
+                                      hipStream_t stream) {
+  hydot_status s = jv_check(op, phi_src, S, phi_det, D, lam_stride, field_dtype, compute, n_v);
+  if (s != HYDOT_OK) return s;
+  if (!v || !y) return fail(HYDOT_EINVAL, "born_apply_noalloc: null v or y");
+  const int cm = jv_cm(field_dtype, compute);
+  // the tuned split, lowered until the partials fit the static scratch
+  const JvPlan P = jv_plan(op, op->tune, S, D, n_v, cm, jv_real_bytes(field_dtype), kNoAllocScratchBytes);
+  if (P.part_bytes > kNoAllocScratchBytes)
+    return fail(HYDOT_ENOMEM, "born_apply_noalloc: the partial sums of one voxel range (" +
+                                  std::to_string(P.part_bytes) + " bytes for n_v * n_lambda * S * D) exceed the " +
+                                  std::to_string(kNoAllocScratchBytes) + "-byte static scratch");
+  void* part = nullptr;
+  s = noalloc_scratch(&part);
+  if (s != HYDOT_OK) return s;
+  return jv_launch(op, P, phi_src, S, phi_det, D, lam_stride, field_dtype, cm, v, n_v, y, part, stream);
 }
 
 hydot_status hydot_born_apply(const hydot_operator* op, const void* phi_src, int32_t S, const void* phi_det,
