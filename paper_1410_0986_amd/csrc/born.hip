@@ -252,9 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_born_jv(int N, int S, int D, int Sp,
 template <typename O>
 __global__ void k_born_apply_finish(int S, int D, int Sp, int Dp, int nsplit, int L, const double* part,
                                     double scale, O* y) {
-  const int cl = blockIdx.x;  // c*L + l
+  const int cl = blockIdx.y;  // c*L + l
   const size_t tile = (size_t)(2 * Sp) * (2 * Dp);
-  for (int e = threadIdx.x; e < S * D; e += blockDim.x) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;   // pair s*D + d
+  if (e < S * D) {
     const int s = e / D, d = e % D;
     double rr = 0, ii = 0, ri = 0, ir = 0;
     for (int sp = 0; sp < nsplit; ++sp) {
@@ -567,6 +568,12 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint(int N, int S, int D, in
   }
 }
 
+}  // namespace hydot
+
+#include "born_wide.h"
+
+namespace hydot {
+
 template <typename TS, int CM, int NCT>
 void launch_jv_pairs(dim3 grid, hipStream_t stream, int N, int S, int D, int64_t ls, const void* phs, const void* phd,
                      const void* v, int n_v, int kb, int L, int ntd, void* part) {
@@ -579,6 +586,7 @@ void launch_jv_pairs(dim3 grid, hipStream_t stream, int N, int S, int D, int64_t
 // the voxels into ranges and the bytes of FP64 split partials it writes (the caller's scratch).
 struct JvPlan {
   bool pairs = false;
+  bool wide = false;                            // k_born_jv_wide (FP32, S and D above 32)
   int Sp = 0, Dp = 0;
   int kt = 32, tpw = 1, nvb = 1, ngroups = 1;   // real-ified kernel
   int nts = 1, ntd = 1, nct = 1;                // pair-product kernel
@@ -597,7 +605,14 @@ static JvPlan jv_plan(const hydot_operator* op, const hydot_tuning& tune, int S,
   const hydot_tuning tu = resolved_tuning(tune);
   P.Sp = pad8(S);
   P.Dp = pad8(D);
-  if (n_v >= kPairsMinNv) {
+  if (n_v < kPairsMinNv && cm == CM_F32 && S >= kWideMin && D >= kWideMin) {
+    // one block per (voxel range, wavelength, probe vector), each holding all S x D pairs:
+    // a quarter of the tuned block count fills the chip (about two blocks per CU by default)
+    P.wide = true;
+    P.kt = 16 * kWideNS;   // voxel ranges hold whole FP32 partial sums
+    const int target = std::max(1, tu.born_blocks / 4);
+    P.nsplit = std::max(1, (target + L * n_v - 1) / (L * n_v));
+  } else if (n_v >= kPairsMinNv) {
     P.pairs = true;
     P.kt = 32;
     P.nts = (S + 7) / 8;
@@ -618,11 +633,13 @@ static JvPlan jv_plan(const hydot_operator* op, const hydot_tuning& tune, int S,
     };
     P.kt = bf16_compute(cm) ? 32 : (lds(32) <= kLdsCap && tu.born_stage != 16 ? 32 : 16);
     P.ngroups = (n_v + P.nvb - 1) / P.nvb;
-    P.nsplit = std::max(1, (tu.born_blocks + L * P.ngroups - 1) / (L * P.ngroups));
+    // a block's work grows with its output tiles: beyond 16 tiles, fewer blocks (and partials)
+    const int tgt = T_all > 16 ? std::max(1, tu.born_blocks * 16 / T_all) : tu.born_blocks;
+    P.nsplit = std::max(1, (tgt + L * P.ngroups - 1) / (L * P.ngroups));
   }
   // split over voxels so the grid has about born_blocks blocks; ranges are whole stages
   const int max_split = (N + P.kt - 1) / P.kt;
-  const size_t per_split_bytes = P.pairs ? (size_t)n_v * L * S * D * 2 * sizeof(double)
+  const size_t per_split_bytes = P.pairs || P.wide ? (size_t)n_v * L * S * D * 2 * sizeof(double)
                                          : (size_t)n_v * L * (2 * P.Sp) * (2 * P.Dp) * sizeof(double);
   P.nsplit = std::min(P.nsplit, max_split);
   if (max_part_bytes > 0) P.nsplit = (int)std::max<long long>(1, std::min<long long>(P.nsplit, (long long)(max_part_bytes / per_split_bytes)));
@@ -652,9 +669,35 @@ hydot_status born_apply_pairs(const hydot_operator* op, const JvPlan& P, const v
   return HYDOT_OK;
 }
 
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// J v on k_born_jv_wide (complex FP32 fields, S and D above 32, fewer than kPairsMinNv probe
+// vectors), then the fixed-order sum over the voxel ranges.
+hydot_status born_apply_wide(const hydot_operator* op, const JvPlan& P, const void* phs, int S, const void* phd,
+                             int D, int64_t ls, const void* v, int n_v, void* y, void* part, hipStream_t stream) {
+  const int N = op->gp.N, L = op->L;
+  const dim3 grid(P.nsplit, L, n_v);
+  const bool vec = N % 4 == 0 && aligned16(phs) && aligned16(phd) && aligned16(v);
+  if (vec)
+    hipLaunchKernelGGL(k_born_jv_wide<true>, grid, dim3(kBlock), 0, stream, N, S, D, ls, (const cf*)phs,
+                       (const cf*)phd, (const float*)v, P.kb, L, (double*)part);
+  else
+    hipLaunchKernelGGL(k_born_jv_wide<false>, grid, dim3(kBlock), 0, stream, N, S, D, ls, (const cf*)phs,
+                       (const cf*)phd, (const float*)v, P.kb, L, (double*)part);
+  const int nout = n_v * L * S * D;
+  const double h = op->grid.h_mm;
+  hipLaunchKernelGGL((k_born_pairs_finish<cf>), dim3((nout + 255) / 256), dim3(256), 0, stream, S * D, P.nsplit,
+                     nout, (const double*)part, -h * h * h, (cf*)y);
+  HYDOT_HIP(hipGetLastError());
+  return HYDOT_OK;
+}
+
 template <typename TS, int CM>
 hydot_status born_apply_impl(const hydot_operator* op, const JvPlan& P, const void* phs, int S, const void* phd,
                              int D, int64_t ls, const void* v, int n_v, void* y, void* part, hipStream_t stream) {
+  if constexpr (std::is_same<TS, cf>::value && CM == CM_F32) {
+    if (P.wide) return born_apply_wide(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
+  }
   if (P.pairs) return born_apply_pairs<TS, CM>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
   using R = typename Field<TS>::real;
   const int N = op->gp.N, L = op->L;
@@ -686,8 +729,8 @@ hydot_status born_apply_impl(const hydot_operator* op, const JvPlan& P, const vo
 #undef HYDOT_BA
 #undef HYDOT_BA_E
   const double h = op->grid.h_mm;
-  hipLaunchKernelGGL((k_born_apply_finish<cplx<R>>), dim3(n_v * L), dim3(256), 0, stream, S, D, Sp, Dp, P.nsplit, L,
-                     (const double*)part, -h * h * h, (cplx<R>*)y);
+  hipLaunchKernelGGL((k_born_apply_finish<cplx<R>>), dim3((S * D + 255) / 256, n_v * L), dim3(256), 0, stream, S, D,
+                     Sp, Dp, P.nsplit, L, (const double*)part, -h * h * h, (cplx<R>*)y);
   HYDOT_HIP(hipGetLastError());
   return HYDOT_OK;
 }
@@ -697,12 +740,30 @@ hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S,
                                int64_t ls, const void* w, int n_w, void* g, hipStream_t stream) {
   using R = typename Field<TS>::real;
   const int N = op->gp.N, L = op->L;
+  const double h = op->grid.h_mm;
+  if constexpr (std::is_same<TS, cf>::value) {
+    if (S >= kWideMin && D >= kWideMin) {   // many pairs: k_born_adjoint_wide, one data vector per launch
+      const bool vec = N % 4 == 0 && aligned16(phs) && aligned16(phd);
+      const dim3 grid((N + 63) / 64);
+      for (int c = 0; c < n_w; ++c) {
+        const cf* wc = (const cf*)w + (size_t)c * L * S * D;
+        cf* gc = (cf*)g + (size_t)c * N;
+        if (vec)
+          hipLaunchKernelGGL(k_born_adjoint_wide<true>, grid, dim3(kBlock), 0, stream, N, S, D, ls, L,
+                             (const cf*)phs, (const cf*)phd, wc, -h * h * h, gc);
+        else
+          hipLaunchKernelGGL(k_born_adjoint_wide<false>, grid, dim3(kBlock), 0, stream, N, S, D, ls, L,
+                             (const cf*)phs, (const cf*)phd, wc, -h * h * h, gc);
+      }
+      HYDOT_HIP(hipGetLastError());
+      return HYDOT_OK;
+    }
+  }
   const int Sp = pad8(S), Dp = pad8(D);
   const int TB = 2 * Dp / 16;
   // four data vectors per block when the detector tiles are few (register budget)
   const int nw = n_w > 1 && TB <= 2 ? 4 : 1;
   dim3 grid((N + 63) / 64, (n_w + nw - 1) / nw);
-  const double h = op->grid.h_mm;
   const double sc = -h * h * h;
 #define HYDOT_BJ(TBM, SQ, NW)                                                                                  \
   hipLaunchKernelGGL((k_born_adjoint<TS, TBM, SQ, NW>), grid, dim3(kBlock), 0, stream, N, S, D, Sp, Dp, ls, L, \

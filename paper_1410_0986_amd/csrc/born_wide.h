@@ -1,0 +1,330 @@
+// Born products for many source-detector pairs (more than 32 sources and more than 32
+// detectors) from complex FP32 fields on the FP32 MFMA.  At these shapes one probe vector
+// already gives S/2 >= 16 flop per field byte, so the products are bound by the MFMA and HBM
+// together; these kernels feed the MFMA straight from registers loaded from HBM (no LDS
+// staging of the fields, no operand reloads per output tile).
+//
+// Operand layout shared by both kernels.  v_mfma_f32_16x16x4f32 takes A[row = lane%16][k =
+// lane/16] and B[k = lane/16][col = lane%16].  The contraction index of J v is the voxel, and a
+// sum over voxels may take them in any order as long as both operands agree; lane (r = lane%16,
+// g = lane/16) therefore loads voxels 4g..4g+3 of a 16-voxel step of its field row (32
+// contiguous bytes, the four groups of a row covering one 128-byte line), and the i-th of the
+// four MFMA k-steps of the step takes voxel 4g + i in every group.
+#pragma once
+
+namespace hydot {
+
+constexpr int kWideMin = 33;     // S and D above 32: the real-ified / pair kernels pad less below
+constexpr int kWideNS = 8;       // 16-voxel steps per FP32 partial sum (128 voxels) before FP64
+
+// 16-byte loads of two complex FP32 values / four floats (the caller checks the alignment)
+__device__ inline void ld2cf(const cf* p, cf& a, cf& b) {
+  const f32x4 x = *reinterpret_cast<const f32x4*>(p);
+  a = cf{x[0], x[1]};
+  b = cf{x[2], x[3]};
+}
+
+// ---------------------------------------------------------------- J v
+// y[c][l][s][d] = -h^3 sum_k phi_s(k) v_c(k) phi_d(k) for one probe vector per block.
+// Block = 4 waves on (split over voxels, wavelength, probe vector).  Wave (wa, wb) = (w/2, w%2)
+// owns the pairs s in [32 wa, 32 wa + 32), d in [32 wb, 32 wb + 32) as 2 x 2 tiles of 16 x 16:
+// the A operand is a = phi_s v, the B operand phi_d, and Re y accumulates Re a Re b + (-Im a) Im b,
+// Im y accumulates Re a Im b + Im a Re b, in FP32 over kWideNS steps and then in FP64.  Each
+// block writes its FP64 partial sums as part[((c L + l) nsplit + split) S D + s D + d] (Re, Im),
+// summed over the splits by k_born_pairs_finish.  VEC: 16-byte loads (N a multiple of 4 and
+// every base pointer 16-byte aligned).
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, int64_t lam_stride,
+                                                        const cf* __restrict__ phs, const cf* __restrict__ phd,
+                                                        const float* __restrict__ v, int kb, int L,
+                                                        double* __restrict__ part) {
+  const int split = blockIdx.x, l = blockIdx.y, c = blockIdx.z, nsplit = gridDim.x;
+  const int k0 = split * kb, k1 = min(N, k0 + kb);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int wa = wave >> 1, wb = wave & 1;
+  const size_t Nz = (size_t)N;
+  // this lane's two A rows (sources) and two B rows (detectors); rows past S or D read zero
+  int srow[2], drow[2];
+  bool sok[2], dok[2];
+  const cf* pa[2];
+  const cf* pb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    srow[t] = 32 * wa + 16 * t + r16;
+    drow[t] = 32 * wb + 16 * t + r16;
+    sok[t] = srow[t] < S;
+    dok[t] = drow[t] < D;
+    pa[t] = phs + ((size_t)l * lam_stride + (sok[t] ? srow[t] : 0)) * Nz;
+    pb[t] = phd + ((size_t)l * lam_stride + (dok[t] ? drow[t] : 0)) * Nz;
+  }
+  const float* vc = v + (size_t)c * Nz;
+  struct Stage {
+    cf a[2][4], b[2][4];
+    float vv[4];
+  };
+  auto fetch = [&](int kbase, Stage& st) {
+    const int kq = kbase + 4 * g;
+    if (VEC && kq + 4 <= k1) {
+      const f32x4 x = *reinterpret_cast<const f32x4*>(vc + kq);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) st.vv[i] = x[i];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        if (sok[t]) {
+          ld2cf(pa[t] + kq, st.a[t][0], st.a[t][1]);
+          ld2cf(pa[t] + kq + 2, st.a[t][2], st.a[t][3]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) st.a[t][i] = cf{0.f, 0.f};
+        }
+        if (dok[t]) {
+          ld2cf(pb[t] + kq, st.b[t][0], st.b[t][1]);
+          ld2cf(pb[t] + kq + 2, st.b[t][2], st.b[t][3]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) st.b[t][i] = cf{0.f, 0.f};
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = kq + i;
+        const bool ok = k < k1;
+        st.vv[i] = ok ? vc[k] : 0.f;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          st.a[t][i] = ok && sok[t] ? pa[t][k] : cf{0.f, 0.f};
+          st.b[t][i] = ok && dok[t] ? pb[t][k] : cf{0.f, 0.f};
+        }
+      }
+    }
+  };
+  f32x4 accR[2][2], accI[2][2];
+  double totR[2][2][4], totI[2][2][4];
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb) {
+      accR[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      accI[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) totR[ta][tb][r] = totI[ta][tb][r] = 0.0;
+    }
+  const int nst = k1 > k0 ? (k1 - k0 + 15) / 16 : 0;
+  Stage cur, nxt;
+  if (nst > 0) fetch(k0, cur);
+  for (int st = 0; st < nst; ++st) {
+    if (st + 1 < nst) fetch(k0 + 16 * (st + 1), nxt);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float ar[2], ai[2], nai[2];
+#pragma unroll
+      for (int ta = 0; ta < 2; ++ta) {
+        ar[ta] = cur.a[ta][i].re * cur.vv[i];
+        ai[ta] = cur.a[ta][i].im * cur.vv[i];
+        nai[ta] = -ai[ta];
+      }
+      // eight independent accumulators between two products into the same one
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta) {
+          accR[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ta], cur.b[tb][i].re, accR[ta][tb], 0, 0, 0);
+          accI[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ta], cur.b[tb][i].im, accI[ta][tb], 0, 0, 0);
+        }
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta) {
+          accR[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[ta], cur.b[tb][i].im, accR[ta][tb], 0, 0, 0);
+          accI[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[ta], cur.b[tb][i].re, accI[ta][tb], 0, 0, 0);
+        }
+    }
+    if ((st + 1) % kWideNS == 0 || st + 1 == nst) {
+#pragma unroll
+      for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            totR[ta][tb][r] += (double)accR[ta][tb][r];
+            totI[ta][tb][r] += (double)accI[ta][tb][r];
+          }
+          accR[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
+          accI[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    cur = nxt;
+  }
+  // accumulator register r of lane (col = lane%16, g) holds row 4g + r of the tile
+  double* out = part + ((size_t)(c * L + l) * nsplit + split) * (size_t)S * D * 2;
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = 32 * wa + 16 * ta + 4 * g + r, d = 32 * wb + 16 * tb + r16;
+        if (s < S && d < D) {
+          const size_t o = ((size_t)s * D + d) * 2;
+          out[o] = totR[ta][tb][r];
+          out[o + 1] = totI[ta][tb][r];
+        }
+      }
+}
+
+// ---------------------------------------------------------------- J^H w
+// g[k] = scale sum_l sum_d conj(phi_d(k)) T_l[k][d],  T_l[k][d] = sum_s conj(phi_s(k)) w_l[s][d].
+// Block = 4 waves on 64 voxels (16 per wave), looping over the wavelengths.  Per wavelength the
+// block stages w_l (S x D, zero-padded to 64 x 64) in LDS; each wave forms T for its 16 voxels
+// and the 64 detector columns on the MFMA: A[row = voxel][k] = conj(phi_s), lane (voxel
+// vox0 + lane%16, group g = lane/16) holding the sources s = g + 4q, q < 16 (each load reads 16
+// consecutive voxels of one source row across the lanes: 128 bytes), so that the q-th k-step
+// takes source g + 4q in every group; B[k][col] = w[g + 4q][16 t + lane%16] from LDS, t < 4
+// column tiles.  Re T accumulates Re phi Re w + Im phi Im w and Im T accumulates
+// Re phi Im w + (-Im phi) Re w (FP32 over the 64 sources of one wavelength).  The epilogue
+// contracts T with conj(phi_d) at the lane's accumulator entries (voxel vox0 + 4g + r,
+// detector 16 t + lane%16) into FP64 sums over the wavelengths, which are reduced over the 16
+// detector lanes at the end.  The next wavelength's source values and w_l are loaded while
+// the current products run.  VEC: 16-byte loads of the detector fields (N a multiple of 4,
+// base pointers 16-byte aligned).
+constexpr int kWPitch = 66;    // LDS row pitch of w (complex elements)
+
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_born_adjoint_wide(int N, int S, int D, int64_t lam_stride, int L,
+                                                             const cf* __restrict__ phs,
+                                                             const cf* __restrict__ phd,
+                                                             const cf* __restrict__ w, double scale,
+                                                             cf* __restrict__ gout) {
+  __shared__ cf Ws[64 * kWPitch];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int vox0 = (blockIdx.x * 4 + wave) * 16;
+  const int vox = vox0 + r16;               // A row of this lane
+  const bool vok = vox < N;
+  const size_t Nz = (size_t)N;
+  // w_l staging: thread tid holds the 16 elements e = tid + 256 j of the 64 x 64 padded tile
+  cf wreg[16];
+  auto fetch_w = [&](int l) {
+    const cf* wl = w + (size_t)l * S * D;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = tid + 256 * j, s = e >> 6, d = e & 63;
+      wreg[j] = s < S && d < D ? wl[s * D + d] : cf{0.f, 0.f};
+    }
+  };
+  auto store_w = [&]() {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = tid + 256 * j, s = e >> 6, d = e & 63;
+      Ws[s * kWPitch + d] = wreg[j];
+    }
+  };
+  // sources s = g + 4q of this lane's voxel
+  cf za[16], zn[16];
+  auto fetch_s = [&](int l, cf (&z)[16]) {
+    const cf* ps = phs + (size_t)l * lam_stride * Nz;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int s = g + 4 * q;
+      z[q] = vok && s < S ? ps[(size_t)s * Nz + vox] : cf{0.f, 0.f};
+    }
+  };
+  // detector fields at the accumulator entries: detector 16 t + r16, voxels vox0 + 4g + r
+  auto fetch_d = [&](int l, cf (&ph)[4][4]) {
+    const cf* pd = phd + (size_t)l * lam_stride * Nz;
+    const int vb = vox0 + 4 * g;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int d = 16 * t + r16;
+      const bool dk = d < D;
+      const cf* row = pd + (size_t)(dk ? d : 0) * Nz;
+      if (VEC && vb + 4 <= N) {
+        if (dk) {
+          ld2cf(row + vb, ph[t][0], ph[t][1]);
+          ld2cf(row + vb + 2, ph[t][2], ph[t][3]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) ph[t][r] = cf{0.f, 0.f};
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ph[t][r] = dk && vb + r < N ? row[vb + r] : cf{0.f, 0.f};
+      }
+    }
+  };
+  double gre[4], gim[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) gre[r] = gim[r] = 0.0;
+  fetch_w(0);
+  fetch_s(0, za);
+  for (int l = 0; l < L; ++l) {
+    __syncthreads();          // the previous wavelength's reads of Ws are done
+    store_w();
+    __syncthreads();
+    cf ph[4][4];
+    fetch_d(l, ph);           // used by the epilogue, after the products
+    if (l + 1 < L) {
+      fetch_w(l + 1);
+      fetch_s(l + 1, zn);
+    }
+    f32x4 accR[4], accI[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      accR[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      accI[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const float pr = za[q].re, pi = za[q].im, npi = -pi;
+      const cf* wrow = Ws + (g + 4 * q) * kWPitch + r16;
+      cf ww[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) ww[t] = wrow[16 * t];
+      // eight independent accumulators between two products into the same one
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, ww[t].re, accR[t], 0, 0, 0);
+        accI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, ww[t].im, accI[t], 0, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pi, ww[t].im, accR[t], 0, 0, 0);
+        accI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(npi, ww[t].re, accI[t], 0, 0, 0);
+      }
+    }
+    // conj(phi_d) T, FP64; accumulator register r of lane (col r16, g) is voxel vox0 + 4g + r
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double e = ph[t][r].re, f = ph[t][r].im;
+        const double tr = (double)accR[t][r], ti = (double)accI[t][r];
+        gre[r] += e * tr + f * ti;
+        gim[r] += e * ti - f * tr;
+      }
+    if (l + 1 < L) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) za[q] = zn[q];
+    }
+  }
+  // sum over the 16 detector lanes of each voxel
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      gre[r] += __shfl_xor(gre[r], off, 64);
+      gim[r] += __shfl_xor(gim[r], off, 64);
+    }
+  }
+  if (r16 == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int vv = vox0 + 4 * g + r;
+      if (vv < N) gout[vv] = cf{(float)(scale * gre[r]), (float)(scale * gim[r])};
+    }
+  }
+}
+
+}  // namespace hydot

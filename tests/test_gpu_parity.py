@@ -253,6 +253,43 @@ def test_born_probe_blocks(hd, S, D, n_v, dtype, tol):
     assert normwise(y.reshape(n_v, -1), ref.reshape(n_v, -1)).max() < tol
 
 
+@pytest.mark.parametrize("S,D", [(33, 47), (64, 40), (64, 64)])
+@pytest.mark.parametrize("grid", [(12, 10, 6), (11, 9, 7)])      # N = 720 (a multiple of 4), 693 (odd)
+def test_born_many_pairs_entrywise(hd, S, D, grid):
+    """More than 32 sources and detectors with complex FP32 fields: the kernels that feed the
+    MFMA from registers (16-byte loads when N is a multiple of 4, element loads otherwise),
+    partial source and detector tiles, a ragged voxel count, 1 and 3 probe vectors, 1 and 2 data
+    vectors.  Every (probe vector, wavelength, source, detector) entry of J v against the FP64
+    definition on the same FP32 operands, within 1e-5 of the absolute sum of its terms (FP32
+    products accumulated over 128 voxels, FP64 beyond); J^H w entry by entry the same way."""
+    nx, ny, nz = grid
+    w = workloads.config("tiny", nx=nx, ny=ny, nz=nz, n_lambda=3)
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(S * 7 + D + nx)
+    P = (rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))) * 1e-3
+    t = torch.from_numpy(P).to(torch.complex64).to(DEV)
+    Pr = t.cpu().numpy().astype(np.complex128)
+    Ps, Pd = Pr[:, :S], Pr[:, S:]
+    for n_v in (1, 3):
+        v = rng.standard_normal((n_v, w.N)).astype(np.float32)
+        y = hd.born_apply(op, t[:, :S], t[:, S:], torch.from_numpy(v).to(DEV)).cpu().numpy().astype(np.complex128)
+        vd = v.astype(np.float64)
+        ref = oborn.born_apply(Ps, Pd, vd, w.h)
+        absum = w.h ** 3 * np.einsum("lsk,ck,ldk->clsd", np.abs(Ps), np.abs(vd), np.abs(Pd), optimize=True)
+        assert y.shape == ref.shape == (n_v, w.L, S, D)
+        assert np.all(np.abs(y - ref) <= 1e-5 * absum), float((np.abs(y - ref) / absum).max())
+    for n_w in (1, 2):
+        wv = rng.standard_normal((n_w, w.L, S, D)) + 1j * rng.standard_normal((n_w, w.L, S, D))
+        wt = torch.from_numpy(wv).to(torch.complex64)
+        wr = wt.numpy().astype(np.complex128)
+        g = hd.born_apply_adjoint(op, t[:, :S], t[:, S:], wt.to(DEV)).cpu().numpy().astype(np.complex128)
+        g = g.reshape(n_w, w.N)
+        for c in range(n_w):
+            refg = oborn.born_apply_adjoint(Ps, Pd, wr[c], w.h)
+            absg = w.h ** 3 * np.einsum("lsk,lsd,ldk->k", np.abs(Ps), np.abs(wr[c]), np.abs(Pd), optimize=True)
+            assert np.all(np.abs(g[c] - refg) <= 1e-5 * absg), float((np.abs(g[c] - refg) / absg).max())
+
+
 def test_born_dot_test_on_device(hd):
     w = workloads.config("tiny")
     op = hd.Operator.from_workload(w)
