@@ -264,7 +264,7 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
   }
   if (p.nb > 65535 || p.rl > 65535) return fail(HYDOT_EINVAL, "solve: batch above 65535 systems; set max_batch");
   p.nchunks = (p.N + kChunk - 1) / kChunk;
-  p.ndots = 3 * p.k + p.mkmax + 2;
+  p.ndots = ndots_for(p.k, p.mkmax);
   p.ng = op->has_pert ? 4 : 3;
   p.npairs = p.ng * p.k * (p.ng * p.k + 1) / 2;
   p.sl = make_small(p.k, p.mkmax, p.nl);
@@ -962,7 +962,7 @@ hydot_status hydot_solve_inspect(const hydot_operator* op, int32_t n_rhs, const 
   info->rhs = p.per_system ? p.R - 1 : prm.rhs;
   info->lam = prm.lam;
   info->nsteps = st.nsteps;
-  const int k = p.k, m = st.nsteps, ldh = p.mkmax + 1;
+  const int k = p.k, m = st.nsteps;
   if (what == HYDOT_INSPECT_CHOL) {
     if (k == 0) return fail(HYDOT_EINVAL, "inspect: no deflation space (recycle_k = 0 or NO_RECYCLE)");
     if (!out) return HYDOT_OK;
@@ -978,13 +978,13 @@ hydot_status hydot_solve_inspect(const hydot_operator* op, int32_t n_rhs, const 
   if (out_bytes < need) return fail(HYDOT_ENOMEM, "inspect: output buffer too small");
   cd* o = (cd*)out;
   for (int j = 0; j < m; ++j)
-    for (int i = 0; i < k; ++i) o[(size_t)i * m + j] = sm[p.sl.Fp + i + k * j];
+    for (int i = 0; i < k; ++i) o[(size_t)i * m + j] = sm[small_Fp(p.sl, k, i, j)];
   cd* hb = o + (size_t)k * m;
   const double* cs = (const double*)(sm.data() + p.sl.cs);   // cosines in the .re slots
   const cd* sn = sm.data() + p.sl.sn;
   for (int j = 0; j < m; ++j) {
     std::vector<cd> col(m + 1, cd{0.0, 0.0});
-    for (int i = 0; i <= j + 1; ++i) col[i] = sm[p.sl.H + i + ldh * j];
+    for (int i = 0; i <= j + 1; ++i) col[i] = sm[small_H(p.sl, p.mkmax, i, j)];
     // the rotations applied to column j were 0..j in order; undo them in reverse with the
     // adjoint of [[c, s], [-conj(s), c]]
     for (int i = j; i >= 0; --i) {

@@ -9,14 +9,12 @@
 #pragma once
 
 #include "common.h"
+#include "krylov_index.h"
 
 namespace hydot {
 
 constexpr int kVPT = 8;                    // voxels per thread
 constexpr int kChunk = kBlock * kVPT;      // voxels per block
-constexpr int kMaxK = 32;                  // recycle dimension
-constexpr int kMaxMK = 128;                // Arnoldi steps per cycle (also Lanczos steps)
-constexpr int kMaxDots = 3 * kMaxK + kMaxMK + 2;
 
 // Per-system constants (host-built).  Internal order of a batch is rhs-major so
 // the wavelengths of one right-hand side, which share U and C, are adjacent.
@@ -52,29 +50,6 @@ struct SysState {
   double prev_outer;    // outer residual of the previous sweep
 };
 
-// Offsets (in cd units) inside one system's small block.
-struct Small {
-  int coefA, coefB, H, cs, sn, gam, Fp, vs, Lc, y0, cA32, total;
-};
-
-inline Small make_small(int k, int mkmax, int nl) {
-  Small s;
-  int o = 0;
-  s.coefA = o; o += k + mkmax + 2;
-  s.coefB = o; o += k + mkmax + 2;
-  s.H = o; o += (mkmax + 1) * mkmax;
-  s.cs = o; o += mkmax;
-  s.sn = o; o += mkmax;
-  s.gam = o; o += mkmax + 1;
-  s.Fp = o; o += k * mkmax;
-  s.vs = o; o += mkmax + 2;      // basis scales: v_l = vs[l] * (stored V_l)
-  s.Lc = o; o += k * k;          // y0 follows Lc directly (one host copy fills both)
-  s.y0 = o; o += (nl > 0 ? nl : 1);
-  s.cA32 = o; o += (k + mkmax + 3) / 2;   // FP32 copy of the step coefficients coefA (complex float)
-  s.total = (o + 15) & ~15;
-  return s;
-}
-
 template <typename S>
 struct Ctx {
   using R = typename Store<S>::real;
@@ -102,11 +77,6 @@ struct Ctx {
                     // systems re-orthogonalising at step j, right-hand sides stepping at step j
   S* Z = nullptr;   // [nb][N] preconditioned vector P^{-1} V_j (right preconditioning), or null
 };
-
-// slots of the partial sums
-__device__ __host__ inline int slot_defl(int i, int c) { return 3 * i + c; }
-__device__ __host__ inline int slot_v(int k, int l) { return 3 * k + l; }
-__device__ __host__ inline int slot_norm(int k, int mkmax) { return 3 * k + mkmax + 1; }
 
 __device__ inline void wave_store(cd v, int slot, cd* lds) {
   const double re = wave_sum(v.re), im = wave_sum(v.im);
@@ -180,7 +150,7 @@ __device__ inline void chunk_dots(const Ctx<S>& c, int sys, const Chunk<S>& ch, 
     wave_store(cd{a, 0.0}, slot_norm(c.k, c.mkmax), lds);
   }
   __syncthreads();
-  cd* out = c.part + ((size_t)sys * c.nchunks + blockIdx.x) * c.ndots;
+  cd* out = c.part + part_base(sys, c.nchunks, blockIdx.x, c.ndots);
   for (int i = threadIdx.x; i < c.k; i += kBlock) {
     cd a{0.0, 0.0};
 #pragma unroll
@@ -338,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_resid(Ctx<S> c, int force) {
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < kWaves; ++w) t += lds[w * kMaxDots].re;
-    c.part[((size_t)sys * c.nchunks + blockIdx.x) * c.ndots + slot_norm(c.k, c.mkmax)] = cd{t, 0.0};
+    c.part[part_base(sys, c.nchunks, blockIdx.x, c.ndots) + slot_norm(c.k, c.mkmax)] = cd{t, 0.0};
   }
 }
 
@@ -424,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_defl_start(Ctx<S> c) {
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int wq = 0; wq < kWaves; ++wq) t += lds[wq * kMaxDots].re;
-    c.part[((size_t)sys * c.nchunks + blockIdx.x) * c.ndots + slot_norm(c.k, c.mkmax)] = cd{t, 0.0};
+    c.part[part_base(sys, c.nchunks, blockIdx.x, c.ndots) + slot_norm(c.k, c.mkmax)] = cd{t, 0.0};
   }
 }
 
@@ -673,7 +643,7 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
     if (lane == 0 && !earlier) atomicAdd(&c.counter[2 + 2 * kMaxMK + j], 1);
   }
   cd* sm = c.small + (size_t)sys * c.sl.total;
-  const cd* part = c.part + (size_t)sys * c.nchunks * c.ndots;
+  const cd* part = c.part + part_base(sys, c.nchunks, 0, c.ndots);
   const int k = c.k;
   // slots needed by the phase
   int lo = 0, hi = 0;
@@ -698,8 +668,8 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
       int ck = 0;
       for (; ck + 8 <= c.nchunks; ck += 8)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) q[u] = q[u] + part[(size_t)(ck + u) * c.ndots + s];
-      for (; ck < c.nchunks; ++ck) q[0] = q[0] + part[(size_t)ck * c.ndots + s];
+        for (int u = 0; u < 8; ++u) q[u] = q[u] + part[part_base(0, c.nchunks, ck + u, c.ndots) + s];
+      for (; ck < c.nchunks; ++ck) q[0] = q[0] + part[part_base(0, c.nchunks, ck, c.ndots) + s];
       a = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
     }
     sum[s] = a;
@@ -780,13 +750,10 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
     }
     case PH_STEP_A: {
       atomicAdd(&c.counter[2 + j], 1);
-      cd* H = sm + c.sl.H;
-      const int ldh = c.mkmax + 1;
       cd* coef = sm + c.sl.coefA;
       if (k > 0) {
         make_f();
-        cd* Fp = sm + c.sl.Fp;
-        for (int i = 0; i < k; ++i) Fp[i + k * j] = f[i];
+        for (int i = 0; i < k; ++i) sm[small_Fp(c.sl, k, i, j)] = f[i];
         gsolve(k, Lc, f, g);
         for (int i = 0; i < k; ++i) coef[i] = g[i];
       }
@@ -795,7 +762,7 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
         const double sl = vs[l].re;
         const cd h = sl * sum[slot_v(k, l)];   // v_l^H w from the stored V_l
         coef[k + l] = sl * h;                  // multiplier of the stored V_l
-        H[l + ldh * j] = h;
+        sm[small_H(c.sl, c.mkmax, l, j)] = h;
       }
       // FP32 copy for the complex FP32 update kernels (read as block-uniform scalars there)
       cf* c32 = reinterpret_cast<cf*>(sm + c.sl.cA32);
@@ -803,8 +770,6 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
       break;
     }
     case PH_STEP_B: {
-      cd* H = sm + c.sl.H;
-      const int ldh = c.mkmax + 1;
       cd* coef = sm + c.sl.coefB;
       cd* vs = sm + c.sl.vs;
       // second-pass coefficients (f2 -> g2, h2) and the norm of their projection
@@ -830,21 +795,20 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
         st->reorth = 1;
         atomicAdd(&c.counter[2 + kMaxMK + j], 1);
         if (k > 0) {
-          cd* Fp = sm + c.sl.Fp;
           for (int i = 0; i < k; ++i) {
-            Fp[i + k * j] = Fp[i + k * j] + f[i];
+            sm[small_Fp(c.sl, k, i, j)] = sm[small_Fp(c.sl, k, i, j)] + f[i];
             coef[i] = g[i];
           }
         }
         for (int l = 0; l <= j; ++l) {
           coef[k + l] = vs[l].re * h2[l];
-          H[l + ldh * j] = H[l + ldh * j] + h2[l];
+          sm[small_H(c.sl, c.mkmax, l, j)] = sm[small_H(c.sl, c.mkmax, l, j)] + h2[l];
         }
         const double e2 = w2 - proj;
         eta = e2 > 0.0 ? sqrt(e2) : 0.0;
         vs[j + 1] = cd{1.0, 0.0};       // the second pass writes V_{j+1} normalised
       }
-      H[j + 1 + ldh * j] = cd{eta, 0.0};
+      sm[small_H(c.sl, c.mkmax, j + 1, j)] = cd{eta, 0.0};
       const bool breakdown = !(eta > 1e-300);
       coef[k + c.mkmax + 1] = cd{breakdown ? 0.0 : 1.0 / eta, 0.0};
       st->total_iters += 1;
@@ -861,12 +825,12 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
       for (int i = 0; i < j; ++i) {
         const double ci = cs[2 * i];
         const cd si = snv[i];
-        const cd h1 = H[i + ldh * j], h2 = H[i + 1 + ldh * j];
-        H[i + ldh * j] = ci * h1 + si * h2;
-        H[i + 1 + ldh * j] = ci * h2 - conj(si) * h1;
+        const cd h1 = sm[small_H(c.sl, c.mkmax, i, j)], h2 = sm[small_H(c.sl, c.mkmax, i + 1, j)];
+        sm[small_H(c.sl, c.mkmax, i, j)] = ci * h1 + si * h2;
+        sm[small_H(c.sl, c.mkmax, i + 1, j)] = ci * h2 - conj(si) * h1;
       }
       {
-        const cd a = H[j + ldh * j], b = H[j + 1 + ldh * j];
+        const cd a = sm[small_H(c.sl, c.mkmax, j, j)], b = sm[small_H(c.sl, c.mkmax, j + 1, j)];
         const double aa = sqrt(norm2(a)), bb = sqrt(norm2(b));
         const double rr = sqrt(aa * aa + bb * bb);
         double cj;
@@ -881,8 +845,8 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
         }
         cs[2 * j] = cj;
         snv[j] = sj;
-        H[j + ldh * j] = cj * a + sj * b;
-        H[j + 1 + ldh * j] = cd{0.0, 0.0};
+        sm[small_H(c.sl, c.mkmax, j, j)] = cj * a + sj * b;
+        sm[small_H(c.sl, c.mkmax, j + 1, j)] = cd{0.0, 0.0};
         const cd g0 = gam[j];
         gam[j] = cj * g0;
         gam[j + 1] = cd{0.0, 0.0} - conj(sj) * g0;
@@ -895,23 +859,20 @@ __global__ __launch_bounds__(64) void k_reduce(Ctx<S> c, ReduceArgs ra, int phas
     }
     case PH_CYCLE_END: {
       const int ns = st->nsteps;
-      cd* H = sm + c.sl.H;
-      const int ldh = c.mkmax + 1;
       const cd* gam = sm + c.sl.gam;
       cd* y = tmp + 2 * kMaxK;   // ns
       for (int i = ns - 1; i >= 0; --i) {
         cd s = gam[i];
-        for (int q = i + 1; q < ns; ++q) s = s - H[i + ldh * q] * y[q];
-        const cd d = H[i + ldh * i];
+        for (int q = i + 1; q < ns; ++q) s = s - sm[small_H(c.sl, c.mkmax, i, q)] * y[q];
+        const cd d = sm[small_H(c.sl, c.mkmax, i, i)];
         const double dn = norm2(d);
         y[i] = dn > 0.0 ? (1.0 / dn) * (s * conj(d)) : cd{0.0, 0.0};
       }
       cd* coef = sm + c.sl.coefA;
       if (k > 0) {
-        const cd* Fp = sm + c.sl.Fp;
         for (int i = 0; i < k; ++i) {
           cd s{0.0, 0.0};
-          for (int q = 0; q < ns; ++q) s = s + Fp[i + k * q] * y[q];
+          for (int q = 0; q < ns; ++q) s = s + sm[small_Fp(c.sl, k, i, q)] * y[q];
           f[i] = s;
         }
         gsolve(k, Lc, f, g);

@@ -83,31 +83,9 @@ __device__ inline void row_reduce(const ProdTile<P>& pt, int nrows, cd& acc) {
   acc.im += im;
 }
 
-struct TileIdx {
-  int sys, chunk;
-};
-// flags bit 0: XCD-contiguous order; bit 1: z-slab order.
+// this block's (system, chunk): see tile_map
 __device__ inline TileIdx tile_idx(int nchunks, int grp, int flags) {
-  // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
-  // XCD-contiguous: each XCD gets a contiguous range of the logical order (whole
-  // systems), at the price of reading a right-hand side's C and U on every XCD.
-  const int nblk = gridDim.x;
-  int b = blockIdx.x;
-  if ((flags & 1) && (nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
-  const int per = grp * nchunks;
-  const int g = b / per, rem = b - g * per;
-  int ch = rem / grp;
-  // z-slab: the logical chunk position q lands on XCD (q * grp + system) % 8, a class of
-  // q mod Q (Q = 8 / gcd(grp, 8)) when grp * nchunks is a multiple of 8.  Class x is given the
-  // x-th contiguous range of chunks, i.e. a slab of z-planes: the stencil's z-neighbour chunks
-  // are then read on the same XCD, by blocks a few dispatch slots apart, and hit its L2; the
-  // chunks of one right-hand side still stay on one XCD.
-  if (flags & 2) {
-    const int q8 = grp & 7;
-    const int Q = q8 == 0 ? 1 : (q8 & 1) ? 8 : (q8 & 3) ? 4 : 2;
-    if (Q > 1 && nchunks % Q == 0 && (per & 7) == 0) ch = (ch % Q) * (nchunks / Q) + ch / Q;
-  }
-  return TileIdx{g * grp + rem % grp, ch};
+  return tile_map(blockIdx.x, gridDim.x, nchunks, grp, flags);
 }
 
 // finish the TPR-thread row sums and store them as the chunk's partial sums;
@@ -121,8 +99,7 @@ __device__ inline void row_flush(const Ctx<cf>& c, int sys, int chunk, int nrows
   }
   const int t = threadIdx.x, row = t / TPR;
   if ((t % TPR) != 0 || row >= nrows) return;
-  const int slot = row == norm_row ? slot_norm(c.k, c.mkmax) : slot0 + 3 * row;
-  c.part[((size_t)sys * c.nchunks + chunk) * c.ndots + slot] = acc;
+  c.part[part_base(sys, c.nchunks, chunk, c.ndots) + flush_rows_slot(row, slot0, norm_row, c.k, c.mkmax)] = acc;
 }
 
 template <int TPR>
@@ -134,7 +111,7 @@ __device__ inline void row_flush_v(const Ctx<cf>& c, int sys, int chunk, int nro
   }
   const int t = threadIdx.x, row = t / TPR;
   if ((t % TPR) != 0 || row >= nrows) return;
-  c.part[((size_t)sys * c.nchunks + chunk) * c.ndots + slot_v(c.k, row)] = acc;
+  c.part[part_base(sys, c.nchunks, chunk, c.ndots) + flush_v_slot(row, c.k)] = acc;
 }
 
 // Single-round form (at most 16 basis vectors): rows [0, nv) V dots, [nv, nv+k)
@@ -148,11 +125,7 @@ __device__ inline void row_flush_all(const Ctx<cf>& c, int sys, int chunk, int n
   }
   const int t = threadIdx.x, row = t / TPR;
   if ((t % TPR) != 0 || row >= nrows) return;
-  int slot;
-  if (row < nv) slot = slot_v(c.k, row);
-  else if (row < nv + c.k) slot = slot_defl(row - nv, 0);
-  else slot = slot_norm(c.k, c.mkmax);
-  c.part[((size_t)sys * c.nchunks + chunk) * c.ndots + slot] = acc;
+  c.part[part_base(sys, c.nchunks, chunk, c.ndots) + flush_all_slot(row, nv, c.k, c.mkmax)] = acc;
 }
 
 // Buffer-resource access (raw buffer loads): one 32-bit voxel byte offset in a VGPR
@@ -949,7 +922,7 @@ __global__ __launch_bounds__(kTSub) void k_defl_start_t(Ctx<cf> c, int grp, int 
     double a = 0.0;
 #pragma unroll
     for (int w = 0; w < kTSub / 64; ++w) a += wsum[w];
-    c.part[((size_t)sys * c.nchunks + ti.chunk) * c.ndots + slot_norm(c.k, c.mkmax)] = cd{a, 0.0};
+    c.part[part_base(sys, c.nchunks, ti.chunk, c.ndots) + slot_norm(c.k, c.mkmax)] = cd{a, 0.0};
   }
 }
 

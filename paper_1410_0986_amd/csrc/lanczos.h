@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_dots(LzCtx<T> c, int j) {
     lz_put(red, l, a);
   }
   __syncthreads();
-  lz_flush(red, j + 1, -1, c.part + ((size_t)sys * c.nchunks + blockIdx.x) * c.ndots, 0);
+  lz_flush(red, j + 1, -1, c.part + part_base(sys, c.nchunks, blockIdx.x, c.ndots), 0);
 }
 
 // step j, first projection (w' = W - sum coefA_l V_l, stored as V_{j+1}) and second-pass
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzCtx<T> c, int j) {
   }
   lz_put(red, j + 1, nrm);
   __syncthreads();
-  lz_flush(red, j + 2, j + 1, c.part + ((size_t)sys * c.nchunks + blockIdx.x) * c.ndots, slot_norm(0, c.mkmax));
+  lz_flush(red, j + 2, j + 1, c.part + part_base(sys, c.nchunks, blockIdx.x, c.ndots), slot_norm(0, c.mkmax));
 }
 
 // step j, second projection and normalisation of V_{j+1} in place

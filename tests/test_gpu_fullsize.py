@@ -26,7 +26,7 @@ def hd():
 def bench_opts(hd, **kw):
     import bench
     base = dict(rel_tol=1e-8, restart_m=bench.RESTART_M, recycle_k=bench.RECYCLE_K, lanczos_n=bench.LANCZOS_N,
-                precision=hd.PREC_MIXED, inner_tol=1e-5,
+                precision=hd.PREC_MIXED, inner_tol=bench.INNER_TOL,
                 flags=hd.FLAG_MEAN_SHIFT | hd.FLAG_GRAPH, max_iter=5000)
     base.update(kw)
     return hd.SolveOptions(**base)
