@@ -364,7 +364,13 @@ hydot_status hydot_misfit(const hydot_operator* op, int32_t S, int32_t D, const 
  *                2: plain dispatch order; 3: z-slab order, each XCD runs a contiguous range of
  *                chunks (a slab of z-planes) of every system, so the stencil's z-neighbour
  *                chunks are read on the XCD that reads them as centres (falls back to 2 where
- *                the chunk count does not split over the XCDs) (default 3).
+ *                the chunk count does not split over the XCDs); 4: chunk c on XCD c % 8 for
+ *                every system (its z-neighbour chunks on the same XCD), with the wavelengths of
+ *                one right-hand side taking each chunk in consecutive blocks there, so each
+ *                chunk of the shared recycled basis is fetched once per XCD (implies the
+ *                wavelength grouping when the batch holds whole right-hand sides; falls back to
+ *                2 where the chunk count is not a multiple of 8) (default: 4 where nx ny is a
+ *                multiple of 16384, so that a z-plane holds a multiple of 8 chunks, else 3).
  *   step_group   1: consecutive blocks walk the wavelengths of one right-hand side at one chunk
  *                (shared recycled basis in L2); 2: no grouping (default 2).
  *   born_stage   J v voxels per LDS stage: 16 or 32 (default: 32 where the stage fits 64 KB).
@@ -387,7 +393,8 @@ typedef struct {
 } hydot_tune_trial;
 
 /* Times every candidate ((step_presum, step_vx) in {(16,1), (4,1), (2,1), (4,2)} x step_order in
- * {3, 2} x step_group in {2, 1}) on the caller's problem: each
+ * {the grid's default order, 2 (3 where the default is 2)} x step_group in {2, 1}) on the caller's
+ * problem: each
  * trial is the hydot_solve_fields call with these arguments, timed by HIP events around the
  * Arnoldi step kernels only.  Candidates are tried with the library default first; a later one
  * replaces the best only when it is more than 1% faster (timing noise keeps the default).  The

@@ -155,16 +155,11 @@ __host__ __device__ inline VoxelInfo voxel_info(const GridP& g, uint32_t n) {
   v.i = (int32_t)(rem - jy * (uint32_t)g.nx);
   v.j = (int32_t)jy;
   v.k = (int32_t)kz;
-  int nr = 0, nd = 0;
-  const bool e[6] = {v.i == 0, v.i == g.nx - 1, v.j == 0, v.j == g.ny - 1, v.k == 0, v.k == g.nz - 1};
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    if (e[f]) {
-      if ((g.robin >> f) & 1u) ++nr; else ++nd;
-    }
-  }
-  v.nrobin = nr;
-  v.ndir = nd;
+  // exterior faces of the voxel as a mask (-x,+x,-y,+y,-z,+z), split by the Robin mask
+  const uint32_t m = (uint32_t)(v.i == 0) | (uint32_t)(v.i == g.nx - 1) << 1 | (uint32_t)(v.j == 0) << 2 |
+                     (uint32_t)(v.j == g.ny - 1) << 3 | (uint32_t)(v.k == 0) << 4 | (uint32_t)(v.k == g.nz - 1) << 5;
+  v.nrobin = __builtin_popcount(m & g.robin);
+  v.ndir = __builtin_popcount(m & ~g.robin & 0x3fu);
   return v;
 }
 

@@ -177,6 +177,11 @@ struct ProfRec {
   double bytes;
 };
 bool g_prof = false;
+// block-order flags of tile_map for a launch shape (step_order 1, 3, 4 -> bits 0, 1, 2; 2: none)
+inline int step_flags(const hydot_tuning& tu) {
+  return tu.step_order == 1 ? 1 : tu.step_order == 3 ? 2 : tu.step_order == 4 ? 4 : 0;
+}
+
 ProfRec g_rec[3] = {{"k_step_dots", 0, 0.0, 0.0}, {"k_step_update", 0, 0.0, 0.0}, {"k_step_finish", 0, 0.0, 0.0}};
 const char* kTiledNames[3] = {"k_step_dots_t", "k_step_update_t", "k_step_finish_t"};
 const char* kGenericNames[3] = {"k_step_dots", "k_step_update", "k_step_finish"};
@@ -600,13 +605,16 @@ struct Solver {
         used_tiled = true;
         const dim3 gt((unsigned)(nb * p.nchunks));
         const int grp = tile_grp;
-        const hydot_tuning tu = resolved_tuning(op->tune);
-        const int fl = tu.step_order == 1 ? 1 : tu.step_order == 3 ? 2 : 0;
+        const hydot_tuning tu = resolved_tuning(op->tune, &op->gp);
+        const int fl = step_flags(tu);
         const bool small = j + 1 <= 16;
+        const bool plain = c.mu == nullptr && c.Z == nullptr;
 #define HYDOT_STEP_T(KER, NV, P) hipLaunchKernelGGL((KER<NV, P, 1>), gt, dim3(kTSub), 0, stream, c, j, grp, fl)
 // the chunk-accumulating instances come with exact deflation dimensions k = 5 and 10
+// (k = 5 also without a perturbation or preconditioner, the plain instances)
 #define HYDOT_STEP_T16(KER, NV)                                                                                 \
-  if (c.k == 5) hipLaunchKernelGGL((KER<NV, 16, 1, 5>), gt, dim3(kTSub), 0, stream, c, j, grp, fl);           \
+  if (c.k == 5 && plain) hipLaunchKernelGGL((KER<NV, 16, 1, 5, true>), gt, dim3(kTSub), 0, stream, c, j, grp, fl); \
+  else if (c.k == 5) hipLaunchKernelGGL((KER<NV, 16, 1, 5>), gt, dim3(kTSub), 0, stream, c, j, grp, fl);      \
   else if (c.k == 10) hipLaunchKernelGGL((KER<NV, 16, 1, 10>), gt, dim3(kTSub), 0, stream, c, j, grp, fl);    \
   else HYDOT_STEP_T(KER, NV, 16);
 #define HYDOT_STEP_P(KER, NV)                                                                           \
@@ -656,8 +664,8 @@ struct Solver {
     if constexpr (std::is_same<S, cf>::value) {
       if (c.k > kTK) return false;
       const dim3 gt((unsigned)(nb * p.nchunks)), gr(nb);
-      const hydot_tuning tu = resolved_tuning(op->tune);
-      const int fl = tu.step_order == 1 ? 1 : tu.step_order == 3 ? 2 : 0;
+      const hydot_tuning tu = resolved_tuning(op->tune, &op->gp);
+      const int fl = step_flags(tu);
       if (tu.step_presum == 4 || tu.step_presum == 16)
         hipLaunchKernelGGL(k_inner_resid_t<4>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
       else if (tu.step_presum == 2) hipLaunchKernelGGL(k_inner_resid_t<2>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
@@ -765,7 +773,8 @@ struct Solver {
     Ctx<cd> c64 = ctx<cd>(p.k, false);   // FP64 views for residual and output kernels
     // group the wavelengths of one right-hand side when the batch holds whole ones
     tile_grp = 1;
-    if (nb % p.L == 0 && resolved_tuning(op->tune).step_group == 1) {
+    const hydot_tuning tg = resolved_tuning(op->tune, &op->gp);
+    if (nb % p.L == 0 && (tg.step_group == 1 || tg.step_order == 4)) {
       bool aligned = true;
       for (int i = 0; i < nb && aligned; ++i) aligned = sys_l[i] == i % p.L && sys_r[i] == sys_r[i - i % p.L];
       if (aligned) tile_grp = p.L;
@@ -1111,13 +1120,15 @@ hydot_status hydot_autotune_solve(hydot_operator* op, int32_t n_rhs, const int64
   const int presums[4] = {16, 4, 2, 4}, vxs[4] = {1, 1, 1, 2};
   int count = 0;
   double best = 1e300;
-  hydot_tuning best_t = resolved_tuning(keep);
+  hydot_tuning best_t = resolved_tuning(keep, &op->gp);
   hydot_status err = HYDOT_OK;
-  const int orders[2] = {3, 2};
+  // the grid's default block order, then the plain order (the z-slab order where that is 2)
+  const int def_order = best_t.step_order;
+  const int orders[2] = {def_order, def_order == 2 ? 3 : 2};
   for (int ig = 2; ig >= 1 && err == HYDOT_OK; --ig)
     for (int io = 0; io < 2 && err == HYDOT_OK; ++io)
       for (int ip = 0; ip < 4 && err == HYDOT_OK; ++ip) {
-        hydot_tuning t = resolved_tuning(keep);
+        hydot_tuning t = resolved_tuning(keep, &op->gp);
         t.step_presum = presums[ip];
         t.step_vx = vxs[ip];
         t.step_order = orders[io];

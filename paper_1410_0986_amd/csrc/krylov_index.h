@@ -77,11 +77,21 @@ HYDOT_HD inline int small_H(const Small& s, int mkmax, int i, int j) { return s.
 HYDOT_HD inline int small_Fp(const Small& s, int k, int i, int j) { return s.Fp + i + k * j; }
 
 // ----------------------------------------------------------------- block -> (system, chunk)
+constexpr int kChunkVoxels = 2048;   // voxels per (system, chunk) tile of the step kernels
+
+// Default block order of a grid: the chunk-per-XCD order (4) where a z-plane holds a multiple of
+// 8 chunks, so that chunk c and its z-neighbour chunks c +- nx ny / 2048 share XCD c % 8;
+// elsewhere the z-slab order (3).
+HYDOT_HD inline int default_step_order(int nx, int ny) {
+  return ((long long)nx * ny) % (8 * kChunkVoxels) == 0 ? 4 : 3;
+}
+
 struct TileIdx {
   int sys, chunk;
 };
 // Block b of nblk = nb * nchunks blocks, in groups of grp systems (nb a multiple of grp).
-// flags bit 0: XCD-contiguous order; bit 1: z-slab order.
+// flags bit 0: XCD-contiguous order; bit 1: z-slab order; bit 2: chunk-per-XCD order with the
+// systems of a group adjacent (takes precedence over bits 0 and 1).
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
 // XCD-contiguous: each XCD gets a contiguous range of the logical order (whole systems), at the
 // price of reading a right-hand side's C and U on every XCD.
@@ -90,7 +100,17 @@ struct TileIdx {
 // contiguous range of chunks, i.e. a slab of z-planes: the stencil's z-neighbour chunks are then
 // read on the same XCD, by blocks a few dispatch slots apart, and hit its L2; the chunks of one
 // right-hand side still stay on one XCD.
+// Chunk-per-XCD order (bit 2, when the chunk count is a multiple of 8): chunk c always runs on
+// XCD c % 8, so the stencil's z-neighbour chunks c +- 8 (a z-plane holds a multiple of 8 chunks
+// on the large grids) are read on the same XCD; within an XCD the grp systems of one group (the
+// wavelengths of one right-hand side, which share C and U) take one chunk in consecutive
+// blocks, so that chunk of C and U is fetched once into that XCD's L2 and reused grp times.
 HYDOT_HD inline TileIdx tile_map(int b, int nblk, int nchunks, int grp, int flags) {
+  if ((flags & 4) && (nchunks & 7) == 0) {
+    const int x = b & 7, i = b >> 3, nc8 = nchunks >> 3;
+    const int s = i % grp, t = i / grp;
+    return TileIdx{(t / nc8) * grp + s, (t % nc8) * 8 + x};
+  }
   if ((flags & 1) && (nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
   const int per = grp * nchunks;
   const int g = b / per, rem = b - g * per;

@@ -15,6 +15,7 @@ namespace hydot {
 
 constexpr int kVPT = 8;                    // voxels per thread
 constexpr int kChunk = kBlock * kVPT;      // voxels per block
+static_assert(kChunk == kChunkVoxels, "chunk size shared with the index arithmetic");
 
 // Per-system constants (host-built).  Internal order of a batch is rhs-major so
 // the wavelengths of one right-hand side, which share U and C, are adjacent.

@@ -165,6 +165,23 @@ __device__ inline SysBuf sys_buf(const Ctx<cf>& c, int sys, int rhs) {
   b.S = b.precond ? make_rsrc(c.Z + (size_t)sys * N, b.sv) : b.V;
   return b;
 }
+// The buffers of a system without an absorption perturbation or a preconditioner: the basis,
+// C and U only (the other resources alias the basis and are never read).
+__device__ inline SysBuf sys_buf_plain(const Ctx<cf>& c, int sys, int rhs) {
+  const uint32_t N = (uint32_t)c.g.N;
+  SysBuf b;
+  b.sv = N * 8u;
+  b.sc = N * 4u;
+  b.V = make_rsrc(c.V + (size_t)sys * c.vdim * N, (uint32_t)c.vdim * b.sv);
+  b.C = make_rsrc(c.C + (size_t)rhs * c.k * N, (uint32_t)c.k * b.sc);
+  b.U = make_rsrc(c.U + (size_t)rhs * c.k * N, (uint32_t)c.k * b.sc);
+  b.W = b.V;
+  b.M = b.V;
+  b.S = b.V;
+  b.pert = false;
+  b.precond = false;
+  return b;
+}
 // shape value of voxel byte offset vo4 (0 without a perturbation)
 __device__ inline float mu_at(const SysBuf& b, uint32_t vo4) { return b.pert ? ld_f(b.M, vo4, 0u) : 0.f; }
 // per-voxel shift of C'_j: sigma + sigma'_rel rho + tau_rel mu
@@ -252,10 +269,10 @@ __device__ inline void gather_stencil_yz(const GridP& g, Rsrc r, uint32_t so, ui
   const uint32_t sy = (uint32_t)g.nx, sz = (uint32_t)g.nx * (uint32_t)g.ny;
   const int lane = threadIdx.x & 63;
   if (load_centre) sr.xc = ld_cf(r, ok ? n * 8u : kOutside, so);
-  sr.m[0] = cf{0.f, 0.f};
-  sr.m[1] = cf{0.f, 0.f};
-  if (lane == 0 && ok && vi.i > 0) sr.m[0] = ld_cf(r, (n - 1) * 8u, so);
-  if (lane == 63 && ok && vi.i < g.nx - 1) sr.m[1] = ld_cf(r, (n + 1) * 8u, so);
+  // lanes other than 0 and 63 take these from the adjacent lanes (an offset past the resource
+  // reads zero, so every lane issues the load and no branch is needed)
+  sr.m[0] = ld_cf(r, lane == 0 && ok && vi.i > 0 ? (n - 1) * 8u : kOutside, so);
+  sr.m[1] = ld_cf(r, lane == 63 && ok && vi.i < g.nx - 1 ? (n + 1) * 8u : kOutside, so);
   sr.m[2] = cf{0.f, 0.f};
   sr.m[3] = cf{0.f, 0.f};
   if (!y_lo_lds) sr.m[2] = ld_cf(r, ok && vi.j > 0 ? (n - sy) * 8u : kOutside, so);
@@ -647,7 +664,7 @@ __device__ inline void tiled_step_x(const Ctx<cf>& c, int j, TileIdx ti) {
 // set the orthogonalisation, whose loss the second-pass test measures.
 // KX > 0: an instance for exactly k = KX deflation vectors (no per-slot guards or selects);
 // KX = 0: any k <= kTK.
-template <int NV, int KIND, int KX>
+template <int NV, int KIND, int KX, bool PL = false>
 __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   static_assert(NV <= 16, "chunk-accumulating instances hold at most 16 basis vectors");
   static_assert(KX >= 0 && KX <= kTK, "exact deflation dimension out of range");
@@ -672,7 +689,8 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   const bool with_norm = KIND == 1;
   const int nrows = nv + k + (with_norm ? 1 : 0);
   constexpr int nsub = kChunk / kTSub;
-  const SysBuf bf = sys_buf(c, sys, p.rhs);
+  // PL: no absorption perturbation and no preconditioner (known at compile time)
+  const SysBuf bf = PL ? sys_buf_plain(c, sys, p.rhs) : sys_buf(c, sys, p.rhs);
   cf* vnext = c.V + ((size_t)sys * c.vdim + j + 1) * N;
   const bool stencil = KIND == 0 || !bf.precond;
   const bool ytile = stencil && c.g.nx <= kTSub;   // y neighbours in this or the previous sub-tile
@@ -758,12 +776,13 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
 // w = A_hat V_j and first-pass inner products (tiled form of k_step_dots); w is stored as W
 // only where the update cannot recompute it (preconditioner, more than 16 basis vectors).
 // flags: block order (tile_idx).  VX voxels per thread per sub-tile (NV <= 16).
-template <int NV, int P, int VX, int KX = 0>
+// PL: the system has no absorption perturbation and no preconditioner (chunk-accumulating form).
+template <int NV, int P, int VX, int KX = 0, bool PL = false>
 __global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp, int flags) {
   const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   if (!c.st[ti.sys].in_cycle) return;
   if constexpr (P == 16) {
-    if constexpr (NV <= 16) tiled_step_acc<NV, 0, KX>(c, j, ti);
+    if constexpr (NV <= 16) tiled_step_acc<NV, 0, KX, PL>(c, j, ti);
   } else if constexpr (NV <= 16) {
     tiled_step_x<NV, 0, P, VX>(c, j, ti);
   } else {
@@ -772,12 +791,12 @@ __global__ __launch_bounds__(kTSub) void k_step_dots_t(Ctx<cf> c, int j, int grp
 }
 
 // First projection (w' stored as V_{j+1}) + second-pass inner products (tiled form of k_step_update).
-template <int NV, int P, int VX, int KX = 0>
+template <int NV, int P, int VX, int KX = 0, bool PL = false>
 __global__ __launch_bounds__(kTSub) void k_step_update_t(Ctx<cf> c, int j, int grp, int flags) {
   const TileIdx ti = tile_idx(c.nchunks, grp, flags);
   if (!c.st[ti.sys].in_cycle) return;
   if constexpr (P == 16) {
-    if constexpr (NV <= 16) tiled_step_acc<NV, 1, KX>(c, j, ti);
+    if constexpr (NV <= 16) tiled_step_acc<NV, 1, KX, PL>(c, j, ti);
   } else if constexpr (NV <= 16) {
     tiled_step_x<NV, 1, P, VX>(c, j, ti);
   } else {

@@ -39,5 +39,6 @@ struct hydot_operator {
 namespace hydot {
 GridP make_gridp(const hydot_grid& g);
 // launch shapes with defaults filled in
-hydot_tuning resolved_tuning(const hydot_tuning& t);
+// (with the grid: the block order default depends on the plane size, default_step_order)
+hydot_tuning resolved_tuning(const hydot_tuning& t, const GridP* g = nullptr);
 }

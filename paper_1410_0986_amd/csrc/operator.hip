@@ -9,6 +9,7 @@
 
 #include "common.h"
 #include "operator.h"
+#include "krylov_index.h"
 
 namespace hydot {
 
@@ -62,10 +63,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_op(GridP g, const S* __restric
   y[(size_t)v * g.N + n] = scale(a, prm.scl[v]);
 }
 
-hydot_tuning resolved_tuning(const hydot_tuning& t) {
+hydot_tuning resolved_tuning(const hydot_tuning& t, const GridP* g) {
   hydot_tuning r = t;
   if (r.step_presum == 0) r.step_presum = 16;
-  if (r.step_order == 0) r.step_order = 3;
+  if (r.step_order == 0) r.step_order = g ? default_step_order(g->nx, g->ny) : 3;
   if (r.step_group == 0) r.step_group = 2;
   if (r.born_blocks == 0) r.born_blocks = 4096;
   if (r.step_vx == 0) r.step_vx = 1;
@@ -186,7 +187,7 @@ hydot_status hydot_set_absorption_perturbation(hydot_operator* op, const double*
 
 hydot_status hydot_get_tuning(const hydot_operator* op, hydot_tuning* out) {
   if (!op || !out) return hydot::fail(HYDOT_EINVAL, "get_tuning: null argument");
-  *out = hydot::resolved_tuning(op->tune);
+  *out = hydot::resolved_tuning(op->tune, &op->gp);
   return HYDOT_OK;
 }
 
@@ -194,7 +195,7 @@ hydot_status hydot_set_tuning(hydot_operator* op, const hydot_tuning* t) {
   if (!op || !t) return hydot::fail(HYDOT_EINVAL, "set_tuning: null argument");
   const bool ok = (t->step_presum == 0 || t->step_presum == 1 || t->step_presum == 2 || t->step_presum == 4 ||
                    t->step_presum == 16) &&
-                  (t->step_order >= 0 && t->step_order <= 3) && (t->step_group >= 0 && t->step_group <= 2) &&
+                  (t->step_order >= 0 && t->step_order <= 4) && (t->step_group >= 0 && t->step_group <= 2) &&
                   (t->born_stage == 0 || t->born_stage == 16 || t->born_stage == 32) &&
                   (t->born_blocks == 0 || (t->born_blocks >= 256 && t->born_blocks <= 65536)) &&
                   (t->step_vx >= 0 && t->step_vx <= 2) && !(t->step_vx == 2 && t->step_presum != 4);

@@ -156,13 +156,13 @@ int main() {
       for (int nl : {0, 1, 7, 32, 40, mkmax}) check_small(k, mkmax, nl);
   // the step kernels' grids: chunks of 2048 voxels (the grids of every workload and ragged ones),
   // groups of 1 or of the L wavelengths of a right-hand side (the host takes grp > 1 only when
-  // the batch is a multiple of it), all four block orders
-  const int chunk_counts[] = {1, 2, 3, 5, 7, 8, 12, 16, 27, 64, 125, 216, 512};
+  // the batch is a multiple of it), every combination of the block-order bits
+  const int chunk_counts[] = {1, 2, 3, 5, 7, 8, 12, 16, 24, 27, 64, 125, 216, 512};
   const int groups[] = {1, 2, 3, 4, 5, 6, 8, 12, 16, 24, 32, 48, 64, 128};
   for (int nchunks : chunk_counts)
     for (int grp : groups)
       for (int mult : {1, 2, 3, 5, 8})
-        for (int flags = 0; flags < 4; ++flags) {
+        for (int flags = 0; flags < 8; ++flags) {
           const int nb = grp * mult;
           if ((long long)nb * nchunks > 4000000) continue;
           check_tiles(nb, nchunks, grp, flags);

@@ -205,7 +205,7 @@ def test_tuning_defaults_and_validation(hd):
     hd.set_tuning(op, step_presum=4, step_order=1, born_stage=16, born_blocks=1024)
     t = hd.get_tuning(op)
     assert (t["step_presum"], t["step_order"], t["born_stage"], t["born_blocks"]) == (4, 1, 16, 1024)
-    for bad in (dict(step_presum=3), dict(step_order=4), dict(step_group=-1), dict(born_stage=64),
+    for bad in (dict(step_presum=3), dict(step_order=5), dict(step_group=-1), dict(born_stage=64),
                 dict(born_blocks=100), dict(born_blocks=1 << 17), dict(step_vx=3), dict(step_vx=2, step_presum=2)):
         with pytest.raises(hd.HydotError) as e:
             hd.set_tuning(op, **bad)

@@ -39,8 +39,8 @@ def mixed_opts(hd):
 
 
 @pytest.mark.parametrize("presum,vx,order,group",
-                         [(p, 1, o, g) for p, o, g in itertools.product((1, 2, 4, 16), (1, 2, 3), (1, 2))] +
-                         [(4, 2, o, g) for o, g in itertools.product((1, 2, 3), (1, 2))])
+                         [(p, 1, o, g) for p, o, g in itertools.product((1, 2, 4, 16), (1, 2, 3, 4), (1, 2))] +
+                         [(4, 2, o, g) for o, g in itertools.product((1, 2, 3, 4), (1, 2))])
 def test_every_step_variant_meets_tolerance(hd, ragged, presum, vx, order, group):
     w, ref = ragged
     op = hd.Operator.from_workload(w)
@@ -121,16 +121,19 @@ def test_selective_second_pass_matches_full_cgs2(hd, ragged):
     assert abs(out[0].mean() - out[hd.FLAG_FULL_REORTH].mean()) <= 0.1 * out[hd.FLAG_FULL_REORTH].mean() + 2
 
 
+@pytest.mark.parametrize("presum", [4, 16])
 @pytest.mark.parametrize("group", [1, 2])
-def test_block_orders_give_identical_fields(hd, group):
+def test_block_orders_give_identical_fields(hd, group, presum):
     """The block order only changes which workgroup computes a (system, chunk) tile: the
     per-chunk partial sums and their reduction order are the same, so the fields must be
-    bitwise equal.  64 x 64 x 8 grid: 16 chunks, so the z-slab order permutes the chunks."""
+    bitwise equal.  64 x 64 x 8 grid: 16 chunks, so the z-slab order permutes the chunks and
+    the chunk-per-XCD order (4) puts the 5 wavelengths of each right-hand side at one chunk in
+    consecutive blocks of one XCD."""
     w = workloads.config("tiny", nx=64, ny=64, nz=8, n_lambda=5)
     out = []
-    for order in (2, 3, 1):
+    for order in (2, 3, 1, 4):
         op = hd.Operator.from_workload(w)
-        hd.set_tuning(op, step_presum=4, step_vx=1, step_order=order, step_group=group)
+        hd.set_tuning(op, step_presum=presum, step_vx=1, step_order=order, step_group=group)
         s = torch.cuda.Stream()
         with torch.cuda.stream(s):
             phi, it, rel, st = hd.solve_fields(op, w.rhs_voxels, mixed_opts(hd), out_dtype=torch.complex64,
