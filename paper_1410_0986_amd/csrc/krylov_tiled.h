@@ -140,6 +140,10 @@ __device__ inline Rsrc make_rsrc(const void* p, uint32_t bytes) {
 __device__ inline cf ld_cf(Rsrc r, uint32_t vo, uint32_t so) {
   return __builtin_bit_cast(cf, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
 }
+// non-temporal (streaming) form, for data read once per launch
+__device__ inline cf ld_cf_nt(Rsrc r, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(cf, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 2));
+}
 __device__ inline float ld_f(Rsrc r, uint32_t vo, uint32_t so) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
 }
@@ -193,6 +197,19 @@ template <int NV>
 __device__ inline void load_basis(const SysBuf& b, uint32_t vo8, int nv, cf* vr) {
 #pragma unroll
   for (int l = 0; l < NV; ++l) vr[l] = l < nv ? ld_cf(b.V, vo8, (uint32_t)l * b.sv) : cf{0.f, 0.f};
+}
+
+// Exactly NV basis vectors, V_0..V_{NV-2} streamed (read once per launch) and V_{NV-1} = V_j
+// cached (it is also the stencil operand, whose neighbours other threads read).
+template <int NV>
+__device__ inline void load_basis_stream(const SysBuf& b, uint32_t vo8, cf* vr) {
+#pragma unroll
+  for (int l = 0; l < NV; ++l)
+    vr[l] = l + 1 < NV ? ld_cf_nt(b.V, vo8, (uint32_t)l * b.sv) : ld_cf(b.V, vo8, (uint32_t)l * b.sv);
+}
+// non-temporal store of one complex FP32 value
+__device__ inline void st_cf_nt(cf* p, cf v) {
+  __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v), reinterpret_cast<unsigned long long*>(p));
 }
 
 // C and U of one voxel into registers: KM slots, the first k live (all KM when EXACT)
@@ -704,7 +721,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   float muv;
   auto fetch = [&](uint32_t n, bool first) {   // first: the chunk's first sub-tile
     const bool ok = n < (uint32_t)c.g.N;
-    load_basis<NV>(bf, ok ? n * 8u : kOutside, nv, vr);
+    load_basis_stream<NV>(bf, ok ? n * 8u : kOutside, vr);
     load_cu_k<KM, EX>(bf, k, ok ? n * 4u : kOutside, cr, ur);
     vinf = voxel_info(c.g, ok ? n : 0u);
     muv = mu_at(bf, ok ? n * 4u : kOutside);
@@ -740,7 +757,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
         if (bf.precond) wv[n] = w;
       } else {
         w = project_voxel_f<NV, KM, EX>(stencil ? w : wpre, vr, cr, ur, g, h, k, shr, shi);
-        vnext[n] = w;
+        st_cf_nt(vnext + n, w);
       }
 #pragma unroll
       for (int l = 0; l < NV; ++l) {
