@@ -64,17 +64,19 @@ WORKLOADS = {
 
 # Calibrated HBM bytes per dispatch of the Arnoldi step kernels (FETCH_SIZE x 2 + WRITE_SIZE, the
 # factors of a device copy of known size), keyed by workload.  They belong to the kernel sources
-# with this SHA-256 (common.h, krylov_kernels.h, krylov_tiled.h) and to the launch shape
+# with this SHA-256 (common.h, krylov_index.h, krylov_kernels.h, krylov_tiled.h) and to the launch shape
 # TRAFFIC_TUNING; after any change of either the traffic is reported as null.
-TRAFFIC_SOURCES_SHA256 = ""
-TRAFFIC_TUNING = {"step_presum": 16, "step_group": 2, "step_vx": 1, "step_order": 3}
-TRAFFIC_BYTES_PER_LAUNCH: dict = {}   # workload -> kernel -> calibrated HBM bytes per launch
+TRAFFIC_SOURCES_SHA256 = "a0d8adb794fb939981cdd2e7eb0dbf6586679d4602e4c22081b819ae7e4aac3e"
+TRAFFIC_TUNING = {"step_presum": 16, "step_group": 2, "step_vx": 1, "step_order": 4}
+TRAFFIC_BYTES_PER_LAUNCH: dict = {   # workload -> kernel -> calibrated HBM bytes per launch (main grid)
+    "large": {"k_step_update_t": 20785480003, "k_step_dots_t": 17780848181},
+}
 
 
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("common.h", "krylov_kernels.h", "krylov_tiled.h"):
+    for f in ("common.h", "krylov_index.h", "krylov_kernels.h", "krylov_tiled.h"):
         with open(os.path.join(ROOT, "paper_1410_0986_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -137,9 +139,9 @@ def main():
                     help="secondary measurements (heterogeneous forward, boundary/shift study, preconditioner, "
                          "compression, reconstruction) on the first shard")
     ap.add_argument("--no-profile-pass", action="store_true", help="skip the instrumented roofline pass")
-    ap.add_argument("--cpu-sample", type=int, default=1, help="systems in the CPU oracle sample")
-    ap.add_argument("--copy-gib", type=float, default=4.0,
-                    help="size of the device-to-device copy that measures HBM bandwidth (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=3, help="systems in the CPU oracle sample")
+    ap.add_argument("--peaks-gib", type=float, default=8.0,
+                    help="scratch of the peak probes (HBM streams, MFMA loops); 0: skip")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -308,24 +310,13 @@ def main():
             # the batched path's rate on the same grid (shard 0, every right-hand side)
             log("plain path done")
 
-    hbm = None
-    if args.copy_gib > 0:
-        nbytes = int(args.copy_gib * (1 << 30))
-        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
+    peaks = None
+    if args.peaks_gib > 0:
+        # achievable peaks from the library's probe kernels (HBM streams, read/write mix, MFMA loops)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            b.copy_(a)
-        e1.record()
-        e1.synchronize()
-        ms = e0.elapsed_time(e1) / 5
-        hbm = {"copy_bytes": nbytes, "ms": round(ms, 4), "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1),
-               "spec_GBps": HBM_PEAK_GBS}
-        del a, b
-        log("HBM copy done")
+        peaks = {k: (round(v, 1) if isinstance(v, float) else v) for k, v in hd.measure_peaks(dev, args.peaks_gib).items()}
+        peaks["buffer_gib"] = args.peaks_gib
+        log("peak probes done")
 
     elapsed = t1 - t0
     ms_step = 1e3 * elapsed / steps
@@ -346,6 +337,10 @@ def main():
             traffic = TRAFFIC_BYTES_PER_LAUNCH.get(args.config, {}).get(name)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
+                # the same achieved rate against the probes' measured streams: read-only, and the
+                # update kernel's own mix (ten vectors read, one written)
+                "frac_of_measured_read": round(achieved / peaks["read_GBps"], 4) if peaks else None,
+                "frac_of_measured_read10_write1": round(achieved / peaks["read10_write1_GBps"], 4) if peaks else None,
                 "kernel": name, "launches": launches, "avg_launch_ms": round(kms / max(launches, 1), 4),
                 "algorithmic_bytes_per_launch": kbytes / max(launches, 1),
                 "source": "instrumented pass: one main-grid shard solve, HIP events on the solve stream",
@@ -356,11 +351,15 @@ def main():
     born_roof = {
         "jv_fp32": {"ms": round(jv_ms, 4), "tflops": round(jv_flops / (jv_ms * 1e-3) / 1e12, 2),
                     "mfma_frac_fp32": round(jv_flops / (jv_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+                    "mfma_frac_of_measured_fp32": round(jv_flops / (jv_ms * 1e-3) / 1e12 / peaks["mfma_f32_TFLOPs"], 4)
+                    if peaks else None,
                     "field_GBps": round(field_bytes / (jv_ms * 1e-3) / 1e9, 1),
                     "hbm_frac": round(field_bytes / (jv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "flop_convention": "8*S*D*N*L complex MACs (no 3M credit)"},
         "jhw_fp32": {"ms": round(jhw_ms, 4), "tflops": round(jv_flops / (jhw_ms * 1e-3) / 1e12, 2),
                      "mfma_frac_fp32": round(jv_flops / (jhw_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+                     "mfma_frac_of_measured_fp32": round(jv_flops / (jhw_ms * 1e-3) / 1e12 / peaks["mfma_f32_TFLOPs"], 4)
+                     if peaks else None,
                      "field_GBps": round(field_bytes / (jhw_ms * 1e-3) / 1e9, 1),
                      "hbm_frac": round(field_bytes / (jhw_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
@@ -397,7 +396,7 @@ def main():
         "plain_fp64": plain,
         "speedup_vs_plain": round(per_grid[f"{w.nx}x{w.ny}x{w.nz}"] / plain["solves_per_s"], 2) if plain else None,
         "roofline": roof,
-        "hbm_copy_measured": hbm,
+        "peaks_measured": peaks,
         "peaks_spec": {"hbm_GBps": HBM_PEAK_GBS, "fp32_tflops": FP32_PEAK_TFLOPS, "fp64_tflops": FP64_PEAK_TFLOPS,
                        "bf16_tflops": BF16_PEAK_TFLOPS},
         "tuning": {**hd.get_tuning(ops[0]), "autotuned": bool(args.autotune), "solve_candidates": len(solve_trials),
@@ -440,7 +439,8 @@ def born_variants(hd, torch, np, workloads, w, w_shard, phi, v, dev, timed):
             needed = (4.0 * S * D * N * L2 * n_v if pairs else useful) * (3 if split else 1)
             err = float(torch.linalg.vector_norm(y.to(torch.complex128) - ref) / torch.linalg.vector_norm(ref))
             out[f"{name}_nv{nv}"] = {
-                "kernel": "k_born_jv_pairs" if pairs else "k_born_jv", "ms": round(ms, 4),
+                "kernel": ("k_born_jv_pairs" if pairs else "k_born_jv_wide" if name == "fp32" and S > 32 and D > 32
+                           else "k_born_jv"), "ms": round(ms, 4),
                 "tflops_8SDNL_convention": round(useful / (ms * 1e-3) / 1e12, 2),
                 "mfma_tflops_needed": round(needed / (ms * 1e-3) / 1e12, 2),
                 "mfma_frac_needed": round(needed / (ms * 1e-3) / 1e12 / peak, 4),

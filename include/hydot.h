@@ -260,6 +260,21 @@ hydot_status hydot_born_apply_ex(const hydot_operator* op, const void* phi_src, 
                                  int32_t n_v, void* y, void* workspace, size_t ws_bytes,
                                  hipStream_t stream);
 
+/* Measurement hook: achievable peaks of the current GPU from hand-written probe kernels, for
+ * stating rooflines against measured figures beside the published ones (HBM 8 TB/s, FP32 MFMA
+ * 157.3 TFLOP/s, BF16 MFMA 2.5 PFLOP/s dense).  buffer: device, 256-byte aligned, at least 1 GiB
+ * (caller-owned scratch; its contents are overwritten).  Streams: ten vectors read with
+ * non-temporal loads (read_GBps), a copy (copy_GBps, read + write bytes), ten vectors read and
+ * one written (read10_write1_GBps: the traffic mix of an Arnoldi update); MFMA: independent chains
+ * of v_mfma_f32_32x32x2f32 and v_mfma_f32_16x16x32_bf16 with operands in registers.  Each figure
+ * is the median of five timed launches.  Synchronises the stream. */
+typedef struct {
+  double read_GBps, copy_GBps, read10_write1_GBps;
+  double mfma_f32_TFLOPs, mfma_bf16_TFLOPs;
+  int32_t compute_units;
+} hydot_peaks;
+hydot_status hydot_measure_peaks(void* buffer, size_t bytes, hydot_peaks* out, hipStream_t stream);
+
 /* Allocation-free J v, for callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): the same products, kernels and
  * arguments as hydot_born_apply_ex, without the workspace.  The FP64 partial sums live in a

@@ -29,6 +29,7 @@ from ._binding import (  # noqa: F401
     version,
     profile_enable,
     profile_read,
+    measure_peaks,
     get_tuning,
     set_tuning,
     autotune_solve,

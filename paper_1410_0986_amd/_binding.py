@@ -101,6 +101,14 @@ _misfit = _proto("hydot_misfit", c_int32, c_void_p, c_int32, c_int32, POINTER(c_
                  c_void_p, c_int32, c_void_p, POINTER(c_double), POINTER(c_double), c_void_p, c_size_t, c_void_p)
 
 
+class _Peaks(ctypes.Structure):
+    _fields_ = [("read_GBps", c_double), ("copy_GBps", c_double), ("read10_write1_GBps", c_double),
+                ("mfma_f32_TFLOPs", c_double), ("mfma_bf16_TFLOPs", c_double), ("compute_units", c_int32)]
+
+
+_peaks = _proto("hydot_measure_peaks", c_int32, c_void_p, c_size_t, POINTER(_Peaks), c_void_p)
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [("step_presum", c_int32), ("step_order", c_int32), ("step_group", c_int32),
                 ("born_stage", c_int32), ("born_blocks", c_int32), ("step_vx", c_int32)]
@@ -646,3 +654,14 @@ class BornMisfit(torch.autograd.Function):
         gp = pals_shape_vjp(ctx.op, ctx.pn, g, ctx.popts)
         s = float(gf)
         return (torch.from_numpy(s * ctx.gdc), torch.from_numpy(s * gp), None, None, None, None, None, None)
+
+
+def measure_peaks(device="cuda", gib: float = 8.0) -> dict:
+    """Achievable peaks of the GPU from the library's probe kernels (hydot_measure_peaks), on a
+    scratch buffer of `gib` GiB."""
+    nbytes = int(gib * (1 << 30))
+    buf, ptr = _ws(nbytes, device)
+    out = _Peaks()
+    _check(_peaks(c_void_p(ptr), c_size_t(nbytes), ctypes.byref(out), _stream(device)))
+    del buf
+    return {f: getattr(out, f) for f, _ in _Peaks._fields_}

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhydot.so")
-SOURCES = ["operator.hip", "krylov.hip", "born.hip", "pals.hip"]
+SOURCES = ["operator.hip", "krylov.hip", "born.hip", "pals.hip", "peaks.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

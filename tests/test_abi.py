@@ -295,3 +295,16 @@ def test_solve_inspect_validates(hd):
     o2 = nr._c()
     need2 = hd.solve_workspace_bytes(op, 8, nr)
     assert f(op.handle, 8, ctypes.byref(o2), fake, need2, B.INSPECT_U, 0, None, 0, ctypes.byref(info), None) == hd.EINVAL
+
+
+def test_measure_peaks_validates_before_launch(hd):
+    lib = _raw(hd)
+    f = lib.hydot_measure_peaks
+    f.restype = ctypes.c_int32
+    f.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
+    out = hd._binding._Peaks()
+    fake = ctypes.c_void_p(0x7F0000000000)
+    assert f(None, 1 << 31, ctypes.byref(out), None) == hd.EINVAL                         # null buffer
+    assert f(fake, 1 << 31, None, None) == hd.EINVAL                                      # null output
+    assert f(ctypes.c_void_p(0x7F0000000010), 1 << 31, ctypes.byref(out), None) == hd.EINVAL   # misaligned
+    assert f(fake, (1 << 30) - 256, ctypes.byref(out), None) == hd.EINVAL                 # under 1 GiB
