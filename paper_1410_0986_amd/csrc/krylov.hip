@@ -15,6 +15,7 @@
 #include "krylov_kernels.h"
 #include "krylov_tiled.h"
 #include "lanczos.h"
+#include "lanczos_tiled.h"
 #include "precond.h"
 #include "operator.h"
 #include "small_dense.h"
@@ -310,6 +311,7 @@ hydot_status make_plan(const hydot_operator* op, int n_rhs, const hydot_solve_op
 struct RhsSetup {
   std::vector<double> Hbar;   // (nl+1) x nl
   std::vector<double> gram;   // npairs
+  std::vector<double> vs;     // scales of the stored Lanczos vectors: v_l = vs[l] * V_l (nl+1)
 };
 
 struct Solver {
@@ -454,13 +456,45 @@ struct Solver {
     lc.mkmax = p.mkmax;
     const dim3 gv(p.nchunks, nr);
     hipLaunchKernelGGL(k_lz_v0<T>, gv, dim3(kBlock), 0, stream, lc, c.small);
+    // FP32 basis: chunk-accumulating kernels while the basis fits their registers and one buffer
+    // resource (below 2 GiB per right-hand side); the generic kernels otherwise
+    const bool tiled = std::is_same<T, float>::value && (size_t)lc.vdim * p.N * sizeof(float) < ((size_t)1 << 31);
     for (int j = 0; j < p.nl; ++j) {
-      hipLaunchKernelGGL(k_lz_dots<T>, gv, dim3(kBlock), 0, stream, lc, j);
+      const int nv = j + 1;
+      if constexpr (std::is_same<T, float>::value) {
+        if (tiled && nv <= kLzTiledMax) lz_tiled(0, lc, j, gv);
+        else hipLaunchKernelGGL(k_lz_dots<T>, gv, dim3(kBlock), 0, stream, lc, j);
+      } else {
+        hipLaunchKernelGGL(k_lz_dots<T>, gv, dim3(kBlock), 0, stream, lc, j);
+      }
       hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_A, j);
-      hipLaunchKernelGGL(k_lz_update<T>, gv, dim3(kBlock), 0, stream, lc, j);
+      if constexpr (std::is_same<T, float>::value) {
+        if (tiled && nv <= kLzTiledMax) lz_tiled(1, lc, j, gv);
+        else hipLaunchKernelGGL(k_lz_update<T>, gv, dim3(kBlock), 0, stream, lc, j);
+      } else {
+        hipLaunchKernelGGL(k_lz_update<T>, gv, dim3(kBlock), 0, stream, lc, j);
+      }
       hipLaunchKernelGGL(k_reduce<cd>, dim3(nr), dim3(64), 0, stream, c, ra, (int)PH_STEP_B, j);
       hipLaunchKernelGGL(k_lz_finish<T>, gv, dim3(kBlock), 0, stream, lc, j);
     }
+  }
+  // chunk-accumulating Lanczos launch (kind 0: dots, 1: update): the instance with exactly the
+  // j + 1 basis vectors up to 16, the next multiple of 4 beyond
+  void lz_tiled(int kind, const LzCtx<float>& lc, int j, dim3 gv) {
+    const int nv = j + 1;
+#define HYDOT_LZ_T(NV)                                                                            \
+  case NV:                                                                                        \
+    if (kind == 0) hipLaunchKernelGGL((k_lz_dots_t<NV>), gv, dim3(kTSub), 0, stream, lc, j);      \
+    else hipLaunchKernelGGL((k_lz_update_t<NV>), gv, dim3(kTSub), 0, stream, lc, j);              \
+    break;
+    switch (nv <= 16 ? nv : (nv + 3) / 4 * 4) {
+      HYDOT_LZ_T(1) HYDOT_LZ_T(2) HYDOT_LZ_T(3) HYDOT_LZ_T(4) HYDOT_LZ_T(5) HYDOT_LZ_T(6) HYDOT_LZ_T(7)
+      HYDOT_LZ_T(8) HYDOT_LZ_T(9) HYDOT_LZ_T(10) HYDOT_LZ_T(11) HYDOT_LZ_T(12) HYDOT_LZ_T(13) HYDOT_LZ_T(14)
+      HYDOT_LZ_T(15) HYDOT_LZ_T(16) HYDOT_LZ_T(20) HYDOT_LZ_T(24) HYDOT_LZ_T(28) HYDOT_LZ_T(32) HYDOT_LZ_T(36)
+      HYDOT_LZ_T(40) HYDOT_LZ_T(44) HYDOT_LZ_T(48) HYDOT_LZ_T(52) HYDOT_LZ_T(56) HYDOT_LZ_T(60)
+      default: break;
+    }
+#undef HYDOT_LZ_T
   }
 
   // Shift-invariant Krylov basis of K_hat for right-hand sides [r0, r0+nr) (Alg. 1 step 1),
@@ -491,6 +525,10 @@ struct Solver {
     ra.mk = nl;
     ra.lanczos = 1;
     ra.max_iter = 1 << 30;
+    // FP32 basis: the second Gram-Schmidt pass only where the first leaves a projection above
+    // 1e-6 of the vector (C = V_{n+1} Q inherits the basis' orthogonality, so the bar is tighter
+    // than the Arnoldi one); a skipped pass leaves V_{j+1} unnormalised with its scale recorded
+    ra.cgs_tau = p.prec == HYDOT_PREC_MIXED && !(o->flags & HYDOT_FLAG_FULL_REORTH) ? 1e-6 : 0.0;
     if (p.prec == HYDOT_PREC_MIXED) lanczos_run<float>(c, ra, nr);
     else lanczos_run<double>(c, ra, nr);
     HYDOT_HIP(hipGetLastError());
@@ -511,6 +549,9 @@ struct Solver {
       const cd* H = smalls.data() + (size_t)i * p.sl.total + p.sl.H;
       for (int jj = 0; jj < nl; ++jj)
         for (int ii = 0; ii <= std::min(jj + 1, nl); ++ii) R.Hbar[ii + (size_t)(nl + 1) * jj] = H[ii + ldh * jj].re;
+      const cd* vsc = smalls.data() + (size_t)i * p.sl.total + p.sl.vs;
+      R.vs.resize((size_t)nl + 1);
+      for (int l = 0; l <= nl; ++l) R.vs[l] = vsc[l].re;
       if (k == 0) return true;
       std::vector<double> Zk, th;
       if (!dense::harmonic_ritz(nl, k, R.Hbar, Zk, th)) return false;
@@ -531,11 +572,12 @@ struct Solver {
           for (int q = 0; q < cc; ++q) s -= ZY[rr + (size_t)nl * q] * Y[q + (size_t)k * cc];
           ZY[rr + (size_t)nl * cc] = s / Y[cc + (size_t)k * cc];
         }
+      // coefficients of the stored vectors V_l (v_l = vs[l] V_l)
       double* uc = ucoef.data() + (size_t)i * (nl + 1) * 2 * k;
       for (int l = 0; l <= nl; ++l)
         for (int cc = 0; cc < k; ++cc) {
-          uc[l * 2 * k + cc] = l < nl ? ZY[l + (size_t)nl * cc] : 0.0;
-          uc[l * 2 * k + k + cc] = Qs[l + (size_t)(nl + 1) * cc];
+          uc[l * 2 * k + cc] = l < nl ? R.vs[l] * ZY[l + (size_t)nl * cc] : 0.0;
+          uc[l * 2 * k + k + cc] = R.vs[l] * Qs[l + (size_t)(nl + 1) * cc];
         }
       return true;
     });
@@ -756,7 +798,12 @@ struct Solver {
       if (p.nl > 0) {
         std::vector<dense::zc> y;
         dense::shifted_ls(p.nl, rs[r].Hbar, dense::zc(q.sig.re, q.sig.im), 1.0, y);
-        for (int t = 0; t < p.nl; ++t) dst[p.k * p.k + t] = cd{y[t].real(), y[t].imag()};
+        // coefficients of the stored Lanczos vectors (v_l = vs[l] V_l)
+        const std::vector<double>& vsc = rs[r].vs;
+        for (int t = 0; t < p.nl; ++t) {
+          const double sc = t < (int)vsc.size() ? vsc[t] : 1.0;
+          dst[p.k * p.k + t] = cd{sc * y[t].real(), sc * y[t].imag()};
+        }
       }
       return true;
     });

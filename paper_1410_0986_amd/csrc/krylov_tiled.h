@@ -331,17 +331,19 @@ __device__ inline void stencil_y_from_tile(const GridP& g, const VoxelInfo& vi, 
 }
 
 // (A_hat x)_n from gathered operands: the same arithmetic as apply_op.
+// K's diagonal at a voxel: one per interior neighbour, two per Dirichlet face; the exterior faces
+// are the Robin plus the Dirichlet ones, so nn + 2 ndir = 6 - nrobin + ndir.
+__device__ inline float diag_k_of(const VoxelInfo& vi) { return (float)(6 - vi.nrobin + vi.ndir); }
+
 __device__ inline cf stencil_apply(const GridP& g, const StencilRegs& sr, const VoxelInfo& vi, cd sig,
                                    double sigp, double extra) {
-  const int nn = 6 - (vi.i == 0) - (vi.i == g.nx - 1) - (vi.j == 0) - (vi.j == g.ny - 1) - (vi.k == 0) -
-                 (vi.k == g.nz - 1);
   float ar = 0.f, ai = 0.f;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     ar -= sr.m[f].re;
     ai -= sr.m[f].im;
   }
-  const float diag_k = (float)(nn + 2 * vi.ndir);
+  const float diag_k = diag_k_of(vi);
   const float ih2 = (float)g.inv_h2;
   const float dr = (float)(sig.re + sigp * (double)vi.nrobin * g.inv_h + extra);
   const float di = (float)sig.im;
@@ -359,23 +361,27 @@ __device__ inline SysF sys_f(const GridP& g, const SysParam& p) {
   return SysF{(float)p.sig.re, (float)p.sig.im, (float)(p.sigp_abs * g.inv_h), (float)(p.sigp_rel * g.inv_h),
               (float)p.tau_abs, (float)p.tau_rel};
 }
-__device__ inline cf stencil_apply_f(const GridP& g, const StencilRegs& sr, const VoxelInfo& vi, const SysF& q,
-                                     float mu) {
-  const int nn = 6 - (vi.i == 0) - (vi.i == g.nx - 1) - (vi.j == 0) - (vi.j == g.ny - 1) - (vi.k == 0) -
-                 (vi.k == g.nz - 1);
+// s (A_hat x)_n with the stencil constants pre-multiplied by the basis scale s (ScaledOp), so the
+// stored basis vector V_j gives v_j = s V_j's image directly.
+struct ScaledOp {
+  float ih2, sig_re, sig_im, sigp_abs_h, tau_abs;
+};
+__device__ inline ScaledOp scaled_op(const GridP& g, const SysF& q, float s) {
+  return ScaledOp{(float)g.inv_h2 * s, q.sig_re * s, q.sig_im * s, q.sigp_abs_h * s, q.tau_abs * s};
+}
+__device__ inline cf stencil_apply_f(const StencilRegs& sr, const VoxelInfo& vi, const ScaledOp& o, float mu) {
   float ar = 0.f, ai = 0.f;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     ar -= sr.m[f].re;
     ai -= sr.m[f].im;
   }
-  const float diag_k = (float)(nn + 2 * vi.ndir);
-  const float ih2 = (float)g.inv_h2;
-  const float dr = q.sig_re + q.sigp_abs_h * (float)vi.nrobin + q.tau_abs * mu;
-  const float di = q.sig_im;
+  const float diag_k = diag_k_of(vi);
+  const float dr = o.sig_re + o.sigp_abs_h * (float)vi.nrobin + o.tau_abs * mu;
+  const float di = o.sig_im;
   const cf xc = sr.xc;
-  return cf{ih2 * (diag_k * xc.re + ar) + (dr * xc.re - di * xc.im),
-            ih2 * (diag_k * xc.im + ai) + (dr * xc.im + di * xc.re)};
+  return cf{o.ih2 * (diag_k * xc.re + ar) + (dr * xc.re - di * xc.im),
+            o.ih2 * (diag_k * xc.im + ai) + (dr * xc.im + di * xc.re)};
 }
 // w - C'g - sum_l h_l V_l with the per-voxel C' shift (sr, si) in FP32 (KM slots of C, U and g,
 // the first k live; all KM when EXACT)
@@ -713,6 +719,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   const bool ytile = stencil && c.g.nx <= kTSub;   // y neighbours in this or the previous sub-tile
   const float sj = stencil ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
   const SysF q = sys_f(c.g, p);
+  const ScaledOp qs = scaled_op(c.g, q, sj);   // v_j = sj * stored V_j
   cf vr[NV];
   float cr[KM], ur[KM];
   cf wpre{0.f, 0.f};
@@ -733,11 +740,11 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
       wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
     }
   };
-  cf av[NV], ac[KM], an{0.f, 0.f};
+  cf av[NV], ac[KM], au[KM], an{0.f, 0.f};
 #pragma unroll
   for (int l = 0; l < NV; ++l) av[l] = cf{0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < KM; ++i) ac[i] = cf{0.f, 0.f};
+  for (int i = 0; i < KM; ++i) ac[i] = au[i] = cf{0.f, 0.f};
   fetch(ti.chunk * kChunk + t, true);
   for (int sub = 0; sub < nsub; ++sub) {
     const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
@@ -748,11 +755,7 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
       // C' shift of this voxel: sigma + sigma'_rel rho + tau_rel mu
       const float shr = q.sig_re + q.sigp_rel_h * (float)vinf.nrobin + q.tau_rel * muv, shi = q.sig_im;
       cf w{0.f, 0.f};
-      if (stencil) {
-        w = stencil_apply_f(c.g, sreg, vinf, q, muv);
-        w.re *= sj;   // v_j = sj * stored V_j
-        w.im *= sj;
-      }
+      if (stencil) w = stencil_apply_f(sreg, vinf, qs, muv);
       if (KIND == 0) {
         if (bf.precond) wv[n] = w;
       } else {
@@ -765,13 +768,17 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
         av[l].re += v.re * w.re + v.im * w.im;
         av[l].im += v.re * w.im - v.im * w.re;
       }
-      const float sr = shr, si = -shi;   // conj(shift)
+      // conj(C'_i) w = (C_i + Re(shift) U_i) w - i Im(shift) U_i w with C, U real and Im(shift)
+      // uniform: two real-times-complex sums per row here, the imaginary shift applied once per
+      // chunk below
 #pragma unroll
       for (int i = 0; i < KM; ++i)
         if (EX || i < k) {
-          const float ar = cr[i] + sr * ur[i], ai = si * ur[i];
-          ac[i].re += ar * w.re - ai * w.im;
-          ac[i].im += ar * w.im + ai * w.re;
+          const float a = __builtin_fmaf(shr, ur[i], cr[i]);
+          ac[i].re = __builtin_fmaf(a, w.re, ac[i].re);
+          ac[i].im = __builtin_fmaf(a, w.im, ac[i].im);
+          au[i].re = __builtin_fmaf(ur[i], w.re, au[i].re);
+          au[i].im = __builtin_fmaf(ur[i], w.im, au[i].im);
         }
       if (with_norm) an.re += w.re * w.re + w.im * w.im;
     }
@@ -780,9 +787,10 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   // one block reduction per chunk: rows [0, nv) V, [nv, nv + k) C', nv + k the norm
 #pragma unroll
   for (int l = 0; l < NV; ++l) put_product<4>(pt, l, av[l]);
+  const float shi = q.sig_im;
 #pragma unroll
   for (int i = 0; i < KM; ++i)
-    if (EX || i < k) put_product<4>(pt, nv + i, ac[i]);
+    if (EX || i < k) put_product<4>(pt, nv + i, cf{ac[i].re + shi * au[i].im, ac[i].im - shi * au[i].re});
   if (with_norm) put_product<4>(pt, nv + k, an);
   __syncthreads();
   cd acc{0.0, 0.0};
