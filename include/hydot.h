@@ -374,7 +374,7 @@ hydot_status hydot_misfit(const hydot_operator* op, int32_t S, int32_t D, const 
  *                product tile of every 128-voxel sub-tile; 2 and 4 shrink the tile so more
  *                blocks fit a CU; 16: each thread sums the terms of its 16 voxels of the chunk
  *                in registers and the block reduces once per chunk (instances up to 16 basis
- *                vectors; beyond, 4 is used) (default 16).
+ *                vectors and x rows of at most 128 voxels; otherwise 4 is used) (default 16).
  *   step_order   1: blocks ordered so each XCD runs a contiguous range of (system, chunk) tiles;
  *                2: plain dispatch order; 3: z-slab order, each XCD runs a contiguous range of
  *                chunks (a slab of z-planes) of every system, so the stencil's z-neighbour

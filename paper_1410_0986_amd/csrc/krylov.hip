@@ -651,6 +651,8 @@ struct Solver {
         const int fl = step_flags(tu);
         const bool small = j + 1 <= 16;
         const bool plain = c.mu == nullptr && c.Z == nullptr;
+        // the chunk-accumulating instances take x rows of at most one sub-tile
+        const bool rows_fit = op->gp.nx <= kTSub;
 #define HYDOT_STEP_T(KER, NV, P) hipLaunchKernelGGL((KER<NV, P, 1>), gt, dim3(kTSub), 0, stream, c, j, grp, fl)
 // the chunk-accumulating instances come with exact deflation dimensions k = 5 and 10
 // (k = 5 also without a perturbation or preconditioner, the plain instances)
@@ -660,7 +662,7 @@ struct Solver {
   else if (c.k == 10) hipLaunchKernelGGL((KER<NV, 16, 1, 10>), gt, dim3(kTSub), 0, stream, c, j, grp, fl);    \
   else HYDOT_STEP_T(KER, NV, 16);
 #define HYDOT_STEP_P(KER, NV)                                                                           \
-  if (tu.step_presum == 16 && NV <= 16) { HYDOT_STEP_T16(KER, NV) }                                     \
+  if (tu.step_presum == 16 && NV <= 16 && rows_fit) { HYDOT_STEP_T16(KER, NV) }                         \
   else if (tu.step_presum == 4 && tu.step_vx == 2 && NV <= 16)                                          \
     hipLaunchKernelGGL((KER<NV, 4, (NV <= 16 ? 2 : 1)>), gt, dim3(kTSub), 0, stream, c, j, grp, fl);   \
   else if (tu.step_presum == 4 || tu.step_presum == 16) HYDOT_STEP_T(KER, NV, 4);                       \

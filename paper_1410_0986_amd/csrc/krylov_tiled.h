@@ -694,7 +694,9 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   constexpr bool EX = KX > 0;
   constexpr int KM = EX ? KX : kTK;
   __shared__ ProdTile<4> pt;
-  __shared__ cf xs[3][kTSub];   // centres of the last sub-tiles, for the y neighbours
+  // Stencil centres of four consecutive sub-tiles (rotating): the previous, the current and the
+  // next one are read, the fourth is being overwritten, so one barrier per sub-tile suffices.
+  __shared__ cf xs[4][kTSub];
   const int sys = ti.sys;
   const size_t N = (size_t)c.g.N;
   const int k = EX ? KX : c.k, nv = NV, t = threadIdx.x;
@@ -716,41 +718,91 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   const SysBuf bf = PL ? sys_buf_plain(c, sys, p.rhs) : sys_buf(c, sys, p.rhs);
   cf* vnext = c.V + ((size_t)sys * c.vdim + j + 1) * N;
   const bool stencil = KIND == 0 || !bf.precond;
-  const bool ytile = stencil && c.g.nx <= kTSub;   // y neighbours in this or the previous sub-tile
+  // x rows of at most one sub-tile (the host routes longer rows to the other instances): every
+  // face neighbour but the z ones is the centre of a voxel in this, the previous or the next
+  // sub-tile, so the centres go through LDS (each loaded once, one sub-tile ahead) and only the z
+  // neighbours are loaded
+  const bool ytile = stencil;
+  const bool vj_centre = ytile && !bf.precond;   // V_j's register value is the stencil centre
+  const uint32_t so = bf.precond ? 0u : (uint32_t)j * bf.sv;   // stencil source: V_j or P^{-1} V_j
+  const uint32_t Nu = (uint32_t)c.g.N, sz = (uint32_t)c.g.nx * (uint32_t)c.g.ny;
   const float sj = stencil ? (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re : 1.f;
   const SysF q = sys_f(c.g, p);
   const ScaledOp qs = scaled_op(c.g, q, sj);   // v_j = sj * stored V_j
   cf vr[NV];
   float cr[KM], ur[KM];
   cf wpre{0.f, 0.f};
+  cf c_ahead{0.f, 0.f};   // centre of the sub-tile after the one last fetched (published next)
   StencilRegs sreg;
   VoxelInfo vinf;
   float muv;
   auto fetch = [&](uint32_t n, bool first) {   // first: the chunk's first sub-tile
-    const bool ok = n < (uint32_t)c.g.N;
-    load_basis_stream<NV>(bf, ok ? n * 8u : kOutside, vr);
+    const bool ok = n < Nu;
+    if (vj_centre) {
+      // V_0..V_{NV-2} streamed; V_j comes with the centres
+#pragma unroll
+      for (int l = 0; l + 1 < NV; ++l) vr[l] = ld_cf_nt(bf.V, ok ? n * 8u : kOutside, (uint32_t)l * bf.sv);
+    } else {
+      load_basis_stream<NV>(bf, ok ? n * 8u : kOutside, vr);
+    }
     load_cu_k<KM, EX>(bf, k, ok ? n * 4u : kOutside, cr, ur);
     vinf = voxel_info(c.g, ok ? n : 0u);
     muv = mu_at(bf, ok ? n * 4u : kOutside);
-    if (stencil) {
-      gather_stencil_yz(c.g, bf.S, bf.precond ? 0u : (uint32_t)j * bf.sv, n, ok, vinf, sreg, bf.precond,
-                        ytile && (t >= c.g.nx || !first), ytile && t + c.g.nx < kTSub);
-      if (!bf.precond) sreg.xc = vr[NV - 1];
+    if (ytile) {
+      sreg.m[4] = ld_cf(bf.S, ok && vinf.k > 0 ? (n - sz) * 8u : kOutside, so);
+      sreg.m[5] = ld_cf(bf.S, ok && vinf.k < c.g.nz - 1 ? (n + sz) * 8u : kOutside, so);
+      const uint32_t na = n + kTSub;   // centre of the sub-tile after the one being fetched
+      c_ahead = ld_cf(bf.S, na < Nu ? na * 8u : kOutside, so);
     } else {
       wpre = ld_cf(bf.W, ok ? n * 8u : kOutside, 0u);
     }
+    (void)first;
   };
   cf av[NV], ac[KM], au[KM], an{0.f, 0.f};
 #pragma unroll
   for (int l = 0; l < NV; ++l) av[l] = cf{0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < KM; ++i) ac[i] = au[i] = cf{0.f, 0.f};
-  fetch(ti.chunk * kChunk + t, true);
+  const uint32_t n0 = (uint32_t)ti.chunk * kChunk;
+  if (ytile) {
+    // the centres of the sub-tile before the chunk and of its first sub-tile
+    const uint32_t nm = n0 + (uint32_t)t - kTSub, nc = n0 + (uint32_t)t;
+    xs[3][t] = ld_cf(bf.S, n0 >= (uint32_t)kTSub && nm < Nu ? nm * 8u : kOutside, so);
+    xs[0][t] = ld_cf(bf.S, nc < Nu ? nc * 8u : kOutside, so);
+  }
+  fetch(n0 + t, true);
   for (int sub = 0; sub < nsub; ++sub) {
-    const uint32_t n = ti.chunk * kChunk + sub * kTSub + t;
-    const bool ok = n < (uint32_t)c.g.N;
+    const uint32_t n = n0 + sub * kTSub + t;
+    const bool ok = n < Nu;
+    if (ytile) {
+      xs[(sub + 1) & 3][t] = c_ahead;   // the next sub-tile's centres
+      __syncthreads();
+      // rows of the previous, current and next sub-tile (indices into xs, no LDS pointers)
+      const int bp = (sub + 3) & 3, bc = sub & 3, bn = (sub + 1) & 3;
+      const int nxg = c.g.nx, lane = t & 63;
+      sreg.xc = xs[bc][t];
+      if (vj_centre) vr[NV - 1] = sreg.xc;
+      // neighbour positions in the ring (row, index), then value selects (selects between LDS
+      // and register objects would go through generic pointers)
+      const int ym = t - nxg, yp = t + nxg;
+      const cf vym = xs[ym >= 0 ? bc : bp][ym >= 0 ? ym : ym + kTSub];
+      const cf vyp = xs[yp < kTSub ? bc : bn][yp < kTSub ? yp : yp - kTSub];
+      const bool hy0 = vinf.j > 0, hy1 = vinf.j < c.g.ny - 1;
+      sreg.m[2] = cf{hy0 ? vym.re : 0.f, hy0 ? vym.im : 0.f};
+      sreg.m[3] = cf{hy1 ? vyp.re : 0.f, hy1 ? vyp.im : 0.f};
+      // x neighbours of the wave's edge lanes (the inner lanes take theirs by DPP below)
+      if (lane == 0) {
+        const cf v = xs[t > 0 ? bc : bp][t > 0 ? t - 1 : kTSub - 1];
+        const bool hx = vinf.i > 0;
+        sreg.m[0] = cf{hx ? v.re : 0.f, hx ? v.im : 0.f};
+      }
+      if (lane == 63) {
+        const cf v = xs[t + 1 < kTSub ? bc : bn][t + 1 < kTSub ? t + 1 : 0];
+        const bool hx = vinf.i < nxg - 1;
+        sreg.m[1] = cf{hx ? v.re : 0.f, hx ? v.im : 0.f};
+      }
+    }
     if (stencil) stencil_x_from_lanes(c.g, vinf, sreg);   // every lane (no divergence yet)
-    if (ytile) stencil_y_from_tile(c.g, vinf, sreg, xs[sub % 3], xs[(sub + 2) % 3], sub > 0, t);
     if (ok) {
       // C' shift of this voxel: sigma + sigma'_rel rho + tau_rel mu
       const float shr = q.sig_re + q.sigp_rel_h * (float)vinf.nrobin + q.tau_rel * muv, shi = q.sig_im;

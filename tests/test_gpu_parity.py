@@ -109,13 +109,14 @@ def test_solve_mixed_precision(hd):
     _check_fields(w, phi64.cpu().numpy(), rel, 1e-6, 1e-8, ref)
 
 
-@pytest.mark.parametrize("dims", [(150, 5, 4), (128, 6, 4), (40, 7, 6)])
+@pytest.mark.parametrize("dims", [(150, 5, 4), (128, 6, 4), (40, 7, 6), (64, 9, 5), (3, 5, 40)])
 @pytest.mark.parametrize("k", [5, 6])
 def test_solve_mixed_row_lengths(hd, dims, k):
-    """The step kernels take x neighbours from the adjacent lanes and y neighbours from LDS rows
-    of the block's centres when an x row fits a 128-voxel sub-tile: rows longer than a sub-tile
-    (150), exactly one (128) and rows straddling waves (40), with the exact-k (5) and the
-    runtime-k (6) instances."""
+    """The step kernels take x neighbours from the adjacent lanes and, when an x row fits a
+    128-voxel sub-tile, the stencil centres from a ring of four sub-tiles in LDS (loaded one
+    sub-tile ahead): rows longer than a sub-tile (150, other instances), exactly one (128), rows
+    straddling waves (40), one row per wave (64) and many rows per sub-tile (3, whose y
+    neighbours cross sub-tiles), with the exact-k (5) and the runtime-k (6) instances."""
     nx, ny, nz = dims
     w = workloads.config("tiny", nx=nx, ny=ny, nz=nz, n_lambda=3)
     op = hd.Operator.from_workload(w)
