@@ -42,11 +42,12 @@ def test_shift_variants_fp64(hd, case, shift):
     assert normwise(phi.cpu().numpy(), ref).max() < 1e-8
 
 
-@pytest.mark.parametrize("shift", ["mean", "max"])
+@pytest.mark.parametrize("shift", ["mean", "max", "min", "none"])
 def test_shift_variants_mixed(hd, case, shift):
     w, ref = case
     op = hd.Operator.from_workload(w)
-    fl = {"mean": hd.FLAG_MEAN_SHIFT, "max": hd.FLAG_SHIFT_MAX}[shift] | hd.FLAG_GRAPH
+    fl = {"mean": hd.FLAG_MEAN_SHIFT, "max": hd.FLAG_SHIFT_MAX, "min": hd.FLAG_SHIFT_MIN, "none": 0}[shift]
+    fl |= hd.FLAG_GRAPH
     o = hd.SolveOptions(rel_tol=1e-8, restart_m=18, recycle_k=5, lanczos_n=24, precision=hd.PREC_MIXED,
                         inner_tol=1e-5, flags=fl)
     s = torch.cuda.Stream()

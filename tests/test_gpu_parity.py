@@ -191,6 +191,11 @@ def test_born_apply_matches_oracle(hd, dtype, tol):
     ref = oborn.born_apply(Pr[:, :w.S], Pr[:, w.S:], vt.double().numpy(), w.h)
     y = hd.born_apply(op, t[:, :w.S], t[:, w.S:], vt.to(DEV)).cpu().numpy()
     assert normwise(y.reshape(3, -1), ref.reshape(3, -1)).max() < tol
+    # every (probe vector, wavelength, source, detector) entry within tol of the absolute sum of
+    # its terms, so small (far-pair) entries are held to the same relative accuracy
+    absum = w.h ** 3 * np.einsum("lsk,ck,ldk->clsd", np.abs(Pr[:, :w.S]), np.abs(vt.double().numpy()),
+                                 np.abs(Pr[:, w.S:]), optimize=True)
+    assert np.all(np.abs(y - ref) <= tol * absum), float((np.abs(y - ref) / absum).max())
     # against the FP64 oracle without input rounding, within the path's tolerance
     ref64 = oborn.born_apply(Ps, Pd, v, w.h)
     assert normwise(y.reshape(-1), ref64.reshape(-1)) < (1e-8 if dtype == torch.complex128 else 1e-4)
@@ -207,6 +212,10 @@ def test_born_adjoint_matches_oracle(hd, dtype, tol):
     ref = oborn.born_apply_adjoint(Pr[:, :w.S], Pr[:, w.S:], wt.cpu().numpy().astype(np.complex128), w.h)
     g = hd.born_apply_adjoint(op, t[:, :w.S], t[:, w.S:], wt.to(DEV)).cpu().numpy()
     assert normwise(g, ref) < tol
+    # every voxel within tol of the absolute sum of its terms
+    wr = wt.cpu().numpy().astype(np.complex128)
+    absg = w.h ** 3 * np.einsum("lsk,lsd,ldk->k", np.abs(Pr[:, :w.S]), np.abs(wr), np.abs(Pr[:, w.S:]), optimize=True)
+    assert np.all(np.abs(g - ref) <= tol * absg), float((np.abs(g - ref) / absg).max())
 
 
 @pytest.mark.parametrize("S,D", [(3, 5), (9, 2), (24, 24), (64, 64)])
