@@ -409,18 +409,19 @@ def main():
 
 
 def born_variants(hd, torch, np, workloads, w, w_shard, phi, v, dev, timed):
-    """Born J v variants on two wavelengths of the shard: FP32 / split-BF16 / BF16-stored fields, one
-    probe vector and the 42-column Jacobian block, each against the FP64 products of the same fields."""
+    """Born J v variants: FP32 / split-BF16 / BF16-stored fields, one probe vector on every wavelength
+    of the shard and the 42-column Jacobian block on two, each against the FP64 products of the same
+    fields."""
     S, D, N = w.S, w.D, w.N
-    w2 = workloads.subset_lambdas(w_shard, np.arange(2))
-    op2 = hd.Operator.from_workload(w2)
-    f32 = phi[:2]
-    phi64 = f32.to(torch.complex128)
-    bf = torch.view_as_real(f32).to(torch.bfloat16).contiguous()
     vj = torch.from_numpy(workloads.born_v(w, n_v=N_JAC, seed=2024, dtype=np.float32)).to(dev)
     pad = lambda x, m: -(-x // m) * m
     out = {}
-    for nv, vv in (("1", v), (str(N_JAC), vj)):
+    for nv, vv, nl in (("1", v, w_shard.L), (str(N_JAC), vj, 2)):
+        w2 = workloads.subset_lambdas(w_shard, np.arange(nl))
+        op2 = hd.Operator.from_workload(w2)
+        f32 = phi[:nl]
+        phi64 = f32.to(torch.complex128)
+        bf = torch.view_as_real(f32).to(torch.bfloat16).contiguous()
         ref = hd.born_apply(op2, phi64[:, :S], phi64[:, S:], vv.double())
         cases = [("fp32", f32, False, FP32_PEAK_TFLOPS, 8), ("split_bf16", f32, True, BF16_PEAK_TFLOPS, 8),
                  ("bf16_fields", bf, False, BF16_PEAK_TFLOPS, 4)]
@@ -428,7 +429,7 @@ def born_variants(hd, torch, np, workloads, w, w_shard, phi, v, dev, timed):
             ms = timed(lambda: hd.born_apply(op2, f[:, :S], f[:, S:], vv, split_bf16=split))
             y = hd.born_apply(op2, f[:, :S], f[:, S:], vv, split_bf16=split)
             n_v = vv.shape[0]
-            L2 = 2
+            L2 = nl
             useful = 8.0 * S * D * N * L2 * n_v
             pairs = n_v >= hd.BORN_PAIRS_MIN_NV
             # MFMA work the kernel executes: the real-ified complex product (8 S D N per probe vector,
@@ -439,8 +440,9 @@ def born_variants(hd, torch, np, workloads, w, w_shard, phi, v, dev, timed):
             needed = (4.0 * S * D * N * L2 * n_v if pairs else useful) * (3 if split else 1)
             err = float(torch.linalg.vector_norm(y.to(torch.complex128) - ref) / torch.linalg.vector_norm(ref))
             out[f"{name}_nv{nv}"] = {
-                "kernel": ("k_born_jv_pairs" if pairs else "k_born_jv_wide" if name == "fp32" and S > 32 and D > 32
-                           else "k_born_jv"), "ms": round(ms, 4),
+                "kernel": ("k_born_jv_pairs" if pairs else "k_born_jv" if S <= 32 or D <= 32
+                           else "k_born_jv_wide" if name == "fp32" else "k_born_jv_wide_bf"),
+                "wavelengths": nl, "ms": round(ms, 4),
                 "tflops_8SDNL_convention": round(useful / (ms * 1e-3) / 1e12, 2),
                 "mfma_tflops_needed": round(needed / (ms * 1e-3) / 1e12, 2),
                 "mfma_frac_needed": round(needed / (ms * 1e-3) / 1e12 / peak, 4),
@@ -448,12 +450,13 @@ def born_variants(hd, torch, np, workloads, w, w_shard, phi, v, dev, timed):
                 "mfma_frac_executed_padded": round(executed / (ms * 1e-3) / 1e12 / peak, 4), "mfma_peak_tflops": peak,
                 "field_GBps": round((S + D) * N * L2 * bpc / (ms * 1e-3) / 1e9, 1),
                 "rel_err_vs_fp64_products": float(f"{err:.3g}")}
-    out["note"] = ("2 wavelengths of shard 0; 'needed' counts the multiply-adds the algorithm needs (4 S D N per "
+        del phi64, bf
+    out["note"] = ("shard 0: one probe vector on all its wavelengths, the 42-vector block on two; 'needed' counts "
+                   "the multiply-adds the algorithm needs (4 S D N per "
                    "probe vector on the pair-product kernel, whose pair products are shared by the probe vectors; "
                    "8 S D N on the real-ified kernel), 'executed_padded' includes the padding of rows to 8 and of "
                    "probe vectors to 16, and the 8*S*D*N*L convention credits every probe vector with a full complex "
                    "product (it can exceed the MFMA peak on the pair-product kernel)")
-    del phi64, bf
     return out
 
 

@@ -586,7 +586,7 @@ void launch_jv_pairs(dim3 grid, hipStream_t stream, int N, int S, int D, int64_t
 // the voxels into ranges and the bytes of FP64 split partials it writes (the caller's scratch).
 struct JvPlan {
   bool pairs = false;
-  bool wide = false;                            // k_born_jv_wide (FP32, S and D above 32)
+  bool wide = false;                            // k_born_jv_wide(_bf) (S and D above 32)
   int Sp = 0, Dp = 0;
   int kt = 32, tpw = 1, nvb = 1, ngroups = 1;   // real-ified kernel
   int nts = 1, ntd = 1, nct = 1;                // pair-product kernel
@@ -610,6 +610,12 @@ static JvPlan jv_plan(const hydot_operator* op, const hydot_tuning& tune, int S,
     // a quarter of the tuned block count fills the chip (about two blocks per CU by default)
     P.wide = true;
     P.kt = 16 * kWideNS;   // voxel ranges hold whole FP32 partial sums
+    const int target = std::max(1, tu.born_blocks / 4);
+    P.nsplit = std::max(1, (target + L * n_v - 1) / (L * n_v));
+  } else if (n_v < kPairsMinNv && bf16_compute(cm) && S >= kWideMin && D >= kWideMin) {
+    // BF16 MFMA form, the same blocks as the FP32 one
+    P.wide = true;
+    P.kt = kWideBfKt;   // voxel ranges hold whole FP32 partial sums
     const int target = std::max(1, tu.born_blocks / 4);
     P.nsplit = std::max(1, (target + L * n_v - 1) / (L * n_v));
   } else if (n_v >= kPairsMinNv) {
@@ -692,11 +698,39 @@ hydot_status born_apply_wide(const hydot_operator* op, const JvPlan& P, const vo
   return HYDOT_OK;
 }
 
+// J v on k_born_jv_wide_bf (BF16-stored fields with BF16 products, or FP32 fields with split-BF16
+// products; S and D above 32), then the fixed-order sum over the voxel ranges.
+template <typename TS, int CM>
+hydot_status born_apply_wide_bf(const hydot_operator* op, const JvPlan& P, const void* phs, int S, const void* phd,
+                                int D, int64_t ls, const void* v, int n_v, void* y, void* part, hipStream_t stream) {
+  using R = typename Field<TS>::real;
+  const int N = op->gp.N, L = op->L;
+  const dim3 grid(P.nsplit, L, n_v);
+  // 16-byte buffer loads: N a multiple of 8, 16-byte aligned bases, every resource below 2 GiB
+  const bool vec = N % 8 == 0 && aligned16(phs) && aligned16(phd) && aligned16(v) &&
+                   (size_t)std::max(S, D) * N * sizeof(TS) < ((size_t)1 << 31);
+  if (vec)
+    hipLaunchKernelGGL((k_born_jv_wide_bf<TS, CM, true>), grid, dim3(kBlock), 0, stream, N, S, D, ls, (const TS*)phs,
+                       (const TS*)phd, (const float*)v, P.kb, L, (double*)part);
+  else
+    hipLaunchKernelGGL((k_born_jv_wide_bf<TS, CM, false>), grid, dim3(kBlock), 0, stream, N, S, D, ls,
+                       (const TS*)phs, (const TS*)phd, (const float*)v, P.kb, L, (double*)part);
+  const int nout = n_v * L * S * D;
+  const double h = op->grid.h_mm;
+  hipLaunchKernelGGL((k_born_pairs_finish<cplx<R>>), dim3((nout + 255) / 256), dim3(256), 0, stream, S * D, P.nsplit,
+                     nout, (const double*)part, -h * h * h, (cplx<R>*)y);
+  HYDOT_HIP(hipGetLastError());
+  return HYDOT_OK;
+}
+
 template <typename TS, int CM>
 hydot_status born_apply_impl(const hydot_operator* op, const JvPlan& P, const void* phs, int S, const void* phd,
                              int D, int64_t ls, const void* v, int n_v, void* y, void* part, hipStream_t stream) {
   if constexpr (std::is_same<TS, cf>::value && CM == CM_F32) {
     if (P.wide) return born_apply_wide(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
+  }
+  if constexpr ((std::is_same<TS, cbf>::value && CM == CM_BF16) || (std::is_same<TS, cf>::value && CM == CM_SPLIT)) {
+    if (P.wide) return born_apply_wide_bf<TS, CM>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
   }
   if (P.pairs) return born_apply_pairs<TS, CM>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
   using R = typename Field<TS>::real;

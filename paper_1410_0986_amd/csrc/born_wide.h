@@ -174,6 +174,313 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, in
       }
 }
 
+// ---------------------------------------------------------------- J v on the BF16 MFMA
+// The same products from BF16 operands on v_mfma_f32_16x16x32_bf16: CM_BF16 takes BF16-stored
+// fields (cbf) and rounds a = phi_s v (formed in FP32) to BF16, phi_d entering as stored;
+// CM_SPLIT takes FP32 fields and splits a and phi_d into hi + lo BF16 parts, accumulating
+// hi*hi + hi*lo + lo*hi.  Lane (r = lane%16, g = lane/16) supplies row r at voxels 8g..8g+7 of a
+// 32-voxel step for both operands (one MFMA k-step per step).  Block and waves as
+// k_born_jv_wide: wave (wa, wb) owns 32 sources x 32 detectors as 2 x 2 tiles, so each converted
+// operand feeds two tiles.  FP32 MFMA sums cover wide_bf_ns steps and are then folded into FP64;
+// the raw field words of the next step are loaded while the current step's products run (BF16
+// storage); partials as k_born_jv_wide.  VEC: 16-byte loads (N a multiple of 8, base
+// pointers 16-byte aligned).
+typedef __bf16 wbf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// 32-voxel steps per FP32 partial sum: 256 voxels for BF16 products (their rounding, 2^-9, far
+// exceeds the FP32 summation error), 128 for the split
+template <int CM>
+constexpr int wide_bf_ns() { return CM == CM_SPLIT ? 4 : 8; }
+static_assert(8 % 2 == 0 && 4 % 2 == 0, "stages hold whole pairs of steps");
+constexpr int kWideBfKt = 256;   // voxel ranges: a multiple of both
+
+// raw words of eight voxels of one field row: BF16 storage (re, im) pairs in 8 words, FP32 in 16
+template <typename TS>
+struct Raw8 {
+  static constexpr int nw = std::is_same<TS, cbf>::value ? 8 : 16;
+  unsigned int w[nw];
+};
+// Raw buffer resource over nbytes at p (an offset at or past nbytes reads zero)
+__device__ inline __amdgpu_buffer_rsrc_t wide_rsrc(const void* p, uint32_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
+constexpr uint32_t kWideOut = 0x80000000u;   // a byte offset past every resource here
+
+// Voxel of lane-local index i within a 32-voxel step: lane g takes voxels 8g..8g+7 (its two
+// 16-byte loads of a BF16 row, four of an FP32 row, are contiguous), the MFMA k-step 8g + i
+template <typename TS>
+__device__ inline int vox_in_step(int i, int g) {
+  return 8 * g + i;
+}
+
+// VEC: N and every range end are multiples of 8, so a lane's eight voxels lie all inside the range
+// or all past it; rows are read through buffer resources (row_off = byte offset of the row, or
+// kWideOut for a missing row; a piece past the range reads zeros without a branch)
+template <typename TS>
+__device__ inline void load_raw8_buf(__amdgpu_buffer_rsrc_t r, uint32_t row_off, int kbase, int g, int k1,
+                                     Raw8<TS>& q) {
+  constexpr int nw = Raw8<TS>::nw;
+  const int first = kbase + 8 * g;
+  const uint32_t off = row_off != kWideOut && first < k1 ? row_off + (uint32_t)first * (uint32_t)sizeof(TS) : kWideOut;
+#pragma unroll
+  for (int j = 0; j < nw / 4; ++j) {
+    const u32x4 x = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u * j, 0, 0));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q.w[4 * j + i] = x[i];
+  }
+}
+// element by element (any N), zeros past the range or for a missing row
+template <typename TS>
+__device__ inline void load_raw8(const TS* p, int kbase, int g, int k1, bool row_ok, Raw8<TS>& r) {
+  constexpr int nw = Raw8<TS>::nw;
+  const unsigned int* q = reinterpret_cast<const unsigned int*>(p);
+  constexpr int wpv = nw / 8;   // words per voxel
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = kbase + vox_in_step<TS>(i, g);
+    const bool ok = row_ok && k < k1;
+#pragma unroll
+    for (int u = 0; u < wpv; ++u) r.w[wpv * i + u] = ok ? q[(size_t)k * wpv + u] : 0u;
+  }
+}
+// FP32 (re, im) of voxel i from the raw words
+template <typename TS>
+__device__ inline float raw_re(const Raw8<TS>& r, int i) {
+  if constexpr (std::is_same<TS, cbf>::value) return __builtin_bit_cast(float, r.w[i] << 16);
+  else return __builtin_bit_cast(float, r.w[2 * i]);
+}
+template <typename TS>
+__device__ inline float raw_im(const Raw8<TS>& r, int i) {
+  if constexpr (std::is_same<TS, cbf>::value) return __builtin_bit_cast(float, r.w[i] & 0xffff0000u);
+  else return __builtin_bit_cast(float, r.w[2 * i + 1]);
+}
+
+__device__ inline wbf16x8 bf8_round(const float* x) {
+  wbf16x8 r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = (__bf16)x[i];
+  return r;
+}
+// x - hi rounded to BF16 (the lo part of the split)
+__device__ inline wbf16x8 bf8_lo(const float* x, wbf16x8 hi) {
+  wbf16x8 r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = (__bf16)(x[i] - (float)hi[i]);
+  return r;
+}
+__device__ inline wbf16x8 bf8_neg(wbf16x8 x) {   // exact: flips the sign bits
+  return __builtin_bit_cast(wbf16x8, __builtin_bit_cast(u32x4, x) ^ u32x4{0x80008000u, 0x80008000u, 0x80008000u,
+                                                                           0x80008000u});
+}
+
+// BF16 storage: the re (low halves) and im (high halves) of eight voxels packed straight into
+// MFMA operands (exact, no widening)
+__device__ inline void bf8_unzip(const unsigned int* w, wbf16x8& re, wbf16x8& im) {
+  u32x4 r, i;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    r[j] = __builtin_amdgcn_perm(w[2 * j + 1], w[2 * j], 0x05040100u);   // low halves of w[2j], w[2j+1]
+    i[j] = __builtin_amdgcn_perm(w[2 * j + 1], w[2 * j], 0x07060302u);   // high halves
+  }
+  re = __builtin_bit_cast(wbf16x8, r);
+  im = __builtin_bit_cast(wbf16x8, i);
+}
+
+template <typename TS, int CM>
+struct BfOps {   // BF16 operands of one row and step: hi (and lo for the split)
+  wbf16x8 re, im, re_lo, im_lo;
+};
+template <typename TS, int CM>
+__device__ inline BfOps<TS, CM> bf_ops(const float* re, const float* im) {
+  BfOps<TS, CM> o;
+  o.re = bf8_round(re);
+  o.im = bf8_round(im);
+  if constexpr (CM == CM_SPLIT) {
+    o.re_lo = bf8_lo(re, o.re);
+    o.im_lo = bf8_lo(im, o.im);
+  }
+  return o;
+}
+// acc += x y over the BF16 parts: x.hi y.hi (+ x.hi y.lo + x.lo y.hi for the split)
+template <int CM>
+__device__ inline f32x4 bf_mac(wbf16x8 xh, wbf16x8 xl, wbf16x8 yh, wbf16x8 yl, f32x4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yh, acc, 0, 0, 0);
+  if constexpr (CM == CM_SPLIT) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, yh, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <typename TS, int CM, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_born_jv_wide_bf(int N, int S, int D, int64_t lam_stride,
+                                                           const TS* __restrict__ phs, const TS* __restrict__ phd,
+                                                           const float* __restrict__ v, int kb, int L,
+                                                           double* __restrict__ part) {
+  static_assert(CM == CM_BF16 || CM == CM_SPLIT, "BF16 MFMA products");
+  const int split = blockIdx.x, l = blockIdx.y, c = blockIdx.z, nsplit = gridDim.x;
+  const int k0 = split * kb, k1 = min(N, k0 + kb);
+  auto kstep = [&](int st) { return k0 + 32 * st; };
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int wa = wave >> 1, wb = wave & 1;
+  const size_t Nz = (size_t)N;
+  bool sok[2], dok[2];
+  const TS* pa[2];
+  const TS* pb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int s = 32 * wa + 16 * t + r16, d = 32 * wb + 16 * t + r16;
+    sok[t] = s < S;
+    dok[t] = d < D;
+    pa[t] = phs + ((size_t)l * lam_stride + (sok[t] ? s : 0)) * Nz;
+    pb[t] = phd + ((size_t)l * lam_stride + (dok[t] ? d : 0)) * Nz;
+  }
+  const float* vc = v + (size_t)c * Nz;
+  // one step's raw words: two source rows, two detector rows, eight probe-vector values
+  struct Step {
+    Raw8<TS> ra[2], rb[2];
+    float vv[8];
+  };
+  // VEC: buffer resources over this wavelength's source rows, detector rows and the probe vector
+  // (the host keeps each below 2 GiB)
+  const uint32_t rowb = (uint32_t)(Nz * sizeof(TS));
+  const __amdgpu_buffer_rsrc_t rsA = wide_rsrc(phs + (size_t)l * lam_stride * Nz, (uint32_t)S * rowb);
+  const __amdgpu_buffer_rsrc_t rsB = wide_rsrc(phd + (size_t)l * lam_stride * Nz, (uint32_t)D * rowb);
+  const __amdgpu_buffer_rsrc_t rsV = wide_rsrc(vc, (uint32_t)(Nz * sizeof(float)));
+  uint32_t offA[2], offB[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    offA[t] = sok[t] ? (uint32_t)(32 * wa + 16 * t + r16) * rowb : kWideOut;
+    offB[t] = dok[t] ? (uint32_t)(32 * wb + 16 * t + r16) * rowb : kWideOut;
+  }
+  auto fetch = [&](int kbase, Step& q) {
+    if constexpr (VEC) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        load_raw8_buf(rsA, offA[t], kbase, g, k1, q.ra[t]);
+        load_raw8_buf(rsB, offB[t], kbase, g, k1, q.rb[t]);
+      }
+      // the probe vector at the same voxels
+      const int first = kbase + 8 * g;
+      const uint32_t vo = first < k1 ? (uint32_t)first * 4u : kWideOut;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const f32x4 x = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsV, vo + 16u * j, 0, 0));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q.vv[4 * j + i] = x[i];
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        load_raw8(pa[t], kbase, g, k1, sok[t], q.ra[t]);
+        load_raw8(pb[t], kbase, g, k1, dok[t], q.rb[t]);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = kbase + vox_in_step<TS>(i, g);
+        q.vv[i] = k < k1 ? vc[k] : 0.f;
+      }
+    }
+  };
+  f32x4 accR[2][2], accI[2][2];
+  double totR[2][2][4], totI[2][2][4];
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb) {
+      accR[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      accI[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) totR[ta][tb][r] = totI[ta][tb][r] = 0.0;
+    }
+  // BF16 operands of step st from its raw words, then (BF16 storage) the loads of step st + 2 into
+  // the same buffer, then the products; steps alternate between two buffers
+  // BF16 storage: the raw words of step st + 2 are loaded while step st runs (two waves per SIMD);
+  // the split's FP32 rows would leave one, so it loads each step's words at its start
+  constexpr bool kPrefetch = CM == CM_BF16;
+  auto step = [&](int st, Step& q) {
+    if (!kPrefetch) fetch(kstep(st), q);
+    BfOps<TS, CM> A[2], An[2], B[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      float xr[8], xi[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        xr[i] = raw_re(q.ra[t], i) * q.vv[i];
+        xi[i] = raw_im(q.ra[t], i) * q.vv[i];
+      }
+      A[t] = bf_ops<TS, CM>(xr, xi);
+      An[t].im = bf8_neg(A[t].im);
+      if constexpr (CM == CM_SPLIT) An[t].im_lo = bf8_neg(A[t].im_lo);
+      if constexpr (std::is_same<TS, cbf>::value) {
+        bf8_unzip(q.rb[t].w, B[t].re, B[t].im);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          xr[i] = raw_re(q.rb[t], i);
+          xi[i] = raw_im(q.rb[t], i);
+        }
+        B[t] = bf_ops<TS, CM>(xr, xi);
+      }
+    }
+    if (kPrefetch) fetch(kstep(st + 2), q);   // past the range it reads zeros
+    // Re y += Re a Re b - Im a Im b, Im y += Re a Im b + Im a Re b
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int ta = 0; ta < 2; ++ta) {
+        accR[ta][tb] = bf_mac<CM>(A[ta].re, A[ta].re_lo, B[tb].re, B[tb].re_lo, accR[ta][tb]);
+        accR[ta][tb] = bf_mac<CM>(An[ta].im, An[ta].im_lo, B[tb].im, B[tb].im_lo, accR[ta][tb]);
+        accI[ta][tb] = bf_mac<CM>(A[ta].re, A[ta].re_lo, B[tb].im, B[tb].im_lo, accI[ta][tb]);
+        accI[ta][tb] = bf_mac<CM>(A[ta].im, A[ta].im_lo, B[tb].re, B[tb].re_lo, accI[ta][tb]);
+      }
+  };
+  // whole FP32 stages of NS steps (a partial last stage runs its missing steps on zeros)
+  constexpr int NS = wide_bf_ns<CM>();
+  const int nst = k1 > k0 ? (k1 - k0 + 31) / 32 : 0;
+  Step q0, q1;
+  if (kPrefetch) {
+    fetch(kstep(0), q0);
+    fetch(kstep(1), q1);
+  }
+  for (int st0 = 0; st0 < nst; st0 += NS) {
+#pragma unroll
+    for (int u = 0; u < NS; u += 2) {
+      step(st0 + u, q0);
+      step(st0 + u + 1, q1);
+    }
+#pragma unroll
+    for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          totR[ta][tb][r] += (double)accR[ta][tb][r];
+          totI[ta][tb][r] += (double)accI[ta][tb][r];
+        }
+        accR[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        accI[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+  }
+  // accumulator register r of lane (col = lane%16, g) holds row 4g + r of the tile
+  double* out = part + ((size_t)(c * L + l) * nsplit + split) * (size_t)S * D * 2;
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = 32 * wa + 16 * ta + 4 * g + r, d = 32 * wb + 16 * tb + r16;
+        if (s < S && d < D) {
+          const size_t o = ((size_t)s * D + d) * 2;
+          out[o] = totR[ta][tb][r];
+          out[o + 1] = totI[ta][tb][r];
+        }
+      }
+}
+
 // ---------------------------------------------------------------- J^H w
 // g[k] = scale sum_l sum_d conj(phi_d(k)) T_l[k][d],  T_l[k][d] = sum_s conj(phi_s(k)) w_l[s][d].
 // Block = 4 waves on 64 voxels (16 per wave), looping over the wavelengths.  Per wavelength the

@@ -185,6 +185,45 @@ def test_born_split_bf16(hd, S, D, n_v):
     assert normwise(y1, ref) < 1e-5
 
 
+@pytest.mark.parametrize("grid", [(20, 13, 7), (16, 10, 8)])        # N = 1820 (ragged), 1280 (16-byte loads)
+@pytest.mark.parametrize("S,D,n_v", [(33, 47, 1), (64, 64, 2), (48, 64, 3)])
+@pytest.mark.parametrize("mode", ["bf16", "split"])
+def test_born_bf16_wide(hd, mode, S, D, n_v, grid):
+    """More than 32 sources and detectors on the BF16 MFMA (fewer than 12 probe vectors): BF16-
+    stored fields with BF16 products, and FP32 fields with split-BF16 products.  Every (probe
+    vector, wavelength, source, detector) entry against the FP64 products of exactly the operands
+    the kernel multiplies (BF16: phi_s v formed in FP32 and rounded, phi_d as stored), within 1e-5
+    of the absolute sum of its terms (FP32 sums over 32-voxel steps, FP64 beyond); the split
+    within 1e-4 of the absolute sum against the FP32 operands themselves."""
+    nx, ny, nz = grid
+    w = workloads.config("tiny", nx=nx, ny=ny, nz=nz, n_lambda=3)
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(31 + S + D + nx)
+    P = rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))
+    v = workloads.born_v(w, n_v=n_v, dtype=np.float32)
+    vt = torch.from_numpy(v).to(DEV)
+    if mode == "bf16":
+        t = to_bf16_pairs(P).to(DEV)
+        Pr = from_bf16_pairs(t.cpu())
+        y = hd.born_apply(op, t[:, :S], t[:, S:], vt).cpu().numpy().astype(np.complex128)
+        exp = _bf16_expected(Pr[:, :S], Pr[:, S:], v, w.h)
+        tol = 1e-5
+    else:
+        t = torch.from_numpy(P).to(torch.complex64).to(DEV)
+        Pr = t.cpu().numpy().astype(np.complex128)
+        y = hd.born_apply(op, t[:, :S], t[:, S:], vt, split_bf16=True).cpu().numpy().astype(np.complex128)
+        exp = oborn.born_apply(Pr[:, :S], Pr[:, S:], v.astype(np.float64), w.h)
+        tol = 1e-4
+    assert y.shape == exp.shape == (n_v, w.L, S, D)
+    absum = w.h ** 3 * np.einsum("lsk,ck,ldk->clsd", np.abs(Pr[:, :S]), np.abs(v.astype(np.float64)),
+                                 np.abs(Pr[:, S:]), optimize=True)
+    err = np.abs(y - exp)
+    assert np.all(err <= tol * absum), float((err / absum).max())
+    # stated error of the variant against the unrounded FP64 products
+    ref = oborn.born_apply(P[:, :S], P[:, S:], v.astype(np.float64), w.h)
+    assert normwise(y, ref) < (2e-2 if mode == "bf16" else 1e-4)
+
+
 def test_split_bf16_rejects_other_fields(hd, tiny):
     w, ref = tiny
     op = hd.Operator.from_workload(w)
