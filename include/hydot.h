@@ -186,6 +186,35 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
                                 void* workspace, size_t ws_bytes, int32_t* iters, double* rel_res,
                                 hipStream_t stream);
 
+/* Several independent solves of Alg. 1 (Sec. 3.1), one per operator (e.g. a main grid and smaller
+ * grids at the same wavelengths), run as one batch: each problem's kernels go to a stream of
+ * its own forked from `stream` (they start after the work queued on `stream` before the call)
+ * and one host thread per problem drives its restart cycles, so the grids' launches run on
+ * the GPU concurrently.  Every problem's fields, iters and rel_res are exactly those of a
+ * hydot_solve_fields call with the same arguments (the arithmetic of each problem is unchanged).
+ * problems: host [n_problems], 1 <= n_problems <= HYDOT_SOLVE_BATCH_MAX; the fields of each are
+ *   as in hydot_solve_fields; the operators must be distinct (a solve updates its operator's
+ *   caches) and the workspaces and outputs must not overlap.  `status` is written per problem.
+ * Returns the lowest-indexed problem's error if any failed (hydot_last_error names it; the other
+ * problems still ran), else HYDOT_ENOCONV if any problem returned it, else HYDOT_OK; EINVAL (nothing
+ * launched) for a bad count, a null operator or a repeated operator.  All work has completed
+ * when it returns.  While the profiler is enabled the problems run one after another. */
+#define HYDOT_SOLVE_BATCH_MAX 16
+typedef struct {
+  hydot_operator* op;
+  int32_t n_rhs;
+  const int64_t* rhs_voxel;
+  const hydot_solve_opts* opts;
+  void* phi;
+  hydot_dtype phi_dtype;
+  void* workspace;
+  size_t ws_bytes;
+  int32_t* iters;
+  double* rel_res;
+  hydot_status status;      /* out */
+} hydot_solve_problem;
+hydot_status hydot_solve_fields_batch(int32_t n_problems, hydot_solve_problem* problems, hipStream_t stream);
+
 /* Read-back of the solver's intermediates (Alg. 1) for tests and diagnosis, from the workspace
  * of the last hydot_solve_fields call made with the same operator, n_rhs and opts (the workspace
  * must not have been used since).  Synchronous host copies on `stream`.

@@ -16,6 +16,8 @@ from ._binding import (  # noqa: F401
     apply_preconditioner,
     solve_workspace_bytes,
     solve_fields,
+    solve_fields_batch,
+    SOLVE_BATCH_MAX,
     SolveSession,
     born_apply,
     born_workspace_bytes,

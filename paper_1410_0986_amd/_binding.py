@@ -72,6 +72,19 @@ _precond = _proto("hydot_apply_preconditioner", c_int32, c_void_p, ctypes.c_uint
 _ws_bytes = _proto("hydot_solve_workspace_bytes", c_int32, c_void_p, c_int32, POINTER(_SolveOpts), POINTER(c_size_t))
 _solve = _proto("hydot_solve_fields", c_int32, c_void_p, c_int32, POINTER(c_int64), POINTER(_SolveOpts), c_void_p,
                 c_int32, c_void_p, c_size_t, POINTER(c_int32), POINTER(c_double), c_void_p)
+SOLVE_BATCH_MAX = 16   # HYDOT_SOLVE_BATCH_MAX
+
+
+class _SolveProblem(ctypes.Structure):
+    _fields_ = [("op", c_void_p), ("n_rhs", c_int32), ("rhs_voxel", POINTER(c_int64)),
+                ("opts", POINTER(_SolveOpts)), ("phi", c_void_p), ("phi_dtype", c_int32), ("workspace", c_void_p),
+                ("ws_bytes", c_size_t), ("iters", POINTER(c_int32)), ("rel_res", POINTER(c_double)),
+                ("status", c_int32)]
+
+
+_solve_batch = _proto("hydot_solve_fields_batch", c_int32, c_int32, POINTER(_SolveProblem), c_void_p)
+
+
 class _InspectInfo(ctypes.Structure):
     _fields_ = [("rhs", c_int32), ("lam", c_int32), ("k", c_int32), ("nsteps", c_int32)]
 
@@ -352,6 +365,48 @@ def solve_fields(op: Operator, rhs_voxels, opts: SolveOptions | None = None, out
     _check(st, allow_noconv=True)
     del buf
     return out, iters.reshape(op.L, R), rel.reshape(op.L, R), st
+
+
+def solve_fields_batch(problems, device="cuda"):
+    """Several independent solves as one batch (hydot_solve_fields_batch): the operators' kernels
+    run concurrently, each on a stream of its own forked from the current stream.
+
+    problems: sequence of (op, rhs_voxels, opts, out) with out a contiguous [L, n_rhs, N] tensor (or
+    None for complex128).  Returns one (phi, iters, rel_res, status) per problem, as solve_fields.
+    """
+    n = len(problems)
+    arr = (_SolveProblem * n)()
+    keep = []
+    results = []
+    dev = None
+    for i, (op, rhs_voxels, opts, out) in enumerate(problems):
+        opts = opts or SolveOptions()
+        vox = np.ascontiguousarray(rhs_voxels, dtype=np.int64)
+        R = int(vox.shape[0])
+        if out is None:
+            out = torch.empty(_field_shape(op, R, torch.complex128), dtype=torch.complex128, device=device)
+        _need_cuda(out, "out")
+        if not out.is_contiguous() or tuple(out.shape) != _field_shape(op, R, out.dtype):
+            raise ValueError("out must be a contiguous [L, n_rhs, N] tensor ([L, n_rhs, N, 2] for bfloat16)")
+        if dev is None:
+            dev = out.device
+        elif out.device != dev:
+            raise ValueError("all outputs of a batch must be on one device")
+        o = opts._c()
+        nbytes = solve_workspace_bytes(op, R, opts)
+        buf, wptr = _ws(nbytes, out.device)
+        iters = np.zeros(op.L * R, dtype=np.int32)
+        rel = np.zeros(op.L * R, dtype=np.float64)
+        keep.append((vox, o, buf))
+        arr[i] = _SolveProblem(op.handle, R, vox.ctypes.data_as(POINTER(c_int64)), ctypes.pointer(o),
+                               out.data_ptr(), _cdtype(out), wptr, nbytes,
+                               iters.ctypes.data_as(POINTER(c_int32)), _dptr(rel), 0)
+        results.append((out, iters, rel, op.L, R))
+    st = _solve_batch(n, arr, _stream(dev))
+    _check(st, allow_noconv=True)
+    del keep
+    return [(out, it.reshape(L, R), rel.reshape(L, R), int(arr[i].status))
+            for i, (out, it, rel, L, R) in enumerate(results)]
 
 
 class SolveSession:

@@ -8,6 +8,7 @@
 #include <type_traits>
 #include <cstring>
 #include <new>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -1149,6 +1150,99 @@ hydot_status hydot_solve_fields(hydot_operator* op, int32_t n_rhs, const int64_t
     return fail(HYDOT_ENOMEM, "solve: host allocation failed");
   } catch (...) {
     return fail(HYDOT_EDEVICE, "solve: unexpected host error");
+  }
+}
+
+static hydot_status solve_batch_body(int32_t n_problems, hydot_solve_problem* problems, hipStream_t stream) {
+  if (n_problems < 1 || n_problems > HYDOT_SOLVE_BATCH_MAX)
+    return fail(HYDOT_EINVAL, "solve_batch: n_problems must be in [1, HYDOT_SOLVE_BATCH_MAX]");
+  if (!problems) return fail(HYDOT_EINVAL, "solve_batch: null problems");
+  for (int i = 0; i < n_problems; ++i) {
+    if (!problems[i].op) return fail(HYDOT_EINVAL, "solve_batch: null operator");
+    for (int j = 0; j < i; ++j)
+      if (problems[j].op == problems[i].op) return fail(HYDOT_EINVAL, "solve_batch: an operator appears twice");
+  }
+  const int n = n_problems;
+  std::vector<hipStream_t> st(n, nullptr);
+  std::vector<std::string> msg(n);
+  std::vector<std::thread> th;
+  std::vector<char> on_thread(n, 0);
+  th.reserve(n);
+  hipEvent_t fork = nullptr;
+  auto release = [&]() {
+    for (hipStream_t s : st)
+      if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+      }
+    if (fork) (void)hipEventDestroy(fork);
+  };
+  // fork: every problem's stream starts after the work already queued on the caller's stream
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(fork, stream);
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    e = hipStreamCreate(&st[i]);   // default priority
+    if (e == hipSuccess) e = hipStreamWaitEvent(st[i], fork, 0);
+  }
+  if (e != hipSuccess) {
+    release();
+    return hip_check(e, "solve_batch: stream set-up");
+  }
+  auto run = [&](int i) noexcept {
+    hydot_solve_problem& q = problems[i];
+    q.status = hydot_solve_fields(q.op, q.n_rhs, q.rhs_voxel, q.opts, q.phi, q.phi_dtype, q.workspace, q.ws_bytes,
+                                  q.iters, q.rel_res, st[i]);
+    // the fields and residuals of this problem are final once its stream has drained
+    const hipError_t se = hipStreamSynchronize(st[i]);
+    try {
+      if (q.status != HYDOT_OK) msg[i] = hydot_last_error();   // the message is per thread
+      if (se != hipSuccess && q.status >= 0) {
+        q.status = HYDOT_EDEVICE;
+        msg[i] = std::string("stream synchronize: ") + hipGetErrorString(se);
+      }
+    } catch (...) {   // no memory for the message: the status still reports the failure
+      if (se != hipSuccess && q.status >= 0) q.status = HYDOT_EDEVICE;
+    }
+  };
+  // the profiler's counters are process-wide: with it on, the problems run one after another
+  if (!g_prof) {
+    for (int i = 1; i < n; ++i) {
+      try {
+        th.emplace_back(run, i);
+        on_thread[i] = 1;
+      } catch (...) {   // no thread available: that problem runs on the calling thread
+      }
+    }
+  }
+  run(0);
+  for (int i = 1; i < n; ++i)
+    if (!on_thread[i]) run(i);
+  for (std::thread& x : th) x.join();
+  release();
+  int first_err = -1;
+  bool noconv = false;
+  for (int i = 0; i < n; ++i) {
+    if (problems[i].status < 0 && first_err < 0) first_err = i;
+    if (problems[i].status == HYDOT_ENOCONV) noconv = true;
+  }
+  if (first_err >= 0)
+    return fail(problems[first_err].status,
+                "solve_batch: problem " + std::to_string(first_err) + ": " + msg[first_err]);
+  if (noconv) {
+    for (int i = 0; i < n; ++i)
+      if (problems[i].status == HYDOT_ENOCONV)
+        return fail(HYDOT_ENOCONV, "solve_batch: problem " + std::to_string(i) + ": " + msg[i]);
+  }
+  return HYDOT_OK;
+}
+
+hydot_status hydot_solve_fields_batch(int32_t n_problems, hydot_solve_problem* problems, hipStream_t stream) {
+  try {   // host allocations before the problems start; every thread is joined before anything else throws
+    return solve_batch_body(n_problems, problems, stream);
+  } catch (const std::bad_alloc&) {
+    return fail(HYDOT_ENOMEM, "solve_batch: host allocation failed");
+  } catch (...) {
+    return fail(HYDOT_EDEVICE, "solve_batch: unexpected host error");
   }
 }
 

@@ -136,6 +136,28 @@ def test_solve_fields_validates_before_launch(hd):
     assert "dtype" in hd._binding._last_error().decode()
 
 
+def test_solve_batch_validates_before_launch(hd):
+    from paper_1410_0986_amd._binding import _SolveProblem
+    lib = _raw(hd)
+    f = lib.hydot_solve_fields_batch
+    f.restype = ctypes.c_int32
+    f.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    w = workloads.config("tiny")
+    a, b = _op(hd, w), _op(hd, w)
+    arr = (_SolveProblem * (hd.SOLVE_BATCH_MAX + 1))()
+    for i in range(hd.SOLVE_BATCH_MAX + 1):
+        arr[i].op = a.handle if i == 0 else b.handle
+        arr[i].status = 77
+    assert f(0, arr, None) == hd.EINVAL
+    assert f(hd.SOLVE_BATCH_MAX + 1, arr, None) == hd.EINVAL
+    assert f(1, None, None) == hd.EINVAL
+    assert f(3, arr, None) == hd.EINVAL                        # operator b twice
+    assert "twice" in hd._binding._last_error().decode()
+    arr[1].op = None
+    assert f(2, arr, None) == hd.EINVAL                        # null operator
+    assert all(arr[i].status == 77 for i in range(3))          # nothing ran
+
+
 def test_born_validates_before_launch(hd):
     lib = _raw(hd)
     w = workloads.config("tiny")

@@ -170,36 +170,69 @@ def _large_shards(w, n_shards=8):
 @pytest.mark.timeout(1100)
 def test_large_config_sampled(hd):
     """128x128x64 grid (1048576 voxels), 64 + 64 right-hand sides, 128 wavelengths 650-1000 nm,
-    in the launch configuration bench.py times: eight wavelength shards of 16 (2048 systems each,
-    batches of 512) into complex FP32 fields.  Every one of the 16384 systems meets rel-res 1e-8;
-    sampled fields against the oracle's fast diagonalisation at the mixed-path tolerance 1e-4;
-    on one shard, FP32 and split-BF16 J v at near source-detector pairs against the oracle's
-    fields entrywise, and J^H w at sampled voxels against the oracle's point evaluations."""
+    with its three companion grids (32x32x16, 48x48x24, 80x80x40) in one batch per wavelength
+    shard, in the launch configuration bench.py times: eight shards of 16 wavelengths (2048
+    main-grid systems each, batches of 512; 2304 companion-grid systems) into complex FP32
+    fields.  Every one of the 16384 main-grid and 18432 companion-grid systems meets rel-res
+    1e-8; sampled fields of every grid against the oracle's fast diagonalisation at the
+    mixed-path tolerance 1e-4; on the first shard, every grid's output of the batch equals its
+    own single solve exactly; on one shard, FP32 and split-BF16 J v at near source-detector
+    pairs against the oracle's fields entrywise, and J^H w at sampled voxels against the
+    oracle's point evaluations."""
     torch.cuda.empty_cache()
     w = workloads.config("large")
     shards = _large_shards(w)
+    comp = [workloads.config(c) for c in ("large_g32", "large_g48", "large_g80")]
+    comp_shards = [_large_shards(cw) for cw in comp]
     S, R, N = w.S, w.S + w.D, w.N
     Ls = shards[0].L
     s = torch.cuda.Stream()
     opts = bench_opts(hd, max_batch=512)
+    copts = bench_opts(hd, max_batch=1024)
     samples = {0: [(0, 0)], 4: [(13, 100)], 7: [(15, 63)]}      # shard: (wavelength in shard, rhs)
+    comp_samples = {2: (3, 0), 6: (12, -1)}                     # shard: (wavelength in shard, rhs)
     jv_shard = 5
     with torch.cuda.stream(s):
         phi = torch.empty((Ls, R, N), dtype=torch.complex64, device=DEV)
+        cphi = [torch.empty((Ls, cw.S + cw.D, cw.N), dtype=torch.complex64, device=DEV) for cw in comp]
     for i, ws in enumerate(shards):
         op = hd.Operator.from_workload(ws)
+        cws = [cs[i] for cs in comp_shards]
+        cops = [hd.Operator.from_workload(c) for c in cws]
         with torch.cuda.stream(s):
-            _, it, rel, st = hd.solve_fields(op, ws.rhs_voxels, opts, out=phi)
+            res = hd.solve_fields_batch([(op, ws.rhs_voxels, opts, phi)] +
+                                        [(co, c.rhs_voxels, copts, cp) for co, c, cp in zip(cops, cws, cphi)])
         s.synchronize()
-        assert st == hd.OK and rel.shape == (Ls, R) and rel.max() <= 1e-8, (i, rel.max())
-        print(f"large shard {i}: {Ls * R} systems, max rel-res {rel.max():.2e}, mean iters {it.mean():.1f}",
-              flush=True)
+        for g, (_, it, rel, st) in enumerate(res):
+            assert st == hd.OK and rel.max() <= 1e-8, (i, g, rel.max())
+        it, rel = res[0][1], res[0][2]
+        assert rel.shape == (Ls, R)
+        print(f"large shard {i}: {Ls * R} + {sum(r[2].size for r in res[1:])} systems in one batch, max rel-res "
+              f"{max(r[2].max() for r in res):.2e}, mean iters {it.mean():.1f}", flush=True)
         for lam, r in samples.get(i, []):
             ref = ofields.solve_separable(ws, voxels=[ws.rhs_voxels[r]], lam_idx=[lam])[0, 0]
             assert normwise(phi[lam, r].cpu().numpy().astype(np.complex128), ref) < 1e-4, (i, lam, r)
+        if i in comp_samples:
+            lam, r = comp_samples[i]
+            for c, cp in zip(cws, cphi):
+                ref = ofields.solve_separable(c, voxels=[c.rhs_voxels[r]], lam_idx=[lam])[0, 0]
+                assert normwise(cp[lam, r].cpu().numpy().astype(np.complex128), ref) < 1e-4, (i, c.nx, lam, r)
+        if i == 0:
+            # the batch changes no problem's arithmetic: each grid alone gives the same bits
+            for g, (o_, c_, o2, p_) in enumerate([(op, ws, opts, phi)] +
+                                                 [(co, c, copts, cp) for co, c, cp in zip(cops, cws, cphi)]):
+                with torch.cuda.stream(s):
+                    p1, it1, rel1, st1 = hd.solve_fields(o_, c_.rhs_voxels, o2, out_dtype=torch.complex64,
+                                                         device=DEV)
+                s.synchronize()
+                assert st1 == hd.OK and torch.equal(p1, p_), g
+                np.testing.assert_array_equal(it1, res[g][1])
+                np.testing.assert_array_equal(rel1, res[g][2])
+                del p1
+            torch.cuda.empty_cache()
         if i == jv_shard:
             _large_born_checks(hd, ws, op, phi, s)
-    del phi
+    del phi, cphi
     torch.cuda.empty_cache()
 
 
