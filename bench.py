@@ -453,8 +453,29 @@ def born_variants(hd, torch, np, workloads, w, w_shard, phi, v, dev, timed):
                 "mfma_frac_executed_padded": round(executed / (ms * 1e-3) / 1e12 / peak, 4), "mfma_peak_tflops": peak,
                 "field_GBps": round((S + D) * N * L2 * bpc / (ms * 1e-3) / 1e9, 1),
                 "rel_err_vs_fp64_products": float(f"{err:.3g}")}
+        if nv == "1":
+            # J^H w from BF16-stored fields (BF16 MFMA, w split into hi + lo) beside the FP32 one
+            wv = torch.from_numpy(workloads.born_w(w)[:nl]).to(torch.complex64).to(dev)
+            gref = hd.born_apply_adjoint(op2, phi64[:, :S], phi64[:, S:], wv.to(torch.complex128))
+            for name, f, bpc in (("fp32", f32, 8), ("bf16_fields", bf, 4)):
+                ms = timed(lambda: hd.born_apply_adjoint(op2, f[:, :S], f[:, S:], wv))
+                gg = hd.born_apply_adjoint(op2, f[:, :S], f[:, S:], wv)
+                err = float(torch.linalg.vector_norm(gg.to(torch.complex128) - gref) / torch.linalg.vector_norm(gref))
+                flops = 8.0 * S * D * N * nl
+                peak = FP32_PEAK_TFLOPS if name == "fp32" else BF16_PEAK_TFLOPS
+                out[f"adjoint_{name}"] = {
+                    "kernel": "k_born_adjoint_wide" if name == "fp32" else "k_born_adjoint_wide_bf",
+                    "wavelengths": nl, "ms": round(ms, 4),
+                    "tflops_8SDNL_convention": round(flops / (ms * 1e-3) / 1e12, 2),
+                    "mfma_frac_executed": round(flops * (1 if name == "fp32" else 2) / (ms * 1e-3) / 1e12 / peak, 4),
+                    "mfma_peak_tflops": peak,
+                    "field_GBps": round((S + D) * N * nl * bpc / (ms * 1e-3) / 1e9, 1),
+                    "hbm_frac": round((S + D) * N * nl * bpc / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "rel_err_vs_fp64_products": float(f"{err:.3g}")}
+            del gref
         del phi64, bf
-    out["note"] = ("shard 0: one probe vector on all its wavelengths, the 42-vector block on two; 'needed' counts "
+    out["note"] = ("shard 0: one probe vector on all its wavelengths, the 42-vector block on two, J^H w of one data "
+                   "vector on all its wavelengths (BF16 fields: w split into two BF16 products); 'needed' counts "
                    "the multiply-adds the algorithm needs (4 S D N per "
                    "probe vector on the pair-product kernel, whose pair products are shared by the probe vectors; "
                    "8 S D N on the real-ified kernel), 'executed_padded' includes the padding of rows to 8 and of "

@@ -328,7 +328,10 @@ hydot_status hydot_born_apply_noalloc(const hydot_operator* op, const void* phi_
  * Jacobian step of Alg. opt):
  *   g[k] = sum_{l,s,d} conj(J_l[s,d,k]) w[l][s][d] = -h^3 sum conj(phi_src[l][s][k] phi_det[l][d][k]) w[l][s][d]
  * w: device [n_lambda][S][D] complex and g: device [N] complex, both C128 for C128 fields and C64
- * for C64 or CBF16 fields (CBF16 fields are widened exactly to FP32 for the FP32 MFMA).
+ * for C64 or CBF16 fields.  CBF16 fields are widened exactly to FP32 for the FP32 MFMA, except
+ * with S and D both above 32: then the BF16 MFMA multiplies the stored field words directly with
+ * w split into BF16 hi + lo (w kept to about 2^-17 relative; sums in FP32 over the sources, FP64
+ * over detectors and wavelengths).
  * Field layout and lam_stride as hydot_born_apply.  Needs no scratch: each block owns a range of
  * voxels and sums over every wavelength in registers, writing g once. */
 hydot_status hydot_born_apply_adjoint(const hydot_operator* op, const void* phi_src, int32_t S,

@@ -793,6 +793,26 @@ hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S,
       return HYDOT_OK;
     }
   }
+  if constexpr (std::is_same<TS, cbf>::value) {
+    // many pairs from BF16 fields: k_born_adjoint_wide_bf (BF16 MFMA, w split into BF16 hi + lo),
+    // one data vector per launch; its buffer resources span one wavelength's rows
+    if (S >= kWideMin && D >= kWideMin && (size_t)std::max(S, D) * (size_t)N * 4u < (size_t(1) << 31)) {
+      const bool vec = N % 4 == 0 && aligned16(phs) && aligned16(phd);
+      const dim3 grid((N + kAdjBfVox - 1) / kAdjBfVox);
+      for (int c = 0; c < n_w; ++c) {
+        const cf* wc = (const cf*)w + (size_t)c * L * S * D;
+        cf* gc = (cf*)g + (size_t)c * N;
+        if (vec)
+          hipLaunchKernelGGL(k_born_adjoint_wide_bf<true>, grid, dim3(kBlock), 0, stream, N, S, D, ls, L,
+                             (const cbf*)phs, (const cbf*)phd, wc, -h * h * h, gc);
+        else
+          hipLaunchKernelGGL(k_born_adjoint_wide_bf<false>, grid, dim3(kBlock), 0, stream, N, S, D, ls, L,
+                             (const cbf*)phs, (const cbf*)phd, wc, -h * h * h, gc);
+      }
+      HYDOT_HIP(hipGetLastError());
+      return HYDOT_OK;
+    }
+  }
   const int Sp = pad8(S), Dp = pad8(D);
   const int TB = 2 * Dp / 16;
   // four data vectors per block when the detector tiles are few (register budget)

@@ -634,4 +634,201 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint_wide(int N, int S, int 
   }
 }
 
+// J^H w for BF16 fields with S and D above 32, on the BF16 MFMA.  Block = 4 waves on 256 voxels
+// (64 per wave, in two passes of two 16-voxel tiles), looping over the wavelengths.  With the k
+// index k = 2s + c (c = 0: real part, c = 1: imaginary part of source s) the product
+// T[voxel][d] = sum_s conj(phi_s) w[s][d] is real: A[voxel][2s + c] = (Re phi_s, Im phi_s) is a
+// BF16 field word as stored (two k values per 32-bit word), and
+//   Re T = A B_re,  B_re[2s + c][d] = (Re w[s][d], Im w[s][d]),
+//   Im T = A B_im,  B_im[2s + c][d] = (Im w[s][d], -Re w[s][d]).
+// w is split exactly enough into BF16 hi + lo (hi = bf16(w), lo = bf16(w - hi); relative error of
+// the pair about 2^-16), so the fields' BF16 storage is the only rounding of the operands.  Per
+// wavelength the block stages the hi and lo words of B_re in LDS (rows d, columns s; a pitch of
+// 68 words keeps each 16-byte operand read aligned); a B_im word is B_re's with its halves swapped
+// and the sign bit of the new upper half flipped (exact).  Lane (r = lane%16, g = lane/16) of a
+// tile takes, for k-step q, the four words of sources 16q + 4g + i (i < 4) at its voxel r from
+// HBM and the four words of the same sources at detector 16t + r from LDS, one 16-byte read per
+// operand, each operand serving both tiles of the pass.  T accumulates in FP32 over the sources;
+// the epilogue contracts it with conj(phi_d) in FP64 at the lane's accumulator entries (voxels
+// 4g + j of the tile, detector 16t + r: the four voxels of one detector row are one 16-byte word
+// group), summed over the detectors and wavelengths and, at the end, over the 16 detector lanes.
+// VEC: 16-byte loads of the detector words (N a multiple of 4, base pointers 16-byte aligned).
+constexpr int kAdjBfPitch = 68;   // LDS row pitch (words) of the staged B operands
+constexpr int kAdjBfVox = 256;    // voxels per block
+
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_born_adjoint_wide_bf(int N, int S, int D, int64_t lam_stride, int L,
+                                                                const cbf* __restrict__ phs,
+                                                                const cbf* __restrict__ phd,
+                                                                const cf* __restrict__ w, double scale,
+                                                                cf* __restrict__ gout) {
+  static_assert(kBlock == 256, "the staging maps 256 threads onto the 64 x 64 operand tile");
+  __shared__ __attribute__((aligned(16))) unsigned int Bhi[64 * kAdjBfPitch];
+  __shared__ __attribute__((aligned(16))) unsigned int Blo[64 * kAdjBfPitch];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int wbase = blockIdx.x * kAdjBfVox + wave * 64;   // this wave's 64 voxels
+  const uint32_t rowb = (uint32_t)N * 4u;                 // bytes per field row
+  double gre[2][2][4], gim[2][2][4];                      // [pass][tile][j]
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gre[p][mt][j] = gim[p][mt][j] = 0.0;
+
+  for (int l = 0; l < L; ++l) {
+    __syncthreads();   // the previous wavelength's operand reads are done
+    {
+      const cf* wl = w + (size_t)l * S * D;
+#pragma unroll 4
+      for (int j = 0; j < 16; ++j) {
+        const int s = 4 * j + wave, d = lane;   // element (s, d) of the padded 64 x 64 tile
+        const cf x = s < S && d < D ? wl[s * D + d] : cf{0.f, 0.f};
+        const __bf16 hr = (__bf16)x.re, hi_ = (__bf16)x.im;
+        const __bf16 lr = (__bf16)(x.re - (float)hr), li = (__bf16)(x.im - (float)hi_);
+        Bhi[d * kAdjBfPitch + s] = (unsigned)__builtin_bit_cast(unsigned short, hr) |
+                                   ((unsigned)__builtin_bit_cast(unsigned short, hi_) << 16);
+        Blo[d * kAdjBfPitch + s] = (unsigned)__builtin_bit_cast(unsigned short, lr) |
+                                   ((unsigned)__builtin_bit_cast(unsigned short, li) << 16);
+      }
+    }
+    __syncthreads();
+    const __amdgpu_buffer_rsrc_t rs = wide_rsrc(phs + (size_t)l * lam_stride * N, (uint32_t)S * rowb);
+    const __amdgpu_buffer_rsrc_t rd = wide_rsrc(phd + (size_t)l * lam_stride * N, (uint32_t)D * rowb);
+#pragma unroll 1
+    for (int p = 0; p < 2; ++p) {
+      const int tb = wbase + 32 * p;   // first voxel of the pass's two tiles
+      u32x4 a[2][4];                   // [tile][k-step]: words of sources 16q + 4g + i at voxel r
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const int v = tb + 16 * mt + r16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int s = 16 * q + 4 * g + i;
+            const uint32_t off = s < S && v < N ? (uint32_t)s * rowb + (uint32_t)v * 4u : kWideOut;
+            a[mt][q][i] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+          }
+      }
+      u32x4 ph[2][4];                  // [tile][detector tile]: words of voxels 4g + j at detector 16t + r
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const int v0 = tb + 16 * mt + 4 * g;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int d = 16 * t + r16;
+          if (VEC) {
+            const uint32_t off = d < D && v0 < N ? (uint32_t)d * rowb + (uint32_t)v0 * 4u : kWideOut;
+            ph[mt][t] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rd, off, 0, 0));
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const uint32_t off = d < D && v0 + j < N ? (uint32_t)d * rowb + (uint32_t)(v0 + j) * 4u : kWideOut;
+              ph[mt][t][j] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rd, off, 0, 0);
+            }
+          }
+        }
+      }
+      f32x4 accR[2][4], accI[2][4];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          accR[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+          accI[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      // the (k-step, detector tile) operands from LDS one step ahead of their products; the
+      // scheduling barrier keeps the reads from being hoisted further (their registers)
+      auto lds_op = [&](int it, u32x4& h, u32x4& lo) {
+        const int o = (16 * (it & 3) + r16) * kAdjBfPitch + 16 * (it >> 2) + 4 * g;
+        h = *reinterpret_cast<const u32x4*>(&Bhi[o]);
+        lo = *reinterpret_cast<const u32x4*>(&Blo[o]);
+      };
+      u32x4 nbh, nbl;
+      lds_op(0, nbh, nbl);
+#pragma unroll
+      for (int it = 0; it < 16; ++it) {
+        const int q = it >> 2, t = it & 3;
+        const u32x4 bh = nbh, bl = nbl;
+        if (it + 1 < 16) lds_op(it + 1, nbh, nbl);
+        u32x4 ih, il;   // B_im words: halves swapped, the new upper half negated
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          ih[i] = __builtin_amdgcn_alignbit(bh[i], bh[i], 16) ^ 0x80000000u;
+          il[i] = __builtin_amdgcn_alignbit(bl[i], bl[i], 16) ^ 0x80000000u;
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          const wbf16x8 av = __builtin_bit_cast(wbf16x8, a[mt][q]);
+          accR[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(wbf16x8, bh), accR[mt][t], 0, 0, 0);
+          accI[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(wbf16x8, ih), accI[mt][t], 0, 0, 0);
+          accR[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(wbf16x8, bl), accR[mt][t], 0, 0, 0);
+          accI[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(wbf16x8, il), accI[mt][t], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // conj(phi_d) T in FP64: accumulator entry j of lane (r, g) is voxel 4g + j, detector 16t + r
+      double er[2][4], ei[2][4];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          er[mt][j] = ei[mt][j] = 0.0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const unsigned x = ph[mt][t][j];
+            const double e = __builtin_bit_cast(float, x << 16), f = __builtin_bit_cast(float, x & 0xffff0000u);
+            const double tr = (double)accR[mt][t][j], ti = (double)accI[mt][t][j];
+            er[mt][j] += e * tr + f * ti;
+            ei[mt][j] += e * ti - f * tr;
+          }
+        }
+      // added to the pass's own registers by a uniform branch (the pass loop stays rolled)
+      if (p == 0) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            gre[0][mt][j] += er[mt][j];
+            gim[0][mt][j] += ei[mt][j];
+          }
+      } else {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            gre[1][mt][j] += er[mt][j];
+            gim[1][mt][j] += ei[mt][j];
+          }
+      }
+    }
+  }
+  // sum over the 16 detector lanes of each voxel
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+          gre[p][mt][j] += __shfl_xor(gre[p][mt][j], off, 64);
+          gim[p][mt][j] += __shfl_xor(gim[p][mt][j], off, 64);
+        }
+      }
+  if (r16 == 0) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int vv = wbase + 32 * p + 16 * mt + 4 * g + j;
+          if (vv < N) gout[vv] = cf{(float)(scale * gre[p][mt][j]), (float)(scale * gim[p][mt][j])};
+        }
+  }
+}
+
 }  // namespace hydot

@@ -224,6 +224,34 @@ def test_born_bf16_wide(hd, mode, S, D, n_v, grid):
     assert normwise(y, ref) < (2e-2 if mode == "bf16" else 1e-4)
 
 
+@pytest.mark.parametrize("grid", [(20, 13, 7), (16, 10, 8)])        # N = 1820 (ragged), 1280 (16-byte loads)
+@pytest.mark.parametrize("S,D,n_w", [(33, 47, 1), (64, 64, 2), (48, 64, 1)])
+def test_born_adjoint_bf16_wide(hd, S, D, n_w, grid):
+    """J^H w from BF16-stored fields with more than 32 sources and detectors (BF16 MFMA, w split
+    into BF16 hi + lo): every voxel against the FP64 products of the stored fields and the
+    unrounded w, within 2e-5 of the absolute sum of its terms (the split's 2^-18 and FP32 sums
+    over the sources); stated error against the unrounded fields."""
+    nx, ny, nz = grid
+    w = workloads.config("tiny", nx=nx, ny=ny, nz=nz, n_lambda=3)
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(71 + S + D + nx)
+    P = rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))
+    t = to_bf16_pairs(P).to(DEV)
+    Pr = from_bf16_pairs(t.cpu())
+    W = (rng.standard_normal((n_w, w.L, S, D)) + 1j * rng.standard_normal((n_w, w.L, S, D))).astype(np.complex64)
+    g = hd.born_apply_adjoint(op, t[:, :S], t[:, S:], torch.from_numpy(W).to(DEV)).cpu().numpy()
+    assert g.shape == (n_w, w.N)
+    Wd = W.astype(np.complex128)
+    for c in range(n_w):
+        exp = oborn.born_apply_adjoint(Pr[:, :S], Pr[:, S:], Wd[c], w.h)
+        absum = w.h ** 3 * np.einsum("lsk,lsd,ldk->k", np.abs(Pr[:, :S]), np.abs(Wd[c]), np.abs(Pr[:, S:]),
+                                     optimize=True)
+        err = np.abs(g[c].astype(np.complex128) - exp)
+        assert np.all(err <= 2e-5 * absum), float((err / absum).max())
+        ref = oborn.born_apply_adjoint(P[:, :S], P[:, S:], Wd[c], w.h)
+        assert normwise(g[c].astype(np.complex128), ref) < 2e-2
+
+
 def test_split_bf16_rejects_other_fields(hd, tiny):
     w, ref = tiny
     op = hd.Operator.from_workload(w)
