@@ -711,7 +711,15 @@ struct Solver {
       const dim3 gt((unsigned)(nb * p.nchunks)), gr(nb);
       const hydot_tuning tu = resolved_tuning(op->tune, &op->gp);
       const int fl = step_flags(tu);
-      if (tu.step_presum == 4 || tu.step_presum == 16)
+      const bool plain = c.mu == nullptr && c.Z == nullptr;
+      // the chunk-accumulating form under the same conditions as the step kernels' (rows of at
+      // most one sub-tile), with the same exact-k and plain instances
+      if (tu.step_presum == 16 && op->gp.nx <= kTSub) {
+        if (c.k == 5 && plain) hipLaunchKernelGGL((k_inner_resid_acc<5, true>), gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
+        else if (c.k == 5) hipLaunchKernelGGL((k_inner_resid_acc<5, false>), gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
+        else if (c.k == 10) hipLaunchKernelGGL((k_inner_resid_acc<10, false>), gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
+        else hipLaunchKernelGGL((k_inner_resid_acc<0, false>), gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
+      } else if (tu.step_presum == 4 || tu.step_presum == 16)
         hipLaunchKernelGGL(k_inner_resid_t<4>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
       else if (tu.step_presum == 2) hipLaunchKernelGGL(k_inner_resid_t<2>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);
       else hipLaunchKernelGGL(k_inner_resid_t<1>, gt, dim3(kTSub), 0, stream, c, tile_grp, fl);

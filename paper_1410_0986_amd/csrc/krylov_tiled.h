@@ -970,6 +970,112 @@ __global__ __launch_bounds__(kTSub) void k_inner_resid_t(Ctx<cf> c, int grp, int
   row_flush_all<4>(c, sys, ti.chunk, 0, k + 1, acc);
 }
 
+// Cycle start, first half in the chunk-accumulating form of the step kernels (x rows of at most
+// one sub-tile): W = Rin - A_hat Din with the stencil centres of Din through the four-sub-tile LDS
+// ring (each loaded once, one sub-tile ahead; only the z neighbours are loaded besides), FP32
+// running sums of conj(C'_i) W and |W|^2 per thread over its 16 voxels and one block reduction
+// per chunk into the rows of k_inner_resid_t (rows [0, k) C', row k the norm).  KX, PL as the
+// step kernels.
+template <int KX, bool PL>
+__global__ __launch_bounds__(kTSub) void k_inner_resid_acc(Ctx<cf> c, int grp, int flags) {
+  static_assert(KX >= 0 && KX <= kTK, "exact deflation dimension out of range");
+  constexpr bool EX = KX > 0;
+  constexpr int KM = EX ? KX : kTK;
+  __shared__ ProdTile<4> pt;
+  __shared__ cf xs[4][kTSub];
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags);
+  const int sys = ti.sys;
+  if (!c.st[sys].in_inner) return;
+  const size_t N = (size_t)c.g.N;
+  const int k = EX ? KX : c.k, t = threadIdx.x;
+  const SysParam p = c.prm[sys];
+  const SysBuf bf = PL ? sys_buf_plain(c, sys, p.rhs) : sys_buf(c, sys, p.rhs);
+  const Rsrc rD = make_rsrc(c.Din + (size_t)sys * N, bf.sv), rR = make_rsrc(c.Rin + (size_t)sys * N, bf.sv);
+  cf* wv = c.W + (size_t)sys * N;
+  const uint32_t Nu = (uint32_t)c.g.N, sz = (uint32_t)c.g.nx * (uint32_t)c.g.ny;
+  const SysF q = sys_f(c.g, p);
+  const ScaledOp qs = scaled_op(c.g, q, 1.f);
+  float cr[KM], ur[KM];
+  cf rin{0.f, 0.f}, c_ahead{0.f, 0.f};
+  StencilRegs sreg;
+  VoxelInfo vinf;
+  float muv;
+  auto fetch = [&](uint32_t n) {
+    const bool ok = n < Nu;
+    load_cu_k<KM, EX>(bf, k, ok ? n * 4u : kOutside, cr, ur);
+    vinf = voxel_info(c.g, ok ? n : 0u);
+    muv = mu_at(bf, ok ? n * 4u : kOutside);
+    sreg.m[4] = ld_cf(rD, ok && vinf.k > 0 ? (n - sz) * 8u : kOutside, 0u);
+    sreg.m[5] = ld_cf(rD, ok && vinf.k < c.g.nz - 1 ? (n + sz) * 8u : kOutside, 0u);
+    const uint32_t na = n + kTSub;   // centre of the sub-tile after the one being fetched
+    c_ahead = ld_cf(rD, na < Nu ? na * 8u : kOutside, 0u);
+    rin = ld_cf(rR, ok ? n * 8u : kOutside, 0u);
+  };
+  cf ac[KM], au[KM], an{0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < KM; ++i) ac[i] = au[i] = cf{0.f, 0.f};
+  const uint32_t n0 = (uint32_t)ti.chunk * kChunk;
+  {
+    const uint32_t nm = n0 + (uint32_t)t - kTSub, nc = n0 + (uint32_t)t;
+    xs[3][t] = ld_cf(rD, n0 >= (uint32_t)kTSub && nm < Nu ? nm * 8u : kOutside, 0u);
+    xs[0][t] = ld_cf(rD, nc < Nu ? nc * 8u : kOutside, 0u);
+  }
+  fetch(n0 + t);
+  constexpr int nsub = kChunk / kTSub;
+  for (int sub = 0; sub < nsub; ++sub) {
+    const uint32_t n = n0 + sub * kTSub + t;
+    const bool ok = n < Nu;
+    xs[(sub + 1) & 3][t] = c_ahead;
+    __syncthreads();
+    const int bp = (sub + 3) & 3, bc = sub & 3, bn = (sub + 1) & 3;
+    const int nxg = c.g.nx, lane = t & 63;
+    sreg.xc = xs[bc][t];
+    const int ym = t - nxg, yp = t + nxg;
+    const cf vym = xs[ym >= 0 ? bc : bp][ym >= 0 ? ym : ym + kTSub];
+    const cf vyp = xs[yp < kTSub ? bc : bn][yp < kTSub ? yp : yp - kTSub];
+    const bool hy0 = vinf.j > 0, hy1 = vinf.j < c.g.ny - 1;
+    sreg.m[2] = cf{hy0 ? vym.re : 0.f, hy0 ? vym.im : 0.f};
+    sreg.m[3] = cf{hy1 ? vyp.re : 0.f, hy1 ? vyp.im : 0.f};
+    if (lane == 0) {
+      const cf v = xs[t > 0 ? bc : bp][t > 0 ? t - 1 : kTSub - 1];
+      const bool hx = vinf.i > 0;
+      sreg.m[0] = cf{hx ? v.re : 0.f, hx ? v.im : 0.f};
+    }
+    if (lane == 63) {
+      const cf v = xs[t + 1 < kTSub ? bc : bn][t + 1 < kTSub ? t + 1 : 0];
+      const bool hx = vinf.i < nxg - 1;
+      sreg.m[1] = cf{hx ? v.re : 0.f, hx ? v.im : 0.f};
+    }
+    stencil_x_from_lanes(c.g, vinf, sreg);   // every lane (no divergence yet)
+    if (ok) {
+      const float shr = q.sig_re + q.sigp_rel_h * (float)vinf.nrobin + q.tau_rel * muv;
+      const cf ad = stencil_apply_f(sreg, vinf, qs, muv);
+      const cf w{rin.re - ad.re, rin.im - ad.im};
+      wv[n] = w;
+#pragma unroll
+      for (int i = 0; i < KM; ++i)
+        if (EX || i < k) {
+          const float a = __builtin_fmaf(shr, ur[i], cr[i]);
+          ac[i].re = __builtin_fmaf(a, w.re, ac[i].re);
+          ac[i].im = __builtin_fmaf(a, w.im, ac[i].im);
+          au[i].re = __builtin_fmaf(ur[i], w.re, au[i].re);
+          au[i].im = __builtin_fmaf(ur[i], w.im, au[i].im);
+        }
+      an.re += w.re * w.re + w.im * w.im;
+    }
+    if (sub + 1 < nsub) fetch(n + kTSub);
+  }
+  const float shi = q.sig_im;
+#pragma unroll
+  for (int i = 0; i < KM; ++i)
+    if (EX || i < k) put_product<4>(pt, i, cf{ac[i].re + shi * au[i].im, ac[i].im - shi * au[i].re});
+  put_product<4>(pt, k, an);
+  __syncthreads();
+  cd acc{0.0, 0.0};
+  row_reduce<4, 4>(pt, k + 1, acc);
+  row_flush_all<4>(c, sys, ti.chunk, 0, k + 1, acc);
+}
+
 // Cycle start, second half (tiled form of k_defl_start): with g = G^-1 f,
 // W <- W - C'g, Din += U g, V_0 = W (stored unnormalised), |V_0|^2 as chunk partials.
 __global__ __launch_bounds__(kTSub) void k_defl_start_t(Ctx<cf> c, int grp, int flags) {
