@@ -424,11 +424,18 @@ hydot_status hydot_misfit(const hydot_operator* op, int32_t S, int32_t D, const 
  *   born_blocks  J v target grid size in blocks (split over voxels), 256..65536 (default 4096).
  *   step_vx      Arnoldi step kernels, up to 16 basis vectors: voxels per thread per sub-tile,
  *                1 or 2 (2 only with step_presum 4); their terms are summed in registers before
- *                the pre-sum (default 1). */
+ *                the pre-sum (default 1).
+ *   step_pair    2: with step_presum 16, the Arnoldi step kernels of systems without an absorption
+ *                perturbation or a preconditioner take two wavelengths of one right-hand side per
+ *                block, loading the C and U they share once (batches of whole right-hand sides
+ *                with an even number of wavelengths; results identical with the instances for
+ *                k = 5, equal to rounding otherwise); 1: one system per block
+ *                (default 2). */
 typedef struct {
   int32_t step_presum, step_order, step_group;
   int32_t born_stage, born_blocks;
   int32_t step_vx;
+  int32_t step_pair;
 } hydot_tuning;
 hydot_status hydot_get_tuning(const hydot_operator* op, hydot_tuning* out);   /* resolved values */
 hydot_status hydot_set_tuning(hydot_operator* op, const hydot_tuning* t);      /* EINVAL if out of range */

@@ -124,7 +124,8 @@ _peaks = _proto("hydot_measure_peaks", c_int32, c_void_p, c_size_t, POINTER(_Pea
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("step_presum", c_int32), ("step_order", c_int32), ("step_group", c_int32),
-                ("born_stage", c_int32), ("born_blocks", c_int32), ("step_vx", c_int32)]
+                ("born_stage", c_int32), ("born_blocks", c_int32), ("step_vx", c_int32),
+                ("step_pair", c_int32)]
 
 
 class _Trial(ctypes.Structure):
@@ -140,7 +141,7 @@ _tune_born = _proto("hydot_autotune_born", c_int32, c_void_p, c_void_p, c_int32,
                     c_void_p)
 _tune_born_ws = _proto("hydot_autotune_born_workspace_bytes", c_int32, c_void_p, c_int32, c_int32, c_int32, c_int32,
                        POINTER(c_size_t))
-_TUNE_FIELDS = ("step_presum", "step_order", "step_group", "born_stage", "born_blocks", "step_vx")
+_TUNE_FIELDS = ("step_presum", "step_order", "step_group", "born_stage", "born_blocks", "step_vx", "step_pair")
 
 
 class _KProf(ctypes.Structure):

@@ -187,6 +187,7 @@ inline int step_flags(const hydot_tuning& tu) {
 ProfRec g_rec[3] = {{"k_step_dots", 0, 0.0, 0.0}, {"k_step_update", 0, 0.0, 0.0}, {"k_step_finish", 0, 0.0, 0.0}};
 const char* kTiledNames[3] = {"k_step_dots_t", "k_step_update_t", "k_step_finish_t"};
 const char* kGenericNames[3] = {"k_step_dots", "k_step_update", "k_step_finish"};
+const char* kPairNames[3] = {"k_step_pair_t<dots>", "k_step_pair_t<update>", "k_step_finish_t"};
 
 struct Plan {
   int R, L, N;
@@ -376,6 +377,8 @@ struct Solver {
 
   // systems per block group of the tiled kernels (see krylov_tiled.h)
   int tile_grp = 1;
+  // the batch holds whole right-hand sides with an even number of wavelengths, in order
+  bool pair_ok = false;
   PrecP pc{};   // separable preconditioner (p.precond != 0)
 
   // P^{-1} applied to one vector per system: in (system stride in_stride) -> Z
@@ -396,6 +399,7 @@ struct Solver {
     }
   }
   bool used_tiled = false;   // the last cycle ran the register-resident FP32 kernels
+  bool used_pairs = false;   // ... in their two-system form
 
   // event pairs around the step kernels of one cycle (profiling only)
   std::vector<hipEvent_t> ev;
@@ -426,7 +430,7 @@ struct Solver {
         if (kind == 2 && j + 1 >= p.mk) continue;   // no finish after the last step
         float ms = 0.f;
         HYDOT_HIP(hipEventElapsedTime(&ms, ev[2 * (3 * j + kind)], ev[2 * (3 * j + kind) + 1]));
-        g_rec[kind].name = used_tiled ? kTiledNames[kind] : kGenericNames[kind];
+        g_rec[kind].name = used_pairs ? kPairNames[kind] : used_tiled ? kTiledNames[kind] : kGenericNames[kind];
         g_rec[kind].launches += 1;
         g_rec[kind].ms += ms;
         g_rec[kind].bytes += (act_k[kind] * extra[kind] + rhs_k[kind] * k) * N * b;
@@ -681,7 +685,33 @@ struct Solver {
     case 13: { HYDOT_STEP_P(KER, 13) } break; case 14: { HYDOT_STEP_P(KER, 14) } break;                   \
     case 15: { HYDOT_STEP_P(KER, 15) } break; default: { HYDOT_STEP_P(KER, 16) } break;                   \
   }
-        if (kind == 0) {
+        // two systems per block where they are plain and share their right-hand side
+        const bool pairs = kind != 2 && small && tu.step_pair == 2 && pair_ok && plain && rows_fit &&
+                           tu.step_presum == 16;
+        used_pairs = pairs;
+        if (pairs) {
+          const dim3 gp((unsigned)(nb / 2 * p.nchunks));
+          const int pg = tile_grp > 1 ? tile_grp / 2 : 1;
+#define HYDOT_PAIR(NV)                                                                                        \
+  if (kind == 0) {                                                                                            \
+    if (c.k == 5) hipLaunchKernelGGL((k_step_pair_t<NV, 0, 5>), gp, dim3(kTSub), 0, stream, c, j, pg, fl);     \
+    else hipLaunchKernelGGL((k_step_pair_t<NV, 0, 0>), gp, dim3(kTSub), 0, stream, c, j, pg, fl);              \
+  } else {                                                                                                    \
+    if (c.k == 5) hipLaunchKernelGGL((k_step_pair_t<NV, 1, 5>), gp, dim3(kTSub), 0, stream, c, j, pg, fl);     \
+    else hipLaunchKernelGGL((k_step_pair_t<NV, 1, 0>), gp, dim3(kTSub), 0, stream, c, j, pg, fl);              \
+  }
+          switch (j + 1) {
+            case 1: { HYDOT_PAIR(1) } break;   case 2: { HYDOT_PAIR(2) } break;
+            case 3: { HYDOT_PAIR(3) } break;   case 4: { HYDOT_PAIR(4) } break;
+            case 5: { HYDOT_PAIR(5) } break;   case 6: { HYDOT_PAIR(6) } break;
+            case 7: { HYDOT_PAIR(7) } break;   case 8: { HYDOT_PAIR(8) } break;
+            case 9: { HYDOT_PAIR(9) } break;   case 10: { HYDOT_PAIR(10) } break;
+            case 11: { HYDOT_PAIR(11) } break; case 12: { HYDOT_PAIR(12) } break;
+            case 13: { HYDOT_PAIR(13) } break; case 14: { HYDOT_PAIR(14) } break;
+            case 15: { HYDOT_PAIR(15) } break; default: { HYDOT_PAIR(16) } break;
+          }
+#undef HYDOT_PAIR
+        } else if (kind == 0) {
           if (small) { HYDOT_STEP_NV(k_step_dots_t) } else { HYDOT_STEP_P(k_step_dots_t, 32) }
         } else if (kind == 1) {
           if (small) { HYDOT_STEP_NV(k_step_update_t) } else { HYDOT_STEP_P(k_step_update_t, 32) }
@@ -697,6 +727,7 @@ struct Solver {
       }
     }
     used_tiled = false;
+    used_pairs = false;
     if (kind == 0) hipLaunchKernelGGL(k_step_dots<S>, gv, dim3(kBlock), 0, stream, c, j);
     else if (kind == 1) hipLaunchKernelGGL(k_step_update<S>, gv, dim3(kBlock), 0, stream, c, j);
     else hipLaunchKernelGGL(k_step_finish<S>, gv, dim3(kBlock), 0, stream, c, j);
@@ -831,11 +862,14 @@ struct Solver {
     Ctx<cd> c64 = ctx<cd>(p.k, false);   // FP64 views for residual and output kernels
     // group the wavelengths of one right-hand side when the batch holds whole ones
     tile_grp = 1;
+    pair_ok = false;
     const hydot_tuning tg = resolved_tuning(op->tune, &op->gp);
-    if (nb % p.L == 0 && (tg.step_group == 1 || tg.step_order == 4)) {
+    if (nb % p.L == 0) {
       bool aligned = true;
       for (int i = 0; i < nb && aligned; ++i) aligned = sys_l[i] == i % p.L && sys_r[i] == sys_r[i - i % p.L];
-      if (aligned) tile_grp = p.L;
+      if (aligned && (tg.step_group == 1 || tg.step_order == 4)) tile_grp = p.L;
+      // systems 2i and 2i + 1 share a right-hand side (two-system step kernels)
+      pair_ok = aligned && p.L % 2 == 0;
     }
     ReduceArgs ra{};
     ra.tol = o->rel_tol;

@@ -309,9 +309,12 @@ __device__ inline void stencil_x_from_lanes(const GridP& g, const VoxelInfo& vi,
   const int lane = threadIdx.x & 63;
   const cf prev{lane_prev(sr.xc.re), lane_prev(sr.xc.im)};
   const cf next{lane_next(sr.xc.re), lane_next(sr.xc.im)};
-  const cf z{0.f, 0.f};
-  sr.m[0] = lane == 0 ? sr.m[0] : (vi.i > 0 ? prev : z);
-  sr.m[1] = lane == 63 ? sr.m[1] : (vi.i < g.nx - 1 ? next : z);
+  // component selects (a select between two structs may be lowered through scratch memory)
+  const bool kp = lane == 0, hp = vi.i > 0, kn = lane == 63, hn = vi.i < g.nx - 1;
+  sr.m[0].re = kp ? sr.m[0].re : (hp ? prev.re : 0.f);
+  sr.m[0].im = kp ? sr.m[0].im : (hp ? prev.im : 0.f);
+  sr.m[1].re = kn ? sr.m[1].re : (hn ? next.re : 0.f);
+  sr.m[1].im = kn ? sr.m[1].im : (hn ? next.im : 0.f);
 }
 
 // y neighbours from other threads' centres (x rows of at most one sub-tile): every thread
@@ -848,6 +851,181 @@ __device__ inline void tiled_step_acc(const Ctx<cf>& c, int j, TileIdx ti) {
   cd acc{0.0, 0.0};
   row_reduce<4, 4>(pt, nrows, acc);
   row_flush_all<4>(c, sys, ti.chunk, nv, nrows, acc);
+}
+
+// Two systems per block (pairs of wavelengths of one right-hand side at one chunk): the form of
+// tiled_step_acc for plain systems (no absorption perturbation, no preconditioner) in which each
+// thread handles its voxel for both systems, so C and U, which the wavelengths of a right-hand
+// side share, are loaded once for the two.  The arithmetic of each system is that of
+// tiled_step_acc's plain instances (same operations in the same order, same block reduction), so
+// the results are identical to theirs.  A system that is not stepping is skipped (block-uniform
+// branches).
+template <int NV, int KIND, int KX>
+__device__ inline void tiled_step_acc2(const Ctx<cf>& c, int j, int sys0, int chunk) {
+  static_assert(NV >= 1 && NV <= 16, "chunk-accumulating instances hold 1 to 16 basis vectors");
+  static_assert(KX >= 0 && KX <= kTK, "exact deflation dimension out of range");
+  constexpr bool EX = KX > 0;
+  constexpr int KM = EX ? KX : kTK;
+  __shared__ ProdTile<4> pt;
+  __shared__ cf xs[2][4][kTSub];
+  const size_t N = (size_t)c.g.N;
+  const int k = EX ? KX : c.k, nv = NV, t = threadIdx.x;
+  const bool act[2] = {c.st[sys0].in_cycle != 0, c.st[sys0 + 1].in_cycle != 0};
+  const int rhs = c.prm[sys0].rhs;   // shared by the pair
+  const SysBuf bf = sys_buf_plain(c, sys0, rhs);   // C and U; the basis resources per system below
+  Rsrc rv[2];
+  cf* vnext[2];
+  float sjs[2];
+  SysF q[2];
+  ScaledOp qs[2];
+  cf g[2][KM], h[2][NV];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int sys = sys0 + s;
+    const SysParam p = c.prm[sys];
+    rv[s] = make_rsrc(c.V + (size_t)sys * c.vdim * N, (uint32_t)c.vdim * bf.sv);
+    vnext[s] = c.V + ((size_t)sys * c.vdim + j + 1) * N;
+    sjs[s] = (float)c.small[(size_t)sys * c.sl.total + c.sl.vs + j].re;
+    q[s] = sys_f(c.g, p);
+    qs[s] = scaled_op(c.g, q[s], sjs[s]);
+    if (KIND == 1) {
+      const cf* coef = reinterpret_cast<const cf*>(c.small + (size_t)sys * c.sl.total + c.sl.cA32);
+#pragma unroll
+      for (int i = 0; i < KM; ++i) g[s][i] = EX || i < k ? coef[i] : cf{0.f, 0.f};
+#pragma unroll
+      for (int l = 0; l < NV; ++l) h[s][l] = coef[k + l];
+    }
+  }
+  const bool with_norm = KIND == 1;
+  const int nrows = nv + k + (with_norm ? 1 : 0);
+  constexpr int nsub = kChunk / kTSub;
+  const uint32_t so = (uint32_t)j * bf.sv;   // V_j within a system's basis
+  const uint32_t Nu = (uint32_t)c.g.N, sz = (uint32_t)c.g.nx * (uint32_t)c.g.ny;
+  cf vr[2][NV];
+  float cr[KM], ur[KM];
+  cf c_ahead[2];
+  StencilRegs sreg[2];
+  VoxelInfo vinf;
+  auto fetch = [&](uint32_t n) {
+    const bool ok = n < Nu;
+    load_cu_k<KM, EX>(bf, k, ok ? n * 4u : kOutside, cr, ur);
+    vinf = voxel_info(c.g, ok ? n : 0u);
+    const uint32_t na = n + kTSub;   // centre of the sub-tile after the one being fetched
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (act[s]) {
+#pragma unroll
+        for (int l = 0; l + 1 < NV; ++l) vr[s][l] = ld_cf_nt(rv[s], ok ? n * 8u : kOutside, (uint32_t)l * bf.sv);
+        sreg[s].m[4] = ld_cf(rv[s], ok && vinf.k > 0 ? (n - sz) * 8u : kOutside, so);
+        sreg[s].m[5] = ld_cf(rv[s], ok && vinf.k < c.g.nz - 1 ? (n + sz) * 8u : kOutside, so);
+        c_ahead[s] = ld_cf(rv[s], na < Nu ? na * 8u : kOutside, so);
+      }
+    }
+  };
+  cf av[2][NV], ac[2][KM], au[2][KM], an[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    an[s] = cf{0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l < NV; ++l) av[s][l] = cf{0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < KM; ++i) ac[s][i] = au[s][i] = cf{0.f, 0.f};
+  }
+  const uint32_t n0 = (uint32_t)chunk * kChunk;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const uint32_t nm = n0 + (uint32_t)t - kTSub, nc = n0 + (uint32_t)t;
+    xs[s][3][t] = act[s] ? ld_cf(rv[s], n0 >= (uint32_t)kTSub && nm < Nu ? nm * 8u : kOutside, so) : cf{0.f, 0.f};
+    xs[s][0][t] = act[s] ? ld_cf(rv[s], nc < Nu ? nc * 8u : kOutside, so) : cf{0.f, 0.f};
+    c_ahead[s] = cf{0.f, 0.f};
+  }
+  fetch(n0 + t);
+  for (int sub = 0; sub < nsub; ++sub) {
+    const uint32_t n = n0 + sub * kTSub + t;
+    const bool ok = n < Nu;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) xs[s][(sub + 1) & 3][t] = c_ahead[s];
+    __syncthreads();
+    const int bp = (sub + 3) & 3, bc = sub & 3, bn = (sub + 1) & 3;
+    const int nxg = c.g.nx, lane = t & 63;
+    const int ym = t - nxg, yp = t + nxg;
+    const bool hy0 = vinf.j > 0, hy1 = vinf.j < c.g.ny - 1;
+    const bool hx0 = vinf.i > 0, hx1 = vinf.i < nxg - 1;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      sreg[s].xc = xs[s][bc][t];
+      vr[s][NV - 1] = sreg[s].xc;
+      const cf vym = xs[s][ym >= 0 ? bc : bp][ym >= 0 ? ym : ym + kTSub];
+      const cf vyp = xs[s][yp < kTSub ? bc : bn][yp < kTSub ? yp : yp - kTSub];
+      sreg[s].m[2] = cf{hy0 ? vym.re : 0.f, hy0 ? vym.im : 0.f};
+      sreg[s].m[3] = cf{hy1 ? vyp.re : 0.f, hy1 ? vyp.im : 0.f};
+      if (lane == 0) {
+        const cf v = xs[s][t > 0 ? bc : bp][t > 0 ? t - 1 : kTSub - 1];
+        sreg[s].m[0] = cf{hx0 ? v.re : 0.f, hx0 ? v.im : 0.f};
+      }
+      if (lane == 63) {
+        const cf v = xs[s][t + 1 < kTSub ? bc : bn][t + 1 < kTSub ? t + 1 : 0];
+        sreg[s].m[1] = cf{hx1 ? v.re : 0.f, hx1 ? v.im : 0.f};
+      }
+      stencil_x_from_lanes(c.g, vinf, sreg[s]);   // every lane (no divergence yet)
+    }
+    if (ok) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        if (!act[s]) continue;
+        const float shr = q[s].sig_re + q[s].sigp_rel_h * (float)vinf.nrobin, shi = q[s].sig_im;
+        cf w = stencil_apply_f(sreg[s], vinf, qs[s], 0.f);
+        if (KIND == 1) {
+          w = project_voxel_f<NV, KM, EX>(w, vr[s], cr, ur, g[s], h[s], k, shr, shi);
+          st_cf_nt(vnext[s] + n, w);
+        }
+#pragma unroll
+        for (int l = 0; l < NV; ++l) {
+          const cf v = vr[s][l];
+          av[s][l].re += v.re * w.re + v.im * w.im;
+          av[s][l].im += v.re * w.im - v.im * w.re;
+        }
+#pragma unroll
+        for (int i = 0; i < KM; ++i)
+          if (EX || i < k) {
+            const float a = __builtin_fmaf(shr, ur[i], cr[i]);
+            ac[s][i].re = __builtin_fmaf(a, w.re, ac[s][i].re);
+            ac[s][i].im = __builtin_fmaf(a, w.im, ac[s][i].im);
+            au[s][i].re = __builtin_fmaf(ur[i], w.re, au[s][i].re);
+            au[s][i].im = __builtin_fmaf(ur[i], w.im, au[s][i].im);
+          }
+        if (with_norm) an[s].re += w.re * w.re + w.im * w.im;
+      }
+    }
+    if (sub + 1 < nsub) fetch(n + kTSub);
+  }
+  // one block reduction per chunk and system, the product tile reused
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (!act[s]) continue;
+    if (s == 1) __syncthreads();   // the first system's rows have been read
+#pragma unroll
+    for (int l = 0; l < NV; ++l) put_product<4>(pt, l, av[s][l]);
+    const float shi = q[s].sig_im;
+#pragma unroll
+    for (int i = 0; i < KM; ++i)
+      if (EX || i < k) put_product<4>(pt, nv + i, cf{ac[s][i].re + shi * au[s][i].im, ac[s][i].im - shi * au[s][i].re});
+    if (with_norm) put_product<4>(pt, nv + k, an[s]);
+    __syncthreads();
+    cd acc{0.0, 0.0};
+    row_reduce<4, 4>(pt, nrows, acc);
+    row_flush_all<4>(c, sys0 + s, chunk, nv, nrows, acc);
+  }
+}
+
+// The two-system step kernels: block b takes the pair (2i, 2i + 1) of tile_map's index i over
+// nb / 2 pairs in groups of grp pairs (half the wavelengths of one right-hand side, or 1).
+template <int NV, int KIND, int KX>
+__global__ __launch_bounds__(kTSub) void k_step_pair_t(Ctx<cf> c, int j, int grp, int flags) {
+  const TileIdx ti = tile_idx(c.nchunks, grp, flags);
+  const int sys0 = 2 * ti.sys;
+  if (!c.st[sys0].in_cycle && !c.st[sys0 + 1].in_cycle) return;
+  tiled_step_acc2<NV, KIND, KX>(c, j, sys0, ti.chunk);
 }
 
 // w = A_hat V_j and first-pass inner products (tiled form of k_step_dots); w is stored as W

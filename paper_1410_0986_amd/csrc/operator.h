@@ -33,7 +33,7 @@ struct hydot_operator {
   mutable double pc_sigp = 0.0;
   mutable bool pc_valid = false;
   ~hydot_operator();
-  hydot_tuning tune{0, 0, 0, 0, 0, 0};  // launch shapes; 0 = library default
+  hydot_tuning tune{0, 0, 0, 0, 0, 0, 0};  // launch shapes; 0 = library default
 };
 
 namespace hydot {

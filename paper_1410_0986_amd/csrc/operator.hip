@@ -70,6 +70,7 @@ hydot_tuning resolved_tuning(const hydot_tuning& t, const GridP* g) {
   if (r.step_group == 0) r.step_group = 2;
   if (r.born_blocks == 0) r.born_blocks = 4096;
   if (r.step_vx == 0) r.step_vx = 1;
+  if (r.step_pair == 0) r.step_pair = 2;
   return r;   // born_stage 0 stays: chosen per call from the LDS footprint
 }
 
@@ -198,7 +199,8 @@ hydot_status hydot_set_tuning(hydot_operator* op, const hydot_tuning* t) {
                   (t->step_order >= 0 && t->step_order <= 4) && (t->step_group >= 0 && t->step_group <= 2) &&
                   (t->born_stage == 0 || t->born_stage == 16 || t->born_stage == 32) &&
                   (t->born_blocks == 0 || (t->born_blocks >= 256 && t->born_blocks <= 65536)) &&
-                  (t->step_vx >= 0 && t->step_vx <= 2) && !(t->step_vx == 2 && t->step_presum != 4);
+                  (t->step_vx >= 0 && t->step_vx <= 2) && !(t->step_vx == 2 && t->step_presum != 4) &&
+                  (t->step_pair >= 0 && t->step_pair <= 2);
   if (!ok) return hydot::fail(HYDOT_EINVAL, "set_tuning: field out of range");
   op->tune = *t;
   return HYDOT_OK;

@@ -223,12 +223,13 @@ def test_tuning_defaults_and_validation(hd):
     op = _op(hd, workloads.config("tiny"))
     t = hd.get_tuning(op)
     assert t == {"step_presum": 16, "step_order": 3, "step_group": 2, "born_stage": 0, "born_blocks": 4096,
-                 "step_vx": 1}
+                 "step_vx": 1, "step_pair": 2}
     hd.set_tuning(op, step_presum=4, step_order=1, born_stage=16, born_blocks=1024)
     t = hd.get_tuning(op)
     assert (t["step_presum"], t["step_order"], t["born_stage"], t["born_blocks"]) == (4, 1, 16, 1024)
     for bad in (dict(step_presum=3), dict(step_order=5), dict(step_group=-1), dict(born_stage=64),
-                dict(born_blocks=100), dict(born_blocks=1 << 17), dict(step_vx=3), dict(step_vx=2, step_presum=2)):
+                dict(born_blocks=100), dict(born_blocks=1 << 17), dict(step_vx=3), dict(step_vx=2, step_presum=2),
+                dict(step_pair=3), dict(step_pair=-1)):
         with pytest.raises(hd.HydotError) as e:
             hd.set_tuning(op, **bad)
         assert e.value.status == hd.EINVAL
