@@ -67,10 +67,10 @@ WORKLOADS = {
 # factors of a device copy of known size), keyed by workload.  They belong to the kernel sources
 # with this SHA-256 (common.h, krylov_index.h, krylov_kernels.h, krylov_tiled.h) and to the launch shape
 # TRAFFIC_TUNING; after any change of either the traffic is reported as null.
-TRAFFIC_SOURCES_SHA256 = "172c253df43573e0192a2fd1037d618b0c4331a091a5aa61eec66b56a54d33c3"
-TRAFFIC_TUNING = {"step_presum": 16, "step_group": 2, "step_vx": 1, "step_order": 4}
+TRAFFIC_SOURCES_SHA256 = "ea2a412b68babc8261a5658dc07573b9bc6592c9961b0c35b440d362c874e740"
+TRAFFIC_TUNING = {"step_presum": 16, "step_group": 2, "step_vx": 1, "step_order": 4, "step_pair": 2}
 TRAFFIC_BYTES_PER_LAUNCH: dict = {   # workload -> kernel -> calibrated HBM bytes per launch (main grid)
-    "large": {"k_step_update_t": 20764339196, "k_step_dots_t": 17696763357},
+    "large": {"k_step_pair_t<update>": 20735429937, "k_step_pair_t<dots>": 17688562392},
 }
 
 
