@@ -499,7 +499,7 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide_bf(int N, int S, int D,
 constexpr int kWPitch = 66;    // LDS row pitch of w (complex elements)
 
 template <bool VEC>
-__global__ __launch_bounds__(kBlock) void k_born_adjoint_wide(int N, int S, int D, int64_t lam_stride, int L,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_born_adjoint_wide(int N, int S, int D, int64_t lam_stride, int L,
                                                              const cf* __restrict__ phs,
                                                              const cf* __restrict__ phd,
                                                              const cf* __restrict__ w, double scale,
@@ -511,21 +511,13 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint_wide(int N, int S, int 
   const int vox = vox0 + r16;               // A row of this lane
   const bool vok = vox < N;
   const size_t Nz = (size_t)N;
-  // w_l staging: thread tid holds the 16 elements e = tid + 256 j of the 64 x 64 padded tile
-  cf wreg[16];
-  auto fetch_w = [&](int l) {
+  // w_l staging: thread tid copies the 16 elements e = tid + 256 j of the 64 x 64 padded tile
+  auto stage_w = [&](int l) {
     const cf* wl = w + (size_t)l * S * D;
-#pragma unroll
+#pragma unroll 4
     for (int j = 0; j < 16; ++j) {
       const int e = tid + 256 * j, s = e >> 6, d = e & 63;
-      wreg[j] = s < S && d < D ? wl[s * D + d] : cf{0.f, 0.f};
-    }
-  };
-  auto store_w = [&]() {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int e = tid + 256 * j, s = e >> 6, d = e & 63;
-      Ws[s * kWPitch + d] = wreg[j];
+      Ws[s * kWPitch + d] = s < S && d < D ? wl[s * D + d] : cf{0.f, 0.f};
     }
   };
   // sources s = g + 4q of this lane's voxel
@@ -564,18 +556,14 @@ __global__ __launch_bounds__(kBlock) void k_born_adjoint_wide(int N, int S, int 
   double gre[4], gim[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) gre[r] = gim[r] = 0.0;
-  fetch_w(0);
   fetch_s(0, za);
   for (int l = 0; l < L; ++l) {
     __syncthreads();          // the previous wavelength's reads of Ws are done
-    store_w();
+    stage_w(l);
     __syncthreads();
     cf ph[4][4];
     fetch_d(l, ph);           // used by the epilogue, after the products
-    if (l + 1 < L) {
-      fetch_w(l + 1);
-      fetch_s(l + 1, zn);
-    }
+    if (l + 1 < L) fetch_s(l + 1, zn);
     f32x4 accR[4], accI[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
