@@ -70,7 +70,7 @@ WORKLOADS = {
 TRAFFIC_SOURCES_SHA256 = "ea2a412b68babc8261a5658dc07573b9bc6592c9961b0c35b440d362c874e740"
 TRAFFIC_TUNING = {"step_presum": 16, "step_group": 2, "step_vx": 1, "step_order": 4, "step_pair": 2}
 TRAFFIC_BYTES_PER_LAUNCH: dict = {   # workload -> kernel -> calibrated HBM bytes per launch (main grid)
-    "large": {"k_step_pair_t<update>": 20735429937, "k_step_pair_t<dots>": 17688562392},
+    "large": {"k_step_pair_t<update>": 20738055511, "k_step_pair_t<dots>": 17695971737},
 }
 
 
