@@ -486,9 +486,13 @@ hydot_status hydot_autotune_born(hydot_operator* op, const void* phi_src, int32_
  * shared by the wavelengths of a right-hand side, so they count once per right-hand side.
  * The complex FP32 kernels for up to 16 basis vectors without a preconditioner keep the
  * work vector W = A v_j out of memory (the update recomputes it from the stencil of V_j):
- * there dots (A*(j+1) + R'*k)*N*b and update (A*(j+2) + R'*k)*N*b.
+ * there dots (A*(j+1) + R'*k)*N*b and update (A*(j+2) + R'*k)*N*b.  Record names: the kernel
+ * of the last solve's form ("k_step_dots_t", "k_step_update_t", "k_step_finish_t"; with two
+ * systems per block "k_step_pair_t<dots>", "k_step_pair_t<update>"; "k_step_dots" etc. for
+ * the generic kernels).
  * Enabling resets the counters; the graph flag is ignored while enabled (launches are
- * timed one by one).  Process-wide; not thread-safe. */
+ * timed one by one).  Process-wide; not thread-safe (hydot_solve_fields_batch runs its
+ * problems one after another while it is enabled). */
 typedef struct {
   char name[32];
   int64_t launches;
