@@ -446,6 +446,10 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide_bf(int N, int S, int D,
     fetch(kstep(1), q1);
   }
   for (int st0 = 0; st0 < nst; st0 += NS) {
+    // the four waves stay within one FP32 stage of each other, so that the second read of a row
+    // shared by two waves finds it in the cache (1.0x instead of 1.27-1.33x the field bytes
+    // fetched; the FP32-MFMA kernel is slower with it and has none)
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < NS; u += 2) {
       step(st0 + u, q0);
