@@ -314,7 +314,7 @@ __device__ inline f32x4 bf_mac(wbf16x8 xh, wbf16x8 xl, wbf16x8 yh, wbf16x8 yl, f
 }
 
 template <typename TS, int CM, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_born_jv_wide_bf(int N, int S, int D, int64_t lam_stride,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_born_jv_wide_bf(int N, int S, int D, int64_t lam_stride,
                                                            const TS* __restrict__ phs, const TS* __restrict__ phd,
                                                            const float* __restrict__ v, int kb, int L,
                                                            double* __restrict__ part) {
@@ -385,7 +385,12 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide_bf(int N, int S, int D,
     }
   };
   f32x4 accR[2][2], accI[2][2];
-  double totR[2][2][4], totI[2][2][4];
+  // FP64 running sums in LDS, one slot per (wave, tile, entry, part) and lane: their registers
+  // hold loads in flight instead
+  __shared__ double tot[4 * 2 * 2 * 4 * 2 * 64];
+  auto tslot = [&](int ta, int tb, int r, int part) {
+    return ((((wave * 2 + ta) * 2 + tb) * 4 + r) * 2 + part) * 64 + lane;
+  };
 #pragma unroll
   for (int ta = 0; ta < 2; ++ta)
 #pragma unroll
@@ -393,13 +398,15 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide_bf(int N, int S, int D,
       accR[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
       accI[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) totR[ta][tb][r] = totI[ta][tb][r] = 0.0;
+      for (int r = 0; r < 4; ++r) tot[tslot(ta, tb, r, 0)] = tot[tslot(ta, tb, r, 1)] = 0.0;
     }
-  // BF16 operands of step st from its raw words, then (BF16 storage) the loads of step st + 2 into
-  // the same buffer, then the products; steps alternate between two buffers
-  // BF16 storage: the raw words of step st + 2 are loaded while step st runs (two waves per SIMD);
-  // the split's FP32 rows would leave one, so it loads each step's words at its start
+  // BF16 operands of step st from its raw words, then (BF16 storage) the loads of step
+  // st + kDepth into the same buffer, then the products; steps rotate over kDepth buffers
+  // BF16 storage: the raw words of the next kDepth steps are in flight while step st runs (two
+  // waves per SIMD); the split's FP32 rows would leave one, so it loads each step's words at
+  // its start
   constexpr bool kPrefetch = CM == CM_BF16;
+  constexpr int kDepth = VEC ? 4 : 2;   // element loads (any N) take more registers
   auto step = [&](int st, Step& q) {
     if (!kPrefetch) fetch(kstep(st), q);
     BfOps<TS, CM> A[2], An[2], B[2];
@@ -425,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide_bf(int N, int S, int D,
         B[t] = bf_ops<TS, CM>(xr, xi);
       }
     }
-    if (kPrefetch) fetch(kstep(st + 2), q);   // past the range it reads zeros
+    if (kPrefetch) fetch(kstep(st + kDepth), q);   // past the range it reads zeros
     // Re y += Re a Re b - Im a Im b, Im y += Re a Im b + Im a Re b
 #pragma unroll
     for (int tb = 0; tb < 2; ++tb)
@@ -440,10 +447,11 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide_bf(int N, int S, int D,
   // whole FP32 stages of NS steps (a partial last stage runs its missing steps on zeros)
   constexpr int NS = wide_bf_ns<CM>();
   const int nst = k1 > k0 ? (k1 - k0 + 31) / 32 : 0;
-  Step q0, q1;
+  static_assert(NS % kDepth == 0, "stages hold whole rotations of the step buffers");
+  Step q[kDepth];
   if (kPrefetch) {
-    fetch(kstep(0), q0);
-    fetch(kstep(1), q1);
+#pragma unroll
+    for (int u = 0; u < kDepth; ++u) fetch(kstep(u), q[u]);
   }
   for (int st0 = 0; st0 < nst; st0 += NS) {
     // the four waves stay within one FP32 stage of each other, so that the second read of a row
@@ -451,18 +459,15 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide_bf(int N, int S, int D,
     // fetched; the FP32-MFMA kernel is slower with it and has none)
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < NS; u += 2) {
-      step(st0 + u, q0);
-      step(st0 + u + 1, q1);
-    }
+    for (int u = 0; u < NS; ++u) step(st0 + u, q[u % kDepth]);
 #pragma unroll
     for (int ta = 0; ta < 2; ++ta)
 #pragma unroll
       for (int tb = 0; tb < 2; ++tb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          totR[ta][tb][r] += (double)accR[ta][tb][r];
-          totI[ta][tb][r] += (double)accI[ta][tb][r];
+          tot[tslot(ta, tb, r, 0)] += (double)accR[ta][tb][r];
+          tot[tslot(ta, tb, r, 1)] += (double)accI[ta][tb][r];
         }
         accR[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
         accI[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -479,8 +484,8 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide_bf(int N, int S, int D,
         const int s = 32 * wa + 16 * ta + 4 * g + r, d = 32 * wb + 16 * tb + r16;
         if (s < S && d < D) {
           const size_t o = ((size_t)s * D + d) * 2;
-          out[o] = totR[ta][tb][r];
-          out[o + 1] = totI[ta][tb][r];
+          out[o] = tot[tslot(ta, tb, r, 0)];
+          out[o + 1] = tot[tslot(ta, tb, r, 1)];
         }
       }
 }
