@@ -181,9 +181,10 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, in
 // hi*hi + hi*lo + lo*hi.  Lane (r = lane%16, g = lane/16) supplies row r at voxels 8g..8g+7 of a
 // 32-voxel step for both operands (one MFMA k-step per step).  Block and waves as
 // k_born_jv_wide: wave (wa, wb) owns 32 sources x 32 detectors as 2 x 2 tiles, so each converted
-// operand feeds two tiles.  FP32 MFMA sums cover wide_bf_ns steps and are then folded into FP64;
-// the raw field words of the next step are loaded while the current step's products run (BF16
-// storage); partials as k_born_jv_wide.  VEC: 16-byte loads (N a multiple of 8, base
+// operand feeds two tiles.  FP32 MFMA sums cover wide_bf_ns steps and are then folded into FP64
+// running sums held in LDS; the four waves synchronise once per such stage; with BF16 storage the
+// raw field words of the next steps (four with 16-byte loads) are in flight while the current
+// step's products run; partials as k_born_jv_wide.  VEC: 16-byte loads (N a multiple of 8, base
 // pointers 16-byte aligned).
 typedef __bf16 wbf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -192,7 +193,6 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 // exceeds the FP32 summation error), 128 for the split
 template <int CM>
 constexpr int wide_bf_ns() { return CM == CM_SPLIT ? 4 : 8; }
-static_assert(8 % 2 == 0 && 4 % 2 == 0, "stages hold whole pairs of steps");
 constexpr int kWideBfKt = 256;   // voxel ranges: a multiple of both
 
 // raw words of eight voxels of one field row: BF16 storage (re, im) pairs in 8 words, FP32 in 16
