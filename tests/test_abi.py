@@ -4,6 +4,8 @@ with the oracle's independent one."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -331,3 +333,35 @@ def test_measure_peaks_validates_before_launch(hd):
     assert f(fake, 1 << 31, None, None) == hd.EINVAL                                      # null output
     assert f(ctypes.c_void_p(0x7F0000000010), 1 << 31, ctypes.byref(out), None) == hd.EINVAL   # misaligned
     assert f(fake, (1 << 30) - 256, ctypes.byref(out), None) == hd.EINVAL                 # under 1 GiB
+
+
+# ctypes structures of the binding and the C types they marshal
+_STRUCTS = {"_Grid": "hydot_grid", "_Optics": "hydot_optics", "_SolveOpts": "hydot_solve_opts",
+            "_PalsOpts": "hydot_pals_opts", "_SolveProblem": "hydot_solve_problem", "_InspectInfo": "hydot_inspect_info",
+            "_Peaks": "hydot_peaks", "_Tuning": "hydot_tuning", "_Trial": "hydot_tune_trial",
+            "_KProf": "hydot_kernel_profile"}
+
+
+@pytest.mark.skipif(shutil.which("g++") is None or not os.path.isdir("/opt/rocm/include"),
+                    reason="needs a host C++ compiler and the HIP headers")
+def test_binding_structs_match_the_header(hd, tmp_path):
+    """Every structure the binding passes through the C ABI has the size and field offsets the
+    header gives it (compiled with the host compiler)."""
+    from paper_1410_0986_amd import _binding as b
+    lines = ['#include <cstdio>', '#include <cstddef>', '#include "hydot.h"', 'int main() {']
+    expect = []
+    for py, c in _STRUCTS.items():
+        cls = getattr(b, py)
+        lines.append(f'  std::printf("%zu\\n", sizeof({c}));')
+        expect.append(ctypes.sizeof(cls))
+        for name, *_ in cls._fields_:
+            lines.append(f'  std::printf("%zu\\n", offsetof({c}, {name}));')
+            expect.append(getattr(cls, name).offset)
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True, capture_output=True, text=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == expect
