@@ -587,6 +587,8 @@ void launch_jv_pairs(dim3 grid, hipStream_t stream, int N, int S, int D, int64_t
 struct JvPlan {
   bool pairs = false;
   bool wide = false;                            // k_born_jv_wide(_bf) (S and D above 32)
+  bool wide_vs = false;                         // its voxel-split form (one probe vector, S, D <= 32)
+  int wide_tt = 2;                              // tiles per wave and dimension of that form
   int Sp = 0, Dp = 0;
   int kt = 32, tpw = 1, nvb = 1, ngroups = 1;   // real-ified kernel
   int nts = 1, ntd = 1, nct = 1;                // pair-product kernel
@@ -616,6 +618,15 @@ static JvPlan jv_plan(const hydot_operator* op, const hydot_tuning& tune, int S,
     // BF16 MFMA form, the same blocks as the FP32 one
     P.wide = true;
     P.kt = kWideBfKt;   // voxel ranges hold whole FP32 partial sums
+    const int target = std::max(1, tu.born_blocks / 4);
+    P.nsplit = std::max(1, (target + L * n_v - 1) / (L * n_v));
+  } else if (n_v == 1 && cm == CM_F32 && S >= kWideVsMin && D >= kWideVsMin && S <= 32 && D <= 32) {
+    // one probe vector and 9..32 sources and detectors: the wide kernel with its four waves
+    // splitting the voxels (each holds every pair), so each field row is read once per block
+    P.wide = true;
+    P.wide_vs = true;
+    P.wide_tt = std::max(S, D) > 16 ? 2 : 1;
+    P.kt = 4 * 16 * kWideNS;   // every wave gets whole FP32 partial sums
     const int target = std::max(1, tu.born_blocks / 4);
     P.nsplit = std::max(1, (target + L * n_v - 1) / (L * n_v));
   } else if (n_v >= kPairsMinNv) {
@@ -684,12 +695,17 @@ hydot_status born_apply_wide(const hydot_operator* op, const JvPlan& P, const vo
   const int N = op->gp.N, L = op->L;
   const dim3 grid(P.nsplit, L, n_v);
   const bool vec = N % 4 == 0 && aligned16(phs) && aligned16(phd) && aligned16(v);
-  if (vec)
-    hipLaunchKernelGGL(k_born_jv_wide<true>, grid, dim3(kBlock), 0, stream, N, S, D, ls, (const cf*)phs,
-                       (const cf*)phd, (const float*)v, P.kb, L, (double*)part);
-  else
-    hipLaunchKernelGGL(k_born_jv_wide<false>, grid, dim3(kBlock), 0, stream, N, S, D, ls, (const cf*)phs,
-                       (const cf*)phd, (const float*)v, P.kb, L, (double*)part);
+#define HYDOT_JVW(VEC, TT, VS)                                                                                   \
+  hipLaunchKernelGGL((k_born_jv_wide<VEC, TT, VS>), grid, dim3(kBlock), 0, stream, N, S, D, ls, (const cf*)phs, \
+                     (const cf*)phd, (const float*)v, P.kb, L, (double*)part)
+  if (P.wide_vs && P.wide_tt == 1) {
+    if (vec) HYDOT_JVW(true, 1, true); else HYDOT_JVW(false, 1, true);
+  } else if (P.wide_vs) {
+    if (vec) HYDOT_JVW(true, 2, true); else HYDOT_JVW(false, 2, true);
+  } else {
+    if (vec) HYDOT_JVW(true, 2, false); else HYDOT_JVW(false, 2, false);
+  }
+#undef HYDOT_JVW
   const int nout = n_v * L * S * D;
   const double h = op->grid.h_mm;
   hipLaunchKernelGGL((k_born_pairs_finish<cf>), dim3((nout + 255) / 256), dim3(256), 0, stream, S * D, P.nsplit,

@@ -16,6 +16,7 @@ namespace hydot {
 
 constexpr int kWideMin = 33;     // S and D above 32: the real-ified / pair kernels pad less below
 constexpr int kWideNS = 8;       // 16-voxel steps per FP32 partial sum (128 voxels) before FP64
+constexpr int kWideVsMin = 9;    // one probe vector, 9..32 sources and detectors: the voxel-split form
 
 // 16-byte loads of two complex FP32 values / four floats (the caller checks the alignment)
 __device__ inline void ld2cf(const cf* p, cf& a, cf& b) {
@@ -33,7 +34,7 @@ __device__ inline void ld2cf(const cf* p, cf& a, cf& b) {
 // block writes its FP64 partial sums as part[((c L + l) nsplit + split) S D + s D + d] (Re, Im),
 // summed over the splits by k_born_pairs_finish.  VEC: 16-byte loads (N a multiple of 4 and
 // every base pointer 16-byte aligned).
-template <bool VEC>
+template <bool VEC, int TT = 2, bool VS = false>
 __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, int64_t lam_stride,
                                                         const cf* __restrict__ phs, const cf* __restrict__ phd,
                                                         const float* __restrict__ v, int kb, int L,
@@ -42,15 +43,19 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, in
   const int k0 = split * kb, k1 = min(N, k0 + kb);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r16 = lane & 15, g = lane >> 4;
-  const int wa = wave >> 1, wb = wave & 1;
+  static_assert(VS || TT == 2, "the row-split form holds 2 x 2 tiles per wave");
+  // row split (VS false): wave (wa, wb) takes sources [32 wa, 32 wa + 32) and detectors
+  // [32 wb, 32 wb + 32); voxel split (VS true, S and D up to 16 TT): every wave takes all the
+  // pairs and every fourth 16-voxel step of the block's range
+  const int wa = VS ? 0 : wave >> 1, wb = VS ? 0 : wave & 1;
   const size_t Nz = (size_t)N;
-  // this lane's two A rows (sources) and two B rows (detectors); rows past S or D read zero
-  int srow[2], drow[2];
-  bool sok[2], dok[2];
-  const cf* pa[2];
-  const cf* pb[2];
+  // this lane's TT A rows (sources) and TT B rows (detectors); rows past S or D read zero
+  int srow[TT], drow[TT];
+  bool sok[TT], dok[TT];
+  const cf* pa[TT];
+  const cf* pb[TT];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < TT; ++t) {
     srow[t] = 32 * wa + 16 * t + r16;
     drow[t] = 32 * wb + 16 * t + r16;
     sok[t] = srow[t] < S;
@@ -60,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, in
   }
   const float* vc = v + (size_t)c * Nz;
   struct Stage {
-    cf a[2][4], b[2][4];
+    cf a[TT][4], b[TT][4];
     float vv[4];
   };
   auto fetch = [&](int kbase, Stage& st) {
@@ -70,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, in
 #pragma unroll
       for (int i = 0; i < 4; ++i) st.vv[i] = x[i];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < TT; ++t) {
         if (sok[t]) {
           ld2cf(pa[t] + kq, st.a[t][0], st.a[t][1]);
           ld2cf(pa[t] + kq + 2, st.a[t][2], st.a[t][3]);
@@ -93,59 +98,63 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, in
         const bool ok = k < k1;
         st.vv[i] = ok ? vc[k] : 0.f;
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < TT; ++t) {
           st.a[t][i] = ok && sok[t] ? pa[t][k] : cf{0.f, 0.f};
           st.b[t][i] = ok && dok[t] ? pb[t][k] : cf{0.f, 0.f};
         }
       }
     }
   };
-  f32x4 accR[2][2], accI[2][2];
-  double totR[2][2][4], totI[2][2][4];
+  f32x4 accR[TT][TT], accI[TT][TT];
+  double totR[TT][TT][4], totI[TT][TT][4];
 #pragma unroll
-  for (int ta = 0; ta < 2; ++ta)
+  for (int ta = 0; ta < TT; ++ta)
 #pragma unroll
-    for (int tb = 0; tb < 2; ++tb) {
+    for (int tb = 0; tb < TT; ++tb) {
       accR[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
       accI[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int r = 0; r < 4; ++r) totR[ta][tb][r] = totI[ta][tb][r] = 0.0;
     }
-  const int nst = k1 > k0 ? (k1 - k0 + 15) / 16 : 0;
+  // this wave's steps: all of the block's (row split) or every fourth (voxel split)
+  const int nst_all = k1 > k0 ? (k1 - k0 + 15) / 16 : 0;
+  const int s0 = VS ? wave : 0, sstr = VS ? 4 : 1;
+  const int nst = VS ? (nst_all > wave ? (nst_all - wave + 3) / 4 : 0) : nst_all;
+  auto kstep = [&](int st) { return k0 + 16 * (s0 + sstr * st); };
   Stage cur, nxt;
-  if (nst > 0) fetch(k0, cur);
+  if (nst > 0) fetch(kstep(0), cur);
   for (int st = 0; st < nst; ++st) {
-    if (st + 1 < nst) fetch(k0 + 16 * (st + 1), nxt);
+    if (st + 1 < nst) fetch(kstep(st + 1), nxt);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      float ar[2], ai[2], nai[2];
+      float ar[TT], ai[TT], nai[TT];
 #pragma unroll
-      for (int ta = 0; ta < 2; ++ta) {
+      for (int ta = 0; ta < TT; ++ta) {
         ar[ta] = cur.a[ta][i].re * cur.vv[i];
         ai[ta] = cur.a[ta][i].im * cur.vv[i];
         nai[ta] = -ai[ta];
       }
       // eight independent accumulators between two products into the same one
 #pragma unroll
-      for (int tb = 0; tb < 2; ++tb)
+      for (int tb = 0; tb < TT; ++tb)
 #pragma unroll
-        for (int ta = 0; ta < 2; ++ta) {
+        for (int ta = 0; ta < TT; ++ta) {
           accR[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ta], cur.b[tb][i].re, accR[ta][tb], 0, 0, 0);
           accI[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ta], cur.b[tb][i].im, accI[ta][tb], 0, 0, 0);
         }
 #pragma unroll
-      for (int tb = 0; tb < 2; ++tb)
+      for (int tb = 0; tb < TT; ++tb)
 #pragma unroll
-        for (int ta = 0; ta < 2; ++ta) {
+        for (int ta = 0; ta < TT; ++ta) {
           accR[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[ta], cur.b[tb][i].im, accR[ta][tb], 0, 0, 0);
           accI[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[ta], cur.b[tb][i].re, accI[ta][tb], 0, 0, 0);
         }
     }
     if ((st + 1) % kWideNS == 0 || st + 1 == nst) {
 #pragma unroll
-      for (int ta = 0; ta < 2; ++ta)
+      for (int ta = 0; ta < TT; ++ta)
 #pragma unroll
-        for (int tb = 0; tb < 2; ++tb) {
+        for (int tb = 0; tb < TT; ++tb) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             totR[ta][tb][r] += (double)accR[ta][tb][r];
@@ -157,12 +166,40 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, in
     }
     cur = nxt;
   }
+  if constexpr (VS) {
+    // the four waves' sums of the same pairs, added in wave order through LDS
+    __shared__ double red[3][TT * TT * 8][64];
+    if (wave > 0) {
+#pragma unroll
+      for (int ta = 0; ta < TT; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < TT; ++tb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            red[wave - 1][((ta * TT + tb) * 4 + r) * 2][lane] = totR[ta][tb][r];
+            red[wave - 1][((ta * TT + tb) * 4 + r) * 2 + 1][lane] = totI[ta][tb][r];
+          }
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+      for (int ta = 0; ta < TT; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < TT; ++tb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            totR[ta][tb][r] += red[w][((ta * TT + tb) * 4 + r) * 2][lane];
+            totI[ta][tb][r] += red[w][((ta * TT + tb) * 4 + r) * 2 + 1][lane];
+          }
+  }
   // accumulator register r of lane (col = lane%16, g) holds row 4g + r of the tile
   double* out = part + ((size_t)(c * L + l) * nsplit + split) * (size_t)S * D * 2;
 #pragma unroll
-  for (int ta = 0; ta < 2; ++ta)
+  for (int ta = 0; ta < TT; ++ta)
 #pragma unroll
-    for (int tb = 0; tb < 2; ++tb)
+    for (int tb = 0; tb < TT; ++tb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int s = 32 * wa + 16 * ta + 4 * g + r, d = 32 * wb + 16 * tb + r16;

@@ -218,6 +218,29 @@ def test_born_adjoint_matches_oracle(hd, dtype, tol):
     assert np.all(np.abs(g - ref) <= tol * absg), float((np.abs(g - ref) / absg).max())
 
 
+@pytest.mark.parametrize("grid", [(10, 9, 7), (16, 10, 8)])         # N = 630 (element loads), 1280 (16-byte)
+@pytest.mark.parametrize("S,D", [(9, 16), (16, 16), (16, 9), (17, 32), (32, 9), (32, 32), (33, 33)])
+def test_born_one_vector_wide_shapes(hd, S, D, grid):
+    """One probe vector on FP32 fields with 9..32 sources and detectors (the wide kernel with its
+    waves splitting the voxels, one or 2 x 2 tiles per wave) and just above (the row-split
+    form): every (wavelength, source, detector) entry within 1e-5 of the absolute sum of its
+    terms against the oracle on the same FP32 operands."""
+    nx, ny, nz = grid
+    w = workloads.config("tiny", nx=nx, ny=ny, nz=nz, n_lambda=3)
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(7 * S + D + nx)
+    P = rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))
+    t = torch.from_numpy(P).to(torch.complex64).to(DEV)
+    Pr = t.cpu().numpy().astype(np.complex128)
+    v = rng.standard_normal((1, w.N)).astype(np.float32)
+    y = hd.born_apply(op, t[:, :S], t[:, S:], torch.from_numpy(v).to(DEV)).cpu().numpy().astype(np.complex128)
+    ref = oborn.born_apply(Pr[:, :S], Pr[:, S:], v.astype(np.float64), w.h)
+    absum = w.h ** 3 * np.einsum("lsk,ck,ldk->clsd", np.abs(Pr[:, :S]), np.abs(v.astype(np.float64)),
+                                 np.abs(Pr[:, S:]), optimize=True)
+    err = np.abs(y - ref)
+    assert np.all(err <= 1e-5 * absum), float((err / absum).max())
+
+
 @pytest.mark.parametrize("S,D", [(3, 5), (9, 2), (24, 24), (64, 64)])
 @pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
 def test_born_shapes(hd, S, D, dtype, tol):
