@@ -792,18 +792,29 @@ hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S,
   const int N = op->gp.N, L = op->L;
   const double h = op->grid.h_mm;
   if constexpr (std::is_same<TS, cf>::value) {
-    if (S >= kWideMin && D >= kWideMin) {   // many pairs: k_born_adjoint_wide, one data vector per launch
+    // many pairs: k_born_adjoint_wide, one data vector per launch; one data vector with 9..32
+    // sources and detectors: its instances with fewer source steps and detector tiles
+    const bool wide = S >= kWideMin && D >= kWideMin;
+    const bool mid = n_w == 1 && S >= kWideVsMin && D >= kWideVsMin && S <= 32 && D <= 32;
+    if (wide || mid) {
       const bool vec = N % 4 == 0 && aligned16(phs) && aligned16(phd);
       const dim3 grid((N + 63) / 64);
+      const int qn = wide ? 16 : S <= 16 ? 4 : 8, td = wide ? 4 : D <= 16 ? 1 : 2;
       for (int c = 0; c < n_w; ++c) {
         const cf* wc = (const cf*)w + (size_t)c * L * S * D;
         cf* gc = (cf*)g + (size_t)c * N;
-        if (vec)
-          hipLaunchKernelGGL(k_born_adjoint_wide<true>, grid, dim3(kBlock), 0, stream, N, S, D, ls, L,
-                             (const cf*)phs, (const cf*)phd, wc, -h * h * h, gc);
-        else
-          hipLaunchKernelGGL(k_born_adjoint_wide<false>, grid, dim3(kBlock), 0, stream, N, S, D, ls, L,
-                             (const cf*)phs, (const cf*)phd, wc, -h * h * h, gc);
+#define HYDOT_ADJW(VEC, QN, TD)                                                                                \
+  hipLaunchKernelGGL((k_born_adjoint_wide<VEC, QN, TD>), grid, dim3(kBlock), 0, stream, N, S, D, ls, L, \
+                     (const cf*)phs, (const cf*)phd, wc, -h * h * h, gc)
+#define HYDOT_ADJW_V(QN, TD) \
+  if (vec) HYDOT_ADJW(true, QN, TD); else HYDOT_ADJW(false, QN, TD);
+        if (qn == 16) { HYDOT_ADJW_V(16, 4) }
+        else if (qn == 4 && td == 1) { HYDOT_ADJW_V(4, 1) }
+        else if (qn == 4) { HYDOT_ADJW_V(4, 2) }
+        else if (td == 1) { HYDOT_ADJW_V(8, 1) }
+        else { HYDOT_ADJW_V(8, 2) }
+#undef HYDOT_ADJW_V
+#undef HYDOT_ADJW
       }
       HYDOT_HIP(hipGetLastError());
       return HYDOT_OK;

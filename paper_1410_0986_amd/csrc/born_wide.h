@@ -544,7 +544,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 // base pointers 16-byte aligned).
 constexpr int kWPitch = 66;    // LDS row pitch of w (complex elements)
 
-template <bool VEC>
+// QN source k-steps of 4 (sources up to 4 QN) and TD detector tiles of 16 (detectors up to
+// 16 TD): 16 and 4 above 32 sources and detectors, fewer for smaller S and D (one data vector)
+template <bool VEC, int QN = 16, int TD = 4>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_born_adjoint_wide(int N, int S, int D, int64_t lam_stride, int L,
                                                              const cf* __restrict__ phs,
                                                              const cf* __restrict__ phd,
@@ -567,21 +569,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     }
   };
   // sources s = g + 4q of this lane's voxel
-  cf za[16], zn[16];
-  auto fetch_s = [&](int l, cf (&z)[16]) {
+  cf za[QN], zn[QN];
+  auto fetch_s = [&](int l, cf (&z)[QN]) {
     const cf* ps = phs + (size_t)l * lam_stride * Nz;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < QN; ++q) {
       const int s = g + 4 * q;
       z[q] = vok && s < S ? ps[(size_t)s * Nz + vox] : cf{0.f, 0.f};
     }
   };
   // detector fields at the accumulator entries: detector 16 t + r16, voxels vox0 + 4g + r
-  auto fetch_d = [&](int l, cf (&ph)[4][4]) {
+  auto fetch_d = [&](int l, cf (&ph)[TD][4]) {
     const cf* pd = phd + (size_t)l * lam_stride * Nz;
     const int vb = vox0 + 4 * g;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < TD; ++t) {
       const int d = 16 * t + r16;
       const bool dk = d < D;
       const cf* row = pd + (size_t)(dk ? d : 0) * Nz;
@@ -607,37 +609,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     __syncthreads();          // the previous wavelength's reads of Ws are done
     stage_w(l);
     __syncthreads();
-    cf ph[4][4];
+    cf ph[TD][4];
     fetch_d(l, ph);           // used by the epilogue, after the products
     if (l + 1 < L) fetch_s(l + 1, zn);
-    f32x4 accR[4], accI[4];
+    f32x4 accR[TD], accI[TD];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < TD; ++t) {
       accR[t] = f32x4{0.f, 0.f, 0.f, 0.f};
       accI[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < QN; ++q) {
       const float pr = za[q].re, pi = za[q].im, npi = -pi;
       const cf* wrow = Ws + (g + 4 * q) * kWPitch + r16;
-      cf ww[4];
+      cf ww[TD];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) ww[t] = wrow[16 * t];
-      // eight independent accumulators between two products into the same one
+      for (int t = 0; t < TD; ++t) ww[t] = wrow[16 * t];
+      // 2 TD independent accumulators between two products into the same one
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TD; ++t) {
         accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, ww[t].re, accR[t], 0, 0, 0);
         accI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, ww[t].im, accI[t], 0, 0, 0);
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TD; ++t) {
         accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pi, ww[t].im, accR[t], 0, 0, 0);
         accI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(npi, ww[t].re, accI[t], 0, 0, 0);
       }
     }
     // conj(phi_d) T, FP64; accumulator register r of lane (col r16, g) is voxel vox0 + 4g + r
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < TD; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const double e = ph[t][r].re, f = ph[t][r].im;
@@ -647,7 +649,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       }
     if (l + 1 < L) {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) za[q] = zn[q];
+      for (int q = 0; q < QN; ++q) za[q] = zn[q];
     }
   }
   // sum over the 16 detector lanes of each voxel

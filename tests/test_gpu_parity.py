@@ -224,7 +224,8 @@ def test_born_one_vector_wide_shapes(hd, S, D, grid):
     """One probe vector on FP32 fields with 9..32 sources and detectors (the wide kernel with its
     waves splitting the voxels, one or 2 x 2 tiles per wave) and just above (the row-split
     form): every (wavelength, source, detector) entry within 1e-5 of the absolute sum of its
-    terms against the oracle on the same FP32 operands."""
+    terms against the oracle on the same FP32 operands; the same for J^H w of one data vector
+    (the wide adjoint's instances with fewer source steps and detector tiles) at every voxel."""
     nx, ny, nz = grid
     w = workloads.config("tiny", nx=nx, ny=ny, nz=nz, n_lambda=3)
     op = hd.Operator.from_workload(w)
@@ -239,6 +240,13 @@ def test_born_one_vector_wide_shapes(hd, S, D, grid):
                                  np.abs(Pr[:, S:]), optimize=True)
     err = np.abs(y - ref)
     assert np.all(err <= 1e-5 * absum), float((err / absum).max())
+    W = (rng.standard_normal((w.L, S, D)) + 1j * rng.standard_normal((w.L, S, D))).astype(np.complex64)
+    g = hd.born_apply_adjoint(op, t[:, :S], t[:, S:], torch.from_numpy(W).to(DEV)).cpu().numpy()
+    Wd = W.astype(np.complex128)
+    gref = oborn.born_apply_adjoint(Pr[:, :S], Pr[:, S:], Wd, w.h)
+    gabs = w.h ** 3 * np.einsum("lsk,lsd,ldk->k", np.abs(Pr[:, :S]), np.abs(Wd), np.abs(Pr[:, S:]), optimize=True)
+    gerr = np.abs(g.astype(np.complex128) - gref)
+    assert np.all(gerr <= 1e-5 * gabs), float((gerr / gabs).max())
 
 
 @pytest.mark.parametrize("S,D", [(3, 5), (9, 2), (24, 24), (64, 64)])
