@@ -559,15 +559,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int vox = vox0 + r16;               // A row of this lane
   const bool vok = vox < N;
   const size_t Nz = (size_t)N;
-  // w_l staging: thread tid copies the 16 elements e = tid + 256 j of the 64 x 64 padded tile
+  // w_l staging: with all 16 source steps thread tid copies the elements e = tid + 256 j of the
+  // 64 x 64 padded tile; with fewer, only the S x D elements (the padding is cleared once,
+  // before the first wavelength)
   auto stage_w = [&](int l) {
     const cf* wl = w + (size_t)l * S * D;
+    if constexpr (QN == 16) {
 #pragma unroll 4
-    for (int j = 0; j < 16; ++j) {
-      const int e = tid + 256 * j, s = e >> 6, d = e & 63;
-      Ws[s * kWPitch + d] = s < S && d < D ? wl[s * D + d] : cf{0.f, 0.f};
+      for (int j = 0; j < 16; ++j) {
+        const int e = tid + 256 * j, s = e >> 6, d = e & 63;
+        Ws[s * kWPitch + d] = s < S && d < D ? wl[s * D + d] : cf{0.f, 0.f};
+      }
+    } else {
+      for (int e = tid; e < S * D; e += kBlock) {
+        const int s = e / D, d = e - s * D;
+        Ws[s * kWPitch + d] = wl[e];
+      }
     }
   };
+  if constexpr (QN != 16)
+    for (int e = tid; e < 64 * kWPitch; e += kBlock) Ws[e] = cf{0.f, 0.f};
   // sources s = g + 4q of this lane's voxel
   cf za[QN], zn[QN];
   auto fetch_s = [&](int l, cf (&z)[QN]) {
