@@ -694,7 +694,9 @@ hydot_status born_apply_wide(const hydot_operator* op, const JvPlan& P, const vo
                              int D, int64_t ls, const void* v, int n_v, void* y, void* part, hipStream_t stream) {
   const int N = op->gp.N, L = op->L;
   const dim3 grid(P.nsplit, L, n_v);
-  const bool vec = N % 4 == 0 && aligned16(phs) && aligned16(phd) && aligned16(v);
+  // (the voxel-split form's 16-byte path reads through buffer resources over one wavelength's rows)
+  const bool vec = N % 4 == 0 && aligned16(phs) && aligned16(phd) && aligned16(v) &&
+                   (!P.wide_vs || (size_t)std::max(S, D) * (size_t)N * 8u < (size_t(1) << 31));
 #define HYDOT_JVW(VEC, TT, VS)                                                                                   \
   hipLaunchKernelGGL((k_born_jv_wide<VEC, TT, VS>), grid, dim3(kBlock), 0, stream, N, S, D, ls, (const cf*)phs, \
                      (const cf*)phd, (const float*)v, P.kb, L, (double*)part)

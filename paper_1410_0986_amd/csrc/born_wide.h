@@ -18,6 +18,12 @@ constexpr int kWideMin = 33;     // S and D above 32: the real-ified / pair kern
 constexpr int kWideNS = 8;       // 16-voxel steps per FP32 partial sum (128 voxels) before FP64
 constexpr int kWideVsMin = 9;    // one probe vector, 9..32 sources and detectors: the voxel-split form
 
+// Raw buffer resource over nbytes at p (an offset at or past nbytes reads zero)
+__device__ inline __amdgpu_buffer_rsrc_t wide_rsrc(const void* p, uint32_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
+constexpr uint32_t kWideOut = 0x80000000u;   // a byte offset past every resource here
+
 // 16-byte loads of two complex FP32 values / four floats (the caller checks the alignment)
 __device__ inline void ld2cf(const cf* p, cf& a, cf& b) {
   const f32x4 x = *reinterpret_cast<const f32x4*>(p);
@@ -35,7 +41,7 @@ __device__ inline void ld2cf(const cf* p, cf& a, cf& b) {
 // summed over the splits by k_born_pairs_finish.  VEC: 16-byte loads (N a multiple of 4 and
 // every base pointer 16-byte aligned).
 template <bool VEC, int TT = 2, bool VS = false>
-__global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, int64_t lam_stride,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_born_jv_wide(int N, int S, int D, int64_t lam_stride,
                                                         const cf* __restrict__ phs, const cf* __restrict__ phd,
                                                         const float* __restrict__ v, int kb, int L,
                                                         double* __restrict__ part) {
@@ -105,6 +111,35 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, in
       }
     }
   };
+  // voxel split with 16-byte loads: every operand through a buffer resource over this
+  // wavelength's rows (a missing row or a piece past the range reads zero), so the loads are
+  // unconditional and their waits can sit steps back (loads under a branch are waited for at
+  // its end)
+  const __amdgpu_buffer_rsrc_t ra = wide_rsrc(phs + (size_t)l * lam_stride * Nz, VS && VEC ? (uint32_t)S * (uint32_t)N * 8u : 0u);
+  const __amdgpu_buffer_rsrc_t rb = wide_rsrc(phd + (size_t)l * lam_stride * Nz, VS && VEC ? (uint32_t)D * (uint32_t)N * 8u : 0u);
+  const __amdgpu_buffer_rsrc_t rvv = wide_rsrc(vc, VS && VEC ? (uint32_t)N * 4u : 0u);
+  auto fetch_buf = [&](int kbase, Stage& st) {
+    const int kq = kbase + 4 * g;
+    const bool in = kq < k1;   // N and the range ends are multiples of 4
+    const f32x4 x =
+        __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rvv, in ? (uint32_t)kq * 4u : kWideOut, 0, 0));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) st.vv[i] = x[i];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      const uint32_t oa = in && sok[t] ? ((uint32_t)srow[t] * (uint32_t)N + (uint32_t)kq) * 8u : kWideOut;
+      const uint32_t ob = in && dok[t] ? ((uint32_t)drow[t] * (uint32_t)N + (uint32_t)kq) * 8u : kWideOut;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const f32x4 xa = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, oa + 16u * h, 0, 0));
+        const f32x4 xb = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, ob + 16u * h, 0, 0));
+        st.a[t][2 * h] = cf{xa[0], xa[1]};
+        st.a[t][2 * h + 1] = cf{xa[2], xa[3]};
+        st.b[t][2 * h] = cf{xb[0], xb[1]};
+        st.b[t][2 * h + 1] = cf{xb[2], xb[3]};
+      }
+    }
+  };
   f32x4 accR[TT][TT], accI[TT][TT];
   double totR[TT][TT][4], totI[TT][TT][4];
 #pragma unroll
@@ -121,10 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, in
   const int s0 = VS ? wave : 0, sstr = VS ? 4 : 1;
   const int nst = VS ? (nst_all > wave ? (nst_all - wave + 3) / 4 : 0) : nst_all;
   auto kstep = [&](int st) { return k0 + 16 * (s0 + sstr * st); };
-  Stage cur, nxt;
-  if (nst > 0) fetch(kstep(0), cur);
-  for (int st = 0; st < nst; ++st) {
-    if (st + 1 < nst) fetch(kstep(st + 1), nxt);
+  auto compute = [&](const Stage& cur, int st) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       float ar[TT], ai[TT], nai[TT];
@@ -164,7 +196,31 @@ __global__ __launch_bounds__(kBlock) void k_born_jv_wide(int N, int S, int D, in
           accI[ta][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
     }
-    cur = nxt;
+  };
+  if constexpr (VS && VEC) {
+    // three stage buffers taken in rotation (unrolled by three, so no stage is copied: a copy
+    // would wait for its loads), the operands two steps ahead of the products
+    // steps past the range read zeros and add nothing (at most two per wave), so nothing in the
+    // loop is conditional
+    Stage q0, q1, q2;
+    fetch_buf(kstep(0), q0);
+    fetch_buf(kstep(1), q1);
+    for (int st = 0; st < nst; st += 3) {
+      fetch_buf(kstep(st + 2), q2);
+      compute(q0, st);
+      fetch_buf(kstep(st + 3), q0);
+      compute(q1, st + 1);
+      fetch_buf(kstep(st + 4), q1);
+      compute(q2, st + 2);
+    }
+  } else {
+    Stage cur, nxt;
+    if (nst > 0) fetch(kstep(0), cur);
+    for (int st = 0; st < nst; ++st) {
+      if (st + 1 < nst) fetch(kstep(st + 1), nxt);
+      compute(cur, st);
+      cur = nxt;
+    }
   }
   if constexpr (VS) {
     // the four waves' sums of the same pairs, added in wave order through LDS
@@ -238,11 +294,6 @@ struct Raw8 {
   static constexpr int nw = std::is_same<TS, cbf>::value ? 8 : 16;
   unsigned int w[nw];
 };
-// Raw buffer resource over nbytes at p (an offset at or past nbytes reads zero)
-__device__ inline __amdgpu_buffer_rsrc_t wide_rsrc(const void* p, uint32_t nbytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
-}
-constexpr uint32_t kWideOut = 0x80000000u;   // a byte offset past every resource here
 
 // Voxel of lane-local index i within a 32-voxel step: lane g takes voxels 8g..8g+7 (its two
 // 16-byte loads of a BF16 row, four of an FP32 row, are contiguous), the MFMA k-step 8g + i
