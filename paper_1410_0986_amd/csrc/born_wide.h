@@ -610,26 +610,38 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int vox = vox0 + r16;               // A row of this lane
   const bool vok = vox < N;
   const size_t Nz = (size_t)N;
-  // w_l staging: with all 16 source steps thread tid copies the elements e = tid + 256 j of the
-  // 64 x 64 padded tile; with fewer, only the S x D elements (the padding is cleared once,
-  // before the first wavelength)
+  // w_l staging.  With all 16 source steps thread tid copies the elements e = tid + 256 j of the
+  // 64 x 64 padded tile, between two barriers per wavelength.  With fewer (S, D <= 32, so
+  // S D <= 4 x 256) each thread carries the elements e = tid + 256 j, j < 4, of w_{l+1} in
+  // registers while wavelength l is computed and then stores them into the other half of Ws
+  // (two 32-row buffers whose padding is cleared once): one barrier per wavelength, and the
+  // loads of w overlap the products.
   auto stage_w = [&](int l) {
     const cf* wl = w + (size_t)l * S * D;
-    if constexpr (QN == 16) {
 #pragma unroll 4
-      for (int j = 0; j < 16; ++j) {
-        const int e = tid + 256 * j, s = e >> 6, d = e & 63;
-        Ws[s * kWPitch + d] = s < S && d < D ? wl[s * D + d] : cf{0.f, 0.f};
-      }
-    } else {
-      for (int e = tid; e < S * D; e += kBlock) {
-        const int s = e / D, d = e - s * D;
-        Ws[s * kWPitch + d] = wl[e];
-      }
+    for (int j = 0; j < 16; ++j) {
+      const int e = tid + 256 * j, s = e >> 6, d = e & 63;
+      Ws[s * kWPitch + d] = s < S && d < D ? wl[s * D + d] : cf{0.f, 0.f};
     }
   };
-  if constexpr (QN != 16)
+  constexpr int kWHalf = 32 * kWPitch;
+  constexpr int kWE = QN == 16 ? 1 : 4;
+  int woff[kWE];
+  cf wr[kWE];
+  if constexpr (QN != 16) {
+    const int SD = S * D;
+#pragma unroll
+    for (int j = 0; j < kWE; ++j) {
+      const int e = tid + 256 * j, s = e / D;
+      woff[j] = e < SD ? s * kWPitch + (e - s * D) : -1;
+    }
     for (int e = tid; e < 64 * kWPitch; e += kBlock) Ws[e] = cf{0.f, 0.f};
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kWE; ++j)
+      if (woff[j] >= 0) Ws[woff[j]] = w[tid + 256 * j];
+    __syncthreads();
+  }
   // sources s = g + 4q of this lane's voxel
   cf za[QN], zn[QN];
   auto fetch_s = [&](int l, cf (&z)[QN]) {
@@ -668,9 +680,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   for (int r = 0; r < 4; ++r) gre[r] = gim[r] = 0.0;
   fetch_s(0, za);
   for (int l = 0; l < L; ++l) {
-    __syncthreads();          // the previous wavelength's reads of Ws are done
-    stage_w(l);
-    __syncthreads();
+    const cf* Wc = Ws;
+    if constexpr (QN == 16) {
+      __syncthreads();        // the previous wavelength's reads of Ws are done
+      stage_w(l);
+      __syncthreads();
+    } else {
+      Wc = Ws + (l & 1) * kWHalf;
+      if (l + 1 < L) {
+        const cf* wn = w + (size_t)(l + 1) * S * D;
+#pragma unroll
+        for (int j = 0; j < kWE; ++j) wr[j] = woff[j] >= 0 ? wn[tid + 256 * j] : cf{0.f, 0.f};
+      }
+    }
     cf ph[TD][4];
     fetch_d(l, ph);           // used by the epilogue, after the products
     if (l + 1 < L) fetch_s(l + 1, zn);
@@ -683,7 +705,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
       const float pr = za[q].re, pi = za[q].im, npi = -pi;
-      const cf* wrow = Ws + (g + 4 * q) * kWPitch + r16;
+      const cf* wrow = Wc + (g + 4 * q) * kWPitch + r16;
       cf ww[TD];
 #pragma unroll
       for (int t = 0; t < TD; ++t) ww[t] = wrow[16 * t];
@@ -709,6 +731,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         gre[r] += e * tr + f * ti;
         gim[r] += e * ti - f * tr;
       }
+    if constexpr (QN != 16) {
+      // w_{l+1} into the buffer not read in this wavelength; the barrier also ends this
+      // wavelength's reads of Wc before the next one overwrites it
+      if (l + 1 < L) {
+        cf* Wn = Ws + ((l + 1) & 1) * kWHalf;
+#pragma unroll
+        for (int j = 0; j < kWE; ++j)
+          if (woff[j] >= 0) Wn[woff[j]] = wr[j];
+      }
+      __syncthreads();
+    }
     if (l + 1 < L) {
 #pragma unroll
       for (int q = 0; q < QN; ++q) za[q] = zn[q];
