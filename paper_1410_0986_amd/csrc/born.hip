@@ -822,6 +822,17 @@ hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S,
       return HYDOT_OK;
     }
   }
+  if constexpr (std::is_same<TS, cd>::value) {
+    // many pairs from FP64 fields: k_born_adjoint_wide64 (FP64 MFMA), one data vector per launch
+    if (S >= kWideMin && D >= kWideMin) {
+      const dim3 grid((N + 63) / 64);
+      for (int c = 0; c < n_w; ++c)
+        hipLaunchKernelGGL(k_born_adjoint_wide64, grid, dim3(kBlock), 0, stream, N, S, D, ls, L, (const cd*)phs,
+                           (const cd*)phd, (const cd*)w + (size_t)c * L * S * D, -h * h * h, (cd*)g + (size_t)c * N);
+      HYDOT_HIP(hipGetLastError());
+      return HYDOT_OK;
+    }
+  }
   if constexpr (std::is_same<TS, cbf>::value) {
     // many pairs from BF16 fields: k_born_adjoint_wide_bf (BF16 MFMA, w split into BF16 hi + lo),
     // one data vector per launch; its buffer resources span one wavelength's rows

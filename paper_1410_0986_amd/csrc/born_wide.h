@@ -765,6 +765,108 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
 }
 
+// J^H w for complex FP64 fields with S and D above 32 (one data vector per launch) on the FP64
+// MFMA (v_mfma_f64_16x16x4f64), in the layout of k_born_adjoint_wide: a wave takes 16 voxels,
+// lane (r16 = lane%16, g = lane/16) holds the sources s = g + 4q (q < 16) of voxel vox0 + r16 as
+// A[row = voxel][k], and B[k][col] = w[g + 4q][16 t + r16] comes from LDS (t < 4 column tiles,
+// the 64 x 64 tile of w_l staged once per block and wavelength).  Re T and Im T accumulate in
+// FP64 over the sources; the FP64 accumulator register r of a lane holds row 4 r + g, so the
+// epilogue contracts T with conj(phi_d) at voxels vox0 + 4 r + g and detectors 16 t + r16, and
+// the sums over the 16 detector lanes follow at the end.  Two waves per SIMD: the fields of one
+// wavelength are loaded at its start (the other wave's products cover the wait).
+constexpr int kWPitch64 = 65;   // LDS row pitch of w (complex FP64 elements)
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_born_adjoint_wide64(
+    int N, int S, int D, int64_t lam_stride, int L, const cd* __restrict__ phs, const cd* __restrict__ phd,
+    const cd* __restrict__ w, double scale, cd* __restrict__ gout) {
+  __shared__ cd Ws[64 * kWPitch64];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int vox0 = (blockIdx.x * 4 + wave) * 16;
+  const int vox = vox0 + r16;
+  const bool vok = vox < N;
+  const size_t Nz = (size_t)N;
+  double gre[4], gim[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) gre[r] = gim[r] = 0.0;
+  for (int l = 0; l < L; ++l) {
+    const cd* ps = phs + (size_t)l * lam_stride * Nz;
+    const cd* pd = phd + (size_t)l * lam_stride * Nz;
+    cd z[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int s = g + 4 * q;
+      z[q] = vok && s < S ? ps[(size_t)s * Nz + vox] : cd{0.0, 0.0};
+    }
+    __syncthreads();          // the previous wavelength's reads of Ws are done
+    const cd* wl = w + (size_t)l * S * D;
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
+      const int e = tid + 256 * j, s = e >> 6, d = e & 63;
+      Ws[s * kWPitch64 + d] = s < S && d < D ? wl[s * D + d] : cd{0.0, 0.0};
+    }
+    __syncthreads();
+    // two passes of two detector tiles over the same source values
+#pragma unroll 1
+    for (int p = 0; p < 2; ++p) {
+      cd ph[2][4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int d = 16 * (2 * p + u) + r16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int vv = vox0 + 4 * r + g;
+          ph[u][r] = d < D && vv < N ? pd[(size_t)d * Nz + vv] : cd{0.0, 0.0};
+        }
+      }
+      f64x4 accR[2], accI[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        accR[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+        accI[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double pr = z[q].re, pi = z[q].im, npi = -pi;
+        const cd* wrow = Ws + (g + 4 * q) * kWPitch64 + 32 * p + r16;
+        const cd w0 = wrow[0], w1 = wrow[16];
+        // Re T += Re phi Re w + Im phi Im w, Im T += Re phi Im w - Im phi Re w
+        accR[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, w0.re, accR[0], 0, 0, 0);
+        accI[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, w0.im, accI[0], 0, 0, 0);
+        accR[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, w1.re, accR[1], 0, 0, 0);
+        accI[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, w1.im, accI[1], 0, 0, 0);
+        accR[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(pi, w0.im, accR[0], 0, 0, 0);
+        accI[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(npi, w0.re, accI[0], 0, 0, 0);
+        accR[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(pi, w1.im, accR[1], 0, 0, 0);
+        accI[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(npi, w1.re, accI[1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double e = ph[u][r].re, f = ph[u][r].im, tr = accR[u][r], ti = accI[u][r];
+          gre[r] += e * tr + f * ti;
+          gim[r] += e * ti - f * tr;
+        }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      gre[r] += __shfl_xor(gre[r], off, 64);
+      gim[r] += __shfl_xor(gim[r], off, 64);
+    }
+  }
+  if (r16 == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int vv = vox0 + 4 * r + g;
+      if (vv < N) gout[vv] = cd{scale * gre[r], scale * gim[r]};
+    }
+  }
+}
+
 // J^H w for BF16 fields with S and D above 32, on the BF16 MFMA.  Block = 4 waves on 256 voxels
 // (64 per wave, in two passes of two 16-voxel tiles), looping over the wavelengths.  With the k
 // index k = 2s + c (c = 0: real part, c = 1: imaginary part of source s) the product

@@ -331,6 +331,35 @@ def test_born_many_pairs_entrywise(hd, S, D, grid):
             assert np.all(np.abs(g[c] - refg) <= 1e-5 * absg), float((np.abs(g[c] - refg) / absg).max())
 
 
+@pytest.mark.parametrize("S,D", [(33, 47), (64, 40), (64, 64)])
+@pytest.mark.parametrize("grid", [(12, 10, 6), (11, 9, 7)])      # N = 720, 693 (ragged last tile)
+def test_born_adjoint_fp64_many_pairs_entrywise(hd, S, D, grid):
+    """J^H w of one and of two data vectors on complex FP64 fields with more than 32 sources and
+    detectors (the FP64-MFMA form, one launch per data vector): every voxel against the FP64
+    definition within 1e-13 of the absolute sum of its terms, and the dot-product identity
+    <w, J v> = <J^H w, v> with J v of the same fields."""
+    nx, ny, nz = grid
+    w = workloads.config("tiny", nx=nx, ny=ny, nz=nz, n_lambda=3)
+    op = hd.Operator.from_workload(w)
+    rng = np.random.default_rng(S * 11 + D + nx)
+    P = rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))
+    t = torch.from_numpy(P).to(DEV)
+    Ps, Pd = P[:, :S], P[:, S:]
+    for n_w in (1, 2):
+        wv = rng.standard_normal((n_w, w.L, S, D)) + 1j * rng.standard_normal((n_w, w.L, S, D))
+        g = hd.born_apply_adjoint(op, t[:, :S], t[:, S:], torch.from_numpy(wv).to(DEV)).cpu().numpy()
+        g = g.reshape(n_w, w.N)
+        for c in range(n_w):
+            refg = oborn.born_apply_adjoint(Ps, Pd, wv[c], w.h)
+            absg = w.h ** 3 * np.einsum("lsk,lsd,ldk->k", np.abs(Ps), np.abs(wv[c]), np.abs(Pd), optimize=True)
+            assert np.all(np.abs(g[c] - refg) <= 1e-13 * absg), float((np.abs(g[c] - refg) / absg).max())
+    v = rng.standard_normal((1, w.N))
+    y = hd.born_apply(op, t[:, :S], t[:, S:], torch.from_numpy(v).to(DEV)).cpu().numpy()[0]
+    lhs = np.vdot(wv[0].reshape(-1), y.reshape(-1))
+    rhs = np.vdot(g[0], v[0])
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(wv[0]) * np.linalg.norm(y)
+
+
 def test_born_dot_test_on_device(hd):
     w = workloads.config("tiny")
     op = hd.Operator.from_workload(w)
