@@ -607,11 +607,11 @@ static JvPlan jv_plan(const hydot_operator* op, const hydot_tuning& tune, int S,
   const hydot_tuning tu = resolved_tuning(tune);
   P.Sp = pad8(S);
   P.Dp = pad8(D);
-  if (n_v < kPairsMinNv && cm == CM_F32 && S >= kWideMin && D >= kWideMin) {
+  if (n_v < kPairsMinNv && (cm == CM_F32 || cm == CM_F64) && S >= kWideMin && D >= kWideMin) {
     // one block per (voxel range, wavelength, probe vector), each holding all S x D pairs:
     // a quarter of the tuned block count fills the chip (about two blocks per CU by default)
     P.wide = true;
-    P.kt = 16 * kWideNS;   // voxel ranges hold whole FP32 partial sums
+    P.kt = cm == CM_F64 ? 16 : 16 * kWideNS;   // FP32: voxel ranges hold whole FP32 partial sums
     const int target = std::max(1, tu.born_blocks / 4);
     P.nsplit = std::max(1, (target + L * n_v - 1) / (L * n_v));
   } else if (n_v < kPairsMinNv && bf16_compute(cm) && S >= kWideMin && D >= kWideMin) {
@@ -716,6 +716,27 @@ hydot_status born_apply_wide(const hydot_operator* op, const JvPlan& P, const vo
   return HYDOT_OK;
 }
 
+// J v on k_born_jv_wide64 (complex FP64 fields, S and D above 32, fewer than kPairsMinNv probe
+// vectors), then the fixed-order sum over the voxel ranges.
+hydot_status born_apply_wide64(const hydot_operator* op, const JvPlan& P, const void* phs, int S, const void* phd,
+                               int D, int64_t ls, const void* v, int n_v, void* y, void* part, hipStream_t stream) {
+  const int N = op->gp.N, L = op->L;
+  // buffer resources: one wavelength's rows (and v) below 2 GiB
+  const bool buf = (size_t)std::max(S, D) * (size_t)N * 16u < (size_t(1) << 31);
+  if (buf)
+    hipLaunchKernelGGL(k_born_jv_wide64<true>, dim3(P.nsplit, L, n_v), dim3(kBlock), 0, stream, N, S, D, ls,
+                       (const cd*)phs, (const cd*)phd, (const double*)v, P.kb, L, (double*)part);
+  else
+    hipLaunchKernelGGL(k_born_jv_wide64<false>, dim3(P.nsplit, L, n_v), dim3(kBlock), 0, stream, N, S, D, ls,
+                       (const cd*)phs, (const cd*)phd, (const double*)v, P.kb, L, (double*)part);
+  const int nout = n_v * L * S * D;
+  const double h = op->grid.h_mm;
+  hipLaunchKernelGGL((k_born_pairs_finish<cd>), dim3((nout + 255) / 256), dim3(256), 0, stream, S * D, P.nsplit,
+                     nout, (const double*)part, -h * h * h, (cd*)y);
+  HYDOT_HIP(hipGetLastError());
+  return HYDOT_OK;
+}
+
 // J v on k_born_jv_wide_bf (BF16-stored fields with BF16 products, or FP32 fields with split-BF16
 // products; S and D above 32), then the fixed-order sum over the voxel ranges.
 template <typename TS, int CM>
@@ -749,6 +770,9 @@ hydot_status born_apply_impl(const hydot_operator* op, const JvPlan& P, const vo
   }
   if constexpr ((std::is_same<TS, cbf>::value && CM == CM_BF16) || (std::is_same<TS, cf>::value && CM == CM_SPLIT)) {
     if (P.wide) return born_apply_wide_bf<TS, CM>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
+  }
+  if constexpr (std::is_same<TS, cd>::value && CM == CM_F64) {
+    if (P.wide) return born_apply_wide64(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
   }
   if (P.pairs) return born_apply_pairs<TS, CM>(op, P, phs, S, phd, D, ls, v, n_v, y, part, stream);
   using R = typename Field<TS>::real;

@@ -267,6 +267,156 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       }
 }
 
+// J v for complex FP64 fields with S and D above 32 (fewer than 12 probe vectors) on the FP64
+// MFMA (v_mfma_f64_16x16x4f64), in the block and wave layout of k_born_jv_wide: wave (wa, wb)
+// owns sources [32 wa, 32 wa + 32) and detectors [32 wb, 32 wb + 32) as 2 x 2 tiles of 16 x 16.
+// Per 16-voxel step lane (r16, g) supplies row r16 of each tile at voxels g, g + 4, g + 8, g + 12
+// (k-step i takes voxel 4i + g, so the four lanes of a row read 64 contiguous bytes per load),
+// A = phi_s v and B = phi_d; Re y and Im y accumulate in FP64 on the MFMA
+// over the block's whole voxel range (accumulator register r of a lane holds row 4r + g).  The
+// next step's operands are loaded while the current step's products run.  Partials as
+// k_born_jv_wide.  BUF: the operands through buffer resources over this wavelength's rows (one
+// wavelength's rows below 2 GiB), so no load sits under a branch (loads under a branch are
+// waited for at its end) and steps past the range read zeros; two stage buffers in rotation.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <bool BUF>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_born_jv_wide64(
+    int N, int S, int D, int64_t lam_stride, const cd* __restrict__ phs, const cd* __restrict__ phd,
+    const double* __restrict__ v, int kb, int L, double* __restrict__ part) {
+  const int split = blockIdx.x, l = blockIdx.y, c = blockIdx.z, nsplit = gridDim.x;
+  const int k0 = split * kb, k1 = min(N, k0 + kb);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int wa = wave >> 1, wb = wave & 1;
+  const size_t Nz = (size_t)N;
+  bool sok[2], dok[2];
+  int srow[2], drow[2];
+  const cd* pa[2];
+  const cd* pb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    srow[t] = 32 * wa + 16 * t + r16;
+    drow[t] = 32 * wb + 16 * t + r16;
+    sok[t] = srow[t] < S;
+    dok[t] = drow[t] < D;
+    pa[t] = phs + ((size_t)l * lam_stride + (sok[t] ? srow[t] : 0)) * Nz;
+    pb[t] = phd + ((size_t)l * lam_stride + (dok[t] ? drow[t] : 0)) * Nz;
+  }
+  const double* vc = v + (size_t)c * Nz;
+  struct Stage {
+    cd a[2][4], b[2][4];
+    double vv[4];
+  };
+  auto fetch = [&](int kbase, Stage& st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = kbase + 4 * i + g;
+      const bool ok = k < k1;
+      st.vv[i] = ok ? vc[k] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        st.a[t][i] = ok && sok[t] ? pa[t][k] : cd{0.0, 0.0};
+        st.b[t][i] = ok && dok[t] ? pb[t][k] : cd{0.0, 0.0};
+      }
+    }
+  };
+  const __amdgpu_buffer_rsrc_t ra = wide_rsrc(phs + (size_t)l * lam_stride * Nz, BUF ? (uint32_t)S * (uint32_t)N * 16u : 0u);
+  const __amdgpu_buffer_rsrc_t rb = wide_rsrc(phd + (size_t)l * lam_stride * Nz, BUF ? (uint32_t)D * (uint32_t)N * 16u : 0u);
+  const __amdgpu_buffer_rsrc_t rv = wide_rsrc(vc, BUF ? (uint32_t)N * 8u : 0u);
+  auto fetch_buf = [&](int kbase, Stage& st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = kbase + 4 * i + g;
+      const bool in = k < k1;
+      st.vv[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rv, in ? (uint32_t)k * 8u : kWideOut, 0, 0));
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const uint32_t oa = in && sok[t] ? ((uint32_t)srow[t] * (uint32_t)N + (uint32_t)k) * 16u : kWideOut;
+        const uint32_t ob = in && dok[t] ? ((uint32_t)drow[t] * (uint32_t)N + (uint32_t)k) * 16u : kWideOut;
+        const f64x2 xa = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(ra, oa, 0, 0));
+        const f64x2 xb = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rb, ob, 0, 0));
+        st.a[t][i] = cd{xa[0], xa[1]};
+        st.b[t][i] = cd{xb[0], xb[1]};
+      }
+    }
+  };
+  f64x4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb) {
+      accR[ta][tb] = f64x4{0.0, 0.0, 0.0, 0.0};
+      accI[ta][tb] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+  auto compute = [&](const Stage& cur) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double ar[2], ai[2], nai[2];
+#pragma unroll
+      for (int ta = 0; ta < 2; ++ta) {
+        ar[ta] = cur.a[ta][i].re * cur.vv[i];
+        ai[ta] = cur.a[ta][i].im * cur.vv[i];
+        nai[ta] = -ai[ta];
+      }
+      // Re y += Re a Re b - Im a Im b, Im y += Re a Im b + Im a Re b
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta) {
+          accR[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ta], cur.b[tb][i].re, accR[ta][tb], 0, 0, 0);
+          accI[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ta], cur.b[tb][i].im, accI[ta][tb], 0, 0, 0);
+        }
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta) {
+          accR[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[ta], cur.b[tb][i].im, accR[ta][tb], 0, 0, 0);
+          accI[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[ta], cur.b[tb][i].re, accI[ta][tb], 0, 0, 0);
+        }
+    }
+  };
+  const int nst = k1 > k0 ? (k1 - k0 + 15) / 16 : 0;
+  if constexpr (BUF) {
+    // two stage buffers in rotation (unrolled by two, so no stage is copied: a copy would wait
+    // for its loads); a step past the range reads zeros and adds nothing
+    // (the scheduling barriers keep each step's loads ahead of the products before them)
+    Stage q0, q1;
+    fetch_buf(k0, q0);
+    for (int st = 0; st < nst; st += 2) {
+      fetch_buf(k0 + 16 * (st + 1), q1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(q0);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch_buf(k0 + 16 * (st + 2), q0);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(q1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+    Stage cur, nxt;
+    if (nst > 0) fetch(k0, cur);
+    for (int st = 0; st < nst; ++st) {
+      if (st + 1 < nst) fetch(k0 + 16 * (st + 1), nxt);
+      compute(cur);
+      cur = nxt;
+    }
+  }
+  double* out = part + ((size_t)(c * L + l) * nsplit + split) * (size_t)S * D * 2;
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = 32 * wa + 16 * ta + 4 * r + g, d = 32 * wb + 16 * tb + r16;
+        if (s < S && d < D) {
+          const size_t o = ((size_t)s * D + d) * 2;
+          out[o] = accR[ta][tb][r];
+          out[o + 1] = accI[ta][tb][r];
+        }
+      }
+}
+
 // ---------------------------------------------------------------- J v on the BF16 MFMA
 // The same products from BF16 operands on v_mfma_f32_16x16x32_bf16: CM_BF16 takes BF16-stored
 // fields (cbf) and rounds a = phi_s v (formed in FP32) to BF16, phi_d entering as stored;

@@ -333,11 +333,12 @@ def test_born_many_pairs_entrywise(hd, S, D, grid):
 
 @pytest.mark.parametrize("S,D", [(33, 47), (64, 40), (64, 64)])
 @pytest.mark.parametrize("grid", [(12, 10, 6), (11, 9, 7)])      # N = 720, 693 (ragged last tile)
-def test_born_adjoint_fp64_many_pairs_entrywise(hd, S, D, grid):
-    """J^H w of one and of two data vectors on complex FP64 fields with more than 32 sources and
-    detectors (the FP64-MFMA form, one launch per data vector): every voxel against the FP64
+def test_born_fp64_many_pairs_entrywise(hd, S, D, grid):
+    """J v of one and of three probe vectors and J^H w of one and of two data vectors on complex
+    FP64 fields with more than 32 sources and detectors (the FP64-MFMA wide forms): every
+    (probe vector, wavelength, source, detector) entry and every voxel against the FP64
     definition within 1e-13 of the absolute sum of its terms, and the dot-product identity
-    <w, J v> = <J^H w, v> with J v of the same fields."""
+    <w, J v> = <J^H w, v>."""
     nx, ny, nz = grid
     w = workloads.config("tiny", nx=nx, ny=ny, nz=nz, n_lambda=3)
     op = hd.Operator.from_workload(w)
@@ -345,6 +346,13 @@ def test_born_adjoint_fp64_many_pairs_entrywise(hd, S, D, grid):
     P = rng.standard_normal((w.L, S + D, w.N)) + 1j * rng.standard_normal((w.L, S + D, w.N))
     t = torch.from_numpy(P).to(DEV)
     Ps, Pd = P[:, :S], P[:, S:]
+    for n_v in (1, 3):
+        vv = rng.standard_normal((n_v, w.N))
+        y = hd.born_apply(op, t[:, :S], t[:, S:], torch.from_numpy(vv).to(DEV)).cpu().numpy()
+        ref = oborn.born_apply(Ps, Pd, vv, w.h)
+        absum = w.h ** 3 * np.einsum("lsk,ck,ldk->clsd", np.abs(Ps), np.abs(vv), np.abs(Pd), optimize=True)
+        assert y.shape == ref.shape == (n_v, w.L, S, D)
+        assert np.all(np.abs(y - ref) <= 1e-13 * absum), float((np.abs(y - ref) / absum).max())
     for n_w in (1, 2):
         wv = rng.standard_normal((n_w, w.L, S, D)) + 1j * rng.standard_normal((n_w, w.L, S, D))
         g = hd.born_apply_adjoint(op, t[:, :S], t[:, S:], torch.from_numpy(wv).to(DEV)).cpu().numpy()
