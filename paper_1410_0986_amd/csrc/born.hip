@@ -819,7 +819,8 @@ hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S,
   const double h = op->grid.h_mm;
   if constexpr (std::is_same<TS, cf>::value) {
     // many pairs: k_born_adjoint_wide, one data vector per launch; one data vector with 9..32
-    // sources and detectors: its instances with fewer source steps and detector tiles
+    // sources and detectors: its instances with fewer source steps and detector tiles (which
+    // carry w in registers, four elements per thread: S D <= 1024)
     const bool wide = S >= kWideMin && D >= kWideMin;
     const bool mid = n_w == 1 && S >= kWideVsMin && D >= kWideVsMin && S <= 32 && D <= 32;
     if (wide || mid) {
