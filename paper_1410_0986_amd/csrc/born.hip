@@ -830,12 +830,15 @@ hydot_status born_adjoint_impl(const hydot_operator* op, const void* phs, int S,
       for (int c = 0; c < n_w; ++c) {
         const cf* wc = (const cf*)w + (size_t)c * L * S * D;
         cf* gc = (cf*)g + (size_t)c * N;
-#define HYDOT_ADJW(VEC, QN, TD)                                                                                \
-  hipLaunchKernelGGL((k_born_adjoint_wide<VEC, QN, TD>), grid, dim3(kBlock), 0, stream, N, S, D, ls, L, \
+#define HYDOT_ADJW(VEC, QN, TD, BUF)                                                                           \
+  hipLaunchKernelGGL((k_born_adjoint_wide<VEC, QN, TD, BUF>), grid, dim3(kBlock), 0, stream, N, S, D, ls, L, \
                      (const cf*)phs, (const cf*)phd, wc, -h * h * h, gc)
 #define HYDOT_ADJW_V(QN, TD) \
-  if (vec) HYDOT_ADJW(true, QN, TD); else HYDOT_ADJW(false, QN, TD);
-        if (qn == 16) { HYDOT_ADJW_V(16, 4) }
+  if (vec) HYDOT_ADJW(true, QN, TD, false); else HYDOT_ADJW(false, QN, TD, false);
+        // buffer resources over one wavelength's rows: below 2 GiB
+        const bool buf = vec && (size_t)std::max(S, D) * (size_t)N * 8u < (size_t(1) << 31);
+        if (qn == 16 && buf) { HYDOT_ADJW(true, 16, 4, true); }
+        else if (qn == 16) { HYDOT_ADJW_V(16, 4) }
         else if (qn == 4 && td == 1) { HYDOT_ADJW_V(4, 1) }
         else if (qn == 4) { HYDOT_ADJW_V(4, 2) }
         else if (td == 1) { HYDOT_ADJW_V(8, 1) }

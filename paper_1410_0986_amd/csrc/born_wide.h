@@ -747,7 +747,11 @@ constexpr int kWPitch = 66;    // LDS row pitch of w (complex elements)
 
 // QN source k-steps of 4 (sources up to 4 QN) and TD detector tiles of 16 (detectors up to
 // 16 TD): 16 and 4 above 32 sources and detectors, fewer for smaller S and D (one data vector)
-template <bool VEC, int QN = 16, int TD = 4>
+// BUF (the 64 x 64 instance with 16-byte loads, one wavelength's rows below 2 GiB): w_l, the
+// detector fields of wavelength l and the source values of l + 1 through buffer resources, all
+// issued at the top of the wavelength with no load under a branch (loads under a branch are
+// waited for at its end), so only w_l is waited for before the LDS stores.
+template <bool VEC, int QN = 16, int TD = 4, bool BUF = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_born_adjoint_wide(int N, int S, int D, int64_t lam_stride, int L,
                                                              const cf* __restrict__ phs,
                                                              const cf* __restrict__ phd,
@@ -828,6 +832,91 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   double gre[4], gim[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) gre[r] = gim[r] = 0.0;
+  if constexpr (BUF) {
+    static_assert(QN == 16 && TD == 4 && VEC, "the buffer form is the 64 x 64 instance with 16-byte loads");
+    // source values of wavelength l (none past the last one)
+    auto fetch_s_buf = [&](int l, cf (&z)[QN]) {
+      const __amdgpu_buffer_rsrc_t r =
+          wide_rsrc(phs + (size_t)l * lam_stride * Nz, l < L ? (uint32_t)S * (uint32_t)N * 8u : 0u);
+#pragma unroll
+      for (int q = 0; q < QN; ++q) {
+        const int s = g + 4 * q;
+        const uint32_t off = vok && s < S ? ((uint32_t)s * (uint32_t)N + (uint32_t)vox) * 8u : kWideOut;
+        z[q] = __builtin_bit_cast(cf, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+      }
+    };
+    fetch_s_buf(0, za);
+    const int vb = vox0 + 4 * g;
+    for (int l = 0; l < L; ++l) {
+      // w_l (16 elements of the padded 64 x 64 tile per thread), then the detector fields of l
+      // and the source values of l + 1
+      const __amdgpu_buffer_rsrc_t rw = wide_rsrc(w + (size_t)l * S * D, (uint32_t)S * (uint32_t)D * 8u);
+      cf wt[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int e = tid + 256 * j, s = e >> 6, d = e & 63;
+        const uint32_t off = s < S && d < D ? (uint32_t)(s * D + d) * 8u : kWideOut;
+        wt[j] = __builtin_bit_cast(cf, __builtin_amdgcn_raw_buffer_load_b64(rw, off, 0, 0));
+      }
+      const __amdgpu_buffer_rsrc_t rd = wide_rsrc(phd + (size_t)l * lam_stride * Nz, (uint32_t)D * (uint32_t)N * 8u);
+      cf ph[TD][4];
+#pragma unroll
+      for (int t = 0; t < TD; ++t) {
+        const int d = 16 * t + r16;
+        const uint32_t off = d < D && vb < N ? ((uint32_t)d * (uint32_t)N + (uint32_t)vb) * 8u : kWideOut;
+        const f32x4 x0 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rd, off, 0, 0));
+        const f32x4 x1 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rd, off + 16u, 0, 0));
+        ph[t][0] = cf{x0[0], x0[1]};
+        ph[t][1] = cf{x0[2], x0[3]};
+        ph[t][2] = cf{x1[0], x1[1]};
+        ph[t][3] = cf{x1[2], x1[3]};
+      }
+      fetch_s_buf(l + 1, zn);
+      __builtin_amdgcn_sched_barrier(0);
+      __syncthreads();        // the previous wavelength's reads of Ws are done
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int e = tid + 256 * j;
+        Ws[(e >> 6) * kWPitch + (e & 63)] = wt[j];
+      }
+      __syncthreads();
+      f32x4 accR[TD], accI[TD];
+#pragma unroll
+      for (int t = 0; t < TD; ++t) {
+        accR[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        accI[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int q = 0; q < QN; ++q) {
+        const float pr = za[q].re, pi = za[q].im, npi = -pi;
+        const cf* wrow = Ws + (g + 4 * q) * kWPitch + r16;
+        cf ww[TD];
+#pragma unroll
+        for (int t = 0; t < TD; ++t) ww[t] = wrow[16 * t];
+#pragma unroll
+        for (int t = 0; t < TD; ++t) {
+          accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, ww[t].re, accR[t], 0, 0, 0);
+          accI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, ww[t].im, accI[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < TD; ++t) {
+          accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pi, ww[t].im, accR[t], 0, 0, 0);
+          accI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(npi, ww[t].re, accI[t], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TD; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double e = ph[t][r].re, f = ph[t][r].im;
+          const double tr = (double)accR[t][r], ti = (double)accI[t][r];
+          gre[r] += e * tr + f * ti;
+          gim[r] += e * ti - f * tr;
+        }
+#pragma unroll
+      for (int q = 0; q < QN; ++q) za[q] = zn[q];
+    }
+  } else {
   fetch_s(0, za);
   for (int l = 0; l < L; ++l) {
     const cf* Wc = Ws;
@@ -896,6 +985,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 #pragma unroll
       for (int q = 0; q < QN; ++q) za[q] = zn[q];
     }
+  }
   }
   // sum over the 16 detector lanes of each voxel
 #pragma unroll
